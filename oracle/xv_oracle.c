@@ -1,0 +1,707 @@
+/*
+ * xv_oracle.c -- CPU oracle for the band-packed transform-coding loop.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU path is checked against.  Only the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it; the product
+ * library never does.  It shares no source with the GPU path.
+ *
+ * What is computed, and where it comes from (paper: "Video Compression for
+ * Spatiotemporal Earth System Data", arXiv 2506.19656):
+ *   - bit-depth conversion of every band to B-bit integers   (Sec. II-A)
+ *   - grouping of the bands, in input order, into 3-channel frames, with the
+ *     remainder group padded by repeating its last band      (Sec. II-A, Listing 1 text)
+ *   - forward fill of missing (NaN) data                      (Sec. III-B)
+ *   - bits per pixel per band and per-channel PSNR whose peak is the maximum
+ *     of the original channel                                  (Sec. II-C)
+ * The paper hands frames to an HEVC encoder and describes none of its
+ * internals.  Below the frame level this oracle therefore follows a stated
+ * reading built on the public ITU-T H.265 conventions (integer DCT-II,
+ * QP-driven scalar quantiser, Exp-Golomb codes); each such step is marked
+ * "paper silent; reading".  The readings are listed in the design notes.
+ *
+ * Conventions: all arithmetic on coded values is integer; ">>" of a negative
+ * value must be an arithmetic (flooring) shift, which xvo_selfcheck() asserts.
+ * Floating point is IEEE binary64 with no contraction (build with
+ * -ffp-contract=off, no fast-math).
+ */
+#include "xv_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Basic helpers                                                              */
+/* ------------------------------------------------------------------------- */
+
+static int ilog2(int n) {
+  int k = 0;
+  while ((1 << k) < n) k++;
+  return k;
+}
+
+int xvo_selfcheck(void) {
+  volatile int32_t a = -7;
+  volatile int64_t b = -7;
+  if ((a >> 1) != -4) return -1;
+  if ((b >> 2) != -2) return -1;
+  return 0;
+}
+
+static double read_sample(const void* data, int dtype, int64_t idx) {
+  if (dtype == XVO_U16) return (double)((const uint16_t*)data)[idx];
+  return (double)((const float*)data)[idx];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Step 1: per-band statistics (bit-depth conversion, Sec. II-A; per-channel  */
+/* peak, Sec. II-C).  Paper silent on the conversion; reading: min-max over   */
+/* the whole cube per band, NaN excluded.  All-NaN band -> mn = mx = 0.       */
+/* ------------------------------------------------------------------------- */
+void xvo_stats(const void* data, int dtype, int64_t T, int64_t H, int64_t W,
+               int64_t Bn, double* mn, double* mx, int64_t* n_valid) {
+  for (int64_t b = 0; b < Bn; b++) {
+    double lo = INFINITY, hi = -INFINITY;
+    int64_t cnt = 0;
+    for (int64_t p = 0; p < T * H * W; p++) {
+      double v = read_sample(data, dtype, p * Bn + b);
+      if (isnan(v)) continue;
+      if (v < lo) lo = v;
+      if (v > hi) hi = v;
+      cnt++;
+    }
+    if (cnt == 0) { lo = 0.0; hi = 0.0; }
+    mn[b] = lo;
+    mx[b] = hi;
+    if (n_valid) n_valid[b] = cnt;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Step 2: missing-data fill (Sec. III-B: forward fill).                      */
+/* FILL_FORWARD: the last valid value before t; leading gaps take the first   */
+/* valid value after t.  FILL_NEAREST (reading used for cloud-gapped cubes):  */
+/* the valid sample at the smallest |t - t'|, ties to the earlier t'.  A      */
+/* series with no valid sample takes mn_b.                                    */
+/* ------------------------------------------------------------------------- */
+double xvo_filled_value(const void* data, int dtype, int64_t T, int64_t H,
+                        int64_t W, int64_t Bn, int64_t t, int64_t y, int64_t x,
+                        int64_t b, int fill_mode, double mn_b, int* is_valid) {
+  int64_t pix = (y * W + x) * Bn + b;
+  int64_t frame = H * W * Bn;
+  double v = read_sample(data, dtype, t * frame + pix);
+  if (!isnan(v)) {
+    if (is_valid) *is_valid = 1;
+    return v;
+  }
+  if (is_valid) *is_valid = 0;
+  if (fill_mode == XVO_FILL_FORWARD) {
+    for (int64_t u = t - 1; u >= 0; u--) {
+      double w = read_sample(data, dtype, u * frame + pix);
+      if (!isnan(w)) return w;
+    }
+    for (int64_t u = t + 1; u < T; u++) {
+      double w = read_sample(data, dtype, u * frame + pix);
+      if (!isnan(w)) return w;
+    }
+    return mn_b;
+  }
+  for (int64_t d = 1; d < T; d++) {
+    if (t - d >= 0) {
+      double w = read_sample(data, dtype, (t - d) * frame + pix);
+      if (!isnan(w)) return w;
+    }
+    if (t + d < T) {
+      double w = read_sample(data, dtype, (t + d) * frame + pix);
+      if (!isnan(w)) return w;
+    }
+  }
+  return mn_b;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Step 3: normalisation to B bits (Sec. II-A bit-depth conversion; formula   */
+/* paper silent, reading: per-band min-max, round half up).                   */
+/* q = floor((x - mn) * L / (mx - mn) + 1/2) clamped to [0, L], L = 2^B - 1,  */
+/* evaluated as exactly this chain of IEEE binary64 operations; a constant    */
+/* band (mx == mn) maps to 0.                                                 */
+/* ------------------------------------------------------------------------- */
+int32_t xvo_normalize(double x, double mn, double mx, int B) {
+  double L = (double)((1 << B) - 1);
+  double range = mx - mn;
+  if (range == 0.0) return 0;
+  double d = x - mn;
+  double num = d * L;
+  double v = num / range;
+  double q = floor(v + 0.5);
+  if (q < 0.0) q = 0.0;
+  if (q > L) q = L;
+  return (int32_t)q;
+}
+
+/* Inverse of the conversion, used by decode and the physical-domain PSNR:
+ * x_hat = mn + (q * (mx - mn)) / L in binary64, then cast to the output type
+ * (u16: floor(x_hat + 1/2) clamped to [0, 65535]; f32: round to nearest). */
+double xvo_denormalize(int32_t q, double mn, double mx, int B) {
+  double L = (double)((1 << B) - 1);
+  double range = mx - mn;
+  double num = (double)q * range;
+  return mn + num / L;
+}
+
+double xvo_cast_output(double v, int dtype) {
+  if (dtype == XVO_U16) {
+    double r = floor(v + 0.5);
+    if (r < 0.0) r = 0.0;
+    if (r > 65535.0) r = 65535.0;
+    return r;
+  }
+  return (double)(float)v;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Steps 4-5: packing into 3-channel frames (Sec. II-A: bands split in input  */
+/* order into groups of three; the remainder group repeats its last band) and */
+/* spatial edge padding to a multiple of the block size (paper silent;        */
+/* reading: replicate the last real row/column).                              */
+/* frame: [3][Hp][Wp] u16; valid: [3][Hp][Wp] u8 (1 = real pixel of a real    */
+/* band that was not missing).                                                */
+/* ------------------------------------------------------------------------- */
+int64_t xvo_source_band(int64_t g, int c, int64_t Bn, int pad_mode) {
+  int64_t b = 3 * g + c;
+  if (b < Bn) return b;
+  if (pad_mode == XVO_PAD_REPEAT) return Bn - 1;
+  return -1; /* zero channel */
+}
+
+void xvo_make_frame(const void* data, int dtype, int64_t T, int64_t H,
+                    int64_t W, int64_t Bn, const double* mn, const double* mx,
+                    const xvo_params* p, int64_t g, int64_t t, int64_t Hp,
+                    int64_t Wp, uint16_t* frame, uint8_t* valid) {
+  for (int c = 0; c < 3; c++) {
+    int64_t b = xvo_source_band(g, c, Bn, p->pad_mode);
+    int real_band = (3 * g + c) < Bn;
+    for (int64_t y = 0; y < Hp; y++) {
+      for (int64_t x = 0; x < Wp; x++) {
+        int64_t o = ((int64_t)c * Hp + y) * Wp + x;
+        if (b < 0) {
+          frame[o] = 0;
+          if (valid) valid[o] = 0;
+          continue;
+        }
+        int64_t ys = y < H ? y : H - 1;
+        int64_t xs = x < W ? x : W - 1;
+        int ok = 0;
+        double v = xvo_filled_value(data, dtype, T, H, W, Bn, t, ys, xs, b,
+                                    p->fill_mode, mn[b], &ok);
+        frame[o] = (uint16_t)xvo_normalize(v, mn[b], mx[b], p->bit_depth);
+        if (valid) valid[o] = (uint8_t)(real_band && ok && y < H && x < W);
+      }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Integer DCT-II matrix of ITU-T H.265 (paper silent on codec internals;     */
+/* reading: the standard's transform).  For k > 0 the 32-point entry is the   */
+/* standard's integer approximation of 64*sqrt(2)*cos(pi*m/64) with           */
+/* m = (2n+1)k mod 128; the row k = 0 is 64.  Magnitudes for m = 1..31 are    */
+/* the normative values; the sign and quadrant follow the cosine.  The        */
+/* N-point matrix takes rows k*32/N of the 32-point one, first N columns.     */
+/* ------------------------------------------------------------------------- */
+static const int kCosMag[32] = {
+    0,  90, 90, 90, 89, 88, 87, 85, 83, 82, 80, 78, 75, 73, 70, 67,
+    64, 61, 57, 54, 50, 46, 43, 38, 36, 31, 25, 22, 18, 13, 9,  4};
+
+static int dct32_entry(int k, int n) {
+  if (k == 0) return 64;
+  int m = ((2 * n + 1) * k) % 128;
+  if (m < 32) return kCosMag[m];
+  if (m < 64) return -kCosMag[64 - m];
+  if (m < 96) return -kCosMag[m - 64];
+  return kCosMag[128 - m];
+}
+
+void xvo_dct_matrix(int N, int32_t* M) {
+  for (int k = 0; k < N; k++)
+    for (int n = 0; n < N; n++) M[k * N + n] = dct32_entry(k * (32 / N), n);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Forward 2-D transform (paper silent; reading: H.265 forward core           */
+/* transform).  Stage 1 over each row y: T[y][k] = (sum_x M[k][x] r[y][x] +   */
+/* 2^(s1-1)) >> s1, s1 = log2N + B - 9.  Stage 2 over each column k:          */
+/* C[l][k] = (sum_y M[l][y] T[y][k] + 2^(s2-1)) >> s2, s2 = log2N + 6.        */
+/* r and C are N*N row-major ([y][x] and [l][k], l vertical frequency).       */
+/* ------------------------------------------------------------------------- */
+void xvo_forward_transform(int N, int B, const int32_t* r, int32_t* C) {
+  int32_t M[32 * 32];
+  int32_t Tm[32 * 32];
+  xvo_dct_matrix(N, M);
+  int s1 = ilog2(N) + B - 9;
+  int s2 = ilog2(N) + 6;
+  for (int y = 0; y < N; y++)
+    for (int k = 0; k < N; k++) {
+      int64_t acc = 0;
+      for (int x = 0; x < N; x++) acc += (int64_t)M[k * N + x] * r[y * N + x];
+      Tm[y * N + k] = (int32_t)((acc + ((int64_t)1 << (s1 - 1))) >> s1);
+    }
+  for (int l = 0; l < N; l++)
+    for (int k = 0; k < N; k++) {
+      int64_t acc = 0;
+      for (int y = 0; y < N; y++) acc += (int64_t)M[l * N + y] * Tm[y * N + k];
+      C[l * N + k] = (int32_t)((acc + ((int64_t)1 << (s2 - 1))) >> s2);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Quantiser scales (paper silent; reading: H.265 scalar quantiser).          */
+/* IQ[k] = round(64 * 2^((k-4)/6)), Qf[k] = round(2^20 / IQ[k]), k = 0..5,    */
+/* evaluated here from their closed forms.                                    */
+/* ------------------------------------------------------------------------- */
+int32_t xvo_iq_scale(int k) { return (int32_t)floor(64.0 * pow(2.0, (k - 4) / 6.0) + 0.5); }
+int32_t xvo_q_scale(int k) {
+  return (int32_t)floor(1048576.0 / (double)xvo_iq_scale(k) + 0.5);
+}
+
+/* Dead-zone quantisation.  qP = QP + 6(B-8); qbits = 29 + floor(qP/6) - B -
+ * log2N; rounding offset 171/512 (intra) or 85/512 (inter) of a step;
+ * level = sign(C) * min(32767, (|C| * Qf[qP%6] + off) >> qbits). */
+void xvo_quantize(int N, int B, int qp, int intra, const int32_t* C,
+                  int16_t* lev) {
+  int qP = qp + 6 * (B - 8);
+  int qbits = 29 + qP / 6 - B - ilog2(N);
+  int64_t off = (int64_t)(intra ? 171 : 85) << (qbits - 9);
+  int64_t qf = xvo_q_scale(qP % 6);
+  for (int i = 0; i < N * N; i++) {
+    int64_t a = C[i] < 0 ? -(int64_t)C[i] : (int64_t)C[i];
+    int64_t m = (a * qf + off) >> qbits;
+    if (m > 32767) m = 32767;
+    lev[i] = (int16_t)(C[i] < 0 ? -m : m);
+  }
+}
+
+/* Dequantisation.  bd = B + log2N - 5;
+ * d = clip16((level * IQ[qP%6] * 16 * 2^floor(qP/6) + 2^(bd-1)) >> bd). */
+void xvo_dequantize(int N, int B, int qp, const int16_t* lev, int32_t* d) {
+  int qP = qp + 6 * (B - 8);
+  int bd = B + ilog2(N) - 5;
+  int64_t scale = (int64_t)xvo_iq_scale(qP % 6) * 16 * ((int64_t)1 << (qP / 6));
+  for (int i = 0; i < N * N; i++) {
+    int64_t v = ((int64_t)lev[i] * scale + ((int64_t)1 << (bd - 1))) >> bd;
+    if (v < -32768) v = -32768;
+    if (v > 32767) v = 32767;
+    d[i] = (int32_t)v;
+  }
+}
+
+/* Inverse 2-D transform (paper silent; reading: H.265 inverse transform,
+ * vertical first).  E[y][k] = clip16((sum_l M[l][y] d[l][k] + 64) >> 7);
+ * r[y][x] = (sum_k M[k][x] E[y][k] + 2^(19-B)) >> (20 - B). */
+void xvo_inverse_transform(int N, int B, const int32_t* d, int32_t* r) {
+  int32_t M[32 * 32];
+  int32_t E[32 * 32];
+  xvo_dct_matrix(N, M);
+  int s2 = 20 - B;
+  for (int y = 0; y < N; y++)
+    for (int k = 0; k < N; k++) {
+      int64_t acc = 0;
+      for (int l = 0; l < N; l++) acc += (int64_t)M[l * N + y] * d[l * N + k];
+      int64_t v = (acc + 64) >> 7;
+      if (v < -32768) v = -32768;
+      if (v > 32767) v = 32767;
+      E[y * N + k] = (int32_t)v;
+    }
+  for (int y = 0; y < N; y++)
+    for (int x = 0; x < N; x++) {
+      int64_t acc = 0;
+      for (int k = 0; k < N; k++) acc += (int64_t)M[k * N + x] * E[y * N + k];
+      r[y * N + x] = (int32_t)((acc + ((int64_t)1 << (s2 - 1))) >> s2);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Rate proxy (Exp-Golomb code lengths; paper silent on the entropy coder,    */
+/* reading: order-0 Exp-Golomb lengths in place of CABAC).                    */
+/* ------------------------------------------------------------------------- */
+int xvo_ue_len(uint32_t k) {
+  uint64_t v = (uint64_t)k + 1;
+  int nb = 0;
+  while ((v >> nb) > 1) nb++;
+  return 2 * nb + 1;
+}
+
+int xvo_se_len(int32_t v) {
+  uint32_t k = v > 0 ? (uint32_t)(2 * (int64_t)v - 1) : (uint32_t)(-2 * (int64_t)v);
+  return xvo_ue_len(k);
+}
+
+/* Up-right diagonal scan over the whole N x N block: positions ordered by
+ * anti-diagonal x + y ascending, then by x ascending (x = column).
+ * order[i] = y * N + x of the i-th scanned position. */
+void xvo_scan_order(int N, int32_t* order) {
+  int i = 0;
+  for (int s = 0; s <= 2 * (N - 1); s++)
+    for (int x = 0; x < N; x++) {
+      int y = s - x;
+      if (y < 0 || y >= N) continue;
+      order[i++] = y * N + x;
+    }
+}
+
+/* bits = 1 (coded flag) + [nnz > 0] * (ue(nnz - 1) + sum over nonzero levels in
+ * scan order of (ue(run) + se(level))), run = zeros since the previous
+ * nonzero (or since the scan start). */
+uint32_t xvo_coef_bits(int N, const int16_t* lev) {
+  int32_t order[32 * 32];
+  xvo_scan_order(N, order);
+  int nnz = 0;
+  for (int i = 0; i < N * N; i++) nnz += lev[i] != 0;
+  uint32_t bits = 1;
+  if (nnz == 0) return bits;
+  bits += (uint32_t)xvo_ue_len((uint32_t)(nnz - 1));
+  int run = 0;
+  for (int i = 0; i < N * N; i++) {
+    int16_t v = lev[order[i]];
+    if (v == 0) {
+      run++;
+      continue;
+    }
+    bits += (uint32_t)(xvo_ue_len((uint32_t)run) + xvo_se_len(v));
+    run = 0;
+  }
+  return bits;
+}
+
+/* Motion-vector bits: se(mvx - pmx) + se(mvy - pmy), predictor = the left
+ * neighbour's vector in the same block row, (0,0) in the first column. */
+uint32_t xvo_mv_bits(int mvx, int mvy, int pmx, int pmy) {
+  return (uint32_t)(xvo_se_len(mvx - pmx) + xvo_se_len(mvy - pmy));
+}
+
+/* ------------------------------------------------------------------------- */
+/* Full-search integer-pel motion estimation (paper silent; reading: one      */
+/* vector per N x N block shared by the group's 3 channels, SAD summed over   */
+/* the group's channels that carry a real band (c < nch; padding channels do  */
+/* not steer the search), candidates (dx,dy) in [-R,R]^2 with the displaced block      */
+/* fully inside the padded frame, lexicographic minimum of                   */
+/* (SAD, |dx|+|dy|, dy, dx)).  cur and ref are [3][Hp][Wp].                   */
+/* ------------------------------------------------------------------------- */
+void xvo_motion_search(const uint16_t* cur, const uint16_t* ref, int64_t Hp,
+                       int64_t Wp, int N, int R, int nch, int64_t bx, int64_t by,
+                       int32_t* best_dx, int32_t* best_dy, uint32_t* best_sad) {
+  int64_t x0 = bx * N, y0 = by * N;
+  uint32_t bs = UINT32_MAX;
+  int bl1 = 0, bdx = 0, bdy = 0;
+  for (int dy = -R; dy <= R; dy++) {
+    for (int dx = -R; dx <= R; dx++) {
+      if (x0 + dx < 0 || x0 + dx + N > Wp || y0 + dy < 0 || y0 + dy + N > Hp)
+        continue;
+      uint32_t sad = 0;
+      for (int c = 0; c < nch; c++)
+        for (int i = 0; i < N; i++)
+          for (int j = 0; j < N; j++) {
+            int a = cur[(c * Hp + y0 + i) * Wp + x0 + j];
+            int b = ref[(c * Hp + y0 + dy + i) * Wp + x0 + dx + j];
+            sad += (uint32_t)(a > b ? a - b : b - a);
+          }
+      int l1 = abs(dx) + abs(dy);
+      /* raster order (dy, then dx) makes the first strict improvement the
+       * lexicographic minimum of (SAD, L1, dy, dx) */
+      if (sad < bs || (sad == bs && l1 < bl1)) {
+        bs = sad;
+        bl1 = l1;
+        bdx = dx;
+        bdy = dy;
+      }
+    }
+  }
+  *best_dx = bdx;
+  *best_dy = bdy;
+  *best_sad = bs;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coding of one closed group of pictures of one band group (paper silent on */
+/* codec internals; reading: an I picture predicted from the constant         */
+/* 2^(B-1), then P pictures predicted from the reconstruction of the picture  */
+/* just before, closed loop).                                                 */
+/* Layouts (len frames of this GOP, local index f):                           */
+/*   frames, recon : [len][3][Hp][Wp] u16                                     */
+/*   levels        : [len][3][Hb][Wb][N][N] i16                               */
+/*   mvs           : [len][Hb][Wb][2] i8 (dx, dy); zero for the I picture     */
+/*   coef_bits     : [len][3][Hb][Wb] u32                                     */
+/*   mv_bits       : [len][Hb][Wb] u32                                        */
+/*   sse, nvalid   : [3] u64, over valid pixels of the coded GOP              */
+/* ------------------------------------------------------------------------- */
+static void code_block(const xvo_params* p, int intra, const uint16_t* cur,
+                       const uint16_t* pred_plane, int64_t Wp,
+                       int64_t x0, int64_t y0, int dx, int dy, int16_t* lev_out,
+                       uint16_t* rec_plane, uint32_t* bits_out) {
+  int N = p->block, B = p->bit_depth;
+  int L = (1 << B) - 1;
+  int32_t r[32 * 32] = {0}, C[32 * 32], d[32 * 32], rr[32 * 32], pred[32 * 32];
+  for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++) {
+      int pv = intra ? (1 << (B - 1))
+                     : pred_plane[(y0 + dy + i) * Wp + x0 + dx + j];
+      pred[i * N + j] = pv;
+      r[i * N + j] = (int32_t)cur[(y0 + i) * Wp + x0 + j] - pv;
+    }
+  xvo_forward_transform(N, B, r, C);
+  xvo_quantize(N, B, p->qp, intra, C, lev_out);
+  *bits_out = xvo_coef_bits(N, lev_out);
+  xvo_dequantize(N, B, p->qp, lev_out, d);
+  xvo_inverse_transform(N, B, d, rr);
+  for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++) {
+      int v = pred[i * N + j] + rr[i * N + j];
+      if (v < 0) v = 0;
+      if (v > L) v = L;
+      rec_plane[(y0 + i) * Wp + x0 + j] = (uint16_t)v;
+    }
+}
+
+int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
+                   int64_t W, int64_t Bn, const double* mn, const double* mx,
+                   const xvo_params* p, int64_t g, int64_t t0, int64_t len,
+                   uint16_t* frames, int16_t* levels, int8_t* mvs,
+                   uint16_t* recon, uint32_t* coef_bits, uint32_t* mv_bits,
+                   uint64_t* sse, uint64_t* nvalid) {
+  if (xvo_check_params(p) != 0) return -1;
+  int N = p->block;
+  int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
+  int64_t Hb = Hp / N, Wb = Wp / N;
+  int64_t plane = Hp * Wp, fsz = 3 * plane;
+  int nch = (int)(Bn - 3 * g < 3 ? Bn - 3 * g : 3);
+  uint8_t* valid = (uint8_t*)malloc((size_t)fsz);
+  if (!valid) return -2;
+  for (int c = 0; c < 3; c++) { sse[c] = 0; nvalid[c] = 0; }
+  for (int64_t f = 0; f < len; f++) {
+    int64_t t = t0 + f;
+    uint16_t* cur = frames + f * fsz;
+    uint16_t* rec = recon + f * fsz;
+    const uint16_t* ref = f > 0 ? recon + (f - 1) * fsz : NULL;
+    int intra = (f == 0);
+    xvo_make_frame(data, dtype, T, H, W, Bn, mn, mx, p, g, t, Hp, Wp, cur, valid);
+    for (int64_t by = 0; by < Hb; by++) {
+      int pmx = 0, pmy = 0;
+      for (int64_t bx = 0; bx < Wb; bx++) {
+        int32_t dx = 0, dy = 0;
+        uint32_t sad = 0;
+        int64_t bi = by * Wb + bx;
+        if (!intra)
+          xvo_motion_search(cur, ref, Hp, Wp, N, p->search_range, nch, bx, by, &dx,
+                            &dy, &sad);
+        mvs[(f * Hb * Wb + bi) * 2 + 0] = (int8_t)dx;
+        mvs[(f * Hb * Wb + bi) * 2 + 1] = (int8_t)dy;
+        mv_bits[f * Hb * Wb + bi] = intra ? 0 : xvo_mv_bits(dx, dy, pmx, pmy);
+        pmx = dx;
+        pmy = dy;
+        for (int c = 0; c < 3; c++) {
+          int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + bi) * N * N;
+          code_block(p, intra, cur + c * plane, ref ? ref + c * plane : NULL,
+                     Wp, bx * N, by * N, dx, dy, lev, rec + c * plane,
+                     &coef_bits[(f * 3 + c) * Hb * Wb + bi]);
+        }
+      }
+    }
+    for (int c = 0; c < 3; c++)
+      for (int64_t o = 0; o < plane; o++) {
+        if (!valid[c * plane + o]) continue;
+        int64_t e = (int64_t)cur[c * plane + o] - (int64_t)rec[c * plane + o];
+        sse[c] += (uint64_t)(e * e);
+        nvalid[c] += 1;
+      }
+  }
+  free(valid);
+  return 0;
+}
+
+/* Decoding of one GOP from its levels and vectors: the same prediction,
+ * dequantisation and inverse transform as the encoder's reconstruction. */
+int xvo_decode_gop(const xvo_params* p, int64_t H, int64_t W, int64_t len,
+                   const int16_t* levels, const int8_t* mvs, uint16_t* recon) {
+  if (xvo_check_params(p) != 0) return -1;
+  int N = p->block, B = p->bit_depth, L = (1 << B) - 1;
+  int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
+  int64_t Hb = Hp / N, Wb = Wp / N, plane = Hp * Wp, fsz = 3 * plane;
+  int32_t d[32 * 32], rr[32 * 32];
+  for (int64_t f = 0; f < len; f++) {
+    uint16_t* rec = recon + f * fsz;
+    const uint16_t* ref = f > 0 ? recon + (f - 1) * fsz : NULL;
+    for (int64_t by = 0; by < Hb; by++)
+      for (int64_t bx = 0; bx < Wb; bx++) {
+        int64_t bi = by * Wb + bx;
+        int dx = mvs[(f * Hb * Wb + bi) * 2 + 0];
+        int dy = mvs[(f * Hb * Wb + bi) * 2 + 1];
+        for (int c = 0; c < 3; c++) {
+          const int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + bi) * N * N;
+          xvo_dequantize(N, B, p->qp, lev, d);
+          xvo_inverse_transform(N, B, d, rr);
+          for (int i = 0; i < N; i++)
+            for (int j = 0; j < N; j++) {
+              int64_t y = by * N + i, x = bx * N + j;
+              int pv = f == 0 ? (1 << (B - 1))
+                              : ref[(c * Hp + y + dy) * Wp + x + dx];
+              int v = pv + rr[i * N + j];
+              if (v < 0) v = 0;
+              if (v > L) v = L;
+              rec[(c * Hp + y) * Wp + x] = (uint16_t)v;
+            }
+        }
+      }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Whole-cube drivers: every (group, GOP) unit is independent (closed GOPs),  */
+/* so units run in parallel.  Full-cube layouts prepend [G][T] to the GOP     */
+/* layouts above; sse and nvalid are per real band.                           */
+/* ------------------------------------------------------------------------- */
+int xvo_check_params(const xvo_params* p) {
+  int N = p->block, B = p->bit_depth;
+  if (!(N == 4 || N == 8 || N == 16 || N == 32)) return -1;
+  if (B < 8 || B > 12) return -1;
+  if (p->qp < -6 * (B - 8) || p->qp > 51) return -1;
+  if (p->search_range < 0 || p->search_range > 64) return -1;
+  if (p->gop < 1) return -1;
+  if (p->pad_mode != XVO_PAD_ZERO && p->pad_mode != XVO_PAD_REPEAT) return -1;
+  if (p->fill_mode != XVO_FILL_NEAREST && p->fill_mode != XVO_FILL_FORWARD) return -1;
+  return 0;
+}
+
+int xvo_encode_cube(const void* data, int dtype, int64_t T, int64_t H,
+                    int64_t W, int64_t Bn, const xvo_params* p, double* mn,
+                    double* mx, uint16_t* frames, int16_t* levels, int8_t* mvs,
+                    uint16_t* recon, uint32_t* coef_bits, uint32_t* mv_bits,
+                    uint64_t* sse, uint64_t* nvalid) {
+  if (xvo_check_params(p) != 0) return -1;
+  int N = p->block;
+  int64_t G = (Bn + 2) / 3;
+  int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
+  int64_t Hb = Hp / N, Wb = Wp / N, fsz = 3 * Hp * Wp;
+  int64_t ngop = (T + p->gop - 1) / p->gop;
+  xvo_stats(data, dtype, T, H, W, Bn, mn, mx, NULL);
+  uint64_t* part = (uint64_t*)calloc((size_t)(G * ngop * 6), sizeof(uint64_t));
+  if (!part) return -2;
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int64_t u = 0; u < G * ngop; u++) {
+    int64_t g = u / ngop, k = u % ngop;
+    int64_t t0 = k * p->gop;
+    int64_t len = T - t0 < p->gop ? T - t0 : p->gop;
+    int64_t ft = g * T + t0;
+    err |= xvo_encode_gop(data, dtype, T, H, W, Bn, mn, mx, p, g, t0, len,
+                          frames + ft * fsz, levels + ft * fsz, mvs + ft * Hb * Wb * 2,
+                          recon + ft * fsz, coef_bits + ft * 3 * Hb * Wb,
+                          mv_bits + ft * Hb * Wb, part + u * 6, part + u * 6 + 3);
+  }
+  for (int64_t b = 0; b < Bn; b++) { sse[b] = 0; nvalid[b] = 0; }
+  for (int64_t u = 0; u < G * ngop; u++) {
+    int64_t g = u / ngop;
+    for (int c = 0; c < 3; c++) {
+      int64_t b = 3 * g + c;
+      if (b >= Bn) continue;
+      sse[b] += part[u * 6 + c];
+      nvalid[b] += part[u * 6 + 3 + c];
+    }
+  }
+  free(part);
+  return err ? -1 : 0;
+}
+
+int xvo_decode_cube(const xvo_params* p, int64_t T, int64_t H, int64_t W,
+                    int64_t Bn, const int16_t* levels, const int8_t* mvs,
+                    uint16_t* recon) {
+  if (xvo_check_params(p) != 0) return -1;
+  int N = p->block;
+  int64_t G = (Bn + 2) / 3;
+  int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
+  int64_t Hb = Hp / N, Wb = Wp / N, fsz = 3 * Hp * Wp;
+  int64_t ngop = (T + p->gop - 1) / p->gop;
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int64_t u = 0; u < G * ngop; u++) {
+    int64_t g = u / ngop, k = u % ngop;
+    int64_t t0 = k * p->gop;
+    int64_t len = T - t0 < p->gop ? T - t0 : p->gop;
+    int64_t ft = g * T + t0;
+    err |= xvo_decode_gop(p, H, W, len, levels + ft * fsz, mvs + ft * Hb * Wb * 2,
+                          recon + ft * fsz);
+  }
+  return err ? -1 : 0;
+}
+
+/* Decoded cube in the caller's dtype, [T][H][W][Bn] (inverse conversion of
+ * Sec. II-A; output rounding paper silent, reading in xvo_cast_output). */
+void xvo_denormalize_cube(const uint16_t* recon, int64_t T, int64_t H,
+                          int64_t W, int64_t Bn, int N, int B, const double* mn,
+                          const double* mx, int out_dtype, void* out) {
+  int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
+  for (int64_t t = 0; t < T; t++)
+    for (int64_t y = 0; y < H; y++)
+      for (int64_t x = 0; x < W; x++)
+        for (int64_t b = 0; b < Bn; b++) {
+          int64_t g = b / 3, c = b % 3;
+          int32_t q = recon[(((g * T + t) * 3 + c) * Hp + y) * Wp + x];
+          double v = xvo_cast_output(xvo_denormalize(q, mn[b], mx[b], B), out_dtype);
+          int64_t o = ((t * H + y) * W + x) * Bn + b;
+          if (out_dtype == XVO_U16)
+            ((uint16_t*)out)[o] = (uint16_t)v;
+          else
+            ((float*)out)[o] = (float)v;
+        }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Metrics (Sec. II-C).                                                       */
+/* PSNR with a given peak: 10 log10(peak^2 / MSE); MSE = 0 gives +inf.        */
+/* ------------------------------------------------------------------------- */
+double xvo_psnr(double peak, double sse, double n) {
+  if (n <= 0.0) return NAN;
+  double mse = sse / n;
+  if (mse == 0.0) return INFINITY;
+  return 10.0 * log10(peak * peak / mse);
+}
+
+/* Integer-domain PSNR of band b: peak L = 2^B - 1 (the maximum of the
+ * converted band whenever it is not constant). */
+double xvo_psnr_int(int B, uint64_t sse, uint64_t n) {
+  return xvo_psnr((double)((1 << B) - 1), (double)sse, (double)n);
+}
+
+/* bpppb = stored bits / (pixels x bands) (Sec. II-C), real pixels and bands. */
+double xvo_bpppb(uint64_t bits, int64_t T, int64_t H, int64_t W, int64_t Bn) {
+  return (double)bits / ((double)T * (double)H * (double)W * (double)Bn);
+}
+
+/* Physical-domain squared error of band b over valid samples, decoded in the
+ * original dtype; Neumaier-compensated summation. */
+void xvo_phys_sse(const void* data, int dtype, int64_t T, int64_t H, int64_t W,
+                  int64_t Bn, const uint16_t* recon, int N, int B,
+                  const double* mn, const double* mx, double* sse_out) {
+  int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
+  for (int64_t b = 0; b < Bn; b++) {
+    int64_t g = b / 3, c = b % 3;
+    double s = 0.0, comp = 0.0;
+    for (int64_t t = 0; t < T; t++)
+      for (int64_t y = 0; y < H; y++)
+        for (int64_t x = 0; x < W; x++) {
+          double v = read_sample(data, dtype, ((t * H + y) * W + x) * Bn + b);
+          if (isnan(v)) continue;
+          int32_t q = recon[(((g * T + t) * 3 + c) * Hp + y) * Wp + x];
+          double xh = xvo_cast_output(xvo_denormalize(q, mn[b], mx[b], B), dtype);
+          double e = (v - xh) * (v - xh);
+          double tt = s + e;
+          if (fabs(s) >= fabs(e))
+            comp += (s - tt) + e;
+          else
+            comp += (e - tt) + s;
+          s = tt;
+        }
+    sse_out[b] = s + comp;
+  }
+}

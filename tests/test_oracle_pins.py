@@ -1,0 +1,563 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+library routines, exhaustive exact-rational evaluation, brute force on tiny
+inputs, closed forms, invariants of the transform, and the worked examples the
+paper prints (fixtures under tests/golden/).  All of these run on the CPU."""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    out = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                out.append(line.split())
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Band statistics: numpy's NaN-aware reductions
+# ---------------------------------------------------------------------------
+
+def test_stats_match_numpy_nan_reductions():
+    rng = np.random.default_rng(0)
+    cube = rng.normal(300.0, 40.0, (7, 5, 6, 4)).astype(np.float32)
+    cube[rng.random(cube.shape) < 0.3] = np.nan
+    cube[..., 3] = np.nan  # an all-missing band
+    mn, mx, nv = O.stats(cube)
+    for b in range(3):
+        assert mn[b] == float(np.nanmin(cube[..., b]))
+        assert mx[b] == float(np.nanmax(cube[..., b]))
+        assert nv[b] == int(np.count_nonzero(~np.isnan(cube[..., b])))
+    assert mn[3] == 0.0 and mx[3] == 0.0 and nv[3] == 0
+    u = rng.integers(0, 65536, (3, 4, 5, 2)).astype(np.uint16)
+    mn, mx, nv = O.stats(u)
+    assert list(mn) == [float(u[..., b].min()) for b in range(2)]
+    assert list(mx) == [float(u[..., b].max()) for b in range(2)]
+
+
+# ---------------------------------------------------------------------------
+# Missing-data fill: per-pixel brute force and invariants
+# ---------------------------------------------------------------------------
+
+def _nearest_bruteforce(series, t, mn):
+    if not math.isnan(series[t]):
+        return series[t]
+    valid = [u for u in range(len(series)) if not math.isnan(series[u])]
+    if not valid:
+        return mn
+    best = min(valid, key=lambda u: (abs(u - t), u))  # ties to the earlier time
+    return series[best]
+
+
+def _forward_bruteforce(series, t, mn):
+    if not math.isnan(series[t]):
+        return series[t]
+    past = [u for u in range(t) if not math.isnan(series[u])]
+    if past:
+        return series[past[-1]]
+    fut = [u for u in range(t + 1, len(series)) if not math.isnan(series[u])]
+    return series[fut[0]] if fut else mn
+
+
+@pytest.mark.parametrize("mode", [O.FILL_NEAREST, O.FILL_FORWARD])
+def test_fill_matches_bruteforce(mode):
+    rng = np.random.default_rng(1 + mode)
+    T, H, W, Bn = 12, 3, 4, 2
+    cube = rng.integers(0, 1000, (T, H, W, Bn)).astype(np.float32)
+    cube[rng.random(cube.shape) < 0.45] = np.nan
+    cube[:, 0, 0, 1] = np.nan  # a series with no valid sample
+    mn, _, _ = O.stats(cube)
+    ref = _nearest_bruteforce if mode == O.FILL_NEAREST else _forward_bruteforce
+    for b in range(Bn):
+        for y in range(H):
+            for x in range(W):
+                series = [float(v) for v in cube[:, y, x, b]]
+                for t in range(T):
+                    v, ok = O.filled_value(cube, t, y, x, b, mode, mn[b])
+                    assert ok == (not math.isnan(series[t]))
+                    assert not math.isnan(v)
+                    if ok:
+                        assert v == series[t]  # valid samples unchanged
+                    assert v == ref(series, t, mn[b])
+
+
+def test_forward_fill_holds_last_valid_value():
+    # Sec. III-B: missing data filled forward, holding the last valid value.
+    s = np.array([np.nan, 5, np.nan, np.nan, 7, np.nan], np.float32).reshape(6, 1, 1, 1)
+    got = [O.filled_value(s, t, 0, 0, 0, O.FILL_FORWARD, 0.0)[0] for t in range(6)]
+    assert got == [5.0, 5.0, 5.0, 5.0, 7.0, 7.0]
+    got = [O.filled_value(s, t, 0, 0, 0, O.FILL_NEAREST, 0.0)[0] for t in range(6)]
+    assert got == [5.0, 5.0, 5.0, 7.0, 7.0, 7.0]  # t=2 tie -> earlier; t=3 nearer 7
+
+
+# ---------------------------------------------------------------------------
+# Bit-depth conversion: exhaustive exact-rational check over every u16 input
+# ---------------------------------------------------------------------------
+
+def _norm_exact(x, mn, mx, B):
+    L = (1 << B) - 1
+    if mx == mn:
+        return 0
+    v = Fraction(int(x) - int(mn)) * L / (int(mx) - int(mn)) + Fraction(1, 2)
+    q = math.floor(v)
+    return min(max(q, 0), L)
+
+
+@pytest.mark.parametrize("mn,mx,B", [(0, 65535, 12), (0, 10000, 10), (123, 9876, 12),
+                                     (500, 501, 10), (7, 7, 12), (0, 1, 8), (1000, 4095, 12)])
+def test_normalize_exhaustive_u16(mn, mx, B):
+    L = (1 << B) - 1
+    prev = -1
+    lo, hi = mn, mx
+    for x in range(0, 65536):
+        xc = min(max(x, lo), hi)  # inputs of a band lie within its [mn, mx]
+        q = O.normalize(float(xc), float(mn), float(mx), B)
+        if xc == x:
+            assert q == _norm_exact(xc, mn, mx, B), (x, mn, mx, B)
+        assert q >= prev  # monotone
+        prev = q
+    if mx > mn:
+        assert O.normalize(float(mn), float(mn), float(mx), B) == 0
+        assert O.normalize(float(mx), float(mn), float(mx), B) == L
+
+
+def test_denormalize_endpoints_and_constant_band():
+    assert O.denormalize(0, 100.0, 9000.0, 12) == 100.0
+    assert O.denormalize(4095, 100.0, 9000.0, 12) == 9000.0
+    assert O.denormalize(0, 42.5, 42.5, 10) == 42.5  # constant band decodes exactly
+    # u16 output rounds half up and clamps; f32 output rounds to nearest float
+    assert O.cast_output(2.5, O.U16) == 3.0 and O.cast_output(-3.0, O.U16) == 0.0
+    assert O.cast_output(70000.0, O.U16) == 65535.0
+    assert O.cast_output(0.1, O.F32) == float(np.float32(0.1))
+
+
+# ---------------------------------------------------------------------------
+# Packing (Sec. II-A: R,G,B into the first video; NIR repeated as NIR,NIR,NIR)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("pad_mode", [O.PAD_REPEAT, O.PAD_ZERO])
+def test_pack_worked_example_four_bands(pad_mode):
+    T, H, W, Bn = 2, 4, 4, 4
+    cube = np.zeros((T, H, W, Bn), np.uint16)
+    for b in range(Bn):
+        cube[..., b] = 1000 * (b + 1)
+    cube[0, 0, 0, :] = 0  # make every band non-constant (min 0, max 1000(b+1))
+    mn, mx, _ = O.stats(cube)
+    p = O.CodingParams(bit_depth=10, block=4, pad_mode=pad_mode)
+    assert [O.source_band(0, c, Bn, pad_mode) for c in range(3)] == [0, 1, 2]
+    expect = [3, 3, 3] if pad_mode == O.PAD_REPEAT else [3, -1, -1]
+    assert [O.source_band(1, c, Bn, pad_mode) for c in range(3)] == expect
+    f0, v0 = O.make_frame(cube, mn, mx, p, 0, 1)
+    f1, v1 = O.make_frame(cube, mn, mx, p, 1, 1)
+    assert (f0 == 1023).all() and v0.all()
+    if pad_mode == O.PAD_REPEAT:
+        assert (f1 == 1023).all()
+    else:
+        assert (f1[0] == 1023).all() and (f1[1:] == 0).all()
+    assert v1[0].all() and not v1[1:].any()  # padding channels never count
+
+
+def test_spatial_edge_padding_replicates_last_row_and_column():
+    rng = np.random.default_rng(3)
+    cube = rng.integers(0, 4000, (1, 5, 6, 3)).astype(np.uint16)
+    mn, mx, _ = O.stats(cube)
+    p = O.CodingParams(bit_depth=12, block=4)
+    fr, va = O.make_frame(cube, mn, mx, p, 0, 0)
+    assert fr.shape == (3, 8, 8)
+    for c in range(3):
+        core = fr[c, :5, :6]
+        assert (fr[c, 5:, :6] == core[4:5, :]).all()
+        assert (fr[c, :, 6:] == fr[c, :, 5:6]).all()
+        assert va[c, :5, :6].all() and not va[c, 5:, :].any() and not va[c, :, 6:].any()
+
+
+# ---------------------------------------------------------------------------
+# Motion search: exhaustive Python search with the same key on tiny frames
+# ---------------------------------------------------------------------------
+
+def _me_bruteforce(cur, ref, N, R, bx, by, nch):
+    _, Hp, Wp = cur.shape
+    x0, y0 = bx * N, by * N
+    best = None
+    for dy in range(-R, R + 1):
+        for dx in range(-R, R + 1):
+            if x0 + dx < 0 or y0 + dy < 0 or x0 + dx + N > Wp or y0 + dy + N > Hp:
+                continue
+            a = cur[:nch, y0:y0 + N, x0:x0 + N].astype(np.int64)
+            b = ref[:nch, y0 + dy:y0 + dy + N, x0 + dx:x0 + dx + N].astype(np.int64)
+            key = (int(np.abs(a - b).sum()), abs(dx) + abs(dy), dy, dx)
+            best = key if best is None or key < best else best
+    return best[3], best[2], best[0]
+
+
+@pytest.mark.parametrize("N,R,nch", [(4, 3, 3), (4, 4, 1), (8, 4, 2), (8, 2, 3), (16, 3, 3)])
+def test_motion_search_matches_bruteforce(N, R, nch):
+    rng = np.random.default_rng(N * 100 + R)
+    Hp, Wp = 2 * N, 3 * N
+    for trial in range(3):
+        # few distinct values create many SAD ties, exercising the tie-break
+        cur = rng.integers(0, 4 if trial == 0 else 1024, (3, Hp, Wp)).astype(np.uint16)
+        ref = rng.integers(0, 4 if trial == 0 else 1024, (3, Hp, Wp)).astype(np.uint16)
+        for by in range(Hp // N):
+            for bx in range(Wp // N):
+                assert O.motion_search(cur, ref, N, R, bx, by, nch) == \
+                    _me_bruteforce(cur, ref, N, R, bx, by, nch)
+
+
+def test_motion_search_planted_shift_and_flat():
+    rng = np.random.default_rng(7)
+    N, R = 8, 4
+    big = rng.integers(0, 1024, (3, 48, 48)).astype(np.uint16)
+    ref = big[:, 8:40, 8:40].copy()
+    for (sx, sy) in [(2, -3), (-4, 4), (0, 1)]:
+        # cur(y, x) = ref(y + sy, x + sx): the best vector is (sx, sy), SAD 0
+        cur = big[:, 8 + sy:40 + sy, 8 + sx:40 + sx].copy()
+        dx, dy, sad = O.motion_search(cur, ref, N, R, 1, 1)
+        assert (dx, dy, sad) == (sx, sy, 0)
+    flat = np.full((3, 32, 32), 77, np.uint16)
+    assert O.motion_search(flat, flat, N, R, 1, 2) == (0, 0, 0)
+
+
+# ---------------------------------------------------------------------------
+# Transform matrix invariants (integer approximation of the DCT-II basis)
+# ---------------------------------------------------------------------------
+
+def _float_basis(N):
+    k = np.arange(N)[:, None]
+    n = np.arange(N)[None, :]
+    F = 64.0 * math.sqrt(2.0) * np.cos(np.pi * (2 * n + 1) * k / (2 * N))
+    F[0, :] = 64.0
+    return F
+
+
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_dct_matrix_invariants(N):
+    M = O.dct_matrix(N).astype(np.int64)
+    M32 = O.dct_matrix(32).astype(np.int64)
+    assert (M[0] == 64).all()
+    for k in range(N):
+        assert (M[k] == M32[k * (32 // N), :N]).all()
+        assert (M[k, ::-1] == (-1) ** k * M[k]).all()  # even/odd symmetry
+        if k > 0:
+            assert M[k].sum() == 0
+        assert np.abs(M[k]).sum() <= 64 * N  # int16 headroom of the forward path
+    assert np.abs(M[0]).sum() == 64 * N
+    # every entry within 1 of the rounded scaled cosine, and within 1.37 of it
+    F = _float_basis(N)
+    assert np.abs(M - np.round(F)).max() <= 1
+    assert np.abs(M - F).max() < 1.37
+    # near-orthogonality: M M^T = 4096 N (I + E), |E| small
+    G = (M @ M.T) / (4096.0 * N)
+    assert np.abs(np.diag(G) - 1).max() < 1.5e-3
+    assert np.abs(G - np.diag(np.diag(G))).max() < 3e-3
+
+
+def test_dct4_matrix_is_the_textbook_one():
+    assert O.dct_matrix(4).tolist() == [[64, 64, 64, 64], [83, 36, -36, -83],
+                                        [64, -64, -64, 64], [36, -83, 83, -36]]
+
+
+# ---------------------------------------------------------------------------
+# Forward / inverse transform
+# ---------------------------------------------------------------------------
+
+def _orth_dct(N):
+    k = np.arange(N)[:, None]
+    n = np.arange(N)[None, :]
+    Cm = math.sqrt(2.0 / N) * np.cos(np.pi * (2 * n + 1) * k / (2 * N))
+    Cm[0, :] = math.sqrt(1.0 / N)
+    return Cm
+
+
+@pytest.mark.parametrize("B", [8, 10, 12])
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_forward_transform_vs_float_dct(N, B):
+    """C = 2^(15-B-log2 N) * (orthonormal 2-D DCT-II of r), up to the integer
+    matrix's approximation (<4% of the largest coefficient); a transposed
+    result or a wrong stage order fails this on non-symmetric inputs."""
+    rng = np.random.default_rng(N + B)
+    L = (1 << B) - 1
+    Cm = _orth_dct(N)
+    scale = 2.0 ** (15 - B - int(math.log2(N)))
+    for _ in range(20):
+        r = rng.integers(-L, L + 1, (N, N))
+        got = O.forward_transform(r, B).astype(np.float64)
+        X = Cm @ r @ Cm.T * scale
+        assert np.abs(got - X).max() <= 0.04 * np.abs(X).max() + 2
+    # smooth (ramp) residual: energy compaction into the first column/row
+    r = np.tile(np.arange(N) * (L // (2 * N)), (N, 1))  # varies along x only
+    got = O.forward_transform(r, B)
+    assert (got[1:, :] == 0).all()  # no vertical frequency content
+    assert got[0, 1] < 0  # a rising ramp has a negative first cosine coefficient
+
+
+@pytest.mark.parametrize("B", [8, 10, 12])
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_forward_constant_block_closed_form(N, B):
+    L = (1 << B) - 1
+    s1 = int(math.log2(N)) + B - 9
+    s2 = int(math.log2(N)) + 6
+    for v in [-L, -1, 0, 1, 37, L]:
+        r = np.full((N, N), v, np.int64)
+        got = O.forward_transform(r, B)
+        t = (64 * N * v + (1 << (s1 - 1))) >> s1
+        dc = (64 * N * t + (1 << (s2 - 1))) >> s2
+        assert got[0, 0] == dc
+        assert (got.flatten()[1:] == 0).all()
+
+
+@pytest.mark.parametrize("B", [8, 10, 12])
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_inverse_transform_basis_images_and_roundtrip(N, B):
+    Cm = _orth_dct(N)
+    # a single coefficient d at (l, k) reconstructs d * 2^(B+log2N-15) * basis
+    for (l, k) in [(0, 0), (0, 1), (1, 0), (N - 1, 2), (3 % N, N - 1)]:
+        d = np.zeros((N, N), np.int64)
+        d[l, k] = 4000
+        got = O.inverse_transform(d, B).astype(np.float64)
+        expect = 4000 * 2.0 ** (B + int(math.log2(N)) - 15) * np.outer(Cm[l], Cm[k])
+        assert np.abs(got - expect).max() <= 0.03 * np.abs(expect).max() + 1.0
+    # forward then inverse without quantisation: identity up to the integer
+    # matrix's non-orthogonality (a few % of full scale on white noise)
+    rng = np.random.default_rng(11 * N + B)
+    L = (1 << B) - 1
+    for _ in range(50):
+        r = rng.integers(-L, L + 1, (N, N))
+        back = O.inverse_transform(O.forward_transform(r, B), B)
+        assert np.abs(back - r).max() <= 0.02 * L + 2
+    smooth = np.add.outer(np.arange(N), np.arange(N)) * (L // (4 * N))
+    back = O.inverse_transform(O.forward_transform(smooth, B), B)
+    assert np.abs(back - smooth).max() <= 2 + (L >> 9)
+
+
+def test_transform_dynamic_range_fits_int16():
+    for B in (8, 10, 12):
+        L = (1 << B) - 1
+        for N in (4, 8, 16, 32):
+            M = O.dct_matrix(N)
+            worst = np.sign(M[0]) * L  # DC row attains the row-sum bound
+            r = np.tile(worst, (N, 1))
+            C = O.forward_transform(r, B)
+            assert np.abs(C).max() < 32768
+
+
+# ---------------------------------------------------------------------------
+# Quantiser scales, dead zone and step size
+# ---------------------------------------------------------------------------
+
+def test_scale_tables_closed_forms():
+    iq = [O.iq_scale(k) for k in range(6)]
+    qf = [O.q_scale(k) for k in range(6)]
+    assert iq == [round(64 * 2 ** ((k - 4) / 6)) for k in range(6)]
+    assert iq == [40, 45, 51, 57, 64, 72]
+    assert qf == [26214, 23302, 20560, 18396, 16384, 14564]
+    for k in range(6):
+        assert abs(qf[k] * iq[k] - (1 << 20)) <= iq[k] / 2
+
+
+@pytest.mark.parametrize("B", [8, 10, 12])
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_quant_dequant_within_one_step(N, B):
+    rng = np.random.default_rng(N * B)
+    for qp in (-6 * (B - 8), 0, 17, 27, 37, 51):
+        qP = qp + 6 * (B - 8)
+        qbits = 29 + qP // 6 - B - int(math.log2(N))
+        step = (1 << qbits) / O.q_scale(qP % 6)  # quantisation step in C units
+        c = rng.integers(-32768, 32768, (N, N)).astype(np.int32)
+        for intra in (True, False):
+            lev = O.quantize(c, B, qp, intra)
+            d = O.dequantize(lev, B, qp)
+            sat = np.abs(lev) == 32767
+            ok = ~sat & (np.abs(d) < 32767)
+            assert (np.abs(d - c)[ok] <= step + 1).all()
+            # dead zone: |C| * Qf + offset below 2^qbits quantises to zero
+            off = (171 if intra else 85) << (qbits - 9)
+            small = np.abs(c).astype(np.int64) * O.q_scale(qP % 6) + off < (1 << qbits)
+            assert (lev[small] == 0).all()
+            assert (np.sign(lev) * np.sign(c) >= 0).all()
+
+
+def test_qp_plus_6_doubles_the_step():
+    B, N = 10, 8
+    c = np.arange(-3000, 3000, 93, dtype=np.int32)[:64].reshape(8, 8)
+    for qp in (10, 20, 30):
+        # the dequantised value of a level doubles when QP rises by 6
+        lev = np.full((N, N), 5, np.int16)
+        d1 = O.dequantize(lev, B, qp)
+        d2 = O.dequantize(lev, B, qp + 6)
+        assert (np.abs(d2 - 2 * d1) <= 1).all()
+        # and the level of a coefficient halves (up to rounding)
+        l1 = O.quantize(c, B, qp, False).astype(np.int64)
+        l2 = O.quantize(c, B, qp + 6, False).astype(np.int64)
+        assert (np.abs(l1 - 2 * l2) <= 1).all()
+
+
+# ---------------------------------------------------------------------------
+# Exp-Golomb lengths, scan order and coefficient bits
+# ---------------------------------------------------------------------------
+
+def _eg_write(k):
+    m = k + 1
+    nbits = m.bit_length()
+    return "0" * (nbits - 1) + format(m, "b")
+
+
+def test_ue_len_matches_an_explicit_bit_writer():
+    for k in list(range(0, 5000)) + [2 ** 20 - 1, 2 ** 20, 2 ** 31 - 1]:
+        assert O.ue_len(k) == len(_eg_write(k))
+    for v in range(-3000, 3001):
+        k = 2 * v - 1 if v > 0 else -2 * v
+        assert O.se_len(v) == len(_eg_write(k))
+
+
+def test_scan_order_4x4_matches_standard_table():
+    expect = [int(y) * 4 + int(x) for x, y in _rows("scan4x4.txt")]
+    assert O.scan_order(4).tolist() == expect
+
+
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_scan_order_is_a_diagonal_permutation(N):
+    o = O.scan_order(N)
+    assert sorted(o.tolist()) == list(range(N * N))
+    keys = [((p % N) + (p // N), p % N) for p in o]
+    assert keys == sorted(keys)
+
+
+def test_coef_bits_closed_forms():
+    for N in (4, 8, 16, 32):
+        z = np.zeros((N, N), np.int16)
+        assert O.coef_bits(z) == 1
+        for v in (1, -1, 5, -300, 32767):
+            z[:] = 0
+            z[0, 0] = v
+            assert O.coef_bits(z) == 3 + O.se_len(v)
+    lev = np.zeros((4, 4), np.int16)
+    lev[0, 1] = 2   # (x=1, y=0): scan position 2 -> run 2
+    lev[2, 1] = -1  # (x=1, y=2): scan position 7 -> run 4 after position 2
+    bits = 1 + len(_eg_write(1)) + len(_eg_write(2)) + len(_eg_write(3)) \
+        + len(_eg_write(4)) + len(_eg_write(2))
+    assert O.coef_bits(lev) == bits
+    assert O.mv_bits(3, -2, 1, 0) == len(_eg_write(3)) + len(_eg_write(4))
+
+
+# ---------------------------------------------------------------------------
+# End to end on special cases
+# ---------------------------------------------------------------------------
+
+def _dc_closed_form(N, B, v):
+    s1 = int(math.log2(N)) + B - 9
+    s2 = int(math.log2(N)) + 6
+    t = (64 * N * v + (1 << (s1 - 1))) >> s1
+    return (64 * N * t + (1 << (s2 - 1))) >> s2
+
+
+def test_constant_cube_end_to_end():
+    """A constant cube normalises to 0.  The I picture codes r = -2^(B-1) as a
+    DC-only block; every P candidate ties, so the vector is (0,0) and the
+    residual is again constant per block."""
+    T, H, W, Bn = 5, 16, 16, 3
+    B, N, qp = 10, 8, 27
+    cube = np.full((T, H, W, Bn), 1234, np.uint16)
+    p = O.CodingParams(bit_depth=B, qp=qp, block=N, search_range=3, gop=5)
+    enc = O.encode_cube(cube, p)
+    assert (enc["frames"] == 0).all()
+    assert (enc["mvs"] == 0).all()
+    qP = qp + 6 * (B - 8)
+    qbits = 29 + qP // 6 - B - int(math.log2(N))
+    prev = np.zeros((N, N), np.int64) + (1 << (B - 1))  # I prediction
+    for f in range(T):
+        intra = f == 0
+        r = 0 - int(prev[0, 0])
+        dc = _dc_closed_form(N, B, r)
+        lvl = (abs(dc) * O.q_scale(qP % 6) + ((171 if intra else 85) << (qbits - 9))) >> qbits
+        lvl = -lvl if dc < 0 else lvl
+        lev = enc["levels"][0, f]
+        assert (lev[..., 0, 0] == lvl).all()
+        rest = lev.reshape(lev.shape[:3] + (N * N,))[..., 1:]
+        assert (rest == 0).all()
+        bits = 1 if lvl == 0 else 3 + O.se_len(lvl)
+        assert (enc["coef_bits"][0, f] == bits).all()
+        assert (enc["mv_bits"][0, f] == (0 if intra else 2)).all()
+        rec = enc["recon"][0, f]
+        assert (rec == rec[0, 0, 0]).all()
+        prev = np.full((N, N), int(rec[0, 0, 0]), np.int64)
+    dec = O.decode_cube(p, cube.shape, enc["levels"], enc["mvs"])
+    assert (dec == enc["recon"]).all()
+    # a constant band decodes back to its value exactly
+    out = O.denormalize_cube(dec, cube.shape, N, B, enc["mn"], enc["mx"], O.U16)
+    assert (out == cube).all()
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_decode_reproduces_encoder_reconstruction(dtype):
+    rng = np.random.default_rng(5)
+    T, H, W, Bn = 9, 20, 27, 4
+    base = rng.integers(0, 5000, (H + 8, W + 8, Bn))
+    frames = [np.roll(base, (t % 3, -(t % 2)), axis=(0, 1))[:H, :W] +
+              rng.integers(0, 50, (H, W, Bn)) for t in range(T)]
+    cube = np.stack(frames).astype(np.uint16 if dtype == "u16" else np.float32)
+    if dtype == "f32":
+        cube[rng.random(cube.shape) < 0.1] = np.nan
+    for N in (4, 8):
+        p = O.CodingParams(bit_depth=12, qp=22, block=N, search_range=3, gop=4,
+                           pad_mode=O.PAD_REPEAT)
+        enc = O.encode_cube(cube, p)
+        dec = O.decode_cube(p, cube.shape, enc["levels"], enc["mvs"])
+        assert (dec == enc["recon"]).all()
+        assert enc["mvs"][:, 1::4].any()  # P pictures found non-zero motion
+
+
+# ---------------------------------------------------------------------------
+# Metrics (Sec. II-C) and the paper's worked examples
+# ---------------------------------------------------------------------------
+
+def test_psnr_constant_offset_closed_form():
+    for B in (8, 10, 12):
+        L = (1 << B) - 1
+        for c in (1, 3, 17):
+            n = 12345
+            assert abs(O.psnr_int(B, c * c * n, n) - 20 * math.log10(L / c)) < 1e-9
+    assert O.psnr_int(10, 0, 100) == math.inf  # lossless is printed as infinity
+
+
+def test_psnr_worked_example_from_paper():
+    for peak, rmse, printed, dec in _rows("psnr_worked_example.txt"):
+        n = 1000
+        got = O.psnr(float(peak), float(rmse) ** 2 * n, n)
+        # 53.3855 dB; the paper prints it truncated to two decimals
+        ulp = 10.0 ** -int(dec)
+        assert float(printed) <= got < float(printed) + ulp
+
+
+def test_bpppb_reproduces_paper_compression_ratios():
+    T, H, W, Bn = 10, 100, 100, 4
+    for native, bp, printed, _sec in _rows("compression_ratios.txt"):
+        bits = round(float(bp) * T * H * W * Bn)
+        b = O.bpppb(bits, T, H, W, Bn)
+        assert abs(b - float(bp)) < 1e-12
+        assert round(int(native) / b) == pytest.approx(int(printed), rel=0.005)
+
+
+def test_physical_sse_of_lossless_integer_recon():
+    """With recon equal to the converted frames, the physical error is the
+    bit-depth conversion error alone: at most half a converted step, plus
+    half a unit for the u16 output rounding."""
+    rng = np.random.default_rng(9)
+    cube = rng.integers(100, 9000, (3, 8, 8, 3)).astype(np.uint16)
+    p = O.CodingParams(bit_depth=10, block=8)
+    mn, mx, _ = O.stats(cube)
+    frames = np.stack([O.make_frame(cube, mn, mx, p, 0, t)[0] for t in range(3)])[None]
+    sse = O.phys_sse(cube, frames, 8, 10, mn, mx)
+    for b in range(3):
+        step = (mx[b] - mn[b]) / 1023
+        assert sse[b] <= cube[..., 0].size * (step / 2 + 0.5) ** 2
