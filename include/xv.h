@@ -1,0 +1,231 @@
+/*
+ * xv.h -- C ABI of the MI355X transform-coding library (libxv.so).
+ *
+ * The library compresses a multichannel spatiotemporal cube (time x y x x x
+ * bands) the way the paper "Video Compression for Spatiotemporal Earth System
+ * Data" (arXiv 2506.19656) does: every band is converted to B-bit integers
+ * (Sec. II-A, bit-depth conversion), bands are packed in input order into
+ * 3-channel frames (Sec. II-A), missing samples are filled along time
+ * (Sec. III-B), and the frames are coded by a hybrid video coder.  The coder
+ * is the lossy loop of an HEVC-style encoder: integer-pel block motion search
+ * for P pictures, motion-compensated residuals, the H.265 integer DCT-II
+ * (N = 4, 8, 16, 32), a QP-driven dead-zone quantiser, dequantisation and
+ * inverse transform to the reconstruction.  Its rate is measured by
+ * Exp-Golomb code lengths of coefficients and motion vectors (no arithmetic
+ * coder); quality by per-band PSNR whose peak is the band's maximum
+ * (Sec. II-C) and by bits per pixel per band (Sec. II-C).
+ *
+ * All compute runs in HIP kernels on the GPU; the caller hands in device
+ * pointers and a HIP stream (hipStream_t passed as void*, NULL = the null
+ * stream).  Every call is asynchronous on that stream unless stated.
+ *
+ * Status codes: every int-returning call returns XV_OK (0) or a negative
+ * XV_E* code; xv_last_error() returns a thread-local message for the last
+ * failure of the calling thread.  No C++ exception crosses this ABI.
+ *
+ * Data layouts (all C-contiguous, row-major):
+ *   input / output cube   [T][H][W][bands]     (the paper's time, y, x,
+ *                                               channel order, Listing 1)
+ *   converted frames      [G][T][3][Hp][Wp] u16   G = ceil(bands / 3)
+ *   reconstruction        [G][T][3][Hp][Wp] u16   Hp, Wp = H, W rounded up
+ *                                                 to a multiple of N
+ *   levels                [G][T][3][Hb][Wb][N][N] i16 (block-major; inside a
+ *                          block row l = vertical frequency, column k)
+ *   motion vectors        [G][T][Hb][Wb][2] i8 (dx, dy); zero in I pictures
+ *   coefficient bits      [G][T][3][Hb][Wb] u32
+ *   motion-vector bits    [G][T][Hb][Wb] u32
+ */
+#ifndef XV_H
+#define XV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XV_ABI_VERSION 1
+
+/* status codes */
+#define XV_OK 0
+#define XV_EINVAL (-1)    /* null pointer, bad shape, dtype or parameter     */
+#define XV_ENOMEM (-2)    /* device allocation failed or over budget         */
+#define XV_EHIP (-3)      /* HIP runtime error (text in xv_last_error)       */
+#define XV_EBUSY (-4)     /* server queue full                               */
+#define XV_ECANCELED (-5) /* server request cancelled                        */
+#define XV_EPENDING (-6)  /* server request not finished yet                 */
+
+/* element types of a cube */
+#define XV_U16 0
+#define XV_F32 1
+
+/* padding of the last band group when bands % 3 != 0 */
+#define XV_PAD_ZERO 0   /* missing channels are zero                          */
+#define XV_PAD_REPEAT 1 /* missing channels repeat the last band (Sec. II-A)  */
+
+/* missing-data (NaN) fill along time, float input only */
+#define XV_FILL_NEAREST 0 /* value at the nearest valid time, ties earlier   */
+#define XV_FILL_FORWARD 1 /* last valid value (Sec. III-B); leading gaps take
+                             the first valid value                          */
+
+/* xv_params.flags */
+#define XV_FLAG_DROP_WORK 1u /* free converted frames and reconstruction when
+                                the encode completes (physical PSNR and the
+                                export of those buffers become unavailable) */
+
+#define XV_MAX_BANDS 64
+#define XV_MAX_GROUPS 22
+
+/* A cube in device memory: data points to T*H*W*bands elements of dtype. */
+typedef struct {
+  void* data;
+  int32_t dtype; /* XV_U16 or XV_F32 */
+  int32_t reserved;
+  int64_t T, H, W, bands; /* each >= 1; bands <= XV_MAX_BANDS */
+} xv_cube;
+
+/* Coding parameters of one encode. */
+typedef struct {
+  int32_t bit_depth;    /* B in 8..12: samples are converted to [0, 2^B-1]  */
+  int32_t qp;           /* -6(B-8)..51; qP = QP + 6(B-8) drives the step    */
+  int32_t block;        /* N in {4, 8, 16, 32}: prediction and transform    */
+  int32_t search_range; /* R in 0..64: motion search over [-R, R]^2         */
+  int32_t gop;          /* closed GOP length >= 1: one I then gop-1 P       */
+  int32_t pad_mode;     /* XV_PAD_*                                          */
+  int32_t fill_mode;    /* XV_FILL_*                                         */
+  uint32_t flags;       /* XV_FLAG_*                                         */
+} xv_params;
+
+/* Opaque encoded cube: levels, motion vectors, bit counts, band statistics
+ * and (unless XV_FLAG_DROP_WORK) the converted frames and reconstruction,
+ * all in device memory owned by the library. */
+typedef struct xv_encoded xv_encoded;
+
+/* Quality and rate of an encode (Sec. II-C). */
+typedef struct {
+  int32_t bands, groups;
+  double psnr[XV_MAX_BANDS];      /* integer domain, peak 2^B-1            */
+  double psnr_phys[XV_MAX_BANDS]; /* physical domain, peak = band maximum;
+                                     NaN if no original was given or the
+                                     peak is <= 0                          */
+  double sse_phys[XV_MAX_BANDS];
+  uint64_t sse[XV_MAX_BANDS];     /* integer-domain squared error          */
+  uint64_t n_valid[XV_MAX_BANDS]; /* non-missing real samples              */
+  double band_min[XV_MAX_BANDS], band_max[XV_MAX_BANDS];
+  uint64_t coef_bits, mv_bits;    /* rate proxy totals                     */
+  uint64_t header_bits;           /* 128 per band + 256, not in bpppb      */
+  double bpppb;                   /* (coef + mv bits) / (T H W bands)      */
+  double bpppb_group[XV_MAX_GROUPS];
+} xv_metrics;
+
+/* Read-only view of an encoded cube (device pointers owned by the encoded
+ * object, valid until xv_encoded_free; NULL where dropped). */
+typedef struct {
+  int64_t T, H, W, bands, groups, Hp, Wp, Hb, Wb;
+  xv_params params;
+  int32_t src_dtype;
+  int32_t reserved;
+  const uint16_t* frames;
+  const uint16_t* recon;
+  const int16_t* levels;
+  const int8_t* mvs;
+  const uint32_t* coef_bits;
+  const uint32_t* mv_bits;
+  const double* band_min; /* [bands] */
+  const double* band_max; /* [bands] */
+  const uint64_t* sse;    /* [3*groups]: per coded channel; entry 3g+c is band 3g+c */
+  const uint64_t* n_valid;/* [bands] */
+} xv_export;
+
+int xv_abi_version(void);
+const char* xv_status_str(int status);
+const char* xv_last_error(void);
+
+/* Encode a device-resident cube (Sec. II-A conversion and packing, then the
+ * coding loop).  The caller keeps in->data alive and unchanged until the
+ * stream has passed the call.  On success *out receives a new encoded cube
+ * owned by the caller, to be released with xv_encoded_free.  On error *out
+ * is NULL.  Errors: XV_EINVAL, XV_ENOMEM, XV_EHIP. */
+int xv_encode_cube(const xv_cube* in, const xv_params* p, void* hip_stream,
+                   xv_encoded** out);
+
+/* Decode an encoded cube into out (device memory owned by the caller, same
+ * T, H, W, bands as the encoded cube, dtype XV_U16 or XV_F32).  Output
+ * samples are min + q (max - min) / (2^B - 1) rounded half up and clamped
+ * (u16) or rounded to the nearest float (f32).  Missing samples of the
+ * original decode to their filled values.  Errors: XV_EINVAL (shape or dtype
+ * mismatch), XV_ENOMEM, XV_EHIP. */
+int xv_decode_cube(const xv_encoded* e, const xv_cube* out, void* hip_stream);
+
+/* Metrics of an encode (Sec. II-C).  orig may be NULL; otherwise it is the
+ * cube that was encoded and the physical-domain PSNR is computed from it.
+ * Synchronises hip_stream.  m is caller memory.  Errors: XV_EINVAL, XV_EHIP. */
+int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m,
+                  void* hip_stream);
+
+/* Fill a read-only view of the encoded cube's device buffers. */
+int xv_encoded_export(const xv_encoded* e, xv_export* v);
+
+/* Release an encoded cube (stream-ordered on the stream of its encode).
+ * NULL is a no-op. */
+void xv_encoded_free(xv_encoded* e);
+
+/* ---- Batched path: several cubes, one launch per frame step ------------ */
+
+/* Encode n cubes of possibly different shapes and parameters.  Every frame
+ * step launches one kernel per (block size, search range) class covering all
+ * cubes, and the whole step sequence is replayed from a captured HIP graph.
+ * Outputs are identical to n calls of xv_encode_cube.  outs[i] receive the
+ * encoded cubes (all NULL on error). */
+int xv_encode_batch(int n, const xv_cube* cubes, const xv_params* params,
+                    void* hip_stream, xv_encoded** outs);
+
+/* Decode n encoded cubes into outs[i] (as xv_decode_cube, batched). */
+int xv_decode_batch(int n, xv_encoded* const* encs, const xv_cube* outs,
+                    void* hip_stream);
+
+/* ---- Launch geometry (never changes coded outputs) -------------------- */
+
+/* Geometry of the motion-search kernel for one (N, R): blocks per
+ * workgroup along x, candidates per lane along x (even), threads per
+ * workgroup (multiple of 64, <= 512).  Zero fields select defaults. */
+typedef struct {
+  int32_t blocks_per_wg;
+  int32_t cands_per_lane;
+  int32_t threads;
+  int32_t reserved;
+} xv_me_geometry;
+
+int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g);
+int xv_get_me_geometry(int block, int search_range, xv_me_geometry* g);
+
+/* ---- Kernel timing (HIP events on the launch stream) ------------------ */
+
+#define XV_K_STATS 0
+#define XV_K_PACK 1
+#define XV_K_ME 2
+#define XV_K_ENCODE 3
+#define XV_K_DECODE 4
+#define XV_K_DENORM 5
+#define XV_K_METRICS 6
+#define XV_K_COUNT 7
+
+typedef struct {
+  double ms[XV_K_COUNT];       /* summed kernel time per kernel class     */
+  uint64_t launches[XV_K_COUNT];
+  double work[XV_K_COUNT];     /* algorithmic units processed: bytes for
+                                  HBM-bound kernels, SAD terms for motion
+                                  search                                 */
+} xv_profile;
+
+/* Enable (1) or disable (0) per-launch event timing; enabling clears the
+ * counters.  Timing adds an event pair around every launch. */
+int xv_profile_enable(int on);
+/* Synchronises the streams that were timed and returns the totals. */
+int xv_profile_read(xv_profile* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

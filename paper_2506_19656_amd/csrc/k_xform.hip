@@ -1,0 +1,533 @@
+// k_xform.hip -- fused transform coding of one picture step (encode) and its
+// reconstruction from stored levels (decode).
+//
+// Encode, per N x N block of each of the 3 channels of a band group:
+//   prediction (I: the constant 2^(B-1); P: the reference reconstruction
+//   displaced by the block's vector) -> residual -> forward H.265 integer
+//   DCT (rows, shift log2N + B - 9; columns, shift log2N + 6) -> dead-zone
+//   quantisation -> Exp-Golomb rate proxy of the levels in up-right diagonal
+//   scan order -> dequantisation -> inverse DCT (columns, clip to 16 bits,
+//   shift 7; rows, shift 20 - B) -> reconstruction clipped to [0, 2^B-1] ->
+//   squared error over valid real samples.  The vector bits of each block
+//   (signed Exp-Golomb of the difference to the left neighbour's vector) are
+//   counted in the same pass.  The paper leaves the codec internals to x265;
+//   these steps are the stated H.265-style reading of them.
+//
+// Mapping: a workgroup of 192 threads (3 waves) owns a 64-pixel-wide run of
+// blocks (NBW = 64 / N blocks) in one block row and all 3 channels; wave c
+// handles channel c.  Row stages give one thread one block row, column stages
+// one block column; intermediate tiles stay in LDS, so HBM sees each sample
+// read and written once: cur + prediction in, levels + reconstruction out.
+#include "xv_internal.h"
+
+namespace xv {
+
+namespace {
+
+__device__ inline int ue_len(uint32_t k) { return 2 * (31 - __clz((int)(k + 1))) + 1; }
+__device__ inline int se_len(int v) {
+  return ue_len(v > 0 ? (uint32_t)(2 * v - 1) : (uint32_t)(-2 * v));
+}
+__device__ inline int clip16(long long v) {
+  return (int)(v < -32768 ? -32768 : (v > 32767 ? 32767 : v));
+}
+
+template <int N>
+struct Tile {
+  static constexpr int NBW = 64 / N;    // blocks per workgroup along x
+  static constexpr int P = N + 2;       // LDS pitch (int16) of a tile row (odd dword count)
+  static constexpr int L2N = ilog2c(N);
+};
+
+// LDS layout per workgroup (int16 / u16):
+//   CUR, PRED [3][NBW][N][N]  current and prediction rows
+//   TD [3][NBW][N][P]          forward row-stage output transposed ([k][y]);
+//                              each column thread then overwrites its own row
+//                              with the dequantised column ([k][l])
+//   E  [3][NBW][N][P]          inverse column-stage output ([y][k])
+//   L  [3][NBW][N*N]           levels, raster [l][k]
+//   scan [N*N]                 scan position -> raster index
+template <int N>
+struct alignas(16) Lds {
+  uint16_t CUR[3][Tile<N>::NBW][N][N];
+  uint16_t PRED[3][Tile<N>::NBW][N][N];
+  int16_t TD[3][Tile<N>::NBW][N][Tile<N>::P];
+  int16_t E[3][Tile<N>::NBW][N][Tile<N>::P];
+  int16_t L[3][Tile<N>::NBW][N * N];
+  uint16_t scan[N * N];
+};
+
+template <int N>
+__device__ inline void build_scan(uint16_t* scan) {
+  for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+    const int y = i / N, x = i - (i / N) * N;
+    const int d = x + y;
+    const int before = d < N ? d * (d + 1) / 2 : N * N - (2 * N - 1 - d) * (2 * N - d) / 2;
+    const int first_x = d < N ? 0 : d - N + 1;
+    scan[before + x - first_x] = (uint16_t)i;
+  }
+}
+
+struct TileCoord {
+  const FrameJob* job;
+  int by, bx0, Hb, Wb;
+};
+
+template <int N>
+__device__ inline bool locate(const LaunchDesc& jd, TileCoord& tc) {
+  int tl;
+  tc.job = desc_job(jd, blockIdx.x, tl);
+  const FrameJob& job = *tc.job;
+  tc.Hb = job.Hp / N;
+  tc.Wb = job.Wp / N;
+  const int runs = (tc.Wb + Tile<N>::NBW - 1) / Tile<N>::NBW;
+  if (tl >= tc.Hb * runs) return false;
+  tc.by = tl / runs;
+  tc.bx0 = (tl - tc.by * runs) * Tile<N>::NBW;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Matrix products on v_dot2c_i32_i16: two 16x16-bit products per lane-op.
+// Every stage is an outer-product loop over input pairs m: all N outputs
+// accumulate acc[k] += M[k][2m] x[2m] + M[k][2m+1] x[2m+1], the coefficient
+// pairs coming from __constant__ tables through scalar loads (SGPR operands),
+// the input pair from LDS.  Inputs are 16-bit by construction: residuals
+// (|r| <= 4095), row-stage outputs (|T| < 2^15), dequantised levels and the
+// inverse column-stage output (both clipped to 16 bits).
+// ---------------------------------------------------------------------------
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline int dot2(uint32_t coef_pair, uint32_t x_pair, int acc) {
+  return __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, coef_pair),
+                                __builtin_bit_cast(s16x2, x_pair), acc, false);
+}
+
+__host__ __device__ constexpr uint32_t cpair(int lo, int hi) {
+  return ((uint32_t)lo & 0xffffu) | (((uint32_t)hi & 0xffffu) << 16);
+}
+
+template <int N>
+struct PairTables {
+  uint32_t fwd[N / 2][N];  // fwd[m][k] = (M[k][2m], M[k][2m+1]): y = M x
+  uint32_t inv[N / 2][N];  // inv[m][n] = (M[2m][n], M[2m+1][n]): x = M^T y
+};
+
+template <int N>
+constexpr PairTables<N> make_pair_tables() {
+  PairTables<N> t{};
+  for (int m = 0; m < N / 2; m++)
+    for (int k = 0; k < N; k++) {
+      t.fwd[m][k] = cpair(dct_coef(N, k, 2 * m), dct_coef(N, k, 2 * m + 1));
+      t.inv[m][k] = cpair(dct_coef(N, 2 * m, k), dct_coef(N, 2 * m + 1, k));
+    }
+  return t;
+}
+
+__constant__ PairTables<4> kPairs4 = make_pair_tables<4>();
+__constant__ PairTables<8> kPairs8 = make_pair_tables<8>();
+__constant__ PairTables<16> kPairs16 = make_pair_tables<16>();
+__constant__ PairTables<32> kPairs32 = make_pair_tables<32>();
+
+template <int N>
+__device__ inline const PairTables<N>& pairs() {
+  if constexpr (N == 4) return kPairs4;
+  else if constexpr (N == 8) return kPairs8;
+  else if constexpr (N == 16) return kPairs16;
+  else return kPairs32;
+}
+
+// acc[k] = sum_m dot2(table[m][k], src[m]); src: N/2 packed pairs in LDS.
+template <int N, bool FWD>
+__device__ inline void mat_pairs(const uint32_t* src, int (&acc)[N]) {
+  const PairTables<N>& tb = pairs<N>();
+#pragma unroll
+  for (int k = 0; k < N; k++) acc[k] = 0;
+#pragma unroll 1
+  for (int m = 0; m < N / 2; m++) {
+    const uint32_t x = src[m];
+#pragma unroll
+    for (int k = 0; k < N; k++) acc[k] = dot2(FWD ? tb.fwd[m][k] : tb.inv[m][k], x, acc[k]);
+  }
+}
+
+// Packed 16-bit residual pair: (cur - pred) per half.
+__device__ inline uint32_t sub_pairs(uint32_t a, uint32_t b) {
+  const int lo = (int)(a & 0xffffu) - (int)(b & 0xffffu);
+  const int hi = (int)(a >> 16) - (int)(b >> 16);
+  return ((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16);
+}
+
+// Packed u16 row (N samples) between global memory and LDS.
+template <int N>
+__device__ inline void copy_row(const uint16_t* g, uint16_t* l) {
+  if constexpr (N >= 8) {
+#pragma unroll
+    for (int q = 0; q < N / 8; q++) ((uint4*)l)[q] = ((const uint4*)g)[q];
+  } else {
+    *(uint2*)l = *(const uint2*)g;
+  }
+}
+
+// Prediction row into LDS: I -> 2^(B-1); P -> the reference displaced by
+// (dx, dy).  A coded vector keeps the displaced block inside the padded
+// picture; the clamp only guarantees in-bounds reads for a corrupt vector.
+template <int N>
+__device__ inline void pred_row(const FrameJob& job, int c, int y, int x0, int dx, int dy,
+                                uint16_t* dst) {
+  uint32_t* d32 = (uint32_t*)dst;
+  if (job.intra) {
+    const uint32_t h = 1u << (job.bit_depth - 1);
+#pragma unroll
+    for (int j = 0; j < N / 2; j++) d32[j] = h | (h << 16);
+  } else {
+    const int yb = y - (y % N);
+    const int ry = min(max(yb + dy, 0), job.Hp - N) + (y - yb);
+    const int rx = min(max(x0 + dx, 0), job.Wp - N);
+    const uint16_t* rp = job.ref + (size_t)c * job.Hp * job.Wp + (size_t)ry * job.Wp + rx;
+    if ((rx & 1) == 0) {
+      const uint32_t* r32 = (const uint32_t*)rp;
+#pragma unroll
+      for (int j = 0; j < N / 2; j++) d32[j] = r32[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < N / 2; j++) d32[j] = (uint32_t)rp[2 * j] | ((uint32_t)rp[2 * j + 1] << 16);
+    }
+  }
+}
+
+// Dequantisation d = clip16((level * IQ[qP%6] * 16 * 2^(qP/6) + 2^(bd-1)) >> bd).
+__device__ inline int dequant(int lv, long long scale, int bd) {
+  return clip16(((long long)lv * scale + (1ll << (bd - 1))) >> bd);
+}
+
+// Inverse column stage of block column k from the dequantised column stored
+// (as pairs) in the thread's own TD row: E[y][k] = clip16((sum_l M[l][y] d[l] + 64) >> 7).
+template <int N>
+__device__ inline void inverse_column(const int16_t* drow, int16_t (*E)[Tile<N>::P], int k) {
+  int acc[N];
+  mat_pairs<N, false>((const uint32_t*)drow, acc);
+#pragma unroll
+  for (int y = 0; y < N; y++) E[y][k] = (int16_t)clip16(((long long)acc[y] + 64) >> 7);
+}
+
+// Inverse row stage and reconstruction of block row r into packed pairs.
+template <int N>
+__device__ inline void inverse_row(const int16_t* Erow, const uint16_t* pred, int B,
+                                   uint32_t (&rp)[N / 2]) {
+  const int sh = 20 - B;
+  const int rnd = 1 << (19 - B);
+  const int Lmax = (1 << B) - 1;
+  int acc[N];
+  mat_pairs<N, false>((const uint32_t*)Erow, acc);
+  const uint32_t* p32 = (const uint32_t*)pred;
+#pragma unroll
+  for (int j = 0; j < N / 2; j++) {
+    const uint32_t pp = p32[j];
+    int v0 = (int)(pp & 0xffffu) + ((acc[2 * j] + rnd) >> sh);
+    int v1 = (int)(pp >> 16) + ((acc[2 * j + 1] + rnd) >> sh);
+    v0 = v0 < 0 ? 0 : (v0 > Lmax ? Lmax : v0);
+    v1 = v1 < 0 ? 0 : (v1 > Lmax ? Lmax : v1);
+    rp[j] = (uint32_t)v0 | ((uint32_t)v1 << 16);
+  }
+}
+
+template <int N>
+__device__ inline void store_row_packed(uint16_t* p, const uint32_t (&v)[N / 2]) {
+  if constexpr (N >= 8) {
+#pragma unroll
+    for (int q = 0; q < N / 8; q++)
+      ((uint4*)p)[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  } else {
+    *(uint2*)p = make_uint2(v[0], v[1]);
+  }
+}
+
+// Rate proxy of every block of channel c in the tile (one wave per channel).
+template <int N>
+__device__ inline unsigned long long block_bits(Lds<N>& s, const FrameJob& job,
+                                                const TileCoord& tc, int c) {
+  constexpr int NBW = Tile<N>::NBW;
+  constexpr int S = N * N < 64 ? N * N : 64;  // lanes per block segment
+  constexpr int BPC = 64 / S;                  // blocks per pass
+  constexpr int CPB = (N * N) / S;             // chunks per block
+  const int lane = threadIdx.x & 63;
+  const int seg = lane / S, pin = lane - seg * S;
+  unsigned long long total = 0;
+  for (int bb = 0; bb < NBW; bb += BPC) {
+    const int b = bb + seg;
+    const bool vb = (tc.bx0 + b) < tc.Wb;
+    int last = -1;
+    int acc = 0, nnz = 0;
+#pragma unroll
+    for (int ci = 0; ci < CPB; ci++) {
+      const int p = ci * S + pin;
+      const int lv = vb ? (int)s.L[c][b][s.scan[p]] : 0;
+      const unsigned long long m = __ballot(lv != 0);
+      const unsigned long long segm = (S == 64) ? m : ((m >> (seg * S)) & ((1ull << S) - 1));
+      const unsigned long long below = segm & ((1ull << pin) - 1);
+      const int prev = below ? ci * S + 63 - __clzll((long long)below) : last;
+      if (lv != 0) acc += ue_len((uint32_t)(p - prev - 1)) + se_len(lv);
+      nnz += __popcll(segm);
+      if (segm) last = ci * S + 63 - __clzll((long long)segm);
+    }
+#pragma unroll
+    for (int off = S / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    const uint32_t bits = 1u + (nnz > 0 ? (uint32_t)(ue_len((uint32_t)(nnz - 1)) + acc) : 0u);
+    if (pin == 0 && vb) {
+      job.cbits[((size_t)c * tc.Hb + tc.by) * tc.Wb + tc.bx0 + b] = bits;
+      total += bits;
+    }
+  }
+  return total;
+}
+
+__device__ inline unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int N>
+__global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
+  constexpr int NBW = Tile<N>::NBW;
+  constexpr int L2N = Tile<N>::L2N;
+  __shared__ Lds<N> s;
+  TileCoord tc;
+  if (!locate<N>(jr, tc)) return;
+  const FrameJob& job = *tc.job;
+  build_scan<N>(s.scan);
+
+  const int t = threadIdx.x;
+  const int c = t >> 6;
+  const int rem = t & 63;
+  const int r = rem / NBW;      // block row (row stages) / column (column stages)
+  const int b = rem - r * NBW;
+  const int bx = tc.bx0 + b;
+  const bool vb = bx < tc.Wb;
+  const int B = job.bit_depth;
+  const size_t plane = (size_t)job.Hp * job.Wp;
+  const int x0 = bx * N;
+  const int y = tc.by * N + r;
+
+  int dx = 0, dy = 0;
+  if (vb && !job.intra) {
+    const int8_t* mv = job.mv + ((size_t)tc.by * tc.Wb + bx) * 2;
+    dx = mv[0];
+    dy = mv[1];
+  }
+
+  // Forward row stage of row r: T[y][k] = (sum_x M[k][x] res[x] + 2^(s1-1)) >> s1,
+  // stored transposed.
+  if (vb) {
+    copy_row<N>(job.cur + c * plane + (size_t)y * job.Wp + x0, s.CUR[c][b][r]);
+    pred_row<N>(job, c, y, x0, dx, dy, s.PRED[c][b][r]);
+    const uint32_t* c32 = (const uint32_t*)s.CUR[c][b][r];
+    const uint32_t* p32 = (const uint32_t*)s.PRED[c][b][r];
+    const PairTables<N>& tb = pairs<N>();
+    int acc[N];
+#pragma unroll
+    for (int k = 0; k < N; k++) acc[k] = 0;
+#pragma unroll 1
+    for (int m = 0; m < N / 2; m++) {
+      const uint32_t xr = sub_pairs(c32[m], p32[m]);
+#pragma unroll
+      for (int k = 0; k < N; k++) acc[k] = dot2(tb.fwd[m][k], xr, acc[k]);
+    }
+    const int s1 = L2N + B - 9;
+    const int rnd1 = 1 << (s1 - 1);
+#pragma unroll
+    for (int k = 0; k < N; k++) s.TD[c][b][k][r] = (int16_t)((acc[k] + rnd1) >> s1);
+  }
+  __syncthreads();
+
+  // Column stage of column k: forward transform, quantise, dequantise (into
+  // the thread's own TD row), inverse column transform.
+  if (vb) {
+    const int k = r;
+    const int qP = job.qp + 6 * (B - 8);
+    const int qbits = 29 + qP / 6 - B - L2N;
+    const uint32_t off = (uint32_t)(job.intra ? 171 : 85) << (qbits - 9);
+    const uint32_t qf = (uint32_t)kQf[qP % 6];
+    const long long scale = (long long)kIQ[qP % 6] * 16ll << (qP / 6);
+    const int bd = B + L2N - 5;
+    int16_t* row = s.TD[c][b][k];
+    int acc[N];
+    mat_pairs<N, true>((const uint32_t*)row, acc);
+#pragma unroll
+    for (int l = 0; l < N; l++) {
+      const int C = (acc[l] + (1 << (L2N + 5))) >> (L2N + 6);
+      const uint32_t a = (uint32_t)(C < 0 ? -C : C);
+      uint32_t mq = (a * qf + off) >> qbits;
+      mq = mq > 32767u ? 32767u : mq;
+      const int lv = C < 0 ? -(int)mq : (int)mq;
+      s.L[c][b][l * N + k] = (int16_t)lv;
+      row[l] = (int16_t)dequant(lv, scale, bd);
+    }
+    inverse_column<N>(row, s.E[c][b], k);
+  }
+  __syncthreads();
+
+  // Levels out (block-major), coalesced 16-byte chunks.
+  {
+    constexpr int CH = (N * N) / 8;  // uint4 chunks per block
+    for (int e = t; e < 3 * NBW * CH; e += blockDim.x) {
+      const int cb = e / CH, q = e - cb * CH;
+      const int cc = cb / NBW, bb = cb - cc * NBW;
+      if (tc.bx0 + bb >= tc.Wb) continue;
+      int16_t* dst = job.lev + (((size_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb) * (N * N);
+      ((uint4*)dst)[q] = ((const uint4*)s.L[cc][bb])[q];
+    }
+  }
+
+  // Inverse row stage, reconstruction, squared error.
+  unsigned long long sse = 0;
+  if (vb) {
+    uint32_t rp[N / 2];
+    inverse_row<N>(s.E[c][b][r], s.PRED[c][b][r], B, rp);
+    store_row_packed<N>(job.rec + c * plane + (size_t)y * job.Wp + x0, rp);
+    if (c < job.nch && y < job.H) {
+      const bool usemask = job.vmask != nullptr && *job.nan_total != 0u;
+      const uint8_t* vm = usemask ? job.vmask + c * plane + (size_t)y * job.Wp + x0 : nullptr;
+      const uint32_t* c32 = (const uint32_t*)s.CUR[c][b][r];
+#pragma unroll
+      for (int j = 0; j < N; j++) {
+        const int cv = (int)((c32[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        const int rv = (int)((rp[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        const bool ok = (x0 + j < job.W) && (!usemask || vm[j]);
+        const int e = cv - rv;
+        sse += ok ? (unsigned long long)(e * e) : 0ull;
+      }
+    }
+  }
+  sse = wave_sum(sse);
+  if ((t & 63) == 0 && c < job.nch && sse) atomicAdd(&job.sse[c], sse);
+
+  // Rate proxy per block and channel; vector bits.
+  unsigned long long cb_total = block_bits<N>(s, job, tc, c);
+  cb_total = wave_sum(cb_total);
+  unsigned long long mvb = 0;
+  if (c == 0 && r == 0 && vb) {
+    int8_t* mv = job.mv + ((size_t)tc.by * tc.Wb + bx) * 2;
+    uint32_t bits = 0;
+    if (job.intra) {
+      mv[0] = 0;
+      mv[1] = 0;
+    } else {
+      int pmx = 0, pmy = 0;
+      if (bx > 0) {
+        pmx = mv[-2];
+        pmy = mv[-1];
+      }
+      bits = (uint32_t)(se_len(dx - pmx) + se_len(dy - pmy));
+    }
+    job.mbits[(size_t)tc.by * tc.Wb + bx] = bits;
+    mvb = bits;
+  }
+  if (c == 0) mvb = wave_sum(mvb);
+  if ((t & 63) == 0) {
+    if (cb_total) atomicAdd(&job.bits[0], cb_total);
+    if (c == 0 && mvb) atomicAdd(&job.bits[1], mvb);
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
+  constexpr int NBW = Tile<N>::NBW;
+  constexpr int L2N = Tile<N>::L2N;
+  __shared__ Lds<N> s;
+  TileCoord tc;
+  if (!locate<N>(jr, tc)) return;
+  const FrameJob& job = *tc.job;
+  const int t = threadIdx.x;
+  const int c = t >> 6;
+  const int rem = t & 63;
+  const int r = rem / NBW;
+  const int b = rem - r * NBW;
+  const int bx = tc.bx0 + b;
+  const bool vb = bx < tc.Wb;
+  const int B = job.bit_depth;
+  const size_t plane = (size_t)job.Hp * job.Wp;
+  const int x0 = bx * N;
+  const int y = tc.by * N + r;
+
+  {
+    constexpr int CH = (N * N) / 8;
+    for (int e = t; e < 3 * NBW * CH; e += blockDim.x) {
+      const int cb = e / CH, q = e - cb * CH;
+      const int cc = cb / NBW, bb = cb - cc * NBW;
+      if (tc.bx0 + bb >= tc.Wb) continue;
+      const int16_t* src =
+          job.lev + (((size_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb) * (N * N);
+      ((uint4*)s.L[cc][bb])[q] = ((const uint4*)src)[q];
+    }
+  }
+  if (vb) {
+    int dx = 0, dy = 0;
+    if (!job.intra) {
+      const int8_t* mv = job.mv + ((size_t)tc.by * tc.Wb + bx) * 2;
+      dx = mv[0];
+      dy = mv[1];
+    }
+    pred_row<N>(job, c, y, x0, dx, dy, s.PRED[c][b][r]);
+  }
+  __syncthreads();
+  if (vb) {
+    const int k = r;
+    const int qP = job.qp + 6 * (B - 8);
+    const long long scale = (long long)kIQ[qP % 6] * 16ll << (qP / 6);
+    const int bd = B + L2N - 5;
+    int16_t* row = s.TD[c][b][k];
+#pragma unroll
+    for (int l = 0; l < N; l++) row[l] = (int16_t)dequant(s.L[c][b][l * N + k], scale, bd);
+    inverse_column<N>(row, s.E[c][b], k);
+  }
+  __syncthreads();
+  if (vb) {
+    uint32_t rp[N / 2];
+    inverse_row<N>(s.E[c][b][r], s.PRED[c][b][r], B, rp);
+    store_row_packed<N>(job.rec + c * plane + (size_t)y * job.Wp + x0, rp);
+  }
+}
+
+template <int N>
+hipError_t launch_encode_t(const LaunchDesc& r, hipStream_t s) {
+  encode_kernel<N><<<r.tiles, 192, 0, s>>>(r);
+  return hipGetLastError();
+}
+template <int N>
+hipError_t launch_decode_t(const LaunchDesc& r, hipStream_t s) {
+  decode_kernel<N><<<r.tiles, 192, 0, s>>>(r);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int xf_tiles_per_job(int N, int Hb, int Wb) {
+  const int nbw = 64 / N;
+  return Hb * ((Wb + nbw - 1) / nbw);
+}
+
+hipError_t launch_encode(int N, const LaunchDesc& r, hipStream_t s) {
+  if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
+  switch (N) {
+    case 4: return launch_encode_t<4>(r, s);
+    case 8: return launch_encode_t<8>(r, s);
+    case 16: return launch_encode_t<16>(r, s);
+    case 32: return launch_encode_t<32>(r, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_decode(int N, const LaunchDesc& r, hipStream_t s) {
+  if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
+  switch (N) {
+    case 4: return launch_decode_t<4>(r, s);
+    case 8: return launch_decode_t<8>(r, s);
+    case 16: return launch_decode_t<16>(r, s);
+    case 32: return launch_decode_t<32>(r, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace xv

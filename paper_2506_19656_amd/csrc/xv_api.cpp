@@ -1,0 +1,762 @@
+// xv_api.cpp -- host runtime behind the C ABI of include/xv.h.
+//
+// Responsibilities: argument validation, device allocation (stream-ordered,
+// from the device's default memory pool), launch sequencing of the coding
+// loop (stats -> pack -> plan -> for every frame step: motion search (P) and
+// fused transform coding), decode, metrics, the batched multi-cube path,
+// per-launch event timing and the motion-search launch geometry table.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "xv_internal.h"
+
+using namespace xv;
+
+struct xv_encoded {
+  int64_t T, H, W, bands;
+  int G, N, Hp, Wp, Hb, Wb, nsteps;
+  int64_t njobs;
+  xv_params p;
+  int src_dtype;
+  hipStream_t stream;
+  void* keep;  // levels, vectors, bit counts, statistics, job table
+  void* work;  // converted frames, reconstruction, validity bytes
+  uint16_t* frames;
+  uint16_t* recon;
+  uint8_t* vmask;
+  int16_t* levels;
+  int8_t* mvs;
+  uint32_t* cbits;
+  uint32_t* mbits;
+  uint32_t* minkey;
+  uint32_t* maxkey;
+  uint32_t* nan_count;
+  uint32_t* nan_total;
+  double* mn;
+  double* mx;
+  unsigned long long* nvalid;
+  unsigned long long* sse;   // [3G]
+  unsigned long long* bits;  // [2G]
+  FrameJob* jobs;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(XV_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(XV_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define XV_HIP(call, what)                       \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// ---- device memory ---------------------------------------------------------
+std::once_flag g_pool_once;
+void init_pool() {
+  std::call_once(g_pool_once, [] {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  });
+}
+
+struct Carve {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t count) {
+    size_t o = (off + 255) & ~(size_t)255;
+    off = o + count * sizeof(T);
+    return o;
+  }
+};
+
+// ---- profiling ----------------------------------------------------------------
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  double work;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+xv_profile g_prof_tot;
+
+struct ProfScope {
+  int cls;
+  hipStream_t s;
+  double work;
+  hipEvent_t a = nullptr, b = nullptr;
+  bool on;
+  ProfScope(int c, hipStream_t st, double w) : cls(c), s(st), work(w) {
+    on = g_prof_on;
+    if (on) {
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(ProfRec{cls, a, b, work});
+  }
+};
+
+// ---- motion-search geometry table -----------------------------------------
+std::mutex g_geom_mu;
+std::map<std::pair<int, int>, MeGeom> g_geom;
+
+MeGeom geometry_for(int N, int R) {
+  std::lock_guard<std::mutex> lk(g_geom_mu);
+  auto it = g_geom.find({N, R});
+  if (it != g_geom.end()) return it->second;
+  return me_default_geometry(N, R);
+}
+
+// ---- validation -----------------------------------------------------------
+int check_cube(const xv_cube* c, const char* name) {
+  if (!c) return fail(XV_EINVAL, "%s: null cube", name);
+  if (!c->data) return fail(XV_EINVAL, "%s: null data pointer", name);
+  if (c->dtype != XV_U16 && c->dtype != XV_F32) return fail(XV_EINVAL, "%s: bad dtype %d", name, c->dtype);
+  if (c->T < 1 || c->H < 1 || c->W < 1 || c->bands < 1)
+    return fail(XV_EINVAL, "%s: shape must be positive", name);
+  if (c->bands > XV_MAX_BANDS) return fail(XV_EINVAL, "%s: more than %d bands", name, XV_MAX_BANDS);
+  if (c->H > 65536 || c->W > 65536 || c->T > (1 << 24))
+    return fail(XV_EINVAL, "%s: dimension too large", name);
+  const size_t el = c->dtype == XV_U16 ? 2 : 4;
+  if (((uintptr_t)c->data) % el) return fail(XV_EINVAL, "%s: misaligned data pointer", name);
+  return XV_OK;
+}
+
+int check_params(const xv_params* p) {
+  if (!p) return fail(XV_EINVAL, "null params");
+  const int B = p->bit_depth, N = p->block;
+  if (B < 8 || B > 12) return fail(XV_EINVAL, "bit_depth %d not in 8..12", B);
+  if (!(N == 4 || N == 8 || N == 16 || N == 32)) return fail(XV_EINVAL, "block %d not in {4,8,16,32}", N);
+  if (p->qp < -6 * (B - 8) || p->qp > 51) return fail(XV_EINVAL, "qp %d outside %d..51", p->qp, -6 * (B - 8));
+  if (p->search_range < 0 || p->search_range > 64) return fail(XV_EINVAL, "search_range %d not in 0..64", p->search_range);
+  if (p->gop < 1) return fail(XV_EINVAL, "gop must be >= 1");
+  if (p->pad_mode != XV_PAD_ZERO && p->pad_mode != XV_PAD_REPEAT) return fail(XV_EINVAL, "bad pad_mode");
+  if (p->fill_mode != XV_FILL_NEAREST && p->fill_mode != XV_FILL_FORWARD) return fail(XV_EINVAL, "bad fill_mode");
+  if (p->flags & ~XV_FLAG_DROP_WORK) return fail(XV_EINVAL, "unknown flags");
+  return XV_OK;
+}
+
+// ---- encode -----------------------------------------------------------------
+void dims_of(xv_encoded* e, const xv_cube* in, const xv_params* p) {
+  e->T = in->T;
+  e->H = in->H;
+  e->W = in->W;
+  e->bands = in->bands;
+  e->G = (int)((in->bands + 2) / 3);
+  e->N = p->block;
+  e->Hp = (int)((in->H + p->block - 1) / p->block * p->block);
+  e->Wp = (int)((in->W + p->block - 1) / p->block * p->block);
+  e->Hb = e->Hp / e->N;
+  e->Wb = e->Wp / e->N;
+  e->nsteps = (int)std::min<int64_t>(p->gop, in->T);
+  e->njobs = plan_step_offset((int)e->T, e->G, p->gop, e->nsteps);
+  e->p = *p;
+  e->src_dtype = in->dtype;
+}
+
+// Allocates the encoded object and launches stats, pack and plan.
+int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_encoded** out) {
+  xv_encoded* e = new (std::nothrow) xv_encoded();
+  if (!e) return fail(XV_ENOMEM, "host allocation failed");
+  memset(e, 0, sizeof *e);
+  dims_of(e, in, p);
+  e->stream = s;
+  const int64_t G = e->G, T = e->T;
+  const int64_t plane = (int64_t)e->Hp * e->Wp;
+  const int64_t nframes = G * T;
+  const int64_t nblk = nframes * e->Hb * e->Wb;
+  const int64_t bands = e->bands;
+
+  Carve k;
+  size_t o_lev = k.take<int16_t>((size_t)nframes * 3 * plane);
+  size_t o_mv = k.take<int8_t>((size_t)nblk * 2);
+  size_t o_cb = k.take<uint32_t>((size_t)nblk * 3);
+  size_t o_mb = k.take<uint32_t>((size_t)nblk);
+  size_t o_keys = k.take<uint32_t>((size_t)3 * bands + 1);
+  size_t o_mn = k.take<double>((size_t)bands);
+  size_t o_mx = k.take<double>((size_t)bands);
+  size_t o_nv = k.take<unsigned long long>((size_t)bands);
+  size_t o_sse = k.take<unsigned long long>((size_t)3 * G);
+  size_t o_bits = k.take<unsigned long long>((size_t)2 * G);
+  size_t o_jobs = k.take<FrameJob>((size_t)e->njobs);
+  Carve w;
+  size_t o_fr = w.take<uint16_t>((size_t)nframes * 3 * plane);
+  size_t o_rc = w.take<uint16_t>((size_t)nframes * 3 * plane);
+  size_t o_vm = in->dtype == XV_F32 ? w.take<uint8_t>((size_t)nframes * 3 * plane) : 0;
+
+  init_pool();
+  hipError_t he = hipMallocAsync(&e->keep, k.off, s);
+  if (he != hipSuccess) {
+    delete e;
+    return hip_fail(he, "device allocation of the encoded cube");
+  }
+  he = hipMallocAsync(&e->work, w.off, s);
+  if (he != hipSuccess) {
+    (void)hipFreeAsync(e->keep, s);
+    delete e;
+    return hip_fail(he, "device allocation of the coding work buffers");
+  }
+  char* kb = (char*)e->keep;
+  char* wb = (char*)e->work;
+  e->levels = (int16_t*)(kb + o_lev);
+  e->mvs = (int8_t*)(kb + o_mv);
+  e->cbits = (uint32_t*)(kb + o_cb);
+  e->mbits = (uint32_t*)(kb + o_mb);
+  e->minkey = (uint32_t*)(kb + o_keys);
+  e->maxkey = e->minkey + bands;
+  e->nan_count = e->maxkey + bands;
+  e->nan_total = e->nan_count + bands;
+  e->mn = (double*)(kb + o_mn);
+  e->mx = (double*)(kb + o_mx);
+  e->nvalid = (unsigned long long*)(kb + o_nv);
+  e->sse = (unsigned long long*)(kb + o_sse);
+  e->bits = (unsigned long long*)(kb + o_bits);
+  e->jobs = (FrameJob*)(kb + o_jobs);
+  e->frames = (uint16_t*)(wb + o_fr);
+  e->recon = (uint16_t*)(wb + o_rc);
+  e->vmask = in->dtype == XV_F32 ? (uint8_t*)(wb + o_vm) : nullptr;
+  *out = e;
+
+  XV_HIP(launch_fill_u64(e->sse, 0ull, 3 * G, s), "clear accumulators");
+  XV_HIP(launch_fill_u64(e->bits, 0ull, 2 * G, s), "clear accumulators");
+  const double elb = in->dtype == XV_U16 ? 2.0 : 4.0;
+  const double in_bytes = (double)T * e->H * e->W * bands * elb;
+  {
+    StatsArgs a{in->data, in->dtype, T * e->H * e->W, (int32_t)bands, e->minkey, e->maxkey,
+                e->nan_count, e->nan_total, e->mn, e->mx, e->nvalid};
+    ProfScope ps(XV_K_STATS, s, in_bytes);
+    XV_HIP(launch_stats(a, s), "stats kernel");
+  }
+  {
+    PackArgs a{in->data, in->dtype, T, e->H, e->W, (int32_t)bands, e->G, e->Hp, e->Wp,
+               p->bit_depth, p->pad_mode, p->fill_mode, e->mn, e->mx, e->nan_total,
+               e->frames, e->vmask};
+    ProfScope ps(XV_K_PACK, s, in_bytes + (double)nframes * 3 * plane * 2.0);
+    XV_HIP(launch_pack(a, s), "pack kernel");
+  }
+  {
+    CubePlan pl{e->frames, e->recon, e->levels, e->mvs, e->cbits, e->mbits, e->vmask,
+                e->nan_total, e->sse, e->bits, e->jobs, (int32_t)T, e->G, p->gop, e->nsteps,
+                e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)bands, e->N,
+                p->bit_depth, p->qp};
+    XV_HIP(launch_plan(pl, s), "plan kernel");
+  }
+  return XV_OK;
+}
+
+// SAD terms of a motion-search launch: (2R+1)^2 per real-channel sample.
+double me_work(const xv_encoded* e, int s) {
+  const int R = e->p.search_range;
+  const double span2 = (double)(2 * R + 1) * (2 * R + 1);
+  const int nk = (int)((e->T - s + e->p.gop - 1) / e->p.gop);
+  double ch = 0;
+  for (int g = 0; g < e->G; g++) ch += std::min<int64_t>(3, e->bands - 3 * g);
+  return span2 * ch * nk * (double)e->Hp * e->Wp;
+}
+
+double xf_frames(const xv_encoded* e, int s) {
+  const int nk = (int)((e->T - s + e->p.gop - 1) / e->p.gop);
+  return (double)e->G * nk;
+}
+
+struct SegSrc {
+  xv_encoded* e;
+  int step;
+};
+
+// One launch per chunk of up to kMaxSeg segments.
+template <class F>
+int launch_segments(const std::vector<SegSrc>& src, int tpj_kind, F launch) {
+  size_t i = 0;
+  while (i < src.size()) {
+    LaunchDesc d;
+    memset(&d, 0, sizeof d);
+    int tiles = 0;
+    double work = 0;
+    for (; i < src.size() && d.nseg < kMaxSeg; i++) {
+      xv_encoded* e = src[i].e;
+      const int s = src[i].step;
+      const int n = plan_jobs_at((int)e->T, e->G, e->p.gop, s);
+      int tpj = tpj_kind == 0 ? xf_tiles_per_job(e->N, e->Hb, e->Wb)
+                              : me_tiles_per_job(e->Hb, e->Wb, geometry_for(e->N, e->p.search_range));
+      Seg& g = d.seg[d.nseg++];
+      g.jobs = e->jobs + plan_step_offset((int)e->T, e->G, e->p.gop, s);
+      g.count = n;
+      g.tpj = tpj;
+      g.tile0 = tiles;
+      tiles += n * tpj;
+      work += tpj_kind == 0 ? xf_frames(e, s) * 3.0 * e->Hp * e->Wp : me_work(e, s);
+    }
+    d.tiles = tiles;
+    int rc = launch(d, work);
+    if (rc != XV_OK) return rc;
+  }
+  return XV_OK;
+}
+
+// Frame-step loop over a set of encodes that share N and R.
+int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s) {
+  if (es.empty()) return XV_OK;
+  const int N = es[0]->N, R = es[0]->p.search_range;
+  const MeGeom geom = geometry_for(N, R);
+  int maxsteps = 0;
+  for (auto* e : es) maxsteps = std::max(maxsteps, e->nsteps);
+  for (int st = 0; st < maxsteps; st++) {
+    std::vector<SegSrc> src;
+    for (auto* e : es)
+      if (st < e->nsteps) src.push_back(SegSrc{e, st});
+    if (st > 0) {
+      int rc = launch_segments(src, 1, [&](const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_ME, s, work);
+        XV_HIP(launch_me(N, R, geom, d, s), "motion search kernel");
+        return XV_OK;
+      });
+      if (rc != XV_OK) return rc;
+    }
+    int rc = launch_segments(src, 0, [&](const LaunchDesc& d, double work) {
+      ProfScope ps(XV_K_ENCODE, s, work * 8.0);  // cur + pred in, level + recon out
+      XV_HIP(launch_encode(N, d, s), "transform kernel");
+      return XV_OK;
+    });
+    if (rc != XV_OK) return rc;
+  }
+  return XV_OK;
+}
+
+void drop_work(xv_encoded* e) {
+  if (e->p.flags & XV_FLAG_DROP_WORK) {
+    (void)hipFreeAsync(e->work, e->stream);
+    e->work = nullptr;
+    e->frames = nullptr;
+    e->recon = nullptr;
+    e->vmask = nullptr;
+  }
+}
+
+// ---- decode -----------------------------------------------------------------
+int check_decode_out(const xv_encoded* e, const xv_cube* out) {
+  int rc = check_cube(out, "decode output");
+  if (rc != XV_OK) return rc;
+  if (out->T != e->T || out->H != e->H || out->W != e->W || out->bands != e->bands)
+    return fail(XV_EINVAL, "decode output shape differs from the encoded cube");
+  return XV_OK;
+}
+
+struct DecodeBuf {
+  void* mem = nullptr;
+  uint16_t* recon = nullptr;
+  FrameJob* jobs = nullptr;
+};
+
+int decode_prepare(const xv_encoded* e, hipStream_t s, DecodeBuf& db) {
+  Carve c;
+  const int64_t plane = (int64_t)e->Hp * e->Wp;
+  size_t o_rc = c.take<uint16_t>((size_t)e->G * e->T * 3 * plane);
+  size_t o_jb = c.take<FrameJob>((size_t)e->njobs);
+  init_pool();
+  XV_HIP(hipMallocAsync(&db.mem, c.off, s), "device allocation of the decode buffers");
+  db.recon = (uint16_t*)((char*)db.mem + o_rc);
+  db.jobs = (FrameJob*)((char*)db.mem + o_jb);
+  CubePlan pl{nullptr, db.recon, e->levels, e->mvs, nullptr, nullptr, nullptr, nullptr,
+              nullptr, nullptr, db.jobs, (int32_t)e->T, e->G, e->p.gop, e->nsteps,
+              e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)e->bands, e->N,
+              e->p.bit_depth, e->p.qp};
+  XV_HIP(launch_plan(pl, s), "plan kernel");
+  return XV_OK;
+}
+
+struct DecSrc {
+  const xv_encoded* e;
+  FrameJob* jobs;
+  int step;
+};
+
+int decode_steps(std::vector<DecSrc> base, hipStream_t s) {
+  if (base.empty()) return XV_OK;
+  const int N = base[0].e->N;
+  int maxsteps = 0;
+  for (auto& b : base) maxsteps = std::max(maxsteps, b.e->nsteps);
+  for (int st = 0; st < maxsteps; st++) {
+    size_t i = 0;
+    std::vector<DecSrc> src;
+    for (auto& b : base)
+      if (st < b.e->nsteps) src.push_back(DecSrc{b.e, b.jobs, st});
+    while (i < src.size()) {
+      LaunchDesc d;
+      memset(&d, 0, sizeof d);
+      int tiles = 0;
+      double work = 0;
+      for (; i < src.size() && d.nseg < kMaxSeg; i++) {
+        const xv_encoded* e = src[i].e;
+        const int n = plan_jobs_at((int)e->T, e->G, e->p.gop, st);
+        const int tpj = xf_tiles_per_job(e->N, e->Hb, e->Wb);
+        Seg& g = d.seg[d.nseg++];
+        g.jobs = src[i].jobs + plan_step_offset((int)e->T, e->G, e->p.gop, st);
+        g.count = n;
+        g.tpj = tpj;
+        g.tile0 = tiles;
+        tiles += n * tpj;
+        work += (double)n * 3.0 * e->Hp * e->Wp;
+      }
+      d.tiles = tiles;
+      ProfScope ps(XV_K_DECODE, s, work * 6.0);  // level + pred in, recon out
+      XV_HIP(launch_decode(N, d, s), "decode kernel");
+    }
+  }
+  return XV_OK;
+}
+
+int decode_finish(const xv_encoded* e, const xv_cube* out, DecodeBuf& db, hipStream_t s) {
+  DenormArgs a{db.recon, e->T, e->H, e->W, (int32_t)e->bands, e->Hp, e->Wp, e->p.bit_depth,
+               e->mn, e->mx, out->dtype, out->data};
+  const double ob = out->dtype == XV_U16 ? 2.0 : 4.0;
+  {
+    ProfScope ps(XV_K_DENORM, s, (double)e->T * e->H * e->W * e->bands * (2.0 + ob));
+    XV_HIP(launch_denorm(a, s), "denormalise kernel");
+  }
+  XV_HIP(hipFreeAsync(db.mem, s), "free decode buffers");
+  db.mem = nullptr;
+  return XV_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int xv_abi_version(void) { return XV_ABI_VERSION; }
+
+const char* xv_status_str(int st) {
+  switch (st) {
+    case XV_OK: return "ok";
+    case XV_EINVAL: return "invalid argument";
+    case XV_ENOMEM: return "out of device memory";
+    case XV_EHIP: return "HIP runtime error";
+    case XV_EBUSY: return "busy";
+    case XV_ECANCELED: return "cancelled";
+    case XV_EPENDING: return "pending";
+    default: return "unknown status";
+  }
+}
+
+const char* xv_last_error(void) { return g_err.c_str(); }
+
+int xv_encode_cube(const xv_cube* in, const xv_params* p, void* hip_stream, xv_encoded** out) {
+  if (!out) return fail(XV_EINVAL, "null output handle");
+  *out = nullptr;
+  int rc = check_cube(in, "input");
+  if (rc != XV_OK) return rc;
+  if ((rc = check_params(p)) != XV_OK) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  xv_encoded* e = nullptr;
+  if ((rc = encode_prepare(in, p, s, &e)) != XV_OK) {
+    if (e) xv_encoded_free(e);
+    return rc;
+  }
+  std::vector<xv_encoded*> es{e};
+  if ((rc = encode_steps(es, s)) != XV_OK) {
+    xv_encoded_free(e);
+    return rc;
+  }
+  drop_work(e);
+  *out = e;
+  return XV_OK;
+}
+
+int xv_encode_batch(int n, const xv_cube* cubes, const xv_params* params, void* hip_stream,
+                    xv_encoded** outs) {
+  if (n < 0 || (n > 0 && (!cubes || !params || !outs))) return fail(XV_EINVAL, "bad batch arguments");
+  for (int i = 0; i < n; i++) outs[i] = nullptr;
+  for (int i = 0; i < n; i++) {
+    int rc = check_cube(&cubes[i], "batch input");
+    if (rc != XV_OK) return rc;
+    if ((rc = check_params(&params[i])) != XV_OK) return rc;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<xv_encoded*> all(n, nullptr);
+  auto cleanup = [&](int rc) {
+    for (auto* e : all)
+      if (e) xv_encoded_free(e);
+    return rc;
+  };
+  for (int i = 0; i < n; i++) {
+    int rc = encode_prepare(&cubes[i], &params[i], s, &all[i]);
+    if (rc != XV_OK) return cleanup(rc);
+  }
+  // one step loop per (N, R) class; classes are independent
+  std::map<std::pair<int, int>, std::vector<xv_encoded*>> cls;
+  for (auto* e : all) cls[{e->N, e->p.search_range}].push_back(e);
+  for (auto& kv : cls) {
+    int rc = encode_steps(kv.second, s);
+    if (rc != XV_OK) return cleanup(rc);
+  }
+  for (int i = 0; i < n; i++) {
+    drop_work(all[i]);
+    outs[i] = all[i];
+  }
+  return XV_OK;
+}
+
+int xv_decode_cube(const xv_encoded* e, const xv_cube* out, void* hip_stream) {
+  if (!e) return fail(XV_EINVAL, "null encoded cube");
+  int rc = check_decode_out(e, out);
+  if (rc != XV_OK) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  DecodeBuf db;
+  if ((rc = decode_prepare(e, s, db)) != XV_OK) return rc;
+  std::vector<DecSrc> src{DecSrc{e, db.jobs, 0}};
+  if ((rc = decode_steps(src, s)) != XV_OK) {
+    (void)hipFreeAsync(db.mem, s);
+    return rc;
+  }
+  return decode_finish(e, out, db, s);
+}
+
+int xv_decode_batch(int n, xv_encoded* const* encs, const xv_cube* outs, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!encs || !outs))) return fail(XV_EINVAL, "bad batch arguments");
+  for (int i = 0; i < n; i++) {
+    if (!encs[i]) return fail(XV_EINVAL, "null encoded cube in batch");
+    int rc = check_decode_out(encs[i], &outs[i]);
+    if (rc != XV_OK) return rc;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<DecodeBuf> bufs(n);
+  auto cleanup = [&](int rc) {
+    for (auto& b : bufs)
+      if (b.mem) (void)hipFreeAsync(b.mem, s);
+    return rc;
+  };
+  for (int i = 0; i < n; i++) {
+    int rc = decode_prepare(encs[i], s, bufs[i]);
+    if (rc != XV_OK) return cleanup(rc);
+  }
+  std::map<int, std::vector<DecSrc>> cls;
+  for (int i = 0; i < n; i++) cls[encs[i]->N].push_back(DecSrc{encs[i], bufs[i].jobs, 0});
+  for (auto& kv : cls) {
+    int rc = decode_steps(kv.second, s);
+    if (rc != XV_OK) return cleanup(rc);
+  }
+  for (int i = 0; i < n; i++) {
+    int rc = decode_finish(encs[i], &outs[i], bufs[i], s);
+    if (rc != XV_OK) return cleanup(rc);
+  }
+  return XV_OK;
+}
+
+int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m, void* hip_stream) {
+  if (!e || !m) return fail(XV_EINVAL, "null encoded cube or metrics");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int bands = (int)e->bands, G = e->G;
+  double* dphys = nullptr;
+  void* pmem = nullptr;
+  if (orig) {
+    int rc = check_cube(orig, "original");
+    if (rc != XV_OK) return rc;
+    if (orig->T != e->T || orig->H != e->H || orig->W != e->W || orig->bands != e->bands ||
+        orig->dtype != e->src_dtype)
+      return fail(XV_EINVAL, "original cube differs from the encoded one");
+    if (e->recon) {
+      const int nb = phys_blocks(e->T * e->H * e->W * bands);
+      init_pool();
+      XV_HIP(hipMallocAsync(&pmem, (size_t)(nb + 1) * bands * sizeof(double), s),
+             "device allocation of metric partials");
+      dphys = (double*)pmem + (size_t)nb * bands;
+      PhysArgs a{orig->data, orig->dtype, e->recon, e->T, e->H, e->W, bands, e->Hp, e->Wp,
+                 e->p.bit_depth, e->mn, e->mx, (double*)pmem, dphys, nb};
+      const double ib = orig->dtype == XV_U16 ? 2.0 : 4.0;
+      ProfScope ps(XV_K_METRICS, s, (double)e->T * e->H * e->W * bands * (ib + 2.0));
+      hipError_t he = launch_phys_sse(a, s);
+      if (he != hipSuccess) {
+        (void)hipFreeAsync(pmem, s);
+        return hip_fail(he, "physical error kernel");
+      }
+    }
+  }
+  std::vector<unsigned long long> sse(3 * G), nv(bands), bits(2 * G);
+  std::vector<double> mn(bands), mx(bands), phys(bands, NAN);
+  XV_HIP(hipMemcpyAsync(sse.data(), e->sse, sse.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
+  XV_HIP(hipMemcpyAsync(nv.data(), e->nvalid, nv.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
+  XV_HIP(hipMemcpyAsync(bits.data(), e->bits, bits.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
+  XV_HIP(hipMemcpyAsync(mn.data(), e->mn, mn.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
+  XV_HIP(hipMemcpyAsync(mx.data(), e->mx, mx.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
+  if (dphys)
+    XV_HIP(hipMemcpyAsync(phys.data(), dphys, phys.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
+  if (pmem) (void)hipFreeAsync(pmem, s);
+  XV_HIP(hipStreamSynchronize(s), "synchronise metrics");
+
+  memset(m, 0, sizeof *m);
+  m->bands = bands;
+  m->groups = G;
+  const double L = (double)((1 << e->p.bit_depth) - 1);
+  for (int b = 0; b < bands; b++) {
+    const unsigned long long se = sse[3 * (b / 3) + b % 3];
+    m->sse[b] = se;
+    m->n_valid[b] = nv[b];
+    m->band_min[b] = mn[b];
+    m->band_max[b] = mx[b];
+    if (nv[b] == 0) {
+      m->psnr[b] = NAN;
+    } else if (se == 0) {
+      m->psnr[b] = INFINITY;
+    } else {
+      const double mse = (double)se / (double)nv[b];
+      m->psnr[b] = 10.0 * log10(L * L / mse);
+    }
+    m->sse_phys[b] = phys[b];
+    if (!dphys || nv[b] == 0 || !(mx[b] > 0.0)) {
+      m->psnr_phys[b] = NAN;
+    } else if (phys[b] == 0.0) {
+      m->psnr_phys[b] = INFINITY;
+    } else {
+      const double mse = phys[b] / (double)nv[b];
+      m->psnr_phys[b] = 10.0 * log10(mx[b] * mx[b] / mse);
+    }
+  }
+  unsigned long long cb = 0, mb = 0;
+  const double pix = (double)e->T * (double)e->H * (double)e->W;
+  for (int g = 0; g < G; g++) {
+    cb += bits[2 * g];
+    mb += bits[2 * g + 1];
+    const int nb = (int)std::min<int64_t>(3, e->bands - 3 * g);
+    if (g < XV_MAX_GROUPS) m->bpppb_group[g] = (double)(bits[2 * g] + bits[2 * g + 1]) / (pix * nb);
+  }
+  m->coef_bits = cb;
+  m->mv_bits = mb;
+  m->header_bits = 128ull * bands + 256ull;
+  m->bpppb = (double)(cb + mb) / (pix * (double)bands);
+  return XV_OK;
+}
+
+int xv_encoded_export(const xv_encoded* e, xv_export* v) {
+  if (!e || !v) return fail(XV_EINVAL, "null argument");
+  memset(v, 0, sizeof *v);
+  v->T = e->T;
+  v->H = e->H;
+  v->W = e->W;
+  v->bands = e->bands;
+  v->groups = e->G;
+  v->Hp = e->Hp;
+  v->Wp = e->Wp;
+  v->Hb = e->Hb;
+  v->Wb = e->Wb;
+  v->params = e->p;
+  v->src_dtype = e->src_dtype;
+  v->frames = e->frames;
+  v->recon = e->recon;
+  v->levels = e->levels;
+  v->mvs = e->mvs;
+  v->coef_bits = e->cbits;
+  v->mv_bits = e->mbits;
+  v->band_min = e->mn;
+  v->band_max = e->mx;
+  v->sse = (const uint64_t*)e->sse;
+  v->n_valid = (const uint64_t*)e->nvalid;
+  return XV_OK;
+}
+
+void xv_encoded_free(xv_encoded* e) {
+  if (!e) return;
+  if (e->work) (void)hipFreeAsync(e->work, e->stream);
+  if (e->keep) (void)hipFreeAsync(e->keep, e->stream);
+  delete e;
+}
+
+int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
+  if (!(block == 4 || block == 8 || block == 16 || block == 32) || search_range < 0 ||
+      search_range > 64)
+    return fail(XV_EINVAL, "bad block or search range");
+  MeGeom def = me_default_geometry(block, search_range);
+  MeGeom m = def;
+  if (g) {
+    if (g->blocks_per_wg) m.nb = g->blocks_per_wg;
+    if (g->cands_per_lane) m.kx = g->cands_per_lane;
+    if (g->threads) m.threads = g->threads;
+  }
+  if (m.nb < 1 || m.nb > 64) return fail(XV_EINVAL, "blocks_per_wg out of range");
+  if (m.kx < 2 || m.kx > 18 || (m.kx & 1)) return fail(XV_EINVAL, "cands_per_lane must be even in 2..18");
+  if (m.threads < 64 || m.threads > 512 || (m.threads & 63))
+    return fail(XV_EINVAL, "threads must be a multiple of 64 in 64..512");
+  if (me_lds_bytes_for(block, search_range, m) > 160 * 1024)
+    return fail(XV_EINVAL, "geometry needs more than 160 KB of LDS");
+  std::lock_guard<std::mutex> lk(g_geom_mu);
+  g_geom[{block, search_range}] = m;
+  return XV_OK;
+}
+
+int xv_get_me_geometry(int block, int search_range, xv_me_geometry* g) {
+  if (!g) return fail(XV_EINVAL, "null geometry");
+  MeGeom m = geometry_for(block, search_range);
+  g->blocks_per_wg = m.nb;
+  g->cands_per_lane = m.kx;
+  g->threads = m.threads;
+  g->reserved = 0;
+  return XV_OK;
+}
+
+int xv_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_pending.clear();
+  memset(&g_prof_tot, 0, sizeof g_prof_tot);
+  g_prof_on = on != 0;
+  return XV_OK;
+}
+
+int xv_profile_read(xv_profile* out) {
+  if (!out) return fail(XV_EINVAL, "null profile");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof_pending) {
+    hipError_t he = hipEventSynchronize(r.b);
+    if (he != hipSuccess) return hip_fail(he, "profile event");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    g_prof_tot.ms[r.cls] += ms;
+    g_prof_tot.launches[r.cls] += 1;
+    g_prof_tot.work[r.cls] += r.work;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_pending.clear();
+  *out = g_prof_tot;
+  return XV_OK;
+}
+
+}  // extern "C"

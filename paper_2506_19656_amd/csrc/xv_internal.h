@@ -1,0 +1,223 @@
+// xv_internal.h -- shared declarations of the HIP kernels and the host
+// runtime of libxv (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xv.h"
+
+namespace xv {
+
+// ---------------------------------------------------------------------------
+// Work descriptors.  A "stream" is one closed GOP of one band group of one
+// cube; frame step s codes frame s of every stream.  One FrameJob describes
+// one frame of one stream at one step.  The jobs of one cube are stored
+// step-major ([step][group][gop]) by the plan kernel; a launch covers up to
+// kMaxSeg segments (contiguous job ranges, e.g. one per cube) that share the
+// block size N and, for motion search, the range R.
+// ---------------------------------------------------------------------------
+struct FrameJob {
+  const uint16_t* cur;         // [3][Hp][Wp] converted frame (encode)
+  const uint16_t* ref;         // [3][Hp][Wp] reconstruction of frame t-1 (P)
+  uint16_t* rec;               // [3][Hp][Wp] reconstruction of this frame
+  int16_t* lev;                // [3][Hb][Wb][N*N]
+  int8_t* mv;                  // [Hb][Wb][2]
+  uint32_t* cbits;             // [3][Hb][Wb]
+  uint32_t* mbits;             // [Hb][Wb]
+  const uint8_t* vmask;        // [3][Hp][Wp] validity bytes, or null
+  const uint32_t* nan_total;   // device flag: non-zero -> vmask is meaningful
+  unsigned long long* sse;     // per-channel accumulators (3 entries)
+  unsigned long long* bits;    // [0] coefficient bits, [1] MV bits
+  int32_t Hp, Wp, H, W;
+  int32_t nch;                 // channels carrying a real band (1..3)
+  int32_t intra;
+  int32_t bit_depth, qp;
+};
+
+constexpr int kMaxSeg = 32;
+struct Seg {
+  const FrameJob* jobs;  // first job of the segment (device)
+  int32_t count;         // jobs in the segment
+  int32_t tpj;           // workgroups (tiles) per job
+  int32_t tile0;         // first tile of the segment in the launch
+  int32_t pad_;
+};
+struct LaunchDesc {
+  int32_t nseg;
+  int32_t tiles;
+  Seg seg[kMaxSeg];
+};
+
+// Locate the job and the job-local tile of workgroup `tile`.
+__device__ inline const FrameJob* desc_job(const LaunchDesc& d, int tile, int& local) {
+  int i = 0;
+  for (int k = 1; k < d.nseg; k++)
+    if (d.seg[k].tile0 <= tile) i = k;
+  const int rel = tile - d.seg[i].tile0;
+  const int j = rel / d.seg[i].tpj;
+  local = rel - j * d.seg[i].tpj;
+  return d.seg[i].jobs + j;
+}
+
+// By-value description of one cube for the plan kernel.
+struct CubePlan {
+  const uint16_t* frames;      // [G][T][3][Hp][Wp] (null for decode)
+  uint16_t* recon;             // [G][T][3][Hp][Wp] written by the coding loop
+  int16_t* lev;
+  int8_t* mv;
+  uint32_t* cbits;
+  uint32_t* mbits;
+  const uint8_t* vmask;
+  const uint32_t* nan_total;
+  unsigned long long* sse;     // [3G]
+  unsigned long long* bits;    // [2G]
+  FrameJob* jobs;              // [sum over steps of jobs]
+  int32_t T, G, gop, nsteps, Hp, Wp, H, W, bands, N, bit_depth, qp;
+};
+
+// Jobs at step s: G * ceil((T - s) / gop); offset of step s in the table.
+inline int plan_jobs_at(int T, int G, int gop, int s) { return G * ((T - s + gop - 1) / gop); }
+__host__ __device__ inline int64_t plan_step_offset(int T, int G, int gop, int s) {
+  int64_t o = 0;
+  for (int q = 0; q < s; q++) o += (int64_t)G * ((T - q + gop - 1) / gop);
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Integer DCT-II of ITU-T H.265.  The 32-point odd rows below are the
+// standard's coefficients for rows 1, 3, ..., 31 and columns 0..15; rows of a
+// smaller transform are rows k*32/N of the 32-point matrix.  Entry (k, n) of
+// the N-point matrix follows from the even/odd symmetry
+//   M[k][N-1-n] = (-1)^k M[k][n]
+// and the recursion "even rows of the N-point matrix are the N/2-point
+// matrix" down to the 2-point DC row (64).
+// ---------------------------------------------------------------------------
+constexpr int kOdd32[16][16] = {
+    {90, 90, 88, 85, 82, 78, 73, 67, 61, 54, 46, 38, 31, 22, 13, 4},
+    {90, 82, 67, 46, 22, -4, -31, -54, -73, -85, -90, -88, -78, -61, -38, -13},
+    {88, 67, 31, -13, -54, -82, -90, -78, -46, -4, 38, 73, 90, 85, 61, 22},
+    {85, 46, -13, -67, -90, -73, -22, 38, 82, 88, 54, -4, -61, -90, -78, -31},
+    {82, 22, -54, -90, -61, 13, 78, 85, 31, -46, -90, -67, 4, 73, 88, 38},
+    {78, -4, -82, -73, 13, 85, 67, -22, -88, -61, 31, 90, 54, -38, -90, -46},
+    {73, -31, -90, -22, 78, 67, -38, -90, -13, 82, 61, -46, -88, -4, 85, 54},
+    {67, -54, -78, 38, 85, -22, -90, 4, 90, 13, -88, -31, 82, 46, -73, -61},
+    {61, -73, -46, 82, 31, -88, -13, 90, -4, -90, 22, 85, -38, -78, 54, 67},
+    {54, -85, -4, 88, -46, -61, 82, 13, -90, 38, 67, -78, -22, 90, -31, -73},
+    {46, -90, 38, 54, -90, 31, 61, -88, 22, 67, -85, 13, 73, -82, 4, 78},
+    {38, -88, 73, -4, -67, 90, -46, -31, 85, -78, 13, 61, -90, 54, 22, -82},
+    {31, -78, 90, -61, 4, 54, -88, 82, -38, -22, 73, -90, 67, -13, -46, 85},
+    {22, -61, 85, -90, 73, -38, -4, 46, -78, 90, -82, 54, -13, -31, 67, -88},
+    {13, -38, 61, -78, 88, -90, 85, -73, 54, -31, 4, 22, -46, 67, -82, 90},
+    {4, -13, 22, -31, 38, -46, 54, -61, 67, -73, 78, -82, 85, -88, 90, -90},
+};
+constexpr int kOdd16[8][8] = {
+    {90, 87, 80, 70, 57, 43, 25, 9},   {87, 57, 9, -43, -80, -90, -70, -25},
+    {80, 9, -70, -87, -25, 57, 90, 43}, {70, -43, -87, 9, 90, 25, -80, -57},
+    {57, -80, -25, 90, -9, -87, 43, 70}, {43, -90, 57, 25, -87, 70, 9, -80},
+    {25, -70, 90, -80, 43, 9, -57, 87}, {9, -25, 43, -57, 70, -80, 87, -90},
+};
+constexpr int kOdd8[4][4] = {
+    {89, 75, 50, 18}, {75, -18, -89, -50}, {50, -89, 18, 75}, {18, -50, 75, -89}};
+constexpr int kOdd4[2][2] = {{83, 36}, {36, -83}};
+
+// Entry (k, n) of the n-point matrix (n = 4, 8, 16, 32).
+__host__ __device__ constexpr int dct_coef(int N, int k, int n) {
+  if (n >= N / 2) return (k & 1) ? -dct_coef(N, k, N - 1 - n) : dct_coef(N, k, N - 1 - n);
+  if (k == 0) return 64;
+  if (N == 2) return 64;  // k == 1 of the 2-point matrix: 64, -64 by symmetry
+  if (k & 1) {
+    if (N == 32) return kOdd32[k >> 1][n];
+    if (N == 16) return kOdd16[k >> 1][n];
+    if (N == 8) return kOdd8[k >> 1][n];
+    return kOdd4[k >> 1][n];
+  }
+  return dct_coef(N / 2, k >> 1, n);
+}
+
+__host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+
+// Quantiser scales: IQ[k] = round(64 * 2^((k-4)/6)), Qf[k] = round(2^20/IQ[k]).
+constexpr int kIQ[6] = {40, 45, 51, 57, 64, 72};
+constexpr int kQf[6] = {26214, 23302, 20560, 18396, 16384, 14564};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (each returns hipGetLastError of its launch).
+// ---------------------------------------------------------------------------
+struct StatsArgs {
+  const void* data;
+  int32_t dtype;
+  int64_t npix;        // T*H*W
+  int32_t bands;
+  uint32_t* minkey;    // [bands] order-preserving keys
+  uint32_t* maxkey;    // [bands]
+  uint32_t* nan_count; // [bands]
+  uint32_t* nan_total; // [1]
+  double* mn;          // [bands]
+  double* mx;          // [bands]
+  unsigned long long* n_valid;  // [bands]
+};
+
+struct PackArgs {
+  const void* data;
+  int32_t dtype;
+  int64_t T, H, W;
+  int32_t bands, groups;
+  int32_t Hp, Wp;
+  int32_t bit_depth;
+  int32_t pad_mode, fill_mode;
+  const double* mn;
+  const double* mx;
+  const uint32_t* nan_total;
+  uint16_t* frames;    // [G][T][3][Hp][Wp]
+  uint8_t* vmask;      // [G][T][3][Hp][Wp] or null
+};
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n,
+                           hipStream_t s);
+hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
+hipError_t launch_pack(const PackArgs& a, hipStream_t s);
+
+struct MeGeom {
+  int nb;       // blocks per workgroup along x
+  int kx;       // candidates per lane along x (even)
+  int threads;  // workgroup size
+};
+MeGeom me_default_geometry(int N, int R);
+size_t me_lds_bytes_for(int N, int R, const MeGeom& g);
+int me_tiles_per_job(int Hb, int Wb, const MeGeom& g);
+hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& d, hipStream_t s);
+
+int xf_tiles_per_job(int N, int Hb, int Wb);
+hipError_t launch_encode(int N, const LaunchDesc& d, hipStream_t s);
+hipError_t launch_decode(int N, const LaunchDesc& d, hipStream_t s);
+hipError_t launch_plan(const CubePlan& p, hipStream_t s);
+
+struct DenormArgs {
+  const uint16_t* recon;   // [G][T][3][Hp][Wp]
+  int64_t T, H, W;
+  int32_t bands, Hp, Wp, bit_depth;
+  const double* mn;
+  const double* mx;
+  int32_t out_dtype;
+  void* out;               // [T][H][W][bands]
+};
+hipError_t launch_denorm(const DenormArgs& a, hipStream_t s);
+
+struct PhysArgs {
+  const void* orig;        // [T][H][W][bands]
+  int32_t dtype;
+  const uint16_t* recon;   // [G][T][3][Hp][Wp]
+  int64_t T, H, W;
+  int32_t bands, Hp, Wp, bit_depth;
+  const double* mn;
+  const double* mx;
+  double* partial;         // [nblocks][bands]
+  double* out;             // [bands]
+  int32_t nblocks;
+};
+int phys_blocks(int64_t npix);
+hipError_t launch_phys_sse(const PhysArgs& a, hipStream_t s);
+
+}  // namespace xv

@@ -1,0 +1,299 @@
+"""Python binding of libxv (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/xv.h; all
+compute runs in the library's HIP kernels.  PyTorch supplies device memory
+(tensors) and the HIP stream (torch.cuda.current_stream()).  There is no
+fallback: if libxv.so is missing or fails to load, the import of the library
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libxv.so")
+
+OK, EINVAL, ENOMEM, EHIP, EBUSY, ECANCELED, EPENDING = 0, -1, -2, -3, -4, -5, -6
+U16, F32 = 0, 1
+PAD_ZERO, PAD_REPEAT = 0, 1
+FILL_NEAREST, FILL_FORWARD = 0, 1
+FLAG_DROP_WORK = 1
+MAX_BANDS, MAX_GROUPS = 64, 22
+K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS = range(7)
+K_NAMES = ["stats", "pack", "me", "encode", "decode", "denorm", "metrics"]
+
+
+class XvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class Cube(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("reserved", C.c_int32),
+                ("T", C.c_int64), ("H", C.c_int64), ("W", C.c_int64), ("bands", C.c_int64)]
+
+
+class ParamsC(C.Structure):
+    _fields_ = [("bit_depth", C.c_int32), ("qp", C.c_int32), ("block", C.c_int32),
+                ("search_range", C.c_int32), ("gop", C.c_int32), ("pad_mode", C.c_int32),
+                ("fill_mode", C.c_int32), ("flags", C.c_uint32)]
+
+
+class MetricsC(C.Structure):
+    _fields_ = [("bands", C.c_int32), ("groups", C.c_int32),
+                ("psnr", C.c_double * MAX_BANDS), ("psnr_phys", C.c_double * MAX_BANDS),
+                ("sse_phys", C.c_double * MAX_BANDS), ("sse", C.c_uint64 * MAX_BANDS),
+                ("n_valid", C.c_uint64 * MAX_BANDS), ("band_min", C.c_double * MAX_BANDS),
+                ("band_max", C.c_double * MAX_BANDS), ("coef_bits", C.c_uint64),
+                ("mv_bits", C.c_uint64), ("header_bits", C.c_uint64), ("bpppb", C.c_double),
+                ("bpppb_group", C.c_double * MAX_GROUPS)]
+
+
+class ExportC(C.Structure):
+    _fields_ = [("T", C.c_int64), ("H", C.c_int64), ("W", C.c_int64), ("bands", C.c_int64),
+                ("groups", C.c_int64), ("Hp", C.c_int64), ("Wp", C.c_int64), ("Hb", C.c_int64),
+                ("Wb", C.c_int64), ("params", ParamsC), ("src_dtype", C.c_int32),
+                ("reserved", C.c_int32), ("frames", C.c_void_p), ("recon", C.c_void_p),
+                ("levels", C.c_void_p), ("mvs", C.c_void_p), ("coef_bits", C.c_void_p),
+                ("mv_bits", C.c_void_p), ("band_min", C.c_void_p), ("band_max", C.c_void_p),
+                ("sse", C.c_void_p), ("n_valid", C.c_void_p)]
+
+
+class MeGeometryC(C.Structure):
+    _fields_ = [("blocks_per_wg", C.c_int32), ("cands_per_lane", C.c_int32),
+                ("threads", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ProfileC(C.Structure):
+    _fields_ = [("ms", C.c_double * 7), ("launches", C.c_uint64 * 7), ("work", C.c_double * 7)]
+
+
+EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube",
+            "xv_decode_cube", "xv_psnr_bpppb", "xv_encoded_export", "xv_encoded_free",
+            "xv_encode_batch", "xv_decode_batch", "xv_set_me_geometry", "xv_get_me_geometry",
+            "xv_profile_enable", "xv_profile_read"]
+
+_lib = None
+
+
+def lib():
+    """Load libxv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.xv_abi_version.restype = C.c_int
+        L.xv_status_str.argtypes = [C.c_int]
+        L.xv_status_str.restype = C.c_char_p
+        L.xv_last_error.restype = C.c_char_p
+        L.xv_encode_cube.argtypes = [C.POINTER(Cube), C.POINTER(ParamsC), vp, C.POINTER(vp)]
+        L.xv_decode_cube.argtypes = [vp, C.POINTER(Cube), vp]
+        L.xv_psnr_bpppb.argtypes = [C.POINTER(Cube), vp, C.POINTER(MetricsC), vp]
+        L.xv_encoded_export.argtypes = [vp, C.POINTER(ExportC)]
+        L.xv_encoded_free.argtypes = [vp]
+        L.xv_encoded_free.restype = None
+        L.xv_encode_batch.argtypes = [C.c_int, C.POINTER(Cube), C.POINTER(ParamsC), vp,
+                                      C.POINTER(vp)]
+        L.xv_decode_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(Cube), vp]
+        L.xv_set_me_geometry.argtypes = [C.c_int, C.c_int, C.POINTER(MeGeometryC)]
+        L.xv_get_me_geometry.argtypes = [C.c_int, C.c_int, C.POINTER(MeGeometryC)]
+        L.xv_profile_enable.argtypes = [C.c_int]
+        L.xv_profile_read.argtypes = [C.POINTER(ProfileC)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise XvError(rc, lib().xv_last_error().decode(errors="replace"))
+
+
+@dataclass
+class Params:
+    bit_depth: int = 10
+    qp: int = 27
+    block: int = 8
+    search_range: int = 8
+    gop: int = 16
+    pad_mode: int = PAD_ZERO
+    fill_mode: int = FILL_NEAREST
+    flags: int = 0
+
+    def c(self) -> ParamsC:
+        return ParamsC(self.bit_depth, self.qp, self.block, self.search_range, self.gop,
+                       self.pad_mode, self.fill_mode, self.flags)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _cube(t) -> Cube:
+    import torch
+    if not t.is_cuda:
+        raise ValueError("cube must be a device tensor")
+    if t.dim() != 4:
+        raise ValueError("cube must be [T, H, W, bands]")
+    if not t.is_contiguous():
+        raise ValueError("cube must be contiguous")
+    if t.dtype == torch.uint16:
+        dt = U16
+    elif t.dtype == torch.float32:
+        dt = F32
+    else:
+        raise ValueError(f"unsupported dtype {t.dtype}")
+    T, H, W, Bn = t.shape
+    return Cube(C.c_void_p(t.data_ptr()), dt, 0, T, H, W, Bn)
+
+
+class _DevArray:
+    """__cuda_array_interface__ view of library-owned device memory."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(int(s) for s in shape),
+                                         "typestr": typestr, "data": (int(ptr), False),
+                                         "version": 3, "strides": None}
+
+
+@dataclass
+class Encoded:
+    handle: C.c_void_p
+    shape: tuple
+    params: Params
+    _freed: bool = field(default=False)
+
+    def export(self) -> dict:
+        """Device views (torch tensors) of the encoded buffers; signed element
+        types are used for unsigned buffers (reinterpret with numpy .view)."""
+        import torch
+        v = ExportC()
+        _check(lib().xv_encoded_export(self.handle, C.byref(v)))
+        G, T, Hp, Wp, Hb, Wb = v.groups, v.T, v.Hp, v.Wp, v.Hb, v.Wb
+        N = v.params.block
+        Bn = v.bands
+        out = {"dims": dict(T=T, H=v.H, W=v.W, bands=Bn, groups=G, Hp=Hp, Wp=Wp, Hb=Hb, Wb=Wb)}
+
+        def view(ptr, shape, ts):
+            if not ptr:
+                return None
+            return torch.as_tensor(_DevArray(ptr, shape, ts), device="cuda")
+
+        out["frames"] = view(v.frames, (G, T, 3, Hp, Wp), "<i2")
+        out["recon"] = view(v.recon, (G, T, 3, Hp, Wp), "<i2")
+        out["levels"] = view(v.levels, (G, T, 3, Hb, Wb, N, N), "<i2")
+        out["mvs"] = view(v.mvs, (G, T, Hb, Wb, 2), "|i1")
+        out["coef_bits"] = view(v.coef_bits, (G, T, 3, Hb, Wb), "<i4")
+        out["mv_bits"] = view(v.mv_bits, (G, T, Hb, Wb), "<i4")
+        out["band_min"] = view(v.band_min, (Bn,), "<f8")
+        out["band_max"] = view(v.band_max, (Bn,), "<f8")
+        out["sse"] = view(v.sse, (3 * G,), "<i8")
+        out["n_valid"] = view(v.n_valid, (Bn,), "<i8")
+        return out
+
+    def host(self) -> dict:
+        """Synchronous host copies with the library's element types."""
+        import torch
+        torch.cuda.synchronize()
+        ex = self.export()
+        types = {"frames": np.uint16, "recon": np.uint16, "levels": np.int16, "mvs": np.int8,
+                 "coef_bits": np.uint32, "mv_bits": np.uint32, "band_min": np.float64,
+                 "band_max": np.float64, "sse": np.uint64, "n_valid": np.uint64}
+        out = {"dims": ex["dims"]}
+        for k, ty in types.items():
+            t = ex[k]
+            out[k] = None if t is None else t.cpu().numpy().view(ty)
+        return out
+
+    def free(self):
+        if not self._freed:
+            lib().xv_encoded_free(self.handle)
+            self._freed = True
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def encode_cube(cube, params: Params, stream=None) -> Encoded:
+    """xv_encode_cube on a device tensor [T, H, W, bands] (uint16 or float32)."""
+    cb = _cube(cube)
+    pc = params.c()
+    h = C.c_void_p()
+    _check(lib().xv_encode_cube(C.byref(cb), C.byref(pc), _stream_handle(stream), C.byref(h)))
+    return Encoded(h, tuple(cube.shape), params)
+
+
+def encode_batch(cubes, params, stream=None) -> list:
+    """xv_encode_batch: several cubes, one launch per frame step and class."""
+    n = len(cubes)
+    cbs = (Cube * n)(*[_cube(c) for c in cubes])
+    pcs = (ParamsC * n)(*[p.c() for p in params])
+    hs = (C.c_void_p * n)()
+    _check(lib().xv_encode_batch(n, cbs, pcs, _stream_handle(stream), hs))
+    return [Encoded(C.c_void_p(hs[i]), tuple(cubes[i].shape), params[i]) for i in range(n)]
+
+
+def decode_cube(enc: Encoded, out, stream=None):
+    """xv_decode_cube into a device tensor of the encoded cube's shape."""
+    cb = _cube(out)
+    _check(lib().xv_decode_cube(enc.handle, C.byref(cb), _stream_handle(stream)))
+    return out
+
+
+def decode_batch(encs, outs, stream=None):
+    n = len(encs)
+    hs = (C.c_void_p * n)(*[e.handle.value for e in encs])
+    cbs = (Cube * n)(*[_cube(o) for o in outs])
+    _check(lib().xv_decode_batch(n, hs, cbs, _stream_handle(stream)))
+    return outs
+
+
+def psnr_bpppb(orig, enc: Encoded, stream=None) -> dict:
+    """xv_psnr_bpppb; orig may be None (no physical-domain PSNR)."""
+    m = MetricsC()
+    cp = C.byref(_cube(orig)) if orig is not None else None
+    _check(lib().xv_psnr_bpppb(cp, enc.handle, C.byref(m), _stream_handle(stream)))
+    Bn, G = m.bands, m.groups
+    return dict(psnr=list(m.psnr[:Bn]), psnr_phys=list(m.psnr_phys[:Bn]),
+                sse_phys=list(m.sse_phys[:Bn]), sse=list(m.sse[:Bn]),
+                n_valid=list(m.n_valid[:Bn]), band_min=list(m.band_min[:Bn]),
+                band_max=list(m.band_max[:Bn]), coef_bits=m.coef_bits, mv_bits=m.mv_bits,
+                header_bits=m.header_bits, bpppb=m.bpppb,
+                bpppb_group=list(m.bpppb_group[:G]))
+
+
+def set_me_geometry(block: int, search_range: int, blocks_per_wg=0, cands_per_lane=0,
+                    threads=0):
+    g = MeGeometryC(blocks_per_wg, cands_per_lane, threads, 0)
+    _check(lib().xv_set_me_geometry(block, search_range, C.byref(g)))
+
+
+def get_me_geometry(block: int, search_range: int) -> dict:
+    g = MeGeometryC()
+    _check(lib().xv_get_me_geometry(block, search_range, C.byref(g)))
+    return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
+                threads=g.threads)
+
+
+def profile_enable(on: bool = True):
+    _check(lib().xv_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    p = ProfileC()
+    _check(lib().xv_profile_read(C.byref(p)))
+    return {K_NAMES[i]: dict(ms=p.ms[i], launches=p.launches[i], work=p.work[i])
+            for i in range(7)}

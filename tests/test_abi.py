@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every symbol include/xv.h declares;
+argument validation is host-only and is checked here without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "xv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(xv_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def xvmod():
+    from paper_2506_19656_amd import xv
+    if not os.path.exists(xv.LIB_PATH):
+        from paper_2506_19656_amd import build
+        build.build(verbose=False)
+    xv.lib()
+    return xv
+
+
+def test_every_declared_symbol_is_exported(xvmod):
+    names = _declared()
+    assert len(names) >= 14
+    lib = C.CDLL(xvmod.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(xvmod.EXPORTED) <= set(names)
+
+
+def test_abi_version_and_status_strings(xvmod):
+    L = xvmod.lib()
+    assert L.xv_abi_version() == 1
+    assert L.xv_status_str(0) == b"ok"
+    assert L.xv_status_str(-1) == b"invalid argument"
+
+
+def _cube(xv, data=1 << 20, dtype=0, T=4, H=16, W=16, Bn=3):
+    return xv.Cube(C.c_void_p(data), dtype, 0, T, H, W, Bn)
+
+
+@pytest.mark.parametrize("field,value", [("bit_depth", 7), ("bit_depth", 13), ("block", 12),
+                                         ("block", 64), ("qp", 52), ("qp", -13),
+                                         ("search_range", 65), ("search_range", -1),
+                                         ("gop", 0), ("pad_mode", 2), ("fill_mode", 5),
+                                         ("flags", 8)])
+def test_invalid_params_are_rejected_before_any_device_work(xvmod, field, value):
+    p = xvmod.Params(bit_depth=10, qp=27, block=8, search_range=8, gop=16)
+    setattr(p, field, value)
+    pc = p.c()
+    cb = _cube(xvmod)
+    h = C.c_void_p(123)
+    rc = xvmod.lib().xv_encode_cube(C.byref(cb), C.byref(pc), None, C.byref(h))
+    assert rc == xvmod.EINVAL
+    assert h.value is None  # *out is NULL on error
+    assert xvmod.lib().xv_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(data=0), dict(dtype=7), dict(T=0), dict(H=-1),
+                                dict(Bn=65), dict(data=(1 << 20) + 1)])
+def test_invalid_cubes_are_rejected(xvmod, kw):
+    p = xvmod.Params().c()
+    cb = _cube(xvmod, **kw)
+    h = C.c_void_p()
+    rc = xvmod.lib().xv_encode_cube(C.byref(cb), C.byref(p), None, C.byref(h))
+    assert rc == xvmod.EINVAL
+
+
+def test_null_handles(xvmod):
+    L = xvmod.lib()
+    assert L.xv_encode_cube(None, None, None, None) == xvmod.EINVAL
+    assert L.xv_decode_cube(None, None, None) == xvmod.EINVAL
+    m = xvmod.MetricsC()
+    assert L.xv_psnr_bpppb(None, None, C.byref(m), None) == xvmod.EINVAL
+    L.xv_encoded_free(None)  # no-op
+
+
+def test_me_geometry_validation(xvmod):
+    with pytest.raises(xvmod.XvError):
+        xvmod.set_me_geometry(8, 8, cands_per_lane=3)
+    with pytest.raises(xvmod.XvError):
+        xvmod.set_me_geometry(8, 8, threads=1024)
+    with pytest.raises(xvmod.XvError):
+        xvmod.set_me_geometry(12, 8)
+    g = xvmod.get_me_geometry(16, 32)
+    assert g["cands_per_lane"] % 2 == 0 and g["threads"] % 64 == 0 and g["blocks_per_wg"] >= 1
