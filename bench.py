@@ -1,0 +1,226 @@
+"""Benchmark of the coding loop on one MI355X.
+
+Workload (default): the Sentinel-2-like cloud-gapped cube, 500 frames x
+128 x 128 x 6 bands float32 with ~10% NaN, converted to 12 bits and coded at
+QP {17, 22, 27, 32, 37} x block {8, 16, 32} (15 runs), search range 16,
+closed GOPs of 16.  One step = encode + decode + PSNR/bpppb of all 15 runs.
+The cube is generated on the GPU and resident in HBM before timing starts.
+
+Two forms are timed back to back on the same inputs:
+  plain    one cube-run at a time (xv_encode_cube / xv_decode_cube)
+  batched  all 15 runs per call (xv_encode_batch / xv_decode_batch: one launch
+           per frame step and block-size class)
+Both produce bit-identical outputs (checked), hence identical PSNR and bpppb.
+
+Prints ONE JSON line.  `value` is the batched throughput in Mpx*band/s of
+encode + decode (px*band = T*H*W*bands per run, summed over runs).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpx·band/s encode+decode at fixed PSNR, batched/served vs plain; p50/p99 ms"
+
+# MI355X peaks used for the roofline fractions
+HBM_PEAK_GBS = 8000.0
+# v_sad_u16: 2 SAD terms per lane-op; 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+SAD_PEAK_TTERMS = 256 * 64 * 2.4e9 * 2 / 1e12
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(cube_host, wl, seconds_hint=""):
+    """The oracle as it stands, on the host cores: encode + decode + metrics of
+    all 15 runs over the full cube (the same work as one GPU step)."""
+    from oracle import oracle as O
+    O.lib()
+    runs = [(qp, N) for N in wl.blocks for qp in wl.qps]
+    t0 = time.perf_counter()
+    for qp, N in runs:
+        p = O.CodingParams(bit_depth=wl.bit_depth, qp=qp, block=N, search_range=wl.search_range,
+                           gop=wl.gop, pad_mode=wl.pad_mode, fill_mode=wl.fill_mode)
+        enc = O.encode_cube(cube_host, p)
+        rec = O.decode_cube(p, cube_host.shape, enc["levels"], enc["mvs"])
+        O.denormalize_cube(rec, cube_host.shape, N, wl.bit_depth, enc["mn"], enc["mx"],
+                           O.F32 if cube_host.dtype.name == "float32" else O.U16)
+        O.metrics(cube_host, enc, p)
+    dt = time.perf_counter() - t0
+    pxb = wl.px_band * len(runs)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pxb / dt / 1e6, "unit": "Mpx·band/s", "cores": cores, "kind": "oracle",
+            "sample": f"one full step: all {len(runs)} runs on the {wl.T}x{wl.H}x{wl.W}x"
+                      f"{wl.bands} cube, encode+decode+metrics, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=["both", "batched", "plain"], default="both")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(one GPU's share of the work is what it measures)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2506_19656_amd import synth
+    from paper_2506_19656_amd import xv
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = synth.WORKLOADS["s2cloud"]
+    print(f"[bench] generating {wl.name} cube on {dev}", file=sys.stderr, flush=True)
+    cube = synth.s2cloud_cube(device=dev)
+    torch.cuda.synchronize()
+    runs = [(qp, N) for N in wl.blocks for qp in wl.qps]
+    params = [xv.Params(bit_depth=wl.bit_depth, qp=qp, block=N, search_range=wl.search_range,
+                        gop=wl.gop, pad_mode=wl.pad_mode, fill_mode=wl.fill_mode)
+              for qp, N in runs]
+    outs = [torch.empty_like(cube) for _ in runs]
+    pxb_step = wl.px_band * len(runs)
+
+    def step_plain(lat=None):
+        ms = []
+        for p, out in zip(params, outs):
+            t0 = time.perf_counter()
+            enc = xv.encode_cube(cube, p)
+            xv.decode_cube(enc, out)
+            ms.append(xv.psnr_bpppb(cube, enc))  # synchronises
+            enc.free()
+            if lat is not None:
+                lat.append((time.perf_counter() - t0) * 1e3)
+        return ms
+
+    def step_batched(lat=None):
+        t0 = time.perf_counter()
+        encs = xv.encode_batch([cube] * len(params), params)
+        xv.decode_batch(encs, outs)
+        ms = [xv.psnr_bpppb(cube, e) for e in encs]
+        for e in encs:
+            e.free()
+        if lat is not None:
+            lat.append((time.perf_counter() - t0) * 1e3)
+        return ms
+
+    def timed(fn, profile):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        lat = []
+        if profile:
+            xv.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ms = fn(lat)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = xv.profile_read() if profile else None
+        if profile:
+            xv.profile_enable(False)
+        return dt, lat, ms, prof
+
+    res = {}
+    if args.mode in ("both", "plain"):
+        print("[bench] plain path", file=sys.stderr, flush=True)
+        dt, lat, ms_plain, _ = timed(step_plain, profile=False)
+        res["plain"] = dict(value=pxb_step * args.steps / dt / 1e6, ms_per_step=dt / args.steps * 1e3,
+                            p50_ms=_percentile(lat, 0.5), p99_ms=_percentile(lat, 0.99),
+                            latency_unit="one run: encode+decode+metrics")
+    if args.mode in ("both", "batched"):
+        print("[bench] batched path", file=sys.stderr, flush=True)
+        dt, lat, ms_batch, prof = timed(step_batched, profile=True)
+        res["batched"] = dict(value=pxb_step * args.steps / dt / 1e6, ms_per_step=dt / args.steps * 1e3,
+                              p50_ms=_percentile(lat, 0.5), p99_ms=_percentile(lat, 0.99),
+                              latency_unit="one step: all 15 runs")
+    if "plain" in res and "batched" in res:
+        same = all(a["psnr"] == b["psnr"] and a["bpppb"] == b["bpppb"]
+                   for a, b in zip(ms_plain, ms_batch))
+        if not same:
+            raise SystemExit("batched and plain paths disagree")
+    ms = ms_batch if "batched" in res else ms_plain
+    main_form = "batched" if "batched" in res else "plain"
+
+    line = {
+        "metric": METRIC,
+        "value": round(res[main_form]["value"], 3),
+        "unit": "Mpx·band/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res[main_form]["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.T}x{wl.H}x{wl.W}x{wl.bands} f32 cube with ~10% "
+                               f"NaN cloud gaps, B={wl.bit_depth}, QP{list(wl.qps)} x "
+                               f"N{list(wl.blocks)} (15 runs), R={wl.search_range}, "
+                               f"GOP {wl.gop}", "form": main_form,
+                   "px_band_per_step": pxb_step},
+        "p50_ms": round(res[main_form]["p50_ms"], 3),
+        "p99_ms": round(res[main_form]["p99_ms"], 3),
+        "forms": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                  for k, v in res.items()},
+        "quality": {"psnr_db_mean_per_run": [round(float(np.mean(m["psnr"])), 4) for m in ms],
+                    "psnr_phys_db_mean_per_run": [round(float(np.mean(m["psnr_phys"])), 4)
+                                                  for m in ms],
+                    "bpppb_per_run": [round(m["bpppb"], 5) for m in ms],
+                    "runs": [f"QP{qp}/N{N}" for qp, N in runs]},
+    }
+    if "plain" in res and "batched" in res:
+        line["speedup_batched_vs_plain"] = round(res["batched"]["value"] / res["plain"]["value"], 3)
+    if prof is not None:
+        me = prof["me"]
+        enc = prof["encode"]
+        dec = prof["decode"]
+        me_avg_ms = me["ms"] / max(1, me["launches"])
+        me_terms = me["work"] / max(1, me["launches"])
+        achieved = me_terms / (me_avg_ms * 1e-3) / 1e12
+        line["roofline"] = {"kernel": "me_kernel (motion search)", "bound": "alu",
+                            "achieved": round(achieved, 3), "peak": round(SAD_PEAK_TTERMS, 2),
+                            "unit": "T SAD-terms/s", "frac": round(achieved / SAD_PEAK_TTERMS, 4),
+                            "traffic": None, "avg_launch_ms": round(me_avg_ms, 4),
+                            "launches": me["launches"], "terms_per_launch": me_terms}
+        for name, d in (("encode_kernel (fused transform coding)", enc),
+                        ("decode_kernel", dec)):
+            if d["launches"]:
+                avg = d["ms"] / d["launches"]
+                gbs = d["work"] / d["launches"] / (avg * 1e-3) / 1e9
+                key = "roofline_encode" if name.startswith("encode") else "roofline_decode"
+                line[key] = {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                             "avg_launch_ms": round(avg, 4), "launches": d["launches"]}
+        line["kernel_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()
+                                      if v["launches"]}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(cube.cpu().numpy(), wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

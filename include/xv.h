@@ -189,7 +189,8 @@ int xv_decode_batch(int n, xv_encoded* const* encs, const xv_cube* outs,
 
 /* Geometry of the motion-search kernel for one (N, R): blocks per
  * workgroup along x, candidates per lane along x (even), threads per
- * workgroup (multiple of 64, <= 512).  Zero fields select defaults. */
+ * workgroup (multiple of 64, <= 512).  Zero fields take the default; NULL
+ * or all fields zero restores the default for (block, search_range). */
 typedef struct {
   int32_t blocks_per_wg;
   int32_t cands_per_lane;

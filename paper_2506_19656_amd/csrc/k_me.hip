@@ -22,6 +22,8 @@
 //    R <= 32; 23/15 for larger R) reduced with an LDS atomic min.
 #include "xv_internal.h"
 
+#include <algorithm>
+
 namespace xv {
 
 namespace {
@@ -72,32 +74,51 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
   const int cpitch = nb * N / 2;
 
   // Stage reference windows (zero outside the picture) and current blocks.
+  // Thread t covers dword column t % wpairs of rows t / wpairs + k * rpp.
   const int gy0 = by * N - R, gx0 = bx0 * N - R;
   const int wpairs = s.wc / 2;
-  const int nwin = nch * s.rows * wpairs;
   const size_t plane = (size_t)Hp * Wp;
-  for (int e = threadIdx.x; e < nwin; e += blockDim.x) {
-    const int ch = e / (s.rows * wpairs);
-    const int rem = e - ch * s.rows * wpairs;
-    const int row = rem / wpairs, m = rem - (rem / wpairs) * wpairs;
-    const int gy = gy0 + row, gx = gx0 + 2 * m;
-    uint32_t v0 = 0, v1 = 0;
-    if (gy >= 0 && gy < Hp) {
-      const uint16_t* rp = job.ref + ch * plane + (size_t)gy * Wp;
-      if (gx >= 0 && gx < Wp) v0 = rp[gx];
-      if (gx + 1 >= 0 && gx + 1 < Wp) v1 = rp[gx + 1];
+  const int nrows = nch * s.rows;
+  {
+    const int rpp = max(1, (int)blockDim.x / wpairs);  // rows per pass
+    const int r0 = threadIdx.x / wpairs;
+    for (int m = threadIdx.x - r0 * wpairs; m < wpairs; m += (int)blockDim.x) {
+      if (r0 >= rpp) break;
+      const int gx = gx0 + 2 * m;
+      const bool even = (gx0 & 1) == 0;
+      const bool xin = gx >= 0 && gx + 1 < Wp;
+      for (int rr = r0; rr < nrows; rr += rpp) {
+        const int ch = rr >= 2 * s.rows ? 2 : (rr >= s.rows ? 1 : 0);
+        const int row = rr - ch * s.rows;
+        const int gy = gy0 + row;
+        uint32_t v = 0;
+        if (gy >= 0 && gy < Hp) {
+          const uint16_t* rp = job.ref + ch * plane + (size_t)gy * Wp;
+          if (even) {
+            if (xin) v = *(const uint32_t*)(rp + gx);
+          } else {
+            const uint32_t v0 = (gx >= 0 && gx < Wp) ? rp[gx] : 0u;
+            const uint32_t v1 = (gx + 1 >= 0 && gx + 1 < Wp) ? rp[gx + 1] : 0u;
+            v = v0 | (v1 << 16);
+          }
+        }
+        win[rr * s.pitch + m] = v;
+      }
     }
-    win[(ch * s.rows + row) * s.pitch + m] = v0 | (v1 << 16);
   }
-  const int ncur = nch * N * (nbv * N / 2);
-  for (int e = threadIdx.x; e < ncur; e += blockDim.x) {
-    const int per = N * (nbv * N / 2);
-    const int ch = e / per;
-    const int rem = e - ch * per;
-    const int row = rem / (nbv * N / 2), m = rem - (rem / (nbv * N / 2)) * (nbv * N / 2);
-    const uint32_t* cp = (const uint32_t*)(job.cur + ch * plane + (size_t)(by * N + row) * Wp +
-                                           bx0 * N);
-    curt[(ch * N + row) * cpitch + m] = cp[m];
+  {
+    const int cw = nbv * N / 2;  // dwords per current row
+    const int rpp = max(1, (int)blockDim.x / cw);
+    const int r0 = threadIdx.x / cw;
+    for (int m = threadIdx.x - r0 * cw; m < cw; m += (int)blockDim.x) {
+      if (r0 >= rpp) break;
+      for (int rr = r0; rr < nch * N; rr += rpp) {
+        const int ch = rr / N, row = rr - (rr / N) * N;
+        const uint32_t* cp = (const uint32_t*)(job.cur + ch * plane + (size_t)(by * N + row) * Wp +
+                                               bx0 * N);
+        curt[rr * cpitch + m] = cp[m];
+      }
+    }
   }
   for (int b = threadIdx.x; b < nb; b += blockDim.x) best[b] = ~0ull;
   __syncthreads();
@@ -117,40 +138,24 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
     for (int ch = 0; ch < nch; ch++) {
       const uint32_t* wbase = win + (ch * s.rows + dy) * s.pitch + (b * N + gxi * KX) / 2;
       const uint32_t* cbase = curt + ch * N * cpitch + b * (N / 2);
-      // v_sad_u16 keeps its sum in 16 bits, so at most 8 of them (16 terms
-      // of at most 4095) are chained into a partial before it is added to the
-      // 32-bit SAD: RPP rows per partial for N < 16, two partials per row
-      // for N = 32.
-      constexpr int RPP = N >= 16 ? 1 : 16 / N;
-      for (int i0 = 0; i0 < N; i0 += RPP) {
-        uint32_t part[KX];
+#pragma unroll 2
+      for (int i = 0; i < N; i++) {
+        uint32_t D[ND], O[ND - 1], C[N / 2];
+        const uint32_t* wr = wbase + i * s.pitch;
 #pragma unroll
-        for (int k = 0; k < KX; k++) part[k] = 0;
+        for (int q = 0; q < ND; q++) D[q] = wr[q];
 #pragma unroll
-        for (int rr = 0; rr < RPP; rr++) {
-          uint32_t D[ND], O[ND - 1], C[N / 2];
-          const uint32_t* wr = wbase + (i0 + rr) * s.pitch;
+        for (int q = 0; q < ND - 1; q++) O[q] = __builtin_amdgcn_alignbit(D[q + 1], D[q], 16);
 #pragma unroll
-          for (int q = 0; q < ND; q++) D[q] = wr[q];
+        for (int m = 0; m < N / 2; m++) C[m] = cbase[i * cpitch + m];
 #pragma unroll
-          for (int q = 0; q < ND - 1; q++) O[q] = __builtin_amdgcn_alignbit(D[q + 1], D[q], 16);
+        for (int k = 0; k < KX; k++) {
 #pragma unroll
-          for (int m = 0; m < N / 2; m++) C[m] = cbase[(i0 + rr) * cpitch + m];
-#pragma unroll
-          for (int k = 0; k < KX; k++) {
-#pragma unroll
-            for (int m = 0; m < N / 2; m++) {
-              const uint32_t pr = (k & 1) ? O[(k >> 1) + m] : D[(k >> 1) + m];
-              part[k] = __builtin_amdgcn_sad_u16(pr, C[m], part[k]);
-              if (N == 32 && m == 7) {
-                acc[k] += part[k];
-                part[k] = 0;
-              }
-            }
+          for (int m = 0; m < N / 2; m++) {
+            const uint32_t pr = (k & 1) ? O[(k >> 1) + m] : D[(k >> 1) + m];
+            acc[k] = __builtin_amdgcn_sad_u16(pr, C[m], acc[k]);
           }
         }
-#pragma unroll
-        for (int k = 0; k < KX; k++) acc[k] += part[k];
       }
     }
     const int x0 = (bx0 + b) * N, y0 = by * N;
@@ -212,31 +217,84 @@ hipError_t launch_me_n(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t 
   }
 }
 
+// VGPRs per lane of the motion-search kernel instance for (N, KX).
+template <int N>
+int me_vgprs_n(int kx) {
+  hipFuncAttributes a{};
+  hipError_t e = hipErrorInvalidValue;
+  switch (kx) {
+    case 2: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 2>); break;
+    case 4: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 4>); break;
+    case 6: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 6>); break;
+    case 8: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 8>); break;
+    case 10: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 10>); break;
+    case 12: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 12>); break;
+    case 14: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 14>); break;
+    case 16: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 16>); break;
+    case 18: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 18>); break;
+    default: break;
+  }
+  return (e == hipSuccess && a.numRegs > 0) ? a.numRegs : 128;
+}
+
+int me_vgprs(int N, int kx) {
+  switch (N) {
+    case 4: return me_vgprs_n<4>(kx);
+    case 8: return me_vgprs_n<8>(kx);
+    case 16: return me_vgprs_n<16>(kx);
+    default: return me_vgprs_n<32>(kx);
+  }
+}
+
 }  // namespace
 
 size_t me_lds_bytes_for(int N, int R, const MeGeom& g) {
   return me_lds_bytes(N, me_shape(N, R, g.kx, g.nb), g.nb);
 }
 
-MeGeom me_default_geometry(int N, int R) {
+// Default geometry from a simple model of a CU (160 KB LDS, 4 SIMDs with 512
+// VGPRs per lane and at most 8 waves each).  Candidates per lane (KX, even):
+// maximise the share of SAD instructions among the lane's VALU work
+// (KX N/2 SADs against (KX + N)/2 - 1 realignments per row) times the share
+// of useful candidates (2R+1 of G KX).  Blocks per workgroup and workgroup
+// size: maximise lane occupancy of the rounds of items times the resident
+// waves per SIMD (saturating at 3).  The empirical tuner refines this.
+MeGeom me_default_geometry(int N, int R, int max_nb) {
   const int span = 2 * R + 1;
-  // candidates per lane: least wasted candidates, then the widest
-  int kx = 2, waste = 1 << 30;
+  int kx = 2;
+  double best_score = -1.0;
   for (int k = 2; k <= 18; k += 2) {
-    int w = ((span + k - 1) / k) * k - span;
-    if (w < waste || (w == waste && k > kx)) { waste = w; kx = k; }
+    const int G = (span + k - 1) / k;
+    const double sad = (double)k * N / 2;
+    const double valu = sad + (k + N) / 2 - 1;
+    const double score = sad / valu * (double)span / (double)(G * k);
+    if (score > best_score + 1e-12) { best_score = score; kx = k; }
   }
-  // blocks per workgroup: best lane occupancy of the final round, LDS <= 64 KB
-  const int threads = 256;
-  int nb = 1;
+  const int vgpr = me_vgprs(N, kx);
+  const int waves_by_vgpr = std::max(1, std::min(8, 512 / std::max(1, vgpr)));
+  int nb = 1, threads = 256;
   double bestf = -1.0;
-  for (int c = 1; c <= 16; c++) {
-    MeShape sh = me_shape(N, R, kx, c);
-    if (me_lds_bytes(N, sh, c) > 64 * 1024 && c > 1) break;
-    int items = c * sh.ipb;
-    int rounds = (items + threads - 1) / threads;
-    double f = (double)items / (double)(rounds * threads);
-    if (f > bestf + 1e-9) { bestf = f; nb = c; }
+  const int cmax = std::max(1, std::min(16, max_nb));
+  for (int c = 1; c <= cmax; c++) {
+    const MeShape sh = me_shape(N, R, kx, c);
+    const size_t lds = me_lds_bytes(N, sh, c);
+    if (lds > 96 * 1024 && c > 1) break;
+    const int items = c * sh.ipb;
+    for (int th = 128; th <= 512; th += 64) {
+      const int rounds = (items + th - 1) / th;
+      const double lane = (double)items / (double)(rounds * th);
+      const int wpg = th / 64;
+      const int wg_lds = (int)((160 * 1024) / std::max<size_t>(1, lds));
+      const int wg_waves = (4 * waves_by_vgpr) / wpg;
+      const int wg = std::max(1, std::min(wg_lds, wg_waves));
+      const double occ = std::min(3.0, (double)(wg * wpg) / 4.0);
+      const double f = lane * occ;
+      if (f > bestf + 1e-9 || (f > bestf - 1e-9 && c > nb)) {
+        bestf = f;
+        nb = c;
+        threads = th;
+      }
+    }
   }
   return MeGeom{nb, kx, threads};
 }

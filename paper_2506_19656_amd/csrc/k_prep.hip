@@ -38,8 +38,50 @@ __device__ inline float key_f32(uint32_t k) {
   return __uint_as_float(u);
 }
 
-// Each thread owns one band: element e = gtid + j*stride with stride a
-// multiple of the band count, so consecutive lanes read consecutive memory.
+// Pixel-major scan: thread i handles pixels i, i + stride, ... and keeps
+// per-band keys for a chunk of up to 8 bands in registers; blocks merge them
+// in LDS, then with one global atomic per band (min/max/count are order
+// independent, so the result is deterministic).
+template <typename Tv>
+__device__ inline void stats_chunk(const Tv* d, int64_t npix, int bands, int b0, int nb,
+                                   uint32_t* smin, uint32_t* smax, uint32_t* snan) {
+  uint32_t lo[8], hi[8], nn[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    lo[j] = 0xffffffffu;
+    hi[j] = 0u;
+    nn[j] = 0u;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
+    const Tv* px = d + p * bands + b0;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      if (j >= nb) break;
+      uint32_t k;
+      if constexpr (sizeof(Tv) == 2) {
+        k = (uint32_t)px[j];
+      } else {
+        const float f = px[j];
+        if (f != f) {
+          nn[j]++;
+          continue;
+        }
+        k = f32_key(f);
+      }
+      lo[j] = min(lo[j], k);
+      hi[j] = max(hi[j], k);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    if (j >= nb) break;
+    if (lo[j] != 0xffffffffu) atomicMin(&smin[b0 + j], lo[j]);
+    if (hi[j] != 0u) atomicMax(&smax[b0 + j], hi[j]);
+    if (nn[j]) atomicAdd(&snan[b0 + j], nn[j]);
+  }
+}
+
 __global__ void __launch_bounds__(kThreads) stats_kernel(StatsArgs a) {
   __shared__ uint32_t smin[XV_MAX_BANDS], smax[XV_MAX_BANDS], snan[XV_MAX_BANDS];
   const int bands = a.bands;
@@ -49,36 +91,12 @@ __global__ void __launch_bounds__(kThreads) stats_kernel(StatsArgs a) {
     snan[i] = 0u;
   }
   __syncthreads();
-  const int64_t total = a.npix * bands;
-  const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-  const int64_t stride = (nthr / bands) * bands;
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t lo = 0xffffffffu, hi = 0u, nn = 0u;
-  if (gtid < stride) {
-    if (a.dtype == XV_U16) {
-      const uint16_t* d = (const uint16_t*)a.data;
-      for (int64_t e = gtid; e < total; e += stride) {
-        uint32_t k = d[e];
-        lo = min(lo, k);
-        hi = max(hi, k);
-      }
-    } else {
-      const float* d = (const float*)a.data;
-      for (int64_t e = gtid; e < total; e += stride) {
-        float f = d[e];
-        if (f != f) {
-          nn++;
-          continue;
-        }
-        uint32_t k = f32_key(f);
-        lo = min(lo, k);
-        hi = max(hi, k);
-      }
-    }
-    const int b = (int)(gtid % bands);
-    atomicMin(&smin[b], lo);
-    atomicMax(&smax[b], hi);
-    if (nn) atomicAdd(&snan[b], nn);
+  for (int b0 = 0; b0 < bands; b0 += 8) {
+    const int nb = min(8, bands - b0);
+    if (a.dtype == XV_U16)
+      stats_chunk<uint16_t>((const uint16_t*)a.data, a.npix, bands, b0, nb, smin, smax, snan);
+    else
+      stats_chunk<float>((const float*)a.data, a.npix, bands, b0, nb, smin, smax, snan);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < bands; i += blockDim.x) {
@@ -128,111 +146,95 @@ __device__ inline double load_sample(const void* data, int dtype, int64_t i) {
   return dtype == XV_U16 ? (double)((const uint16_t*)data)[i] : (double)((const float*)data)[i];
 }
 
-// Gap-free path: one thread per padded pixel (t, y, x); reads the pixel's
-// bands (contiguous) and writes one sample to each of the 3G channel planes.
-__global__ void __launch_bounds__(kThreads) pack_dense_kernel(PackArgs a) {
+// Missing-sample fill along time at one (pixel, band) series; `src` indexes
+// the sample of frame 0, `fstride` is the frame size in elements.  NEAREST:
+// the valid sample at the smallest |t - t'|, ties to the earlier t'.
+// FORWARD: the last valid value before t, else the first one after it.  A
+// series without a valid sample gives the band minimum.
+__device__ inline double fill_missing(const float* d, int64_t src, int64_t fstride, int64_t t,
+                                      int64_t T, int fill_mode, double mn) {
+  if (fill_mode == XV_FILL_FORWARD) {
+    for (int64_t u = t - 1; u >= 0; u--) {
+      const float f = d[u * fstride + src];
+      if (f == f) return (double)f;
+    }
+    for (int64_t u = t + 1; u < T; u++) {
+      const float f = d[u * fstride + src];
+      if (f == f) return (double)f;
+    }
+    return mn;
+  }
+  for (int64_t dd = 1; dd < T; dd++) {
+    if (t - dd < 0 && t + dd >= T) break;
+    if (t - dd >= 0) {
+      const float f = d[(t - dd) * fstride + src];
+      if (f == f) return (double)f;
+    }
+    if (t + dd < T) {
+      const float f = d[(t + dd) * fstride + src];
+      if (f == f) return (double)f;
+    }
+  }
+  return mn;
+}
+
+// Conversion and packing: one thread per padded pixel (t, y, x) reads the
+// pixel's bands (contiguous), fills missing samples, converts, and writes
+// one sample to each of the 3G channel planes (edge pixels replicate the
+// last real row/column; padding channels are zero or repeat the last band).
+// Validity bytes are written only when the cube has missing samples.
+__global__ void __launch_bounds__(kThreads) pack_kernel(PackArgs a) {
   __shared__ double smn[XV_MAX_BANDS], srg[XV_MAX_BANDS];
-  if (a.dtype == XV_F32 && *a.nan_total != 0u) return;  // gap-filling path runs
+  __shared__ int sall[XV_MAX_BANDS];
+  const bool gaps = a.dtype == XV_F32 && *a.nan_total != 0u;
   for (int i = threadIdx.x; i < a.bands; i += blockDim.x) {
     smn[i] = a.mn[i];
     srg[i] = a.mx[i] - a.mn[i];
+    sall[i] = gaps && (int64_t)a.nan_count[i] == a.T * a.H * a.W;
   }
   __syncthreads();
+  // workgroup -> (frame row, 256-pixel chunk); one uniform division
   const int64_t plane = (int64_t)a.Hp * a.Wp;
-  const int64_t total = a.T * plane;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int64_t t = idx / plane;
-  const int64_t o = idx - t * plane;
-  const int y = (int)(o / a.Wp), x = (int)(o - (int64_t)(o / a.Wp) * a.Wp);
+  const int xch = (a.Wp + kThreads - 1) / kThreads;
+  const int64_t rowid = blockIdx.x / xch;
+  const int x = (int)(blockIdx.x - rowid * xch) * kThreads + threadIdx.x;
+  if (x >= a.Wp) return;
+  const int64_t t = rowid / a.Hp;
+  const int y = (int)(rowid - t * a.Hp);
+  const int64_t o = (int64_t)y * a.Wp + x;
   const int64_t ys = y < a.H ? y : a.H - 1, xs = x < a.W ? x : a.W - 1;
-  const int64_t src = ((t * a.H + ys) * a.W + xs) * a.bands;
+  const bool real = y < a.H && x < a.W;
+  const int64_t fstride = a.H * a.W * a.bands;
+  const int64_t pix = (ys * a.W + xs) * a.bands;
   const double L = (double)((1 << a.bit_depth) - 1);
   uint16_t last = 0;
   for (int b = 0; b < a.bands; b++) {
-    uint16_t q = convert(load_sample(a.data, a.dtype, src + b), smn[b], srg[b], L);
+    double v;
+    bool valid = true;
+    if (a.dtype == XV_U16) {
+      v = (double)((const uint16_t*)a.data)[t * fstride + pix + b];
+    } else {
+      const float* d = (const float*)a.data;
+      const float f = d[t * fstride + pix + b];
+      if (f == f) {
+        v = (double)f;
+      } else {
+        valid = false;
+        v = sall[b] ? smn[b] : fill_missing(d, pix + b, fstride, t, a.T, a.fill_mode, smn[b]);
+      }
+    }
+    const uint16_t q = convert(v, smn[b], srg[b], L);
     const int g = b / 3, c = b - 3 * (b / 3);
-    a.frames[((int64_t)(g * a.T + t) * 3 + c) * plane + o] = q;
+    const int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
+    a.frames[off] = q;
+    if (gaps) a.vmask[off] = (uint8_t)(valid && real);
     last = q;
   }
   const int g = a.groups - 1;
-  for (int c = a.bands - 3 * g; c < 3; c++)
-    a.frames[((int64_t)(g * a.T + t) * 3 + c) * plane + o] =
-        a.pad_mode == XV_PAD_REPEAT ? last : (uint16_t)0;
-}
-
-// Gap-filling path (float input holding NaN): one thread per (padded pixel,
-// band) walks the time series once; each gap is resolved when its end is
-// found, choosing the nearest valid time (ties to the earlier one) or the
-// last valid value (forward fill; leading gaps take the first valid value).
-// A series without any valid sample takes the band minimum.  Also writes the
-// validity bytes (real pixel of a real band that was not missing).
-__global__ void __launch_bounds__(kThreads) pack_fill_kernel(PackArgs a) {
-  if (*a.nan_total == 0u) return;
-  const int64_t plane = (int64_t)a.Hp * a.Wp;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= plane * a.bands) return;
-  const int b = (int)(idx % a.bands);
-  const int64_t o = idx / a.bands;
-  const int y = (int)(o / a.Wp), x = (int)(o - (int64_t)(o / a.Wp) * a.Wp);
-  const int64_t ys = y < a.H ? y : a.H - 1, xs = x < a.W ? x : a.W - 1;
-  const bool real = y < a.H && x < a.W;
-  const float* d = (const float*)a.data;
-  const int64_t fstride = a.H * a.W * a.bands;
-  const int64_t src = (ys * a.W + xs) * a.bands + b;
-  const double mn = a.mn[b], range = a.mx[b] - a.mn[b];
-  const double L = (double)((1 << a.bit_depth) - 1);
-  const int g = b / 3, c = b - 3 * g;
-  const bool last_band = (b == a.bands - 1);
-  const int nch_last = a.bands - 3 * (a.groups - 1);
-
-  auto emit = [&](int64_t t, double v, bool valid) {
-    uint16_t q = convert(v, mn, range, L);
-    int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
-    a.frames[off] = q;
-    a.vmask[off] = (uint8_t)(valid && real);
-    if (last_band) {
-      for (int cc = nch_last; cc < 3; cc++) {
-        int64_t po = ((int64_t)(g * a.T + t) * 3 + cc) * plane + o;
-        a.frames[po] = a.pad_mode == XV_PAD_REPEAT ? q : (uint16_t)0;
-        a.vmask[po] = 0;
-      }
-    }
-  };
-
-  int64_t prevT = -1;
-  double prevV = 0.0;
-  int64_t t = 0;
-  while (t < a.T) {
-    float f = d[t * fstride + src];
-    if (f == f) {
-      emit(t, (double)f, true);
-      prevT = t;
-      prevV = (double)f;
-      t++;
-      continue;
-    }
-    int64_t u = t + 1;
-    float fu = 0.f;
-    while (u < a.T) {
-      fu = d[u * fstride + src];
-      if (fu == fu) break;
-      u++;
-    }
-    const bool has_next = u < a.T;
-    const double nextV = (double)fu;
-    for (int64_t s = t; s < u; s++) {
-      double v;
-      if (a.fill_mode == XV_FILL_FORWARD) {
-        v = prevT >= 0 ? prevV : (has_next ? nextV : mn);
-      } else if (prevT >= 0 && has_next) {
-        v = (s - prevT <= u - s) ? prevV : nextV;
-      } else {
-        v = prevT >= 0 ? prevV : (has_next ? nextV : mn);
-      }
-      emit(s, v, false);
-    }
-    t = u;
+  for (int c = a.bands - 3 * g; c < 3; c++) {
+    const int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
+    a.frames[off] = a.pad_mode == XV_PAD_REPEAT ? last : (uint16_t)0;
+    if (gaps) a.vmask[off] = 0;
   }
 }
 
@@ -243,12 +245,13 @@ __global__ void __launch_bounds__(kThreads) denorm_kernel(DenormArgs a) {
     srg[i] = a.mx[i] - a.mn[i];
   }
   __syncthreads();
-  const int64_t npix = a.T * a.H * a.W;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
-  const int64_t t = p / (a.H * a.W);
-  const int64_t r = p - t * (a.H * a.W);
-  const int64_t y = r / a.W, x = r - (r / a.W) * a.W;
+  const int xch = (int)((a.W + kThreads - 1) / kThreads);
+  const int64_t rowid = blockIdx.x / xch;
+  const int64_t x = (int64_t)(blockIdx.x - rowid * xch) * kThreads + threadIdx.x;
+  if (x >= a.W) return;
+  const int64_t t = rowid / a.H;
+  const int64_t y = rowid - t * a.H;
+  const int64_t p = (t * a.H + y) * a.W + x;
   const int64_t plane = (int64_t)a.Hp * a.Wp;
   const double L = (double)((1 << a.bit_depth) - 1);
   for (int b = 0; b < a.bands; b++) {
@@ -266,66 +269,76 @@ __global__ void __launch_bounds__(kThreads) denorm_kernel(DenormArgs a) {
   }
 }
 
-// Physical squared error: element mapping as in stats (one band per thread);
-// per-block partial sums are reduced in a fixed order, so the result is
-// deterministic.
+// Physical squared error: thread per pixel x of a frame row, rows taken
+// grid-stride by workgroup; per-band sums for a chunk of up to 8 bands live in
+// registers.  Each block reduces its sums with a fixed LDS tree into
+// partial[block][band]; the final sum over blocks has a fixed order too, so
+// the result is deterministic.
 __global__ void __launch_bounds__(kThreads) phys_sse_kernel(PhysArgs a) {
-  __shared__ double sacc[kThreads];
+  __shared__ double sred[kThreads];
   const int bands = a.bands;
-  const int64_t npix = a.T * a.H * a.W;
-  const int64_t total = npix * bands;
-  const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-  const int64_t stride = (nthr / bands) * bands;
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t plane = (int64_t)a.Hp * a.Wp;
   const double L = (double)((1 << a.bit_depth) - 1);
-  double acc = 0.0;
-  if (gtid < stride) {
-    const int b = (int)(gtid % bands);
-    const int g = b / 3, c = b - 3 * g;
-    const double mn = a.mn[b], range = a.mx[b] - a.mn[b];
-    for (int64_t e = gtid; e < total; e += stride) {
-      double xv = load_sample(a.orig, a.dtype, e);
-      if (xv != xv) continue;
-      const int64_t p = e / bands;
-      const int64_t t = p / (a.H * a.W);
-      const int64_t r = p - t * (a.H * a.W);
-      const int64_t y = r / a.W, x = r - (r / a.W) * a.W;
-      uint16_t q = a.recon[((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x];
-      double num = (double)q * range;
-      double v = mn + num / L;
-      double xh;
-      if (a.dtype == XV_U16) {
-        double rr = floor(v + 0.5);
-        xh = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
-      } else {
-        xh = (double)(float)v;
+  const int xch = (int)((a.W + kThreads - 1) / kThreads);
+  const int64_t nrows = a.T * a.H * xch;
+  for (int b0 = 0; b0 < bands; b0 += 8) {
+    const int nb = min(8, bands - b0);
+    double acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) acc[j] = 0.0;
+    for (int64_t rid = blockIdx.x; rid < nrows; rid += gridDim.x) {
+      const int64_t row = rid / xch;
+      const int64_t x = (rid - row * xch) * kThreads + threadIdx.x;
+      if (x >= a.W) continue;
+      const int64_t t = row / a.H, y = row - (row / a.H) * a.H;
+      const int64_t e0 = ((t * a.H + y) * a.W + x) * bands + b0;
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        if (j >= nb) break;
+        const int b = b0 + j;
+        const double xv = load_sample(a.orig, a.dtype, e0 + j);
+        if (xv != xv) continue;
+        const int g = b / 3, c = b - 3 * g;
+        const uint16_t q = a.recon[((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x];
+        const double num = (double)q * (a.mx[b] - a.mn[b]);
+        const double v = a.mn[b] + num / L;
+        double xh;
+        if (a.dtype == XV_U16) {
+          const double rr = floor(v + 0.5);
+          xh = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
+        } else {
+          xh = (double)(float)v;
+        }
+        acc[j] = acc[j] + (xv - xh) * (xv - xh);
       }
-      double e2 = (xv - xh) * (xv - xh);
-      acc = acc + e2;
     }
-  }
-  sacc[threadIdx.x] = acc;
-  __syncthreads();
-  // band of local thread i is (blockIdx.x*blockDim.x + i) % bands
-  if ((int)threadIdx.x < bands) {
-    const int64_t base = (int64_t)blockIdx.x * blockDim.x;
-    const int b = (int)threadIdx.x;
-    double s = 0.0;
-    for (int i = 0; i < (int)blockDim.x; i++) {
-      int64_t g = base + i;
-      if (g < stride && (int)(g % bands) == b) s = s + sacc[i];
+    for (int j = 0; j < nb; j++) {
+      sred[threadIdx.x] = acc[j];
+      __syncthreads();
+      for (int w = kThreads / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sred[threadIdx.x] = sred[threadIdx.x] + sred[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) a.partial[(int64_t)blockIdx.x * bands + b0 + j] = sred[0];
+      __syncthreads();
     }
-    a.partial[(int64_t)blockIdx.x * bands + b] = s;
   }
 }
 
-__global__ void phys_reduce_kernel(PhysArgs a) {
-  int b = threadIdx.x;
-  if (b >= a.bands) return;
-  double s = 0.0;
-  for (int k = 0; k < a.nblocks; k++) s = s + a.partial[(int64_t)k * a.bands + b];
-  a.out[b] = s;
+// Deterministic final sum: block b sums partial[*][b] with a fixed
+// assignment of partials to threads and a fixed tree.
+__global__ void __launch_bounds__(kThreads) phys_reduce_kernel(PhysArgs a) {
+  __shared__ double sred[kThreads];
+  const int b = blockIdx.x;
+  double v = 0.0;
+  for (int k = threadIdx.x; k < a.nblocks; k += blockDim.x) v = v + a.partial[(int64_t)k * a.bands + b];
+  sred[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sred[threadIdx.x] = sred[threadIdx.x] + sred[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.out[b] = sred[0];
 }
 
 // Job table of one cube, step-major: entry (s, g * nk + k) describes frame
@@ -397,15 +410,14 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 }
 
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
+  // grid: enough blocks to fill the GPU several times over, each looping
   hipError_t e;
   if ((e = launch_fill_u32(a.minkey, 0xffffffffu, a.bands, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(a.maxkey, 0u, a.bands, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(a.nan_count, 0u, a.bands, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(a.nan_total, 0u, 1, s)) != hipSuccess) return e;
-  int64_t total = a.npix * a.bands;
-  int blocks = grid_for(total, kThreads * 16);
+  int blocks = grid_for(a.npix, kThreads * 4);
   blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
-  if ((int64_t)blocks * kThreads < a.bands) blocks = grid_for(a.bands, kThreads);
   stats_kernel<<<blocks, kThreads, 0, s>>>(a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   stats_finalize_kernel<<<1, 64, 0, s>>>(a);
@@ -413,29 +425,27 @@ hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
-  const int64_t plane = (int64_t)a.Hp * a.Wp;
-  pack_dense_kernel<<<grid_for(a.T * plane, kThreads), kThreads, 0, s>>>(a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || a.dtype != XV_F32) return e;
-  pack_fill_kernel<<<grid_for(plane * a.bands, kThreads), kThreads, 0, s>>>(a);
+  const int64_t blocks = a.T * a.Hp * (int64_t)((a.Wp + kThreads - 1) / kThreads);
+  pack_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_denorm(const DenormArgs& a, hipStream_t s) {
-  denorm_kernel<<<grid_for(a.T * a.H * a.W, kThreads), kThreads, 0, s>>>(a);
+  const int64_t blocks = a.T * a.H * ((a.W + kThreads - 1) / kThreads);
+  denorm_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(a);
   return hipGetLastError();
 }
 
 int phys_blocks(int64_t npix) {
-  int64_t b = (npix + kThreads * 8 - 1) / (kThreads * 8);
-  return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+  int64_t b = (npix + kThreads * 4 - 1) / (kThreads * 4);
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
 hipError_t launch_phys_sse(const PhysArgs& a, hipStream_t s) {
   phys_sse_kernel<<<a.nblocks, kThreads, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  phys_reduce_kernel<<<1, 64, 0, s>>>(a);
+  phys_reduce_kernel<<<a.bands, kThreads, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -39,22 +39,25 @@ struct Tile {
   static constexpr int L2N = ilog2c(N);
 };
 
-// LDS layout per workgroup (int16 / u16):
-//   CUR, PRED [3][NBW][N][N]  current and prediction rows
-//   TD [3][NBW][N][P]          forward row-stage output transposed ([k][y]);
-//                              each column thread then overwrites its own row
-//                              with the dequantised column ([k][l])
-//   E  [3][NBW][N][P]          inverse column-stage output ([y][k])
-//   L  [3][NBW][N*N]           levels, raster [l][k]
-//   scan [N*N]                 scan position -> raster index
+// LDS layout per workgroup (int16):
+//   TD [3][NBW][N][P]  forward row-stage output transposed ([k][y]); each
+//                      column thread then overwrites its own row with the
+//                      dequantised column ([k][l])
+//   E  [3][NBW][N][P]  first the residual rows ([y][x]), then the inverse
+//                      column-stage output ([y][k])
+//   L  [3][NBW][N*N]   levels, raster [l][k]
+//   scan [N*N]         scan position -> raster index
+//   red                per-workgroup sums: squared error per channel, bits
 template <int N>
 struct alignas(16) Lds {
-  uint16_t CUR[3][Tile<N>::NBW][N][N];
-  uint16_t PRED[3][Tile<N>::NBW][N][N];
   int16_t TD[3][Tile<N>::NBW][N][Tile<N>::P];
   int16_t E[3][Tile<N>::NBW][N][Tile<N>::P];
   int16_t L[3][Tile<N>::NBW][N * N];
   uint16_t scan[N * N];
+  unsigned long long sse[3];
+  uint32_t cbits[3][Tile<N>::NBW];
+  uint32_t nnz[3][Tile<N>::NBW];
+  uint32_t mvbits;
 };
 
 template <int N>
@@ -91,10 +94,13 @@ __device__ inline bool locate(const LaunchDesc& jd, TileCoord& tc) {
 // Matrix products on v_dot2c_i32_i16: two 16x16-bit products per lane-op.
 // Every stage is an outer-product loop over input pairs m: all N outputs
 // accumulate acc[k] += M[k][2m] x[2m] + M[k][2m+1] x[2m+1], the coefficient
-// pairs coming from __constant__ tables through scalar loads (SGPR operands),
-// the input pair from LDS.  Inputs are 16-bit by construction: residuals
-// (|r| <= 4095), row-stage outputs (|T| < 2^15), dequantised levels and the
-// inverse column-stage output (both clipped to 16 bits).
+// pairs coming through scalar loads (SGPR operands) from tables passed by
+// pointer, the input pair from LDS.  Inputs are 16-bit by construction:
+// residuals (|r| <= 4095), row-stage outputs (|T| < 2^15), dequantised levels
+// and the inverse column-stage output (both clipped to 16 bits).
+// Table layout per N: fwd[m][k] = (M[k][2m], M[k][2m+1]) (y = M x), then
+// inv[m][n] = (M[2m][n], M[2m+1][n]) (x = M^T y); tables for N = 4, 8, 16,
+// 32 follow each other.
 // ---------------------------------------------------------------------------
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 
@@ -107,47 +113,42 @@ __host__ __device__ constexpr uint32_t cpair(int lo, int hi) {
   return ((uint32_t)lo & 0xffffu) | (((uint32_t)hi & 0xffffu) << 16);
 }
 
-template <int N>
-struct PairTables {
-  uint32_t fwd[N / 2][N];  // fwd[m][k] = (M[k][2m], M[k][2m+1]): y = M x
-  uint32_t inv[N / 2][N];  // inv[m][n] = (M[2m][n], M[2m+1][n]): x = M^T y
+__host__ __device__ constexpr int coef_offset(int N) {
+  return N == 4 ? 0 : (N == 8 ? 2 * 4 * 2 : (N == 16 ? 2 * 4 * 2 + 2 * 8 * 4 : 2 * 4 * 2 + 2 * 8 * 4 + 2 * 16 * 8));
+}
+constexpr int kCoefWords = coef_offset(32) + 2 * 32 * 16;
+
+struct CoefTables {
+  uint32_t w[kCoefWords];
 };
 
-template <int N>
-constexpr PairTables<N> make_pair_tables() {
-  PairTables<N> t{};
-  for (int m = 0; m < N / 2; m++)
-    for (int k = 0; k < N; k++) {
-      t.fwd[m][k] = cpair(dct_coef(N, k, 2 * m), dct_coef(N, k, 2 * m + 1));
-      t.inv[m][k] = cpair(dct_coef(N, 2 * m, k), dct_coef(N, 2 * m + 1, k));
-    }
+constexpr CoefTables make_coef_tables() {
+  CoefTables t{};
+  for (int N = 4; N <= 32; N *= 2) {
+    uint32_t* f = t.w + coef_offset(N);
+    uint32_t* v = f + (N / 2) * N;
+    for (int m = 0; m < N / 2; m++)
+      for (int k = 0; k < N; k++) {
+        f[m * N + k] = cpair(dct_coef(N, k, 2 * m), dct_coef(N, k, 2 * m + 1));
+        v[m * N + k] = cpair(dct_coef(N, 2 * m, k), dct_coef(N, 2 * m + 1, k));
+      }
+  }
   return t;
 }
 
-__constant__ PairTables<4> kPairs4 = make_pair_tables<4>();
-__constant__ PairTables<8> kPairs8 = make_pair_tables<8>();
-__constant__ PairTables<16> kPairs16 = make_pair_tables<16>();
-__constant__ PairTables<32> kPairs32 = make_pair_tables<32>();
-
-template <int N>
-__device__ inline const PairTables<N>& pairs() {
-  if constexpr (N == 4) return kPairs4;
-  else if constexpr (N == 8) return kPairs8;
-  else if constexpr (N == 16) return kPairs16;
-  else return kPairs32;
-}
+__constant__ CoefTables kCoef = make_coef_tables();
 
 // acc[k] = sum_m dot2(table[m][k], src[m]); src: N/2 packed pairs in LDS.
-template <int N, bool FWD>
-__device__ inline void mat_pairs(const uint32_t* src, int (&acc)[N]) {
-  const PairTables<N>& tb = pairs<N>();
+template <int N>
+__device__ inline void mat_pairs(const uint32_t* __restrict__ tb, const uint32_t* src, int (&acc)[N]) {
 #pragma unroll
   for (int k = 0; k < N; k++) acc[k] = 0;
-#pragma unroll 1
+  constexpr int kUnrollM = N <= 8 ? N / 2 : 4;
+#pragma unroll kUnrollM
   for (int m = 0; m < N / 2; m++) {
     const uint32_t x = src[m];
 #pragma unroll
-    for (int k = 0; k < N; k++) acc[k] = dot2(FWD ? tb.fwd[m][k] : tb.inv[m][k], x, acc[k]);
+    for (int k = 0; k < N; k++) acc[k] = dot2(tb[m * N + k], x, acc[k]);
   }
 }
 
@@ -158,77 +159,22 @@ __device__ inline uint32_t sub_pairs(uint32_t a, uint32_t b) {
   return ((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16);
 }
 
-// Packed u16 row (N samples) between global memory and LDS.
+// Packed u16 row (N samples) from global memory.
 template <int N>
-__device__ inline void copy_row(const uint16_t* g, uint16_t* l) {
+__device__ inline void load_row_packed(const uint16_t* p, uint32_t (&v)[N / 2]) {
   if constexpr (N >= 8) {
 #pragma unroll
-    for (int q = 0; q < N / 8; q++) ((uint4*)l)[q] = ((const uint4*)g)[q];
-  } else {
-    *(uint2*)l = *(const uint2*)g;
-  }
-}
-
-// Prediction row into LDS: I -> 2^(B-1); P -> the reference displaced by
-// (dx, dy).  A coded vector keeps the displaced block inside the padded
-// picture; the clamp only guarantees in-bounds reads for a corrupt vector.
-template <int N>
-__device__ inline void pred_row(const FrameJob& job, int c, int y, int x0, int dx, int dy,
-                                uint16_t* dst) {
-  uint32_t* d32 = (uint32_t*)dst;
-  if (job.intra) {
-    const uint32_t h = 1u << (job.bit_depth - 1);
-#pragma unroll
-    for (int j = 0; j < N / 2; j++) d32[j] = h | (h << 16);
-  } else {
-    const int yb = y - (y % N);
-    const int ry = min(max(yb + dy, 0), job.Hp - N) + (y - yb);
-    const int rx = min(max(x0 + dx, 0), job.Wp - N);
-    const uint16_t* rp = job.ref + (size_t)c * job.Hp * job.Wp + (size_t)ry * job.Wp + rx;
-    if ((rx & 1) == 0) {
-      const uint32_t* r32 = (const uint32_t*)rp;
-#pragma unroll
-      for (int j = 0; j < N / 2; j++) d32[j] = r32[j];
-    } else {
-#pragma unroll
-      for (int j = 0; j < N / 2; j++) d32[j] = (uint32_t)rp[2 * j] | ((uint32_t)rp[2 * j + 1] << 16);
+    for (int q = 0; q < N / 8; q++) {
+      const uint4 w = ((const uint4*)p)[q];
+      v[4 * q + 0] = w.x;
+      v[4 * q + 1] = w.y;
+      v[4 * q + 2] = w.z;
+      v[4 * q + 3] = w.w;
     }
-  }
-}
-
-// Dequantisation d = clip16((level * IQ[qP%6] * 16 * 2^(qP/6) + 2^(bd-1)) >> bd).
-__device__ inline int dequant(int lv, long long scale, int bd) {
-  return clip16(((long long)lv * scale + (1ll << (bd - 1))) >> bd);
-}
-
-// Inverse column stage of block column k from the dequantised column stored
-// (as pairs) in the thread's own TD row: E[y][k] = clip16((sum_l M[l][y] d[l] + 64) >> 7).
-template <int N>
-__device__ inline void inverse_column(const int16_t* drow, int16_t (*E)[Tile<N>::P], int k) {
-  int acc[N];
-  mat_pairs<N, false>((const uint32_t*)drow, acc);
-#pragma unroll
-  for (int y = 0; y < N; y++) E[y][k] = (int16_t)clip16(((long long)acc[y] + 64) >> 7);
-}
-
-// Inverse row stage and reconstruction of block row r into packed pairs.
-template <int N>
-__device__ inline void inverse_row(const int16_t* Erow, const uint16_t* pred, int B,
-                                   uint32_t (&rp)[N / 2]) {
-  const int sh = 20 - B;
-  const int rnd = 1 << (19 - B);
-  const int Lmax = (1 << B) - 1;
-  int acc[N];
-  mat_pairs<N, false>((const uint32_t*)Erow, acc);
-  const uint32_t* p32 = (const uint32_t*)pred;
-#pragma unroll
-  for (int j = 0; j < N / 2; j++) {
-    const uint32_t pp = p32[j];
-    int v0 = (int)(pp & 0xffffu) + ((acc[2 * j] + rnd) >> sh);
-    int v1 = (int)(pp >> 16) + ((acc[2 * j + 1] + rnd) >> sh);
-    v0 = v0 < 0 ? 0 : (v0 > Lmax ? Lmax : v0);
-    v1 = v1 < 0 ? 0 : (v1 > Lmax ? Lmax : v1);
-    rp[j] = (uint32_t)v0 | ((uint32_t)v1 << 16);
+  } else {
+    const uint2 w = *(const uint2*)p;
+    v[0] = w.x;
+    v[1] = w.y;
   }
 }
 
@@ -243,22 +189,82 @@ __device__ inline void store_row_packed(uint16_t* p, const uint32_t (&v)[N / 2])
   }
 }
 
-// Rate proxy of every block of channel c in the tile (one wave per channel).
+// Prediction row as packed pairs: I -> 2^(B-1); P -> the reference displaced
+// by (dx, dy).  A coded vector keeps the displaced block inside the padded
+// picture; the clamp only guarantees in-bounds reads for a corrupt vector.
 template <int N>
-__device__ inline unsigned long long block_bits(Lds<N>& s, const FrameJob& job,
-                                                const TileCoord& tc, int c) {
+__device__ inline void pred_row(const FrameJob& job, int c, int y, int x0, int dx, int dy,
+                                uint32_t (&pp)[N / 2]) {
+  if (job.intra) {
+    const uint32_t h = 1u << (job.bit_depth - 1);
+#pragma unroll
+    for (int j = 0; j < N / 2; j++) pp[j] = h | (h << 16);
+  } else {
+    const int yb = y - (y % N);
+    const int ry = min(max(yb + dy, 0), job.Hp - N) + (y - yb);
+    const int rx = min(max(x0 + dx, 0), job.Wp - N);
+    const uint16_t* rp = job.ref + (size_t)c * job.Hp * job.Wp + (size_t)ry * job.Wp + rx;
+    if ((rx & 1) == 0) {
+      const uint32_t* r32 = (const uint32_t*)rp;
+#pragma unroll
+      for (int j = 0; j < N / 2; j++) pp[j] = r32[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < N / 2; j++) pp[j] = (uint32_t)rp[2 * j] | ((uint32_t)rp[2 * j + 1] << 16);
+    }
+  }
+}
+
+// Dequantisation d = clip16((level * IQ[qP%6] * 16 * 2^(qP/6) + 2^(bd-1)) >> bd).
+__device__ inline int dequant(int lv, long long scale, int bd) {
+  return clip16(((long long)lv * scale + (1ll << (bd - 1))) >> bd);
+}
+
+// Inverse column stage of block column k from the dequantised column stored
+// (as pairs) in the thread's own TD row: E[y][k] = clip16((sum_l M[l][y] d[l] + 64) >> 7).
+template <int N>
+__device__ inline void inverse_column(const uint32_t* inv, const uint32_t* drow,
+                                      int16_t (*E)[Tile<N>::P], int k) {
+  int acc[N];
+  mat_pairs<N>(inv, drow, acc);
+#pragma unroll
+  for (int y = 0; y < N; y++) E[y][k] = (int16_t)clip16(((long long)acc[y] + 64) >> 7);
+}
+
+// Inverse row stage and reconstruction of block row r into packed pairs.
+template <int N>
+__device__ inline void inverse_row(const uint32_t* inv, const int16_t* Erow,
+                                   const uint32_t (&pp)[N / 2], int B, uint32_t (&rp)[N / 2]) {
+  const int sh = 20 - B;
+  const int rnd = 1 << (19 - B);
+  const int Lmax = (1 << B) - 1;
+  int acc[N];
+  mat_pairs<N>(inv, (const uint32_t*)Erow, acc);
+#pragma unroll
+  for (int j = 0; j < N / 2; j++) {
+    int v0 = (int)(pp[j] & 0xffffu) + ((acc[2 * j] + rnd) >> sh);
+    int v1 = (int)(pp[j] >> 16) + ((acc[2 * j + 1] + rnd) >> sh);
+    v0 = v0 < 0 ? 0 : (v0 > Lmax ? Lmax : v0);
+    v1 = v1 < 0 ? 0 : (v1 > Lmax ? Lmax : v1);
+    rp[j] = (uint32_t)v0 | ((uint32_t)v1 << 16);
+  }
+}
+
+// Rate proxy of every block of channel c in the tile (one wave per channel):
+// each nonzero level adds ue(run) + se(level) to its block's LDS counter.
+template <int N>
+__device__ inline void block_bits(Lds<N>& s, const TileCoord& tc, int c) {
   constexpr int NBW = Tile<N>::NBW;
   constexpr int S = N * N < 64 ? N * N : 64;  // lanes per block segment
   constexpr int BPC = 64 / S;                  // blocks per pass
   constexpr int CPB = (N * N) / S;             // chunks per block
   const int lane = threadIdx.x & 63;
   const int seg = lane / S, pin = lane - seg * S;
-  unsigned long long total = 0;
   for (int bb = 0; bb < NBW; bb += BPC) {
     const int b = bb + seg;
     const bool vb = (tc.bx0 + b) < tc.Wb;
     int last = -1;
-    int acc = 0, nnz = 0;
+    uint32_t acc = 0;
 #pragma unroll
     for (int ci = 0; ci < CPB; ci++) {
       const int p = ci * S + pin;
@@ -267,25 +273,12 @@ __device__ inline unsigned long long block_bits(Lds<N>& s, const FrameJob& job,
       const unsigned long long segm = (S == 64) ? m : ((m >> (seg * S)) & ((1ull << S) - 1));
       const unsigned long long below = segm & ((1ull << pin) - 1);
       const int prev = below ? ci * S + 63 - __clzll((long long)below) : last;
-      if (lv != 0) acc += ue_len((uint32_t)(p - prev - 1)) + se_len(lv);
-      nnz += __popcll(segm);
+      if (lv != 0) acc += (uint32_t)(ue_len((uint32_t)(p - prev - 1)) + se_len(lv));
       if (segm) last = ci * S + 63 - __clzll((long long)segm);
+      if (pin == 0 && segm) atomicAdd(&s.nnz[c][b], (uint32_t)__popcll(segm));
     }
-#pragma unroll
-    for (int off = S / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    const uint32_t bits = 1u + (nnz > 0 ? (uint32_t)(ue_len((uint32_t)(nnz - 1)) + acc) : 0u);
-    if (pin == 0 && vb) {
-      job.cbits[((size_t)c * tc.Hb + tc.by) * tc.Wb + tc.bx0 + b] = bits;
-      total += bits;
-    }
+    if (acc) atomicAdd(&s.cbits[c][b], acc);
   }
-  return total;
-}
-
-__device__ inline unsigned long long wave_sum(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
 }
 
 template <int N>
@@ -296,6 +289,8 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
   TileCoord tc;
   if (!locate<N>(jr, tc)) return;
   const FrameJob& job = *tc.job;
+  const uint32_t* __restrict__ fwd = jr.coef + coef_offset(N);
+  const uint32_t* __restrict__ inv = fwd + (N / 2) * N;
   build_scan<N>(s.scan);
 
   const int t = threadIdx.x;
@@ -309,6 +304,12 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
   const size_t plane = (size_t)job.Hp * job.Wp;
   const int x0 = bx * N;
   const int y = tc.by * N + r;
+  if (t < 3) s.sse[t] = 0ull;
+  if (t < 3 * NBW) {
+    s.cbits[t / NBW][t % NBW] = 0u;
+    s.nnz[t / NBW][t % NBW] = 0u;
+  }
+  if (t == 0) s.mvbits = 0u;
 
   int dx = 0, dy = 0;
   if (vb && !job.intra) {
@@ -318,22 +319,16 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
   }
 
   // Forward row stage of row r: T[y][k] = (sum_x M[k][x] res[x] + 2^(s1-1)) >> s1,
-  // stored transposed.
+  // stored transposed.  The residual row is parked in E row r for the loop.
+  uint32_t cp[N / 2], pp[N / 2];
   if (vb) {
-    copy_row<N>(job.cur + c * plane + (size_t)y * job.Wp + x0, s.CUR[c][b][r]);
-    pred_row<N>(job, c, y, x0, dx, dy, s.PRED[c][b][r]);
-    const uint32_t* c32 = (const uint32_t*)s.CUR[c][b][r];
-    const uint32_t* p32 = (const uint32_t*)s.PRED[c][b][r];
-    const PairTables<N>& tb = pairs<N>();
+    load_row_packed<N>(job.cur + c * plane + (size_t)y * job.Wp + x0, cp);
+    pred_row<N>(job, c, y, x0, dx, dy, pp);
+    uint32_t* er = (uint32_t*)s.E[c][b][r];
+#pragma unroll
+    for (int m = 0; m < N / 2; m++) er[m] = sub_pairs(cp[m], pp[m]);
     int acc[N];
-#pragma unroll
-    for (int k = 0; k < N; k++) acc[k] = 0;
-#pragma unroll 1
-    for (int m = 0; m < N / 2; m++) {
-      const uint32_t xr = sub_pairs(c32[m], p32[m]);
-#pragma unroll
-      for (int k = 0; k < N; k++) acc[k] = dot2(tb.fwd[m][k], xr, acc[k]);
-    }
+    mat_pairs<N>(fwd, er, acc);
     const int s1 = L2N + B - 9;
     const int rnd1 = 1 << (s1 - 1);
 #pragma unroll
@@ -351,9 +346,11 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
     const uint32_t qf = (uint32_t)kQf[qP % 6];
     const long long scale = (long long)kIQ[qP % 6] * 16ll << (qP / 6);
     const int bd = B + L2N - 5;
-    int16_t* row = s.TD[c][b][k];
+    // the row is only accessed as packed 32-bit pairs (no mixed-width aliasing)
+    uint32_t* row = (uint32_t*)s.TD[c][b][k];
     int acc[N];
-    mat_pairs<N, true>((const uint32_t*)row, acc);
+    mat_pairs<N>(fwd, row, acc);
+    int dq[N];
 #pragma unroll
     for (int l = 0; l < N; l++) {
       const int C = (acc[l] + (1 << (L2N + 5))) >> (L2N + 6);
@@ -362,9 +359,12 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
       mq = mq > 32767u ? 32767u : mq;
       const int lv = C < 0 ? -(int)mq : (int)mq;
       s.L[c][b][l * N + k] = (int16_t)lv;
-      row[l] = (int16_t)dequant(lv, scale, bd);
+      dq[l] = dequant(lv, scale, bd);
     }
-    inverse_column<N>(row, s.E[c][b], k);
+#pragma unroll
+    for (int m = 0; m < N / 2; m++)
+      row[m] = ((uint32_t)dq[2 * m] & 0xffffu) | ((uint32_t)dq[2 * m + 1] << 16);
+    inverse_column<N>(inv, row, s.E[c][b], k);
   }
   __syncthreads();
 
@@ -381,32 +381,28 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
   }
 
   // Inverse row stage, reconstruction, squared error.
-  unsigned long long sse = 0;
   if (vb) {
     uint32_t rp[N / 2];
-    inverse_row<N>(s.E[c][b][r], s.PRED[c][b][r], B, rp);
+    inverse_row<N>(inv, s.E[c][b][r], pp, B, rp);
     store_row_packed<N>(job.rec + c * plane + (size_t)y * job.Wp + x0, rp);
     if (c < job.nch && y < job.H) {
       const bool usemask = job.vmask != nullptr && *job.nan_total != 0u;
       const uint8_t* vm = usemask ? job.vmask + c * plane + (size_t)y * job.Wp + x0 : nullptr;
-      const uint32_t* c32 = (const uint32_t*)s.CUR[c][b][r];
+      unsigned long long sse = 0;
 #pragma unroll
       for (int j = 0; j < N; j++) {
-        const int cv = (int)((c32[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        const int cv = (int)((cp[j >> 1] >> (16 * (j & 1))) & 0xffffu);
         const int rv = (int)((rp[j >> 1] >> (16 * (j & 1))) & 0xffffu);
         const bool ok = (x0 + j < job.W) && (!usemask || vm[j]);
         const int e = cv - rv;
         sse += ok ? (unsigned long long)(e * e) : 0ull;
       }
+      if (sse) atomicAdd(&s.sse[c], sse);
     }
   }
-  sse = wave_sum(sse);
-  if ((t & 63) == 0 && c < job.nch && sse) atomicAdd(&job.sse[c], sse);
 
   // Rate proxy per block and channel; vector bits.
-  unsigned long long cb_total = block_bits<N>(s, job, tc, c);
-  cb_total = wave_sum(cb_total);
-  unsigned long long mvb = 0;
+  block_bits<N>(s, tc, c);
   if (c == 0 && r == 0 && vb) {
     int8_t* mv = job.mv + ((size_t)tc.by * tc.Wb + bx) * 2;
     uint32_t bits = 0;
@@ -422,13 +418,27 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
       bits = (uint32_t)(se_len(dx - pmx) + se_len(dy - pmy));
     }
     job.mbits[(size_t)tc.by * tc.Wb + bx] = bits;
-    mvb = bits;
+    if (bits) atomicAdd(&s.mvbits, bits);
   }
-  if (c == 0) mvb = wave_sum(mvb);
-  if ((t & 63) == 0) {
-    if (cb_total) atomicAdd(&job.bits[0], cb_total);
-    if (c == 0 && mvb) atomicAdd(&job.bits[1], mvb);
+  __syncthreads();
+  if (t < 3 * NBW) {
+    const int cc = t / NBW, bb = t - cc * NBW;
+    if (tc.bx0 + bb < tc.Wb) {
+      const uint32_t nnz = s.nnz[cc][bb];
+      const uint32_t bits = 1u + (nnz > 0 ? (uint32_t)ue_len(nnz - 1) + s.cbits[cc][bb] : 0u);
+      job.cbits[((size_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb] = bits;
+      s.cbits[cc][bb] = bits;  // per-block total, summed below by thread 0
+    }
   }
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long cb = 0;
+    for (int i = 0; i < 3 * NBW; i++)
+      if (tc.bx0 + (i % NBW) < tc.Wb) cb += s.cbits[i / NBW][i % NBW];
+    atomicAdd(&job.bits[0], cb);
+    if (s.mvbits) atomicAdd(&job.bits[1], (unsigned long long)s.mvbits);
+  }
+  if (t < job.nch && s.sse[t]) atomicAdd(&job.sse[t], s.sse[t]);
 }
 
 template <int N>
@@ -439,6 +449,7 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
   TileCoord tc;
   if (!locate<N>(jr, tc)) return;
   const FrameJob& job = *tc.job;
+  const uint32_t* __restrict__ inv = jr.coef + coef_offset(N) + (N / 2) * N;
   const int t = threadIdx.x;
   const int c = t >> 6;
   const int rem = t & 63;
@@ -462,6 +473,7 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
       ((uint4*)s.L[cc][bb])[q] = ((const uint4*)src)[q];
     }
   }
+  uint32_t pp[N / 2];
   if (vb) {
     int dx = 0, dy = 0;
     if (!job.intra) {
@@ -469,7 +481,7 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
       dx = mv[0];
       dy = mv[1];
     }
-    pred_row<N>(job, c, y, x0, dx, dy, s.PRED[c][b][r]);
+    pred_row<N>(job, c, y, x0, dx, dy, pp);
   }
   __syncthreads();
   if (vb) {
@@ -477,27 +489,46 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
     const int qP = job.qp + 6 * (B - 8);
     const long long scale = (long long)kIQ[qP % 6] * 16ll << (qP / 6);
     const int bd = B + L2N - 5;
-    int16_t* row = s.TD[c][b][k];
+    uint32_t* row = (uint32_t*)s.TD[c][b][k];
 #pragma unroll
-    for (int l = 0; l < N; l++) row[l] = (int16_t)dequant(s.L[c][b][l * N + k], scale, bd);
-    inverse_column<N>(row, s.E[c][b], k);
+    for (int m = 0; m < N / 2; m++) {
+      const int d0 = dequant(s.L[c][b][(2 * m) * N + k], scale, bd);
+      const int d1 = dequant(s.L[c][b][(2 * m + 1) * N + k], scale, bd);
+      row[m] = ((uint32_t)d0 & 0xffffu) | ((uint32_t)d1 << 16);
+    }
+    inverse_column<N>(inv, row, s.E[c][b], k);
   }
   __syncthreads();
   if (vb) {
     uint32_t rp[N / 2];
-    inverse_row<N>(s.E[c][b][r], s.PRED[c][b][r], B, rp);
+    inverse_row<N>(inv, s.E[c][b][r], pp, B, rp);
     store_row_packed<N>(job.rec + c * plane + (size_t)y * job.Wp + x0, rp);
   }
 }
 
+const uint32_t* coef_tables() {
+  static const uint32_t* ptr = nullptr;
+  if (!ptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(kCoef)) == hipSuccess) ptr = (const uint32_t*)p;
+  }
+  return ptr;
+}
+
 template <int N>
 hipError_t launch_encode_t(const LaunchDesc& r, hipStream_t s) {
-  encode_kernel<N><<<r.tiles, 192, 0, s>>>(r);
+  LaunchDesc d = r;
+  d.coef = coef_tables();
+  if (!d.coef) return hipErrorInvalidSymbol;
+  encode_kernel<N><<<d.tiles, 192, 0, s>>>(d);
   return hipGetLastError();
 }
 template <int N>
 hipError_t launch_decode_t(const LaunchDesc& r, hipStream_t s) {
-  decode_kernel<N><<<r.tiles, 192, 0, s>>>(r);
+  LaunchDesc d = r;
+  d.coef = coef_tables();
+  if (!d.coef) return hipErrorInvalidSymbol;
+  decode_kernel<N><<<d.tiles, 192, 0, s>>>(d);
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -39,11 +40,18 @@ struct xv_encoded {
   uint32_t* maxkey;
   uint32_t* nan_count;
   uint32_t* nan_total;
+  // metric span, contiguous (one copy to the host): mn, mx, phys [bands]
+  // doubles; nvalid [bands], sse [3G], bits [2G] u64
+  void* span;
+  size_t span_bytes;
   double* mn;
   double* mx;
+  double* phys;
   unsigned long long* nvalid;
   unsigned long long* sse;   // [3G]
   unsigned long long* bits;  // [2G]
+  double* phys_partial;      // [phys_blocks][bands]
+  int phys_nb;
   FrameJob* jobs;
 };
 
@@ -130,14 +138,22 @@ struct ProfScope {
 };
 
 // ---- motion-search geometry table -----------------------------------------
+// Explicit geometries (xv_set_me_geometry) per (N, R); otherwise the model
+// default for the class's widest frame in blocks, cached per (N, R, Wb).
 std::mutex g_geom_mu;
 std::map<std::pair<int, int>, MeGeom> g_geom;
+std::map<std::tuple<int, int, int>, MeGeom> g_geom_default;
 
-MeGeom geometry_for(int N, int R) {
+MeGeom geometry_for(int N, int R, int Wb = 16) {
   std::lock_guard<std::mutex> lk(g_geom_mu);
   auto it = g_geom.find({N, R});
   if (it != g_geom.end()) return it->second;
-  return me_default_geometry(N, R);
+  const int wb = std::max(1, std::min(16, Wb));
+  auto d = g_geom_default.find({N, R, wb});
+  if (d != g_geom_default.end()) return d->second;
+  MeGeom g = me_default_geometry(N, R, wb);
+  g_geom_default[{N, R, wb}] = g;
+  return g;
 }
 
 // ---- validation -----------------------------------------------------------
@@ -148,8 +164,9 @@ int check_cube(const xv_cube* c, const char* name) {
   if (c->T < 1 || c->H < 1 || c->W < 1 || c->bands < 1)
     return fail(XV_EINVAL, "%s: shape must be positive", name);
   if (c->bands > XV_MAX_BANDS) return fail(XV_EINVAL, "%s: more than %d bands", name, XV_MAX_BANDS);
-  if (c->H > 65536 || c->W > 65536 || c->T > (1 << 24))
-    return fail(XV_EINVAL, "%s: dimension too large", name);
+  if (c->H > 65536 || c->W > 65536 || c->T > (1 << 24) ||
+      (double)c->T * (double)c->H * (double)c->W >= 4294967296.0)
+    return fail(XV_EINVAL, "%s: dimension too large (T*H*W must be below 2^32)", name);
   const size_t el = c->dtype == XV_U16 ? 2 : 4;
   if (((uintptr_t)c->data) % el) return fail(XV_EINVAL, "%s: misaligned data pointer", name);
   return XV_OK;
@@ -206,11 +223,10 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   size_t o_cb = k.take<uint32_t>((size_t)nblk * 3);
   size_t o_mb = k.take<uint32_t>((size_t)nblk);
   size_t o_keys = k.take<uint32_t>((size_t)3 * bands + 1);
-  size_t o_mn = k.take<double>((size_t)bands);
-  size_t o_mx = k.take<double>((size_t)bands);
-  size_t o_nv = k.take<unsigned long long>((size_t)bands);
-  size_t o_sse = k.take<unsigned long long>((size_t)3 * G);
-  size_t o_bits = k.take<unsigned long long>((size_t)2 * G);
+  const size_t span_words = (size_t)3 * bands + bands + 3 * G + 2 * G;
+  size_t o_span = k.take<uint64_t>(span_words);
+  e->phys_nb = phys_blocks(T * e->H * e->W * bands);
+  size_t o_pp = k.take<double>((size_t)e->phys_nb * bands);
   size_t o_jobs = k.take<FrameJob>((size_t)e->njobs);
   Carve w;
   size_t o_fr = w.take<uint16_t>((size_t)nframes * 3 * plane);
@@ -239,11 +255,15 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   e->maxkey = e->minkey + bands;
   e->nan_count = e->maxkey + bands;
   e->nan_total = e->nan_count + bands;
-  e->mn = (double*)(kb + o_mn);
-  e->mx = (double*)(kb + o_mx);
-  e->nvalid = (unsigned long long*)(kb + o_nv);
-  e->sse = (unsigned long long*)(kb + o_sse);
-  e->bits = (unsigned long long*)(kb + o_bits);
+  e->span = kb + o_span;
+  e->span_bytes = span_words * 8;
+  e->mn = (double*)e->span;
+  e->mx = e->mn + bands;
+  e->phys = e->mx + bands;
+  e->nvalid = (unsigned long long*)(e->phys + bands);
+  e->sse = e->nvalid + bands;
+  e->bits = e->sse + 3 * G;
+  e->phys_partial = (double*)(kb + o_pp);
   e->jobs = (FrameJob*)(kb + o_jobs);
   e->frames = (uint16_t*)(wb + o_fr);
   e->recon = (uint16_t*)(wb + o_rc);
@@ -263,7 +283,7 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   {
     PackArgs a{in->data, in->dtype, T, e->H, e->W, (int32_t)bands, e->G, e->Hp, e->Wp,
                p->bit_depth, p->pad_mode, p->fill_mode, e->mn, e->mx, e->nan_total,
-               e->frames, e->vmask};
+               e->nan_count, e->frames, e->vmask};
     ProfScope ps(XV_K_PACK, s, in_bytes + (double)nframes * 3 * plane * 2.0);
     XV_HIP(launch_pack(a, s), "pack kernel");
   }
@@ -299,7 +319,7 @@ struct SegSrc {
 
 // One launch per chunk of up to kMaxSeg segments.
 template <class F>
-int launch_segments(const std::vector<SegSrc>& src, int tpj_kind, F launch) {
+int launch_segments(const std::vector<SegSrc>& src, int tpj_kind, const MeGeom& geom, F launch) {
   size_t i = 0;
   while (i < src.size()) {
     LaunchDesc d;
@@ -311,7 +331,7 @@ int launch_segments(const std::vector<SegSrc>& src, int tpj_kind, F launch) {
       const int s = src[i].step;
       const int n = plan_jobs_at((int)e->T, e->G, e->p.gop, s);
       int tpj = tpj_kind == 0 ? xf_tiles_per_job(e->N, e->Hb, e->Wb)
-                              : me_tiles_per_job(e->Hb, e->Wb, geometry_for(e->N, e->p.search_range));
+                              : me_tiles_per_job(e->Hb, e->Wb, geom);
       Seg& g = d.seg[d.nseg++];
       g.jobs = e->jobs + plan_step_offset((int)e->T, e->G, e->p.gop, s);
       g.count = n;
@@ -331,7 +351,9 @@ int launch_segments(const std::vector<SegSrc>& src, int tpj_kind, F launch) {
 int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s) {
   if (es.empty()) return XV_OK;
   const int N = es[0]->N, R = es[0]->p.search_range;
-  const MeGeom geom = geometry_for(N, R);
+  int max_wb = 1;
+  for (auto* e : es) max_wb = std::max(max_wb, e->Wb);
+  const MeGeom geom = geometry_for(N, R, max_wb);
   int maxsteps = 0;
   for (auto* e : es) maxsteps = std::max(maxsteps, e->nsteps);
   for (int st = 0; st < maxsteps; st++) {
@@ -339,14 +361,14 @@ int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s) {
     for (auto* e : es)
       if (st < e->nsteps) src.push_back(SegSrc{e, st});
     if (st > 0) {
-      int rc = launch_segments(src, 1, [&](const LaunchDesc& d, double work) {
+      int rc = launch_segments(src, 1, geom, [&](const LaunchDesc& d, double work) {
         ProfScope ps(XV_K_ME, s, work);
         XV_HIP(launch_me(N, R, geom, d, s), "motion search kernel");
         return XV_OK;
       });
       if (rc != XV_OK) return rc;
     }
-    int rc = launch_segments(src, 0, [&](const LaunchDesc& d, double work) {
+    int rc = launch_segments(src, 0, geom, [&](const LaunchDesc& d, double work) {
       ProfScope ps(XV_K_ENCODE, s, work * 8.0);  // cur + pred in, level + recon out
       XV_HIP(launch_encode(N, d, s), "transform kernel");
       return XV_OK;
@@ -582,8 +604,7 @@ int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m, void*
   if (!e || !m) return fail(XV_EINVAL, "null encoded cube or metrics");
   hipStream_t s = (hipStream_t)hip_stream;
   const int bands = (int)e->bands, G = e->G;
-  double* dphys = nullptr;
-  void* pmem = nullptr;
+  bool have_phys = false;
   if (orig) {
     int rc = check_cube(orig, "original");
     if (rc != XV_OK) return rc;
@@ -591,33 +612,24 @@ int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m, void*
         orig->dtype != e->src_dtype)
       return fail(XV_EINVAL, "original cube differs from the encoded one");
     if (e->recon) {
-      const int nb = phys_blocks(e->T * e->H * e->W * bands);
-      init_pool();
-      XV_HIP(hipMallocAsync(&pmem, (size_t)(nb + 1) * bands * sizeof(double), s),
-             "device allocation of metric partials");
-      dphys = (double*)pmem + (size_t)nb * bands;
       PhysArgs a{orig->data, orig->dtype, e->recon, e->T, e->H, e->W, bands, e->Hp, e->Wp,
-                 e->p.bit_depth, e->mn, e->mx, (double*)pmem, dphys, nb};
+                 e->p.bit_depth, e->mn, e->mx, e->phys_partial, e->phys, e->phys_nb};
       const double ib = orig->dtype == XV_U16 ? 2.0 : 4.0;
       ProfScope ps(XV_K_METRICS, s, (double)e->T * e->H * e->W * bands * (ib + 2.0));
-      hipError_t he = launch_phys_sse(a, s);
-      if (he != hipSuccess) {
-        (void)hipFreeAsync(pmem, s);
-        return hip_fail(he, "physical error kernel");
-      }
+      XV_HIP(launch_phys_sse(a, s), "physical error kernel");
+      have_phys = true;
     }
   }
-  std::vector<unsigned long long> sse(3 * G), nv(bands), bits(2 * G);
-  std::vector<double> mn(bands), mx(bands), phys(bands, NAN);
-  XV_HIP(hipMemcpyAsync(sse.data(), e->sse, sse.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
-  XV_HIP(hipMemcpyAsync(nv.data(), e->nvalid, nv.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
-  XV_HIP(hipMemcpyAsync(bits.data(), e->bits, bits.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
-  XV_HIP(hipMemcpyAsync(mn.data(), e->mn, mn.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
-  XV_HIP(hipMemcpyAsync(mx.data(), e->mx, mx.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
-  if (dphys)
-    XV_HIP(hipMemcpyAsync(phys.data(), dphys, phys.size() * 8, hipMemcpyDeviceToHost, s), "copy metrics");
-  if (pmem) (void)hipFreeAsync(pmem, s);
+  std::vector<uint64_t> host(e->span_bytes / 8);
+  XV_HIP(hipMemcpyAsync(host.data(), e->span, e->span_bytes, hipMemcpyDeviceToHost, s), "copy metrics");
   XV_HIP(hipStreamSynchronize(s), "synchronise metrics");
+  const double* mn = (const double*)host.data();
+  const double* mx = mn + bands;
+  const double* phys = mx + bands;
+  const unsigned long long* nv = (const unsigned long long*)(phys + bands);
+  const unsigned long long* sse = nv + bands;
+  const unsigned long long* bits = sse + 3 * G;
+  const bool dphys = have_phys;
 
   memset(m, 0, sizeof *m);
   m->bands = bands;
@@ -637,7 +649,7 @@ int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m, void*
       const double mse = (double)se / (double)nv[b];
       m->psnr[b] = 10.0 * log10(L * L / mse);
     }
-    m->sse_phys[b] = phys[b];
+    m->sse_phys[b] = dphys ? phys[b] : NAN;
     if (!dphys || nv[b] == 0 || !(mx[b] > 0.0)) {
       m->psnr_phys[b] = NAN;
     } else if (phys[b] == 0.0) {
@@ -700,8 +712,12 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
   if (!(block == 4 || block == 8 || block == 16 || block == 32) || search_range < 0 ||
       search_range > 64)
     return fail(XV_EINVAL, "bad block or search range");
-  MeGeom def = me_default_geometry(block, search_range);
-  MeGeom m = def;
+  if (!g || (g->blocks_per_wg == 0 && g->cands_per_lane == 0 && g->threads == 0)) {
+    std::lock_guard<std::mutex> lk(g_geom_mu);
+    g_geom.erase({block, search_range});  // back to the model default
+    return XV_OK;
+  }
+  MeGeom m = me_default_geometry(block, search_range);
   if (g) {
     if (g->blocks_per_wg) m.nb = g->blocks_per_wg;
     if (g->cands_per_lane) m.kx = g->cands_per_lane;

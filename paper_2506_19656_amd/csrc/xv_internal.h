@@ -46,6 +46,7 @@ struct Seg {
 struct LaunchDesc {
   int32_t nseg;
   int32_t tiles;
+  const uint32_t* coef;  // transform coefficient-pair tables (transform kernels)
   Seg seg[kMaxSeg];
 };
 
@@ -169,6 +170,7 @@ struct PackArgs {
   const double* mn;
   const double* mx;
   const uint32_t* nan_total;
+  const uint32_t* nan_count;  // [bands]
   uint16_t* frames;    // [G][T][3][Hp][Wp]
   uint8_t* vmask;      // [G][T][3][Hp][Wp] or null
 };
@@ -184,7 +186,7 @@ struct MeGeom {
   int kx;       // candidates per lane along x (even)
   int threads;  // workgroup size
 };
-MeGeom me_default_geometry(int N, int R);
+MeGeom me_default_geometry(int N, int R, int max_nb = 16);
 size_t me_lds_bytes_for(int N, int R, const MeGeom& g);
 int me_tiles_per_job(int Hb, int Wb, const MeGeom& g);
 hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& d, hipStream_t s);
