@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["both", "batched", "plain"], default="both")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the motion-search geometry tuner (model defaults)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -100,6 +102,19 @@ def main():
               for qp, N in runs]
     outs = [torch.empty_like(cube) for _ in runs]
     pxb_step = wl.px_band * len(runs)
+
+    # launch-geometry tuning (outside the timed region; outputs never depend on it)
+    tuning = {}
+    for N in wl.blocks:
+        if not args.no_tune:
+            print(f"[bench] tuning motion search N={N}", file=sys.stderr, flush=True)
+            t = xv.autotune_me(cube, xv.Params(bit_depth=wl.bit_depth, qp=27, block=N,
+                                               search_range=wl.search_range, gop=wl.gop,
+                                               pad_mode=wl.pad_mode, fill_mode=wl.fill_mode))
+            tuning[f"N{N}"] = dict(t, tuned=True)
+        else:
+            tuning[f"N{N}"] = dict(xv.get_me_geometry(N, wl.search_range, -(-wl.W // N)),
+                                   tuned=False)
 
     def step_plain(lat=None):
         ms = []
@@ -180,6 +195,7 @@ def main():
                                f"N{list(wl.blocks)} (15 runs), R={wl.search_range}, "
                                f"GOP {wl.gop}", "form": main_form,
                    "px_band_per_step": pxb_step},
+        "me_geometry": tuning,
         "p50_ms": round(res[main_form]["p50_ms"], 3),
         "p99_ms": round(res[main_form]["p99_ms"], 3),
         "forms": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}

@@ -23,6 +23,7 @@
 #include "xv_internal.h"
 
 #include <algorithm>
+#include <vector>
 
 namespace xv {
 
@@ -252,51 +253,59 @@ size_t me_lds_bytes_for(int N, int R, const MeGeom& g) {
   return me_lds_bytes(N, me_shape(N, R, g.kx, g.nb), g.nb);
 }
 
-// Default geometry from a simple model of a CU (160 KB LDS, 4 SIMDs with 512
-// VGPRs per lane and at most 8 waves each).  Candidates per lane (KX, even):
-// maximise the share of SAD instructions among the lane's VALU work
-// (KX N/2 SADs against (KX + N)/2 - 1 realignments per row) times the share
-// of useful candidates (2R+1 of G KX).  Blocks per workgroup and workgroup
-// size: maximise lane occupancy of the rounds of items times the resident
-// waves per SIMD (saturating at 3).  The empirical tuner refines this.
-MeGeom me_default_geometry(int N, int R, int max_nb) {
+// Model of a CU (160 KB LDS, 4 SIMDs with 512 VGPRs per lane, at most 8
+// waves each) used to rank geometries.  Score = share of SAD instructions in
+// a lane's VALU work per row (KX N/2 SADs against (KX+N)/2 - 1
+// realignments) x share of useful candidates (2R+1 of G KX) x lane occupancy
+// of the rounds of items x resident waves per SIMD (saturating at 3).
+double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
   const int span = 2 * R + 1;
-  int kx = 2;
-  double best_score = -1.0;
-  for (int k = 2; k <= 18; k += 2) {
-    const int G = (span + k - 1) / k;
-    const double sad = (double)k * N / 2;
-    const double valu = sad + (k + N) / 2 - 1;
-    const double score = sad / valu * (double)span / (double)(G * k);
-    if (score > best_score + 1e-12) { best_score = score; kx = k; }
-  }
+  const int kx = g.kx, c = std::max(1, std::min(g.nb, width_blocks)), th = g.threads;
+  const int G = (span + kx - 1) / kx;
+  const double sad = (double)kx * N / 2;
+  const double eff = sad / (sad + (kx + N) / 2 - 1) * (double)span / (double)(G * kx);
+  const MeShape sh = me_shape(N, R, kx, g.nb);
+  const size_t lds = me_lds_bytes(N, sh, g.nb);
+  if (lds > 160 * 1024) return -1.0;
+  const int items = c * sh.ipb;
+  const int rounds = (items + th - 1) / th;
+  const double lane = (double)items / (double)(rounds * th);
+  const int wpg = th / 64;
   const int vgpr = me_vgprs(N, kx);
   const int waves_by_vgpr = std::max(1, std::min(8, 512 / std::max(1, vgpr)));
-  int nb = 1, threads = 256;
-  double bestf = -1.0;
-  const int cmax = std::max(1, std::min(16, max_nb));
-  for (int c = 1; c <= cmax; c++) {
-    const MeShape sh = me_shape(N, R, kx, c);
-    const size_t lds = me_lds_bytes(N, sh, c);
-    if (lds > 96 * 1024 && c > 1) break;
-    const int items = c * sh.ipb;
-    for (int th = 128; th <= 512; th += 64) {
-      const int rounds = (items + th - 1) / th;
-      const double lane = (double)items / (double)(rounds * th);
-      const int wpg = th / 64;
-      const int wg_lds = (int)((160 * 1024) / std::max<size_t>(1, lds));
-      const int wg_waves = (4 * waves_by_vgpr) / wpg;
-      const int wg = std::max(1, std::min(wg_lds, wg_waves));
-      const double occ = std::min(3.0, (double)(wg * wpg) / 4.0);
-      const double f = lane * occ;
-      if (f > bestf + 1e-9 || (f > bestf - 1e-9 && c > nb)) {
-        bestf = f;
-        nb = c;
-        threads = th;
+  const int wg_lds = (int)((160 * 1024) / std::max<size_t>(1, lds));
+  const int wg_waves = (4 * waves_by_vgpr) / wpg;
+  const int wg = std::max(0, std::min(wg_lds, wg_waves));
+  if (wg == 0) return -1.0;
+  const double occ = std::min(3.0, (double)(wg * wpg) / 4.0);
+  return eff * lane * occ;
+}
+
+std::vector<MeGeom> me_candidates(int N, int R, int width_blocks) {
+  std::vector<MeGeom> v;
+  const int cmax = std::max(1, std::min(16, width_blocks));
+  for (int kx = 2; kx <= 18; kx += 2)
+    for (int c = 1; c <= cmax; c++)
+      for (int th = 64; th <= 512; th += 64) {
+        const MeGeom g{c, kx, th};
+        if (me_lds_bytes(N, me_shape(N, R, kx, c), c) <= 96 * 1024) v.push_back(g);
       }
+  return v;
+}
+
+// Default geometry: the best model score (ties: more blocks per workgroup,
+// fewer redundant window loads).
+MeGeom me_default_geometry(int N, int R, int max_nb) {
+  MeGeom best{1, 2, 256};
+  double bs = -2.0;
+  for (const MeGeom& g : me_candidates(N, R, max_nb)) {
+    const double sc = me_model_score(N, R, g, max_nb);
+    if (sc > bs + 1e-9 || (sc > bs - 1e-9 && g.nb > best.nb)) {
+      bs = sc;
+      best = g;
     }
   }
-  return MeGeom{nb, kx, threads};
+  return best;
 }
 
 int me_tiles_per_job(int Hb, int Wb, const MeGeom& g) {

@@ -734,13 +734,104 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
   return XV_OK;
 }
 
-int xv_get_me_geometry(int block, int search_range, xv_me_geometry* g) {
+int xv_get_me_geometry(int block, int search_range, int width_blocks, xv_me_geometry* g) {
   if (!g) return fail(XV_EINVAL, "null geometry");
-  MeGeom m = geometry_for(block, search_range);
+  if (!(block == 4 || block == 8 || block == 16 || block == 32) || search_range < 0 ||
+      search_range > 64)
+    return fail(XV_EINVAL, "bad block or search range");
+  MeGeom m = geometry_for(block, search_range, width_blocks > 0 ? width_blocks : 16);
   g->blocks_per_wg = m.nb;
   g->cands_per_lane = m.kx;
   g->threads = m.threads;
   g->reserved = 0;
+  return XV_OK;
+}
+
+int xv_autotune_me(const xv_cube* in, const xv_params* p, void* hip_stream, int max_candidates,
+                   xv_me_geometry* out, double* best_ms) {
+  int rc = check_cube(in, "tuning input");
+  if (rc != XV_OK) return rc;
+  if ((rc = check_params(p)) != XV_OK) return rc;
+  if (in->T < 2 || p->gop < 2) return fail(XV_EINVAL, "tuning needs a P picture (T >= 2, gop >= 2)");
+  hipStream_t s = (hipStream_t)hip_stream;
+  xv_params q = *p;
+  q.flags = 0;
+  xv_encoded* e = nullptr;
+  if ((rc = encode_prepare(in, &q, s, &e)) != XV_OK) {
+    if (e) xv_encoded_free(e);
+    return rc;
+  }
+  const int N = e->N, R = q.search_range;
+  // step 0 (I pictures) provides the references of step 1
+  {
+    std::vector<SegSrc> src{SegSrc{e, 0}};
+    const MeGeom g0 = geometry_for(N, R, e->Wb);
+    rc = launch_segments(src, 0, g0, [&](const LaunchDesc& d, double) {
+      XV_HIP(launch_encode(N, d, s), "transform kernel");
+      return XV_OK;
+    });
+    if (rc != XV_OK) {
+      xv_encoded_free(e);
+      return rc;
+    }
+  }
+  std::vector<MeGeom> cand = me_candidates(N, R, e->Wb);
+  std::stable_sort(cand.begin(), cand.end(), [&](const MeGeom& a, const MeGeom& b) {
+    return me_model_score(N, R, a, e->Wb) > me_model_score(N, R, b, e->Wb);
+  });
+  const size_t keep = (size_t)(max_candidates > 0 ? max_candidates : 24);
+  if (cand.size() > keep) cand.resize(keep);
+  const MeGeom def = geometry_for(N, R, e->Wb);
+  if (std::find_if(cand.begin(), cand.end(), [&](const MeGeom& g) {
+        return g.nb == def.nb && g.kx == def.kx && g.threads == def.threads;
+      }) == cand.end())
+    cand.push_back(def);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  (void)hipEventCreate(&ev0);
+  (void)hipEventCreate(&ev1);
+  MeGeom best = def;
+  float best_t = 1e30f;
+  std::vector<SegSrc> src{SegSrc{e, 1}};
+  for (const MeGeom& g : cand) {
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 4 && rc == XV_OK; rep++) {
+      (void)hipEventRecord(ev0, s);
+      rc = launch_segments(src, 1, g, [&](const LaunchDesc& d, double) {
+        XV_HIP(launch_me(N, R, g, d, s), "motion search kernel");
+        return XV_OK;
+      });
+      (void)hipEventRecord(ev1, s);
+      if (rc != XV_OK) break;
+      if (hipEventSynchronize(ev1) != hipSuccess) {
+        rc = fail(XV_EHIP, "tuning event");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev0, ev1);
+      if (rep > 0) tmin = std::min(tmin, ms);  // first run warms caches
+    }
+    if (rc != XV_OK) break;
+    if (tmin < best_t) {
+      best_t = tmin;
+      best = g;
+    }
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  xv_encoded_free(e);
+  if (rc != XV_OK) return rc;
+  XV_HIP(hipStreamSynchronize(s), "synchronise tuning");
+  {
+    std::lock_guard<std::mutex> lk(g_geom_mu);
+    g_geom[{N, R}] = best;
+  }
+  if (out) {
+    out->blocks_per_wg = best.nb;
+    out->cands_per_lane = best.kx;
+    out->threads = best.threads;
+    out->reserved = 0;
+  }
+  if (best_ms) *best_ms = best_t;
   return XV_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "xv.h"
 
 namespace xv {
@@ -187,6 +189,8 @@ struct MeGeom {
   int threads;  // workgroup size
 };
 MeGeom me_default_geometry(int N, int R, int max_nb = 16);
+double me_model_score(int N, int R, const MeGeom& g, int width_blocks);
+std::vector<MeGeom> me_candidates(int N, int R, int width_blocks);
 size_t me_lds_bytes_for(int N, int R, const MeGeom& g);
 int me_tiles_per_job(int Hb, int Wb, const MeGeom& g);
 hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& d, hipStream_t s);

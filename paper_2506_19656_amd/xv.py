@@ -76,7 +76,7 @@ class ProfileC(C.Structure):
 EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube",
             "xv_decode_cube", "xv_psnr_bpppb", "xv_encoded_export", "xv_encoded_free",
             "xv_encode_batch", "xv_decode_batch", "xv_set_me_geometry", "xv_get_me_geometry",
-            "xv_profile_enable", "xv_profile_read"]
+            "xv_autotune_me", "xv_profile_enable", "xv_profile_read"]
 
 _lib = None
 
@@ -104,7 +104,9 @@ def lib():
                                       C.POINTER(vp)]
         L.xv_decode_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(Cube), vp]
         L.xv_set_me_geometry.argtypes = [C.c_int, C.c_int, C.POINTER(MeGeometryC)]
-        L.xv_get_me_geometry.argtypes = [C.c_int, C.c_int, C.POINTER(MeGeometryC)]
+        L.xv_get_me_geometry.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(MeGeometryC)]
+        L.xv_autotune_me.argtypes = [C.POINTER(Cube), C.POINTER(ParamsC), vp, C.c_int,
+                                     C.POINTER(MeGeometryC), C.POINTER(C.c_double)]
         L.xv_profile_enable.argtypes = [C.c_int]
         L.xv_profile_read.argtypes = [C.POINTER(ProfileC)]
         _lib = L
@@ -281,11 +283,24 @@ def set_me_geometry(block: int, search_range: int, blocks_per_wg=0, cands_per_la
     _check(lib().xv_set_me_geometry(block, search_range, C.byref(g)))
 
 
-def get_me_geometry(block: int, search_range: int) -> dict:
+def get_me_geometry(block: int, search_range: int, width_blocks: int = 0) -> dict:
     g = MeGeometryC()
-    _check(lib().xv_get_me_geometry(block, search_range, C.byref(g)))
+    _check(lib().xv_get_me_geometry(block, search_range, width_blocks, C.byref(g)))
     return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
                 threads=g.threads)
+
+
+def autotune_me(cube, params: Params, stream=None, max_candidates: int = 0) -> dict:
+    """xv_autotune_me: time candidate motion-search geometries on the cube's
+    first P step and install the fastest for (block, search_range)."""
+    cb = _cube(cube)
+    pc = params.c()
+    g = MeGeometryC()
+    ms = C.c_double()
+    _check(lib().xv_autotune_me(C.byref(cb), C.byref(pc), _stream_handle(stream), max_candidates,
+                                C.byref(g), C.byref(ms)))
+    return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
+                threads=g.threads, kernel_ms=ms.value)
 
 
 def profile_enable(on: bool = True):
