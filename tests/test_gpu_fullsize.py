@@ -1,0 +1,163 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (tuned motion-search geometry, batched multi-run encode).
+
+The oracle cannot code a 6-9 GB cube in test time, so it computes sampled
+outputs one by one: whole GOP units of the cloud-gapped sweep, and the first
+pictures (I and P, full search) of sampled GOP units of the Planet-like and
+reanalysis-like cubes, from band statistics it computes itself over the whole
+cube.  Properties that hold at any size are checked on everything: decode ==
+encoder reconstruction, two encodes are identical, and the batched path equals
+the plain one."""
+import concurrent.futures as cf
+import hashlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2506_19656_amd import synth
+from paper_2506_19656_amd import xv
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+KEYS = ("frames", "levels", "mvs", "recon", "coef_bits", "mv_bits")
+
+
+def _op(p: xv.Params) -> O.CodingParams:
+    return O.CodingParams(bit_depth=p.bit_depth, qp=p.qp, block=p.block,
+                          search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
+                          fill_mode=p.fill_mode)
+
+
+def _gpu_unit(enc: xv.Encoded, g: int, t0: int, n: int) -> dict:
+    """Host copies of frames t0..t0+n-1 of group g."""
+    ex = enc.export()
+    types = {"frames": np.uint16, "recon": np.uint16, "levels": np.int16, "mvs": np.int8,
+             "coef_bits": np.uint32, "mv_bits": np.uint32}
+    return {k: ex[k][g, t0:t0 + n].cpu().numpy().view(ty) for k, ty in types.items()}
+
+
+def _oracle_units(cube_host, mn, mx, p: xv.Params, units):
+    """units: list of (g, t0, len); run in parallel host threads."""
+    op = _op(p)
+
+    def one(u):
+        g, t0, n = u
+        return O.encode_gop(cube_host, mn, mx, op, g, t0, n)
+
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        return list(ex.map(one, units))
+
+
+def _compare(name, got, ref):
+    for k in KEYS:
+        a, b = got[k], ref[k]
+        if not np.array_equal(a, b):
+            d = np.argwhere(a != b)
+            raise AssertionError(f"{name}: {k} differs in {len(d)} elements, first {d[0].tolist()}")
+
+
+def _digest(enc: xv.Encoded) -> str:
+    ex = enc.export()
+    h = hashlib.sha256()
+    for k in ("levels", "mvs", "recon", "coef_bits", "mv_bits"):
+        h.update(ex[k].cpu().numpy().tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.timeout(900)
+def test_s2cloud_full_sweep_sampled_units():
+    wl = synth.WORKLOADS["s2cloud"]
+    print(f"[case] s2cloud full {wl.T}x{wl.H}x{wl.W}x{wl.bands}", flush=True)
+    cube = synth.s2cloud_cube(device="cuda")
+    host = cube.cpu().numpy()
+    runs = [(qp, N) for N in wl.blocks for qp in wl.qps]
+    params = [xv.Params(bit_depth=wl.bit_depth, qp=qp, block=N, search_range=wl.search_range,
+                        gop=wl.gop, pad_mode=wl.pad_mode, fill_mode=wl.fill_mode)
+              for qp, N in runs]
+    for N in wl.blocks:
+        xv.autotune_me(cube, xv.Params(bit_depth=wl.bit_depth, qp=27, block=N,
+                                       search_range=wl.search_range, gop=wl.gop))
+    encs = xv.encode_batch([cube] * len(params), params)
+    mn, mx, nv = O.stats(host)
+    ngop = -(-wl.T // wl.gop)
+    rng = np.random.default_rng(123)
+    for i, (p, e) in enumerate(zip(params, encs)):
+        got_all = e.host()
+        assert np.array_equal(got_all["band_min"], mn) and np.array_equal(got_all["band_max"], mx)
+        assert [int(v) for v in got_all["n_valid"]] == [int(v) for v in nv]
+        units = [(int(rng.integers(0, 2)), int(k) * wl.gop) for k in rng.choice(ngop, 2, replace=False)]
+        units = [(g, t0, min(wl.gop, wl.T - t0)) for g, t0 in units] + [(1, (ngop - 1) * wl.gop,
+                                                                          wl.T - (ngop - 1) * wl.gop)]
+        refs = _oracle_units(host, mn, mx, p, units)
+        for (g, t0, n), ref in zip(units, refs):
+            got = {k: got_all[k][g, t0:t0 + n] for k in KEYS}
+            _compare(f"s2cloud {runs[i]} unit g{g} t{t0}+{n}", got, ref)
+    # plain path equals batched path (two runs) and repeat encodes are identical
+    for i in (0, len(params) - 1):
+        plain = xv.encode_cube(cube, params[i])
+        assert _digest(plain) == _digest(encs[i])
+    again = xv.encode_batch([cube] * 2, params[:2])
+    assert _digest(again[0]) == _digest(encs[0]) and _digest(again[1]) == _digest(encs[1])
+
+
+def _first_pictures_parity(name, cube, p: xv.Params, units_k, nframes):
+    host = cube.cpu().numpy()
+    print(f"[case] {name}: oracle stats over {host.size} samples", flush=True)
+    mn, mx, nv = O.stats(host)
+    xv.autotune_me(cube, p)
+    enc = xv.encode_batch([cube], [p])[0]
+    got_all = enc.export()
+    assert np.array_equal(got_all["band_min"].cpu().numpy(), mn)
+    assert np.array_equal(got_all["band_max"].cpu().numpy(), mx)
+    G = (host.shape[3] + 2) // 3
+    units = [(g, k * p.gop, nframes) for g in range(G) for k in units_k]
+    print(f"[case] {name}: oracle on units {units}", flush=True)
+    refs = _oracle_units(host, mn, mx, p, units)
+    for (g, t0, n), ref in zip(units, refs):
+        _compare(f"{name} unit g{g} t{t0}+{n}", _gpu_unit(enc, g, t0, n), ref)
+    # closed loop at full size: decode == denormalised encoder reconstruction
+    out = torch.empty_like(cube)
+    xv.decode_cube(enc, out)
+    m = xv.psnr_bpppb(cube, enc)
+    torch.cuda.synchronize()
+    rec_t = got_all["recon"]
+    for g in range(G):
+        for k in units_k[:1]:
+            t = k * p.gop + 1
+            q = rec_t[g, t].cpu().numpy().view(np.uint16)
+            for c in range(3):
+                b = 3 * g + c
+                if b >= host.shape[3]:
+                    continue
+                H, W = host.shape[1:3]
+                expect = np.array([O.cast_output(O.denormalize(int(v), mn[b], mx[b], p.bit_depth),
+                                                 O.U16 if host.dtype == np.uint16 else O.F32)
+                                   for v in q[c, :H, :W].ravel()[::997]])
+                got = out[t, :, :, b].cpu().numpy().ravel()[::997].astype(np.float64)
+                assert np.array_equal(got, expect), (name, g, t, c)
+    assert all(np.isfinite(m["psnr"])) and m["bpppb"] > 0
+    return enc
+
+
+@pytest.mark.timeout(900)
+def test_planet_full_size_sampled_first_pictures():
+    wl = synth.WORKLOADS["planet"]
+    print(f"[case] planet full {wl.T}x{wl.H}x{wl.W}x{wl.bands}", flush=True)
+    cube = synth.planet_cube(device="cuda")
+    for qp in wl.qps:
+        p = xv.Params(bit_depth=wl.bit_depth, qp=qp, block=16, search_range=wl.search_range,
+                      gop=wl.gop, pad_mode=wl.pad_mode)
+        _first_pictures_parity(f"planet qp{qp}", cube, p, units_k=[0, 45], nframes=2)
+
+
+@pytest.mark.timeout(900)
+def test_era5_full_size_sampled_units():
+    wl = synth.WORKLOADS["era5"]
+    print(f"[case] era5 full {wl.T}x{wl.H}x{wl.W}x{wl.bands}", flush=True)
+    cube = synth.era5_cube(device="cuda")
+    for qp in wl.qps:
+        p = xv.Params(bit_depth=wl.bit_depth, qp=qp, block=32, search_range=wl.search_range,
+                      gop=wl.gop)
+        _first_pictures_parity(f"era5 qp{qp}", cube, p, units_k=[0, 46], nframes=4)
