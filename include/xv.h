@@ -185,6 +185,69 @@ int xv_encode_batch(int n, const xv_cube* cubes, const xv_params* params,
 int xv_decode_batch(int n, xv_encoded* const* encs, const xv_cube* outs,
                     void* hip_stream);
 
+/* ---- Serving loop: continuous batching of encode / decode requests ---- */
+
+/* A server owns one scheduler thread and one HIP stream.  Requests are
+ * admitted in arrival order while a slot is free and their device footprint
+ * fits the memory budget; every scheduler iteration then launches the next
+ * frame step of all resident requests together (one launch per block-size
+ * class, whatever step each request is at), so requests that arrive while
+ * others are on the GPU join the running batch.  A request's outputs are
+ * identical to those of xv_encode_cube / xv_decode_cube. */
+#define XV_OP_ENCODE 0
+#define XV_OP_DECODE 1
+
+typedef struct {
+  uint64_t hbm_budget; /* bytes for in-flight requests (0: 64 GiB)            */
+  int32_t max_slots;   /* resident requests at once (<= 0: 64)                */
+  int32_t max_queue;   /* queued requests before submit fails (<= 0: 65536)   */
+  void* stream;        /* HIP stream to launch on (NULL: the server makes one) */
+} xv_server_cfg;
+
+typedef struct xv_server xv_server;
+
+typedef struct {
+  int32_t op;            /* XV_OP_ENCODE or XV_OP_DECODE                       */
+  int32_t reserved;
+  xv_cube cube;          /* encode: input; decode: output buffer (device)      */
+  xv_params params;      /* encode only                                        */
+  const xv_encoded* enc; /* decode only: the encoded cube (must outlive it)    */
+} xv_request;
+
+typedef struct {
+  int32_t status;  /* XV_OK, XV_ECANCELED or the request's error              */
+  int32_t op;
+  xv_encoded* enc; /* encode result; the caller owns it once returned         */
+  double submit_ms, admit_ms, done_ms; /* steady host clock, milliseconds     */
+} xv_result;
+
+typedef struct {
+  uint64_t submitted, completed, cancelled, failed;
+  uint64_t iterations, launches;
+  uint64_t peak_bytes;
+  int32_t peak_active;
+  int32_t reserved;
+} xv_server_stats;
+
+/* Create a server.  Errors: XV_EINVAL, XV_EHIP. */
+int xv_server_create(const xv_server_cfg* cfg, xv_server** out);
+/* Queue a request (non-blocking); *ticket identifies it.  The caller keeps
+ * the request's device buffers alive until its result is returned.  Errors:
+ * XV_EINVAL (bad request), XV_EBUSY (queue full). */
+int xv_server_submit(xv_server* sv, const xv_request* rq, uint64_t* ticket);
+/* XV_EPENDING while the request runs; XV_OK once *res holds its result (the
+ * ticket is then retired).  XV_EINVAL for an unknown ticket. */
+int xv_server_poll(xv_server* sv, uint64_t ticket, xv_result* res);
+/* As xv_server_poll, but blocks until the request completes. */
+int xv_server_wait(xv_server* sv, uint64_t ticket, xv_result* res);
+/* Cancel: a queued request never runs; a running one finishes on the GPU
+ * and its result is discarded.  Its status becomes XV_ECANCELED. */
+int xv_server_cancel(xv_server* sv, uint64_t ticket);
+int xv_server_stats_read(xv_server* sv, xv_server_stats* st);
+/* Drain queued and running requests, release unretrieved results, stop the
+ * scheduler and free the server.  NULL is a no-op. */
+int xv_server_destroy(xv_server* sv);
+
 /* ---- Launch geometry (never changes coded outputs) -------------------- */
 
 /* Geometry of the motion-search kernel for one (N, R): blocks per

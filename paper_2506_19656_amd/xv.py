@@ -73,10 +73,35 @@ class ProfileC(C.Structure):
     _fields_ = [("ms", C.c_double * 7), ("launches", C.c_uint64 * 7), ("work", C.c_double * 7)]
 
 
+class ServerCfgC(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_slots", C.c_int32), ("max_queue", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class RequestC(C.Structure):
+    _fields_ = [("op", C.c_int32), ("reserved", C.c_int32), ("cube", Cube), ("params", ParamsC),
+                ("enc", C.c_void_p)]
+
+
+class ResultC(C.Structure):
+    _fields_ = [("status", C.c_int32), ("op", C.c_int32), ("enc", C.c_void_p),
+                ("submit_ms", C.c_double), ("admit_ms", C.c_double), ("done_ms", C.c_double)]
+
+
+class ServerStatsC(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("cancelled", C.c_uint64),
+                ("failed", C.c_uint64), ("iterations", C.c_uint64), ("launches", C.c_uint64),
+                ("peak_bytes", C.c_uint64), ("peak_active", C.c_int32), ("reserved", C.c_int32)]
+
+
+OP_ENCODE, OP_DECODE = 0, 1
+
 EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube",
             "xv_decode_cube", "xv_psnr_bpppb", "xv_encoded_export", "xv_encoded_free",
             "xv_encode_batch", "xv_decode_batch", "xv_set_me_geometry", "xv_get_me_geometry",
-            "xv_autotune_me", "xv_profile_enable", "xv_profile_read"]
+            "xv_autotune_me", "xv_profile_enable", "xv_profile_read", "xv_server_create",
+            "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
+            "xv_server_stats_read", "xv_server_destroy"]
 
 _lib = None
 
@@ -107,6 +132,13 @@ def lib():
         L.xv_get_me_geometry.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(MeGeometryC)]
         L.xv_autotune_me.argtypes = [C.POINTER(Cube), C.POINTER(ParamsC), vp, C.c_int,
                                      C.POINTER(MeGeometryC), C.POINTER(C.c_double)]
+        L.xv_server_create.argtypes = [C.POINTER(ServerCfgC), C.POINTER(vp)]
+        L.xv_server_submit.argtypes = [vp, C.POINTER(RequestC), C.POINTER(C.c_uint64)]
+        L.xv_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(ResultC)]
+        L.xv_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(ResultC)]
+        L.xv_server_cancel.argtypes = [vp, C.c_uint64]
+        L.xv_server_stats_read.argtypes = [vp, C.POINTER(ServerStatsC)]
+        L.xv_server_destroy.argtypes = [vp]
         L.xv_profile_enable.argtypes = [C.c_int]
         L.xv_profile_read.argtypes = [C.POINTER(ProfileC)]
         _lib = L
@@ -312,3 +344,71 @@ def profile_read() -> dict:
     _check(lib().xv_profile_read(C.byref(p)))
     return {K_NAMES[i]: dict(ms=p.ms[i], launches=p.launches[i], work=p.work[i])
             for i in range(7)}
+
+
+class Server:
+    """Continuous-batching encode/decode server (xv_server_*)."""
+
+    def __init__(self, hbm_budget: int = 0, max_slots: int = 0, max_queue: int = 0, stream=None):
+        cfg = ServerCfgC(hbm_budget, max_slots, max_queue,
+                         None if stream is None else _stream_handle(stream))
+        h = C.c_void_p()
+        _check(lib().xv_server_create(C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self._keep = {}  # device buffers referenced by in-flight requests
+
+    def submit_encode(self, cube, params: Params) -> int:
+        rq = RequestC(OP_ENCODE, 0, _cube(cube), params.c(), None)
+        t = C.c_uint64()
+        _check(lib().xv_server_submit(self.handle, C.byref(rq), C.byref(t)))
+        self._keep[t.value] = (cube, params)
+        return t.value
+
+    def submit_decode(self, enc: "Encoded", out) -> int:
+        rq = RequestC(OP_DECODE, 0, _cube(out), ParamsC(), enc.handle)
+        t = C.c_uint64()
+        _check(lib().xv_server_submit(self.handle, C.byref(rq), C.byref(t)))
+        self._keep[t.value] = (enc, out)
+        return t.value
+
+    def _result(self, ticket, r: ResultC):
+        kept = self._keep.pop(ticket, None)
+        enc = None
+        if r.enc:
+            cube, params = kept
+            enc = Encoded(C.c_void_p(r.enc), tuple(cube.shape), params)
+        return dict(status=r.status, op=r.op, enc=enc, submit_ms=r.submit_ms,
+                    admit_ms=r.admit_ms, done_ms=r.done_ms)
+
+    def poll(self, ticket: int):
+        r = ResultC()
+        rc = lib().xv_server_poll(self.handle, ticket, C.byref(r))
+        if rc == EPENDING:
+            return None
+        _check(rc)
+        return self._result(ticket, r)
+
+    def wait(self, ticket: int) -> dict:
+        r = ResultC()
+        _check(lib().xv_server_wait(self.handle, ticket, C.byref(r)))
+        return self._result(ticket, r)
+
+    def cancel(self, ticket: int):
+        _check(lib().xv_server_cancel(self.handle, ticket))
+
+    def stats(self) -> dict:
+        st = ServerStatsC()
+        _check(lib().xv_server_stats_read(self.handle, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStatsC._fields_ if k != "reserved"}
+
+    def close(self):
+        if self.handle:
+            lib().xv_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
