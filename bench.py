@@ -67,6 +67,94 @@ def cpu_baseline(cube_host, wl, seconds_hint=""):
                       f"{wl.bands} cube, encode+decode+metrics, {dt:.1f} s wall"}
 
 
+def serve_bench(xv, synth, torch, n=160, seed=4, loads=(0.5, 0.9, 1.2, 2.0)):
+    """Serving mix: requests with the mix's recipe (encode or decode with
+    p = 1/2, log-uniform sizes, bands {3, 4, 6}, QP 17..37, N = 16, R = 16)
+    at sizes capped to T <= 96 and side <= 256 so the run takes seconds.
+    Offered loads are fractions of the plain path's measured capacity; the
+    plain baseline serves the same arrivals one request at a time."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    reqs = synth.request_trace(n, rate_per_s=1.0, seed=seed, t_range=(16, 96), s_range=(64, 256))
+    items = []
+    for r in reqs:
+        cube = synth.tiny_cube(seed=r.seed, T=r.T, H=r.S, W=r.S, bands=r.bands, device=dev)
+        prm = xv.Params(bit_depth=10, qp=r.qp, block=16, search_range=16, gop=16,
+                        flags=xv.FLAG_DROP_WORK)
+        pxb = r.T * r.S * r.S * r.bands
+        if r.op == "decode":
+            items.append(("decode", xv.encode_cube(cube, prm), torch.empty_like(cube), pxb))
+        else:
+            items.append(("encode", cube, prm, pxb))
+    torch.cuda.synchronize()
+    total_pxb = sum(it[3] for it in items)
+
+    def run_plain_one(it):
+        if it[0] == "encode":
+            e = xv.encode_cube(it[1], it[2])
+            torch.cuda.synchronize()
+            e.free()
+        else:
+            xv.decode_cube(it[1], it[2])
+            torch.cuda.synchronize()
+
+    for it in items[:8]:
+        run_plain_one(it)  # warm-up
+    t0 = time.perf_counter()
+    for it in items:
+        run_plain_one(it)
+    cap_s = time.perf_counter() - t0
+    mean_service = cap_s / len(items)
+    out = {"requests": len(items), "px_band_total": total_pxb,
+           "trace": "Poisson arrivals; encode/decode p=1/2; T log-uniform 16..96, side "
+                    "log-uniform 64..256 (multiple of 32), bands {3,4,6}, QP 17..37, N=16, R=16",
+           "plain_capacity_mpxb_s": round(total_pxb / cap_s / 1e6, 3), "loads": []}
+    rng = np.random.default_rng(seed + 1)
+    gaps_unit = rng.exponential(1.0, len(items))
+    for rho in loads:
+        gaps = gaps_unit * mean_service / rho
+        arrive = np.cumsum(gaps) - gaps[0]
+        # plain FIFO at the same arrivals
+        lat = []
+        base = time.perf_counter()
+        for it, a in zip(items, arrive):
+            now = time.perf_counter() - base
+            if now < a:
+                time.sleep(a - now)
+            run_plain_one(it)
+            lat.append((time.perf_counter() - base - a) * 1e3)
+        plain_span = time.perf_counter() - base
+        # served
+        sv = xv.Server(max_slots=64)
+        tickets = []
+        base = time.perf_counter()
+        for it, a in zip(items, arrive):
+            now = time.perf_counter() - base
+            if now < a:
+                time.sleep(a - now)
+            if it[0] == "encode":
+                tickets.append(sv.submit_encode(it[1], it[2]))
+            else:
+                tickets.append(sv.submit_decode(it[1], it[2]))
+        res = [sv.wait(t) for t in tickets]
+        served_span = time.perf_counter() - base
+        st = sv.stats()
+        sv.close()
+        if any(r["status"] != xv.OK for r in res):
+            raise SystemExit("served request failed")
+        slat = [r["done_ms"] - r["submit_ms"] for r in res]
+        out["loads"].append({
+            "rho": rho, "offered_req_per_s": round(1.0 / (mean_service / rho), 2),
+            "served": {"value": round(total_pxb / served_span / 1e6, 3),
+                       "p50_ms": round(_percentile(slat, 0.5), 3),
+                       "p99_ms": round(_percentile(slat, 0.99), 3),
+                       "peak_active": st["peak_active"], "iterations": st["iterations"]},
+            "plain": {"value": round(total_pxb / plain_span / 1e6, 3),
+                      "p50_ms": round(_percentile(lat, 0.5), 3),
+                      "p99_ms": round(_percentile(lat, 0.99), 3)}})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,8 +162,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["both", "batched", "plain"], default="both")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix section")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the motion-search geometry tuner (model defaults)")
+    ap.add_argument("--geometry-file", default=None,
+                    help="load tuned motion-search geometries from this JSON file if it "
+                         "exists, else tune and write them there")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -105,8 +197,17 @@ def main():
 
     # launch-geometry tuning (outside the timed region; outputs never depend on it)
     tuning = {}
+    cached = None
+    if args.geometry_file and os.path.exists(args.geometry_file):
+        with open(args.geometry_file) as f:
+            cached = json.load(f)
     for N in wl.blocks:
-        if not args.no_tune:
+        if cached is not None and f"N{N}" in cached:
+            g = cached[f"N{N}"]
+            xv.set_me_geometry(N, wl.search_range, g["blocks_per_wg"], g["cands_per_lane"],
+                               g["threads"])
+            tuning[f"N{N}"] = dict(g, tuned=True, from_file=True)
+        elif not args.no_tune:
             print(f"[bench] tuning motion search N={N}", file=sys.stderr, flush=True)
             t = xv.autotune_me(cube, xv.Params(bit_depth=wl.bit_depth, qp=27, block=N,
                                                search_range=wl.search_range, gop=wl.gop,
@@ -115,6 +216,9 @@ def main():
         else:
             tuning[f"N{N}"] = dict(xv.get_me_geometry(N, wl.search_range, -(-wl.W // N)),
                                    tuned=False)
+    if args.geometry_file and cached is None:
+        with open(args.geometry_file, "w") as f:
+            json.dump(tuning, f)
 
     def step_plain(lat=None):
         ms = []
@@ -232,6 +336,9 @@ def main():
                              "avg_launch_ms": round(avg, 4), "launches": d["launches"]}
         line["kernel_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()
                                       if v["launches"]}
+    if not args.no_serve:
+        print("[bench] serving mix", file=sys.stderr, flush=True)
+        line["served"] = serve_bench(xv, synth, torch)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cube.cpu().numpy(), wl)
