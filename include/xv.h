@@ -302,6 +302,27 @@ int xv_profile_enable(int on);
 /* Synchronises the streams that were timed and returns the totals. */
 int xv_profile_read(xv_profile* out);
 
+/* ---- device memory ---------------------------------------------------------
+ * Every device buffer of the library comes from one caching allocator per
+ * process.  A freed buffer (xv_encoded_free, the end of a decode, a dropped
+ * work buffer) is kept for reuse instead of being returned to the runtime:
+ * immediately by later work on the stream it was freed on, and by work on
+ * any other stream once everything queued on that stream before the free has
+ * completed.  A stream handed to the library must therefore stay alive until
+ * the objects used on it are freed and that work has completed.  Memory goes
+ * back to the runtime only when an allocation fails for lack of it (cached
+ * blocks are released and the allocation retried) or on xv_cache_release. */
+typedef struct xv_memory {
+  uint64_t live_bytes;    /* held by live objects and in-flight calls */
+  uint64_t cached_bytes;  /* freed, kept for reuse */
+  uint64_t peak_bytes;    /* maximum of live_bytes since the library loaded */
+} xv_memory;
+
+int xv_memory_read(xv_memory* out);
+/* Waits for the last use of every cached block and returns it to the
+ * runtime; *released_bytes (may be NULL) receives the total. */
+int xv_cache_release(uint64_t* released_bytes);
+
 #ifdef __cplusplus
 }
 #endif

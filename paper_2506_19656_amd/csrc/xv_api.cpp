@@ -85,19 +85,6 @@ int hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
-// ---- device memory ---------------------------------------------------------
-std::once_flag g_pool_once;
-void init_pool() {
-  std::call_once(g_pool_once, [] {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t thr = UINT64_MAX;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-  });
-}
 
 struct Carve {
   size_t off = 0;
@@ -274,15 +261,14 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   const size_t span_words = lay.span_words;
   e->phys_nb = lay.phys_nb;
 
-  init_pool();
-  hipError_t he = hipMallocAsync(&e->keep, k.off, s);
+  hipError_t he = dev_alloc(&e->keep, k.off, s);
   if (he != hipSuccess) {
     delete e;
     return hip_fail(he, "device allocation of the encoded cube");
   }
-  he = hipMallocAsync(&e->work, w.off, s);
+  he = dev_alloc(&e->work, w.off, s);
   if (he != hipSuccess) {
-    (void)hipFreeAsync(e->keep, s);
+    dev_free(e->keep, s);
     delete e;
     return hip_fail(he, "device allocation of the coding work buffers");
   }
@@ -421,7 +407,7 @@ int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s) {
 
 void drop_work(xv_encoded* e) {
   if (e->p.flags & XV_FLAG_DROP_WORK) {
-    (void)hipFreeAsync(e->work, e->stream);
+    dev_free(e->work, e->stream);
     e->work = nullptr;
     e->frames = nullptr;
     e->recon = nullptr;
@@ -450,8 +436,7 @@ int decode_prepare(const xv_encoded* e, hipStream_t s, DecodeBuf& db) {
   size_t o_rc = c.take<uint16_t>((size_t)e->G * e->T * 3 * plane);
   size_t o_jb = c.take<FrameJob>((size_t)e->njobs);
   db.mem = nullptr;
-  init_pool();
-  XV_HIP(hipMallocAsync(&db.mem, c.off, s), "device allocation of the decode buffers");
+  XV_HIP(dev_alloc(&db.mem, c.off, s), "device allocation of the decode buffers");
   db.recon = (uint16_t*)((char*)db.mem + o_rc);
   db.jobs = (FrameJob*)((char*)db.mem + o_jb);
   CubePlan pl{nullptr, db.recon, e->levels, e->mvs, nullptr, nullptr, nullptr, nullptr,
@@ -520,7 +505,7 @@ int decode_finish(const xv_encoded* e, const xv_cube* out, DecodeBuf& db, hipStr
     ProfScope ps(XV_K_DENORM, s, (double)e->T * e->H * e->W * e->bands * (2.0 + ob));
     XV_HIP(launch_denorm(a, s), "denormalise kernel");
   }
-  XV_HIP(hipFreeAsync(db.mem, s), "free decode buffers");
+  dev_free(db.mem, s);
   db.mem = nullptr;
   return XV_OK;
 }
@@ -614,7 +599,7 @@ int xv_decode_cube(const xv_encoded* e, const xv_cube* out, void* hip_stream) {
   if ((rc = decode_prepare(e, s, db)) != XV_OK) return rc;
   std::vector<DecSrc> src{DecSrc{e, db.jobs, 0}};
   if ((rc = decode_steps(src, s)) != XV_OK) {
-    (void)hipFreeAsync(db.mem, s);
+    dev_free(db.mem, s);
     return rc;
   }
   return decode_finish(e, out, db, s);
@@ -631,7 +616,7 @@ int xv_decode_batch(int n, xv_encoded* const* encs, const xv_cube* outs, void* h
   std::vector<DecodeBuf> bufs(n);
   auto cleanup = [&](int rc) {
     for (auto& b : bufs)
-      if (b.mem) (void)hipFreeAsync(b.mem, s);
+      if (b.mem) dev_free(b.mem, s);
     return rc;
   };
   for (int i = 0; i < n; i++) {
@@ -754,8 +739,8 @@ int xv_encoded_export(const xv_encoded* e, xv_export* v) {
 
 void xv_encoded_free(xv_encoded* e) {
   if (!e) return;
-  if (e->work) (void)hipFreeAsync(e->work, e->stream);
-  if (e->keep) (void)hipFreeAsync(e->keep, e->stream);
+  if (e->work) dev_free(e->work, e->stream);
+  if (e->keep) dev_free(e->keep, e->stream);
   delete e;
 }
 
@@ -895,6 +880,22 @@ int xv_profile_enable(int on) {
   g_prof_pending.clear();
   memset(&g_prof_tot, 0, sizeof g_prof_tot);
   g_prof_on = on != 0;
+  return XV_OK;
+}
+
+int xv_memory_read(xv_memory* out) {
+  if (!out) return fail(XV_EINVAL, "null memory record");
+  size_t live = 0, cached = 0, peak = 0;
+  dev_cache_stats(&live, &cached, &peak);
+  out->live_bytes = live;
+  out->cached_bytes = cached;
+  out->peak_bytes = peak;
+  return XV_OK;
+}
+
+int xv_cache_release(uint64_t* released_bytes) {
+  const size_t n = dev_cache_release();
+  if (released_bytes) *released_bytes = n;
   return XV_OK;
 }
 
@@ -1205,7 +1206,6 @@ int xv_server_create(const xv_server_cfg* cfg, xv_server** out) {
     }
     sv->own_stream = true;
   }
-  init_pool();
   sv->th = std::thread(scheduler, sv);
   *out = sv;
   return XV_OK;
@@ -1315,7 +1315,10 @@ int xv_server_destroy(xv_server* sv) {
     delete r;
   }
   sv->reqs.clear();
-  if (sv->own_stream) (void)hipStreamDestroy(sv->s);
+  if (sv->own_stream) {
+    dev_stream_retired(sv->s);
+    (void)hipStreamDestroy(sv->s);
+  }
   delete sv;
   return XV_OK;
 }

@@ -226,4 +226,15 @@ struct PhysArgs {
 int phys_blocks(int64_t npix);
 hipError_t launch_phys_sse(const PhysArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Caching device allocator (xv_alloc.cpp).  dev_free keeps the block for
+// reuse: at once on the same stream, on another stream once the work queued
+// before the free has completed.
+// ---------------------------------------------------------------------------
+hipError_t dev_alloc(void** out, size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+void dev_stream_retired(hipStream_t s);  // before a stream is destroyed
+size_t dev_cache_release();              // waits for and frees every cached block
+void dev_cache_stats(size_t* live, size_t* cached, size_t* peak);
+
 }  // namespace xv

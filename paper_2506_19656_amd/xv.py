@@ -73,6 +73,11 @@ class ProfileC(C.Structure):
     _fields_ = [("ms", C.c_double * 7), ("launches", C.c_uint64 * 7), ("work", C.c_double * 7)]
 
 
+class MemoryC(C.Structure):
+    _fields_ = [("live_bytes", C.c_uint64), ("cached_bytes", C.c_uint64),
+                ("peak_bytes", C.c_uint64)]
+
+
 class ServerCfgC(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("max_slots", C.c_int32), ("max_queue", C.c_int32),
                 ("stream", C.c_void_p)]
@@ -101,7 +106,7 @@ EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube"
             "xv_encode_batch", "xv_decode_batch", "xv_set_me_geometry", "xv_get_me_geometry",
             "xv_autotune_me", "xv_profile_enable", "xv_profile_read", "xv_server_create",
             "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
-            "xv_server_stats_read", "xv_server_destroy"]
+            "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release"]
 
 _lib = None
 
@@ -132,6 +137,8 @@ def lib():
         L.xv_get_me_geometry.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(MeGeometryC)]
         L.xv_autotune_me.argtypes = [C.POINTER(Cube), C.POINTER(ParamsC), vp, C.c_int,
                                      C.POINTER(MeGeometryC), C.POINTER(C.c_double)]
+        L.xv_memory_read.argtypes = [C.POINTER(MemoryC)]
+        L.xv_cache_release.argtypes = [C.POINTER(C.c_uint64)]
         L.xv_server_create.argtypes = [C.POINTER(ServerCfgC), C.POINTER(vp)]
         L.xv_server_submit.argtypes = [vp, C.POINTER(RequestC), C.POINTER(C.c_uint64)]
         L.xv_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(ResultC)]
@@ -344,6 +351,20 @@ def profile_read() -> dict:
     _check(lib().xv_profile_read(C.byref(p)))
     return {K_NAMES[i]: dict(ms=p.ms[i], launches=p.launches[i], work=p.work[i])
             for i in range(7)}
+
+
+def memory_read() -> dict:
+    """xv_memory_read: bytes held by live objects, cached for reuse, and the peak."""
+    m = MemoryC()
+    _check(lib().xv_memory_read(C.byref(m)))
+    return dict(live_bytes=m.live_bytes, cached_bytes=m.cached_bytes, peak_bytes=m.peak_bytes)
+
+
+def cache_release() -> int:
+    """xv_cache_release: return every cached device block to the runtime."""
+    n = C.c_uint64(0)
+    _check(lib().xv_cache_release(C.byref(n)))
+    return n.value
 
 
 class Server:

@@ -90,3 +90,11 @@ def test_me_geometry_validation(xvmod):
         xvmod.set_me_geometry(12, 8)
     g = xvmod.get_me_geometry(16, 32)
     assert g["cands_per_lane"] % 2 == 0 and g["threads"] % 64 == 0 and g["blocks_per_wg"] >= 1
+
+
+def test_memory_record_and_release_without_device_work(xvmod):
+    m = xvmod.memory_read()
+    assert set(m) == {"live_bytes", "cached_bytes", "peak_bytes"}
+    assert m["live_bytes"] <= m["peak_bytes"]
+    L = xvmod.lib()
+    assert L.xv_memory_read(None) == xvmod.EINVAL
