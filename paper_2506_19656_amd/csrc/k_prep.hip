@@ -38,50 +38,106 @@ __device__ inline float key_f32(uint32_t k) {
   return __uint_as_float(u);
 }
 
-// Pixel-major scan: thread i handles pixels i, i + stride, ... and keeps
-// per-band keys for a chunk of up to 8 bands in registers; blocks merge them
-// in LDS, then with one global atomic per band (min/max/count are order
-// independent, so the result is deterministic).
+// ---------------------------------------------------------------------------
+// Row-chunk staging through LDS.  The pixel-major cube ([T][H][W][bands]) is
+// read and written in contiguous runs of chunk * bands elements with 16-byte
+// accesses; the kernels then address single samples in LDS.  Element i of a
+// run starting at global address g lives at lds[mis + i], mis being the
+// element offset of g past the previous 16-byte boundary, so every whole
+// 16-byte granule of the run maps onto one aligned LDS vector; the elements
+// of granules cut by either end of the run are copied one by one.
+// ---------------------------------------------------------------------------
+constexpr int kStage = 4096;  // elements of one staged run at most
+
+// The staged run lives in dynamic LDS sized to the launch's chunk (see
+// stage_bytes), so small chunks keep occupancy high.
+extern __shared__ uint4 xv_stage_lds[];
+
+inline size_t stage_bytes(int chunk_px, int bands, int elem) {
+  return ((size_t)chunk_px * bands * elem + 16 + 15) / 16 * 16;
+}
+
+template <typename T>
+__device__ inline int stage_mis(const T* g) {
+  return (int)(((uintptr_t)g & 15) / sizeof(T));
+}
+
+template <typename T>
+__device__ inline int stage_in(const T* __restrict__ g, T* lds, int n) {
+  constexpr int V = 16 / sizeof(T);
+  const int mis = stage_mis(g);
+  const int body0 = mis ? V - mis : 0;  // first element of the first whole granule
+  const int nfull = n > body0 ? (n - body0) / V : 0;
+  const int body1 = body0 + nfull * V;
+  const uint4* gv = (const uint4*)(g + body0);
+  uint4* lv = (uint4*)(lds + mis + body0);
+  for (int k = threadIdx.x; k < nfull; k += blockDim.x) lv[k] = gv[k];
+  const int head = n < body0 ? n : body0;
+  for (int e = threadIdx.x; e < head; e += blockDim.x) lds[mis + e] = g[e];
+  for (int e = body1 + threadIdx.x; e < n; e += blockDim.x) lds[mis + e] = g[e];
+  return mis;
+}
+
+template <typename T>
+__device__ inline void stage_out(const T* lds, T* __restrict__ g, int n, int mis) {
+  constexpr int V = 16 / sizeof(T);
+  const int body0 = mis ? V - mis : 0;
+  const int nfull = n > body0 ? (n - body0) / V : 0;
+  const int body1 = body0 + nfull * V;
+  uint4* gv = (uint4*)(g + body0);
+  const uint4* lv = (const uint4*)(lds + mis + body0);
+  for (int k = threadIdx.x; k < nfull; k += blockDim.x) gv[k] = lv[k];
+  const int head = n < body0 ? n : body0;
+  for (int e = threadIdx.x; e < head; e += blockDim.x) g[e] = lds[mis + e];
+  for (int e = body1 + threadIdx.x; e < n; e += blockDim.x) g[e] = lds[mis + e];
+}
+
+// ---------------------------------------------------------------------------
+// Statistics.  The cube is read as one flat array with coalesced loads of V
+// consecutive elements (16 bytes when the data is 16-byte aligned, else one
+// element).  The grid stride in elements is a multiple of the band count, so
+// slot j of every load a thread makes holds the same band, (tid * V + j) %
+// bands, and the per-band keys stay in V registers per kind.  Blocks merge in
+// LDS and write one partial per band; min, max and counts are order
+// independent, so the result is deterministic.
+// ---------------------------------------------------------------------------
 template <typename Tv>
-__device__ inline void stats_chunk(const Tv* d, int64_t npix, int bands, int b0, int nb,
-                                   uint32_t* smin, uint32_t* smax, uint32_t* snan) {
-  uint32_t lo[8], hi[8], nn[8];
-#pragma unroll
-  for (int j = 0; j < 8; j++) {
-    lo[j] = 0xffffffffu;
-    hi[j] = 0u;
-    nn[j] = 0u;
-  }
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += stride) {
-    const Tv* px = d + p * bands + b0;
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      if (j >= nb) break;
-      uint32_t k;
-      if constexpr (sizeof(Tv) == 2) {
-        k = (uint32_t)px[j];
-      } else {
-        const float f = px[j];
-        if (f != f) {
-          nn[j]++;
-          continue;
-        }
-        k = f32_key(f);
-      }
-      lo[j] = min(lo[j], k);
-      hi[j] = max(hi[j], k);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < 8; j++) {
-    if (j >= nb) break;
-    if (lo[j] != 0xffffffffu) atomicMin(&smin[b0 + j], lo[j]);
-    if (hi[j] != 0u) atomicMax(&smax[b0 + j], hi[j]);
-    if (nn[j]) atomicAdd(&snan[b0 + j], nn[j]);
+__device__ inline void stats_acc(Tv x, uint32_t& lo, uint32_t& hi, uint32_t& nn) {
+  if constexpr (sizeof(Tv) == 2) {
+    const uint32_t k = x;
+    lo = min(lo, k);
+    hi = max(hi, k);
+  } else {
+    const bool nan = x != x;
+    const uint32_t k = f32_key(x);
+    lo = nan ? lo : min(lo, k);
+    hi = nan ? hi : max(hi, k);
+    nn += nan ? 1u : 0u;
   }
 }
 
+template <typename Tv, int V>
+__device__ inline void load_run(const Tv* __restrict__ d, int64_t v, Tv (&x)[V]) {
+  if constexpr (V == 1) {
+    x[0] = d[v];
+  } else if constexpr (sizeof(Tv) == 4) {
+    const float4 f = ((const float4*)d)[v];
+    x[0] = f.x;
+    x[1] = f.y;
+    x[2] = f.z;
+    x[3] = f.w;
+  } else {
+    const uint4 u = ((const uint4*)d)[v];
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      x[2 * j] = (Tv)(w[j] & 0xffffu);
+      x[2 * j + 1] = (Tv)(w[j] >> 16);
+    }
+  }
+}
+
+template <typename Tv, int V>
 __global__ void __launch_bounds__(kThreads) stats_kernel(StatsArgs a) {
   __shared__ uint32_t smin[XV_MAX_BANDS], smax[XV_MAX_BANDS], snan[XV_MAX_BANDS];
   const int bands = a.bands;
@@ -90,44 +146,98 @@ __global__ void __launch_bounds__(kThreads) stats_kernel(StatsArgs a) {
     smax[i] = 0u;
     snan[i] = 0u;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.nan_total = 0u;  // summed by the finalize kernel
   __syncthreads();
-  for (int b0 = 0; b0 < bands; b0 += 8) {
-    const int nb = min(8, bands - b0);
-    if (a.dtype == XV_U16)
-      stats_chunk<uint16_t>((const uint16_t*)a.data, a.npix, bands, b0, nb, smin, smax, snan);
-    else
-      stats_chunk<float>((const float*)a.data, a.npix, bands, b0, nb, smin, smax, snan);
+  const Tv* d = (const Tv*)a.data;
+  const int64_t n = a.npix * bands;
+  const int64_t nvec = n / V;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t lo[V], hi[V], nn[V];
+#pragma unroll
+  for (int j = 0; j < V; j++) {
+    lo[j] = 0xffffffffu;
+    hi[j] = 0u;
+    nn[j] = 0u;
+  }
+  int64_t v = tid;
+  for (; v + 3 * nth < nvec; v += 4 * nth) {
+    Tv x[4][V];
+#pragma unroll
+    for (int u = 0; u < 4; u++) load_run<Tv, V>(d, v + u * nth, x[u]);
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int j = 0; j < V; j++) stats_acc(x[u][j], lo[j], hi[j], nn[j]);
+  }
+  for (; v < nvec; v += nth) {
+    Tv x[V];
+    load_run<Tv, V>(d, v, x);
+#pragma unroll
+    for (int j = 0; j < V; j++) stats_acc(x[j], lo[j], hi[j], nn[j]);
+  }
+  const int bt = (int)((tid * V) % bands);
+#pragma unroll
+  for (int j = 0; j < V; j++) {
+    const int b = (bt + j) % bands;
+    atomicMin(&smin[b], lo[j]);
+    atomicMax(&smax[b], hi[j]);
+    if (nn[j]) atomicAdd(&snan[b], nn[j]);
+  }
+  // the last n % V elements
+  const int64_t e = nvec * V + tid;
+  if (e < n) {
+    uint32_t l = 0xffffffffu, h = 0u, c = 0u;
+    stats_acc(d[e], l, h, c);
+    const int b = (int)(e % bands);
+    atomicMin(&smin[b], l);
+    atomicMax(&smax[b], h);
+    if (c) atomicAdd(&snan[b], c);
   }
   __syncthreads();
+  uint32_t* out = a.part + (int64_t)blockIdx.x * 3 * bands;
   for (int i = threadIdx.x; i < bands; i += blockDim.x) {
-    if (smin[i] != 0xffffffffu) atomicMin(&a.minkey[i], smin[i]);
-    if (smax[i] != 0u) atomicMax(&a.maxkey[i], smax[i]);
-    if (snan[i]) {
-      atomicAdd(&a.nan_count[i], snan[i]);
-      atomicAdd(a.nan_total, snan[i]);
-    }
+    out[i] = smin[i];
+    out[bands + i] = smax[i];
+    out[2 * bands + i] = snan[i];
   }
 }
 
-// Keys -> binary64 statistics.  A band without a valid sample gets 0, 0.
-__global__ void stats_finalize_kernel(StatsArgs a) {
-  int b = threadIdx.x;
-  if (b >= a.bands) return;
-  uint32_t nn = a.nan_count[b];
-  bool any = (uint64_t)nn < (uint64_t)a.npix;
-  double lo = 0.0, hi = 0.0;
+// One wave per band merges the block partials; keys -> binary64 statistics.
+// A band without a valid sample gets 0, 0.
+__global__ void __launch_bounds__(64) stats_finalize_kernel(StatsArgs a) {
+  const int b = blockIdx.x;
+  const int bands = a.bands;
+  uint32_t lo = 0xffffffffu, hi = 0u, nn = 0u;
+  for (int k = threadIdx.x; k < a.nblocks; k += 64) {
+    const uint32_t* p = a.part + (int64_t)k * 3 * bands;
+    lo = min(lo, p[b]);
+    hi = max(hi, p[bands + b]);
+    nn += p[2 * bands + b];
+  }
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, w, 64));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, w, 64));
+    nn += (uint32_t)__shfl_xor((int)nn, w, 64);
+  }
+  if (threadIdx.x != 0) return;
+  const bool any = (uint64_t)nn < (uint64_t)a.npix;
+  double l = 0.0, h = 0.0;
   if (any) {
     if (a.dtype == XV_U16) {
-      lo = (double)a.minkey[b];
-      hi = (double)a.maxkey[b];
+      l = (double)lo;
+      h = (double)hi;
     } else {
-      lo = (double)key_f32(a.minkey[b]);
-      hi = (double)key_f32(a.maxkey[b]);
+      l = (double)key_f32(lo);
+      h = (double)key_f32(hi);
     }
   }
-  a.mn[b] = lo;
-  a.mx[b] = hi;
+  a.mn[b] = l;
+  a.mx[b] = h;
   a.n_valid[b] = (unsigned long long)(a.npix - (int64_t)nn);
+  a.nan_count[b] = nn;
+  if (nn) atomicAdd(a.nan_total, nn);
 }
 
 // q = floor((x - mn) * L / (mx - mn) + 1/2) clamped to [0, L]; constant band -> 0.
@@ -142,174 +252,248 @@ __device__ inline uint16_t convert(double x, double mn, double range, double L) 
   return (uint16_t)q;
 }
 
-__device__ inline double load_sample(const void* data, int dtype, int64_t i) {
-  return dtype == XV_U16 ? (double)((const uint16_t*)data)[i] : (double)((const float*)data)[i];
-}
-
-// Missing-sample fill along time at one (pixel, band) series; `src` indexes
-// the sample of frame 0, `fstride` is the frame size in elements.  NEAREST:
-// the valid sample at the smallest |t - t'|, ties to the earlier t'.
-// FORWARD: the last valid value before t, else the first one after it.  A
-// series without a valid sample gives the band minimum.
-__device__ inline double fill_missing(const float* d, int64_t src, int64_t fstride, int64_t t,
-                                      int64_t T, int fill_mode, double mn) {
+// Missing-sample fill along time for up to 8 bands of one pixel at once;
+// `src` indexes the first of them in frame 0, `fstride` is the frame size in
+// elements, bit j of `miss` marks band j as missing at time t.  NEAREST: the
+// valid sample at the smallest |t - t'|, ties to the earlier t'.  FORWARD:
+// the last valid value before t, else the first one after it.  Each probe
+// of a time reads all the pixel's bands together; bands left without a
+// valid sample in the whole series keep their preset value (the band
+// minimum).
+__device__ inline void fill_missing(const float* __restrict__ d, int64_t src, int nb,
+                                    int64_t fstride, int64_t t, int64_t T, int fill_mode,
+                                    uint32_t miss, double (&v)[8]) {
+  auto probe = [&](int64_t u) {
+    float f[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) f[j] = d[u * fstride + src + min(j, nb - 1)];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      if (((miss >> j) & 1u) && f[j] == f[j]) {
+        v[j] = (double)f[j];
+        miss &= ~(1u << j);
+      }
+    }
+  };
   if (fill_mode == XV_FILL_FORWARD) {
-    for (int64_t u = t - 1; u >= 0; u--) {
-      const float f = d[u * fstride + src];
-      if (f == f) return (double)f;
-    }
-    for (int64_t u = t + 1; u < T; u++) {
-      const float f = d[u * fstride + src];
-      if (f == f) return (double)f;
-    }
-    return mn;
+    for (int64_t u = t - 1; u >= 0 && miss; u--) probe(u);
+    for (int64_t u = t + 1; u < T && miss; u++) probe(u);
+    return;
   }
-  for (int64_t dd = 1; dd < T; dd++) {
-    if (t - dd < 0 && t + dd >= T) break;
-    if (t - dd >= 0) {
-      const float f = d[(t - dd) * fstride + src];
-      if (f == f) return (double)f;
-    }
-    if (t + dd < T) {
-      const float f = d[(t + dd) * fstride + src];
-      if (f == f) return (double)f;
-    }
+  for (int64_t dd = 1; miss && (t - dd >= 0 || t + dd < T); dd++) {
+    if (t - dd >= 0) probe(t - dd);
+    if (miss && t + dd < T) probe(t + dd);
   }
-  return mn;
 }
 
-// Conversion and packing: one thread per padded pixel (t, y, x) reads the
-// pixel's bands (contiguous), fills missing samples, converts, and writes
-// one sample to each of the 3G channel planes (edge pixels replicate the
-// last real row/column; padding channels are zero or repeat the last band).
-// Validity bytes are written only when the cube has missing samples.
+// Conversion and packing.  A workgroup takes one padded row chunk (t, y,
+// x0 .. x0 + chunk - 1): it stages the real pixels of the source row (rows
+// past H replicate row H - 1) and each thread then converts one pixel's bands
+// and writes one sample to each of the 3G channel planes (columns past W
+// replicate column W - 1; padding channels are zero or repeat the last
+// band).  Missing samples are filled along time from global memory.
+// Validity bytes are written only when the cube has missing samples.  The
+// chunk is a multiple of the block size, so every chunk holds a real column.
+template <typename Tv>
 __global__ void __launch_bounds__(kThreads) pack_kernel(PackArgs a) {
+  Tv* stage = (Tv*)xv_stage_lds;
   __shared__ double smn[XV_MAX_BANDS], srg[XV_MAX_BANDS];
   __shared__ int sall[XV_MAX_BANDS];
-  const bool gaps = a.dtype == XV_F32 && *a.nan_total != 0u;
-  for (int i = threadIdx.x; i < a.bands; i += blockDim.x) {
+  const int bands = a.bands;
+  const bool gaps = sizeof(Tv) == 4 && *a.nan_total != 0u;
+  for (int i = threadIdx.x; i < bands; i += blockDim.x) {
     smn[i] = a.mn[i];
     srg[i] = a.mx[i] - a.mn[i];
     sall[i] = gaps && (int64_t)a.nan_count[i] == a.T * a.H * a.W;
   }
-  __syncthreads();
-  // workgroup -> (frame row, 256-pixel chunk); one uniform division
-  const int64_t plane = (int64_t)a.Hp * a.Wp;
-  const int xch = (a.Wp + kThreads - 1) / kThreads;
+  const int P = a.chunk_px;
+  const int xch = (a.Wp + P - 1) / P;
   const int64_t rowid = blockIdx.x / xch;
-  const int x = (int)(blockIdx.x - rowid * xch) * kThreads + threadIdx.x;
-  if (x >= a.Wp) return;
+  const int x0 = (int)(blockIdx.x - rowid * xch) * P;
   const int64_t t = rowid / a.Hp;
   const int y = (int)(rowid - t * a.Hp);
-  const int64_t o = (int64_t)y * a.Wp + x;
-  const int64_t ys = y < a.H ? y : a.H - 1, xs = x < a.W ? x : a.W - 1;
+  const int64_t ys = y < a.H ? y : a.H - 1;
+  const int nreal = min(P, (int)a.W - x0);
+  const Tv* d = (const Tv*)a.data;
+  const int64_t fstride = a.H * a.W * bands;
+  const int mis = stage_in(d + t * fstride + (ys * a.W + x0) * bands, stage, nreal * bands);
+  __syncthreads();
+  const int xi = threadIdx.x;
+  const int x = x0 + xi;
+  if (xi >= P || x >= a.Wp) return;
+  const int xr = min(xi, nreal - 1);
   const bool real = y < a.H && x < a.W;
-  const int64_t fstride = a.H * a.W * a.bands;
-  const int64_t pix = (ys * a.W + xs) * a.bands;
+  const Tv* px = stage + mis + xr * bands;
+  const int64_t pix = (ys * a.W + x0 + xr) * bands;
+  const int64_t plane = (int64_t)a.Hp * a.Wp;
+  const int64_t o = (int64_t)y * a.Wp + x;
   const double L = (double)((1 << a.bit_depth) - 1);
   uint16_t last = 0;
-  for (int b = 0; b < a.bands; b++) {
-    double v;
-    bool valid = true;
-    if (a.dtype == XV_U16) {
-      v = (double)((const uint16_t*)a.data)[t * fstride + pix + b];
-    } else {
-      const float* d = (const float*)a.data;
-      const float f = d[t * fstride + pix + b];
-      if (f == f) {
-        v = (double)f;
+  for (int b0 = 0; b0 < bands; b0 += 8) {
+    const int nb = min(8, bands - b0);
+    double v[8];
+    uint32_t miss = 0u;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      if (j >= nb) break;
+      const int b = b0 + j;
+      if constexpr (sizeof(Tv) == 2) {
+        v[j] = (double)px[b];
       } else {
-        valid = false;
-        v = sall[b] ? smn[b] : fill_missing(d, pix + b, fstride, t, a.T, a.fill_mode, smn[b]);
+        const float f = px[b];
+        const bool nan = f != f;
+        v[j] = nan ? smn[b] : (double)f;
+        // a band missing in every frame keeps its minimum without a search
+        miss |= (nan && !sall[b]) ? (1u << j) : 0u;
       }
     }
-    const uint16_t q = convert(v, smn[b], srg[b], L);
-    const int g = b / 3, c = b - 3 * (b / 3);
-    const int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
-    a.frames[off] = q;
-    if (gaps) a.vmask[off] = (uint8_t)(valid && real);
-    last = q;
+    uint32_t invalid = miss;
+    if constexpr (sizeof(Tv) == 4) {
+#pragma unroll
+      for (int j = 0; j < 8; j++)
+        if (j < nb && px[b0 + j] != px[b0 + j]) invalid |= 1u << j;
+      if (miss) fill_missing(d, pix + b0, nb, fstride, t, a.T, a.fill_mode, miss, v);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      if (j >= nb) break;
+      const int b = b0 + j;
+      const uint16_t q = convert(v[j], smn[b], srg[b], L);
+      const int g = b / 3, c = b - 3 * g;
+      const int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
+      a.frames[off] = q;
+      if (gaps) a.vmask[off] = (uint8_t)(!((invalid >> j) & 1u) && real);
+      last = q;
+    }
   }
   const int g = a.groups - 1;
-  for (int c = a.bands - 3 * g; c < 3; c++) {
+  for (int c = bands - 3 * g; c < 3; c++) {
     const int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
     a.frames[off] = a.pad_mode == XV_PAD_REPEAT ? last : (uint16_t)0;
     if (gaps) a.vmask[off] = 0;
   }
 }
 
+// Decoded frames back to the caller's dtype: x = mn + q * (mx - mn) / L in
+// binary64 (u16: rounded half up and clamped; f32: rounded to nearest).  A
+// workgroup takes one row chunk, reads each band's plane row coalesced,
+// assembles the pixel-major run in LDS and writes it with 16-byte stores.
+template <typename To>
 __global__ void __launch_bounds__(kThreads) denorm_kernel(DenormArgs a) {
+  To* stage = (To*)xv_stage_lds;
   __shared__ double smn[XV_MAX_BANDS], srg[XV_MAX_BANDS];
-  for (int i = threadIdx.x; i < a.bands; i += blockDim.x) {
+  const int bands = a.bands;
+  for (int i = threadIdx.x; i < bands; i += blockDim.x) {
     smn[i] = a.mn[i];
     srg[i] = a.mx[i] - a.mn[i];
   }
   __syncthreads();
-  const int xch = (int)((a.W + kThreads - 1) / kThreads);
+  const int P = a.chunk_px;
+  const int xch = (int)((a.W + P - 1) / P);
   const int64_t rowid = blockIdx.x / xch;
-  const int64_t x = (int64_t)(blockIdx.x - rowid * xch) * kThreads + threadIdx.x;
-  if (x >= a.W) return;
+  const int x0 = (int)(blockIdx.x - rowid * xch) * P;
   const int64_t t = rowid / a.H;
   const int64_t y = rowid - t * a.H;
-  const int64_t p = (t * a.H + y) * a.W + x;
+  const int nreal = min(P, (int)a.W - x0);
+  To* dst = (To*)a.out + ((t * a.H + y) * a.W + x0) * bands;
+  const int mis = stage_mis(dst);
   const int64_t plane = (int64_t)a.Hp * a.Wp;
   const double L = (double)((1 << a.bit_depth) - 1);
-  for (int b = 0; b < a.bands; b++) {
-    const int g = b / 3, c = b - 3 * g;
-    uint16_t q = a.recon[((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x];
-    double num = (double)q * srg[b];
-    double v = smn[b] + num / L;
-    if (a.out_dtype == XV_U16) {
-      double rr = floor(v + 0.5);
-      rr = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
-      ((uint16_t*)a.out)[p * a.bands + b] = (uint16_t)rr;
-    } else {
-      ((float*)a.out)[p * a.bands + b] = (float)v;
+  const int xi = threadIdx.x;
+  if (xi < nreal) {
+    const uint16_t* rrow = a.recon + y * a.Wp + x0 + xi;
+    for (int b0 = 0; b0 < bands; b0 += 8) {
+      uint16_t q[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int b = min(b0 + j, bands - 1);  // in-bounds loads, issued together
+        const int g = b / 3, c = b - 3 * g;
+        q[j] = rrow[((int64_t)(g * a.T + t) * 3 + c) * plane];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int b = b0 + j;
+        if (b >= bands) break;
+        const double num = (double)q[j] * srg[b];
+        const double v = smn[b] + num / L;
+        To o;
+        if constexpr (sizeof(To) == 2) {
+          double rr = floor(v + 0.5);
+          rr = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
+          o = (To)rr;
+        } else {
+          o = (To)v;
+        }
+        stage[mis + xi * bands + b] = o;
+      }
     }
   }
+  __syncthreads();
+  stage_out(stage, dst, nreal * bands, mis);
 }
 
-// Physical squared error: thread per pixel x of a frame row, rows taken
-// grid-stride by workgroup; per-band sums for a chunk of up to 8 bands live in
-// registers.  Each block reduces its sums with a fixed LDS tree into
-// partial[block][band]; the final sum over blocks has a fixed order too, so
-// the result is deterministic.
+// Physical squared error.  Workgroups take row chunks grid-stride, stage the
+// original samples, and each thread accumulates per-band sums of its pixel
+// in registers (8 bands per pass).  Each block reduces with a fixed LDS tree
+// into partial[block][band]; the final sum over blocks has a fixed order
+// too, so the result is deterministic.
+template <typename Tv>
 __global__ void __launch_bounds__(kThreads) phys_sse_kernel(PhysArgs a) {
+  Tv* stage = (Tv*)xv_stage_lds;
   __shared__ double sred[kThreads];
+  __shared__ double smn[XV_MAX_BANDS], srg[XV_MAX_BANDS];
   const int bands = a.bands;
+  for (int i = threadIdx.x; i < bands; i += blockDim.x) {
+    smn[i] = a.mn[i];
+    srg[i] = a.mx[i] - a.mn[i];
+  }
   const int64_t plane = (int64_t)a.Hp * a.Wp;
   const double L = (double)((1 << a.bit_depth) - 1);
-  const int xch = (int)((a.W + kThreads - 1) / kThreads);
-  const int64_t nrows = a.T * a.H * xch;
+  const int P = a.chunk_px;
+  const int xch = (int)((a.W + P - 1) / P);
+  const int64_t units = a.T * a.H * xch;
+  const Tv* orig = (const Tv*)a.orig;
+  const int xi = threadIdx.x;
   for (int b0 = 0; b0 < bands; b0 += 8) {
     const int nb = min(8, bands - b0);
     double acc[8];
 #pragma unroll
     for (int j = 0; j < 8; j++) acc[j] = 0.0;
-    for (int64_t rid = blockIdx.x; rid < nrows; rid += gridDim.x) {
-      const int64_t row = rid / xch;
-      const int64_t x = (rid - row * xch) * kThreads + threadIdx.x;
-      if (x >= a.W) continue;
-      const int64_t t = row / a.H, y = row - (row / a.H) * a.H;
-      const int64_t e0 = ((t * a.H + y) * a.W + x) * bands + b0;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+      const int64_t row = u / xch;
+      const int x0 = (int)(u - row * xch) * P;
+      const int64_t t = row / a.H, y = row - t * a.H;
+      const int nreal = min(P, (int)a.W - x0);
+      __syncthreads();  // the previous chunk has been read
+      const int mis = stage_in(orig + (row * a.W + x0) * bands, stage, nreal * bands);
+      __syncthreads();
+      if (xi < nreal) {
+        const uint16_t* rrow = a.recon + y * a.Wp + x0 + xi;
+        uint16_t q[8];
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        if (j >= nb) break;
-        const int b = b0 + j;
-        const double xv = load_sample(a.orig, a.dtype, e0 + j);
-        if (xv != xv) continue;
-        const int g = b / 3, c = b - 3 * g;
-        const uint16_t q = a.recon[((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x];
-        const double num = (double)q * (a.mx[b] - a.mn[b]);
-        const double v = a.mn[b] + num / L;
-        double xh;
-        if (a.dtype == XV_U16) {
-          const double rr = floor(v + 0.5);
-          xh = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
-        } else {
-          xh = (double)(float)v;
+        for (int j = 0; j < 8; j++) {
+          const int b = min(b0 + j, bands - 1);
+          const int g = b / 3, c = b - 3 * g;
+          q[j] = rrow[((int64_t)(g * a.T + t) * 3 + c) * plane];
         }
-        acc[j] = acc[j] + (xv - xh) * (xv - xh);
+        const Tv* px = stage + mis + xi * bands;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const int b = b0 + j;
+          if (b >= bands) break;
+          const double xv = (double)px[b];
+          const double num = (double)q[j] * srg[b];
+          const double v = smn[b] + num / L;
+          double xh;
+          if constexpr (sizeof(Tv) == 2) {
+            const double rr = floor(v + 0.5);
+            xh = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
+          } else {
+            xh = (double)(float)v;
+          }
+          const double e = xv - xh;
+          acc[j] = (xv == xv) ? acc[j] + e * e : acc[j];
+        }
       }
     }
     for (int j = 0; j < nb; j++) {
@@ -409,40 +593,86 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
-  // grid: enough blocks to fill the GPU several times over, each looping
-  hipError_t e;
-  if ((e = launch_fill_u32(a.minkey, 0xffffffffu, a.bands, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(a.maxkey, 0u, a.bands, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(a.nan_count, 0u, a.bands, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(a.nan_total, 0u, 1, s)) != hipSuccess) return e;
-  int blocks = grid_for(a.npix, kThreads * 4);
-  blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
-  stats_kernel<<<blocks, kThreads, 0, s>>>(a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  stats_finalize_kernel<<<1, 64, 0, s>>>(a);
+int chunk_px_for(int64_t width, int bands) {
+  int p = 64;
+  while (p < kThreads && p < width) p <<= 1;
+  while (p > 64 && p * bands > kStage) p >>= 1;
+  return p;
+}
+
+namespace {
+int gcd_int(int x, int y) {
+  while (y) {
+    const int r = x % y;
+    x = y;
+    y = r;
+  }
+  return x;
+}
+}  // namespace
+
+int stats_blocks(const StatsArgs& a) {
+  const int V = a.vec ? (a.dtype == XV_U16 ? 8 : 4) : 1;
+  const int64_t nvec = a.npix * a.bands / V;
+  int64_t b = (nvec + kThreads * 8 - 1) / (kThreads * 8);  // about 8 loads per thread
+  b = b < 1 ? 1 : (b > kStatsMaxBlocks ? kStatsMaxBlocks : b);
+  // the grid stride in elements must be a multiple of the band count
+  const int m = a.bands / gcd_int(a.bands, kThreads * V);
+  b = b / m * m;
+  if (b < m) b = m;
+  return (int)b;
+}
+
+hipError_t launch_stats(const StatsArgs& in, hipStream_t s) {
+  StatsArgs a = in;
+  a.nblocks = stats_blocks(a);
+  if (a.dtype == XV_U16) {
+    if (a.vec)
+      stats_kernel<uint16_t, 8><<<a.nblocks, kThreads, 0, s>>>(a);
+    else
+      stats_kernel<uint16_t, 1><<<a.nblocks, kThreads, 0, s>>>(a);
+  } else {
+    if (a.vec)
+      stats_kernel<float, 4><<<a.nblocks, kThreads, 0, s>>>(a);
+    else
+      stats_kernel<float, 1><<<a.nblocks, kThreads, 0, s>>>(a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  stats_finalize_kernel<<<a.bands, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
-  const int64_t blocks = a.T * a.Hp * (int64_t)((a.Wp + kThreads - 1) / kThreads);
-  pack_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(a);
+  const int P = a.chunk_px;
+  const int64_t blocks = a.T * a.Hp * (int64_t)((a.Wp + P - 1) / P);
+  if (a.dtype == XV_U16)
+    pack_kernel<uint16_t><<<(unsigned)blocks, P, stage_bytes(P, a.bands, 2), s>>>(a);
+  else
+    pack_kernel<float><<<(unsigned)blocks, P, stage_bytes(P, a.bands, 4), s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_denorm(const DenormArgs& a, hipStream_t s) {
-  const int64_t blocks = a.T * a.H * ((a.W + kThreads - 1) / kThreads);
-  denorm_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(a);
+  const int P = a.chunk_px;
+  const int64_t blocks = a.T * a.H * ((a.W + P - 1) / P);
+  if (a.out_dtype == XV_U16)
+    denorm_kernel<uint16_t><<<(unsigned)blocks, P, stage_bytes(P, a.bands, 2), s>>>(a);
+  else
+    denorm_kernel<float><<<(unsigned)blocks, P, stage_bytes(P, a.bands, 4), s>>>(a);
   return hipGetLastError();
 }
 
 int phys_blocks(int64_t npix) {
-  int64_t b = (npix + kThreads * 4 - 1) / (kThreads * 4);
-  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+  int64_t b = (npix + kThreads * 16 - 1) / (kThreads * 16);
+  return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
 }
 
 hipError_t launch_phys_sse(const PhysArgs& a, hipStream_t s) {
-  phys_sse_kernel<<<a.nblocks, kThreads, 0, s>>>(a);
+  if (a.dtype == XV_U16)
+    phys_sse_kernel<uint16_t><<<a.nblocks, kThreads, stage_bytes(a.chunk_px, a.bands, 2), s>>>(a);
+  else
+    phys_sse_kernel<float><<<a.nblocks, kThreads, stage_bytes(a.chunk_px, a.bands, 4), s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   phys_reduce_kernel<<<a.bands, kThreads, 0, s>>>(a);

@@ -41,8 +41,7 @@ struct xv_encoded {
   int8_t* mvs;
   uint32_t* cbits;
   uint32_t* mbits;
-  uint32_t* minkey;
-  uint32_t* maxkey;
+  uint32_t* stats_part;  // [kStatsMaxBlocks][3][bands] per-block statistics
   uint32_t* nan_count;
   uint32_t* nan_total;
   // metric span, contiguous (one copy to the host): mn, mx, phys [bands]
@@ -218,7 +217,7 @@ EncLayout enc_layout(const xv_encoded* e) {
   L.o_mv = k.take<int8_t>((size_t)nblk * 2);
   L.o_cb = k.take<uint32_t>((size_t)nblk * 3);
   L.o_mb = k.take<uint32_t>((size_t)nblk);
-  L.o_keys = k.take<uint32_t>((size_t)3 * bands + 1);
+  L.o_keys = k.take<uint32_t>((size_t)bands + 1 + (size_t)kStatsMaxBlocks * 3 * bands);
   L.span_words = (size_t)3 * bands + bands + 3 * G + 2 * G;
   L.o_span = k.take<uint64_t>(L.span_words);
   L.phys_nb = phys_blocks(T * e->H * e->W * bands);
@@ -278,10 +277,9 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   e->mvs = (int8_t*)(kb + o_mv);
   e->cbits = (uint32_t*)(kb + o_cb);
   e->mbits = (uint32_t*)(kb + o_mb);
-  e->minkey = (uint32_t*)(kb + o_keys);
-  e->maxkey = e->minkey + bands;
-  e->nan_count = e->maxkey + bands;
+  e->nan_count = (uint32_t*)(kb + o_keys);
   e->nan_total = e->nan_count + bands;
+  e->stats_part = e->nan_total + 1;
   e->span = kb + o_span;
   e->span_bytes = span_words * 8;
   e->mn = (double*)e->span;
@@ -297,20 +295,21 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   e->vmask = in->dtype == XV_F32 ? (uint8_t*)(wb + o_vm) : nullptr;
   *out = e;
 
-  XV_HIP(launch_fill_u64(e->sse, 0ull, 3 * G, s), "clear accumulators");
-  XV_HIP(launch_fill_u64(e->bits, 0ull, 2 * G, s), "clear accumulators");
+  // sse [3G] and bits [2G] are adjacent in the metric span
+  XV_HIP(launch_fill_u64(e->sse, 0ull, 5 * G, s), "clear accumulators");
   const double elb = in->dtype == XV_U16 ? 2.0 : 4.0;
   const double in_bytes = (double)T * e->H * e->W * bands * elb;
   {
-    StatsArgs a{in->data, in->dtype, T * e->H * e->W, (int32_t)bands, e->minkey, e->maxkey,
-                e->nan_count, e->nan_total, e->mn, e->mx, e->nvalid};
+    StatsArgs a{in->data, in->dtype, ((uintptr_t)in->data & 15) == 0, T * e->H * e->W,
+                (int32_t)bands, 0, e->stats_part, e->nan_count, e->nan_total, e->mn, e->mx,
+                e->nvalid};
     ProfScope ps(XV_K_STATS, s, in_bytes);
     XV_HIP(launch_stats(a, s), "stats kernel");
   }
   {
     PackArgs a{in->data, in->dtype, T, e->H, e->W, (int32_t)bands, e->G, e->Hp, e->Wp,
                p->bit_depth, p->pad_mode, p->fill_mode, e->mn, e->mx, e->nan_total,
-               e->nan_count, e->frames, e->vmask};
+               e->nan_count, e->frames, e->vmask, chunk_px_for(e->Wp, (int)bands)};
     ProfScope ps(XV_K_PACK, s, in_bytes + (double)nframes * 3 * plane * 2.0);
     XV_HIP(launch_pack(a, s), "pack kernel");
   }
@@ -499,7 +498,7 @@ int decode_steps(std::vector<DecSrc> base, hipStream_t s) {
 
 int decode_finish(const xv_encoded* e, const xv_cube* out, DecodeBuf& db, hipStream_t s) {
   DenormArgs a{db.recon, e->T, e->H, e->W, (int32_t)e->bands, e->Hp, e->Wp, e->p.bit_depth,
-               e->mn, e->mx, out->dtype, out->data};
+               e->mn, e->mx, out->dtype, out->data, chunk_px_for(e->W, (int)e->bands)};
   const double ob = out->dtype == XV_U16 ? 2.0 : 4.0;
   {
     ProfScope ps(XV_K_DENORM, s, (double)e->T * e->H * e->W * e->bands * (2.0 + ob));
@@ -649,7 +648,8 @@ int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m, void*
       return fail(XV_EINVAL, "original cube differs from the encoded one");
     if (e->recon) {
       PhysArgs a{orig->data, orig->dtype, e->recon, e->T, e->H, e->W, bands, e->Hp, e->Wp,
-                 e->p.bit_depth, e->mn, e->mx, e->phys_partial, e->phys, e->phys_nb};
+                 e->p.bit_depth, e->mn, e->mx, e->phys_partial, e->phys, e->phys_nb,
+                 chunk_px_for(e->W, bands)};
       const double ib = orig->dtype == XV_U16 ? 2.0 : 4.0;
       ProfScope ps(XV_K_METRICS, s, (double)e->T * e->H * e->W * bands * (ib + 2.0));
       XV_HIP(launch_phys_sse(a, s), "physical error kernel");

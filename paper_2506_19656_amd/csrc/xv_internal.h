@@ -150,16 +150,19 @@ constexpr int kQf[6] = {26214, 23302, 20560, 18396, 16384, 14564};
 struct StatsArgs {
   const void* data;
   int32_t dtype;
+  int32_t vec;         // 1: 16-byte loads (data 16-byte aligned); 0: element loads
   int64_t npix;        // T*H*W
   int32_t bands;
-  uint32_t* minkey;    // [bands] order-preserving keys
-  uint32_t* maxkey;    // [bands]
+  int32_t nblocks;     // grid; nblocks * threads * (elements per load) % bands == 0
+  uint32_t* part;      // [nblocks][3][bands] min key, max key, missing count
   uint32_t* nan_count; // [bands]
   uint32_t* nan_total; // [1]
   double* mn;          // [bands]
   double* mx;          // [bands]
   unsigned long long* n_valid;  // [bands]
 };
+constexpr int kStatsMaxBlocks = 2048;
+int stats_blocks(const StatsArgs& a);
 
 struct PackArgs {
   const void* data;
@@ -175,7 +178,11 @@ struct PackArgs {
   const uint32_t* nan_count;  // [bands]
   uint16_t* frames;    // [G][T][3][Hp][Wp]
   uint8_t* vmask;      // [G][T][3][Hp][Wp] or null
+  int32_t chunk_px;    // pixels of one row chunk (chunk_px_for)
 };
+// Pixels per row chunk of the row-staged kernels: a power of two in 64..256,
+// at least the row width when that is below 256, with chunk * bands <= 4096.
+int chunk_px_for(int64_t width, int bands);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n,
@@ -208,6 +215,7 @@ struct DenormArgs {
   const double* mx;
   int32_t out_dtype;
   void* out;               // [T][H][W][bands]
+  int32_t chunk_px;
 };
 hipError_t launch_denorm(const DenormArgs& a, hipStream_t s);
 
@@ -222,6 +230,7 @@ struct PhysArgs {
   double* partial;         // [nblocks][bands]
   double* out;             // [bands]
   int32_t nblocks;
+  int32_t chunk_px;
 };
 int phys_blocks(int64_t npix);
 hipError_t launch_phys_sse(const PhysArgs& a, hipStream_t s);
