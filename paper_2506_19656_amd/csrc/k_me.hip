@@ -54,6 +54,58 @@ __host__ __device__ inline size_t me_lds_bytes(int N, const MeShape& s, int nb) 
   return win + cur + (size_t)nb * 8;
 }
 
+// Global-memory views of the job's pointers (they are stored as generic
+// pointers in the job table; these casts let the loads be global loads that
+// only count against the vector-memory counter).
+typedef const __attribute__((address_space(1))) uint16_t gu16;
+typedef const __attribute__((address_space(1))) uint32_t gu32;
+
+constexpr int kBatch = 8;  // staging loads in flight per thread
+
+// Stages the reference windows of one workgroup: nrows = nch * (N + 2R) rows
+// of wpairs u16 pairs starting at column gx0, zero outside the picture.
+// Thread t covers pair column t % wpairs of rows t / wpairs + k * rpp; loads
+// are issued kBatch at a time from clamped (always in-bounds) addresses and
+// masked afterwards.  With an even gx0 a pair is wholly inside or wholly
+// outside the picture (Wp is even), so one dword load serves it.
+template <bool kEven>
+__device__ inline void stage_window(uint32_t* win, const uint16_t* ref, const MeShape& s,
+                                    int nrows, int wpairs, int gx0, int gy0, int Hp, int Wp) {
+  const size_t plane = (size_t)Hp * Wp;
+  const int rpp = max(1, (int)blockDim.x / wpairs);  // rows per pass
+  const int r0 = threadIdx.x / wpairs;
+  if (r0 >= rpp) return;
+  for (int m = threadIdx.x - r0 * wpairs; m < wpairs; m += (int)blockDim.x) {
+    const int gx = gx0 + 2 * m;
+    const bool in0 = gx >= 0 && gx < Wp, in1 = gx + 1 >= 0 && gx + 1 < Wp;
+    const int cx0 = min(max(gx, 0), Wp - 1), cx1 = min(max(gx + 1, 0), Wp - 1);
+    const int cxe = min(max(gx, 0), Wp - 2);
+    for (int rb = r0; rb < nrows; rb += kBatch * rpp) {
+      uint32_t v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; u++) {
+        const int rr = min(rb + u * rpp, nrows - 1);
+        const int ch = rr >= 2 * s.rows ? 2 : (rr >= s.rows ? 1 : 0);
+        const int gy = gy0 + (rr - ch * s.rows);
+        const bool yin = gy >= 0 && gy < Hp;
+        gu16* rp = (gu16*)(ref + ch * plane + (size_t)min(max(gy, 0), Hp - 1) * Wp);
+        if constexpr (kEven) {
+          const uint32_t w = *(gu32*)(rp + cxe);
+          v[u] = (yin && in0) ? w : 0u;
+        } else {
+          const uint32_t lo = rp[cx0], hi = rp[cx1];
+          v[u] = ((yin && in0) ? lo : 0u) | (((yin && in1) ? hi : 0u) << 16);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; u++) {
+        const int rr = rb + u * rpp;
+        if (rr < nrows) win[rr * s.pitch + m] = v[u];
+      }
+    }
+  }
+}
+
 template <int N, int KX>
 __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int nb) {
   extern __shared__ __align__(16) uint32_t lds[];
@@ -74,50 +126,38 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
   unsigned long long* best = (unsigned long long*)(curt + 3 * N * (nb * N / 2));
   const int cpitch = nb * N / 2;
 
-  // Stage reference windows (zero outside the picture) and current blocks.
-  // Thread t covers dword column t % wpairs of rows t / wpairs + k * rpp.
+  // Stage the reference windows and the current blocks, kBatch loads in
+  // flight per thread.
   const int gy0 = by * N - R, gx0 = bx0 * N - R;
   const int wpairs = s.wc / 2;
   const size_t plane = (size_t)Hp * Wp;
   const int nrows = nch * s.rows;
-  {
-    const int rpp = max(1, (int)blockDim.x / wpairs);  // rows per pass
-    const int r0 = threadIdx.x / wpairs;
-    for (int m = threadIdx.x - r0 * wpairs; m < wpairs; m += (int)blockDim.x) {
-      if (r0 >= rpp) break;
-      const int gx = gx0 + 2 * m;
-      const bool even = (gx0 & 1) == 0;
-      const bool xin = gx >= 0 && gx + 1 < Wp;
-      for (int rr = r0; rr < nrows; rr += rpp) {
-        const int ch = rr >= 2 * s.rows ? 2 : (rr >= s.rows ? 1 : 0);
-        const int row = rr - ch * s.rows;
-        const int gy = gy0 + row;
-        uint32_t v = 0;
-        if (gy >= 0 && gy < Hp) {
-          const uint16_t* rp = job.ref + ch * plane + (size_t)gy * Wp;
-          if (even) {
-            if (xin) v = *(const uint32_t*)(rp + gx);
-          } else {
-            const uint32_t v0 = (gx >= 0 && gx < Wp) ? rp[gx] : 0u;
-            const uint32_t v1 = (gx + 1 >= 0 && gx + 1 < Wp) ? rp[gx + 1] : 0u;
-            v = v0 | (v1 << 16);
-          }
-        }
-        win[rr * s.pitch + m] = v;
-      }
-    }
-  }
+  if ((gx0 & 1) == 0)
+    stage_window<true>(win, job.ref, s, nrows, wpairs, gx0, gy0, Hp, Wp);
+  else
+    stage_window<false>(win, job.ref, s, nrows, wpairs, gx0, gy0, Hp, Wp);
   {
     const int cw = nbv * N / 2;  // dwords per current row
     const int rpp = max(1, (int)blockDim.x / cw);
     const int r0 = threadIdx.x / cw;
+    const int crows = nch * N;
     for (int m = threadIdx.x - r0 * cw; m < cw; m += (int)blockDim.x) {
       if (r0 >= rpp) break;
-      for (int rr = r0; rr < nch * N; rr += rpp) {
-        const int ch = rr / N, row = rr - (rr / N) * N;
-        const uint32_t* cp = (const uint32_t*)(job.cur + ch * plane + (size_t)(by * N + row) * Wp +
-                                               bx0 * N);
-        curt[rr * cpitch + m] = cp[m];
+      for (int rb = r0; rb < crows; rb += kBatch * rpp) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; u++) {
+          const int rr = min(rb + u * rpp, crows - 1);
+          const int ch = rr / N, row = rr - (rr / N) * N;
+          const gu32* cp = (const gu32*)(job.cur + ch * plane + (size_t)(by * N + row) * Wp +
+                                         bx0 * N);
+          v[u] = cp[m];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; u++) {
+          const int rr = rb + u * rpp;
+          if (rr < crows) curt[rr * cpitch + m] = v[u];
+        }
       }
     }
   }
