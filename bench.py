@@ -205,13 +205,13 @@ def main():
         if cached is not None and f"N{N}" in cached:
             g = cached[f"N{N}"]
             xv.set_me_geometry(N, wl.search_range, g["blocks_per_wg"], g["cands_per_lane"],
-                               g["threads"])
+                               g["threads"], g.get("rows_per_lane", 0))
             tuning[f"N{N}"] = dict(g, tuned=True, from_file=True)
         elif not args.no_tune:
             print(f"[bench] tuning motion search N={N}", file=sys.stderr, flush=True)
-            t = xv.autotune_me(cube, xv.Params(bit_depth=wl.bit_depth, qp=27, block=N,
-                                               search_range=wl.search_range, gop=wl.gop,
-                                               pad_mode=wl.pad_mode, fill_mode=wl.fill_mode))
+            # tuned on the first P step of exactly the batch the timed steps launch
+            pn = [p for p in params if p.block == N]
+            t = xv.autotune_me_batch([cube] * len(pn), pn)
             tuning[f"N{N}"] = dict(t, tuned=True)
         else:
             tuning[f"N{N}"] = dict(xv.get_me_geometry(N, wl.search_range, -(-wl.W // N)),

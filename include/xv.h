@@ -252,13 +252,14 @@ int xv_server_destroy(xv_server* sv);
 
 /* Geometry of the motion-search kernel for one (N, R): blocks per
  * workgroup along x, candidates per lane along x (even), threads per
- * workgroup (multiple of 64, <= 512).  Zero fields take the default; NULL
- * or all fields zero restores the default for (block, search_range). */
+ * workgroup (multiple of 64, <= 512), candidate rows per lane (1 or 2).
+ * Zero fields take the default; NULL or all fields zero restores the
+ * default for (block, search_range). */
 typedef struct {
   int32_t blocks_per_wg;
   int32_t cands_per_lane;
   int32_t threads;
-  int32_t reserved;
+  int32_t rows_per_lane;
 } xv_me_geometry;
 
 int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g);
@@ -276,6 +277,12 @@ int xv_get_me_geometry(int block, int search_range, int width_blocks, xv_me_geom
  * XV_EHIP. */
 int xv_autotune_me(const xv_cube* in, const xv_params* p, void* hip_stream, int max_candidates,
                    xv_me_geometry* out, double* best_ms);
+/* The same over the first P-picture step of a batch coded together, as
+ * xv_encode_batch would launch it: n cubes with their params, which must
+ * all share block and search_range.  Tuning on the batch that will run
+ * accounts for its grid size, which changes the best geometry. */
+int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, void* hip_stream,
+                         int max_candidates, xv_me_geometry* out, double* best_ms);
 
 /* ---- Kernel timing (HIP events on the launch stream) ------------------ */
 

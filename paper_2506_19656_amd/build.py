@@ -33,7 +33,7 @@ def hipcc() -> str:
 
 
 def flags() -> list:
-    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",
+    return ["-O3", "-std=c++20", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",
             "-fno-fast-math", "-fno-strict-aliasing", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
 

@@ -10,11 +10,12 @@
 //
 // Mapping onto gfx950:
 //  * a workgroup owns a horizontal run of `nb` blocks; the union of their
-//    search windows, (N + 2R) rows x (nb N + G KX) columns per channel, is
-//    staged in LDS as packed u16 pairs with an odd dword pitch, so lanes that
-//    differ in dy hit different banks;
-//  * a lane evaluates KX consecutive candidates dx at one dy ("item") and
-//    reuses every reference dword it loads for all KX of them;
+//    search windows, (N + 2R + 1) rows x (nb N + G KX) columns per channel,
+//    is staged in LDS as packed u16 pairs with an odd dword pitch, so lanes
+//    that differ in dy hit different banks;
+//  * a lane evaluates KX consecutive candidates dx at two consecutive rows
+//    dy ("item") and reuses every reference dword it loads, and realigns,
+//    for all 2 KX of them;
 //  * v_sad_u16 adds |a.lo-b.lo| + |a.hi-b.hi| in one instruction (two SAD
 //    terms per lane-op); odd candidate offsets use pairs realigned with
 //    alignbit;
@@ -29,29 +30,48 @@ namespace xv {
 
 namespace {
 
+// An item is (block, group of KX candidate columns, ROWS consecutive
+// candidate rows dy0 .. dy0 + ROWS - 1).  With two rows a lane sums both
+// rows' SADs from one pass over the N + 1 window rows they share.
 struct MeShape {
-  int R, G, span, ipb;  // span = 2R+1, ipb = items per block
-  int wc, pitch;        // window columns (u16) and pitch (dwords)
-  int rows;             // N + 2R
+  int R, G, span, dyp, ipb;  // span = 2R+1; dyp = row groups; ipb = items per block
+  int wc, pitch;             // window columns (u16) and pitch (dwords)
+  int rows;                  // staged rows: N + 2R, plus one with two rows per item
+                             // (it only serves dy = 2R+1, outside the range)
 };
 
-__host__ __device__ inline MeShape me_shape(int N, int R, int kx, int nb) {
+__host__ __device__ inline MeShape me_shape(int N, int R, int kx, int nb, int nrow) {
   MeShape s;
   s.R = R;
   s.span = 2 * R + 1;
   s.G = (s.span + kx - 1) / kx;
-  s.ipb = s.span * s.G;
+  s.dyp = nrow == 2 ? R + 1 : s.span;
+  s.ipb = s.dyp * s.G;
   s.wc = nb * N + s.G * kx;
   s.pitch = s.wc / 2;
   if ((s.pitch & 1) == 0) s.pitch += 1;
-  s.rows = N + 2 * R;
+  s.rows = N + 2 * R + (nrow == 2 ? 1 : 0);
   return s;
 }
 
+// LDS layout of a workgroup, in dwords: the windows [3][rows][pitch], the
+// current blocks [3][N][nb N / 2] from a 16-byte boundary, then the nb 64-bit
+// argmin keys from an 8-byte boundary (rows * pitch may be odd).
+struct MeLds {
+  size_t cur, best, bytes;
+};
+
+__host__ __device__ inline MeLds me_lds_layout(int N, const MeShape& s, int nb) {
+  MeLds l;
+  const size_t win = (size_t)3 * s.rows * s.pitch;
+  l.cur = (win + 3) & ~(size_t)3;
+  l.best = (l.cur + (size_t)3 * N * (nb * N / 2) + 1) & ~(size_t)1;
+  l.bytes = l.best * 4 + (size_t)nb * 8;
+  return l;
+}
+
 __host__ __device__ inline size_t me_lds_bytes(int N, const MeShape& s, int nb) {
-  size_t win = (size_t)3 * s.rows * s.pitch * 4;
-  size_t cur = (size_t)3 * N * (nb * N / 2) * 4;
-  return win + cur + (size_t)nb * 8;
+  return me_lds_layout(N, s, nb).bytes;
 }
 
 // Global-memory views of the job's pointers (they are stored as generic
@@ -106,7 +126,7 @@ __device__ inline void stage_window(uint32_t* win, const uint16_t* ref, const Me
   }
 }
 
-template <int N, int KX>
+template <int N, int KX, int ROWS>
 __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int nb) {
   extern __shared__ __align__(16) uint32_t lds[];
   int tl;
@@ -119,11 +139,12 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
   const int bx0 = (tl - by * runs) * nb;
   const int nbv = min(nb, Wb - bx0);
   const int nch = job.nch;
-  const MeShape s = me_shape(N, R, KX, nb);
+  const MeShape s = me_shape(N, R, KX, nb, ROWS);
 
+  const MeLds ll = me_lds_layout(N, s, nb);
   uint32_t* win = lds;
-  uint32_t* curt = lds + 3 * s.rows * s.pitch;
-  unsigned long long* best = (unsigned long long*)(curt + 3 * N * (nb * N / 2));
+  uint32_t* curt = lds + ll.cur;
+  unsigned long long* best = (unsigned long long*)(lds + ll.best);
   const int cpitch = nb * N / 2;
 
   // Stage the reference windows and the current blocks, kBatch loads in
@@ -165,54 +186,96 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
   __syncthreads();
 
   constexpr int ND = (KX + N) / 2;  // reference dwords per row and item
+  constexpr int NC = N / 2;         // current dwords per row
   const int items = nbv * s.ipb;
   const int keyshift_sad = R <= 32 ? 21 : 23;
   const int keyshift_l1 = R <= 32 ? 13 : 15;
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
     const int b = it / s.ipb;
     const int rem = it - b * s.ipb;
-    const int gxi = rem / s.span;
-    const int dy = rem - gxi * s.span;
-    uint32_t acc[KX];
+    const int gxi = rem / s.dyp;
+    const int dy0 = ROWS * (rem - gxi * s.dyp);
+    uint32_t acc0[KX], acc1[KX];
 #pragma unroll
-    for (int k = 0; k < KX; k++) acc[k] = 0;
+    for (int k = 0; k < KX; k++) {
+      acc0[k] = 0;
+      acc1[k] = 0;
+    }
     for (int ch = 0; ch < nch; ch++) {
-      const uint32_t* wbase = win + (ch * s.rows + dy) * s.pitch + (b * N + gxi * KX) / 2;
-      const uint32_t* cbase = curt + ch * N * cpitch + b * (N / 2);
-#pragma unroll 2
-      for (int i = 0; i < N; i++) {
-        uint32_t D[ND], O[ND - 1], C[N / 2];
-        const uint32_t* wr = wbase + i * s.pitch;
+      const uint32_t* wbase = win + (ch * s.rows + dy0) * s.pitch + (b * N + gxi * KX) / 2;
+      const uint32_t* cbase = curt + ch * N * cpitch + b * NC;
+      uint32_t D[ND], O[ND - 1], CA[NC], CB[NC];
+      // window row w serves candidate row dy0 with current row w and
+      // candidate row dy0 + 1 with current row w - 1
+      auto load_win = [&](int w) {
+        const uint32_t* wr = wbase + w * s.pitch;
 #pragma unroll
         for (int q = 0; q < ND; q++) D[q] = wr[q];
 #pragma unroll
         for (int q = 0; q < ND - 1; q++) O[q] = __builtin_amdgcn_alignbit(D[q + 1], D[q], 16);
+      };
+      auto load_cur = [&](int w, uint32_t(&C)[NC]) {
 #pragma unroll
-        for (int m = 0; m < N / 2; m++) C[m] = cbase[i * cpitch + m];
+        for (int m = 0; m < NC; m++) C[m] = cbase[w * cpitch + m];
+      };
+      auto sad = [&](uint32_t(&acc)[KX], const uint32_t(&C)[NC]) {
 #pragma unroll
         for (int k = 0; k < KX; k++) {
 #pragma unroll
-          for (int m = 0; m < N / 2; m++) {
+          for (int m = 0; m < NC; m++) {
             const uint32_t pr = (k & 1) ? O[(k >> 1) + m] : D[(k >> 1) + m];
             acc[k] = __builtin_amdgcn_sad_u16(pr, C[m], acc[k]);
           }
         }
+      };
+      if constexpr (ROWS == 1) {
+#pragma unroll 2
+        for (int w = 0; w < N; w++) {
+          load_win(w);
+          load_cur(w, CA);
+          sad(acc0, CA);
+        }
+        continue;
       }
+      load_win(0);
+      load_cur(0, CA);
+      sad(acc0, CA);
+      for (int w = 1; w + 1 < N; w += 2) {
+        load_win(w);
+        load_cur(w, CB);
+        sad(acc0, CB);
+        sad(acc1, CA);
+        load_win(w + 1);
+        load_cur(w + 1, CA);
+        sad(acc0, CA);
+        sad(acc1, CB);
+      }
+      load_win(N - 1);
+      load_cur(N - 1, CB);
+      sad(acc0, CB);
+      sad(acc1, CA);
+      load_win(N);
+      sad(acc1, CB);
     }
     const int x0 = (bx0 + b) * N, y0 = by * N;
-    const int dyv = dy - R;
     unsigned long long kbest = ~0ull;
-    const bool yok = (y0 + dyv >= 0) && (y0 + dyv + N <= Hp);
 #pragma unroll
-    for (int k = 0; k < KX; k++) {
-      const int cx = gxi * KX + k;
-      const int dxv = cx - R;
-      const bool ok = yok && cx < s.span && (x0 + dxv >= 0) && (x0 + dxv + N <= Wp);
-      const unsigned long long l1 = (unsigned long long)(abs(dxv) + abs(dyv));
-      const unsigned long long key = ((unsigned long long)acc[k] << keyshift_sad) |
-                                     (l1 << keyshift_l1) |
-                                     (unsigned long long)(dy * s.span + cx);
-      kbest = ok && key < kbest ? key : kbest;
+    for (int h = 0; h < ROWS; h++) {
+      const int dy = dy0 + h;
+      const int dyv = dy - R;
+      const bool yok = dy < s.span && (y0 + dyv >= 0) && (y0 + dyv + N <= Hp);
+#pragma unroll
+      for (int k = 0; k < KX; k++) {
+        const int cx = gxi * KX + k;
+        const int dxv = cx - R;
+        const bool ok = yok && cx < s.span && (x0 + dxv >= 0) && (x0 + dxv + N <= Wp);
+        const unsigned long long l1 = (unsigned long long)(abs(dxv) + abs(dyv));
+        const uint32_t sv = h ? acc1[k] : acc0[k];
+        const unsigned long long key = ((unsigned long long)sv << keyshift_sad) |
+                                       (l1 << keyshift_l1) |
+                                       (unsigned long long)(dy * s.span + cx);
+        kbest = ok && key < kbest ? key : kbest;
+      }
     }
     if (kbest != ~0ull) atomicMin(&best[b], kbest);
   }
@@ -227,91 +290,94 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
   }
 }
 
-template <int N, int KX>
+template <int N, int KX, int ROWS>
 hipError_t launch_me_t(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
-  const MeShape sh = me_shape(N, R, KX, g.nb);
+  const MeShape sh = me_shape(N, R, KX, g.nb, ROWS);
   const size_t lds = me_lds_bytes(N, sh, g.nb);
   static bool attr_set = false;
   if (!attr_set && lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)me_kernel<N, KX>,
+    hipError_t e = hipFuncSetAttribute((const void*)me_kernel<N, KX, ROWS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  me_kernel<N, KX><<<r.tiles, g.threads, lds, s>>>(r, R, g.nb);
+  me_kernel<N, KX, ROWS><<<r.tiles, g.threads, lds, s>>>(r, R, g.nb);
   return hipGetLastError();
+}
+
+// Calls f.template operator()<KX, ROWS>() for the geometry's instance.
+template <class F>
+auto me_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<2, 1>()) {
+#define XV_ME_KX(kx)                                                   \
+  case kx:                                                             \
+    return g.rows == 2 ? f.template operator()<kx, 2>() : f.template operator()<kx, 1>();
+  switch (g.kx) {
+    XV_ME_KX(2)
+    XV_ME_KX(4)
+    XV_ME_KX(6)
+    XV_ME_KX(8)
+    XV_ME_KX(10)
+    XV_ME_KX(12)
+    XV_ME_KX(14)
+    XV_ME_KX(16)
+    XV_ME_KX(18)
+    default: return decltype(f.template operator()<2, 1>())();
+  }
+#undef XV_ME_KX
 }
 
 template <int N>
 hipError_t launch_me_n(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
-  switch (g.kx) {
-    case 2: return launch_me_t<N, 2>(R, g, r, s);
-    case 4: return launch_me_t<N, 4>(R, g, r, s);
-    case 6: return launch_me_t<N, 6>(R, g, r, s);
-    case 8: return launch_me_t<N, 8>(R, g, r, s);
-    case 10: return launch_me_t<N, 10>(R, g, r, s);
-    case 12: return launch_me_t<N, 12>(R, g, r, s);
-    case 14: return launch_me_t<N, 14>(R, g, r, s);
-    case 16: return launch_me_t<N, 16>(R, g, r, s);
-    case 18: return launch_me_t<N, 18>(R, g, r, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (g.kx < 2 || g.kx > 18 || (g.kx & 1)) return hipErrorInvalidValue;
+  return me_dispatch(g, [&]<int KX, int ROWS>() { return launch_me_t<N, KX, ROWS>(R, g, r, s); });
 }
 
-// VGPRs per lane of the motion-search kernel instance for (N, KX).
+// VGPRs per lane of the motion-search kernel instance for (N, KX, rows).
 template <int N>
-int me_vgprs_n(int kx) {
+int me_vgprs_n(const MeGeom& g) {
   hipFuncAttributes a{};
-  hipError_t e = hipErrorInvalidValue;
-  switch (kx) {
-    case 2: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 2>); break;
-    case 4: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 4>); break;
-    case 6: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 6>); break;
-    case 8: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 8>); break;
-    case 10: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 10>); break;
-    case 12: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 12>); break;
-    case 14: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 14>); break;
-    case 16: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 16>); break;
-    case 18: e = hipFuncGetAttributes(&a, (const void*)me_kernel<N, 18>); break;
-    default: break;
-  }
+  const hipError_t e = me_dispatch(g, [&]<int KX, int ROWS>() {
+    return hipFuncGetAttributes(&a, (const void*)me_kernel<N, KX, ROWS>);
+  });
   return (e == hipSuccess && a.numRegs > 0) ? a.numRegs : 128;
 }
 
-int me_vgprs(int N, int kx) {
+int me_vgprs(int N, const MeGeom& g) {
   switch (N) {
-    case 4: return me_vgprs_n<4>(kx);
-    case 8: return me_vgprs_n<8>(kx);
-    case 16: return me_vgprs_n<16>(kx);
-    default: return me_vgprs_n<32>(kx);
+    case 4: return me_vgprs_n<4>(g);
+    case 8: return me_vgprs_n<8>(g);
+    case 16: return me_vgprs_n<16>(g);
+    default: return me_vgprs_n<32>(g);
   }
 }
 
 }  // namespace
 
 size_t me_lds_bytes_for(int N, int R, const MeGeom& g) {
-  return me_lds_bytes(N, me_shape(N, R, g.kx, g.nb), g.nb);
+  return me_lds_bytes(N, me_shape(N, R, g.kx, g.nb, g.rows), g.nb);
 }
 
 // Model of a CU (160 KB LDS, 4 SIMDs with 512 VGPRs per lane, at most 8
 // waves each) used to rank geometries.  Score = share of SAD instructions in
-// a lane's VALU work per row (KX N/2 SADs against (KX+N)/2 - 1
-// realignments) x share of useful candidates (2R+1 of G KX) x lane occupancy
-// of the rounds of items x resident waves per SIMD (saturating at 3).
+// a lane's VALU work per window row (rows KX N/2 SADs against (KX+N)/2 - 1
+// realignments) x share of useful candidates (2R+1 of G KX columns; with two
+// rows per lane 2R+1 of 2R+2 rows) x lane occupancy of the rounds of items x
+// resident waves per SIMD (saturating at 3).
 double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
   const int span = 2 * R + 1;
   const int kx = g.kx, c = std::max(1, std::min(g.nb, width_blocks)), th = g.threads;
   const int G = (span + kx - 1) / kx;
-  const double sad = (double)kx * N / 2;
-  const double eff = sad / (sad + (kx + N) / 2 - 1) * (double)span / (double)(G * kx);
-  const MeShape sh = me_shape(N, R, kx, g.nb);
+  const double sad = (double)g.rows * kx * N / 2;
+  const double eff = sad / (sad + (kx + N) / 2 - 1) * (double)span / (double)(G * kx) *
+                     (g.rows == 2 ? (double)span / (double)(2 * (R + 1)) : 1.0);
+  const MeShape sh = me_shape(N, R, kx, g.nb, g.rows);
   const size_t lds = me_lds_bytes(N, sh, g.nb);
   if (lds > 160 * 1024) return -1.0;
   const int items = c * sh.ipb;
   const int rounds = (items + th - 1) / th;
   const double lane = (double)items / (double)(rounds * th);
   const int wpg = th / 64;
-  const int vgpr = me_vgprs(N, kx);
+  const int vgpr = me_vgprs(N, g);
   const int waves_by_vgpr = std::max(1, std::min(8, 512 / std::max(1, vgpr)));
   const int wg_lds = (int)((160 * 1024) / std::max<size_t>(1, lds));
   const int wg_waves = (4 * waves_by_vgpr) / wpg;
@@ -324,19 +390,20 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
 std::vector<MeGeom> me_candidates(int N, int R, int width_blocks) {
   std::vector<MeGeom> v;
   const int cmax = std::max(1, std::min(16, width_blocks));
-  for (int kx = 2; kx <= 18; kx += 2)
-    for (int c = 1; c <= cmax; c++)
-      for (int th = 64; th <= 512; th += 64) {
-        const MeGeom g{c, kx, th};
-        if (me_lds_bytes(N, me_shape(N, R, kx, c), c) <= 96 * 1024) v.push_back(g);
-      }
+  for (int rows = 1; rows <= 2; rows++)
+    for (int kx = 2; kx <= 18; kx += 2)
+      for (int c = 1; c <= cmax; c++)
+        for (int th = 64; th <= 512; th += 64) {
+          const MeGeom g{c, kx, th, rows};
+          if (me_lds_bytes_for(N, R, g) <= 96 * 1024) v.push_back(g);
+        }
   return v;
 }
 
 // Default geometry: the best model score (ties: more blocks per workgroup,
 // fewer redundant window loads).
 MeGeom me_default_geometry(int N, int R, int max_nb) {
-  MeGeom best{1, 2, 256};
+  MeGeom best{1, 2, 256, 1};
   double bs = -2.0;
   for (const MeGeom& g : me_candidates(N, R, max_nb)) {
     const double sc = me_model_score(N, R, g, max_nb);

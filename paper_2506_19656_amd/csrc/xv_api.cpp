@@ -748,7 +748,8 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
   if (!(block == 4 || block == 8 || block == 16 || block == 32) || search_range < 0 ||
       search_range > 64)
     return fail(XV_EINVAL, "bad block or search range");
-  if (!g || (g->blocks_per_wg == 0 && g->cands_per_lane == 0 && g->threads == 0)) {
+  if (!g || (g->blocks_per_wg == 0 && g->cands_per_lane == 0 && g->threads == 0 &&
+             g->rows_per_lane == 0)) {
     std::lock_guard<std::mutex> lk(g_geom_mu);
     g_geom.erase({block, search_range});  // back to the model default
     return XV_OK;
@@ -758,11 +759,13 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
     if (g->blocks_per_wg) m.nb = g->blocks_per_wg;
     if (g->cands_per_lane) m.kx = g->cands_per_lane;
     if (g->threads) m.threads = g->threads;
+    if (g->rows_per_lane) m.rows = g->rows_per_lane;
   }
   if (m.nb < 1 || m.nb > 64) return fail(XV_EINVAL, "blocks_per_wg out of range");
   if (m.kx < 2 || m.kx > 18 || (m.kx & 1)) return fail(XV_EINVAL, "cands_per_lane must be even in 2..18");
   if (m.threads < 64 || m.threads > 512 || (m.threads & 63))
     return fail(XV_EINVAL, "threads must be a multiple of 64 in 64..512");
+  if (m.rows != 1 && m.rows != 2) return fail(XV_EINVAL, "rows_per_lane must be 1 or 2");
   if (me_lds_bytes_for(block, search_range, m) > 160 * 1024)
     return fail(XV_EINVAL, "geometry needs more than 160 KB of LDS");
   std::lock_guard<std::mutex> lk(g_geom_mu);
@@ -779,47 +782,64 @@ int xv_get_me_geometry(int block, int search_range, int width_blocks, xv_me_geom
   g->blocks_per_wg = m.nb;
   g->cands_per_lane = m.kx;
   g->threads = m.threads;
-  g->reserved = 0;
+  g->rows_per_lane = m.rows;
   return XV_OK;
 }
 
 int xv_autotune_me(const xv_cube* in, const xv_params* p, void* hip_stream, int max_candidates,
                    xv_me_geometry* out, double* best_ms) {
-  int rc = check_cube(in, "tuning input");
-  if (rc != XV_OK) return rc;
-  if ((rc = check_params(p)) != XV_OK) return rc;
-  if (in->T < 2 || p->gop < 2) return fail(XV_EINVAL, "tuning needs a P picture (T >= 2, gop >= 2)");
-  hipStream_t s = (hipStream_t)hip_stream;
-  xv_params q = *p;
-  q.flags = 0;
-  xv_encoded* e = nullptr;
-  if ((rc = encode_prepare(in, &q, s, &e)) != XV_OK) {
-    if (e) xv_encoded_free(e);
-    return rc;
+  if (!in || !p) return fail(XV_EINVAL, "null tuning input");
+  return xv_autotune_me_batch(1, in, p, hip_stream, max_candidates, out, best_ms);
+}
+
+int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, void* hip_stream,
+                         int max_candidates, xv_me_geometry* out, double* best_ms) {
+  if (n < 1 || n > kMaxSeg || !cubes || !params)
+    return fail(XV_EINVAL, "tuning needs 1..%d cubes", kMaxSeg);
+  int rc = XV_OK;
+  for (int i = 0; i < n; i++) {
+    if ((rc = check_cube(&cubes[i], "tuning input")) != XV_OK) return rc;
+    if ((rc = check_params(&params[i])) != XV_OK) return rc;
+    if (cubes[i].T < 2 || params[i].gop < 2)
+      return fail(XV_EINVAL, "tuning needs a P picture (T >= 2, gop >= 2)");
+    if (params[i].block != params[0].block || params[i].search_range != params[0].search_range)
+      return fail(XV_EINVAL, "tuning batch mixes block sizes or search ranges");
   }
-  const int N = e->N, R = q.search_range;
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<xv_encoded*> encs(n, nullptr);
+  auto cleanup = [&](int r) {
+    for (auto* e : encs)
+      if (e) xv_encoded_free(e);
+    return r;
+  };
+  for (int i = 0; i < n; i++) {
+    xv_params q = params[i];
+    q.flags = 0;
+    if ((rc = encode_prepare(&cubes[i], &q, s, &encs[i])) != XV_OK) return cleanup(rc);
+  }
+  const int N = encs[0]->N, R = params[0].search_range;
+  int wb = 1;
+  for (auto* e : encs) wb = std::max(wb, e->Wb);
   // step 0 (I pictures) provides the references of step 1
   {
-    std::vector<SegSrc> src{SegSrc{e, 0}};
-    const MeGeom g0 = geometry_for(N, R, e->Wb);
+    std::vector<SegSrc> src;
+    for (auto* e : encs) src.push_back(SegSrc{e, 0});
+    const MeGeom g0 = geometry_for(N, R, wb);
     rc = launch_segments(src, 0, g0, [&](const LaunchDesc& d, double) {
       XV_HIP(launch_encode(N, d, s), "transform kernel");
       return XV_OK;
     });
-    if (rc != XV_OK) {
-      xv_encoded_free(e);
-      return rc;
-    }
+    if (rc != XV_OK) return cleanup(rc);
   }
-  std::vector<MeGeom> cand = me_candidates(N, R, e->Wb);
+  std::vector<MeGeom> cand = me_candidates(N, R, wb);
   std::stable_sort(cand.begin(), cand.end(), [&](const MeGeom& a, const MeGeom& b) {
-    return me_model_score(N, R, a, e->Wb) > me_model_score(N, R, b, e->Wb);
+    return me_model_score(N, R, a, wb) > me_model_score(N, R, b, wb);
   });
-  const size_t keep = (size_t)(max_candidates > 0 ? max_candidates : 24);
+  const size_t keep = (size_t)(max_candidates > 0 ? max_candidates : 32);
   if (cand.size() > keep) cand.resize(keep);
-  const MeGeom def = geometry_for(N, R, e->Wb);
+  const MeGeom def = geometry_for(N, R, wb);
   if (std::find_if(cand.begin(), cand.end(), [&](const MeGeom& g) {
-        return g.nb == def.nb && g.kx == def.kx && g.threads == def.threads;
+        return g.nb == def.nb && g.kx == def.kx && g.threads == def.threads && g.rows == def.rows;
       }) == cand.end())
     cand.push_back(def);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -827,7 +847,8 @@ int xv_autotune_me(const xv_cube* in, const xv_params* p, void* hip_stream, int 
   (void)hipEventCreate(&ev1);
   MeGeom best = def;
   float best_t = 1e30f;
-  std::vector<SegSrc> src{SegSrc{e, 1}};
+  std::vector<SegSrc> src;
+  for (auto* e : encs) src.push_back(SegSrc{e, 1});
   for (const MeGeom& g : cand) {
     float tmin = 1e30f;
     for (int rep = 0; rep < 4 && rc == XV_OK; rep++) {
@@ -854,7 +875,7 @@ int xv_autotune_me(const xv_cube* in, const xv_params* p, void* hip_stream, int 
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
-  xv_encoded_free(e);
+  cleanup(XV_OK);
   if (rc != XV_OK) return rc;
   XV_HIP(hipStreamSynchronize(s), "synchronise tuning");
   {
@@ -865,7 +886,7 @@ int xv_autotune_me(const xv_cube* in, const xv_params* p, void* hip_stream, int 
     out->blocks_per_wg = best.nb;
     out->cands_per_lane = best.kx;
     out->threads = best.threads;
-    out->reserved = 0;
+    out->rows_per_lane = best.rows;
   }
   if (best_ms) *best_ms = best_t;
   return XV_OK;

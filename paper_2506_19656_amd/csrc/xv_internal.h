@@ -194,6 +194,7 @@ struct MeGeom {
   int nb;       // blocks per workgroup along x
   int kx;       // candidates per lane along x (even)
   int threads;  // workgroup size
+  int rows;     // candidate rows per lane (1 or 2)
 };
 MeGeom me_default_geometry(int N, int R, int max_nb = 16);
 double me_model_score(int N, int R, const MeGeom& g, int width_blocks);

@@ -66,7 +66,7 @@ class ExportC(C.Structure):
 
 class MeGeometryC(C.Structure):
     _fields_ = [("blocks_per_wg", C.c_int32), ("cands_per_lane", C.c_int32),
-                ("threads", C.c_int32), ("reserved", C.c_int32)]
+                ("threads", C.c_int32), ("rows_per_lane", C.c_int32)]
 
 
 class ProfileC(C.Structure):
@@ -104,7 +104,7 @@ OP_ENCODE, OP_DECODE = 0, 1
 EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube",
             "xv_decode_cube", "xv_psnr_bpppb", "xv_encoded_export", "xv_encoded_free",
             "xv_encode_batch", "xv_decode_batch", "xv_set_me_geometry", "xv_get_me_geometry",
-            "xv_autotune_me", "xv_profile_enable", "xv_profile_read", "xv_server_create",
+            "xv_autotune_me", "xv_autotune_me_batch", "xv_profile_enable", "xv_profile_read", "xv_server_create",
             "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
             "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release"]
 
@@ -137,6 +137,9 @@ def lib():
         L.xv_get_me_geometry.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(MeGeometryC)]
         L.xv_autotune_me.argtypes = [C.POINTER(Cube), C.POINTER(ParamsC), vp, C.c_int,
                                      C.POINTER(MeGeometryC), C.POINTER(C.c_double)]
+        L.xv_autotune_me_batch.argtypes = [C.c_int, C.POINTER(Cube), C.POINTER(ParamsC), vp,
+                                           C.c_int, C.POINTER(MeGeometryC),
+                                           C.POINTER(C.c_double)]
         L.xv_memory_read.argtypes = [C.POINTER(MemoryC)]
         L.xv_cache_release.argtypes = [C.POINTER(C.c_uint64)]
         L.xv_server_create.argtypes = [C.POINTER(ServerCfgC), C.POINTER(vp)]
@@ -317,8 +320,8 @@ def psnr_bpppb(orig, enc: Encoded, stream=None) -> dict:
 
 
 def set_me_geometry(block: int, search_range: int, blocks_per_wg=0, cands_per_lane=0,
-                    threads=0):
-    g = MeGeometryC(blocks_per_wg, cands_per_lane, threads, 0)
+                    threads=0, rows_per_lane=0):
+    g = MeGeometryC(blocks_per_wg, cands_per_lane, threads, rows_per_lane)
     _check(lib().xv_set_me_geometry(block, search_range, C.byref(g)))
 
 
@@ -326,7 +329,7 @@ def get_me_geometry(block: int, search_range: int, width_blocks: int = 0) -> dic
     g = MeGeometryC()
     _check(lib().xv_get_me_geometry(block, search_range, width_blocks, C.byref(g)))
     return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
-                threads=g.threads)
+                threads=g.threads, rows_per_lane=g.rows_per_lane)
 
 
 def autotune_me(cube, params: Params, stream=None, max_candidates: int = 0) -> dict:
@@ -339,7 +342,21 @@ def autotune_me(cube, params: Params, stream=None, max_candidates: int = 0) -> d
     _check(lib().xv_autotune_me(C.byref(cb), C.byref(pc), _stream_handle(stream), max_candidates,
                                 C.byref(g), C.byref(ms)))
     return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
-                threads=g.threads, kernel_ms=ms.value)
+                threads=g.threads, rows_per_lane=g.rows_per_lane, kernel_ms=ms.value)
+
+
+def autotune_me_batch(cubes, params, stream=None, max_candidates: int = 0) -> dict:
+    """xv_autotune_me_batch: tune on the first P step of the batch as
+    encode_batch would launch it (cubes share block and search_range)."""
+    n = len(cubes)
+    cbs = (Cube * n)(*[_cube(c) for c in cubes])
+    pcs = (ParamsC * n)(*[p.c() for p in params])
+    g = MeGeometryC()
+    ms = C.c_double()
+    _check(lib().xv_autotune_me_batch(n, cbs, pcs, _stream_handle(stream), max_candidates,
+                                      C.byref(g), C.byref(ms)))
+    return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
+                threads=g.threads, rows_per_lane=g.rows_per_lane, kernel_ms=ms.value)
 
 
 def profile_enable(on: bool = True):

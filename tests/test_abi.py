@@ -88,8 +88,11 @@ def test_me_geometry_validation(xvmod):
         xvmod.set_me_geometry(8, 8, threads=1024)
     with pytest.raises(xvmod.XvError):
         xvmod.set_me_geometry(12, 8)
+    with pytest.raises(xvmod.XvError):
+        xvmod.set_me_geometry(8, 8, rows_per_lane=3)
     g = xvmod.get_me_geometry(16, 32)
     assert g["cands_per_lane"] % 2 == 0 and g["threads"] % 64 == 0 and g["blocks_per_wg"] >= 1
+    assert g["rows_per_lane"] in (1, 2)
 
 
 def test_memory_record_and_release_without_device_work(xvmod):

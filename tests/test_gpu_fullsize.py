@@ -76,9 +76,9 @@ def test_s2cloud_full_sweep_sampled_units():
     params = [xv.Params(bit_depth=wl.bit_depth, qp=qp, block=N, search_range=wl.search_range,
                         gop=wl.gop, pad_mode=wl.pad_mode, fill_mode=wl.fill_mode)
               for qp, N in runs]
-    for N in wl.blocks:
-        xv.autotune_me(cube, xv.Params(bit_depth=wl.bit_depth, qp=27, block=N,
-                                       search_range=wl.search_range, gop=wl.gop))
+    for N in wl.blocks:  # tuned as the benchmark tunes: on each block size's batch
+        pn = [p for p in params if p.block == N]
+        xv.autotune_me_batch([cube] * len(pn), pn)
     encs = xv.encode_batch([cube] * len(params), params)
     mn, mx, nv = O.stats(host)
     ngop = -(-wl.T // wl.gop)

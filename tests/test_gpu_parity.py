@@ -192,13 +192,40 @@ def test_motion_geometry_never_changes_outputs():
     p = xv.Params(bit_depth=10, qp=27, block=8, search_range=9, gop=4)
     base = xv.encode_cube(cube, p).host()
     try:
-        for nb, kx, th in [(1, 2, 64), (2, 18, 128), (5, 8, 256), (3, 6, 512), (7, 10, 192)]:
-            xv.set_me_geometry(8, 9, nb, kx, th)
+        for nb, kx, th, rows in [(1, 2, 64, 1), (2, 18, 128, 1), (5, 8, 256, 1), (3, 6, 512, 1),
+                                 (7, 10, 192, 1), (1, 2, 64, 2), (2, 18, 128, 2), (5, 8, 256, 2),
+                                 (3, 6, 512, 2), (12, 12, 320, 2)]:
+            xv.set_me_geometry(8, 9, nb, kx, th, rows)
             got = xv.encode_cube(cube, p).host()
-            assert np.array_equal(got["mvs"], base["mvs"]), (nb, kx, th)
-            assert np.array_equal(got["recon"], base["recon"]), (nb, kx, th)
+            assert np.array_equal(got["mvs"], base["mvs"]), (nb, kx, th, rows)
+            assert np.array_equal(got["recon"], base["recon"]), (nb, kx, th, rows)
     finally:
         xv.set_me_geometry(8, 9)
+    # both kernel forms against the oracle at every block size, odd and even R
+    for N, R in ((4, 3), (16, 8), (32, 5)):
+        q = xv.Params(bit_depth=10, qp=22, block=N, search_range=R, gop=4)
+        try:
+            for rows in (1, 2):
+                xv.set_me_geometry(N, R, 0, 0, 0, rows)
+                check_cube(f"rows{rows}_N{N}_R{R}", host, q)
+        finally:
+            xv.set_me_geometry(N, R)
+
+
+def test_batch_tuner_installs_a_geometry_that_keeps_outputs():
+    cubes = [_to_dev(_textured(5, 48, 80, 4, seed=31 + i)) for i in range(3)]
+    params = [xv.Params(bit_depth=10, qp=qp, block=16, search_range=6, gop=4) for qp in (22, 27, 32)]
+    before = [xv.encode_cube(c, p).host() for c, p in zip(cubes, params)]
+    try:
+        g = xv.autotune_me_batch(cubes, params, max_candidates=6)
+        assert g["rows_per_lane"] in (1, 2) and g["kernel_ms"] > 0
+        assert xv.get_me_geometry(16, 6)["threads"] == g["threads"]
+        after = [e.host() for e in xv.encode_batch(cubes, params)]
+        for a, b in zip(before, after):
+            for k in INT_KEYS:
+                assert np.array_equal(a[k], b[k]), k
+    finally:
+        xv.set_me_geometry(16, 6)
 
 
 def test_large_sad_blocks_rank_correctly():
