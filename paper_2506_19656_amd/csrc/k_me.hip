@@ -365,7 +365,7 @@ size_t me_lds_bytes_for(int N, int R, const MeGeom& g) {
 // resident waves per SIMD (saturating at 3).
 double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
   const int span = 2 * R + 1;
-  const int kx = g.kx, c = std::max(1, std::min(g.nb, width_blocks)), th = g.threads;
+  const int kx = g.kx, th = g.threads;
   const int G = (span + kx - 1) / kx;
   const double sad = (double)g.rows * kx * N / 2;
   const double eff = sad / (sad + (kx + N) / 2 - 1) * (double)span / (double)(G * kx) *
@@ -373,9 +373,17 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
   const MeShape sh = me_shape(N, R, kx, g.nb, g.rows);
   const size_t lds = me_lds_bytes(N, sh, g.nb);
   if (lds > 160 * 1024) return -1.0;
-  const int items = c * sh.ipb;
-  const int rounds = (items + th - 1) / th;
-  const double lane = (double)items / (double)(rounds * th);
+  // lane occupancy over the runs of a block row: full runs of nb blocks and
+  // a last run of the remaining ones
+  const int wbk = std::max(1, width_blocks);
+  const int runs = (wbk + g.nb - 1) / g.nb;
+  double busy = 0.0, slots = 0.0;
+  for (int r = 0; r < runs; r++) {
+    const int items = std::min(g.nb, wbk - r * g.nb) * sh.ipb;
+    busy += items;
+    slots += (double)((items + th - 1) / th) * th;
+  }
+  const double lane = busy / slots;
   const int wpg = th / 64;
   const int vgpr = me_vgprs(N, g);
   const int waves_by_vgpr = std::max(1, std::min(8, 512 / std::max(1, vgpr)));
