@@ -525,6 +525,33 @@ __global__ void __launch_bounds__(kThreads) phys_reduce_kernel(PhysArgs a) {
   if (threadIdx.x == 0) a.out[b] = sred[0];
 }
 
+// Per-group totals of the transform kernel's per-tile sums: block g sums the
+// T * tpf tiles of group g for each of the 5 quantities with a fixed
+// assignment of tiles to threads and a fixed tree.
+__global__ void __launch_bounds__(kThreads) encode_totals_kernel(
+    const unsigned long long* part, int T, int tpf, unsigned long long* sse,
+    unsigned long long* bits) {
+  __shared__ unsigned long long sred[kThreads];
+  const int g = blockIdx.x;
+  const int64_t n = (int64_t)T * tpf;
+  const unsigned long long* pg = part + (int64_t)g * n * 5;
+  for (int i = 0; i < 5; i++) {
+    unsigned long long v = 0;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) v += pg[j * 5 + i];
+    sred[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kThreads / 2; w >= 1; w >>= 1) {
+      if ((int)threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (i < 3) sse[3 * g + i] = sred[0];
+      else bits[2 * g + i - 3] = sred[0];
+    }
+    __syncthreads();
+  }
+}
+
 // Job table of one cube, step-major: entry (s, g * nk + k) describes frame
 // t = k * gop + s of band group g (nk = GOPs that have a frame at step s).
 __global__ void plan_kernel(CubePlan p) {
@@ -556,8 +583,7 @@ __global__ void plan_kernel(CubePlan p) {
   jb.mbits = p.mbits ? p.mbits + f * (int64_t)Hb * Wb : nullptr;
   jb.vmask = p.vmask ? p.vmask + f * 3 * plane : nullptr;
   jb.nan_total = p.nan_total;
-  jb.sse = p.sse ? p.sse + 3 * g : nullptr;
-  jb.bits = p.bits ? p.bits + 2 * g : nullptr;
+  jb.part = p.part ? p.part + f * p.tpf * 5 : nullptr;
   jb.Hp = p.Hp;
   jb.Wp = p.Wp;
   jb.H = p.H;
@@ -577,6 +603,13 @@ hipError_t launch_plan(const CubePlan& p, hipStream_t s) {
   const int64_t total = plan_step_offset(p.T, p.G, p.gop, p.nsteps);
   if (total <= 0) return hipSuccess;
   plan_kernel<<<grid_for(total, 128), 128, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_totals(const unsigned long long* part, int G, int T, int tpf,
+                                unsigned long long* sse, unsigned long long* bits, hipStream_t s) {
+  if (G <= 0) return hipSuccess;
+  encode_totals_kernel<<<G, kThreads, 0, s>>>(part, T, tpf, sse, bits);
   return hipGetLastError();
 }
 

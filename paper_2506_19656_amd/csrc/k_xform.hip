@@ -73,13 +73,14 @@ __device__ inline void build_scan(uint16_t* scan) {
 
 struct TileCoord {
   const FrameJob* job;
-  int by, bx0, Hb, Wb;
+  int tl, by, bx0, Hb, Wb;
 };
 
 template <int N>
 __device__ inline bool locate(const LaunchDesc& jd, TileCoord& tc) {
   int tl;
   tc.job = desc_job(jd, blockIdx.x, tl);
+  tc.tl = tl;
   const FrameJob& job = *tc.job;
   tc.Hb = job.Hp / N;
   tc.Wb = job.Wp / N;
@@ -431,14 +432,16 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
     }
   }
   __syncthreads();
+  // this tile's sums; the per-group totals are formed after the last step
+  unsigned long long* part = job.part + (size_t)tc.tl * 5;
   if (t == 0) {
     unsigned long long cb = 0;
     for (int i = 0; i < 3 * NBW; i++)
       if (tc.bx0 + (i % NBW) < tc.Wb) cb += s.cbits[i / NBW][i % NBW];
-    atomicAdd(&job.bits[0], cb);
-    if (s.mvbits) atomicAdd(&job.bits[1], (unsigned long long)s.mvbits);
+    part[3] = cb;
+    part[4] = s.mvbits;
   }
-  if (t < job.nch && s.sse[t]) atomicAdd(&job.sse[t], s.sse[t]);
+  if (t < 3) part[t] = s.sse[t];
 }
 
 template <int N>

@@ -33,7 +33,9 @@ struct xv_encoded {
   int src_dtype;
   hipStream_t stream;
   void* keep;  // levels, vectors, bit counts, statistics, job table
-  void* work;  // converted frames, reconstruction, validity bytes
+  void* work;  // converted frames, reconstruction, validity bytes, per-tile sums
+  unsigned long long* tile_part;  // [G][T][tpf][5] per-tile sums of the transform kernel
+  int tpf;                        // transform tiles per frame
   uint16_t* frames;
   uint16_t* recon;
   uint8_t* vmask;
@@ -200,7 +202,7 @@ void dims_of(xv_encoded* e, const xv_cube* in, const xv_params* p) {
 // reconstruction, validity bytes).  Offsets in bytes.
 struct EncLayout {
   size_t o_lev, o_mv, o_cb, o_mb, o_keys, o_span, o_pp, o_jobs, keep;
-  size_t o_fr, o_rc, o_vm, work;
+  size_t o_fr, o_rc, o_vm, o_part, work;
   size_t span_words;
   int phys_nb;
 };
@@ -228,6 +230,7 @@ EncLayout enc_layout(const xv_encoded* e) {
   L.o_fr = w.take<uint16_t>((size_t)nframes * 3 * plane);
   L.o_rc = w.take<uint16_t>((size_t)nframes * 3 * plane);
   L.o_vm = e->src_dtype == XV_F32 ? w.take<uint8_t>((size_t)nframes * 3 * plane) : 0;
+  L.o_part = w.take<uint64_t>((size_t)nframes * xf_tiles_per_job(e->N, e->Hb, e->Wb) * 5);
   L.work = w.off;
   return L;
 }
@@ -256,7 +259,7 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   } k{lay.keep}, w{lay.work};
   const size_t o_lev = lay.o_lev, o_mv = lay.o_mv, o_cb = lay.o_cb, o_mb = lay.o_mb,
                o_keys = lay.o_keys, o_span = lay.o_span, o_pp = lay.o_pp, o_jobs = lay.o_jobs,
-               o_fr = lay.o_fr, o_rc = lay.o_rc, o_vm = lay.o_vm;
+               o_fr = lay.o_fr, o_rc = lay.o_rc, o_vm = lay.o_vm, o_part = lay.o_part;
   const size_t span_words = lay.span_words;
   e->phys_nb = lay.phys_nb;
 
@@ -293,10 +296,10 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   e->frames = (uint16_t*)(wb + o_fr);
   e->recon = (uint16_t*)(wb + o_rc);
   e->vmask = in->dtype == XV_F32 ? (uint8_t*)(wb + o_vm) : nullptr;
+  e->tile_part = (unsigned long long*)(wb + o_part);
+  e->tpf = xf_tiles_per_job(e->N, e->Hb, e->Wb);
   *out = e;
 
-  // sse [3G] and bits [2G] are adjacent in the metric span
-  XV_HIP(launch_fill_u64(e->sse, 0ull, 5 * G, s), "clear accumulators");
   const double elb = in->dtype == XV_U16 ? 2.0 : 4.0;
   const double in_bytes = (double)T * e->H * e->W * bands * elb;
   {
@@ -315,9 +318,9 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   }
   {
     CubePlan pl{e->frames, e->recon, e->levels, e->mvs, e->cbits, e->mbits, e->vmask,
-                e->nan_total, e->sse, e->bits, e->jobs, (int32_t)T, e->G, p->gop, e->nsteps,
+                e->nan_total, e->tile_part, e->jobs, (int32_t)T, e->G, p->gop, e->nsteps,
                 e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)bands, e->N,
-                p->bit_depth, p->qp};
+                p->bit_depth, p->qp, e->tpf};
     XV_HIP(launch_plan(pl, s), "plan kernel");
   }
   return XV_OK;
@@ -404,14 +407,20 @@ int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s) {
   return XV_OK;
 }
 
-void drop_work(xv_encoded* e) {
+// After the last step: per-group totals from the per-tile sums, then the
+// work buffers go if the caller asked for that.
+int finish_encode(xv_encoded* e) {
+  XV_HIP(launch_encode_totals(e->tile_part, e->G, (int)e->T, e->tpf, e->sse, e->bits, e->stream),
+         "encode totals kernel");
   if (e->p.flags & XV_FLAG_DROP_WORK) {
     dev_free(e->work, e->stream);
     e->work = nullptr;
+    e->tile_part = nullptr;
     e->frames = nullptr;
     e->recon = nullptr;
     e->vmask = nullptr;
   }
+  return XV_OK;
 }
 
 // ---- decode -----------------------------------------------------------------
@@ -439,9 +448,9 @@ int decode_prepare(const xv_encoded* e, hipStream_t s, DecodeBuf& db) {
   db.recon = (uint16_t*)((char*)db.mem + o_rc);
   db.jobs = (FrameJob*)((char*)db.mem + o_jb);
   CubePlan pl{nullptr, db.recon, e->levels, e->mvs, nullptr, nullptr, nullptr, nullptr,
-              nullptr, nullptr, db.jobs, (int32_t)e->T, e->G, e->p.gop, e->nsteps,
+              nullptr, db.jobs, (int32_t)e->T, e->G, e->p.gop, e->nsteps,
               e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)e->bands, e->N,
-              e->p.bit_depth, e->p.qp};
+              e->p.bit_depth, e->p.qp, 0};
   XV_HIP(launch_plan(pl, s), "plan kernel");
   return XV_OK;
 }
@@ -550,7 +559,10 @@ int xv_encode_cube(const xv_cube* in, const xv_params* p, void* hip_stream, xv_e
     xv_encoded_free(e);
     return rc;
   }
-  drop_work(e);
+  if ((rc = finish_encode(e)) != XV_OK) {
+    xv_encoded_free(e);
+    return rc;
+  }
   *out = e;
   return XV_OK;
 }
@@ -583,9 +595,10 @@ int xv_encode_batch(int n, const xv_cube* cubes, const xv_params* params, void* 
     if (rc != XV_OK) return cleanup(rc);
   }
   for (int i = 0; i < n; i++) {
-    drop_work(all[i]);
-    outs[i] = all[i];
+    int rc = finish_encode(all[i]);
+    if (rc != XV_OK) return cleanup(rc);
   }
+  for (int i = 0; i < n; i++) outs[i] = all[i];
   return XV_OK;
 }
 
@@ -1094,7 +1107,8 @@ int iterate(xv_server* sv) {
         int rc = decode_finish(r->src, &r->cube, r->db, sv->s);
         if (rc != XV_OK) return rc;
       } else {
-        drop_work(r->enc);
+        int rc = finish_encode(r->enc);
+        if (rc != XV_OK) return rc;
       }
       XV_HIP(hipEventRecord(r->ev, sv->s), "request event");
       r->ev_recorded = true;

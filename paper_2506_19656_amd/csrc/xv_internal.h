@@ -29,8 +29,8 @@ struct FrameJob {
   uint32_t* mbits;             // [Hb][Wb]
   const uint8_t* vmask;        // [3][Hp][Wp] validity bytes, or null
   const uint32_t* nan_total;   // device flag: non-zero -> vmask is meaningful
-  unsigned long long* sse;     // per-channel accumulators (3 entries)
-  unsigned long long* bits;    // [0] coefficient bits, [1] MV bits
+  unsigned long long* part;    // [tiles of the frame][5] per-tile sums: squared error of
+                               // channels 0..2, coefficient bits, vector bits
   int32_t Hp, Wp, H, W;
   int32_t nch;                 // channels carrying a real band (1..3)
   int32_t intra;
@@ -73,11 +73,16 @@ struct CubePlan {
   uint32_t* mbits;
   const uint8_t* vmask;
   const uint32_t* nan_total;
-  unsigned long long* sse;     // [3G]
-  unsigned long long* bits;    // [2G]
+  unsigned long long* part;    // [G][T][tpf][5] per-tile sums (null for decode)
   FrameJob* jobs;              // [sum over steps of jobs]
   int32_t T, G, gop, nsteps, Hp, Wp, H, W, bands, N, bit_depth, qp;
+  int32_t tpf;                 // transform tiles per frame
 };
+
+// Per-group totals of the per-tile sums, in a fixed order: sse [3G] and
+// bits [2G] (coefficient, vector) of one encoded cube.
+hipError_t launch_encode_totals(const unsigned long long* part, int G, int T, int tpf,
+                                unsigned long long* sse, unsigned long long* bits, hipStream_t s);
 
 // Jobs at step s: G * ceil((T - s) / gop); offset of step s in the table.
 inline int plan_jobs_at(int T, int G, int gop, int s) { return G * ((T - s + gop - 1) / gop); }
