@@ -28,9 +28,6 @@ __device__ inline int ue_len(uint32_t k) { return 2 * (31 - __clz((int)(k + 1)))
 __device__ inline int se_len(int v) {
   return ue_len(v > 0 ? (uint32_t)(2 * v - 1) : (uint32_t)(-2 * v));
 }
-__device__ inline int clip16(long long v) {
-  return (int)(v < -32768 ? -32768 : (v > 32767 ? 32767 : v));
-}
 
 template <int N>
 struct Tile {
@@ -216,9 +213,24 @@ __device__ inline void pred_row(const FrameJob& job, int c, int y, int x0, int d
   }
 }
 
-// Dequantisation d = clip16((level * IQ[qP%6] * 16 * 2^(qP/6) + 2^(bd-1)) >> bd).
-__device__ inline int dequant(int lv, long long scale, int bd) {
-  return clip16(((long long)lv * scale + (1ll << (bd - 1))) >> bd);
+// Dequantisation d = clip16((level * IQ[qP%6] * 16 * 2^(qP/6) + 2^(bd-1)) >> bd),
+// evaluated exactly in 32 bits: with X = level * IQ * 16 (|X| < 2^26) and
+// sh = bd - qP/6, the power of two factors out of the rounding shift, so
+// d = clip16((X + 2^(sh-1)) >> sh) for sh > 0 and clip16(X << -sh) for
+// sh <= 0, where clamping X to +-2^15 first changes no result.
+struct Dequant {
+  int m;   // IQ[qP%6] * 16
+  int sh;  // bd - qP/6
+};
+
+__device__ inline Dequant dequant_params(int qP, int bd) { return Dequant{kIQ[qP % 6] * 16, bd - qP / 6}; }
+
+__device__ inline int clamp16(int v) { return min(max(v, -32768), 32767); }
+
+__device__ inline int dequant(int lv, const Dequant& q) {
+  const int X = lv * q.m;
+  if (q.sh > 0) return clamp16((X + (1 << (q.sh - 1))) >> q.sh);
+  return clamp16(min(max(X, -32768), 32768) << (-q.sh));
 }
 
 // Inverse column stage of block column k from the dequantised column stored
@@ -229,7 +241,7 @@ __device__ inline void inverse_column(const uint32_t* inv, const uint32_t* drow,
   int acc[N];
   mat_pairs<N>(inv, drow, acc);
 #pragma unroll
-  for (int y = 0; y < N; y++) E[y][k] = (int16_t)clip16(((long long)acc[y] + 64) >> 7);
+  for (int y = 0; y < N; y++) E[y][k] = (int16_t)clamp16((acc[y] + 64) >> 7);
 }
 
 // Inverse row stage and reconstruction of block row r into packed pairs.
@@ -345,8 +357,7 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
     const int qbits = 29 + qP / 6 - B - L2N;
     const uint32_t off = (uint32_t)(job.intra ? 171 : 85) << (qbits - 9);
     const uint32_t qf = (uint32_t)kQf[qP % 6];
-    const long long scale = (long long)kIQ[qP % 6] * 16ll << (qP / 6);
-    const int bd = B + L2N - 5;
+    const Dequant dqp = dequant_params(qP, B + L2N - 5);
     // the row is only accessed as packed 32-bit pairs (no mixed-width aliasing)
     uint32_t* row = (uint32_t*)s.TD[c][b][k];
     int acc[N];
@@ -360,7 +371,7 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
       mq = mq > 32767u ? 32767u : mq;
       const int lv = C < 0 ? -(int)mq : (int)mq;
       s.L[c][b][l * N + k] = (int16_t)lv;
-      dq[l] = dequant(lv, scale, bd);
+      dq[l] = dequant(lv, dqp);
     }
 #pragma unroll
     for (int m = 0; m < N / 2; m++)
@@ -389,16 +400,16 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
     if (c < job.nch && y < job.H) {
       const bool usemask = job.vmask != nullptr && *job.nan_total != 0u;
       const uint8_t* vm = usemask ? job.vmask + c * plane + (size_t)y * job.Wp + x0 : nullptr;
-      unsigned long long sse = 0;
+      uint32_t sse = 0;  // at most 32 * 4095^2 < 2^32
 #pragma unroll
       for (int j = 0; j < N; j++) {
         const int cv = (int)((cp[j >> 1] >> (16 * (j & 1))) & 0xffffu);
         const int rv = (int)((rp[j >> 1] >> (16 * (j & 1))) & 0xffffu);
         const bool ok = (x0 + j < job.W) && (!usemask || vm[j]);
         const int e = cv - rv;
-        sse += ok ? (unsigned long long)(e * e) : 0ull;
+        sse += ok ? (uint32_t)(e * e) : 0u;
       }
-      if (sse) atomicAdd(&s.sse[c], sse);
+      if (sse) atomicAdd(&s.sse[c], (unsigned long long)sse);
     }
   }
 
@@ -490,13 +501,12 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
   if (vb) {
     const int k = r;
     const int qP = job.qp + 6 * (B - 8);
-    const long long scale = (long long)kIQ[qP % 6] * 16ll << (qP / 6);
-    const int bd = B + L2N - 5;
+    const Dequant dqp = dequant_params(qP, B + L2N - 5);
     uint32_t* row = (uint32_t*)s.TD[c][b][k];
 #pragma unroll
     for (int m = 0; m < N / 2; m++) {
-      const int d0 = dequant(s.L[c][b][(2 * m) * N + k], scale, bd);
-      const int d1 = dequant(s.L[c][b][(2 * m + 1) * N + k], scale, bd);
+      const int d0 = dequant(s.L[c][b][(2 * m) * N + k], dqp);
+      const int d1 = dequant(s.L[c][b][(2 * m + 1) * N + k], dqp);
       row[m] = ((uint32_t)d0 & 0xffffu) | ((uint32_t)d1 << 16);
     }
     inverse_column<N>(inv, row, s.E[c][b], k);
