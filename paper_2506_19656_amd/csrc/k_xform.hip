@@ -34,22 +34,25 @@ struct Tile {
   static constexpr int NBW = 64 / N;    // blocks per workgroup along x
   static constexpr int P = N + 2;       // LDS pitch (int16) of a tile row (odd dword count)
   static constexpr int L2N = ilog2c(N);
+  // register target of the encode kernel: 8 waves per SIMD where the
+  // compiler fits that without spilling (N = 8, 16); N = 4 and 32 keep their
+  // natural allocation
+  static constexpr int kEncWaves = (N == 8 || N == 16) ? 8 : 1;
 };
 
-// LDS layout per workgroup (int16):
+// LDS layout per workgroup, encode (int16):
 //   TD [3][NBW][N][P]  forward row-stage output transposed ([k][y]); each
-//                      column thread then overwrites its own row with the
-//                      dequantised column ([k][l])
-//   E  [3][NBW][N][P]  first the residual rows ([y][x]), then the inverse
-//                      column-stage output ([y][k])
-//   L  [3][NBW][N*N]   levels, raster [l][k]
-//   scan [N*N]         scan position -> raster index
-//   red                per-workgroup sums: squared error per channel, bits
+//                      column thread then overwrites its own row k with the
+//                      column's levels ([k][l])
+//   E  [3][NBW][N][P]  inverse column-stage output ([y][k])
+//   scan [N*N]         scan position -> offset (k * P + l) of the level in a
+//                      block's TD tile
+//   sums               per-workgroup squared error per channel, bits
+// Residual rows and dequantised columns stay in registers.
 template <int N>
-struct alignas(16) Lds {
+struct alignas(16) LdsEnc {
   int16_t TD[3][Tile<N>::NBW][N][Tile<N>::P];
   int16_t E[3][Tile<N>::NBW][N][Tile<N>::P];
-  int16_t L[3][Tile<N>::NBW][N * N];
   uint16_t scan[N * N];
   unsigned long long sse[3];
   uint32_t cbits[3][Tile<N>::NBW];
@@ -57,6 +60,17 @@ struct alignas(16) Lds {
   uint32_t mvbits;
 };
 
+// Decode: the levels as stored (raster [l][k] per block) and the inverse
+// column-stage output.
+template <int N>
+struct alignas(16) LdsDec {
+  int16_t L[3][Tile<N>::NBW][N * N];
+  int16_t E[3][Tile<N>::NBW][N][Tile<N>::P];
+};
+
+// Up-right diagonal scan of an N x N block (ITU-T H.265 6.5.3): anti-
+// diagonals d = x + y in order, each from its bottom-left end upwards.  The
+// table maps scan position to the level's offset in the transposed tile.
 template <int N>
 __device__ inline void build_scan(uint16_t* scan) {
   for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
@@ -64,7 +78,7 @@ __device__ inline void build_scan(uint16_t* scan) {
     const int d = x + y;
     const int before = d < N ? d * (d + 1) / 2 : N * N - (2 * N - 1 - d) * (2 * N - d) / 2;
     const int first_x = d < N ? 0 : d - N + 1;
-    scan[before + x - first_x] = (uint16_t)i;
+    scan[before + x - first_x] = (uint16_t)(x * Tile<N>::P + y);
   }
 }
 
@@ -147,6 +161,19 @@ __device__ inline void mat_pairs(const uint32_t* __restrict__ tb, const uint32_t
     const uint32_t x = src[m];
 #pragma unroll
     for (int k = 0; k < N; k++) acc[k] = dot2(tb[m * N + k], x, acc[k]);
+  }
+}
+
+// The same with the input pairs in registers.
+template <int N>
+__device__ inline void mat_pairs_r(const uint32_t* __restrict__ tb, const uint32_t (&src)[N / 2],
+                                   int (&acc)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; k++) acc[k] = 0;
+#pragma unroll
+  for (int m = 0; m < N / 2; m++) {
+#pragma unroll
+    for (int k = 0; k < N; k++) acc[k] = dot2(tb[m * N + k], src[m], acc[k]);
   }
 }
 
@@ -233,13 +260,13 @@ __device__ inline int dequant(int lv, const Dequant& q) {
   return clamp16(min(max(X, -32768), 32768) << (-q.sh));
 }
 
-// Inverse column stage of block column k from the dequantised column stored
-// (as pairs) in the thread's own TD row: E[y][k] = clip16((sum_l M[l][y] d[l] + 64) >> 7).
+// Inverse column stage of block column k from its dequantised column (pairs
+// in registers): E[y][k] = clip16((sum_l M[l][y] d[l] + 64) >> 7).
 template <int N>
-__device__ inline void inverse_column(const uint32_t* inv, const uint32_t* drow,
+__device__ inline void inverse_column(const uint32_t* inv, const uint32_t (&dpair)[N / 2],
                                       int16_t (*E)[Tile<N>::P], int k) {
   int acc[N];
-  mat_pairs<N>(inv, drow, acc);
+  mat_pairs_r<N>(inv, dpair, acc);
 #pragma unroll
   for (int y = 0; y < N; y++) E[y][k] = (int16_t)clamp16((acc[y] + 64) >> 7);
 }
@@ -266,7 +293,7 @@ __device__ inline void inverse_row(const uint32_t* inv, const int16_t* Erow,
 // Rate proxy of every block of channel c in the tile (one wave per channel):
 // each nonzero level adds ue(run) + se(level) to its block's LDS counter.
 template <int N>
-__device__ inline void block_bits(Lds<N>& s, const TileCoord& tc, int c) {
+__device__ inline void block_bits(LdsEnc<N>& s, const TileCoord& tc, int c) {
   constexpr int NBW = Tile<N>::NBW;
   constexpr int S = N * N < 64 ? N * N : 64;  // lanes per block segment
   constexpr int BPC = 64 / S;                  // blocks per pass
@@ -281,7 +308,7 @@ __device__ inline void block_bits(Lds<N>& s, const TileCoord& tc, int c) {
 #pragma unroll
     for (int ci = 0; ci < CPB; ci++) {
       const int p = ci * S + pin;
-      const int lv = vb ? (int)s.L[c][b][s.scan[p]] : 0;
+      const int lv = vb ? (int)(&s.TD[c][b][0][0])[s.scan[p]] : 0;
       const unsigned long long m = __ballot(lv != 0);
       const unsigned long long segm = (S == 64) ? m : ((m >> (seg * S)) & ((1ull << S) - 1));
       const unsigned long long below = segm & ((1ull << pin) - 1);
@@ -295,10 +322,11 @@ __device__ inline void block_bits(Lds<N>& s, const TileCoord& tc, int c) {
 }
 
 template <int N>
-__global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
+__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(Tile<N>::kEncWaves)))
+encode_kernel(const LaunchDesc jr) {
   constexpr int NBW = Tile<N>::NBW;
   constexpr int L2N = Tile<N>::L2N;
-  __shared__ Lds<N> s;
+  __shared__ LdsEnc<N> s;
   TileCoord tc;
   if (!locate<N>(jr, tc)) return;
   const FrameJob& job = *tc.job;
@@ -332,16 +360,16 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
   }
 
   // Forward row stage of row r: T[y][k] = (sum_x M[k][x] res[x] + 2^(s1-1)) >> s1,
-  // stored transposed.  The residual row is parked in E row r for the loop.
+  // stored transposed.
   uint32_t cp[N / 2], pp[N / 2];
   if (vb) {
     load_row_packed<N>(job.cur + c * plane + (size_t)y * job.Wp + x0, cp);
     pred_row<N>(job, c, y, x0, dx, dy, pp);
-    uint32_t* er = (uint32_t*)s.E[c][b][r];
+    uint32_t er[N / 2];
 #pragma unroll
     for (int m = 0; m < N / 2; m++) er[m] = sub_pairs(cp[m], pp[m]);
     int acc[N];
-    mat_pairs<N>(fwd, er, acc);
+    mat_pairs_r<N>(fwd, er, acc);
     const int s1 = L2N + B - 9;
     const int rnd1 = 1 << (s1 - 1);
 #pragma unroll
@@ -349,8 +377,9 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
   }
   __syncthreads();
 
-  // Column stage of column k: forward transform, quantise, dequantise (into
-  // the thread's own TD row), inverse column transform.
+  // Column stage of column k: forward transform, quantise (levels into the
+  // thread's own TD row, transposed), dequantise and inverse column
+  // transform from registers.
   if (vb) {
     const int k = r;
     const int qP = job.qp + 6 * (B - 8);
@@ -362,33 +391,47 @@ __global__ void __launch_bounds__(192) encode_kernel(const LaunchDesc jr) {
     uint32_t* row = (uint32_t*)s.TD[c][b][k];
     int acc[N];
     mat_pairs<N>(fwd, row, acc);
-    int dq[N];
+    uint32_t lpair[N / 2], dpair[N / 2];
 #pragma unroll
-    for (int l = 0; l < N; l++) {
-      const int C = (acc[l] + (1 << (L2N + 5))) >> (L2N + 6);
-      const uint32_t a = (uint32_t)(C < 0 ? -C : C);
-      uint32_t mq = (a * qf + off) >> qbits;
-      mq = mq > 32767u ? 32767u : mq;
-      const int lv = C < 0 ? -(int)mq : (int)mq;
-      s.L[c][b][l * N + k] = (int16_t)lv;
-      dq[l] = dequant(lv, dqp);
+    for (int l = 0; l < N; l += 2) {
+      int lv[2], dq[2];
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const int C = (acc[l + h] + (1 << (L2N + 5))) >> (L2N + 6);
+        const uint32_t a = (uint32_t)(C < 0 ? -C : C);
+        uint32_t mq = (a * qf + off) >> qbits;
+        mq = mq > 32767u ? 32767u : mq;
+        lv[h] = C < 0 ? -(int)mq : (int)mq;
+        dq[h] = dequant(lv[h], dqp);
+      }
+      lpair[l / 2] = ((uint32_t)lv[0] & 0xffffu) | ((uint32_t)lv[1] << 16);
+      dpair[l / 2] = ((uint32_t)dq[0] & 0xffffu) | ((uint32_t)dq[1] << 16);
     }
 #pragma unroll
-    for (int m = 0; m < N / 2; m++)
-      row[m] = ((uint32_t)dq[2 * m] & 0xffffu) | ((uint32_t)dq[2 * m + 1] << 16);
-    inverse_column<N>(inv, row, s.E[c][b], k);
+    for (int m = 0; m < N / 2; m++) row[m] = lpair[m];
+    inverse_column<N>(inv, dpair, s.E[c][b], k);
   }
   __syncthreads();
 
-  // Levels out (block-major), coalesced 16-byte chunks.
+  // Levels out (block-major, raster [l][k] inside a block) in 16-byte
+  // chunks gathered from the transposed tiles.
   {
     constexpr int CH = (N * N) / 8;  // uint4 chunks per block
     for (int e = t; e < 3 * NBW * CH; e += blockDim.x) {
       const int cb = e / CH, q = e - cb * CH;
       const int cc = cb / NBW, bb = cb - cc * NBW;
       if (tc.bx0 + bb >= tc.Wb) continue;
+      const int16_t* tile = &s.TD[cc][bb][0][0];
+      uint32_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int i0 = q * 8 + 2 * j, i1 = i0 + 1;
+        const int v0 = tile[(i0 % N) * Tile<N>::P + i0 / N];
+        const int v1 = tile[(i1 % N) * Tile<N>::P + i1 / N];
+        w[j] = ((uint32_t)v0 & 0xffffu) | ((uint32_t)v1 << 16);
+      }
       int16_t* dst = job.lev + (((size_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb) * (N * N);
-      ((uint4*)dst)[q] = ((const uint4*)s.L[cc][bb])[q];
+      ((uint4*)dst)[q] = make_uint4(w[0], w[1], w[2], w[3]);
     }
   }
 
@@ -459,7 +502,7 @@ template <int N>
 __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
   constexpr int NBW = Tile<N>::NBW;
   constexpr int L2N = Tile<N>::L2N;
-  __shared__ Lds<N> s;
+  __shared__ LdsDec<N> s;
   TileCoord tc;
   if (!locate<N>(jr, tc)) return;
   const FrameJob& job = *tc.job;
@@ -502,14 +545,14 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
     const int k = r;
     const int qP = job.qp + 6 * (B - 8);
     const Dequant dqp = dequant_params(qP, B + L2N - 5);
-    uint32_t* row = (uint32_t*)s.TD[c][b][k];
+    uint32_t dpair[N / 2];
 #pragma unroll
     for (int m = 0; m < N / 2; m++) {
       const int d0 = dequant(s.L[c][b][(2 * m) * N + k], dqp);
       const int d1 = dequant(s.L[c][b][(2 * m + 1) * N + k], dqp);
-      row[m] = ((uint32_t)d0 & 0xffffu) | ((uint32_t)d1 << 16);
+      dpair[m] = ((uint32_t)d0 & 0xffffu) | ((uint32_t)d1 << 16);
     }
-    inverse_column<N>(inv, row, s.E[c][b], k);
+    inverse_column<N>(inv, dpair, s.E[c][b], k);
   }
   __syncthreads();
   if (vb) {
