@@ -525,30 +525,35 @@ __global__ void __launch_bounds__(kThreads) phys_reduce_kernel(PhysArgs a) {
   if (threadIdx.x == 0) a.out[b] = sred[0];
 }
 
-// Per-group totals of the transform kernel's per-tile sums: block g sums the
-// T * tpf tiles of group g for each of the 5 quantities with a fixed
-// assignment of tiles to threads and a fixed tree.
+// Per-group totals of the transform kernel's per-tile sums: block (g, i)
+// sums quantity i over the T * tpf tiles of group g with a fixed assignment
+// of tiles to threads (8 loads in flight per thread) and a fixed tree.
 __global__ void __launch_bounds__(kThreads) encode_totals_kernel(
     const unsigned long long* part, int T, int tpf, unsigned long long* sse,
     unsigned long long* bits) {
   __shared__ unsigned long long sred[kThreads];
-  const int g = blockIdx.x;
+  const int g = blockIdx.x / 5, i = blockIdx.x - g * 5;
   const int64_t n = (int64_t)T * tpf;
-  const unsigned long long* pg = part + (int64_t)g * n * 5;
-  for (int i = 0; i < 5; i++) {
-    unsigned long long v = 0;
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) v += pg[j * 5 + i];
-    sred[threadIdx.x] = v;
+  const unsigned long long* pg = part + (int64_t)g * n * 5 + i;
+  unsigned long long v = 0;
+  int64_t j = threadIdx.x;
+  for (; j + 7 * kThreads < n; j += 8 * kThreads) {
+    unsigned long long w[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) w[u] = pg[(j + u * kThreads) * 5];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v += w[u];
+  }
+  for (; j < n; j += kThreads) v += pg[j * 5];
+  sred[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
     __syncthreads();
-    for (int w = kThreads / 2; w >= 1; w >>= 1) {
-      if ((int)threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      if (i < 3) sse[3 * g + i] = sred[0];
-      else bits[2 * g + i - 3] = sred[0];
-    }
-    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (i < 3) sse[3 * g + i] = sred[0];
+    else bits[2 * g + i - 3] = sred[0];
   }
 }
 
@@ -609,7 +614,7 @@ hipError_t launch_plan(const CubePlan& p, hipStream_t s) {
 hipError_t launch_encode_totals(const unsigned long long* part, int G, int T, int tpf,
                                 unsigned long long* sse, unsigned long long* bits, hipStream_t s) {
   if (G <= 0) return hipSuccess;
-  encode_totals_kernel<<<G, kThreads, 0, s>>>(part, T, tpf, sse, bits);
+  encode_totals_kernel<<<G * 5, kThreads, 0, s>>>(part, T, tpf, sse, bits);
   return hipGetLastError();
 }
 
