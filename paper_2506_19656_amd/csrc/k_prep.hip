@@ -525,6 +525,315 @@ __global__ void __launch_bounds__(kThreads) phys_reduce_kernel(PhysArgs a) {
   if (threadIdx.x == 0) a.out[b] = sred[0];
 }
 
+// ---------------------------------------------------------------------------
+// Pixel-group kernels for up to 8 bands.  A thread owns g consecutive pixels
+// of a row, g the smallest count whose bands fill whole 16-byte granules
+// (6 float bands: 2 pixels, 48 bytes), so the pixel-major side is read or
+// written with aligned 16-byte accesses straight into registers, and each
+// channel plane sees g consecutive samples per thread.  Used when the data
+// pointer is 16-byte aligned and the row width is a multiple of g; the
+// row-staged kernels above cover every other case.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int gcd_c(int x, int y) { return y == 0 ? x : gcd_c(y, x % y); }
+
+template <typename T, int BANDS>
+struct PixGroup {
+  static constexpr int bpp = BANDS * (int)sizeof(T);  // bytes per pixel
+  static constexpr int g = 16 / gcd_c(16, bpp);      // pixels per group
+  static constexpr int nv = g * bpp / 16;            // 16-byte granules per group
+  static constexpr int ne = g * BANDS;               // elements per group
+};
+
+template <typename T, int NE>
+__device__ inline void load_granules(const T* __restrict__ p, T (&v)[NE]) {
+  constexpr int nv = NE * (int)sizeof(T) / 16;
+  uint4 w[nv];
+#pragma unroll
+  for (int i = 0; i < nv; i++) w[i] = ((const uint4*)p)[i];
+  __builtin_memcpy(v, w, sizeof w);
+}
+
+template <typename T, int NE>
+__device__ inline void store_granules(T* __restrict__ p, const T (&v)[NE]) {
+  constexpr int nv = NE * (int)sizeof(T) / 16;
+  uint4 w[nv];
+  __builtin_memcpy(w, v, sizeof w);
+#pragma unroll
+  for (int i = 0; i < nv; i++) ((uint4*)p)[i] = w[i];
+}
+
+// g consecutive u16 samples (or bytes) of a plane, one access when aligned.
+template <int G, typename T>
+__device__ inline void load_run_g(const T* __restrict__ p, T (&q)[G], bool aligned) {
+  if (aligned && G * sizeof(T) >= 2 && G * sizeof(T) <= 16) {
+    if constexpr (G * sizeof(T) == 16) {
+      const uint4 w = *(const uint4*)p;
+      __builtin_memcpy(q, &w, 16);
+      return;
+    } else if constexpr (G * sizeof(T) == 8) {
+      const uint2 w = *(const uint2*)p;
+      __builtin_memcpy(q, &w, 8);
+      return;
+    } else if constexpr (G * sizeof(T) == 4) {
+      const uint32_t w = *(const uint32_t*)p;
+      __builtin_memcpy(q, &w, 4);
+      return;
+    } else if constexpr (G * sizeof(T) == 2) {
+      const uint16_t w = *(const uint16_t*)p;
+      __builtin_memcpy(q, &w, 2);
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < G; i++) q[i] = p[i];
+}
+
+template <int G, typename T>
+__device__ inline void store_run_g(T* __restrict__ p, const T (&q)[G], bool aligned, int n) {
+  if (aligned && n == G) {
+    if constexpr (G * sizeof(T) == 16) {
+      uint4 w;
+      __builtin_memcpy(&w, q, 16);
+      *(uint4*)p = w;
+      return;
+    } else if constexpr (G * sizeof(T) == 8) {
+      uint2 w;
+      __builtin_memcpy(&w, q, 8);
+      *(uint2*)p = w;
+      return;
+    } else if constexpr (G * sizeof(T) == 4) {
+      uint32_t w;
+      __builtin_memcpy(&w, q, 4);
+      *(uint32_t*)p = w;
+      return;
+    } else if constexpr (G * sizeof(T) == 2) {
+      uint16_t w;
+      __builtin_memcpy(&w, q, 2);
+      *(uint16_t*)p = w;
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < G; i++)
+    if (i < n) p[i] = q[i];
+}
+
+// Conversion and packing of one pixel group per thread over the padded
+// frame (rows past H replicate row H - 1, columns past W column W - 1).
+template <typename Tv, int BANDS>
+__global__ void __launch_bounds__(kThreads) pack_vec_kernel(PackArgs a) {
+  using PG = PixGroup<Tv, BANDS>;
+  constexpr int G = PG::g;
+  __shared__ double smn[BANDS], srg[BANDS];
+  __shared__ int sall[BANDS];
+  const bool gaps = sizeof(Tv) == 4 && *a.nan_total != 0u;
+  if (threadIdx.x < BANDS) {
+    const int i = threadIdx.x;
+    smn[i] = a.mn[i];
+    srg[i] = a.mx[i] - a.mn[i];
+    sall[i] = gaps && (int64_t)a.nan_count[i] == a.T * a.H * a.W;
+  }
+  __syncthreads();
+  const int gpr = (a.Wp + G - 1) / G;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= a.T * a.Hp * gpr) return;
+  const int64_t row = gid / gpr;
+  const int x0 = (int)(gid - row * gpr) * G;
+  const int64_t t = row / a.Hp;
+  const int y = (int)(row - t * a.Hp);
+  const int64_t ys = y < a.H ? y : a.H - 1;
+  const Tv* d = (const Tv*)a.data;
+  const int64_t fstride = a.H * a.W * BANDS;
+  const Tv* src = d + t * fstride + ys * a.W * BANDS;
+  Tv v[PG::ne];
+  if (x0 + G <= a.W) {
+    load_granules<Tv, PG::ne>(src + (int64_t)x0 * BANDS, v);
+  } else {
+#pragma unroll
+    for (int p = 0; p < G; p++) {
+      const int xs = min(x0 + p, (int)a.W - 1);
+#pragma unroll
+      for (int b = 0; b < BANDS; b++) v[p * BANDS + b] = src[(int64_t)xs * BANDS + b];
+    }
+  }
+  const double L = (double)((1 << a.bit_depth) - 1);
+  uint16_t q[BANDS][G];
+  uint8_t ok[BANDS][G];
+#pragma unroll
+  for (int p = 0; p < G; p++) {
+    double dv[8];
+    uint32_t miss = 0u;
+#pragma unroll
+    for (int b = 0; b < BANDS; b++) {
+      if constexpr (sizeof(Tv) == 2) {
+        dv[b] = (double)v[p * BANDS + b];
+      } else {
+        const float f = v[p * BANDS + b];
+        const bool nan = f != f;
+        dv[b] = nan ? smn[b] : (double)f;
+        miss |= (nan && !sall[b]) ? (1u << b) : 0u;
+      }
+    }
+    const bool real = y < a.H && x0 + p < a.W;
+    if constexpr (sizeof(Tv) == 4) {
+      if (miss) {
+        const int xs = min(x0 + p, (int)a.W - 1);
+        fill_missing((const float*)d, (ys * a.W + xs) * BANDS, BANDS, fstride, t, a.T,
+                     a.fill_mode, miss, dv);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < BANDS; b++) {
+      q[b][p] = convert(dv[b], smn[b], srg[b], L);
+      bool valid = true;
+      if constexpr (sizeof(Tv) == 4) {
+        const float f = v[p * BANDS + b];
+        valid = f == f;
+      }
+      ok[b][p] = (uint8_t)(valid && real);
+    }
+  }
+  const int64_t plane = (int64_t)a.Hp * a.Wp;
+  const int64_t o = (int64_t)y * a.Wp + x0;
+  const bool al = (a.Wp % G) == 0;
+  const int n = min(G, a.Wp - x0);
+#pragma unroll
+  for (int b = 0; b < BANDS; b++) {
+    const int g = b / 3, c = b - 3 * g;
+    const int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
+    store_run_g<G>(a.frames + off, q[b], al, n);
+    if (gaps) store_run_g<G>(a.vmask + off, ok[b], al, n);
+  }
+  constexpr int GL = (BANDS - 1) / 3;  // last group
+  uint16_t z[G];
+  uint8_t zm[G];
+#pragma unroll
+  for (int p = 0; p < G; p++) {
+    z[p] = a.pad_mode == XV_PAD_REPEAT ? q[BANDS - 1][p] : (uint16_t)0;
+    zm[p] = 0;
+  }
+#pragma unroll
+  for (int c = BANDS - 3 * GL; c < 3; c++) {
+    const int64_t off = ((int64_t)(GL * a.T + t) * 3 + c) * plane + o;
+    store_run_g<G>(a.frames + off, z, al, n);
+    if (gaps) store_run_g<G>(a.vmask + off, zm, al, n);
+  }
+}
+
+// Decoded frames back to the caller's dtype, one pixel group per thread.
+template <typename To, int BANDS>
+__global__ void __launch_bounds__(kThreads) denorm_vec_kernel(DenormArgs a) {
+  using PG = PixGroup<To, BANDS>;
+  constexpr int G = PG::g;
+  __shared__ double smn[BANDS], srg[BANDS];
+  if (threadIdx.x < BANDS) {
+    smn[threadIdx.x] = a.mn[threadIdx.x];
+    srg[threadIdx.x] = a.mx[threadIdx.x] - a.mn[threadIdx.x];
+  }
+  __syncthreads();
+  const int gpr = (int)(a.W / G);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= a.T * a.H * gpr) return;
+  const int64_t row = gid / gpr;
+  const int x0 = (int)(gid - row * gpr) * G;
+  const int64_t t = row / a.H;
+  const int64_t y = row - t * a.H;
+  const int64_t plane = (int64_t)a.Hp * a.Wp;
+  const bool al = (a.Wp % G) == 0;
+  const double L = (double)((1 << a.bit_depth) - 1);
+  uint16_t q[BANDS][G];
+#pragma unroll
+  for (int b = 0; b < BANDS; b++) {
+    const int g = b / 3, c = b - 3 * g;
+    load_run_g<G>(a.recon + ((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x0, q[b], al);
+  }
+  To v[PG::ne];
+#pragma unroll
+  for (int p = 0; p < G; p++) {
+#pragma unroll
+    for (int b = 0; b < BANDS; b++) {
+      const double num = (double)q[b][p] * srg[b];
+      const double x = smn[b] + num / L;
+      if constexpr (sizeof(To) == 2) {
+        double rr = floor(x + 0.5);
+        rr = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
+        v[p * BANDS + b] = (To)rr;
+      } else {
+        v[p * BANDS + b] = (To)x;
+      }
+    }
+  }
+  store_granules<To, PG::ne>((To*)a.out + (row * a.W + x0) * BANDS, v);
+}
+
+// Physical squared error, one pixel group per thread and step of a
+// grid-stride loop; per-band sums in registers, fixed LDS tree per block.
+template <typename Tv, int BANDS>
+__global__ void __launch_bounds__(kThreads) phys_vec_kernel(PhysArgs a) {
+  using PG = PixGroup<Tv, BANDS>;
+  constexpr int G = PG::g;
+  __shared__ double sred[kThreads];
+  __shared__ double smn[BANDS], srg[BANDS];
+  if (threadIdx.x < BANDS) {
+    smn[threadIdx.x] = a.mn[threadIdx.x];
+    srg[threadIdx.x] = a.mx[threadIdx.x] - a.mn[threadIdx.x];
+  }
+  __syncthreads();
+  const int gpr = (int)(a.W / G);
+  const int64_t total = a.T * a.H * gpr;
+  const int64_t plane = (int64_t)a.Hp * a.Wp;
+  const bool al = (a.Wp % G) == 0;
+  const double L = (double)((1 << a.bit_depth) - 1);
+  const Tv* orig = (const Tv*)a.orig;
+  double acc[BANDS];
+#pragma unroll
+  for (int b = 0; b < BANDS; b++) acc[b] = 0.0;
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+       gid += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = gid / gpr;
+    const int x0 = (int)(gid - row * gpr) * G;
+    const int64_t t = row / a.H;
+    const int64_t y = row - t * a.H;
+    Tv v[PG::ne];
+    load_granules<Tv, PG::ne>(orig + (row * a.W + x0) * BANDS, v);
+    uint16_t q[BANDS][G];
+#pragma unroll
+    for (int b = 0; b < BANDS; b++) {
+      const int g = b / 3, c = b - 3 * g;
+      load_run_g<G>(a.recon + ((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x0, q[b], al);
+    }
+#pragma unroll
+    for (int p = 0; p < G; p++) {
+#pragma unroll
+      for (int b = 0; b < BANDS; b++) {
+        const double xv = (double)v[p * BANDS + b];
+        const double num = (double)q[b][p] * srg[b];
+        const double x = smn[b] + num / L;
+        double xh;
+        if constexpr (sizeof(Tv) == 2) {
+          const double rr = floor(x + 0.5);
+          xh = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
+        } else {
+          xh = (double)(float)x;
+        }
+        const double e = xv - xh;
+        acc[b] = (xv == xv) ? acc[b] + e * e : acc[b];
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < BANDS; b++) {
+    sred[threadIdx.x] = acc[b];
+    __syncthreads();
+    for (int w = kThreads / 2; w >= 1; w >>= 1) {
+      if ((int)threadIdx.x < w) sred[threadIdx.x] = sred[threadIdx.x] + sred[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.partial[(int64_t)blockIdx.x * BANDS + b] = sred[0];
+    __syncthreads();
+  }
+}
+
 // Per-group totals of the transform kernel's per-tile sums: block (g, i)
 // sums quantity i over the T * tpf tiles of group g with a fixed assignment
 // of tiles to threads (8 loads in flight per thread) and a fixed tree.
@@ -681,7 +990,38 @@ hipError_t launch_stats(const StatsArgs& in, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Pixels per group of the pixel-group kernels for (element size, bands).
+int group_px(int elem, int bands) { return 16 / gcd_int(16, bands * elem); }
+
+#define XV_BANDS_SWITCH(bands, CALL) \
+  switch (bands) {                   \
+    case 1: CALL(1); break;          \
+    case 2: CALL(2); break;          \
+    case 3: CALL(3); break;          \
+    case 4: CALL(4); break;          \
+    case 5: CALL(5); break;          \
+    case 6: CALL(6); break;          \
+    case 7: CALL(7); break;          \
+    default: CALL(8); break;         \
+  }
+
 hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
+  const int elem = a.dtype == XV_U16 ? 2 : 4;
+  const int g = group_px(elem, a.bands);
+  if (a.bands <= 8 && ((uintptr_t)a.data & 15) == 0 && a.W % g == 0) {
+    const int64_t n = a.T * a.Hp * (int64_t)((a.Wp + g - 1) / g);
+    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
+    if (a.dtype == XV_U16) {
+#define XV_CALL(B) pack_vec_kernel<uint16_t, B><<<grid, kThreads, 0, s>>>(a)
+      XV_BANDS_SWITCH(a.bands, XV_CALL)
+#undef XV_CALL
+    } else {
+#define XV_CALL(B) pack_vec_kernel<float, B><<<grid, kThreads, 0, s>>>(a)
+      XV_BANDS_SWITCH(a.bands, XV_CALL)
+#undef XV_CALL
+    }
+    return hipGetLastError();
+  }
   const int P = a.chunk_px;
   const int64_t blocks = a.T * a.Hp * (int64_t)((a.Wp + P - 1) / P);
   if (a.dtype == XV_U16)
@@ -692,6 +1032,22 @@ hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_denorm(const DenormArgs& a, hipStream_t s) {
+  const int elem = a.out_dtype == XV_U16 ? 2 : 4;
+  const int g = group_px(elem, a.bands);
+  if (a.bands <= 8 && ((uintptr_t)a.out & 15) == 0 && a.W % g == 0) {
+    const int64_t n = a.T * a.H * (a.W / g);
+    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
+    if (a.out_dtype == XV_U16) {
+#define XV_CALL(B) denorm_vec_kernel<uint16_t, B><<<grid, kThreads, 0, s>>>(a)
+      XV_BANDS_SWITCH(a.bands, XV_CALL)
+#undef XV_CALL
+    } else {
+#define XV_CALL(B) denorm_vec_kernel<float, B><<<grid, kThreads, 0, s>>>(a)
+      XV_BANDS_SWITCH(a.bands, XV_CALL)
+#undef XV_CALL
+    }
+    return hipGetLastError();
+  }
   const int P = a.chunk_px;
   const int64_t blocks = a.T * a.H * ((a.W + P - 1) / P);
   if (a.out_dtype == XV_U16)
@@ -707,10 +1063,23 @@ int phys_blocks(int64_t npix) {
 }
 
 hipError_t launch_phys_sse(const PhysArgs& a, hipStream_t s) {
-  if (a.dtype == XV_U16)
+  const int elem = a.dtype == XV_U16 ? 2 : 4;
+  const int g = group_px(elem, a.bands);
+  if (a.bands <= 8 && ((uintptr_t)a.orig & 15) == 0 && a.W % g == 0) {
+    if (a.dtype == XV_U16) {
+#define XV_CALL(B) phys_vec_kernel<uint16_t, B><<<a.nblocks, kThreads, 0, s>>>(a)
+      XV_BANDS_SWITCH(a.bands, XV_CALL)
+#undef XV_CALL
+    } else {
+#define XV_CALL(B) phys_vec_kernel<float, B><<<a.nblocks, kThreads, 0, s>>>(a)
+      XV_BANDS_SWITCH(a.bands, XV_CALL)
+#undef XV_CALL
+    }
+  } else if (a.dtype == XV_U16) {
     phys_sse_kernel<uint16_t><<<a.nblocks, kThreads, stage_bytes(a.chunk_px, a.bands, 2), s>>>(a);
-  else
+  } else {
     phys_sse_kernel<float><<<a.nblocks, kThreads, stage_bytes(a.chunk_px, a.bands, 4), s>>>(a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   phys_reduce_kernel<<<a.bands, kThreads, 0, s>>>(a);
