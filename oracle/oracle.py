@@ -118,6 +118,12 @@ def lib():
         L.xvo_bpppb.restype = C.c_double
         L.xvo_phys_sse.argtypes = [p, C.c_int, i64, i64, i64, i64, p, C.c_int, C.c_int,
                                    p, p, p]
+        L.xvo_bitstream_bits.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, p, p]
+        L.xvo_bitstream_bits.restype = C.c_uint64
+        L.xvo_write_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, p, p, p,
+                                          C.c_uint64, p]
+        L.xvo_read_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, p, C.c_uint64,
+                                         p, p, p]
         if L.xvo_selfcheck() != 0:
             raise RuntimeError("oracle requires arithmetic right shifts")
         _lib = L
@@ -344,6 +350,41 @@ def encode_cube(cube: np.ndarray, params: CodingParams) -> dict:
         raise ValueError(f"xvo_encode_cube failed ({rc})")
     o.update(mn=mn, mx=mx, sse=sse, nvalid=nv)
     return o
+
+
+def write_bitstream(levels: np.ndarray, mvs: np.ndarray, gop: int) -> dict:
+    """xvo_write_bitstream: levels [G][T][3][Hb][Wb][N][N] i16 and vectors
+    [G][T][Hb][Wb][2] i8 -> payload bytes, its length in bits and the bit
+    offset of every segment (4 * Hb per frame)."""
+    G, T, _, Hb, Wb, N, _ = levels.shape
+    levels = np.ascontiguousarray(levels, np.int16)
+    mvs = np.ascontiguousarray(mvs, np.int8)
+    bits = int(lib().xvo_bitstream_bits(N, G, T, gop, Hb, Wb, _ptr(levels), _ptr(mvs)))
+    nbytes = (bits + 7) // 8
+    out = np.zeros(max(1, nbytes), np.uint8)
+    index = np.zeros(G * T * 4 * Hb, np.uint64)
+    rc = lib().xvo_write_bitstream(N, G, T, gop, Hb, Wb, _ptr(levels), _ptr(mvs), _ptr(out),
+                                   out.size, _ptr(index))
+    if rc != 0:
+        raise ValueError(f"xvo_write_bitstream failed ({rc})")
+    return dict(payload=out[:nbytes], bits=bits, index=index)
+
+
+def read_bitstream(payload: np.ndarray, bits: int, shape_lev, gop: int) -> dict:
+    """xvo_read_bitstream: sequential parse back to levels and vectors; also
+    returns the segment offsets met."""
+    G, T, _, Hb, Wb, N, _ = shape_lev
+    levels = np.zeros(shape_lev, np.int16)
+    mvs = np.zeros((G, T, Hb, Wb, 2), np.int8)
+    index = np.zeros(G * T * 4 * Hb, np.uint64)
+    buf = np.ascontiguousarray(payload, np.uint8)
+    if buf.size == 0:
+        buf = np.zeros(1, np.uint8)
+    rc = lib().xvo_read_bitstream(N, G, T, gop, Hb, Wb, _ptr(buf), bits, _ptr(levels),
+                                  _ptr(mvs), _ptr(index))
+    if rc != 0:
+        raise ValueError(f"xvo_read_bitstream failed ({rc})")
+    return dict(levels=levels, mvs=mvs, index=index)
 
 
 def decode_cube(params: CodingParams, shape, levels, mvs) -> np.ndarray:

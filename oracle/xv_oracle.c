@@ -381,6 +381,212 @@ uint32_t xvo_mv_bits(int mvx, int mvy, int pmx, int pmy) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Bitstream.  The codes the rate proxy counts, written out MSB-first:        */
+/* ue(k) = floor(log2(k+1)) zero bits followed by k+1 in binary; se(v) maps   */
+/* v > 0 to 2v - 1 and v <= 0 to -2v (the Exp-Golomb codes of ITU-T H.265    */
+/* clause 9.2, which the rate proxy's lengths are the lengths of).            */
+/* Order, frame by frame (f = g * T + t):                                     */
+/*   the Hb block rows of vectors: per block, se(dx - pdx) then se(dy - pdy), */
+/*   pdx/pdy the left neighbour's vector, (0,0) in column 0; nothing for an   */
+/*   I frame;                                                                 */
+/*   for channel c = 0, 1, 2 the Hb block rows of coefficients: per block the */
+/*   coded flag (1 bit, set when a level is nonzero), then ue(nnz - 1) and,   */
+/*   per nonzero level in up-right diagonal scan order, ue(run) and          */
+/*   se(level).                                                               */
+/* Each block row is a segment; the bit offset of every segment is recorded  */
+/* so that rows can be parsed independently.  The code lengths are exactly   */
+/* the rate proxy's, so the payload holds coef_bits + mv_bits bits.          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  uint8_t* buf;
+  uint64_t cap_bits;
+  uint64_t pos;
+  int overflow;
+} bit_writer;
+
+static void put_bit(bit_writer* w, int b) {
+  if (w->pos >= w->cap_bits) {
+    w->overflow = 1;
+    return;
+  }
+  if (b) w->buf[w->pos >> 3] |= (uint8_t)(0x80u >> (w->pos & 7));
+  w->pos++;
+}
+
+static void put_ue(bit_writer* w, uint32_t k) {
+  uint64_t v = (uint64_t)k + 1;
+  int m = 0;
+  while ((v >> m) > 1) m++;
+  for (int i = 0; i < m; i++) put_bit(w, 0);
+  for (int i = m; i >= 0; i--) put_bit(w, (int)((v >> i) & 1));
+}
+
+static void put_se(bit_writer* w, int32_t v) {
+  put_ue(w, v > 0 ? (uint32_t)(2 * (int64_t)v - 1) : (uint32_t)(-2 * (int64_t)v));
+}
+
+typedef struct {
+  const uint8_t* buf;
+  uint64_t bits;
+  uint64_t pos;
+  int overrun;
+} bit_reader;
+
+static int get_bit(bit_reader* r) {
+  if (r->pos >= r->bits) {
+    r->overrun = 1;
+    return 0;
+  }
+  int b = (r->buf[r->pos >> 3] >> (7 - (r->pos & 7))) & 1;
+  r->pos++;
+  return b;
+}
+
+static uint32_t get_ue(bit_reader* r) {
+  int m = 0;
+  while (!r->overrun && get_bit(r) == 0) {
+    m++;
+    if (m > 32) {
+      r->overrun = 1;
+      return 0;
+    }
+  }
+  uint64_t v = 1;
+  for (int i = 0; i < m; i++) v = (v << 1) | (uint64_t)get_bit(r);
+  return (uint32_t)(v - 1);
+}
+
+static int32_t get_se(bit_reader* r) {
+  uint32_t k = get_ue(r);
+  return (k & 1) ? (int32_t)((k + 1) / 2) : -(int32_t)(k / 2);
+}
+
+uint64_t xvo_bitstream_bits(int N, int64_t G, int64_t T, int gop, int64_t Hb,
+                            int64_t Wb, const int16_t* levels, const int8_t* mvs) {
+  uint64_t bits = 0;
+  for (int64_t f = 0; f < G * T; f++) {
+    int intra = (f % T) % gop == 0;
+    for (int64_t by = 0; by < Hb; by++) {
+      int pmx = 0, pmy = 0;
+      for (int64_t bx = 0; bx < Wb; bx++) {
+        const int8_t* mv = mvs + ((f * Hb + by) * Wb + bx) * 2;
+        if (!intra) bits += xvo_mv_bits(mv[0], mv[1], pmx, pmy);
+        pmx = mv[0];
+        pmy = mv[1];
+      }
+    }
+    for (int64_t i = 0; i < 3 * Hb * Wb; i++)
+      bits += xvo_coef_bits(N, levels + (f * 3 * Hb * Wb + i) * N * N);
+  }
+  return bits;
+}
+
+int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
+                        int64_t Wb, const int16_t* levels, const int8_t* mvs,
+                        uint8_t* out, uint64_t out_bytes, uint64_t* index) {
+  int32_t order[32 * 32];
+  xvo_scan_order(N, order);
+  memset(out, 0, out_bytes);
+  bit_writer w = {out, out_bytes * 8, 0, 0};
+  int64_t seg = 0;
+  for (int64_t f = 0; f < G * T; f++) {
+    int intra = (f % T) % gop == 0;
+    for (int64_t by = 0; by < Hb; by++) {
+      index[seg++] = w.pos;
+      int pmx = 0, pmy = 0;
+      for (int64_t bx = 0; bx < Wb; bx++) {
+        const int8_t* mv = mvs + ((f * Hb + by) * Wb + bx) * 2;
+        if (!intra) {
+          put_se(&w, mv[0] - pmx);
+          put_se(&w, mv[1] - pmy);
+        }
+        pmx = mv[0];
+        pmy = mv[1];
+      }
+    }
+    for (int c = 0; c < 3; c++)
+      for (int64_t by = 0; by < Hb; by++) {
+        index[seg++] = w.pos;
+        for (int64_t bx = 0; bx < Wb; bx++) {
+          const int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + by * Wb + bx) * N * N;
+          int nnz = 0;
+          for (int i = 0; i < N * N; i++) nnz += lev[i] != 0;
+          put_bit(&w, nnz > 0);
+          if (nnz == 0) continue;
+          put_ue(&w, (uint32_t)(nnz - 1));
+          int run = 0;
+          for (int i = 0; i < N * N; i++) {
+            int16_t v = lev[order[i]];
+            if (v == 0) {
+              run++;
+              continue;
+            }
+            put_ue(&w, (uint32_t)run);
+            put_se(&w, v);
+            run = 0;
+          }
+        }
+      }
+  }
+  return w.overflow ? -1 : 0;
+}
+
+/* Sequential parse of the whole stream; index (may be NULL) receives the
+ * segment offsets met on the way.  Levels not listed are zero; I frames get
+ * the vector (0,0). */
+int xvo_read_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
+                       int64_t Wb, const uint8_t* in, uint64_t bits,
+                       int16_t* levels, int8_t* mvs, uint64_t* index) {
+  int32_t order[32 * 32];
+  xvo_scan_order(N, order);
+  bit_reader r = {in, bits, 0, 0};
+  int64_t seg = 0;
+  memset(levels, 0, (size_t)(G * T * 3 * Hb * Wb * N * N) * sizeof(int16_t));
+  for (int64_t f = 0; f < G * T; f++) {
+    int intra = (f % T) % gop == 0;
+    for (int64_t by = 0; by < Hb; by++) {
+      if (index) index[seg] = r.pos;
+      seg++;
+      int pmx = 0, pmy = 0;
+      for (int64_t bx = 0; bx < Wb; bx++) {
+        int8_t* mv = mvs + ((f * Hb + by) * Wb + bx) * 2;
+        int dx = 0, dy = 0;
+        if (!intra) {
+          dx = pmx + get_se(&r);
+          dy = pmy + get_se(&r);
+        }
+        mv[0] = (int8_t)dx;
+        mv[1] = (int8_t)dy;
+        pmx = dx;
+        pmy = dy;
+      }
+    }
+    for (int c = 0; c < 3; c++)
+      for (int64_t by = 0; by < Hb; by++) {
+        if (index) index[seg] = r.pos;
+        seg++;
+        for (int64_t bx = 0; bx < Wb; bx++) {
+          int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + by * Wb + bx) * N * N;
+          if (!get_bit(&r)) continue;
+          int nnz = (int)get_ue(&r) + 1;
+          int p = -1;
+          for (int k = 0; k < nnz && !r.overrun; k++) {
+            p += (int)get_ue(&r) + 1;
+            int32_t v = get_se(&r);
+            if (p >= N * N) {
+              r.overrun = 1;
+              break;
+            }
+            lev[order[p]] = (int16_t)v;
+          }
+        }
+      }
+  }
+  if (r.overrun) return -1;
+  return r.pos == bits ? 0 : -2;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Full-search integer-pel motion estimation (paper silent; reading: one      */
 /* vector per N x N block shared by the group's 3 channels, SAD summed over   */
 /* the group's channels that carry a real band (c < nch; padding channels do  */

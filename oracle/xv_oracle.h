@@ -86,6 +86,19 @@ void xvo_denormalize_cube(const uint16_t* recon, int64_t T, int64_t H,
                           int64_t W, int64_t Bn, int N, int B, const double* mn,
                           const double* mx, int out_dtype, void* out);
 
+/* Bitstream: the rate proxy's Exp-Golomb codes written out (see the
+ * comment above xvo_write_bitstream for the order).  nframes = G * T frames,
+ * frame f = g * T + t, intra when t % gop == 0.  index receives the bit
+ * offset of each of the 4 * Hb segments per frame. */
+uint64_t xvo_bitstream_bits(int N, int64_t G, int64_t T, int gop, int64_t Hb,
+                            int64_t Wb, const int16_t* levels, const int8_t* mvs);
+int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
+                        int64_t Wb, const int16_t* levels, const int8_t* mvs,
+                        uint8_t* out, uint64_t out_bytes, uint64_t* index);
+int xvo_read_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
+                       int64_t Wb, const uint8_t* in, uint64_t bits,
+                       int16_t* levels, int8_t* mvs, uint64_t* index);
+
 double xvo_psnr(double peak, double sse, double n);
 double xvo_psnr_int(int B, uint64_t sse, uint64_t n);
 double xvo_bpppb(uint64_t bits, int64_t T, int64_t H, int64_t W, int64_t Bn);

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_2506_19656_amd import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -561,3 +562,111 @@ def test_physical_sse_of_lossless_integer_recon():
     for b in range(3):
         step = (mx[b] - mn[b]) / 1023
         assert sse[b] <= cube[..., 0].size * (step / 2 + 0.5) ** 2
+
+
+# ---------------------------------------------------------------------------
+# Bitstream (the rate proxy's codes written out)
+# ---------------------------------------------------------------------------
+
+def _golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, *v = line.split()
+            out[k] = v
+    return out
+
+
+def test_bitstream_hand_example():
+    g = _golden("bitstream_example.txt")
+    lev = np.zeros((1, 1, 3, 1, 1, 4, 4), np.int16)
+    lev[0, 0, 0, 0, 0, 0, 0] = 3
+    lev[0, 0, 0, 0, 0, 0, 1] = -1
+    mv = np.zeros((1, 1, 1, 1, 2), np.int8)
+    w = O.write_bitstream(lev, mv, gop=16)
+    assert w["bits"] == int(g["bits"][0])
+    assert w["payload"].tobytes().hex() == g["bytes"][0]
+    assert w["index"].tolist() == [int(v) for v in g["index"]]
+
+
+def _random_stream(rng, N, G, T, Hb, Wb, density):
+    lev = np.zeros((G, T, 3, Hb, Wb, N, N), np.int16)
+    mask = rng.random(lev.shape) < density
+    vals = rng.integers(-300, 301, lev.shape).astype(np.int16)
+    vals[vals == 0] = 1
+    lev[mask] = vals[mask]
+    # a few extreme levels and whole-zero blocks
+    lev.reshape(-1)[rng.integers(0, lev.size, 4)] = 32767
+    lev.reshape(-1)[rng.integers(0, lev.size, 4)] = -32767
+    lev[0, 0, 1] = 0
+    mvs = rng.integers(-64, 65, (G, T, Hb, Wb, 2)).astype(np.int8)
+    return lev, mvs
+
+
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_bitstream_round_trip_and_length_is_the_rate_proxy(N):
+    rng = np.random.default_rng(N)
+    G, T, gop, Hb, Wb = 2, 5, 3, 2, 3
+    lev, mvs = _random_stream(rng, N, G, T, Hb, Wb, density=0.15)
+    for g in range(G):  # I frames carry the vector (0, 0)
+        for t in range(0, T, gop):
+            mvs[g, t] = 0
+    w = O.write_bitstream(lev, mvs, gop)
+    # length: the rate proxy's coefficient and vector bits, counted per block
+    expect = 0
+    for g in range(G):
+        for t in range(T):
+            for c in range(3):
+                for by in range(Hb):
+                    for bx in range(Wb):
+                        expect += O.coef_bits(lev[g, t, c, by, bx])
+            if t % gop:
+                for by in range(Hb):
+                    px = py = 0
+                    for bx in range(Wb):
+                        dx, dy = int(mvs[g, t, by, bx, 0]), int(mvs[g, t, by, bx, 1])
+                        expect += O.mv_bits(dx, dy, px, py)
+                        px, py = dx, dy
+    assert w["bits"] == expect
+    assert len(w["payload"]) == (expect + 7) // 8
+    r = O.read_bitstream(w["payload"], w["bits"], lev.shape, gop)
+    assert np.array_equal(r["levels"], lev)
+    assert np.array_equal(r["mvs"], mvs)
+    assert np.array_equal(r["index"], w["index"])
+
+
+def test_bitstream_single_level_blocks_match_an_explicit_writer():
+    # one nonzero level v at scan position p in channel 0 of a P frame with
+    # vector (dx, dy): vector codes, then 1 + ue(0) + ue(p) + se(v), then
+    # the two empty channels
+    rng = np.random.default_rng(5)
+    order = O.scan_order(8).tolist()
+    for _ in range(200):
+        p = int(rng.integers(0, 64))
+        v = int(rng.integers(-2000, 2001)) or 7
+        dx, dy = int(rng.integers(-20, 21)), int(rng.integers(-20, 21))
+        lev = np.zeros((1, 2, 3, 1, 1, 8, 8), np.int16)
+        mvs = np.zeros((1, 2, 1, 1, 2), np.int8)
+        lev[0, 1, 0, 0, 0].reshape(-1)[order[p]] = v
+        mvs[0, 1, 0, 0] = (dx, dy)
+        se = lambda x: _eg_write(2 * x - 1 if x > 0 else -2 * x)
+        bits = "000"  # I frame: three empty channels
+        bits += se(dx) + se(dy) + "1" + _eg_write(0) + _eg_write(p) + se(v) + "00"
+        w = O.write_bitstream(lev, mvs, gop=2)
+        assert w["bits"] == len(bits)
+        padded = bits + "0" * (-len(bits) % 8)
+        expect = bytes(int(padded[i:i + 8], 2) for i in range(0, len(padded), 8))
+        assert w["payload"].tobytes() == expect
+
+
+def test_bitstream_of_an_encoded_cube_has_the_encoders_bit_count():
+    host = synth.tiny_cube(seed=0, T=6, H=40, W=56, bands=4).numpy()
+    p = O.CodingParams(bit_depth=10, qp=27, block=8, search_range=4, gop=4)
+    enc = O.encode_cube(host, p)
+    w = O.write_bitstream(enc["levels"], enc["mvs"], p.gop)
+    assert w["bits"] == int(enc["coef_bits"].sum()) + int(enc["mv_bits"].sum())
+    r = O.read_bitstream(w["payload"], w["bits"], enc["levels"].shape, p.gop)
+    assert np.array_equal(r["levels"], enc["levels"]) and np.array_equal(r["mvs"], enc["mvs"])
