@@ -67,6 +67,62 @@ def cpu_baseline(cube_host, wl, seconds_hint=""):
                       f"{wl.bands} cube, encode+decode+metrics, {dt:.1f} s wall"}
 
 
+def bits_bench(xv, torch, cube, params, pxb_step, steps):
+    """Serialise the sweep's 15 encoded runs (xv_pack) and parse them back
+    (xv_unpack), timed per call on the host (each call synchronises once) and
+    per kernel with HIP events; checks that the parsed levels equal the
+    encoded ones."""
+    import numpy as np
+    encs = xv.encode_batch([cube] * len(params), params)
+    torch.cuda.synchronize()
+    packed = [xv.pack(e) for e in encs]  # warm-up
+    for u in [xv.unpack(p.tensor()) for p in packed]:
+        u.free()
+    for p in packed:
+        p.free()
+    xv.profile_enable(True)
+    t_pack = t_unpack = 0.0
+    payload = 0
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        packed = [xv.pack(e) for e in encs]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        unpacked = [xv.unpack(p.tensor()) for p in packed]
+        t2 = time.perf_counter()
+        t_pack += t1 - t0
+        t_unpack += t2 - t1
+        payload = sum(p.view()["payload_bits"] for p in packed)
+        for u in unpacked:
+            u.free()
+        for p in packed:
+            p.free()
+    prof = xv.profile_read()
+    xv.profile_enable(False)
+    same = all(np.array_equal(a.export()["levels"].cpu().numpy(),
+                              b.export()["levels"].cpu().numpy())
+               for a, b in [(encs[0], xv.unpack(xv.pack(encs[0]).tensor()))])
+    wr, pa = prof["bits_write"], prof["bits_parse"]
+    coded = sum(e.export()["levels"].numel() for e in encs)  # coded samples (levels read)
+    out = {"runs": len(encs), "payload_MB_per_step": round(payload / 8 / 1e6, 3),
+           "pack_ms_per_step": round(t_pack / steps * 1e3, 3),
+           "unpack_ms_per_step": round(t_unpack / steps * 1e3, 3),
+           "pack_Mpx_band_s": round(pxb_step * steps / t_pack / 1e6, 1),
+           "unpack_Mpx_band_s": round(pxb_step * steps / t_unpack / 1e6, 1),
+           "parsed_equals_encoded": bool(same)}
+    if wr["launches"]:
+        ms = wr["ms"] / steps
+        out["write_kernel_ms_per_step"] = round(ms, 3)
+        out["write_kernel_levels_GBs"] = round(coded * 2 / (ms * 1e-3) / 1e9, 1)
+    if pa["launches"]:
+        ms = pa["ms"] / steps
+        out["parse_kernel_ms_per_step"] = round(ms, 3)
+        out["parse_kernel_payload_GBs"] = round(payload / 8 / (ms * 1e-3) / 1e9, 2)
+    for e in encs:
+        e.free()
+    return out
+
+
 def serve_bench(xv, synth, torch, n=160, seed=4, loads=(0.5, 0.9, 1.2, 2.0)):
     """Serving mix: requests with the mix's recipe (encode or decode with
     p = 1/2, log-uniform sizes, bands {3, 4, 6}, QP 17..37, N = 16, R = 16)
@@ -163,6 +219,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["both", "batched", "plain"], default="both")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix section")
+    ap.add_argument("--no-bits", action="store_true", help="skip the bitstream section")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the motion-search geometry tuner (model defaults)")
     ap.add_argument("--geometry-file", default=None,
@@ -336,6 +393,9 @@ def main():
                              "avg_launch_ms": round(avg, 4), "launches": d["launches"]}
         line["kernel_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()
                                       if v["launches"]}
+    if not args.no_bits:
+        print("[bench] bitstream", file=sys.stderr, flush=True)
+        line["bitstream"] = bits_bench(xv, torch, cube, params, pxb_step, args.steps)
     if not args.no_serve:
         print("[bench] serving mix", file=sys.stderr, flush=True)
         line["served"] = serve_bench(xv, synth, torch)

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define XV_ABI_VERSION 1
+#define XV_ABI_VERSION 2
 
 /* status codes */
 #define XV_OK 0
@@ -293,7 +293,9 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
 #define XV_K_DECODE 4
 #define XV_K_DENORM 5
 #define XV_K_METRICS 6
-#define XV_K_COUNT 7
+#define XV_K_BITS_WRITE 7
+#define XV_K_BITS_PARSE 8
+#define XV_K_COUNT 9
 
 typedef struct {
   double ms[XV_K_COUNT];       /* summed kernel time per kernel class     */
@@ -308,6 +310,45 @@ typedef struct {
 int xv_profile_enable(int on);
 /* Synchronises the streams that were timed and returns the totals. */
 int xv_profile_read(xv_profile* out);
+
+/* ---- bitstream -------------------------------------------------------------
+ * The codes the rate proxy counts, written out: a serialised encoded cube.
+ * Codes are the Exp-Golomb ue/se codes of ITU-T H.265 clause 9.2, MSB-first.
+ * Payload order, frame by frame (f = g*T + t): the vectors of the frame's
+ * blocks in raster order (se(dx - pdx), se(dy - pdy) with the left
+ * neighbour's vector as predictor, (0,0) in column 0; nothing for I frames),
+ * then for channel c = 0, 1, 2 the blocks' coefficients in raster order (a
+ * coded-flag bit, then ue(nnz-1) and per nonzero level in up-right diagonal
+ * scan order ue(run), se(level)).  The payload has exactly coef_bits +
+ * mv_bits bits.  Every block row of vectors or of one channel's
+ * coefficients is a segment whose bit offset is stored, so rows parse in
+ * parallel.  Buffer layout (little-endian): a 256-byte header (magic
+ * "XVPACK01", dims, dtype, params, offsets), the metric span (band min/max,
+ * squared errors, valid counts, bit totals), the segment index (u64 bit
+ * offsets, 4*Hb per frame) and the payload bytes. */
+typedef struct xv_packed xv_packed;
+
+/* Serialise an encoded cube into one device buffer on hip_stream.
+ * Synchronises the stream once (the payload size comes from a device-side
+ * scan of the per-block bit counts).  *out is owned by the caller
+ * (xv_packed_free); e may be freed afterwards.  Errors: XV_EINVAL,
+ * XV_ENOMEM, XV_EHIP. */
+int xv_pack(const xv_encoded* e, void* hip_stream, xv_packed** out);
+/* Device pointer and size of the serialised buffer, and the payload length
+ * in bits (all outputs optional).  The buffer is valid until xv_packed_free
+ * and complete once the stream passed the xv_pack call. */
+int xv_packed_view(const xv_packed* p, const void** data, uint64_t* bytes,
+                   uint64_t* payload_bits);
+void xv_packed_free(xv_packed* p);
+/* Parse a serialised cube (device memory holding what xv_pack wrote, of
+ * `bytes` bytes; the caller keeps it alive during the call) into a new
+ * encoded cube: levels, vectors, per-block bit counts and the metric span,
+ * which xv_decode_cube and xv_psnr_bpppb accept (physical PSNR needs the
+ * encoder's reconstruction and is NaN here).  Synchronises hip_stream.
+ * Errors: XV_EINVAL for a header that does not describe a valid cube or a
+ * payload that does not parse as the codes above (nothing is written to
+ * *out then), XV_ENOMEM, XV_EHIP. */
+int xv_unpack(const void* data, uint64_t bytes, void* hip_stream, xv_encoded** out);
 
 /* ---- device memory ---------------------------------------------------------
  * Every device buffer of the library comes from one caching allocator per

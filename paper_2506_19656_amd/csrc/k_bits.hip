@@ -1,0 +1,347 @@
+// k_bits.hip -- the Exp-Golomb bitstream of an encoded cube: the codes the
+// rate proxy counts, written out, and parsed back.
+//
+// Code of a value: ue(k) is floor(log2(k+1)) zero bits followed by k+1 in
+// binary, se(v) is ue(2v - 1) for v > 0 and ue(-2v) otherwise (the
+// Exp-Golomb codes of ITU-T H.265 clause 9.2).  Bits are MSB-first in
+// bytes.  Stream order, frame by frame (f = g * T + t): the vector units of
+// the frame's blocks in raster order (se(dx - pdx), se(dy - pdy), the left
+// neighbour's vector as predictor, (0,0) in column 0; I frames have empty
+// vector units), then for channel c = 0, 1, 2 the coefficient units of the
+// blocks in raster order (coded flag, then ue(nnz - 1) and per nonzero level
+// in up-right diagonal scan order ue(run), se(level)).  A frame therefore
+// has 4 Hb Wb units; a row of Wb units is a segment, whose bit offset is
+// stored so that segments parse independently.
+//
+// Packing: the unit lengths are the per-block bit counts the transform
+// kernel already produced; an exclusive scan over them gives every unit its
+// offset and one thread per unit emits its codes.  Words a unit owns
+// completely are stored; the words it shares with its neighbours at either
+// end are OR-ed in atomically (the payload starts zeroed).
+// Parsing: one thread per segment.
+#include "xv_internal.h"
+
+namespace xv {
+
+namespace {
+
+constexpr int kBitsThreads = 256;
+
+// Length of unit u (stream order) from the per-block bit counts.
+__device__ inline uint32_t unit_len(const BitsArgs& a, int64_t u) {
+  const int64_t hw = (int64_t)a.Hb * a.Wb;
+  const int64_t f = u / (4 * hw);
+  const int64_t r = u - f * 4 * hw;
+  if (r < hw) return a.mbits[f * hw + r];
+  return a.cbits[f * 3 * hw + (r - hw)];
+}
+
+__device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
+  // fixed-order tree over the block
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kBitsThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const uint64_t s = red[0];
+  __syncthreads();
+  return s;
+}
+
+// Exclusive prefix sum over the block (Hillis-Steele in LDS).
+__device__ inline uint64_t block_exclusive_u64(uint64_t v, uint64_t* buf) {
+  buf[threadIdx.x] = v;
+  __syncthreads();
+  for (int d = 1; d < kBitsThreads; d <<= 1) {
+    const uint64_t add = (int)threadIdx.x >= d ? buf[threadIdx.x - d] : 0ull;
+    __syncthreads();
+    buf[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const uint64_t incl = buf[threadIdx.x];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(kBitsThreads) unit_block_sums_kernel(BitsArgs a) {
+  __shared__ uint64_t red[kBitsThreads];
+  const int64_t u = (int64_t)blockIdx.x * kBitsThreads + threadIdx.x;
+  const uint64_t len = u < a.nunits ? unit_len(a, u) : 0u;
+  const uint64_t s = block_sum_u64(len, red);
+  if (threadIdx.x == 0) a.block_off[blockIdx.x] = s;
+}
+
+// One workgroup turns the block sums into exclusive block offsets (in
+// place) and writes the total.
+__global__ void __launch_bounds__(1024) scan_block_sums_kernel(uint64_t* v, int64_t n,
+                                                               uint64_t* total) {
+  __shared__ uint64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b0 = t * per, b1 = min(n, b0 + per);
+  uint64_t s = 0;
+  for (int64_t i = b0; i < b1; i++) s += v[i];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint64_t add = t >= d ? part[t - d] : 0ull;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  uint64_t run = part[t] - s;
+  for (int64_t i = b0; i < b1; i++) {
+    const uint64_t x = v[i];
+    v[i] = run;
+    run += x;
+  }
+  if (t == 1023) *total = part[1023];
+}
+
+// Bit sink of one unit: pending bits in the low n bits of acc (earliest
+// first); complete words leave in stream order, byte-swapped so that memory
+// holds the stream's bytes in order.
+struct BitSink {
+  uint32_t* words;
+  uint64_t w;       // index of the word being filled
+  uint64_t acc;
+  int n;
+  bool first;       // the word being filled is shared with the previous unit
+
+  __device__ void emit(uint32_t word, bool shared) {
+    const uint32_t m = __builtin_bswap32(word);
+    if (shared)
+      atomicOr(&words[w], m);
+    else
+      words[w] = m;
+    w++;
+  }
+  __device__ void put(uint32_t v, int len) {  // len <= 32
+    acc = (acc << len) | v;
+    n += len;
+    if (n >= 32) {
+      emit((uint32_t)(acc >> (n - 32)), first);
+      first = false;
+      n -= 32;
+      acc &= (n ? ((1ull << n) - 1) : 0ull);
+    }
+  }
+  __device__ void ue(uint32_t k) {
+    const uint32_t v = k + 1;
+    const int m = 31 - __clz((int)v);
+    put(v, 2 * m + 1);
+  }
+  __device__ void se(int v) { ue(v > 0 ? (uint32_t)(2 * v - 1) : (uint32_t)(-2 * v)); }
+  __device__ void flush() {
+    if (n > 0) emit((uint32_t)(acc << (32 - n)), true);
+  }
+};
+
+__device__ inline void build_scan_table(uint16_t* scan, int N) {
+  for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+    const int y = i / N, x = i - (i / N) * N;
+    const int d = x + y;
+    const int before = d < N ? d * (d + 1) / 2 : N * N - (2 * N - 1 - d) * (2 * N - d) / 2;
+    const int first_x = d < N ? 0 : d - N + 1;
+    scan[before + x - first_x] = (uint16_t)i;
+  }
+}
+
+__global__ void __launch_bounds__(kBitsThreads) write_units_kernel(BitsArgs a) {
+  __shared__ uint64_t buf[kBitsThreads];
+  __shared__ uint16_t scan[32 * 32];
+  const int N = a.N;
+  build_scan_table(scan, N);
+  const int64_t u = (int64_t)blockIdx.x * kBitsThreads + threadIdx.x;
+  const uint64_t len = u < a.nunits ? unit_len(a, u) : 0u;
+  const uint64_t off = a.block_off[blockIdx.x] + block_exclusive_u64(len, buf);  // syncs
+  if (u >= a.nunits) return;
+  if (u % a.Wb == 0) a.index[u / a.Wb] = off;
+  if (len == 0) return;
+  BitSink bs{a.words, off >> 5, 0ull, (int)(off & 31), (off & 31) != 0};
+  const int64_t hw = (int64_t)a.Hb * a.Wb;
+  const int64_t f = u / (4 * hw);
+  const int64_t r = u - f * 4 * hw;
+  if (r < hw) {
+    const int8_t* mv = a.mvs + (f * hw + r) * 2;
+    int pmx = 0, pmy = 0;
+    if (r % a.Wb != 0) {
+      pmx = mv[-2];
+      pmy = mv[-1];
+    }
+    bs.se(mv[0] - pmx);
+    bs.se(mv[1] - pmy);
+  } else {
+    const int16_t* lev = a.levels + (f * 3 * hw + (r - hw)) * N * N;
+    int nnz = 0;
+    for (int i = 0; i < N * N; i += 8) {
+      const uint4 w = *(const uint4*)(lev + i);
+      const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int j = 0; j < 4; j++) nnz += ((q[j] & 0xffffu) != 0) + ((q[j] >> 16) != 0);
+    }
+    bs.put(nnz > 0 ? 1u : 0u, 1);
+    if (nnz > 0) {
+      bs.ue((uint32_t)(nnz - 1));
+      int run = 0, seen = 0;
+      for (int p = 0; p < N * N && seen < nnz; p++) {
+        const int v = lev[scan[p]];
+        if (v == 0) {
+          run++;
+          continue;
+        }
+        bs.ue((uint32_t)run);
+        bs.se(v);
+        run = 0;
+        seen++;
+      }
+    }
+  }
+  bs.flush();
+}
+
+// Bit source over the payload words (byte-swapped back to stream order).
+struct BitSource {
+  const uint32_t* words;
+  int64_t nwords;
+  uint64_t pos;
+
+  __device__ uint64_t window() const {  // the next 64 bits, MSB first
+    const int64_t w = min((int64_t)(pos >> 5), nwords - 2);
+    const uint64_t hi = __builtin_bswap32(words[w]);
+    const uint64_t lo = __builtin_bswap32(words[w + 1]);
+    return ((hi << 32) | lo) << (pos & 31);
+  }
+  __device__ int bit() {
+    const int b = (int)(window() >> 63);
+    pos++;
+    return b;
+  }
+  // ue(k): m leading zeros, then m + 1 bits holding k + 1; false on a code
+  // longer than any the writer emits.
+  __device__ bool ue(uint32_t& k) {
+    const uint64_t wv = window();
+    if (wv == 0) return false;
+    const int m = __clzll((long long)wv);
+    if (m > 16) return false;
+    const int len = 2 * m + 1;
+    k = (uint32_t)(wv >> (64 - len)) - 1u;
+    pos += len;
+    return true;
+  }
+  __device__ bool se(int& v) {
+    uint32_t k;
+    if (!ue(k)) return false;
+    v = (k & 1) ? (int)((k + 1) / 2) : -(int)(k / 2);
+    return true;
+  }
+};
+
+// One thread per segment (a row of Wb units).  Levels must be zero on entry.
+// Any inconsistency (a code no writer emits, a position past the block, a
+// vector out of range, a segment not ending where the next begins) sets
+// *err and stops that segment.
+__global__ void __launch_bounds__(kBitsThreads) parse_segments_kernel(BitsArgs a) {
+  __shared__ uint16_t scan[32 * 32];
+  const int N = a.N;
+  build_scan_table(scan, N);
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * kBitsThreads + threadIdx.x;
+  const int64_t nseg = a.nunits / a.Wb;
+  if (s >= nseg) return;
+  const int64_t hw = (int64_t)a.Hb * a.Wb;
+  const int64_t spf = 4 * (int64_t)a.Hb;  // segments per frame
+  const int64_t f = s / spf;
+  const int64_t r = s - f * spf;
+  const uint64_t end = s + 1 < nseg ? a.index[s + 1] : a.total_bits;
+  BitSource src{a.words, a.nwords, a.index[s]};
+  const int t = (int)(f % a.T);
+  const bool intra = t % a.gop == 0;
+  bool ok = true;
+  if (r < a.Hb) {
+    const int64_t row = r;
+    int pmx = 0, pmy = 0;
+    for (int bx = 0; bx < a.Wb && ok; bx++) {
+      const int64_t blk = f * hw + row * a.Wb + bx;
+      int dx = 0, dy = 0;
+      const uint64_t p0 = src.pos;
+      if (!intra) {
+        int ddx = 0, ddy = 0;
+        ok = src.se(ddx) && src.se(ddy);
+        dx = pmx + ddx;
+        dy = pmy + ddy;
+        ok = ok && dx >= -128 && dx <= 127 && dy >= -128 && dy <= 127;
+      }
+      a.mvs_out[blk * 2] = (int8_t)dx;
+      a.mvs_out[blk * 2 + 1] = (int8_t)dy;
+      a.mbits_out[blk] = (uint32_t)(src.pos - p0);
+      pmx = dx;
+      pmy = dy;
+    }
+  } else {
+    const int c = (int)((r - a.Hb) / a.Hb);
+    const int64_t row = (r - a.Hb) - (int64_t)c * a.Hb;
+    for (int bx = 0; bx < a.Wb && ok; bx++) {
+      const int64_t blk = (f * 3 + c) * hw + row * a.Wb + bx;
+      int16_t* lev = a.levels_out + blk * N * N;
+      const uint64_t p0 = src.pos;
+      if (src.bit()) {
+        uint32_t k;
+        ok = src.ue(k) && k < (uint32_t)(N * N);
+        const int nnz = ok ? (int)k + 1 : 0;
+        int p = -1;
+        for (int i = 0; i < nnz && ok; i++) {
+          uint32_t run;
+          int v;
+          ok = src.ue(run) && src.se(v) && v != 0 && v >= -32767 && v <= 32767;
+          if (!ok) break;
+          p += (int)run + 1;
+          ok = p < N * N;
+          if (ok) lev[scan[p]] = (int16_t)v;
+        }
+      }
+      a.cbits_out[blk] = (uint32_t)(src.pos - p0);
+    }
+  }
+  if (!ok || src.pos != end) atomicOr(a.err, 1u);
+}
+
+__global__ void write_header_kernel(PackHeader h, PackHeader* dst) { *dst = h; }
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+int64_t bits_scan_blocks(int64_t nunits) { return (nunits + kBitsThreads - 1) / kBitsThreads; }
+
+hipError_t launch_bits_scan(const BitsArgs& a, hipStream_t s) {
+  const int64_t nb = bits_scan_blocks(a.nunits);
+  if (nb <= 0) return hipSuccess;
+  unit_block_sums_kernel<<<(unsigned)nb, kBitsThreads, 0, s>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  scan_block_sums_kernel<<<1, 1024, 0, s>>>(a.block_off, nb, a.total);
+  return hipGetLastError();
+}
+
+hipError_t launch_bits_write(const BitsArgs& a, hipStream_t s) {
+  const int64_t nb = bits_scan_blocks(a.nunits);
+  if (nb <= 0) return hipSuccess;
+  write_units_kernel<<<(unsigned)nb, kBitsThreads, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bits_parse(const BitsArgs& a, hipStream_t s) {
+  const int64_t nseg = a.nunits / a.Wb;
+  if (nseg <= 0) return hipSuccess;
+  parse_segments_kernel<<<blocks_for(nseg, kBitsThreads), kBitsThreads, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_header(const PackHeader& h, void* dst, hipStream_t s) {
+  write_header_kernel<<<1, 1, 0, s>>>(h, (PackHeader*)dst);
+  return hipGetLastError();
+}
+
+}  // namespace xv

@@ -242,6 +242,30 @@ EncLayout enc_layout(const xv_encoded* e) {
   return c.off;
 }
 
+// Pointers into the keep buffer (levels, vectors, bit counts, statistics,
+// metric span, job table).
+void bind_keep(xv_encoded* e, const EncLayout& lay) {
+  const int64_t bands = e->bands, G = e->G;
+  char* kb = (char*)e->keep;
+  e->levels = (int16_t*)(kb + lay.o_lev);
+  e->mvs = (int8_t*)(kb + lay.o_mv);
+  e->cbits = (uint32_t*)(kb + lay.o_cb);
+  e->mbits = (uint32_t*)(kb + lay.o_mb);
+  e->nan_count = (uint32_t*)(kb + lay.o_keys);
+  e->nan_total = e->nan_count + bands;
+  e->stats_part = e->nan_total + 1;
+  e->span = kb + lay.o_span;
+  e->span_bytes = lay.span_words * 8;
+  e->mn = (double*)e->span;
+  e->mx = e->mn + bands;
+  e->phys = e->mx + bands;
+  e->nvalid = (unsigned long long*)(e->phys + bands);
+  e->sse = e->nvalid + bands;
+  e->bits = e->sse + 3 * G;
+  e->phys_partial = (double*)(kb + lay.o_pp);
+  e->jobs = (FrameJob*)(kb + lay.o_jobs);
+}
+
 // Allocates the encoded object and launches stats, pack and plan.
 int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_encoded** out) {
   xv_encoded* e = new (std::nothrow) xv_encoded();
@@ -257,10 +281,7 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   struct {
     size_t off;
   } k{lay.keep}, w{lay.work};
-  const size_t o_lev = lay.o_lev, o_mv = lay.o_mv, o_cb = lay.o_cb, o_mb = lay.o_mb,
-               o_keys = lay.o_keys, o_span = lay.o_span, o_pp = lay.o_pp, o_jobs = lay.o_jobs,
-               o_fr = lay.o_fr, o_rc = lay.o_rc, o_vm = lay.o_vm, o_part = lay.o_part;
-  const size_t span_words = lay.span_words;
+  const size_t o_fr = lay.o_fr, o_rc = lay.o_rc, o_vm = lay.o_vm, o_part = lay.o_part;
   e->phys_nb = lay.phys_nb;
 
   hipError_t he = dev_alloc(&e->keep, k.off, s);
@@ -274,25 +295,8 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
     delete e;
     return hip_fail(he, "device allocation of the coding work buffers");
   }
-  char* kb = (char*)e->keep;
+  bind_keep(e, lay);
   char* wb = (char*)e->work;
-  e->levels = (int16_t*)(kb + o_lev);
-  e->mvs = (int8_t*)(kb + o_mv);
-  e->cbits = (uint32_t*)(kb + o_cb);
-  e->mbits = (uint32_t*)(kb + o_mb);
-  e->nan_count = (uint32_t*)(kb + o_keys);
-  e->nan_total = e->nan_count + bands;
-  e->stats_part = e->nan_total + 1;
-  e->span = kb + o_span;
-  e->span_bytes = span_words * 8;
-  e->mn = (double*)e->span;
-  e->mx = e->mn + bands;
-  e->phys = e->mx + bands;
-  e->nvalid = (unsigned long long*)(e->phys + bands);
-  e->sse = e->nvalid + bands;
-  e->bits = e->sse + 3 * G;
-  e->phys_partial = (double*)(kb + o_pp);
-  e->jobs = (FrameJob*)(kb + o_jobs);
   e->frames = (uint16_t*)(wb + o_fr);
   e->recon = (uint16_t*)(wb + o_rc);
   e->vmask = in->dtype == XV_F32 ? (uint8_t*)(wb + o_vm) : nullptr;
@@ -914,6 +918,214 @@ int xv_profile_enable(int on) {
   g_prof_pending.clear();
   memset(&g_prof_tot, 0, sizeof g_prof_tot);
   g_prof_on = on != 0;
+  return XV_OK;
+}
+
+// ---- bitstream ---------------------------------------------------------------
+
+}  // extern "C"
+
+struct xv_packed {
+  void* mem;
+  uint64_t bytes;
+  uint64_t payload_bits;
+  hipStream_t stream;
+};
+
+namespace {
+
+constexpr char kPackMagic[8] = {'X', 'V', 'P', 'A', 'C', 'K', '0', '1'};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+BitsArgs bits_args_of(const xv_encoded* e) {
+  BitsArgs a{};
+  a.N = e->N;
+  a.Hb = e->Hb;
+  a.Wb = e->Wb;
+  a.T = (int32_t)e->T;
+  a.gop = e->p.gop;
+  a.nunits = (int64_t)e->G * e->T * 4 * e->Hb * e->Wb;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xv_pack(const xv_encoded* e, void* hip_stream, xv_packed** out) {
+  if (!out) return fail(XV_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!e) return fail(XV_EINVAL, "null encoded cube");
+  hipStream_t s = (hipStream_t)hip_stream;
+  BitsArgs a = bits_args_of(e);
+  a.cbits = e->cbits;
+  a.mbits = e->mbits;
+  a.levels = e->levels;
+  a.mvs = e->mvs;
+  const int64_t nb = bits_scan_blocks(a.nunits);
+  void* scratch = nullptr;
+  XV_HIP(dev_alloc(&scratch, (size_t)(nb + 1) * 8, s), "device allocation of the scan buffer");
+  a.block_off = (uint64_t*)scratch;
+  a.total = a.block_off + nb;
+  uint64_t total = 0;
+  hipError_t he = launch_bits_scan(a, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(&total, a.total, 8, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) {
+    dev_free(scratch, s);
+    return hip_fail(he, "bitstream scan");
+  }
+  const uint64_t nseg = (uint64_t)(a.nunits / a.Wb);
+  const uint64_t nwords = (total + 31) / 32 + 2;  // two words of padding for readers
+  PackHeader h;
+  memset(&h, 0, sizeof h);
+  memcpy(h.magic, kPackMagic, 8);
+  h.version = 1;
+  h.header_bytes = sizeof(PackHeader);
+  h.T = e->T;
+  h.H = e->H;
+  h.W = e->W;
+  h.bands = e->bands;
+  h.src_dtype = e->src_dtype;
+  h.G = e->G;
+  h.N = e->N;
+  h.Hp = e->Hp;
+  h.Wp = e->Wp;
+  h.Hb = e->Hb;
+  h.Wb = e->Wb;
+  h.params = e->p;
+  h.nseg = nseg;
+  h.payload_bits = total;
+  h.nwords = nwords;
+  h.off_span = align256(sizeof(PackHeader));
+  h.span_bytes = e->span_bytes;
+  h.off_index = align256(h.off_span + h.span_bytes);
+  h.off_payload = align256(h.off_index + nseg * 8);
+  h.total_bytes = h.off_payload + nwords * 4;
+  xv_packed* pk = new (std::nothrow) xv_packed();
+  if (!pk) {
+    dev_free(scratch, s);
+    return fail(XV_ENOMEM, "host allocation failed");
+  }
+  pk->bytes = h.total_bytes;
+  pk->payload_bits = total;
+  pk->stream = s;
+  he = dev_alloc(&pk->mem, h.total_bytes, s);
+  if (he != hipSuccess) {
+    delete pk;
+    dev_free(scratch, s);
+    return hip_fail(he, "device allocation of the serialised cube");
+  }
+  char* m = (char*)pk->mem;
+  a.index = (uint64_t*)(m + h.off_index);
+  a.words = (uint32_t*)(m + h.off_payload);
+  he = launch_write_header(h, m, s);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(m + h.off_span, e->span, e->span_bytes, hipMemcpyDeviceToDevice, s);
+  if (he == hipSuccess) he = launch_fill_u32(a.words, 0u, (int64_t)nwords, s);
+  if (he == hipSuccess) {
+    ProfScope ps(XV_K_BITS_WRITE, s, (double)total / 8.0);
+    he = launch_bits_write(a, s);
+  }
+  dev_free(scratch, s);
+  if (he != hipSuccess) {
+    dev_free(pk->mem, s);
+    delete pk;
+    return hip_fail(he, "bitstream write");
+  }
+  *out = pk;
+  return XV_OK;
+}
+
+int xv_packed_view(const xv_packed* p, const void** data, uint64_t* bytes, uint64_t* payload_bits) {
+  if (!p) return fail(XV_EINVAL, "null packed cube");
+  if (data) *data = p->mem;
+  if (bytes) *bytes = p->bytes;
+  if (payload_bits) *payload_bits = p->payload_bits;
+  return XV_OK;
+}
+
+void xv_packed_free(xv_packed* p) {
+  if (!p) return;
+  if (p->mem) dev_free(p->mem, p->stream);
+  delete p;
+}
+
+int xv_unpack(const void* data, uint64_t bytes, void* hip_stream, xv_encoded** out) {
+  if (!out) return fail(XV_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!data || bytes < sizeof(PackHeader)) return fail(XV_EINVAL, "buffer too small for a header");
+  hipStream_t s = (hipStream_t)hip_stream;
+  PackHeader h;
+  XV_HIP(hipMemcpyAsync(&h, data, sizeof h, hipMemcpyDeviceToHost, s), "copy header");
+  XV_HIP(hipStreamSynchronize(s), "synchronise header copy");
+  if (memcmp(h.magic, kPackMagic, 8) != 0 || h.version != 1 || h.header_bytes != sizeof h)
+    return fail(XV_EINVAL, "not a serialised cube (bad magic or version)");
+  xv_cube cube{(void*)data, h.src_dtype, 0, h.T, h.H, h.W, h.bands};
+  int rc = check_cube(&cube, "serialised cube");
+  if (rc != XV_OK) return rc;
+  if ((rc = check_params(&h.params)) != XV_OK) return rc;
+  xv_encoded* e = new (std::nothrow) xv_encoded();
+  if (!e) return fail(XV_ENOMEM, "host allocation failed");
+  memset(e, 0, sizeof *e);
+  dims_of(e, &cube, &h.params);
+  e->stream = s;
+  BitsArgs a = bits_args_of(e);
+  const uint64_t nseg = (uint64_t)(a.nunits / a.Wb);
+  const EncLayout lay = enc_layout(e);
+  if (e->G != h.G || e->N != h.N || e->Hp != h.Hp || e->Wp != h.Wp || e->Hb != h.Hb ||
+      e->Wb != h.Wb || h.nseg != nseg || h.span_bytes != lay.span_words * 8 ||
+      h.nwords != (h.payload_bits + 31) / 32 + 2 || h.off_span < sizeof h ||
+      h.off_index < h.off_span + h.span_bytes || h.off_payload < h.off_index + nseg * 8 ||
+      h.total_bytes != h.off_payload + h.nwords * 4 || h.total_bytes > bytes) {
+    delete e;
+    return fail(XV_EINVAL, "serialised cube header is inconsistent");
+  }
+  e->phys_nb = lay.phys_nb;
+  hipError_t he = dev_alloc(&e->keep, lay.keep, s);
+  if (he != hipSuccess) {
+    delete e;
+    return hip_fail(he, "device allocation of the encoded cube");
+  }
+  bind_keep(e, lay);
+  void* err = nullptr;
+  he = dev_alloc(&err, 256, s);
+  if (he != hipSuccess) {
+    xv_encoded_free(e);
+    return hip_fail(he, "device allocation");
+  }
+  const char* m = (const char*)data;
+  a.index = (uint64_t*)(m + h.off_index);
+  a.words = (uint32_t*)(m + h.off_payload);
+  a.nwords = (int64_t)h.nwords;
+  a.total_bits = h.payload_bits;
+  a.levels_out = e->levels;
+  a.mvs_out = e->mvs;
+  a.cbits_out = e->cbits;
+  a.mbits_out = e->mbits;
+  a.err = (uint32_t*)err;
+  const int64_t lev_words = (int64_t)e->G * e->T * 3 * e->Hp * e->Wp / 2;
+  uint32_t herr = 0;
+  he = hipMemcpyAsync(e->span, m + h.off_span, h.span_bytes, hipMemcpyDeviceToDevice, s);
+  if (he == hipSuccess) he = launch_fill_u32((uint32_t*)e->levels, 0u, lev_words, s);
+  if (he == hipSuccess) he = launch_fill_u32(a.err, 0u, 1, s);
+  if (he == hipSuccess) {
+    ProfScope ps(XV_K_BITS_PARSE, s, (double)h.payload_bits / 8.0);
+    he = launch_bits_parse(a, s);
+  }
+  if (he == hipSuccess) he = hipMemcpyAsync(&herr, a.err, 4, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  dev_free(err, s);
+  if (he != hipSuccess) {
+    xv_encoded_free(e);
+    return hip_fail(he, "bitstream parse");
+  }
+  if (herr) {
+    xv_encoded_free(e);
+    return fail(XV_EINVAL, "payload does not parse as the stored codes");
+  }
+  *out = e;
   return XV_OK;
 }
 

@@ -242,6 +242,48 @@ int phys_blocks(int64_t npix);
 hipError_t launch_phys_sse(const PhysArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Bitstream (k_bits.hip).  Units in stream order: per frame the Hb*Wb vector
+// units, then the 3*Hb*Wb coefficient units; a row of Wb units is a segment.
+// ---------------------------------------------------------------------------
+struct BitsArgs {
+  int32_t N, Hb, Wb, T, gop;
+  int64_t nunits;              // G * T * 4 * Hb * Wb
+  const uint32_t* cbits;       // [G][T][3][Hb][Wb] unit lengths (pack)
+  const uint32_t* mbits;       // [G][T][Hb][Wb]
+  const int16_t* levels;       // [G][T][3][Hb][Wb][N*N] (pack)
+  const int8_t* mvs;           // [G][T][Hb][Wb][2] (pack)
+  uint64_t* block_off;         // [bits_scan_blocks] scratch: block sums -> offsets
+  uint64_t* total;             // [1] payload bits
+  uint64_t* index;             // [nunits / Wb] segment bit offsets
+  uint32_t* words;             // payload, byte order = stream order
+  int64_t nwords;              // payload words incl. 2 words of padding (parse)
+  uint64_t total_bits;         // (parse)
+  int16_t* levels_out;         // (parse) zero on entry
+  int8_t* mvs_out;
+  uint32_t* cbits_out;
+  uint32_t* mbits_out;
+  uint32_t* err;               // (parse) set on an inconsistent stream
+};
+int64_t bits_scan_blocks(int64_t nunits);
+hipError_t launch_bits_scan(const BitsArgs& a, hipStream_t s);
+hipError_t launch_bits_write(const BitsArgs& a, hipStream_t s);
+hipError_t launch_bits_parse(const BitsArgs& a, hipStream_t s);
+
+// Header of a serialised cube (first 256 bytes of the buffer).
+struct PackHeader {
+  char magic[8];               // "XVPACK01"
+  uint32_t version, header_bytes;
+  int64_t T, H, W, bands;
+  int32_t src_dtype, G, N, Hp, Wp, Hb, Wb, reserved;
+  xv_params params;
+  uint64_t nseg, payload_bits, nwords;
+  uint64_t off_span, span_bytes, off_index, off_payload, total_bytes;
+  uint8_t pad[256 - 176];
+};
+static_assert(sizeof(PackHeader) == 256, "pack header size");
+hipError_t launch_write_header(const PackHeader& h, void* dst, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Caching device allocator (xv_alloc.cpp).  dev_free keeps the block for
 // reuse: at once on the same stream, on another stream once the work queued
 // before the free has completed.

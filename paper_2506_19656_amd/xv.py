@@ -23,8 +23,10 @@ PAD_ZERO, PAD_REPEAT = 0, 1
 FILL_NEAREST, FILL_FORWARD = 0, 1
 FLAG_DROP_WORK = 1
 MAX_BANDS, MAX_GROUPS = 64, 22
-K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS = range(7)
-K_NAMES = ["stats", "pack", "me", "encode", "decode", "denorm", "metrics"]
+K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS, K_BITS_WRITE, K_BITS_PARSE = \
+    range(9)
+K_NAMES = ["stats", "pack", "me", "encode", "decode", "denorm", "metrics", "bits_write",
+           "bits_parse"]
 
 
 class XvError(RuntimeError):
@@ -70,7 +72,7 @@ class MeGeometryC(C.Structure):
 
 
 class ProfileC(C.Structure):
-    _fields_ = [("ms", C.c_double * 7), ("launches", C.c_uint64 * 7), ("work", C.c_double * 7)]
+    _fields_ = [("ms", C.c_double * 9), ("launches", C.c_uint64 * 9), ("work", C.c_double * 9)]
 
 
 class MemoryC(C.Structure):
@@ -106,7 +108,8 @@ EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube"
             "xv_encode_batch", "xv_decode_batch", "xv_set_me_geometry", "xv_get_me_geometry",
             "xv_autotune_me", "xv_autotune_me_batch", "xv_profile_enable", "xv_profile_read", "xv_server_create",
             "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
-            "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release"]
+            "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release", "xv_pack", "xv_packed_view",
+            "xv_packed_free", "xv_unpack"]
 
 _lib = None
 
@@ -140,6 +143,12 @@ def lib():
         L.xv_autotune_me_batch.argtypes = [C.c_int, C.POINTER(Cube), C.POINTER(ParamsC), vp,
                                            C.c_int, C.POINTER(MeGeometryC),
                                            C.POINTER(C.c_double)]
+        L.xv_pack.argtypes = [vp, vp, C.POINTER(vp)]
+        L.xv_packed_view.argtypes = [vp, C.POINTER(vp), C.POINTER(C.c_uint64),
+                                     C.POINTER(C.c_uint64)]
+        L.xv_packed_free.argtypes = [vp]
+        L.xv_packed_free.restype = None
+        L.xv_unpack.argtypes = [vp, C.c_uint64, vp, C.POINTER(vp)]
         L.xv_memory_read.argtypes = [C.POINTER(MemoryC)]
         L.xv_cache_release.argtypes = [C.POINTER(C.c_uint64)]
         L.xv_server_create.argtypes = [C.POINTER(ServerCfgC), C.POINTER(vp)]
@@ -367,7 +376,61 @@ def profile_read() -> dict:
     p = ProfileC()
     _check(lib().xv_profile_read(C.byref(p)))
     return {K_NAMES[i]: dict(ms=p.ms[i], launches=p.launches[i], work=p.work[i])
-            for i in range(7)}
+            for i in range(9)}
+
+
+class Packed:
+    """A serialised encoded cube (xv_pack): one device buffer."""
+
+    def __init__(self, handle, shape, params):
+        self.handle = handle
+        self.shape = shape
+        self.params = params
+        self._freed = False
+
+    def view(self) -> dict:
+        d = C.c_void_p()
+        n = C.c_uint64()
+        bits = C.c_uint64()
+        _check(lib().xv_packed_view(self.handle, C.byref(d), C.byref(n), C.byref(bits)))
+        return dict(ptr=d.value, bytes=n.value, payload_bits=bits.value)
+
+    def tensor(self):
+        """The buffer as a uint8 device tensor (a view; valid while self lives)."""
+        import torch
+        v = self.view()
+
+        class _CAI:
+            __cuda_array_interface__ = dict(shape=(v["bytes"],), typestr="|u1",
+                                            data=(v["ptr"], False), version=3)
+        return torch.as_tensor(_CAI(), device="cuda")
+
+    def free(self):
+        if not self._freed:
+            lib().xv_packed_free(self.handle)
+            self._freed = True
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pack(enc: "Encoded", stream=None) -> Packed:
+    """xv_pack: serialise an encoded cube (header, metric span, segment index,
+    Exp-Golomb payload)."""
+    h = C.c_void_p()
+    _check(lib().xv_pack(enc.handle, _stream_handle(stream), C.byref(h)))
+    return Packed(h, enc.shape, enc.params)
+
+
+def unpack(buf, stream=None, shape=None, params=None) -> "Encoded":
+    """xv_unpack: parse a serialised cube held in a uint8 device tensor."""
+    h = C.c_void_p()
+    _check(lib().xv_unpack(C.c_void_p(buf.data_ptr()), buf.numel(), _stream_handle(stream),
+                           C.byref(h)))
+    return Encoded(h, shape, params)
 
 
 def memory_read() -> dict:

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(xvmod):
 
 def test_abi_version_and_status_strings(xvmod):
     L = xvmod.lib()
-    assert L.xv_abi_version() == 1
+    assert L.xv_abi_version() == 2
     assert L.xv_status_str(0) == b"ok"
     assert L.xv_status_str(-1) == b"invalid argument"
 
@@ -101,3 +101,14 @@ def test_memory_record_and_release_without_device_work(xvmod):
     assert m["live_bytes"] <= m["peak_bytes"]
     L = xvmod.lib()
     assert L.xv_memory_read(None) == xvmod.EINVAL
+
+
+def test_bitstream_entry_points_reject_bad_arguments(xvmod):
+    L = xvmod.lib()
+    h = C.c_void_p()
+    assert L.xv_pack(None, None, C.byref(h)) == xvmod.EINVAL
+    assert L.xv_pack(None, None, None) == xvmod.EINVAL
+    assert L.xv_unpack(None, 0, None, C.byref(h)) == xvmod.EINVAL
+    assert L.xv_unpack(C.c_void_p(16), 100, None, C.byref(h)) == xvmod.EINVAL  # < header
+    assert L.xv_packed_view(None, None, None, None) == xvmod.EINVAL
+    L.xv_packed_free(None)  # no-op

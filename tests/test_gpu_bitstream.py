@@ -1,0 +1,120 @@
+"""The serialised bitstream: the GPU payload and segment index are
+bit-identical with the oracle's writer applied to the oracle's own encode of
+the same cube, and parsing it back reproduces the encoded cube."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2506_19656_amd import synth
+from paper_2506_19656_amd import xv
+
+pytestmark = pytest.mark.gpu
+
+HDR = 256
+
+
+def _oparams(p: xv.Params) -> O.CodingParams:
+    return O.CodingParams(bit_depth=p.bit_depth, qp=p.qp, block=p.block,
+                          search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
+                          fill_mode=p.fill_mode)
+
+
+def _sections(buf: np.ndarray) -> dict:
+    h = buf[:HDR]
+    q = h[:176].view(np.uint8)
+    u64 = lambda off: int(np.frombuffer(q[off:off + 8].tobytes(), np.uint64)[0])
+    # offsets of the 64-bit fields after magic(8) version,hdr(8) dims(32)
+    # dtype..reserved(32) params(32): nseg at 112
+    nseg, bits, nwords = u64(112), u64(120), u64(128)
+    off_span, span_bytes, off_index, off_payload, total = (u64(136), u64(144), u64(152),
+                                                           u64(160), u64(168))
+    assert bytes(h[:8]) == b"XVPACK01" and total == len(buf)
+    return dict(nseg=nseg, bits=bits, index=buf[off_index:off_index + 8 * nseg].view(np.uint64),
+                payload=buf[off_payload:off_payload + (bits + 7) // 8],
+                tail=buf[off_payload + (bits + 7) // 8:], span=buf[off_span:off_span + span_bytes])
+
+
+def _case(host: np.ndarray, p: xv.Params, name: str):
+    print(f"[case] {name} {host.shape} {p}", flush=True)
+    cube = torch.from_numpy(host).cuda()
+    enc = xv.encode_cube(cube, p)
+    pk = xv.pack(enc)
+    buf = pk.tensor().cpu().numpy()
+    sec = _sections(buf)
+    ref = O.encode_cube(host, _oparams(p))
+    w = O.write_bitstream(ref["levels"], ref["mvs"], p.gop)
+    assert sec["bits"] == w["bits"] == pk.view()["payload_bits"], name
+    assert np.array_equal(sec["payload"], w["payload"]), name
+    assert not sec["tail"].any(), name  # padding stays zero
+    assert np.array_equal(sec["index"], w["index"]), name
+    # parse back: the encoded cube again
+    un = xv.unpack(pk.tensor(), shape=enc.shape, params=p)
+    a, b = enc.host(), un.host()
+    for k in ("levels", "mvs", "coef_bits", "mv_bits", "band_min", "band_max", "sse", "n_valid"):
+        assert np.array_equal(a[k], b[k]), (name, k)
+    m1, m2 = xv.psnr_bpppb(None, enc), xv.psnr_bpppb(None, un)
+    assert m1["psnr"] == m2["psnr"] and m1["bpppb"] == m2["bpppb"], name
+    o1, o2 = torch.empty_like(cube), torch.empty_like(cube)
+    xv.decode_cube(enc, o1)
+    xv.decode_cube(un, o2)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2), name
+    pk.free()
+    un.free()
+    enc.free()
+
+
+def _textured(T, H, W, Bn, seed, dtype=np.uint16, nan_frac=0.0):
+    c = synth.tiny_cube(seed=seed, T=T, H=H, W=W, bands=Bn).numpy()
+    if dtype == np.float32:
+        c = c.astype(np.float32)
+        rng = np.random.default_rng(seed)
+        c[rng.random(c.shape[:3]) < nan_frac] = np.nan
+    return c
+
+
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_payload_matches_oracle_and_round_trips(N):
+    host = _textured(7, 2 * N + 5, 3 * N - 3, 4, seed=N)
+    for qp in (12, 37):
+        _case(host, xv.Params(bit_depth=10, qp=qp, block=N, search_range=5, gop=3),
+              f"N{N}_qp{qp}")
+
+
+def test_twelve_bit_float_gaps_and_padding():
+    host = _textured(9, 40, 56, 5, seed=3, dtype=np.float32, nan_frac=0.08)
+    _case(host, xv.Params(bit_depth=12, qp=17, block=8, search_range=8, gop=4,
+                          pad_mode=1), "f32_gaps_b12")
+    _case(host, xv.Params(bit_depth=8, qp=51, block=16, search_range=3, gop=1), "all_intra_qp51")
+
+
+def test_reduced_sweep_cube():
+    host = synth.s2cloud_cube(T=24, H=128, W=128, device="cpu").numpy()
+    for N in (8, 32):
+        _case(host, xv.Params(bit_depth=12, qp=22, block=N, search_range=16, gop=16),
+              f"s2cloud24_N{N}")
+
+
+def test_corrupt_buffers_are_rejected():
+    host = _textured(4, 32, 32, 3, seed=9)
+    cube = torch.from_numpy(host).cuda()
+    enc = xv.encode_cube(cube, xv.Params(bit_depth=10, qp=22, block=8, search_range=4, gop=4))
+    pk = xv.pack(enc)
+    good = pk.tensor().clone()
+    v = pk.view()
+    with pytest.raises(xv.XvError):  # shorter than the header says
+        xv.unpack(good[: v["bytes"] - 8])
+    bad = good.clone()
+    bad[:8] = 0  # magic
+    with pytest.raises(xv.XvError):
+        xv.unpack(bad)
+    sec = _sections(good.cpu().numpy())
+    bad = good.clone()
+    off_payload = v["bytes"] - 4 * ((sec["bits"] + 31) // 32 + 2)
+    bad[off_payload:] = 0  # payload of zeros parses to no valid code
+    with pytest.raises(xv.XvError):
+        xv.unpack(bad)
+    # the intact buffer still parses
+    un = xv.unpack(good)
+    assert np.array_equal(un.host()["levels"], enc.host()["levels"])
