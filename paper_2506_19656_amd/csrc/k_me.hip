@@ -257,27 +257,38 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
       load_win(N);
       sad(acc1, CB);
     }
+    // Best candidate of the item.  SAD < 2^24 and L1 <= 128, so (SAD, L1)
+    // fits one 32-bit key; candidates are visited in increasing raster
+    // index (dy, then dx), so a strict < keeps the smallest index among
+    // equal keys and the item's winner is its lexicographic minimum of
+    // (SAD, L1, dy, dx).  Only that one gets the full 64-bit key.
     const int x0 = (bx0 + b) * N, y0 = by * N;
-    unsigned long long kbest = ~0ull;
+    const int c0 = gxi * KX;
+    const int klo = max(0, R - x0) - c0;                        // displaced block inside
+    const int khi = min(s.span - 1, Wp - N - x0 + R) - c0;      // the padded picture
+    uint32_t kb32 = 0xffffffffu;
+    int bsel = -1;
 #pragma unroll
     for (int h = 0; h < ROWS; h++) {
-      const int dy = dy0 + h;
-      const int dyv = dy - R;
-      const bool yok = dy < s.span && (y0 + dyv >= 0) && (y0 + dyv + N <= Hp);
+      const int dyv = dy0 + h - R;
+      const bool yok = dy0 + h < s.span && (y0 + dyv >= 0) && (y0 + dyv + N <= Hp);
 #pragma unroll
       for (int k = 0; k < KX; k++) {
-        const int cx = gxi * KX + k;
-        const int dxv = cx - R;
-        const bool ok = yok && cx < s.span && (x0 + dxv >= 0) && (x0 + dxv + N <= Wp);
-        const unsigned long long l1 = (unsigned long long)(abs(dxv) + abs(dyv));
-        const uint32_t sv = h ? acc1[k] : acc0[k];
-        const unsigned long long key = ((unsigned long long)sv << keyshift_sad) |
-                                       (l1 << keyshift_l1) |
-                                       (unsigned long long)(dy * s.span + cx);
-        kbest = ok && key < kbest ? key : kbest;
+        const bool ok = yok && k >= klo && k <= khi;
+        const uint32_t l1 = (uint32_t)(abs(c0 + k - R) + abs(dyv));
+        const uint32_t key = ((h ? acc1[k] : acc0[k]) << 8) | l1;
+        const bool take = ok && key < kb32;
+        kb32 = take ? key : kb32;
+        bsel = take ? h * KX + k : bsel;
       }
     }
-    if (kbest != ~0ull) atomicMin(&best[b], kbest);
+    if (bsel >= 0) {
+      const int h = bsel / KX, k = bsel - h * KX;
+      const unsigned long long idx = (unsigned long long)((dy0 + h) * s.span + c0 + k);
+      const unsigned long long key = ((unsigned long long)(kb32 >> 8) << keyshift_sad) |
+                                     ((unsigned long long)(kb32 & 0xffu) << keyshift_l1) | idx;
+      atomicMin(&best[b], key);
+    }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < nbv; b += blockDim.x) {

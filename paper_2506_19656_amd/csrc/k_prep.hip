@@ -203,13 +203,17 @@ __global__ void __launch_bounds__(kThreads) stats_kernel(StatsArgs a) {
   }
 }
 
-// One wave per band merges the block partials; keys -> binary64 statistics.
-// A band without a valid sample gets 0, 0.
-__global__ void __launch_bounds__(64) stats_finalize_kernel(StatsArgs a) {
+// One workgroup per band merges the block partials (fixed tree; min, max and
+// counts are order independent anyway); keys -> binary64 statistics.  A band
+// without a valid sample gets 0, 0.
+constexpr int kFinThreads = 1024;
+
+__global__ void __launch_bounds__(kFinThreads) stats_finalize_kernel(StatsArgs a) {
+  __shared__ uint32_t rlo[kFinThreads / 64], rhi[kFinThreads / 64], rnn[kFinThreads / 64];
   const int b = blockIdx.x;
   const int bands = a.bands;
   uint32_t lo = 0xffffffffu, hi = 0u, nn = 0u;
-  for (int k = threadIdx.x; k < a.nblocks; k += 64) {
+  for (int k = threadIdx.x; k < a.nblocks; k += kFinThreads) {
     const uint32_t* p = a.part + (int64_t)k * 3 * bands;
     lo = min(lo, p[b]);
     hi = max(hi, p[bands + b]);
@@ -221,7 +225,19 @@ __global__ void __launch_bounds__(64) stats_finalize_kernel(StatsArgs a) {
     hi = max(hi, (uint32_t)__shfl_xor((int)hi, w, 64));
     nn += (uint32_t)__shfl_xor((int)nn, w, 64);
   }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    rlo[wv] = lo;
+    rhi[wv] = hi;
+    rnn[wv] = nn;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  for (int i = 1; i < kFinThreads / 64; i++) {
+    lo = min(lo, rlo[i]);
+    hi = max(hi, rhi[i]);
+    nn += rnn[i];
+  }
   const bool any = (uint64_t)nn < (uint64_t)a.npix;
   double l = 0.0, h = 0.0;
   if (any) {
@@ -836,27 +852,29 @@ __global__ void __launch_bounds__(kThreads) phys_vec_kernel(PhysArgs a) {
 
 // Per-group totals of the transform kernel's per-tile sums: block (g, i)
 // sums quantity i over the T * tpf tiles of group g with a fixed assignment
-// of tiles to threads (8 loads in flight per thread) and a fixed tree.
-__global__ void __launch_bounds__(kThreads) encode_totals_kernel(
+// of tiles to threads (4 loads in flight per thread) and a fixed tree.
+constexpr int kTotThreads = 1024;
+
+__global__ void __launch_bounds__(kTotThreads) encode_totals_kernel(
     const unsigned long long* part, int T, int tpf, unsigned long long* sse,
     unsigned long long* bits) {
-  __shared__ unsigned long long sred[kThreads];
+  __shared__ unsigned long long sred[kTotThreads];
   const int g = blockIdx.x / 5, i = blockIdx.x - g * 5;
   const int64_t n = (int64_t)T * tpf;
   const unsigned long long* pg = part + (int64_t)g * n * 5 + i;
   unsigned long long v = 0;
   int64_t j = threadIdx.x;
-  for (; j + 7 * kThreads < n; j += 8 * kThreads) {
-    unsigned long long w[8];
+  for (; j + 3 * kTotThreads < n; j += 4 * kTotThreads) {
+    unsigned long long w[4];
 #pragma unroll
-    for (int u = 0; u < 8; u++) w[u] = pg[(j + u * kThreads) * 5];
+    for (int u = 0; u < 4; u++) w[u] = pg[(j + u * kTotThreads) * 5];
 #pragma unroll
-    for (int u = 0; u < 8; u++) v += w[u];
+    for (int u = 0; u < 4; u++) v += w[u];
   }
-  for (; j < n; j += kThreads) v += pg[j * 5];
+  for (; j < n; j += kTotThreads) v += pg[j * 5];
   sred[threadIdx.x] = v;
   __syncthreads();
-  for (int w = kThreads / 2; w >= 1; w >>= 1) {
+  for (int w = kTotThreads / 2; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
     __syncthreads();
   }
@@ -923,7 +941,7 @@ hipError_t launch_plan(const CubePlan& p, hipStream_t s) {
 hipError_t launch_encode_totals(const unsigned long long* part, int G, int T, int tpf,
                                 unsigned long long* sse, unsigned long long* bits, hipStream_t s) {
   if (G <= 0) return hipSuccess;
-  encode_totals_kernel<<<G * 5, kThreads, 0, s>>>(part, T, tpf, sse, bits);
+  encode_totals_kernel<<<G * 5, kTotThreads, 0, s>>>(part, T, tpf, sse, bits);
   return hipGetLastError();
 }
 
@@ -986,7 +1004,7 @@ hipError_t launch_stats(const StatsArgs& in, hipStream_t s) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  stats_finalize_kernel<<<a.bands, 64, 0, s>>>(a);
+  stats_finalize_kernel<<<a.bands, kFinThreads, 0, s>>>(a);
   return hipGetLastError();
 }
 
