@@ -31,13 +31,13 @@ namespace xv {
 namespace {
 
 // An item is (block, group of KX candidate columns, ROWS consecutive
-// candidate rows dy0 .. dy0 + ROWS - 1).  With two rows a lane sums both
-// rows' SADs from one pass over the N + 1 window rows they share.
+// candidate rows dy0 .. dy0 + ROWS - 1).  A lane sums all ROWS rows' SADs
+// from one pass over the N + ROWS - 1 window rows they share.
 struct MeShape {
   int R, G, span, dyp, ipb;  // span = 2R+1; dyp = row groups; ipb = items per block
   int wc, pitch;             // window columns (u16) and pitch (dwords)
-  int rows;                  // staged rows: N + 2R, plus one with two rows per item
-                             // (it only serves dy = 2R+1, outside the range)
+  int rows;                  // staged rows ROWS * dyp + N - 1 (rows past N + 2R only
+                             // serve candidate rows outside the range)
 };
 
 __host__ __device__ inline MeShape me_shape(int N, int R, int kx, int nb, int nrow) {
@@ -45,12 +45,12 @@ __host__ __device__ inline MeShape me_shape(int N, int R, int kx, int nb, int nr
   s.R = R;
   s.span = 2 * R + 1;
   s.G = (s.span + kx - 1) / kx;
-  s.dyp = nrow == 2 ? R + 1 : s.span;
+  s.dyp = (s.span + nrow - 1) / nrow;
   s.ipb = s.dyp * s.G;
   s.wc = nb * N + s.G * kx;
   s.pitch = s.wc / 2;
   if ((s.pitch & 1) == 0) s.pitch += 1;
-  s.rows = N + 2 * R + (nrow == 2 ? 1 : 0);
+  s.rows = nrow * s.dyp + N - 1;
   return s;
 }
 
@@ -195,18 +195,16 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
     const int rem = it - b * s.ipb;
     const int gxi = rem / s.dyp;
     const int dy0 = ROWS * (rem - gxi * s.dyp);
-    uint32_t acc0[KX], acc1[KX];
+    uint32_t acc[ROWS][KX];
 #pragma unroll
-    for (int k = 0; k < KX; k++) {
-      acc0[k] = 0;
-      acc1[k] = 0;
-    }
+    for (int h = 0; h < ROWS; h++)
+#pragma unroll
+      for (int k = 0; k < KX; k++) acc[h][k] = 0;
     for (int ch = 0; ch < nch; ch++) {
       const uint32_t* wbase = win + (ch * s.rows + dy0) * s.pitch + (b * N + gxi * KX) / 2;
       const uint32_t* cbase = curt + ch * N * cpitch + b * NC;
       uint32_t D[ND], O[ND - 1], CA[NC], CB[NC];
-      // window row w serves candidate row dy0 with current row w and
-      // candidate row dy0 + 1 with current row w - 1
+      // window row w serves candidate row dy0 + h with current row w - h
       auto load_win = [&](int w) {
         const uint32_t* wr = wbase + w * s.pitch;
 #pragma unroll
@@ -233,29 +231,48 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
         for (int w = 0; w < N; w++) {
           load_win(w);
           load_cur(w, CA);
-          sad(acc0, CA);
+          sad(acc[0], CA);
         }
-        continue;
+      } else if constexpr (ROWS == 2) {
+        load_win(0);
+        load_cur(0, CA);
+        sad(acc[0], CA);
+        for (int w = 1; w + 1 < N; w += 2) {
+          load_win(w);
+          load_cur(w, CB);
+          sad(acc[0], CB);
+          sad(acc[1], CA);
+          load_win(w + 1);
+          load_cur(w + 1, CA);
+          sad(acc[0], CA);
+          sad(acc[1], CB);
+        }
+        load_win(N - 1);
+        load_cur(N - 1, CB);
+        sad(acc[0], CB);
+        sad(acc[1], CA);
+        load_win(N);
+        sad(acc[1], CB);
+      } else {
+        // ring of the last ROWS current rows: current row r lives in slot
+        // r % ROWS; the loop is unrolled by ROWS so every slot index is a
+        // compile-time constant
+        uint32_t ring[ROWS][NC];
+        constexpr int NW = N + ROWS - 1;  // window rows of the item
+        for (int w0 = 0; w0 < NW; w0 += ROWS) {
+#pragma unroll
+          for (int j = 0; j < ROWS; j++) {
+            const int w = w0 + j;
+            if (w < NW) {
+              load_win(w);
+              if (w < N) load_cur(w, ring[j]);
+#pragma unroll
+              for (int h = 0; h < ROWS; h++)
+                if (w - h >= 0 && w - h < N) sad(acc[h], ring[(j - h + ROWS) % ROWS]);
+            }
+          }
+        }
       }
-      load_win(0);
-      load_cur(0, CA);
-      sad(acc0, CA);
-      for (int w = 1; w + 1 < N; w += 2) {
-        load_win(w);
-        load_cur(w, CB);
-        sad(acc0, CB);
-        sad(acc1, CA);
-        load_win(w + 1);
-        load_cur(w + 1, CA);
-        sad(acc0, CA);
-        sad(acc1, CB);
-      }
-      load_win(N - 1);
-      load_cur(N - 1, CB);
-      sad(acc0, CB);
-      sad(acc1, CA);
-      load_win(N);
-      sad(acc1, CB);
     }
     // Best candidate of the item.  SAD < 2^24 and L1 <= 128, so (SAD, L1)
     // fits one 32-bit key; candidates are visited in increasing raster
@@ -276,7 +293,7 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
       for (int k = 0; k < KX; k++) {
         const bool ok = yok && k >= klo && k <= khi;
         const uint32_t l1 = (uint32_t)(abs(c0 + k - R) + abs(dyv));
-        const uint32_t key = ((h ? acc1[k] : acc0[k]) << 8) | l1;
+        const uint32_t key = (acc[h][k] << 8) | l1;
         const bool take = ok && key < kb32;
         kb32 = take ? key : kb32;
         bsel = take ? h * KX + k : bsel;
@@ -319,9 +336,11 @@ hipError_t launch_me_t(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t 
 // Calls f.template operator()<KX, ROWS>() for the geometry's instance.
 template <class F>
 auto me_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<2, 1>()) {
-#define XV_ME_KX(kx)                                                   \
-  case kx:                                                             \
-    return g.rows == 2 ? f.template operator()<kx, 2>() : f.template operator()<kx, 1>();
+#define XV_ME_KX(kx)                                                               \
+  case kx:                                                                         \
+    return g.rows == 3   ? f.template operator()<kx, 3>()                          \
+           : g.rows == 2 ? f.template operator()<kx, 2>()                          \
+                         : f.template operator()<kx, 1>();
   switch (g.kx) {
     XV_ME_KX(2)
     XV_ME_KX(4)
@@ -370,17 +389,22 @@ size_t me_lds_bytes_for(int N, int R, const MeGeom& g) {
 
 // Model of a CU (160 KB LDS, 4 SIMDs with 512 VGPRs per lane, at most 8
 // waves each) used to rank geometries.  Score = share of SAD instructions in
-// a lane's VALU work per window row (rows KX N/2 SADs against (KX+N)/2 - 1
-// realignments) x share of useful candidates (2R+1 of G KX columns; with two
-// rows per lane 2R+1 of 2R+2 rows) x lane occupancy of the rounds of items x
-// resident waves per SIMD (saturating at 3).
+// a lane's VALU work (rows N KX N/2 SADs against N + rows - 1 realigned
+// window rows of (KX+N)/2 - 1 realignments each) x share of useful
+// candidates (2R+1 of G KX columns, 2R+1 of rows * ceil((2R+1)/rows) rows) x
+// lane occupancy of the rounds of items x resident waves per SIMD
+// (saturating at 3).
 double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
   const int span = 2 * R + 1;
   const int kx = g.kx, th = g.threads;
   const int G = (span + kx - 1) / kx;
-  const double sad = (double)g.rows * kx * N / 2;
-  const double eff = sad / (sad + (kx + N) / 2 - 1) * (double)span / (double)(G * kx) *
-                     (g.rows == 2 ? (double)span / (double)(2 * (R + 1)) : 1.0);
+  // per item and channel: rows * N window-row SAD passes of KX N/2 SADs
+  // against N + rows - 1 realigned window rows
+  const double sad = (double)g.rows * N * kx * N / 2;
+  const double perm = (double)(N + g.rows - 1) * ((kx + N) / 2 - 1);
+  const int dyp = (span + g.rows - 1) / g.rows;
+  const double eff = sad / (sad + perm) * (double)span / (double)(G * kx) *
+                     (double)span / (double)(g.rows * dyp);
   const MeShape sh = me_shape(N, R, kx, g.nb, g.rows);
   const size_t lds = me_lds_bytes(N, sh, g.nb);
   if (lds > 160 * 1024) return -1.0;
@@ -409,7 +433,7 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
 std::vector<MeGeom> me_candidates(int N, int R, int width_blocks) {
   std::vector<MeGeom> v;
   const int cmax = std::max(1, std::min(16, width_blocks));
-  for (int rows = 1; rows <= 2; rows++)
+  for (int rows = 1; rows <= 3; rows++)
     for (int kx = 2; kx <= 18; kx += 2)
       for (int c = 1; c <= cmax; c++)
         for (int th = 64; th <= 512; th += 64) {
