@@ -252,7 +252,8 @@ int xv_server_destroy(xv_server* sv);
 
 /* Geometry of the motion-search kernel for one (N, R): blocks per
  * workgroup along x, candidates per lane along x (even), threads per
- * workgroup (multiple of 64, <= 512), candidate rows per lane (1, 2 or 3).
+ * workgroup (multiple of 64, <= 512), candidate rows per lane (1, 2 or 3
+ * for any candidate count; 5 for 2 or 4 candidates).
  * Zero fields take the default; NULL or all fields zero restores the
  * default for (block, search_range). */
 typedef struct {

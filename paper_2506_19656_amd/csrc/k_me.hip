@@ -334,13 +334,21 @@ hipError_t launch_me_t(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t 
 }
 
 // Calls f.template operator()<KX, ROWS>() for the geometry's instance.
+// Rows 1..3 exist for every even KX in 2..18; 5 rows (which divide the
+// span 2R+1 = 65 of R = 32) for KX = 2 and 4.
 template <class F>
 auto me_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<2, 1>()) {
+  using Ret = decltype(f.template operator()<2, 1>());
 #define XV_ME_KX(kx)                                                               \
   case kx:                                                                         \
     return g.rows == 3   ? f.template operator()<kx, 3>()                          \
            : g.rows == 2 ? f.template operator()<kx, 2>()                          \
                          : f.template operator()<kx, 1>();
+  if (g.rows == 5) {
+    if (g.kx == 2) return f.template operator()<2, 5>();
+    if (g.kx == 4) return f.template operator()<4, 5>();
+    return (Ret)hipErrorInvalidValue;
+  }
   switch (g.kx) {
     XV_ME_KX(2)
     XV_ME_KX(4)
@@ -351,7 +359,7 @@ auto me_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<2, 1>
     XV_ME_KX(14)
     XV_ME_KX(16)
     XV_ME_KX(18)
-    default: return decltype(f.template operator()<2, 1>())();
+    default: return (Ret)hipErrorInvalidValue;
   }
 #undef XV_ME_KX
 }
@@ -382,6 +390,13 @@ int me_vgprs(int N, const MeGeom& g) {
 }
 
 }  // namespace
+
+// Whether a kernel instance exists for (KX, rows).
+bool me_instance_exists(int kx, int rows) {
+  if (kx < 2 || kx > 18 || (kx & 1)) return false;
+  if (rows >= 1 && rows <= 3) return true;
+  return rows == 5 && (kx == 2 || kx == 4);
+}
 
 size_t me_lds_bytes_for(int N, int R, const MeGeom& g) {
   return me_lds_bytes(N, me_shape(N, R, g.kx, g.nb, g.rows), g.nb);
@@ -433,12 +448,13 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
 std::vector<MeGeom> me_candidates(int N, int R, int width_blocks) {
   std::vector<MeGeom> v;
   const int cmax = std::max(1, std::min(16, width_blocks));
-  for (int rows = 1; rows <= 3; rows++)
+  for (int rows : {1, 2, 3, 5})
     for (int kx = 2; kx <= 18; kx += 2)
       for (int c = 1; c <= cmax; c++)
         for (int th = 64; th <= 512; th += 64) {
           const MeGeom g{c, kx, th, rows};
-          if (me_lds_bytes_for(N, R, g) <= 96 * 1024) v.push_back(g);
+          if (me_instance_exists(kx, rows) && me_lds_bytes_for(N, R, g) <= 96 * 1024)
+            v.push_back(g);
         }
   return v;
 }
@@ -464,7 +480,9 @@ int me_tiles_per_job(int Hb, int Wb, const MeGeom& g) {
 
 hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
   if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
-  if (g.threads <= 0 || g.threads > 512 || (g.threads & 63) || g.nb < 1) return hipErrorInvalidValue;
+  if (g.threads <= 0 || g.threads > 512 || (g.threads & 63) || g.nb < 1 ||
+      !me_instance_exists(g.kx, g.rows))
+    return hipErrorInvalidValue;
   if (me_lds_bytes_for(N, R, g) > 160 * 1024) return hipErrorInvalidValue;
   switch (N) {
     case 4: return launch_me_n<4>(R, g, r, s);

@@ -782,7 +782,9 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
   if (m.kx < 2 || m.kx > 18 || (m.kx & 1)) return fail(XV_EINVAL, "cands_per_lane must be even in 2..18");
   if (m.threads < 64 || m.threads > 512 || (m.threads & 63))
     return fail(XV_EINVAL, "threads must be a multiple of 64 in 64..512");
-  if (m.rows < 1 || m.rows > 3) return fail(XV_EINVAL, "rows_per_lane must be 1, 2 or 3");
+  if (!me_instance_exists(m.kx, m.rows))
+    return fail(XV_EINVAL, "no kernel for %d candidates x %d rows per lane (rows 1..3 for any "
+                "even count 2..18; 5 rows for 2 or 4 candidates)", m.kx, m.rows);
   if (me_lds_bytes_for(block, search_range, m) > 160 * 1024)
     return fail(XV_EINVAL, "geometry needs more than 160 KB of LDS");
   std::lock_guard<std::mutex> lk(g_geom_mu);

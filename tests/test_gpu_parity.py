@@ -195,7 +195,7 @@ def test_motion_geometry_never_changes_outputs():
         for nb, kx, th, rows in [(1, 2, 64, 1), (2, 18, 128, 1), (5, 8, 256, 1), (3, 6, 512, 1),
                                  (7, 10, 192, 1), (1, 2, 64, 2), (2, 18, 128, 2), (5, 8, 256, 2),
                                  (3, 6, 512, 2), (12, 12, 320, 2), (1, 2, 64, 3), (4, 6, 192, 3),
-                                 (7, 12, 448, 3)]:
+                                 (7, 12, 448, 3), (1, 2, 64, 5), (6, 4, 256, 5), (2, 2, 128, 5)]:
             xv.set_me_geometry(8, 9, nb, kx, th, rows)
             got = xv.encode_cube(cube, p).host()
             assert np.array_equal(got["mvs"], base["mvs"]), (nb, kx, th, rows)
@@ -206,9 +206,9 @@ def test_motion_geometry_never_changes_outputs():
     for N, R in ((4, 3), (16, 8), (32, 5)):
         q = xv.Params(bit_depth=10, qp=22, block=N, search_range=R, gop=4)
         try:
-            for rows in (1, 2, 3):
-                xv.set_me_geometry(N, R, 0, 0, 0, rows)
-                check_cube(f"rows{rows}_N{N}_R{R}", host, q)
+            for kx, rows in ((0, 1), (0, 2), (0, 3), (2, 5), (4, 5)):
+                xv.set_me_geometry(N, R, 0, kx, 0, rows)
+                check_cube(f"rows{rows}_kx{kx}_N{N}_R{R}", host, q)
         finally:
             xv.set_me_geometry(N, R)
 
@@ -219,7 +219,7 @@ def test_batch_tuner_installs_a_geometry_that_keeps_outputs():
     before = [xv.encode_cube(c, p).host() for c, p in zip(cubes, params)]
     try:
         g = xv.autotune_me_batch(cubes, params, max_candidates=6)
-        assert g["rows_per_lane"] in (1, 2, 3) and g["kernel_ms"] > 0
+        assert g["rows_per_lane"] in (1, 2, 3, 5) and g["kernel_ms"] > 0
         assert xv.get_me_geometry(16, 6)["threads"] == g["threads"]
         after = [e.host() for e in xv.encode_batch(cubes, params)]
         for a, b in zip(before, after):
