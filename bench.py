@@ -34,6 +34,30 @@ HBM_PEAK_GBS = 8000.0
 # v_sad_u16: 2 SAD terms per lane-op; 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 SAD_PEAK_TTERMS = 256 * 64 * 2.4e9 * 2 / 1e12
 
+# Measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB
+# copy), with the sha256 of the kernel sources they were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "s2cloud_sweep_hbm_traffic.json")
+
+
+def _measured_traffic():
+    """Per-kernel HBM bytes per launch from the committed counter summary, or
+    None when any listed kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        for rel, digest in t["sources_sha256"].items():
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+    except (OSError, KeyError, ValueError):
+        return None
+    out = {}
+    for k, v in t["per_launch_bytes"].items():
+        out.setdefault(k.split("<")[0], []).append(float(v))
+    # each kernel launches equally often per block size in the sweep step
+    return {k: sum(v) / len(v) for k, v in out.items()}
+
 
 def _percentile(xs, q):
     xs = sorted(xs)
@@ -220,6 +244,10 @@ def main():
     ap.add_argument("--mode", choices=["both", "batched", "plain"], default="both")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix section")
     ap.add_argument("--no-bits", action="store_true", help="skip the bitstream section")
+    ap.add_argument("--counters", action="store_true",
+                    help="workload for hardware-counter runs only: one 1 GiB device copy (the "
+                         "calibration of FETCH_SIZE / WRITE_SIZE), then one batched sweep step "
+                         "with the geometry file's geometry; prints no result line")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the motion-search geometry tuner (model defaults)")
     ap.add_argument("--geometry-file", default=None,
@@ -252,6 +280,14 @@ def main():
     outs = [torch.empty_like(cube) for _ in runs]
     pxb_step = wl.px_band * len(runs)
 
+    if args.counters:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # launch-geometry tuning (outside the timed region; outputs never depend on it)
     tuning = {}
     cached = None
@@ -276,6 +312,17 @@ def main():
     if args.geometry_file and cached is None:
         with open(args.geometry_file, "w") as f:
             json.dump(tuning, f)
+
+    if args.counters:
+        if cached is None:
+            raise SystemExit("--counters needs an existing --geometry-file")
+        encs = xv.encode_batch([cube] * len(params), params)
+        xv.decode_batch(encs, outs)
+        torch.cuda.synchronize()
+        for e in encs:
+            e.free()
+        print("[bench] counter workload done", file=sys.stderr, flush=True)
+        return
 
     def step_plain(lat=None):
         ms = []
@@ -370,6 +417,7 @@ def main():
     if "plain" in res and "batched" in res:
         line["speedup_batched_vs_plain"] = round(res["batched"]["value"] / res["plain"]["value"], 3)
     if prof is not None:
+        traffic = _measured_traffic() or {}
         me = prof["me"]
         enc = prof["encode"]
         dec = prof["decode"]
@@ -379,17 +427,24 @@ def main():
         line["roofline"] = {"kernel": "me_kernel (motion search)", "bound": "alu",
                             "achieved": round(achieved, 3), "peak": round(SAD_PEAK_TTERMS, 2),
                             "unit": "T SAD-terms/s", "frac": round(achieved / SAD_PEAK_TTERMS, 4),
-                            "traffic": None, "avg_launch_ms": round(me_avg_ms, 4),
+                            "traffic": (round(traffic["me_kernel"])
+                                        if "me_kernel" in traffic else None),
+                            "traffic_unit": "bytes per launch",
+                            "avg_launch_ms": round(me_avg_ms, 4),
                             "launches": me["launches"], "terms_per_launch": me_terms}
         for name, d in (("encode_kernel (fused transform coding)", enc),
                         ("decode_kernel", dec)):
             if d["launches"]:
                 avg = d["ms"] / d["launches"]
                 gbs = d["work"] / d["launches"] / (avg * 1e-3) / 1e9
+                kname = name.split(" ")[0]
                 key = "roofline_encode" if name.startswith("encode") else "roofline_decode"
                 line[key] = {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                             "frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "traffic": (round(traffic[kname]) if kname in traffic else None),
+                             "traffic_unit": "bytes per launch",
+                             "algorithmic_bytes_per_launch": round(d["work"] / d["launches"]),
                              "avg_launch_ms": round(avg, 4), "launches": d["launches"]}
         line["kernel_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()
                                       if v["launches"]}

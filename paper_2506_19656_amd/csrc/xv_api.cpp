@@ -371,7 +371,10 @@ int launch_segments(const std::vector<SegSrc>& src, int tpj_kind, const MeGeom& 
       g.tpj = tpj;
       g.tile0 = tiles;
       tiles += n * tpj;
-      work += tpj_kind == 0 ? xf_frames(e, s) * 3.0 * e->Hp * e->Wp : me_work(e, s);
+      // transform: algorithmic bytes (cur + pred in, level + recon out, 8 B per
+      // sample; an I step has a constant prediction, 6 B); search: SAD terms
+      work += tpj_kind == 0 ? xf_frames(e, s) * 3.0 * e->Hp * e->Wp * (s == 0 ? 6.0 : 8.0)
+                            : me_work(e, s);
     }
     d.tiles = tiles;
     int rc = launch(d, work);
@@ -402,7 +405,7 @@ int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s) {
       if (rc != XV_OK) return rc;
     }
     int rc = launch_segments(src, 0, geom, [&](const LaunchDesc& d, double work) {
-      ProfScope ps(XV_K_ENCODE, s, work * 8.0);  // cur + pred in, level + recon out
+      ProfScope ps(XV_K_ENCODE, s, work);
       XV_HIP(launch_encode(N, d, s), "transform kernel");
       return XV_OK;
     });
@@ -486,10 +489,11 @@ int decode_launch(const std::vector<DecSrc>& src, hipStream_t s) {
       g.tpj = tpj;
       g.tile0 = tiles;
       tiles += n * tpj;
-      work += (double)n * 3.0 * e->Hp * e->Wp;
+      // level + pred in, recon out: 6 B per sample (an I step has no pred read)
+      work += (double)n * 3.0 * e->Hp * e->Wp * (st == 0 ? 4.0 : 6.0);
     }
     d.tiles = tiles;
-    ProfScope ps(XV_K_DECODE, s, work * 6.0);  // level + pred in, recon out
+    ProfScope ps(XV_K_DECODE, s, work);
     XV_HIP(launch_decode(N, d, s), "decode kernel");
   }
   return XV_OK;
@@ -1302,7 +1306,7 @@ int iterate(xv_server* sv) {
       if (rc != XV_OK) return rc;
     }
     int rc = launch_segments(kv.second, 0, geom, [&](const LaunchDesc& d, double work) {
-      ProfScope ps(XV_K_ENCODE, sv->s, work * 8.0);
+      ProfScope ps(XV_K_ENCODE, sv->s, work);
       XV_HIP(launch_encode(N, d, sv->s), "transform kernel");
       sv->st.launches++;
       return XV_OK;
