@@ -30,7 +30,8 @@
  *   reconstruction        [G][T][3][Hp][Wp] u16   Hp, Wp = H, W rounded up
  *                                                 to a multiple of N
  *   levels                [G][T][3][Hb][Wb][N][N] i16 (block-major; inside a
- *                          block row l = vertical frequency, column k)
+ *                          block column-major: the level of vertical
+ *                          frequency l, horizontal frequency k at k * N + l)
  *   motion vectors        [G][T][Hb][Wb][2] i8 (dx, dy); zero in I pictures
  *   coefficient bits      [G][T][3][Hb][Wb] u32
  *   motion-vector bits    [G][T][Hb][Wb] u32

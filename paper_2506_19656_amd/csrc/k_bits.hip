@@ -144,7 +144,7 @@ __device__ inline void build_scan_table(uint16_t* scan, int N) {
     const int d = x + y;
     const int before = d < N ? d * (d + 1) / 2 : N * N - (2 * N - 1 - d) * (2 * N - d) / 2;
     const int first_x = d < N ? 0 : d - N + 1;
-    scan[before + x - first_x] = (uint16_t)i;
+    scan[before + x - first_x] = (uint16_t)(x * N + y);  // levels are column-major
   }
 }
 

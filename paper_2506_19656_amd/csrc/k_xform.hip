@@ -18,16 +18,66 @@
 // handles channel c.  Row stages give one thread one block row, column stages
 // one block column; intermediate tiles stay in LDS, so HBM sees each sample
 // read and written once: cur + prediction in, levels + reconstruction out.
+//
+// Arithmetic: every product is a v_dot2 of two 16-bit pairs with the matrix
+// entries as instruction literals.  The forward row stage and both inverse
+// stages use the even/odd (butterfly) factorisation of the H.265 matrices;
+// the forward column stage, whose inputs may need the full 16 bits, stays a
+// plain matrix product.  All sums are exact integers, so the factorised
+// forms give the same results as the matrix products they replace.
+#include <utility>
+
 #include "xv_internal.h"
 
 namespace xv {
 
 namespace {
 
-__device__ inline int ue_len(uint32_t k) { return 2 * (31 - __clz((int)(k + 1))) + 1; }
-__device__ inline int se_len(int v) {
-  return ue_len(v > 0 ? (uint32_t)(2 * v - 1) : (uint32_t)(-2 * v));
+// ---------------------------------------------------------------------------
+// Compile-time loops: f(Ic<0>{}), ..., f(Ic<n-1>{}), so that loop indices are
+// constant expressions (matrix entries become instruction literals).
+// ---------------------------------------------------------------------------
+template <int I>
+using Ic = std::integral_constant<int, I>;
+
+#define XV_INLINE __attribute__((always_inline))
+
+template <class F, int... I>
+__device__ inline XV_INLINE void unroll_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(Ic<I>{}), ...);
 }
+template <int n, class F>
+__device__ inline XV_INLINE void unroll(F&& f) {
+  unroll_impl(f, std::make_integer_sequence<int, n>{});
+}
+
+// Packed 16-bit pairs (lo = element 2j, hi = element 2j + 1).
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline s16x2 as_v(uint32_t x) { return __builtin_bit_cast(s16x2, x); }
+__device__ inline uint32_t as_u(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ inline uint32_t swap_halves(uint32_t x) { return (x >> 16) | (x << 16); }
+__device__ inline uint32_t padd(uint32_t a, uint32_t b) { return as_u(as_v(a) + as_v(b)); }
+__device__ inline uint32_t psub(uint32_t a, uint32_t b) { return as_u(as_v(a) - as_v(b)); }
+// Two int32 -> one pair, each saturated to [-32768, 32767].
+__device__ inline uint32_t pack_sat(int lo, int hi) {
+  return as_u(__builtin_amdgcn_cvt_pk_i16(lo, hi));
+}
+
+__host__ __device__ constexpr uint32_t cpair(int lo, int hi) {
+  return ((uint32_t)lo & 0xffffu) | (((uint32_t)hi & 0xffffu) << 16);
+}
+
+// Coefficient pair (M_n[k0][m0], M_n[k1][m1]), formed at compile time.
+template <int n, int k0, int m0, int k1, int m1>
+constexpr uint32_t kPair = cpair(dct_coef(n, k0, m0), dct_coef(n, k1, m1));
+
+// acc + lo(c) lo(x) + hi(c) hi(x), signed 16-bit halves, exact in int32.
+__device__ inline int dot2(uint32_t c, uint32_t x, int acc) {
+  return __builtin_amdgcn_sdot2(as_v(c), as_v(x), acc, false);
+}
+
+__device__ inline int clz32(uint32_t v) { return __clz((int)v); }
 
 template <int N>
 struct Tile {
@@ -40,15 +90,133 @@ struct Tile {
   static constexpr int kEncWaves = (N == 8 || N == 16) ? 8 : 1;
 };
 
+// ---------------------------------------------------------------------------
+// Forward n-point transform of x (n/2 packed pairs): out[S k] = sum_m M_n[k][m]
+// x[m] + rnd.  Odd outputs come from o[m] = x[m] - x[n-1-m] (M_n[k][n-1-m] =
+// -M_n[k][m] for odd k), even ones are the n/2-point transform of e[m] = x[m]
+// + x[n-1-m] (M_n[2k][m] = M_{n/2}[k][m]).  The pre-adds run on packed 16-bit
+// pairs: for residuals |x| <= 4095 the sums stay within 8190, 16380 and
+// 32760 after one, two and three levels, and the 4-point base takes a plain
+// product, so no level overflows 16 bits for n <= 32.
+// ---------------------------------------------------------------------------
+template <int n, int S, int NF>
+__device__ inline void fwd_part(const uint32_t (&xp)[n / 2], int (&out)[NF], int rnd) {
+  if constexpr (n == 4) {
+    unroll<4>([&](auto kk) XV_INLINE {
+      constexpr int k = kk;
+      int a = dot2(kPair<4, k, 0, k, 1>, xp[0], rnd);
+      a = dot2(kPair<4, k, 2, k, 3>, xp[1], a);
+      out[S * k] = a;
+    });
+  } else {
+    uint32_t ep[n / 4], op[n / 4];
+    unroll<n / 4>([&](auto jj) XV_INLINE {
+      constexpr int j = jj;
+      // (x[n-1-2j], x[n-2-2j]) against (x[2j], x[2j+1])
+      const uint32_t m = swap_halves(xp[n / 2 - 1 - j]);
+      ep[j] = padd(xp[j], m);
+      op[j] = psub(xp[j], m);
+    });
+    unroll<n / 2>([&](auto kk) XV_INLINE {
+      constexpr int k = 2 * kk + 1;
+      int a = rnd;
+      unroll<n / 4>([&](auto jj) XV_INLINE {
+        constexpr int j = jj;
+        a = dot2(kPair<n, k, 2 * j, k, 2 * j + 1>, op[j], a);
+      });
+      out[S * k] = a;
+    });
+    fwd_part<n / 2, 2 * S, NF>(ep, out, rnd);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse n-point transform: out[m] = sum_k M_n[k][m] y[k] + rnd, m < n, with
+// y given as packed pairs in "inverse order": the odd entries (y1, y3), (y5,
+// y7), ... first, then the even entries y0, y2, ... in the same order
+// recursively, down to a 4-point part in natural order.  out[m] = E[m] +
+// O[m] and out[n-1-m] = E[m] - O[m], E the inverse n/2-point transform of
+// the even entries, O the odd entries against the odd rows.
+// ---------------------------------------------------------------------------
+template <int n>
+__device__ inline void inv_part(const uint32_t* ip, int (&out)[n], int rnd) {
+  if constexpr (n == 4) {
+    unroll<4>([&](auto mm) XV_INLINE {
+      constexpr int m = mm;
+      int a = dot2(kPair<4, 0, m, 1, m>, ip[0], rnd);
+      a = dot2(kPair<4, 2, m, 3, m>, ip[1], a);
+      out[m] = a;
+    });
+  } else {
+    int E[n / 2];
+    inv_part<n / 2>(ip + n / 4, E, rnd);
+    unroll<n / 2>([&](auto mm) XV_INLINE {
+      constexpr int m = mm;
+      int o = 0;
+      unroll<n / 4>([&](auto jj) XV_INLINE {
+        constexpr int j = jj;
+        o = dot2(kPair<n, 4 * j + 1, m, 4 * j + 3, m>, ip[j], o);
+      });
+      out[m] = E[m] + o;
+      out[n - 1 - m] = E[m] - o;
+    });
+  }
+}
+
+// Element of y held in slot s of the inverse order, and the slot of element k.
+__host__ __device__ constexpr int inv_elem(int n, int s) {
+  if (n == 4) return s;
+  if (s < n / 2) return 2 * s + 1;
+  return 2 * inv_elem(n / 2, s - n / 2);
+}
+template <int N>
+__device__ inline int inv_slot(int k) {
+  int slot = 0, kk = k;
+#pragma unroll
+  for (int n = N; n > 4; n >>= 1) {
+    if (kk & 1) return slot + (kk >> 1);
+    slot += n / 2;
+    kk >>= 1;
+  }
+  return slot + kk;
+}
+
+// y[0..N-1] (int32, saturated to 16 bits) as pairs in inverse order.
+template <int N>
+__device__ inline void to_inverse_order(const int (&y)[N], uint32_t (&ip)[N / 2]) {
+  unroll<N / 2>([&](auto ss) XV_INLINE {
+    constexpr int s = ss;
+    constexpr int e0 = inv_elem(N, 2 * s), e1 = inv_elem(N, 2 * s + 1);
+    ip[s] = pack_sat(y[e0], y[e1]);
+  });
+}
+
+// Forward column stage: out[l] = sum_y M[l][y] T[y] + rnd, T as N/2 pairs.
+template <int N>
+__device__ inline void fwd_full(const uint32_t* tp, int (&out)[N], int rnd) {
+  uint32_t t[N / 2];
+#pragma unroll
+  for (int j = 0; j < N / 2; j++) t[j] = tp[j];
+  unroll<N>([&](auto ll) XV_INLINE {
+    constexpr int l = ll;
+    int a = rnd;
+    unroll<N / 2>([&](auto jj) XV_INLINE {
+      constexpr int j = jj;
+      a = dot2(kPair<N, l, 2 * j, l, 2 * j + 1>, t[j], a);
+    });
+    out[l] = a;
+  });
+}
+
 // LDS layout per workgroup, encode (int16):
 //   TD [3][NBW][N][P]  forward row-stage output transposed ([k][y]); each
 //                      column thread then overwrites its own row k with the
 //                      column's levels ([k][l])
-//   E  [3][NBW][N][P]  inverse column-stage output ([y][k])
+//   E  [3][NBW][N][P]  inverse column-stage output, row y, entries in
+//                      inverse order
 //   scan [N*N]         scan position -> offset (k * P + l) of the level in a
 //                      block's TD tile
 //   sums               per-workgroup squared error per channel, bits
-// Residual rows and dequantised columns stay in registers.
 template <int N>
 struct alignas(16) LdsEnc {
   int16_t TD[3][Tile<N>::NBW][N][Tile<N>::P];
@@ -56,15 +224,11 @@ struct alignas(16) LdsEnc {
   uint16_t scan[N * N];
   unsigned long long sse[3];
   uint32_t cbits[3][Tile<N>::NBW];
-  uint32_t nnz[3][Tile<N>::NBW];
   uint32_t mvbits;
 };
 
-// Decode: the levels as stored (raster [l][k] per block) and the inverse
-// column-stage output.
 template <int N>
 struct alignas(16) LdsDec {
-  int16_t L[3][Tile<N>::NBW][N * N];
   int16_t E[3][Tile<N>::NBW][N][Tile<N>::P];
 };
 
@@ -102,88 +266,6 @@ __device__ inline bool locate(const LaunchDesc& jd, TileCoord& tc) {
   return true;
 }
 
-// ---------------------------------------------------------------------------
-// Matrix products on v_dot2c_i32_i16: two 16x16-bit products per lane-op.
-// Every stage is an outer-product loop over input pairs m: all N outputs
-// accumulate acc[k] += M[k][2m] x[2m] + M[k][2m+1] x[2m+1], the coefficient
-// pairs coming through scalar loads (SGPR operands) from tables passed by
-// pointer, the input pair from LDS.  Inputs are 16-bit by construction:
-// residuals (|r| <= 4095), row-stage outputs (|T| < 2^15), dequantised levels
-// and the inverse column-stage output (both clipped to 16 bits).
-// Table layout per N: fwd[m][k] = (M[k][2m], M[k][2m+1]) (y = M x), then
-// inv[m][n] = (M[2m][n], M[2m+1][n]) (x = M^T y); tables for N = 4, 8, 16,
-// 32 follow each other.
-// ---------------------------------------------------------------------------
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-
-__device__ inline int dot2(uint32_t coef_pair, uint32_t x_pair, int acc) {
-  return __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, coef_pair),
-                                __builtin_bit_cast(s16x2, x_pair), acc, false);
-}
-
-__host__ __device__ constexpr uint32_t cpair(int lo, int hi) {
-  return ((uint32_t)lo & 0xffffu) | (((uint32_t)hi & 0xffffu) << 16);
-}
-
-__host__ __device__ constexpr int coef_offset(int N) {
-  return N == 4 ? 0 : (N == 8 ? 2 * 4 * 2 : (N == 16 ? 2 * 4 * 2 + 2 * 8 * 4 : 2 * 4 * 2 + 2 * 8 * 4 + 2 * 16 * 8));
-}
-constexpr int kCoefWords = coef_offset(32) + 2 * 32 * 16;
-
-struct CoefTables {
-  uint32_t w[kCoefWords];
-};
-
-constexpr CoefTables make_coef_tables() {
-  CoefTables t{};
-  for (int N = 4; N <= 32; N *= 2) {
-    uint32_t* f = t.w + coef_offset(N);
-    uint32_t* v = f + (N / 2) * N;
-    for (int m = 0; m < N / 2; m++)
-      for (int k = 0; k < N; k++) {
-        f[m * N + k] = cpair(dct_coef(N, k, 2 * m), dct_coef(N, k, 2 * m + 1));
-        v[m * N + k] = cpair(dct_coef(N, 2 * m, k), dct_coef(N, 2 * m + 1, k));
-      }
-  }
-  return t;
-}
-
-__constant__ CoefTables kCoef = make_coef_tables();
-
-// acc[k] = sum_m dot2(table[m][k], src[m]); src: N/2 packed pairs in LDS.
-template <int N>
-__device__ inline void mat_pairs(const uint32_t* __restrict__ tb, const uint32_t* src, int (&acc)[N]) {
-#pragma unroll
-  for (int k = 0; k < N; k++) acc[k] = 0;
-  constexpr int kUnrollM = N <= 8 ? N / 2 : 4;
-#pragma unroll kUnrollM
-  for (int m = 0; m < N / 2; m++) {
-    const uint32_t x = src[m];
-#pragma unroll
-    for (int k = 0; k < N; k++) acc[k] = dot2(tb[m * N + k], x, acc[k]);
-  }
-}
-
-// The same with the input pairs in registers.
-template <int N>
-__device__ inline void mat_pairs_r(const uint32_t* __restrict__ tb, const uint32_t (&src)[N / 2],
-                                   int (&acc)[N]) {
-#pragma unroll
-  for (int k = 0; k < N; k++) acc[k] = 0;
-#pragma unroll
-  for (int m = 0; m < N / 2; m++) {
-#pragma unroll
-    for (int k = 0; k < N; k++) acc[k] = dot2(tb[m * N + k], src[m], acc[k]);
-  }
-}
-
-// Packed 16-bit residual pair: (cur - pred) per half.
-__device__ inline uint32_t sub_pairs(uint32_t a, uint32_t b) {
-  const int lo = (int)(a & 0xffffu) - (int)(b & 0xffffu);
-  const int hi = (int)(a >> 16) - (int)(b >> 16);
-  return ((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16);
-}
-
 // Packed u16 row (N samples) from global memory.
 template <int N>
 __device__ inline void load_row_packed(const uint16_t* p, uint32_t (&v)[N / 2]) {
@@ -217,26 +299,30 @@ __device__ inline void store_row_packed(uint16_t* p, const uint32_t (&v)[N / 2])
 // Prediction row as packed pairs: I -> 2^(B-1); P -> the reference displaced
 // by (dx, dy).  A coded vector keeps the displaced block inside the padded
 // picture; the clamp only guarantees in-bounds reads for a corrupt vector.
+// The row is read as aligned dwords and shifted by one sample when the
+// displaced column is odd; the extra dword is then in bounds (rx + N is odd
+// and Wp even, so rx + N < Wp).
 template <int N>
-__device__ inline void pred_row(const FrameJob& job, int c, int y, int x0, int dx, int dy,
+__device__ inline void pred_row(const FrameJob& job, int c, int r, int y, int x0, int dx, int dy,
                                 uint32_t (&pp)[N / 2]) {
   if (job.intra) {
     const uint32_t h = 1u << (job.bit_depth - 1);
 #pragma unroll
     for (int j = 0; j < N / 2; j++) pp[j] = h | (h << 16);
   } else {
-    const int yb = y - (y % N);
-    const int ry = min(max(yb + dy, 0), job.Hp - N) + (y - yb);
+    const int yb = y - r;
+    const int ry = min(max(yb + dy, 0), job.Hp - N) + r;
     const int rx = min(max(x0 + dx, 0), job.Wp - N);
-    const uint16_t* rp = job.ref + (size_t)c * job.Hp * job.Wp + (size_t)ry * job.Wp + rx;
-    if ((rx & 1) == 0) {
-      const uint32_t* r32 = (const uint32_t*)rp;
+    const uint32_t* r32 = (const uint32_t*)(job.ref + (size_t)c * job.Hp * job.Wp +
+                                            (size_t)ry * job.Wp + (rx & ~1));
+    uint32_t w[N / 2 + 1];
 #pragma unroll
-      for (int j = 0; j < N / 2; j++) pp[j] = r32[j];
-    } else {
+    for (int j = 0; j < N / 2; j++) w[j] = r32[j];
+    const int odd = rx & 1;
+    w[N / 2] = odd ? r32[N / 2] : 0u;
+    const uint32_t sh = (uint32_t)odd << 4;
 #pragma unroll
-      for (int j = 0; j < N / 2; j++) pp[j] = (uint32_t)rp[2 * j] | ((uint32_t)rp[2 * j + 1] << 16);
-    }
+    for (int j = 0; j < N / 2; j++) pp[j] = __builtin_amdgcn_alignbit(w[j + 1], w[j], sh);
   }
 }
 
@@ -244,7 +330,8 @@ __device__ inline void pred_row(const FrameJob& job, int c, int y, int x0, int d
 // evaluated exactly in 32 bits: with X = level * IQ * 16 (|X| < 2^26) and
 // sh = bd - qP/6, the power of two factors out of the rounding shift, so
 // d = clip16((X + 2^(sh-1)) >> sh) for sh > 0 and clip16(X << -sh) for
-// sh <= 0, where clamping X to +-2^15 first changes no result.
+// sh <= 0, where clamping X to +-2^15 first changes no result.  The final
+// clip16 is the saturation of the pair packing.
 struct Dequant {
   int m;   // IQ[qP%6] * 16
   int sh;  // bd - qP/6
@@ -252,73 +339,144 @@ struct Dequant {
 
 __device__ inline Dequant dequant_params(int qP, int bd) { return Dequant{kIQ[qP % 6] * 16, bd - qP / 6}; }
 
-__device__ inline int clamp16(int v) { return min(max(v, -32768), 32767); }
-
-__device__ inline int dequant(int lv, const Dequant& q) {
-  const int X = lv * q.m;
-  if (q.sh > 0) return clamp16((X + (1 << (q.sh - 1))) >> q.sh);
-  return clamp16(min(max(X, -32768), 32768) << (-q.sh));
+template <int N>
+__device__ inline void dequant_pairs(const int (&lv)[N], const Dequant& q, uint32_t (&ip)[N / 2]) {
+  int d[N];
+  if (q.sh > 0) {
+    const int rnd = 1 << (q.sh - 1);
+#pragma unroll
+    for (int l = 0; l < N; l++) d[l] = (__mul24(lv[l], q.m) + rnd) >> q.sh;
+  } else {
+#pragma unroll
+    for (int l = 0; l < N; l++) d[l] = min(max(__mul24(lv[l], q.m), -32768), 32768) << (-q.sh);
+  }
+  to_inverse_order<N>(d, ip);
 }
 
 // Inverse column stage of block column k from its dequantised column (pairs
-// in registers): E[y][k] = clip16((sum_l M[l][y] d[l] + 64) >> 7).
+// in inverse order): E[y][slot(k)] = clip16((sum_l M[l][y] d[l] + 64) >> 7).
 template <int N>
-__device__ inline void inverse_column(const uint32_t* inv, const uint32_t (&dpair)[N / 2],
-                                      int16_t (*E)[Tile<N>::P], int k) {
+__device__ inline void inverse_column(const uint32_t (&dq)[N / 2], int16_t (*E)[Tile<N>::P],
+                                      int slot) {
   int acc[N];
-  mat_pairs_r<N>(inv, dpair, acc);
+  inv_part<N>(dq, acc, 64);
 #pragma unroll
-  for (int y = 0; y < N; y++) E[y][k] = (int16_t)clamp16((acc[y] + 64) >> 7);
+  for (int y = 0; y < N; y += 2) {
+    const uint32_t e = pack_sat(acc[y] >> 7, acc[y + 1] >> 7);
+    E[y][slot] = (int16_t)(e & 0xffffu);
+    E[y + 1][slot] = (int16_t)(e >> 16);
+  }
 }
 
-// Inverse row stage and reconstruction of block row r into packed pairs.
+// Inverse row stage and reconstruction of block row r into packed pairs:
+// rec = clip(pred + ((sum_k M[k][x] E[k] + 2^(19-B)) >> (20-B)), 0, 2^B-1).
+// The residual is saturated to 16 bits and added with 16-bit saturation; as
+// |pred| < 2^12, neither saturation can change the clipped result.
 template <int N>
-__device__ inline void inverse_row(const uint32_t* inv, const int16_t* Erow,
-                                   const uint32_t (&pp)[N / 2], int B, uint32_t (&rp)[N / 2]) {
+__device__ inline void inverse_row(const int16_t* Erow, const uint32_t (&pp)[N / 2], int B,
+                                   uint32_t (&rp)[N / 2]) {
   const int sh = 20 - B;
-  const int rnd = 1 << (19 - B);
-  const int Lmax = (1 << B) - 1;
+  uint32_t ein[N / 2];
+#pragma unroll
+  for (int j = 0; j < N / 2; j++) ein[j] = ((const uint32_t*)Erow)[j];
   int acc[N];
-  mat_pairs<N>(inv, (const uint32_t*)Erow, acc);
+  inv_part<N>(ein, acc, 1 << (19 - B));
+  const s16x2 zero = {0, 0};
+  const s16x2 top = {(short)((1 << B) - 1), (short)((1 << B) - 1)};
 #pragma unroll
   for (int j = 0; j < N / 2; j++) {
-    int v0 = (int)(pp[j] & 0xffffu) + ((acc[2 * j] + rnd) >> sh);
-    int v1 = (int)(pp[j] >> 16) + ((acc[2 * j + 1] + rnd) >> sh);
-    v0 = v0 < 0 ? 0 : (v0 > Lmax ? Lmax : v0);
-    v1 = v1 < 0 ? 0 : (v1 > Lmax ? Lmax : v1);
-    rp[j] = (uint32_t)v0 | ((uint32_t)v1 << 16);
+    const s16x2 res = as_v(pack_sat(acc[2 * j] >> sh, acc[2 * j + 1] >> sh));
+    s16x2 v = __builtin_elementwise_add_sat(as_v(pp[j]), res);
+    v = __builtin_elementwise_min(__builtin_elementwise_max(v, zero), top);
+    rp[j] = as_u(v);
   }
 }
 
-// Rate proxy of every block of channel c in the tile (one wave per channel):
-// each nonzero level adds ue(run) + se(level) to its block's LDS counter.
+// Rate proxy of every block of channel c in the tile (one wave per channel).
+// Lane (b, j) takes scan positions jN .. jN+N-1 of block b.  Each nonzero
+// level at position p with previous nonzero q (-1 if none) costs ue(p-q-1) +
+// se(level) = 128 - 2 (clz(p - q) + clz(|level|)) bits; a lane adds up count
+// and clz terms with its own segment start as q of its first nonzero, then
+// replaces that term once the last nonzero of the earlier segments is known.
+// Returns nothing; adds 2^17 * count + sum of clz terms to s.cbits[c][b].
 template <int N>
 __device__ inline void block_bits(LdsEnc<N>& s, const TileCoord& tc, int c) {
-  constexpr int NBW = Tile<N>::NBW;
-  constexpr int S = N * N < 64 ? N * N : 64;  // lanes per block segment
-  constexpr int BPC = 64 / S;                  // blocks per pass
-  constexpr int CPB = (N * N) / S;             // chunks per block
   const int lane = threadIdx.x & 63;
-  const int seg = lane / S, pin = lane - seg * S;
-  for (int bb = 0; bb < NBW; bb += BPC) {
-    const int b = bb + seg;
-    const bool vb = (tc.bx0 + b) < tc.Wb;
-    int last = -1;
-    uint32_t acc = 0;
+  const int b = lane / N, j = lane - b * N;
+  const bool vb = (tc.bx0 + b) < tc.Wb;
+  const int16_t* tile = &s.TD[c][b][0][0];
+  const uint16_t* sc = s.scan + j * N;
+  uint32_t acc = 0;
+  int prev = -1, first = N;
+  if (vb) {
 #pragma unroll
-    for (int ci = 0; ci < CPB; ci++) {
-      const int p = ci * S + pin;
-      const int lv = vb ? (int)(&s.TD[c][b][0][0])[s.scan[p]] : 0;
-      const unsigned long long m = __ballot(lv != 0);
-      const unsigned long long segm = (S == 64) ? m : ((m >> (seg * S)) & ((1ull << S) - 1));
-      const unsigned long long below = segm & ((1ull << pin) - 1);
-      const int prev = below ? ci * S + 63 - __clzll((long long)below) : last;
-      if (lv != 0) acc += (uint32_t)(ue_len((uint32_t)(p - prev - 1)) + se_len(lv));
-      if (segm) last = ci * S + 63 - __clzll((long long)segm);
-      if (pin == 0 && segm) atomicAdd(&s.nnz[c][b], (uint32_t)__popcll(segm));
+    for (int i = 0; i < N; i++) {
+      const int lv = tile[sc[i]];
+      const uint32_t a = (uint32_t)(lv < 0 ? -lv : lv);
+      const uint32_t t = (uint32_t)(clz32((uint32_t)(i - prev)) + clz32(a)) + (1u << 17);
+      const bool nz = lv != 0;
+      acc += nz ? t : 0u;
+      first = (nz && first == N) ? i : first;
+      prev = nz ? i : prev;
     }
-    if (acc) atomicAdd(&s.cbits[c][b], acc);
   }
+  // last nonzero of the nearest earlier segment of the same block
+  const bool has = first < N;
+  const unsigned long long m = __ballot(has);
+  const unsigned long long below = m & ((1ull << lane) - 1) & ~((1ull << (b * N)) - 1);
+  const int src = below ? 63 - __clzll((long long)below) : lane;
+  const int src_last = __shfl(prev + (lane - b * N) * N, src);  // block-relative position
+  if (has) {
+    const int pf = j * N + first;
+    const int q = below ? src_last : -1;
+    acc += (uint32_t)clz32((uint32_t)(pf - q)) - (uint32_t)clz32((uint32_t)(first + 1));
+  }
+  if (vb && acc) atomicAdd(&s.cbits[c][b], acc);
+}
+
+template <int N, bool kMask>
+__device__ inline uint32_t row_sse(const uint32_t (&cp)[N / 2], const uint32_t (&rp)[N / 2],
+                                   const uint8_t* vm, int x0, int W) {
+  uint32_t pm[N / 2];
+#pragma unroll
+  for (int j = 0; j < N / 2; j++) pm[j] = 0xffffffffu;
+  if constexpr (kMask) {
+    uint32_t w[N / 4 > 0 ? N / 4 : 1];
+    if constexpr (N >= 16) {
+#pragma unroll
+      for (int q = 0; q < N / 16; q++) {
+        const uint4 v = ((const uint4*)vm)[q];
+        w[4 * q] = v.x;
+        w[4 * q + 1] = v.y;
+        w[4 * q + 2] = v.z;
+        w[4 * q + 3] = v.w;
+      }
+    } else if constexpr (N == 8) {
+      const uint2 v = *(const uint2*)vm;
+      w[0] = v.x;
+      w[1] = v.y;
+    } else {
+      w[0] = *(const uint32_t*)vm;
+    }
+#pragma unroll
+    for (int j = 0; j < N / 2; j++) {
+      const uint32_t h = w[j >> 1] >> (16 * (j & 1));  // bytes 2j, 2j+1: 0 or 1
+      const uint32_t t = (h & 0xffu) | ((h & 0xff00u) << 8);
+      pm[j] = __umul24(t, 0xffffu);
+    }
+  }
+  if (x0 + N > W) {
+#pragma unroll
+    for (int j = 0; j < N / 2; j++)
+      pm[j] &= (x0 + 2 * j < W ? 0xffffu : 0u) | (x0 + 2 * j + 1 < W ? 0xffff0000u : 0u);
+  }
+  int sse = 0;  // at most 32 * 4095^2 < 2^31
+#pragma unroll
+  for (int j = 0; j < N / 2; j++) {
+    const uint32_t d = psub(cp[j], rp[j]) & pm[j];
+    sse = dot2(d, d, sse);
+  }
+  return (uint32_t)sse;
 }
 
 template <int N>
@@ -330,8 +488,6 @@ encode_kernel(const LaunchDesc jr) {
   TileCoord tc;
   if (!locate<N>(jr, tc)) return;
   const FrameJob& job = *tc.job;
-  const uint32_t* __restrict__ fwd = jr.coef + coef_offset(N);
-  const uint32_t* __restrict__ inv = fwd + (N / 2) * N;
   build_scan<N>(s.scan);
 
   const int t = threadIdx.x;
@@ -346,10 +502,7 @@ encode_kernel(const LaunchDesc jr) {
   const int x0 = bx * N;
   const int y = tc.by * N + r;
   if (t < 3) s.sse[t] = 0ull;
-  if (t < 3 * NBW) {
-    s.cbits[t / NBW][t % NBW] = 0u;
-    s.nnz[t / NBW][t % NBW] = 0u;
-  }
+  if (t < 3 * NBW) s.cbits[t / NBW][t % NBW] = 0u;
   if (t == 0) s.mvbits = 0u;
 
   int dx = 0, dy = 0;
@@ -364,100 +517,73 @@ encode_kernel(const LaunchDesc jr) {
   uint32_t cp[N / 2], pp[N / 2];
   if (vb) {
     load_row_packed<N>(job.cur + c * plane + (size_t)y * job.Wp + x0, cp);
-    pred_row<N>(job, c, y, x0, dx, dy, pp);
+    pred_row<N>(job, c, r, y, x0, dx, dy, pp);
     uint32_t er[N / 2];
 #pragma unroll
-    for (int m = 0; m < N / 2; m++) er[m] = sub_pairs(cp[m], pp[m]);
-    int acc[N];
-    mat_pairs_r<N>(fwd, er, acc);
+    for (int m = 0; m < N / 2; m++) er[m] = psub(cp[m], pp[m]);  // |res| <= 4095
     const int s1 = L2N + B - 9;
-    const int rnd1 = 1 << (s1 - 1);
+    int acc[N];
+    fwd_part<N, 1, N>(er, acc, 1 << (s1 - 1));
 #pragma unroll
-    for (int k = 0; k < N; k++) s.TD[c][b][k][r] = (int16_t)((acc[k] + rnd1) >> s1);
+    for (int k = 0; k < N; k++) s.TD[c][b][k][r] = (int16_t)(acc[k] >> s1);
   }
   __syncthreads();
 
-  // Column stage of column k: forward transform, quantise (levels into the
-  // thread's own TD row, transposed), dequantise and inverse column
-  // transform from registers.
+  // Column stage of column k: forward transform, quantise (levels out to
+  // global memory, column-major inside the block, and into the thread's own
+  // TD row), dequantise and inverse column transform.
   if (vb) {
     const int k = r;
     const int qP = job.qp + 6 * (B - 8);
     const int qbits = 29 + qP / 6 - B - L2N;
-    const uint32_t off = (uint32_t)(job.intra ? 171 : 85) << (qbits - 9);
-    const uint32_t qf = (uint32_t)kQf[qP % 6];
+    const int off = (job.intra ? 171 : 85) << (qbits - 9);
+    const int offn = (1 << qbits) - 1 - off;
+    const int qf = kQf[qP % 6];
     const Dequant dqp = dequant_params(qP, B + L2N - 5);
-    // the row is only accessed as packed 32-bit pairs (no mixed-width aliasing)
     uint32_t* row = (uint32_t*)s.TD[c][b][k];
     int acc[N];
-    mat_pairs<N>(fwd, row, acc);
-    uint32_t lpair[N / 2], dpair[N / 2];
+    fwd_full<N>(row, acc, 1 << (L2N + 5));
+    // level = sgn(C) min(32767, (|C| Qf + off) >> qbits) in signed form:
+    // C >= 0: (C Qf + off) >> qbits; C < 0: (C Qf + 2^qbits - 1 - off) >> qbits
+    // (|C Qf| < 2^30, so nothing overflows)
+    int lv[N];
 #pragma unroll
-    for (int l = 0; l < N; l += 2) {
-      int lv[2], dq[2];
-#pragma unroll
-      for (int h = 0; h < 2; h++) {
-        const int C = (acc[l + h] + (1 << (L2N + 5))) >> (L2N + 6);
-        const uint32_t a = (uint32_t)(C < 0 ? -C : C);
-        uint32_t mq = (a * qf + off) >> qbits;
-        mq = mq > 32767u ? 32767u : mq;
-        lv[h] = C < 0 ? -(int)mq : (int)mq;
-        dq[h] = dequant(lv[h], dqp);
-      }
-      lpair[l / 2] = ((uint32_t)lv[0] & 0xffffu) | ((uint32_t)lv[1] << 16);
-      dpair[l / 2] = ((uint32_t)dq[0] & 0xffffu) | ((uint32_t)dq[1] << 16);
+    for (int l = 0; l < N; l++) {
+      const int C = acc[l] >> (L2N + 6);
+      const int v = (__mul24(C, qf) + (C >= 0 ? off : offn)) >> qbits;
+      lv[l] = min(max(v, -32767), 32767);
     }
+    uint32_t lpair[N / 2];
 #pragma unroll
-    for (int m = 0; m < N / 2; m++) row[m] = lpair[m];
-    inverse_column<N>(inv, dpair, s.E[c][b], k);
+    for (int m = 0; m < N / 2; m++) {
+      lpair[m] = pack_sat(lv[2 * m], lv[2 * m + 1]);
+      row[m] = lpair[m];
+    }
+    int16_t* dst = job.lev + (((size_t)c * tc.Hb + tc.by) * tc.Wb + bx) * (N * N) + k * N;
+    store_row_packed<N>((uint16_t*)dst, lpair);
+    uint32_t dq[N / 2];
+    dequant_pairs<N>(lv, dqp, dq);
+    inverse_column<N>(dq, s.E[c][b], inv_slot<N>(k));
   }
   __syncthreads();
 
-  // Levels out (block-major, raster [l][k] inside a block) in 16-byte
-  // chunks gathered from the transposed tiles.
-  {
-    constexpr int CH = (N * N) / 8;  // uint4 chunks per block
-    for (int e = t; e < 3 * NBW * CH; e += blockDim.x) {
-      const int cb = e / CH, q = e - cb * CH;
-      const int cc = cb / NBW, bb = cb - cc * NBW;
-      if (tc.bx0 + bb >= tc.Wb) continue;
-      const int16_t* tile = &s.TD[cc][bb][0][0];
-      uint32_t w[4];
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int i0 = q * 8 + 2 * j, i1 = i0 + 1;
-        const int v0 = tile[(i0 % N) * Tile<N>::P + i0 / N];
-        const int v1 = tile[(i1 % N) * Tile<N>::P + i1 / N];
-        w[j] = ((uint32_t)v0 & 0xffffu) | ((uint32_t)v1 << 16);
-      }
-      int16_t* dst = job.lev + (((size_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb) * (N * N);
-      ((uint4*)dst)[q] = make_uint4(w[0], w[1], w[2], w[3]);
-    }
-  }
+  // Rate proxy per block and channel (levels in TD).
+  block_bits<N>(s, tc, c);
 
   // Inverse row stage, reconstruction, squared error.
   if (vb) {
     uint32_t rp[N / 2];
-    inverse_row<N>(inv, s.E[c][b][r], pp, B, rp);
+    inverse_row<N>(s.E[c][b][r], pp, B, rp);
     store_row_packed<N>(job.rec + c * plane + (size_t)y * job.Wp + x0, rp);
     if (c < job.nch && y < job.H) {
       const bool usemask = job.vmask != nullptr && *job.nan_total != 0u;
-      const uint8_t* vm = usemask ? job.vmask + c * plane + (size_t)y * job.Wp + x0 : nullptr;
-      uint32_t sse = 0;  // at most 32 * 4095^2 < 2^32
-#pragma unroll
-      for (int j = 0; j < N; j++) {
-        const int cv = (int)((cp[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-        const int rv = (int)((rp[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-        const bool ok = (x0 + j < job.W) && (!usemask || vm[j]);
-        const int e = cv - rv;
-        sse += ok ? (uint32_t)(e * e) : 0u;
-      }
+      const uint32_t sse =
+          usemask ? row_sse<N, true>(cp, rp, job.vmask + c * plane + (size_t)y * job.Wp + x0, x0, job.W)
+                  : row_sse<N, false>(cp, rp, nullptr, x0, job.W);
       if (sse) atomicAdd(&s.sse[c], (unsigned long long)sse);
     }
   }
 
-  // Rate proxy per block and channel; vector bits.
-  block_bits<N>(s, tc, c);
   if (c == 0 && r == 0 && vb) {
     int8_t* mv = job.mv + ((size_t)tc.by * tc.Wb + bx) * 2;
     uint32_t bits = 0;
@@ -470,7 +596,10 @@ encode_kernel(const LaunchDesc jr) {
         pmx = mv[-2];
         pmy = mv[-1];
       }
-      bits = (uint32_t)(se_len(dx - pmx) + se_len(dy - pmy));
+      // se(v) costs 2 floor(log2 |v|) + 3 bits, 1 for v = 0
+      const int ex = dx - pmx, ey = dy - pmy;
+      bits = (ex ? 65u - 2u * (uint32_t)clz32((uint32_t)abs(ex)) : 1u) +
+             (ey ? 65u - 2u * (uint32_t)clz32((uint32_t)abs(ey)) : 1u);
     }
     job.mbits[(size_t)tc.by * tc.Wb + bx] = bits;
     if (bits) atomicAdd(&s.mvbits, bits);
@@ -479,8 +608,11 @@ encode_kernel(const LaunchDesc jr) {
   if (t < 3 * NBW) {
     const int cc = t / NBW, bb = t - cc * NBW;
     if (tc.bx0 + bb < tc.Wb) {
-      const uint32_t nnz = s.nnz[cc][bb];
-      const uint32_t bits = 1u + (nnz > 0 ? (uint32_t)ue_len(nnz - 1) + s.cbits[cc][bb] : 0u);
+      // bits = 1 (coded flag) + [nnz > 0] (ue(nnz - 1) + 128 nnz - 2 sum clz)
+      const uint32_t v = s.cbits[cc][bb];
+      const uint32_t nnz = v >> 17, sum = v & 0x1ffffu;
+      const uint32_t bits =
+          1u + (nnz > 0 ? 63u - 2u * (uint32_t)clz32(nnz) + 128u * nnz - 2u * sum : 0u);
       job.cbits[((size_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb] = bits;
       s.cbits[cc][bb] = bits;  // per-block total, summed below by thread 0
     }
@@ -506,7 +638,6 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
   TileCoord tc;
   if (!locate<N>(jr, tc)) return;
   const FrameJob& job = *tc.job;
-  const uint32_t* __restrict__ inv = jr.coef + coef_offset(N) + (N / 2) * N;
   const int t = threadIdx.x;
   const int c = t >> 6;
   const int rem = t & 63;
@@ -519,71 +650,47 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
   const int x0 = bx * N;
   const int y = tc.by * N + r;
 
-  {
-    constexpr int CH = (N * N) / 8;
-    for (int e = t; e < 3 * NBW * CH; e += blockDim.x) {
-      const int cb = e / CH, q = e - cb * CH;
-      const int cc = cb / NBW, bb = cb - cc * NBW;
-      if (tc.bx0 + bb >= tc.Wb) continue;
-      const int16_t* src =
-          job.lev + (((size_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb) * (N * N);
-      ((uint4*)s.L[cc][bb])[q] = ((const uint4*)src)[q];
-    }
-  }
   uint32_t pp[N / 2];
   if (vb) {
+    // column k = r of the block: its N levels are contiguous
+    const int k = r;
+    const int16_t* src = job.lev + (((size_t)c * tc.Hb + tc.by) * tc.Wb + bx) * (N * N) + k * N;
+    uint32_t lp[N / 2];
+    load_row_packed<N>((const uint16_t*)src, lp);
     int dx = 0, dy = 0;
     if (!job.intra) {
       const int8_t* mv = job.mv + ((size_t)tc.by * tc.Wb + bx) * 2;
       dx = mv[0];
       dy = mv[1];
     }
-    pred_row<N>(job, c, y, x0, dx, dy, pp);
-  }
-  __syncthreads();
-  if (vb) {
-    const int k = r;
+    pred_row<N>(job, c, r, y, x0, dx, dy, pp);
     const int qP = job.qp + 6 * (B - 8);
     const Dequant dqp = dequant_params(qP, B + L2N - 5);
-    uint32_t dpair[N / 2];
+    int lv[N];
 #pragma unroll
     for (int m = 0; m < N / 2; m++) {
-      const int d0 = dequant(s.L[c][b][(2 * m) * N + k], dqp);
-      const int d1 = dequant(s.L[c][b][(2 * m + 1) * N + k], dqp);
-      dpair[m] = ((uint32_t)d0 & 0xffffu) | ((uint32_t)d1 << 16);
+      lv[2 * m] = (int)(int16_t)(lp[m] & 0xffffu);
+      lv[2 * m + 1] = (int)(int16_t)(lp[m] >> 16);
     }
-    inverse_column<N>(inv, dpair, s.E[c][b], k);
+    uint32_t dq[N / 2];
+    dequant_pairs<N>(lv, dqp, dq);
+    inverse_column<N>(dq, s.E[c][b], inv_slot<N>(k));
   }
   __syncthreads();
   if (vb) {
     uint32_t rp[N / 2];
-    inverse_row<N>(inv, s.E[c][b][r], pp, B, rp);
+    inverse_row<N>(s.E[c][b][r], pp, B, rp);
     store_row_packed<N>(job.rec + c * plane + (size_t)y * job.Wp + x0, rp);
   }
 }
 
-const uint32_t* coef_tables() {
-  static const uint32_t* ptr = nullptr;
-  if (!ptr) {
-    void* p = nullptr;
-    if (hipGetSymbolAddress(&p, HIP_SYMBOL(kCoef)) == hipSuccess) ptr = (const uint32_t*)p;
-  }
-  return ptr;
-}
-
 template <int N>
-hipError_t launch_encode_t(const LaunchDesc& r, hipStream_t s) {
-  LaunchDesc d = r;
-  d.coef = coef_tables();
-  if (!d.coef) return hipErrorInvalidSymbol;
+hipError_t launch_encode_t(const LaunchDesc& d, hipStream_t s) {
   encode_kernel<N><<<d.tiles, 192, 0, s>>>(d);
   return hipGetLastError();
 }
 template <int N>
-hipError_t launch_decode_t(const LaunchDesc& r, hipStream_t s) {
-  LaunchDesc d = r;
-  d.coef = coef_tables();
-  if (!d.coef) return hipErrorInvalidSymbol;
+hipError_t launch_decode_t(const LaunchDesc& d, hipStream_t s) {
   decode_kernel<N><<<d.tiles, 192, 0, s>>>(d);
   return hipGetLastError();
 }

@@ -23,7 +23,7 @@ struct FrameJob {
   const uint16_t* cur;         // [3][Hp][Wp] converted frame (encode)
   const uint16_t* ref;         // [3][Hp][Wp] reconstruction of frame t-1 (P)
   uint16_t* rec;               // [3][Hp][Wp] reconstruction of this frame
-  int16_t* lev;                // [3][Hb][Wb][N*N]
+  int16_t* lev;                // [3][Hb][Wb][N][N], column-major in a block
   int8_t* mv;                  // [Hb][Wb][2]
   uint32_t* cbits;             // [3][Hb][Wb]
   uint32_t* mbits;             // [Hb][Wb]
@@ -48,7 +48,6 @@ struct Seg {
 struct LaunchDesc {
   int32_t nseg;
   int32_t tiles;
-  const uint32_t* coef;  // transform coefficient-pair tables (transform kernels)
   Seg seg[kMaxSeg];
 };
 

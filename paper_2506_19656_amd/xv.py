@@ -244,7 +244,9 @@ class Encoded:
 
         out["frames"] = view(v.frames, (G, T, 3, Hp, Wp), "<i2")
         out["recon"] = view(v.recon, (G, T, 3, Hp, Wp), "<i2")
-        out["levels"] = view(v.levels, (G, T, 3, Hb, Wb, N, N), "<i2")
+        # stored column-major inside a block ([k][l]); presented as [l][k]
+        lev = view(v.levels, (G, T, 3, Hb, Wb, N, N), "<i2")
+        out["levels"] = None if lev is None else lev.transpose(-1, -2)
         out["mvs"] = view(v.mvs, (G, T, Hb, Wb, 2), "|i1")
         out["coef_bits"] = view(v.coef_bits, (G, T, 3, Hb, Wb), "<i4")
         out["mv_bits"] = view(v.mv_bits, (G, T, Hb, Wb), "<i4")
