@@ -83,7 +83,8 @@ typedef struct {
   void* data;
   int32_t dtype; /* XV_U16 or XV_F32 */
   int32_t reserved;
-  int64_t T, H, W, bands; /* each >= 1; bands <= XV_MAX_BANDS */
+  int64_t T, H, W, bands; /* each >= 1; bands <= XV_MAX_BANDS; H, W <= 65536,
+                             T*H*W < 2^32 and (H+31)*(W+31) < 2^31 / 6 */
 } xv_cube;
 
 /* Coding parameters of one encode. */

@@ -53,6 +53,7 @@ __device__ inline XV_INLINE void unroll(F&& f) {
 
 // Packed 16-bit pairs (lo = element 2j, hi = element 2j + 1).
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 __device__ inline s16x2 as_v(uint32_t x) { return __builtin_bit_cast(s16x2, x); }
 __device__ inline uint32_t as_u(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
@@ -76,8 +77,6 @@ constexpr uint32_t kPair = cpair(dct_coef(n, k0, m0), dct_coef(n, k1, m1));
 __device__ inline int dot2(uint32_t c, uint32_t x, int acc) {
   return __builtin_amdgcn_sdot2(as_v(c), as_v(x), acc, false);
 }
-
-__device__ inline int clz32(uint32_t v) { return __clz((int)v); }
 
 template <int N>
 struct Tile {
@@ -214,17 +213,15 @@ __device__ inline void fwd_full(const uint32_t* tp, int (&out)[N], int rnd) {
 //                      column's levels ([k][l])
 //   E  [3][NBW][N][P]  inverse column-stage output, row y, entries in
 //                      inverse order
-//   scan [N*N]         scan position -> offset (k * P + l) of the level in a
-//                      block's TD tile
 //   sums               per-workgroup squared error per channel, bits
 template <int N>
 struct alignas(16) LdsEnc {
   int16_t TD[3][Tile<N>::NBW][N][Tile<N>::P];
   int16_t E[3][Tile<N>::NBW][N][Tile<N>::P];
-  uint16_t scan[N * N];
   unsigned long long sse[3];
   uint32_t cbits[3][Tile<N>::NBW];
   uint32_t mvbits;
+  uint32_t cbsum;
 };
 
 template <int N>
@@ -234,17 +231,26 @@ struct alignas(16) LdsDec {
 
 // Up-right diagonal scan of an N x N block (ITU-T H.265 6.5.3): anti-
 // diagonals d = x + y in order, each from its bottom-left end upwards.  The
-// table maps scan position to the level's offset in the transposed tile.
+// table maps scan position to the byte offset 2 (x * P + y) of the level in
+// the transposed LDS tile.
 template <int N>
-__device__ inline void build_scan(uint16_t* scan) {
-  for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
-    const int y = i / N, x = i - (i / N) * N;
+struct alignas(16) ScanTab {
+  uint32_t v[N * N];
+};
+template <int N>
+constexpr ScanTab<N> make_scan_tab() {
+  ScanTab<N> t{};
+  for (int i = 0; i < N * N; i++) {
+    const int y = i / N, x = i % N;
     const int d = x + y;
     const int before = d < N ? d * (d + 1) / 2 : N * N - (2 * N - 1 - d) * (2 * N - d) / 2;
     const int first_x = d < N ? 0 : d - N + 1;
-    scan[before + x - first_x] = (uint16_t)(x * Tile<N>::P + y);
+    t.v[before + x - first_x] = (uint32_t)(2 * (x * Tile<N>::P + y));
   }
+  return t;
 }
+template <int N>
+constexpr ScanTab<N> kScanTab = make_scan_tab<N>();
 
 struct TileCoord {
   const FrameJob* job;
@@ -266,33 +272,52 @@ __device__ inline bool locate(const LaunchDesc& jd, TileCoord& tc) {
   return true;
 }
 
-// Packed u16 row (N samples) from global memory.
+// Global memory through address space 1 at a 32-bit byte offset from a base
+// pointer (global loads and stores with a scalar base; a padded frame stays
+// below 2^31 bytes, which the host checks).
+#define XV_G __attribute__((address_space(1)))
+template <class T>
+__device__ inline T gld(const void* base, uint32_t off) {
+  return *(const XV_G T*)((const XV_G char*)base + off);
+}
+template <class T>
+__device__ inline void gst(void* base, uint32_t off, T v) {
+  *(XV_G T*)((XV_G char*)base + off) = v;
+}
+
+// N packed u16 (or i16) samples at base + off (16-byte aligned for N >= 8).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 template <int N>
-__device__ inline void load_row_packed(const uint16_t* p, uint32_t (&v)[N / 2]) {
+__device__ inline void load_row_packed(const void* base, uint32_t off, uint32_t (&v)[N / 2]) {
   if constexpr (N >= 8) {
 #pragma unroll
     for (int q = 0; q < N / 8; q++) {
-      const uint4 w = ((const uint4*)p)[q];
+      const u32x4 w = gld<u32x4>(base, off + 16 * q);
       v[4 * q + 0] = w.x;
       v[4 * q + 1] = w.y;
       v[4 * q + 2] = w.z;
       v[4 * q + 3] = w.w;
     }
   } else {
-    const uint2 w = *(const uint2*)p;
+    const u32x2 w = gld<u32x2>(base, off);
     v[0] = w.x;
     v[1] = w.y;
   }
 }
 
 template <int N>
-__device__ inline void store_row_packed(uint16_t* p, const uint32_t (&v)[N / 2]) {
+__device__ inline void store_row_packed(void* base, uint32_t off, const uint32_t (&v)[N / 2]) {
   if constexpr (N >= 8) {
 #pragma unroll
-    for (int q = 0; q < N / 8; q++)
-      ((uint4*)p)[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    for (int q = 0; q < N / 8; q++) {
+      const u32x4 w = {v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+      gst<u32x4>(base, off + 16 * q, w);
+    }
   } else {
-    *(uint2*)p = make_uint2(v[0], v[1]);
+    const u32x2 w = {v[0], v[1]};
+    gst<u32x2>(base, off, w);
   }
 }
 
@@ -310,20 +335,27 @@ __device__ inline void pred_row(const FrameJob& job, int c, int r, int y, int x0
 #pragma unroll
     for (int j = 0; j < N / 2; j++) pp[j] = h | (h << 16);
   } else {
-    const int yb = y - r;
-    const int ry = min(max(yb + dy, 0), job.Hp - N) + r;
+    const int ry = min(max(y - r + dy, 0), job.Hp - N) + r;
     const int rx = min(max(x0 + dx, 0), job.Wp - N);
-    const uint32_t* r32 = (const uint32_t*)(job.ref + (size_t)c * job.Hp * job.Wp +
-                                            (size_t)ry * job.Wp + (rx & ~1));
+    const uint32_t off = 2u * ((uint32_t)(c * job.Hp + ry) * (uint32_t)job.Wp + (uint32_t)(rx & ~1));
+    // one row pointer with constant offsets, so that the loads merge
+    const XV_G uint32_t* rw = (const XV_G uint32_t*)((const XV_G char*)job.ref + off);
     uint32_t w[N / 2 + 1];
 #pragma unroll
-    for (int j = 0; j < N / 2; j++) w[j] = r32[j];
+    for (int j = 0; j < N / 2; j++) w[j] = rw[j];
     const int odd = rx & 1;
-    w[N / 2] = odd ? r32[N / 2] : 0u;
+    w[N / 2] = odd ? rw[N / 2] : 0u;
     const uint32_t sh = (uint32_t)odd << 4;
 #pragma unroll
     for (int j = 0; j < N / 2; j++) pp[j] = __builtin_amdgcn_alignbit(w[j + 1], w[j], sh);
   }
+}
+
+// The block's vector (dx, dy), two int8 at byte offset off of mv.
+__device__ inline void load_mv(const int8_t* mv, uint32_t off, int& dx, int& dy) {
+  const uint32_t v = gld<uint16_t>(mv, off);
+  dx = (int)(int8_t)(v & 0xffu);
+  dy = (int)(int8_t)(v >> 8);
 }
 
 // Dequantisation d = clip16((level * IQ[qP%6] * 16 * 2^(qP/6) + 2^(bd-1)) >> bd),
@@ -371,7 +403,7 @@ __device__ inline void inverse_column(const uint32_t (&dq)[N / 2], int16_t (*E)[
 // Inverse row stage and reconstruction of block row r into packed pairs:
 // rec = clip(pred + ((sum_k M[k][x] E[k] + 2^(19-B)) >> (20-B)), 0, 2^B-1).
 // The residual is saturated to 16 bits and added with 16-bit saturation; as
-// |pred| < 2^12, neither saturation can change the clipped result.
+// 0 <= pred < 2^12, neither saturation can change the clipped result.
 template <int N>
 __device__ inline void inverse_row(const int16_t* Erow, const uint32_t (&pp)[N / 2], int B,
                                    uint32_t (&rp)[N / 2]) {
@@ -393,30 +425,41 @@ __device__ inline void inverse_row(const int16_t* Erow, const uint32_t (&pp)[N /
 }
 
 // Rate proxy of every block of channel c in the tile (one wave per channel).
-// Lane (b, j) takes scan positions jN .. jN+N-1 of block b.  Each nonzero
-// level at position p with previous nonzero q (-1 if none) costs ue(p-q-1) +
-// se(level) = 128 - 2 (clz(p - q) + clz(|level|)) bits; a lane adds up count
-// and clz terms with its own segment start as q of its first nonzero, then
+// The tile holds w = 2|level| + 1.  Lane (b, j) takes scan positions jN ..
+// jN+N-1 of block b.  Each nonzero level at position p with previous nonzero
+// q (-1 if none) costs ue(p-q-1) + se(level) = 128 - 2 (clz(p - q) +
+// clz(|level|)) bits, and clz(|level|) = clz(w) + 1.  A lane adds up count and
+// clz terms with its own segment start as q of its first nonzero, then
 // replaces that term once the last nonzero of the earlier segments is known.
-// Returns nothing; adds 2^17 * count + sum of clz terms to s.cbits[c][b].
+// Adds 2^17 * count + sum of clz terms to s.cbits[c][b].
 template <int N>
 __device__ inline void block_bits(LdsEnc<N>& s, const TileCoord& tc, int c) {
   const int lane = threadIdx.x & 63;
   const int b = lane / N, j = lane - b * N;
   const bool vb = (tc.bx0 + b) < tc.Wb;
-  const int16_t* tile = &s.TD[c][b][0][0];
-  const uint16_t* sc = s.scan + j * N;
+  const char* tile = (const char*)&s.TD[c][b][0][0];
   uint32_t acc = 0;
   int prev = -1, first = N;
   if (vb) {
+    uint32_t sc[N];
+    const uint32_t* tab = kScanTab<N>.v + j * N;
+#pragma unroll
+    for (int q = 0; q < N / 4; q++) {
+      const u32x4 w = gld<u32x4>(tab, 16 * q);
+      sc[4 * q] = w.x;
+      sc[4 * q + 1] = w.y;
+      sc[4 * q + 2] = w.z;
+      sc[4 * q + 3] = w.w;
+    }
 #pragma unroll
     for (int i = 0; i < N; i++) {
-      const int lv = tile[sc[i]];
-      const uint32_t a = (uint32_t)(lv < 0 ? -lv : lv);
-      const uint32_t t = (uint32_t)(clz32((uint32_t)(i - prev)) + clz32(a)) + (1u << 17);
-      const bool nz = lv != 0;
+      const uint32_t w = *(const uint16_t*)(tile + sc[i]);
+      const bool nz = w != 1u;
+      // i - prev >= 1 and w >= 1: both counts are defined
+      const uint32_t t = (uint32_t)__builtin_clz((uint32_t)(i - prev)) + (uint32_t)__builtin_clz(w) +
+                         ((1u << 17) + 1u);
       acc += nz ? t : 0u;
-      first = (nz && first == N) ? i : first;
+      first = min(first, nz ? i : N);
       prev = nz ? i : prev;
     }
   }
@@ -425,18 +468,20 @@ __device__ inline void block_bits(LdsEnc<N>& s, const TileCoord& tc, int c) {
   const unsigned long long m = __ballot(has);
   const unsigned long long below = m & ((1ull << lane) - 1) & ~((1ull << (b * N)) - 1);
   const int src = below ? 63 - __clzll((long long)below) : lane;
-  const int src_last = __shfl(prev + (lane - b * N) * N, src);  // block-relative position
+  const int src_last = __shfl(prev + j * N, src);  // block-relative position
   if (has) {
     const int pf = j * N + first;
     const int q = below ? src_last : -1;
-    acc += (uint32_t)clz32((uint32_t)(pf - q)) - (uint32_t)clz32((uint32_t)(first + 1));
+    acc += (uint32_t)__builtin_clz((uint32_t)(pf - q)) - (uint32_t)__builtin_clz((uint32_t)(first + 1));
   }
   if (vb && acc) atomicAdd(&s.cbits[c][b], acc);
 }
 
+// Squared error of one reconstructed row against the current row over the
+// valid samples: x < W and, with kMask, a nonzero validity byte.
 template <int N, bool kMask>
 __device__ inline uint32_t row_sse(const uint32_t (&cp)[N / 2], const uint32_t (&rp)[N / 2],
-                                   const uint8_t* vm, int x0, int W) {
+                                   const uint8_t* vmask, uint32_t voff, int x0, int W) {
   uint32_t pm[N / 2];
 #pragma unroll
   for (int j = 0; j < N / 2; j++) pm[j] = 0xffffffffu;
@@ -445,18 +490,18 @@ __device__ inline uint32_t row_sse(const uint32_t (&cp)[N / 2], const uint32_t (
     if constexpr (N >= 16) {
 #pragma unroll
       for (int q = 0; q < N / 16; q++) {
-        const uint4 v = ((const uint4*)vm)[q];
+        const u32x4 v = gld<u32x4>(vmask, voff + 16 * q);
         w[4 * q] = v.x;
         w[4 * q + 1] = v.y;
         w[4 * q + 2] = v.z;
         w[4 * q + 3] = v.w;
       }
     } else if constexpr (N == 8) {
-      const uint2 v = *(const uint2*)vm;
+      const u32x2 v = gld<u32x2>(vmask, voff);
       w[0] = v.x;
       w[1] = v.y;
     } else {
-      w[0] = *(const uint32_t*)vm;
+      w[0] = gld<uint32_t>(vmask, voff);
     }
 #pragma unroll
     for (int j = 0; j < N / 2; j++) {
@@ -487,8 +532,9 @@ encode_kernel(const LaunchDesc jr) {
   __shared__ LdsEnc<N> s;
   TileCoord tc;
   if (!locate<N>(jr, tc)) return;
-  const FrameJob& job = *tc.job;
-  build_scan<N>(s.scan);
+  const FrameJob job = *tc.job;
+  // read before any store of the kernel, so that it stays a scalar load
+  const bool usemask = job.vmask != nullptr && gld<uint32_t>(job.nan_total, 0) != 0u;
 
   const int t = threadIdx.x;
   const int c = t >> 6;
@@ -498,25 +544,25 @@ encode_kernel(const LaunchDesc jr) {
   const int bx = tc.bx0 + b;
   const bool vb = bx < tc.Wb;
   const int B = job.bit_depth;
-  const size_t plane = (size_t)job.Hp * job.Wp;
   const int x0 = bx * N;
   const int y = tc.by * N + r;
+  const uint32_t blk = (uint32_t)(tc.by * tc.Wb + bx);                  // block index in a plane
+  const uint32_t row_off = ((uint32_t)(c * job.Hp + y) * (uint32_t)job.Wp + (uint32_t)x0);  // samples
   if (t < 3) s.sse[t] = 0ull;
   if (t < 3 * NBW) s.cbits[t / NBW][t % NBW] = 0u;
-  if (t == 0) s.mvbits = 0u;
+  if (t == 0) {
+    s.mvbits = 0u;
+    s.cbsum = 0u;
+  }
 
   int dx = 0, dy = 0;
-  if (vb && !job.intra) {
-    const int8_t* mv = job.mv + ((size_t)tc.by * tc.Wb + bx) * 2;
-    dx = mv[0];
-    dy = mv[1];
-  }
+  if (vb && !job.intra) load_mv(job.mv, 2u * blk, dx, dy);
 
   // Forward row stage of row r: T[y][k] = (sum_x M[k][x] res[x] + 2^(s1-1)) >> s1,
   // stored transposed.
   uint32_t cp[N / 2], pp[N / 2];
   if (vb) {
-    load_row_packed<N>(job.cur + c * plane + (size_t)y * job.Wp + x0, cp);
+    load_row_packed<N>(job.cur, 2u * row_off, cp);
     pred_row<N>(job, c, r, y, x0, dx, dy, pp);
     uint32_t er[N / 2];
 #pragma unroll
@@ -553,14 +599,16 @@ encode_kernel(const LaunchDesc jr) {
       const int v = (__mul24(C, qf) + (C >= 0 ? off : offn)) >> qbits;
       lv[l] = min(max(v, -32767), 32767);
     }
+    // levels out; the tile row gets 2|level| + 1 (never zero) for the rate proxy
     uint32_t lpair[N / 2];
 #pragma unroll
     for (int m = 0; m < N / 2; m++) {
       lpair[m] = pack_sat(lv[2 * m], lv[2 * m + 1]);
-      row[m] = lpair[m];
+      const s16x2 v = as_v(lpair[m]);
+      const u16x2 a = __builtin_bit_cast(u16x2, __builtin_elementwise_max(v, -v));
+      row[m] = __builtin_bit_cast(uint32_t, (u16x2)(a + a + (u16x2){1, 1}));
     }
-    int16_t* dst = job.lev + (((size_t)c * tc.Hb + tc.by) * tc.Wb + bx) * (N * N) + k * N;
-    store_row_packed<N>((uint16_t*)dst, lpair);
+    store_row_packed<N>(job.lev, 2u * (((uint32_t)c * tc.Hb * tc.Wb + blk) * (N * N) + k * N), lpair);
     uint32_t dq[N / 2];
     dequant_pairs<N>(lv, dqp, dq);
     inverse_column<N>(dq, s.E[c][b], inv_slot<N>(k));
@@ -574,34 +622,27 @@ encode_kernel(const LaunchDesc jr) {
   if (vb) {
     uint32_t rp[N / 2];
     inverse_row<N>(s.E[c][b][r], pp, B, rp);
-    store_row_packed<N>(job.rec + c * plane + (size_t)y * job.Wp + x0, rp);
+    store_row_packed<N>(job.rec, 2u * row_off, rp);
     if (c < job.nch && y < job.H) {
-      const bool usemask = job.vmask != nullptr && *job.nan_total != 0u;
-      const uint32_t sse =
-          usemask ? row_sse<N, true>(cp, rp, job.vmask + c * plane + (size_t)y * job.Wp + x0, x0, job.W)
-                  : row_sse<N, false>(cp, rp, nullptr, x0, job.W);
+      const uint32_t sse = usemask ? row_sse<N, true>(cp, rp, job.vmask, row_off, x0, job.W)
+                                   : row_sse<N, false>(cp, rp, nullptr, 0, x0, job.W);
       if (sse) atomicAdd(&s.sse[c], (unsigned long long)sse);
     }
   }
 
   if (c == 0 && r == 0 && vb) {
-    int8_t* mv = job.mv + ((size_t)tc.by * tc.Wb + bx) * 2;
     uint32_t bits = 0;
     if (job.intra) {
-      mv[0] = 0;
-      mv[1] = 0;
+      gst<uint16_t>(job.mv, 2u * blk, (uint16_t)0);
     } else {
       int pmx = 0, pmy = 0;
-      if (bx > 0) {
-        pmx = mv[-2];
-        pmy = mv[-1];
-      }
+      if (bx > 0) load_mv(job.mv, 2u * (blk - 1), pmx, pmy);
       // se(v) costs 2 floor(log2 |v|) + 3 bits, 1 for v = 0
       const int ex = dx - pmx, ey = dy - pmy;
-      bits = (ex ? 65u - 2u * (uint32_t)clz32((uint32_t)abs(ex)) : 1u) +
-             (ey ? 65u - 2u * (uint32_t)clz32((uint32_t)abs(ey)) : 1u);
+      bits = (ex ? 65u - 2u * (uint32_t)__builtin_clz((uint32_t)abs(ex)) : 1u) +
+             (ey ? 65u - 2u * (uint32_t)__builtin_clz((uint32_t)abs(ey)) : 1u);
     }
-    job.mbits[(size_t)tc.by * tc.Wb + bx] = bits;
+    gst<uint32_t>(job.mbits, 4u * blk, bits);
     if (bits) atomicAdd(&s.mvbits, bits);
   }
   __syncthreads();
@@ -612,22 +653,19 @@ encode_kernel(const LaunchDesc jr) {
       const uint32_t v = s.cbits[cc][bb];
       const uint32_t nnz = v >> 17, sum = v & 0x1ffffu;
       const uint32_t bits =
-          1u + (nnz > 0 ? 63u - 2u * (uint32_t)clz32(nnz) + 128u * nnz - 2u * sum : 0u);
-      job.cbits[((size_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb] = bits;
-      s.cbits[cc][bb] = bits;  // per-block total, summed below by thread 0
+          1u + (nnz > 0 ? 63u - 2u * (uint32_t)__builtin_clz(nnz) + 128u * nnz - 2u * sum : 0u);
+      gst<uint32_t>(job.cbits, 4u * (((uint32_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb), bits);
+      atomicAdd(&s.cbsum, bits);  // 3 * 64 * N coefficients of < 64 bits: no overflow
     }
   }
   __syncthreads();
   // this tile's sums; the per-group totals are formed after the last step
-  unsigned long long* part = job.part + (size_t)tc.tl * 5;
+  const uint32_t part = 40u * (uint32_t)tc.tl;
   if (t == 0) {
-    unsigned long long cb = 0;
-    for (int i = 0; i < 3 * NBW; i++)
-      if (tc.bx0 + (i % NBW) < tc.Wb) cb += s.cbits[i / NBW][i % NBW];
-    part[3] = cb;
-    part[4] = s.mvbits;
+    gst<unsigned long long>(job.part, part + 24, (unsigned long long)s.cbsum);
+    gst<unsigned long long>(job.part, part + 32, (unsigned long long)s.mvbits);
   }
-  if (t < 3) part[t] = s.sse[t];
+  if (t < 3) gst<unsigned long long>(job.part, part + 8 * t, s.sse[t]);
 }
 
 template <int N>
@@ -637,7 +675,7 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
   __shared__ LdsDec<N> s;
   TileCoord tc;
   if (!locate<N>(jr, tc)) return;
-  const FrameJob& job = *tc.job;
+  const FrameJob job = *tc.job;
   const int t = threadIdx.x;
   const int c = t >> 6;
   const int rem = t & 63;
@@ -646,23 +684,19 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
   const int bx = tc.bx0 + b;
   const bool vb = bx < tc.Wb;
   const int B = job.bit_depth;
-  const size_t plane = (size_t)job.Hp * job.Wp;
   const int x0 = bx * N;
   const int y = tc.by * N + r;
+  const uint32_t blk = (uint32_t)(tc.by * tc.Wb + bx);
+  const uint32_t row_off = ((uint32_t)(c * job.Hp + y) * (uint32_t)job.Wp + (uint32_t)x0);
 
   uint32_t pp[N / 2];
   if (vb) {
     // column k = r of the block: its N levels are contiguous
     const int k = r;
-    const int16_t* src = job.lev + (((size_t)c * tc.Hb + tc.by) * tc.Wb + bx) * (N * N) + k * N;
     uint32_t lp[N / 2];
-    load_row_packed<N>((const uint16_t*)src, lp);
+    load_row_packed<N>(job.lev, 2u * (((uint32_t)c * tc.Hb * tc.Wb + blk) * (N * N) + k * N), lp);
     int dx = 0, dy = 0;
-    if (!job.intra) {
-      const int8_t* mv = job.mv + ((size_t)tc.by * tc.Wb + bx) * 2;
-      dx = mv[0];
-      dy = mv[1];
-    }
+    if (!job.intra) load_mv(job.mv, 2u * blk, dx, dy);
     pred_row<N>(job, c, r, y, x0, dx, dy, pp);
     const int qP = job.qp + 6 * (B - 8);
     const Dequant dqp = dequant_params(qP, B + L2N - 5);
@@ -680,7 +714,7 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
   if (vb) {
     uint32_t rp[N / 2];
     inverse_row<N>(s.E[c][b][r], pp, B, rp);
-    store_row_packed<N>(job.rec + c * plane + (size_t)y * job.Wp + x0, rp);
+    store_row_packed<N>(job.rec, 2u * row_off, rp);
   }
 }
 

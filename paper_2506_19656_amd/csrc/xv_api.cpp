@@ -160,6 +160,9 @@ int check_cube(const xv_cube* c, const char* name) {
   if (c->H > 65536 || c->W > 65536 || c->T > (1 << 24) ||
       (double)c->T * (double)c->H * (double)c->W >= 4294967296.0)
     return fail(XV_EINVAL, "%s: dimension too large (T*H*W must be below 2^32)", name);
+  // a padded 3-channel u16 frame must stay addressable with 32-bit byte offsets
+  if ((double)(c->H + 31) * (double)(c->W + 31) * 6.0 >= 2147483648.0)
+    return fail(XV_EINVAL, "%s: frame too large ((H+31)*(W+31) must be below 2^31/6)", name);
   const size_t el = c->dtype == XV_U16 ? 2 : 4;
   if (((uintptr_t)c->data) % el) return fail(XV_EINVAL, "%s: misaligned data pointer", name);
   return XV_OK;
