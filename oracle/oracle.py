@@ -124,6 +124,13 @@ def lib():
                                           C.c_uint64, p]
         L.xvo_read_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, p, C.c_uint64,
                                          p, p, p]
+        L.xvo_ssim_window.argtypes = [p]
+        L.xvo_ssim_plane.argtypes = [p, p, i64, i64, i64, C.c_int]
+        L.xvo_ssim_plane.restype = C.c_double
+        L.xvo_ssim_bands.argtypes = [p, p, i64, i64, i64, i64, C.c_int, C.c_int, p]
+        L.xvo_spectral_angle.argtypes = [p, C.c_int, p, C.c_int, i64, i64, i64, i64,
+                                         C.POINTER(C.c_uint64)]
+        L.xvo_spectral_angle.restype = C.c_double
         if L.xvo_selfcheck() != 0:
             raise RuntimeError("oracle requires arithmetic right shifts")
         _lib = L
@@ -447,3 +454,39 @@ def metrics(cube: np.ndarray, enc: dict, params: CodingParams) -> dict:
         per_group.append(bpppb(bits_g, T, H, W, nb))
     return dict(psnr=psnr_i, psnr_phys=psnr_p, sse_phys=sse_p, coef_bits=coef, mv_bits=mvb,
                 bpppb=bpppb(coef + mvb, T, H, W, Bn), bpppb_group=per_group)
+
+
+def ssim_window() -> np.ndarray:
+    """xvo_ssim_window: the normalised 11-tap Gaussian (sigma 1.5)."""
+    w = np.zeros(11, np.float64)
+    lib().xvo_ssim_window(_ptr(w))
+    return w
+
+
+def ssim_plane(a: np.ndarray, b: np.ndarray, B: int) -> float:
+    """xvo_ssim_plane: mean SSIM of two u16 planes (coded domain, L = 2^B - 1)."""
+    a = np.ascontiguousarray(a, np.uint16)
+    b = np.ascontiguousarray(b, np.uint16)
+    H, W = a.shape
+    return lib().xvo_ssim_plane(_ptr(a), _ptr(b), W, H, W, B)
+
+
+def ssim_bands(frames, recon, shape, N: int, B: int) -> np.ndarray:
+    """xvo_ssim_bands: per-band mean SSIM of an encode's frames and recon."""
+    T, H, W, Bn = shape
+    out = np.zeros(Bn, np.float64)
+    lib().xvo_ssim_bands(_ptr(np.ascontiguousarray(frames)), _ptr(np.ascontiguousarray(recon)),
+                         T, H, W, Bn, N, B, _ptr(out))
+    return out
+
+
+def spectral_angle(orig: np.ndarray, dec: np.ndarray):
+    """xvo_spectral_angle: mean angle (radians) and the number of pixels used."""
+    T, H, W, Bn = orig.shape
+    assert dec.shape == orig.shape
+    n = C.c_uint64(0)
+    orig = np.ascontiguousarray(orig)
+    dec = np.ascontiguousarray(dec)
+    v = lib().xvo_spectral_angle(_ptr(orig), _dtype_code(orig), _ptr(dec), _dtype_code(dec),
+                                 T, H, W, Bn, C.byref(n))
+    return v, int(n.value)

@@ -911,3 +911,116 @@ void xvo_phys_sse(const void* data, int dtype, int64_t T, int64_t H, int64_t W,
     sse_out[b] = s + comp;
   }
 }
+
+/* ---- Quality metrics reported beside PSNR (Sec. II-C) ----------------------
+ * The paper names SSIM (Wang et al., 2004) and the spectral angle (Kruse et
+ * al., 1993) without parameters or domain; paper silent; reading:
+ *   SSIM: per coded plane (one real channel of one frame) in the coded integer
+ *   domain -- converted frame q against its reconstruction, dynamic range
+ *   L = 2^B - 1 -- with the 11 x 11 circularly symmetric Gaussian window of
+ *   standard deviation 1.5 normalised to unit sum, K1 = 0.01, K2 = 0.03, at
+ *   every window position that lies entirely inside the real H x W picture.
+ *   Local statistics are the weighted mean, the weighted variance about it
+ *   and the weighted covariance.  A plane scores the mean over its window
+ *   positions, a band the mean over its frames; NaN when no window fits.
+ *   Spectral angle: per pixel, the angle in radians between the original and
+ *   the decoded band vectors, arccos(<s, d> / (|s| |d|)) with the ratio
+ *   clamped to [-1, 1]; pixels with a NaN in either vector or a zero-norm
+ *   vector are skipped; the cube scores the mean over the remaining pixels
+ *   (NaN if none). */
+
+/* Normalised 1-D Gaussian, sigma 1.5, 11 taps; the 2-D window is the outer
+ * product of two of them, which is the normalised 2-D Gaussian. */
+void xvo_ssim_window(double w[11]) {
+  double s = 0.0;
+  for (int i = 0; i < 11; i++) {
+    double d = (double)(i - 5);
+    w[i] = exp(-(d * d) / (2.0 * 1.5 * 1.5));
+    s += w[i];
+  }
+  for (int i = 0; i < 11; i++) w[i] /= s;
+}
+
+/* Mean SSIM of one plane pair (row stride `stride` samples). */
+double xvo_ssim_plane(const uint16_t* a, const uint16_t* b, int64_t stride, int64_t H,
+                      int64_t W, int B) {
+  if (H < 11 || W < 11) return NAN;
+  double w[11];
+  xvo_ssim_window(w);
+  double L = (double)((1 << B) - 1);
+  double C1 = (0.01 * L) * (0.01 * L), C2 = (0.03 * L) * (0.03 * L);
+  double sum = 0.0;
+  int64_t n = 0;
+  for (int64_t y0 = 0; y0 + 11 <= H; y0++)
+    for (int64_t x0 = 0; x0 + 11 <= W; x0++) {
+      double ma = 0.0, mb = 0.0;
+      for (int i = 0; i < 11; i++)
+        for (int j = 0; j < 11; j++) {
+          double wt = w[i] * w[j];
+          ma += wt * a[(y0 + i) * stride + x0 + j];
+          mb += wt * b[(y0 + i) * stride + x0 + j];
+        }
+      double va = 0.0, vb = 0.0, cab = 0.0;
+      for (int i = 0; i < 11; i++)
+        for (int j = 0; j < 11; j++) {
+          double wt = w[i] * w[j];
+          double da = a[(y0 + i) * stride + x0 + j] - ma;
+          double db = b[(y0 + i) * stride + x0 + j] - mb;
+          va += wt * da * da;
+          vb += wt * db * db;
+          cab += wt * da * db;
+        }
+      sum += ((2.0 * ma * mb + C1) * (2.0 * cab + C2)) /
+             ((ma * ma + mb * mb + C1) * (va + vb + C2));
+      n++;
+    }
+  return sum / (double)n;
+}
+
+/* Per-band mean SSIM of an encode: frames and recon are [G][T][3][Hp][Wp]. */
+void xvo_ssim_bands(const uint16_t* frames, const uint16_t* recon, int64_t T, int64_t H,
+                    int64_t W, int64_t Bn, int N, int B, double* out) {
+  int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
+  for (int64_t band = 0; band < Bn; band++) {
+    int64_t g = band / 3, c = band % 3;
+    double s = 0.0;
+    for (int64_t t = 0; t < T; t++) {
+      int64_t off = ((g * T + t) * 3 + c) * Hp * Wp;
+      s += xvo_ssim_plane(frames + off, recon + off, Wp, H, W, B);
+    }
+    out[band] = s / (double)T;
+  }
+}
+
+/* Mean spectral angle (radians) between two [T][H][W][Bn] cubes. */
+double xvo_spectral_angle(const void* orig, int dtype_o, const void* dec, int dtype_d,
+                          int64_t T, int64_t H, int64_t W, int64_t Bn, uint64_t* n_out) {
+  double s = 0.0, comp = 0.0;
+  uint64_t n = 0;
+  for (int64_t p = 0; p < T * H * W; p++) {
+    double dot = 0.0, n1 = 0.0, n2 = 0.0;
+    int bad = 0;
+    for (int64_t b = 0; b < Bn; b++) {
+      double u = read_sample(orig, dtype_o, p * Bn + b);
+      double v = read_sample(dec, dtype_d, p * Bn + b);
+      if (isnan(u) || isnan(v)) bad = 1;
+      dot += u * v;
+      n1 += u * u;
+      n2 += v * v;
+    }
+    if (bad || n1 == 0.0 || n2 == 0.0) continue;
+    double r = dot / (sqrt(n1) * sqrt(n2));
+    if (r > 1.0) r = 1.0;
+    if (r < -1.0) r = -1.0;
+    double e = acos(r);
+    double tt = s + e;
+    if (fabs(s) >= fabs(e))
+      comp += (s - tt) + e;
+    else
+      comp += (e - tt) + s;
+    s = tt;
+    n++;
+  }
+  if (n_out) *n_out = n;
+  return n ? (s + comp) / (double)n : NAN;
+}

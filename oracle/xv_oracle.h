@@ -106,6 +106,14 @@ void xvo_phys_sse(const void* data, int dtype, int64_t T, int64_t H, int64_t W,
                   int64_t Bn, const uint16_t* recon, int N, int B,
                   const double* mn, const double* mx, double* sse_out);
 
+void xvo_ssim_window(double w[11]);
+double xvo_ssim_plane(const uint16_t* a, const uint16_t* b, int64_t stride, int64_t H,
+                      int64_t W, int B);
+void xvo_ssim_bands(const uint16_t* frames, const uint16_t* recon, int64_t T, int64_t H,
+                    int64_t W, int64_t Bn, int N, int B, double* out);
+double xvo_spectral_angle(const void* orig, int dtype_o, const void* dec, int dtype_d,
+                          int64_t T, int64_t H, int64_t W, int64_t Bn, uint64_t* n_out);
+
 #ifdef __cplusplus
 }
 #endif

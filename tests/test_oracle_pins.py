@@ -670,3 +670,103 @@ def test_bitstream_of_an_encoded_cube_has_the_encoders_bit_count():
     assert w["bits"] == int(enc["coef_bits"].sum()) + int(enc["mv_bits"].sum())
     r = O.read_bitstream(w["payload"], w["bits"], enc["levels"].shape, p.gop)
     assert np.array_equal(r["levels"], enc["levels"]) and np.array_equal(r["mvs"], enc["mvs"])
+
+
+# ---- SSIM and spectral angle (Sec. II-C metrics; stated readings) -----------
+
+def _ssim_reference_scipy(a, b, B):
+    """Wang et al. (2004) SSIM map from scipy's own Gaussian filter (sigma 1.5,
+    radius 5 = 11 taps), one-pass moments, cropped to the positions whose
+    window lies inside the picture; an independent route to the same number."""
+    from scipy.ndimage import gaussian_filter
+    a = a.astype(np.float64)
+    b = b.astype(np.float64)
+    f = lambda z: gaussian_filter(z, sigma=1.5, truncate=5 / 1.5, mode="constant")
+    ma, mb = f(a), f(b)
+    va = f(a * a) - ma * ma
+    vb = f(b * b) - mb * mb
+    cab = f(a * b) - ma * mb
+    L = (1 << B) - 1
+    C1, C2 = (0.01 * L) ** 2, (0.03 * L) ** 2
+    s = ((2 * ma * mb + C1) * (2 * cab + C2)) / ((ma ** 2 + mb ** 2 + C1) * (va + vb + C2))
+    return float(s[5:-5, 5:-5].mean())
+
+
+@pytest.mark.parametrize("shape,B", [((11, 11), 8), ((16, 23), 10), ((37, 29), 12)])
+def test_ssim_matches_scipy_gaussian_route(shape, B):
+    rng = np.random.default_rng(sum(shape) + B)
+    L = (1 << B) - 1
+    a = rng.integers(0, L + 1, shape).astype(np.uint16)
+    noise = rng.integers(-L // 20, L // 20 + 1, shape)
+    b = np.clip(a.astype(np.int64) + noise, 0, L).astype(np.uint16)
+    got = O.ssim_plane(a, b, B)
+    ref = _ssim_reference_scipy(a, b, B)
+    assert abs(got - ref) < 1e-12, (got, ref)
+    assert abs(O.ssim_plane(b, a, B) - got) < 1e-15  # symmetric
+
+
+def test_ssim_identity_constant_planes_and_small_pictures():
+    rng = np.random.default_rng(3)
+    a = rng.integers(0, 4096, (14, 15)).astype(np.uint16)
+    assert abs(O.ssim_plane(a, a, 12) - 1.0) < 1e-15
+    # constant planes: no variance, SSIM = (2 x y + C1) / (x^2 + y^2 + C1)
+    for x, y, B in [(100, 140, 8), (0, 1023, 10), (4000, 3900, 12)]:
+        L = (1 << B) - 1
+        C1 = (0.01 * L) ** 2
+        p = np.full((12, 13), x, np.uint16)
+        q = np.full((12, 13), y, np.uint16)
+        want = (2 * x * y + C1) / (x * x + y * y + C1)
+        assert abs(O.ssim_plane(p, q, B) - want) < 1e-14
+    assert math.isnan(O.ssim_plane(a[:10], a[:10], 12))  # no 11 x 11 window fits
+    # window: symmetric, unit sum, peak at the centre
+    w = O.ssim_window()
+    assert abs(w.sum() - 1.0) < 1e-15 and np.allclose(w, w[::-1], rtol=0, atol=0)
+    assert w.argmax() == 5
+
+
+def test_ssim_bands_is_mean_over_frames_of_real_channels():
+    rng = np.random.default_rng(5)
+    T, H, W, Bn, N, B = 3, 13, 12, 4, 8, 10
+    Hp, Wp = 16, 16
+    G = 2
+    frames = rng.integers(0, 1024, (G, T, 3, Hp, Wp)).astype(np.uint16)
+    recon = np.clip(frames.astype(np.int64) + rng.integers(-9, 10, frames.shape), 0, 1023
+                    ).astype(np.uint16)
+    got = O.ssim_bands(frames, recon, (T, H, W, Bn), N, B)
+    for band in range(Bn):
+        g, c = divmod(band, 3)
+        want = np.mean([_ssim_reference_scipy(frames[g, t, c, :H, :W], recon[g, t, c, :H, :W], B)
+                        for t in range(T)])
+        assert abs(got[band] - want) < 1e-12
+
+
+def test_spectral_angle_closed_forms():
+    # one pixel each: pi/4, acos(24/25), pi/2, and parallel vectors (zero angle)
+    cases = [([1.0, 0.0, 0.0], [1.0, 1.0, 0.0], math.pi / 4),
+             ([3.0, 4.0, 0.0], [4.0, 3.0, 0.0], math.acos(24 / 25)),
+             ([1.0, 0.0, 2.0], [0.0, 5.0, 0.0], math.pi / 2),
+             ([2.0, 7.0, 1.0], [4.0, 14.0, 2.0], 0.0)]
+    for s, d, want in cases:
+        o = np.array(s, np.float32).reshape(1, 1, 1, 3)
+        r = np.array(d, np.float32).reshape(1, 1, 1, 3)
+        v, n = O.spectral_angle(o, r)
+        assert n == 1 and abs(v - want) < 1e-7, (s, d, v, want)
+    # mean over pixels; NaN and zero-norm pixels are skipped
+    o = np.array([[1, 0, 0], [3, 4, 0], [np.nan, 1, 1], [0, 0, 0]], np.float32).reshape(1, 2, 2, 3)
+    r = np.array([[1, 1, 0], [4, 3, 0], [1, 1, 1], [1, 2, 3]], np.float32).reshape(1, 2, 2, 3)
+    v, n = O.spectral_angle(o, r)
+    assert n == 2 and abs(v - (math.pi / 4 + math.acos(24 / 25)) / 2) < 1e-12
+    # all pixels skipped -> NaN
+    v, n = O.spectral_angle(np.zeros((1, 1, 2, 3), np.uint16), np.ones((1, 1, 2, 3), np.uint16))
+    assert n == 0 and math.isnan(v)
+
+
+def test_spectral_angle_matches_numpy_bruteforce():
+    rng = np.random.default_rng(11)
+    o = rng.integers(0, 10001, (3, 5, 7, 6)).astype(np.uint16)
+    d = np.clip(o.astype(np.int64) + rng.integers(-300, 301, o.shape), 0, 65535).astype(np.uint16)
+    v, n = O.spectral_angle(o, d)
+    u = o.reshape(-1, 6).astype(np.float64)
+    w = d.reshape(-1, 6).astype(np.float64)
+    r = np.clip((u * w).sum(1) / (np.sqrt((u * u).sum(1)) * np.sqrt((w * w).sum(1))), -1, 1)
+    assert n == u.shape[0] and abs(v - float(np.arccos(r).mean())) < 1e-12
