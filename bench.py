@@ -91,6 +91,37 @@ def cpu_baseline(cube_host, wl, seconds_hint=""):
                       f"{wl.bands} cube, encode+decode+metrics, {dt:.1f} s wall"}
 
 
+def quality_bench(xv, torch, cube, params, runs, steps):
+    """SSIM of the coded planes (xv_ssim) and spectral angle of the decoded
+    cube (xv_spectral_angle) for every run of the sweep: the values, and the
+    kernel time per step of all runs from HIP events."""
+    encs = xv.encode_batch([cube] * len(params), params)
+    outs = [torch.empty_like(cube) for _ in params]
+    xv.decode_batch(encs, outs)
+    torch.cuda.synchronize()
+    vals = [(xv.ssim(e), xv.spectral_angle(cube, o)) for e, o in zip(encs, outs)]  # warm-up
+    xv.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        vals = [(xv.ssim(e), xv.spectral_angle(cube, o)) for e, o in zip(encs, outs)]
+    dt = time.perf_counter() - t0
+    prof = xv.profile_read()["quality"]
+    xv.profile_enable(False)
+    for e in encs:
+        e.free()
+    pxb = cube.numel() * len(params)
+    out = {"ssim_mean_per_run": [round(sum(s) / len(s), 6) for s, _ in vals],
+           "spectral_angle_rad_per_run": [round(a, 8) for _, (a, _) in vals],
+           "runs": [f"QP{qp}/N{N}" for qp, N in runs],
+           "ms_per_step": round(dt / steps * 1e3, 3),
+           "Mpx_band_s": round(pxb * steps / dt / 1e6, 1)}
+    if prof["launches"]:
+        ms = prof["ms"] / steps
+        out["kernel_ms_per_step"] = round(ms, 3)
+        out["kernel_input_GBs"] = round(prof["work"] / steps / (ms * 1e-3) / 1e9, 1)
+    return out
+
+
 def bits_bench(xv, torch, cube, params, pxb_step, steps):
     """Serialise the sweep's 15 encoded runs (xv_pack) and parse them back
     (xv_unpack), timed per call on the host (each call synchronises once) and
@@ -244,6 +275,8 @@ def main():
     ap.add_argument("--mode", choices=["both", "batched", "plain"], default="both")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix section")
     ap.add_argument("--no-bits", action="store_true", help="skip the bitstream section")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the SSIM / spectral-angle section")
     ap.add_argument("--counters", action="store_true",
                     help="workload for hardware-counter runs only: one 1 GiB device copy (the "
                          "calibration of FETCH_SIZE / WRITE_SIZE), then one batched sweep step "
@@ -448,6 +481,9 @@ def main():
                              "avg_launch_ms": round(avg, 4), "launches": d["launches"]}
         line["kernel_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()
                                       if v["launches"]}
+    if not args.no_quality:
+        print("[bench] quality metrics", file=sys.stderr, flush=True)
+        line["quality_metrics"] = quality_bench(xv, torch, cube, params, runs, args.steps)
     if not args.no_bits:
         print("[bench] bitstream", file=sys.stderr, flush=True)
         line["bitstream"] = bits_bench(xv, torch, cube, params, pxb_step, args.steps)

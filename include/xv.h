@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define XV_ABI_VERSION 2
+#define XV_ABI_VERSION 3
 
 /* status codes */
 #define XV_OK 0
@@ -165,6 +165,30 @@ int xv_decode_cube(const xv_encoded* e, const xv_cube* out, void* hip_stream);
  * Synchronises hip_stream.  m is caller memory.  Errors: XV_EINVAL, XV_EHIP. */
 int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m,
                   void* hip_stream);
+
+/* Structural similarity per band (Sec. II-C names SSIM, Wang et al. 2004,
+ * without parameters; this is the stated reading): in the coded domain, each
+ * real channel of each frame -- the converted frame against its
+ * reconstruction, dynamic range L = 2^B - 1 -- with an 11 x 11 Gaussian
+ * window of standard deviation 1.5 (unit sum), K1 = 0.01, K2 = 0.03, at every
+ * window position inside the real H x W picture; a plane scores the mean over
+ * its positions, a band the mean over its frames.  ssim[b] for b < bands
+ * (caller memory); NaN when H or W is below 11.  Needs the encode's converted
+ * frames and reconstruction: XV_EINVAL after XV_FLAG_DROP_WORK or for a cube
+ * read from a bitstream.  Synchronises hip_stream.  Errors: XV_EINVAL,
+ * XV_ENOMEM, XV_EHIP. */
+int xv_ssim(const xv_encoded* e, double* ssim, void* hip_stream);
+
+/* Mean spectral angle in radians between two device cubes of equal shape
+ * (Sec. II-C names it, Kruse et al. 1993): per pixel arccos(<s, d> / (|s|
+ * |d|)) over the band vectors, in binary64, the ratio clamped to [-1, 1];
+ * pixels with a NaN in either vector or a zero-norm vector are skipped.
+ * *mean_rad is NaN when every pixel is skipped; *n_pixels (may be NULL)
+ * receives the number used.  Either cube may be XV_U16 or XV_F32.
+ * Synchronises hip_stream.  Errors: XV_EINVAL (shape mismatch), XV_ENOMEM,
+ * XV_EHIP. */
+int xv_spectral_angle(const xv_cube* orig, const xv_cube* decoded, double* mean_rad,
+                      uint64_t* n_pixels, void* hip_stream);
 
 /* Fill a read-only view of the encoded cube's device buffers. */
 int xv_encoded_export(const xv_encoded* e, xv_export* v);
@@ -298,7 +322,8 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
 #define XV_K_METRICS 6
 #define XV_K_BITS_WRITE 7
 #define XV_K_BITS_PARSE 8
-#define XV_K_COUNT 9
+#define XV_K_QUALITY 9
+#define XV_K_COUNT 10
 
 typedef struct {
   double ms[XV_K_COUNT];       /* summed kernel time per kernel class     */

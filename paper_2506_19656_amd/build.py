@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libxv.so")
 
-SOURCES = ["k_prep.hip", "k_me.hip", "k_xform.hip", "k_bits.hip", "xv_alloc.cpp", "xv_api.cpp"]
+SOURCES = ["k_prep.hip", "k_me.hip", "k_xform.hip", "k_bits.hip", "k_quality.hip", "xv_alloc.cpp",
+           "xv_api.cpp"]
 
 ARCH = os.environ.get("XV_OFFLOAD_ARCH", "gfx950")
 

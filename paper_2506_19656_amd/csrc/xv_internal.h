@@ -148,6 +148,31 @@ __host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c
 constexpr int kIQ[6] = {40, 45, 51, 57, 64, 72};
 constexpr int kQf[6] = {26214, 23302, 20560, 18396, 16384, 14564};
 
+// Quality metrics beside PSNR: SSIM of the coded planes and the spectral angle.
+struct SsimArgs {
+  const uint16_t* frames;      // [G][T][3][Hp][Wp] converted frames
+  const uint16_t* recon;       // [G][T][3][Hp][Wp] reconstruction
+  double* part;                // [bands][T][tiles] per-tile SSIM sums
+  double w[11];                // normalised Gaussian taps (sigma 1.5)
+  double C1, C2;               // (0.01 L)^2, (0.03 L)^2
+  int32_t T, Hp, Wp, H, W, bands;
+  int32_t tiles_x, tiles_y;
+};
+constexpr int kSaThreads = 256;
+struct SaArgs {
+  const void* orig;            // [T][H][W][bands]
+  const void* dec;             // [T][H][W][bands]
+  int32_t dtype_orig, dtype_dec;
+  int32_t bands;
+  int64_t npix;                // T * H * W
+  double* part_sum;            // [blocks]
+  unsigned long long* part_n;  // [blocks]
+  double* out;                 // [2]: sum of angles, pixel count (u64 bits)
+};
+void ssim_tiles(int H, int W, int* tiles_x, int* tiles_y);
+hipError_t launch_ssim(const SsimArgs& a, double* out, hipStream_t s);
+hipError_t launch_spectral_angle(const SaArgs& a, int nblocks, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (each returns hipGetLastError of its launch).
 // ---------------------------------------------------------------------------

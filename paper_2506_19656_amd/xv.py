@@ -23,10 +23,10 @@ PAD_ZERO, PAD_REPEAT = 0, 1
 FILL_NEAREST, FILL_FORWARD = 0, 1
 FLAG_DROP_WORK = 1
 MAX_BANDS, MAX_GROUPS = 64, 22
-K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS, K_BITS_WRITE, K_BITS_PARSE = \
-    range(9)
+K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS, K_BITS_WRITE, K_BITS_PARSE, \
+    K_QUALITY = range(10)
 K_NAMES = ["stats", "pack", "me", "encode", "decode", "denorm", "metrics", "bits_write",
-           "bits_parse"]
+           "bits_parse", "quality"]
 
 
 class XvError(RuntimeError):
@@ -72,7 +72,7 @@ class MeGeometryC(C.Structure):
 
 
 class ProfileC(C.Structure):
-    _fields_ = [("ms", C.c_double * 9), ("launches", C.c_uint64 * 9), ("work", C.c_double * 9)]
+    _fields_ = [("ms", C.c_double * 10), ("launches", C.c_uint64 * 10), ("work", C.c_double * 10)]
 
 
 class MemoryC(C.Structure):
@@ -109,7 +109,7 @@ EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube"
             "xv_autotune_me", "xv_autotune_me_batch", "xv_profile_enable", "xv_profile_read", "xv_server_create",
             "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
             "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release", "xv_pack", "xv_packed_view",
-            "xv_packed_free", "xv_unpack"]
+            "xv_packed_free", "xv_unpack", "xv_ssim", "xv_spectral_angle"]
 
 _lib = None
 
@@ -130,6 +130,9 @@ def lib():
         L.xv_encode_cube.argtypes = [C.POINTER(Cube), C.POINTER(ParamsC), vp, C.POINTER(vp)]
         L.xv_decode_cube.argtypes = [vp, C.POINTER(Cube), vp]
         L.xv_psnr_bpppb.argtypes = [C.POINTER(Cube), vp, C.POINTER(MetricsC), vp]
+        L.xv_ssim.argtypes = [vp, C.POINTER(C.c_double), vp]
+        L.xv_spectral_angle.argtypes = [C.POINTER(Cube), C.POINTER(Cube), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_uint64), vp]
         L.xv_encoded_export.argtypes = [vp, C.POINTER(ExportC)]
         L.xv_encoded_free.argtypes = [vp]
         L.xv_encoded_free.restype = None
@@ -330,6 +333,22 @@ def psnr_bpppb(orig, enc: Encoded, stream=None) -> dict:
                 bpppb_group=list(m.bpppb_group[:G]))
 
 
+def ssim(enc: Encoded, stream=None) -> list:
+    """xv_ssim: per-band mean SSIM of the coded planes (NaN below 11 x 11)."""
+    out = (C.c_double * MAX_BANDS)()
+    _check(lib().xv_ssim(enc.handle, out, _stream_handle(stream)))
+    return list(out[:enc.shape[-1]])
+
+
+def spectral_angle(orig, decoded, stream=None):
+    """xv_spectral_angle: (mean angle in radians, pixels used)."""
+    v = C.c_double()
+    n = C.c_uint64()
+    _check(lib().xv_spectral_angle(C.byref(_cube(orig)), C.byref(_cube(decoded)), C.byref(v),
+                                   C.byref(n), _stream_handle(stream)))
+    return v.value, int(n.value)
+
+
 def set_me_geometry(block: int, search_range: int, blocks_per_wg=0, cands_per_lane=0,
                     threads=0, rows_per_lane=0):
     g = MeGeometryC(blocks_per_wg, cands_per_lane, threads, rows_per_lane)
@@ -378,7 +397,7 @@ def profile_read() -> dict:
     p = ProfileC()
     _check(lib().xv_profile_read(C.byref(p)))
     return {K_NAMES[i]: dict(ms=p.ms[i], launches=p.launches[i], work=p.work[i])
-            for i in range(9)}
+            for i in range(len(K_NAMES))}
 
 
 class Packed:

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(xvmod):
 
 def test_abi_version_and_status_strings(xvmod):
     L = xvmod.lib()
-    assert L.xv_abi_version() == 2
+    assert L.xv_abi_version() == 3
     assert L.xv_status_str(0) == b"ok"
     assert L.xv_status_str(-1) == b"invalid argument"
 
@@ -112,3 +112,13 @@ def test_bitstream_entry_points_reject_bad_arguments(xvmod):
     assert L.xv_unpack(C.c_void_p(16), 100, None, C.byref(h)) == xvmod.EINVAL  # < header
     assert L.xv_packed_view(None, None, None, None) == xvmod.EINVAL
     L.xv_packed_free(None)  # no-op
+
+
+def test_profile_classes_match_the_header():
+    import re
+    from paper_2506_19656_amd import xv
+    hdr = open(os.path.join(ROOT, "include", "xv.h")).read()
+    n = int(re.search(r"#define XV_K_COUNT (\d+)", hdr).group(1))
+    assert len(xv.K_NAMES) == n
+    p = xv.ProfileC()
+    assert len(p.ms) == n and len(p.launches) == n and len(p.work) == n
