@@ -187,14 +187,34 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
 
   constexpr int ND = (KX + N) / 2;  // reference dwords per row and item
   constexpr int NC = N / 2;         // current dwords per row
-  const int items = nbv * s.ipb;
+  // Only items holding a candidate that keeps the displaced block inside the
+  // padded picture are evaluated: candidate rows dy + R in [rlo, rhi] (the
+  // same for every block of the run) and, per block, candidate columns
+  // dx + R in [max(0, R - x0), min(2R, Wp - N - x0 + R)].  Consecutive items
+  // of a block differ in their row group, so neighbouring lanes read window
+  // rows a pitch apart.
+  const int y0b = by * N;
+  const int glo_r = max(0, R - y0b) / ROWS;
+  const int ndy = min(s.span - 1, Hp - N - y0b + R) / ROWS - glo_r + 1;
+  int items = 0;
+  for (int b = 0; b < nbv; b++) {
+    const int x0 = (bx0 + b) * N;
+    items += ndy * (min(s.span - 1, Wp - N - x0 + R) / KX - max(0, R - x0) / KX + 1);
+  }
   const int keyshift_sad = R <= 32 ? 21 : 23;
   const int keyshift_l1 = R <= 32 ? 13 : 15;
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int b = it / s.ipb;
-    const int rem = it - b * s.ipb;
-    const int gxi = rem / s.dyp;
-    const int dy0 = ROWS * (rem - gxi * s.dyp);
+    int b = 0, rem = it, glo_c = 0;
+    for (;; b++) {
+      const int x0 = (bx0 + b) * N;
+      glo_c = max(0, R - x0) / KX;
+      const int n = ndy * (min(s.span - 1, Wp - N - x0 + R) / KX - glo_c + 1);
+      if (rem < n || b + 1 >= nbv) break;
+      rem -= n;
+    }
+    const int gq = rem / ndy;
+    const int gxi = glo_c + gq;
+    const int dy0 = ROWS * (glo_r + rem - gq * ndy);
     uint32_t acc[ROWS][KX];
 #pragma unroll
     for (int h = 0; h < ROWS; h++)

@@ -22,16 +22,16 @@ namespace xv {
 
 namespace {
 
-constexpr int kTileX = 64;               // window positions per tile along x
-constexpr int kTileY = 8;                // and along y
+constexpr int kTileX = 32;               // window positions per tile along x
+constexpr int kTileY = 16;               // and along y
 constexpr int kInX = kTileX + 10;        // input columns of a tile
 constexpr int kInY = kTileY + 10;        // input rows of a tile
 constexpr int kSsimThreads = 256;
 
 struct alignas(16) SsimLds {
   double h[5][kInY][kTileX];             // row-filtered a, b, aa, bb, ab
-  uint16_t a[kInY][kInX + 2];
-  uint16_t b[kInY][kInX + 2];
+  double a[kInY][kInX];                  // the tile's samples, converted once
+  double b[kInY][kInX];
   double red[kSsimThreads / 64];
 };
 
@@ -65,8 +65,8 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_kernel(const SsimArgs a) {
     const int r = i / kInX, q = i - r * kInX;
     const int y = y0 + r, x = x0 + q;
     const bool in = y < a.H && x < a.W;  // outside samples only feed skipped positions
-    s.a[r][q] = in ? pa[(size_t)y * a.Wp + x] : (uint16_t)0;
-    s.b[r][q] = in ? pb[(size_t)y * a.Wp + x] : (uint16_t)0;
+    s.a[r][q] = in ? (double)pa[(size_t)y * a.Wp + x] : 0.0;
+    s.b[r][q] = in ? (double)pb[(size_t)y * a.Wp + x] : 0.0;
   }
   __syncthreads();
 
@@ -76,12 +76,12 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_kernel(const SsimArgs a) {
 #pragma unroll
     for (int k = 0; k < 11; k++) {
       const double u = s.a[r][j + k], v = s.b[r][j + k];
-      const double w = a.w[k];
-      sa += w * u;
-      sb += w * v;
-      saa += w * (u * u);
-      sbb += w * (v * v);
-      sab += w * (u * v);
+      const double wu = a.w[k] * u, wv = a.w[k] * v;
+      sa += wu;
+      sb += wv;
+      saa = fma(wu, u, saa);
+      sbb = fma(wv, v, sbb);
+      sab = fma(wu, v, sab);
     }
     s.h[0][r][j] = sa;
     s.h[1][r][j] = sb;
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_kernel(const SsimArgs a) {
     for (int k = 0; k < 11; k++) {
       const double w = a.w[k];
 #pragma unroll
-      for (int q = 0; q < 5; q++) m[q] += w * s.h[q][r + k][j];
+      for (int q = 0; q < 5; q++) m[q] = fma(w, s.h[q][r + k][j], m[q]);
     }
     const double va = m[2] - m[0] * m[0];
     const double vb = m[3] - m[1] * m[1];

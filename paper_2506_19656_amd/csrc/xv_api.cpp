@@ -334,13 +334,19 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
 }
 
 // SAD terms of a motion-search launch: (2R+1)^2 per real-channel sample.
+// SAD terms of one motion-search step: every candidate that keeps the
+// displaced block inside the padded picture, N^2 terms per real channel.
 double me_work(const xv_encoded* e, int s) {
-  const int R = e->p.search_range;
-  const double span2 = (double)(2 * R + 1) * (2 * R + 1);
+  const int R = e->p.search_range, N = e->N;
+  auto axis = [&](int P) {  // sum over block positions of the admissible displacements
+    double tot = 0;
+    for (int x0 = 0; x0 + N <= P; x0 += N) tot += std::min(R, P - N - x0) - std::max(-R, -x0) + 1;
+    return tot;
+  };
   const int nk = (int)((e->T - s + e->p.gop - 1) / e->p.gop);
   double ch = 0;
   for (int g = 0; g < e->G; g++) ch += std::min<int64_t>(3, e->bands - 3 * g);
-  return span2 * ch * nk * (double)e->Hp * e->Wp;
+  return axis(e->Hp) * axis(e->Wp) * (double)N * N * ch * nk;
 }
 
 double xf_frames(const xv_encoded* e, int s) {

@@ -76,8 +76,8 @@ def test_s2cloud_like_with_gaps(qp, N):
 
 
 def test_several_tiles_ragged_in_both_directions():
-    # 140 x 160 window positions: 3 x 18 tiles of 64 x 8, both ragged
-    host = synth.tiny_cube(seed=9, T=2, H=150, W=170, bands=4).numpy()
+    # 161 x 140 window positions: 6 x 9 tiles of 32 x 16, both ragged
+    host = synth.tiny_cube(seed=9, T=2, H=150, W=171, bands=4).numpy()
     p = xv.Params(bit_depth=10, qp=32, block=16, search_range=2, gop=2, pad_mode=xv.PAD_REPEAT)
     _check("ragged tiles", host, p)
 
