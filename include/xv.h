@@ -334,8 +334,12 @@ typedef struct {
 } xv_profile;
 
 /* Enable (1) or disable (0) per-launch event timing; enabling clears the
- * counters.  Timing adds an event pair around every launch. */
+ * counters.  Timing adds an event pair around every timed launch. */
 int xv_profile_enable(int on);
+/* Restrict timing to the kernel classes whose bits (1 << XV_K_*) are set in
+ * class_mask; 0 times every class (the default).  Fewer timed launches cost
+ * less: each event pair adds a few microseconds of queue time. */
+int xv_profile_select(uint32_t class_mask);
 /* Synchronises the streams that were timed and returns the totals. */
 int xv_profile_read(xv_profile* out);
 

@@ -105,8 +105,21 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+uint32_t g_prof_mask = ~0u;           // classes timed while enabled
 std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_events;  // idle events, reused across launches
 xv_profile g_prof_tot;
+
+hipEvent_t prof_event_locked() {
+  if (!g_prof_events.empty()) {
+    hipEvent_t e = g_prof_events.back();
+    g_prof_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
 
 struct ProfScope {
   int cls;
@@ -115,10 +128,13 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   bool on;
   ProfScope(int c, hipStream_t st, double w) : cls(c), s(st), work(w) {
-    on = g_prof_on;
+    on = g_prof_on && ((g_prof_mask >> c) & 1u);
     if (on) {
-      (void)hipEventCreate(&a);
-      (void)hipEventCreate(&b);
+      {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        a = prof_event_locked();
+        b = prof_event_locked();
+      }
       (void)hipEventRecord(a, s);
     }
   }
@@ -1020,12 +1036,19 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
 int xv_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   for (auto& r : g_prof_pending) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    (void)hipEventSynchronize(r.b);
+    g_prof_events.push_back(r.a);
+    g_prof_events.push_back(r.b);
   }
   g_prof_pending.clear();
   memset(&g_prof_tot, 0, sizeof g_prof_tot);
   g_prof_on = on != 0;
+  return XV_OK;
+}
+
+int xv_profile_select(uint32_t class_mask) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_mask = class_mask ? class_mask : ~0u;
   return XV_OK;
 }
 
@@ -1264,8 +1287,8 @@ int xv_profile_read(xv_profile* out) {
     g_prof_tot.ms[r.cls] += ms;
     g_prof_tot.launches[r.cls] += 1;
     g_prof_tot.work[r.cls] += r.work;
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    g_prof_events.push_back(r.a);
+    g_prof_events.push_back(r.b);
   }
   g_prof_pending.clear();
   *out = g_prof_tot;

@@ -106,7 +106,7 @@ OP_ENCODE, OP_DECODE = 0, 1
 EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube",
             "xv_decode_cube", "xv_psnr_bpppb", "xv_encoded_export", "xv_encoded_free",
             "xv_encode_batch", "xv_decode_batch", "xv_set_me_geometry", "xv_get_me_geometry",
-            "xv_autotune_me", "xv_autotune_me_batch", "xv_profile_enable", "xv_profile_read", "xv_server_create",
+            "xv_autotune_me", "xv_autotune_me_batch", "xv_profile_enable", "xv_profile_select", "xv_profile_read", "xv_server_create",
             "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
             "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release", "xv_pack", "xv_packed_view",
             "xv_packed_free", "xv_unpack", "xv_ssim", "xv_spectral_angle"]
@@ -162,6 +162,7 @@ def lib():
         L.xv_server_stats_read.argtypes = [vp, C.POINTER(ServerStatsC)]
         L.xv_server_destroy.argtypes = [vp]
         L.xv_profile_enable.argtypes = [C.c_int]
+        L.xv_profile_select.argtypes = [C.c_uint32]
         L.xv_profile_read.argtypes = [C.POINTER(ProfileC)]
         _lib = L
     return _lib
@@ -391,6 +392,13 @@ def autotune_me_batch(cubes, params, stream=None, max_candidates: int = 0) -> di
 
 def profile_enable(on: bool = True):
     _check(lib().xv_profile_enable(1 if on else 0))
+
+
+def profile_select(classes=None):
+    """xv_profile_select: time only the given kernel classes (K_* indices);
+    None times all of them."""
+    mask = 0 if not classes else sum(1 << k for k in classes)
+    _check(lib().xv_profile_select(mask))
 
 
 def profile_read() -> dict:
