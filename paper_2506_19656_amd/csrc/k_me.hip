@@ -82,45 +82,56 @@ typedef const __attribute__((address_space(1))) uint32_t gu32;
 
 constexpr int kBatch = 8;  // staging loads in flight per thread
 
-// Stages the reference windows of one workgroup: nrows = nch * (N + 2R) rows
-// of wpairs u16 pairs starting at column gx0, zero outside the picture.
+// Stages the reference windows of one workgroup: per channel, s.rows rows of
+// wpairs u16 pairs starting at column gx0, zero outside the picture.
 // Thread t covers pair column t % wpairs of rows t / wpairs + k * rpp; loads
 // are issued kBatch at a time from clamped (always in-bounds) addresses and
 // masked afterwards.  With an even gx0 a pair is wholly inside or wholly
-// outside the picture (Wp is even), so one dword load serves it.
+// outside the picture (Wp is even), so one dword load serves it.  Offsets
+// are 32-bit byte offsets from the channel plane (a padded frame stays below
+// 2^31 bytes, which the host checks).
+typedef const __attribute__((address_space(1))) char gchar;
+
 template <bool kEven>
-__device__ inline void stage_window(uint32_t* win, const uint16_t* ref, const MeShape& s,
-                                    int nrows, int wpairs, int gx0, int gy0, int Hp, int Wp) {
-  const size_t plane = (size_t)Hp * Wp;
+__device__ inline void stage_window(uint32_t* win, const uint16_t* ref, const MeShape& s, int nch,
+                                    int wpairs, int gx0, int gy0, int Hp, int Wp) {
+  const uint32_t plane_bytes = 2u * (uint32_t)Hp * (uint32_t)Wp;
   const int rpp = max(1, (int)blockDim.x / wpairs);  // rows per pass
   const int r0 = threadIdx.x / wpairs;
   if (r0 >= rpp) return;
   for (int m = threadIdx.x - r0 * wpairs; m < wpairs; m += (int)blockDim.x) {
     const int gx = gx0 + 2 * m;
     const bool in0 = gx >= 0 && gx < Wp, in1 = gx + 1 >= 0 && gx + 1 < Wp;
-    const int cx0 = min(max(gx, 0), Wp - 1), cx1 = min(max(gx + 1, 0), Wp - 1);
-    const int cxe = min(max(gx, 0), Wp - 2);
-    for (int rb = r0; rb < nrows; rb += kBatch * rpp) {
-      uint32_t v[kBatch];
+    const uint32_t bx0 = 2u * (uint32_t)min(max(gx, 0), Wp - 1);
+    const uint32_t bx1 = 2u * (uint32_t)min(max(gx + 1, 0), Wp - 1);
+    const uint32_t bxe = 2u * (uint32_t)min(max(gx, 0), Wp - 2);
+    for (int ch = 0; ch < nch; ch++) {
+      gchar* base = (gchar*)ref + (size_t)ch * plane_bytes;
+      uint32_t* wch = win + ch * s.rows * s.pitch + m;
+      for (int rb = r0; rb < s.rows; rb += kBatch * rpp) {
+        uint32_t v[kBatch];
 #pragma unroll
-      for (int u = 0; u < kBatch; u++) {
-        const int rr = min(rb + u * rpp, nrows - 1);
-        const int ch = rr >= 2 * s.rows ? 2 : (rr >= s.rows ? 1 : 0);
-        const int gy = gy0 + (rr - ch * s.rows);
-        const bool yin = gy >= 0 && gy < Hp;
-        gu16* rp = (gu16*)(ref + ch * plane + (size_t)min(max(gy, 0), Hp - 1) * Wp);
-        if constexpr (kEven) {
-          const uint32_t w = *(gu32*)(rp + cxe);
-          v[u] = (yin && in0) ? w : 0u;
-        } else {
-          const uint32_t lo = rp[cx0], hi = rp[cx1];
-          v[u] = ((yin && in0) ? lo : 0u) | (((yin && in1) ? hi : 0u) << 16);
+        for (int u = 0; u < kBatch; u++) {
+          const int gy = gy0 + min(rb + u * rpp, s.rows - 1);
+          const bool yin = (unsigned)gy < (unsigned)Hp;
+          // row * Wp < 2^31 / 6, so the 24-bit multiply is exact
+          const uint32_t row = 2u * __umul24((uint32_t)min(max(gy, 0), Hp - 1), (uint32_t)Wp);
+          if constexpr (kEven) {
+            const uint32_t off = row + bxe;
+            const uint32_t w = *(const __attribute__((address_space(1))) uint32_t*)(base + off);
+            v[u] = (yin && in0) ? w : 0u;
+          } else {
+            const uint32_t o0 = row + bx0, o1 = row + bx1;
+            const uint32_t lo = *(const __attribute__((address_space(1))) uint16_t*)(base + o0);
+            const uint32_t hi = *(const __attribute__((address_space(1))) uint16_t*)(base + o1);
+            v[u] = ((yin && in0) ? lo : 0u) | (((yin && in1) ? hi : 0u) << 16);
+          }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < kBatch; u++) {
-        const int rr = rb + u * rpp;
-        if (rr < nrows) win[rr * s.pitch + m] = v[u];
+        for (int u = 0; u < kBatch; u++) {
+          const int rr = rb + u * rpp;
+          if (rr < s.rows) wch[rr * s.pitch] = v[u];
+        }
       }
     }
   }
@@ -151,12 +162,10 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
   // flight per thread.
   const int gy0 = by * N - R, gx0 = bx0 * N - R;
   const int wpairs = s.wc / 2;
-  const size_t plane = (size_t)Hp * Wp;
-  const int nrows = nch * s.rows;
   if ((gx0 & 1) == 0)
-    stage_window<true>(win, job.ref, s, nrows, wpairs, gx0, gy0, Hp, Wp);
+    stage_window<true>(win, job.ref, s, nch, wpairs, gx0, gy0, Hp, Wp);
   else
-    stage_window<false>(win, job.ref, s, nrows, wpairs, gx0, gy0, Hp, Wp);
+    stage_window<false>(win, job.ref, s, nch, wpairs, gx0, gy0, Hp, Wp);
   {
     const int cw = nbv * N / 2;  // dwords per current row
     const int rpp = max(1, (int)blockDim.x / cw);
@@ -169,10 +178,11 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
 #pragma unroll
         for (int u = 0; u < kBatch; u++) {
           const int rr = min(rb + u * rpp, crows - 1);
-          const int ch = rr / N, row = rr - (rr / N) * N;
-          const gu32* cp = (const gu32*)(job.cur + ch * plane + (size_t)(by * N + row) * Wp +
-                                         bx0 * N);
-          v[u] = cp[m];
+          const int ch = rr / N, row = rr - (rr / N) * N;  // N is a power of two
+          const uint32_t off =
+              4u * (uint32_t)m + 2u * __umul24((uint32_t)(ch * Hp + by * N + row), (uint32_t)Wp) +
+              2u * (uint32_t)(bx0 * N);
+          v[u] = *(const __attribute__((address_space(1))) uint32_t*)((gchar*)job.cur + off);
         }
 #pragma unroll
         for (int u = 0; u < kBatch; u++) {
