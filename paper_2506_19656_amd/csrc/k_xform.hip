@@ -98,8 +98,8 @@ struct Tile {
 // 32760 after one, two and three levels, and the 4-point base takes a plain
 // product, so no level overflows 16 bits for n <= 32.
 // ---------------------------------------------------------------------------
-template <int n, int S, int NF>
-__device__ inline void fwd_part(const uint32_t (&xp)[n / 2], int (&out)[NF], int rnd) {
+template <int n, int S, class Out>
+__device__ inline void fwd_part(const uint32_t (&xp)[n / 2], Out& out, int rnd) {
   if constexpr (n == 4) {
     unroll<4>([&](auto kk) XV_INLINE {
       constexpr int k = kk;
@@ -125,7 +125,7 @@ __device__ inline void fwd_part(const uint32_t (&xp)[n / 2], int (&out)[NF], int
       });
       out[S * k] = a;
     });
-    fwd_part<n / 2, 2 * S, NF>(ep, out, rnd);
+    fwd_part<n / 2, 2 * S>(ep, out, rnd);
   }
 }
 
@@ -191,11 +191,18 @@ __device__ inline void to_inverse_order(const int (&y)[N], uint32_t (&ip)[N / 2]
 }
 
 // Forward column stage: out[l] = sum_y M[l][y] T[y] + rnd, T as N/2 pairs.
+// Row-stage outputs may use all 16 bits, which the butterfly's packed
+// pre-adds cannot take in general; but when every |T| of the wave's columns is
+// at most 32767 >> (log2 N - 2), the sums of all its pre-add levels stay in
+// 16 bits and the even/odd form gives the same sums with fewer products.  The
+// choice is one vote per wave, so lanes never diverge on it.
+// Column-stage accumulators as one vector value: the two forms of the stage
+// then update it by element insertion, which stays in registers.
 template <int N>
-__device__ inline void fwd_full(const uint32_t* tp, int (&out)[N], int rnd) {
-  uint32_t t[N / 2];
-#pragma unroll
-  for (int j = 0; j < N / 2; j++) t[j] = tp[j];
+using ivec = int __attribute__((ext_vector_type(N)));
+
+template <int N>
+__device__ inline void fwd_product(const uint32_t (&t)[N / 2], ivec<N>& out, int rnd) {
   unroll<N>([&](auto ll) XV_INLINE {
     constexpr int l = ll;
     int a = rnd;
@@ -205,6 +212,28 @@ __device__ inline void fwd_full(const uint32_t* tp, int (&out)[N], int rnd) {
     });
     out[l] = a;
   });
+}
+
+template <int N>
+__device__ inline void fwd_column(const uint32_t* tp, ivec<N>& out, int rnd) {
+  uint32_t t[N / 2];
+#pragma unroll
+  for (int j = 0; j < N / 2; j++) t[j] = tp[j];
+  bool fast = false;
+  if constexpr (N >= 16) {
+    constexpr short kLim = (short)(32767 >> (ilog2c(N) - 2));
+    s16x2 mx = {0, 0};
+#pragma unroll
+    for (int j = 0; j < N / 2; j++) {
+      const s16x2 v = as_v(t[j]);  // |T| < 2^15 (row-stage headroom), so -v is exact
+      mx = __builtin_elementwise_max(mx, __builtin_elementwise_max(v, -v));
+    }
+    fast = __all(mx.x <= kLim && mx.y <= kLim);
+  }
+  if (fast)
+    fwd_part<N, 1>(t, out, rnd);
+  else
+    fwd_product<N>(t, out, rnd);
 }
 
 // LDS layout per workgroup, encode (int16):
@@ -569,7 +598,7 @@ encode_kernel(const LaunchDesc jr) {
     for (int m = 0; m < N / 2; m++) er[m] = psub(cp[m], pp[m]);  // |res| <= 4095
     const int s1 = L2N + B - 9;
     int acc[N];
-    fwd_part<N, 1, N>(er, acc, 1 << (s1 - 1));
+    fwd_part<N, 1>(er, acc, 1 << (s1 - 1));
 #pragma unroll
     for (int k = 0; k < N; k++) s.TD[c][b][k][r] = (int16_t)(acc[k] >> s1);
   }
@@ -587,8 +616,8 @@ encode_kernel(const LaunchDesc jr) {
     const int qf = kQf[qP % 6];
     const Dequant dqp = dequant_params(qP, B + L2N - 5);
     uint32_t* row = (uint32_t*)s.TD[c][b][k];
-    int acc[N];
-    fwd_full<N>(row, acc, 1 << (L2N + 5));
+    ivec<N> acc;
+    fwd_column<N>(row, acc, 1 << (L2N + 5));
     // level = sgn(C) min(32767, (|C| Qf + off) >> qbits) in signed form:
     // C >= 0: (C Qf + off) >> qbits; C < 0: (C Qf + 2^qbits - 1 - off) >> qbits
     // (|C Qf| < 2^30, so nothing overflows)
