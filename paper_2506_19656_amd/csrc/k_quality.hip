@@ -70,43 +70,63 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_kernel(const SsimArgs a) {
   }
   __syncthreads();
 
-  for (int i = threadIdx.x; i < kInY * kTileX; i += kSsimThreads) {
-    const int r = i / kTileX, j = i - r * kTileX;
-    double sa = 0.0, sb = 0.0, saa = 0.0, sbb = 0.0, sab = 0.0;
+  // Row pass: a thread filters 4 adjacent positions of one input row from 14
+  // samples held in registers.
+  constexpr int kHx = 4;
+  for (int i = threadIdx.x; i < kInY * (kTileX / kHx); i += kSsimThreads) {
+    const int r = i / (kTileX / kHx), j0 = (i - r * (kTileX / kHx)) * kHx;
+    double u[kHx + 10], v[kHx + 10];
 #pragma unroll
-    for (int k = 0; k < 11; k++) {
-      const double u = s.a[r][j + k], v = s.b[r][j + k];
-      const double wu = a.w[k] * u, wv = a.w[k] * v;
-      sa += wu;
-      sb += wv;
-      saa = fma(wu, u, saa);
-      sbb = fma(wv, v, sbb);
-      sab = fma(wu, v, sab);
+    for (int q = 0; q < kHx + 10; q++) {
+      u[q] = s.a[r][j0 + q];
+      v[q] = s.b[r][j0 + q];
     }
-    s.h[0][r][j] = sa;
-    s.h[1][r][j] = sb;
-    s.h[2][r][j] = saa;
-    s.h[3][r][j] = sbb;
-    s.h[4][r][j] = sab;
+#pragma unroll
+    for (int jj = 0; jj < kHx; jj++) {
+      double sa = 0.0, sb = 0.0, saa = 0.0, sbb = 0.0, sab = 0.0;
+#pragma unroll
+      for (int k = 0; k < 11; k++) {
+        const double wu = a.w[k] * u[jj + k], wv = a.w[k] * v[jj + k];
+        sa += wu;
+        sb += wv;
+        saa = fma(wu, u[jj + k], saa);
+        sbb = fma(wv, v[jj + k], sbb);
+        sab = fma(wu, v[jj + k], sab);
+      }
+      s.h[0][r][j0 + jj] = sa;
+      s.h[1][r][j0 + jj] = sb;
+      s.h[2][r][j0 + jj] = saa;
+      s.h[3][r][j0 + jj] = sbb;
+      s.h[4][r][j0 + jj] = sab;
+    }
   }
   __syncthreads();
 
+  // Column pass: a thread takes 2 vertically adjacent window positions, which
+  // share 10 of their 11 filtered rows.
   double acc = 0.0;
-  for (int i = threadIdx.x; i < kTileY * kTileX; i += kSsimThreads) {
-    const int r = i / kTileX, j = i - r * kTileX;
-    if (y0 + r + 11 > a.H || x0 + j + 11 > a.W) continue;
-    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < (kTileY / 2) * kTileX; i += kSsimThreads) {
+    const int r0 = (i / kTileX) * 2, j = i - (i / kTileX) * kTileX;
+    double m0[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, m1[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 11; k++) {
-      const double w = a.w[k];
+    for (int k = 0; k < 12; k++) {
 #pragma unroll
-      for (int q = 0; q < 5; q++) m[q] = fma(w, s.h[q][r + k][j], m[q]);
+      for (int q = 0; q < 5; q++) {
+        const double h = s.h[q][r0 + k][j];
+        if (k < 11) m0[q] = fma(a.w[k], h, m0[q]);
+        if (k > 0) m1[q] = fma(a.w[k - 1], h, m1[q]);
+      }
     }
-    const double va = m[2] - m[0] * m[0];
-    const double vb = m[3] - m[1] * m[1];
-    const double cab = m[4] - m[0] * m[1];
-    acc += ((2.0 * m[0] * m[1] + a.C1) * (2.0 * cab + a.C2)) /
-           ((m[0] * m[0] + m[1] * m[1] + a.C1) * (va + vb + a.C2));
+#pragma unroll
+    for (int d = 0; d < 2; d++) {
+      const double* m = d == 0 ? m0 : m1;
+      if (y0 + r0 + d + 11 > a.H || x0 + j + 11 > a.W) continue;
+      const double va = m[2] - m[0] * m[0];
+      const double vb = m[3] - m[1] * m[1];
+      const double cab = m[4] - m[0] * m[1];
+      acc += ((2.0 * m[0] * m[1] + a.C1) * (2.0 * cab + a.C2)) /
+             ((m[0] * m[0] + m[1] * m[1] + a.C1) * (va + vb + a.C2));
+    }
   }
   const double tot = block_sum(acc, s.red);
   if (threadIdx.x == 0) a.part[blk] = tot;
