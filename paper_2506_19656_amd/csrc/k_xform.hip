@@ -253,9 +253,11 @@ struct alignas(16) LdsEnc {
   uint32_t cbsum;
 };
 
+// Decode works one channel per workgroup (the channels of a frame are
+// independent there): the inverse column-stage output of that channel.
 template <int N>
 struct alignas(16) LdsDec {
-  int16_t E[3][Tile<N>::NBW][N][Tile<N>::P];
+  int16_t E[Tile<N>::NBW][N][Tile<N>::P];
 };
 
 // Up-right diagonal scan of an N x N block (ITU-T H.265 6.5.3): anti-
@@ -287,9 +289,9 @@ struct TileCoord {
 };
 
 template <int N>
-__device__ inline bool locate(const LaunchDesc& jd, TileCoord& tc) {
+__device__ inline bool locate_at(const LaunchDesc& jd, int tile, TileCoord& tc) {
   int tl;
-  tc.job = desc_job(jd, blockIdx.x, tl);
+  tc.job = desc_job(jd, tile, tl);
   tc.tl = tl;
   const FrameJob& job = *tc.job;
   tc.Hb = job.Hp / N;
@@ -299,6 +301,11 @@ __device__ inline bool locate(const LaunchDesc& jd, TileCoord& tc) {
   tc.by = tl / runs;
   tc.bx0 = (tl - tc.by * runs) * Tile<N>::NBW;
   return true;
+}
+
+template <int N>
+__device__ inline bool locate(const LaunchDesc& jd, TileCoord& tc) {
+  return locate_at<N>(jd, (int)blockIdx.x, tc);
 }
 
 // Global memory through address space 1 at a 32-bit byte offset from a base
@@ -697,17 +704,17 @@ encode_kernel(const LaunchDesc jr) {
   if (t < 3) gst<unsigned long long>(job.part, part + 8 * t, s.sse[t]);
 }
 
+// One wave per (tile, channel): workgroup 3 w + c decodes channel c of tile w.
 template <int N>
-__global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
+__global__ void __launch_bounds__(64) decode_kernel(const LaunchDesc jr) {
   constexpr int NBW = Tile<N>::NBW;
   constexpr int L2N = Tile<N>::L2N;
   __shared__ LdsDec<N> s;
   TileCoord tc;
-  if (!locate<N>(jr, tc)) return;
+  const int c = (int)(blockIdx.x % 3u);
+  if (!locate_at<N>(jr, (int)(blockIdx.x / 3u), tc)) return;
   const FrameJob job = *tc.job;
-  const int t = threadIdx.x;
-  const int c = t >> 6;
-  const int rem = t & 63;
+  const int rem = threadIdx.x;
   const int r = rem / NBW;
   const int b = rem - r * NBW;
   const int bx = tc.bx0 + b;
@@ -737,12 +744,12 @@ __global__ void __launch_bounds__(192) decode_kernel(const LaunchDesc jr) {
     }
     uint32_t dq[N / 2];
     dequant_pairs<N>(lv, dqp, dq);
-    inverse_column<N>(dq, s.E[c][b], inv_slot<N>(k));
+    inverse_column<N>(dq, s.E[b], inv_slot<N>(k));
   }
   __syncthreads();
   if (vb) {
     uint32_t rp[N / 2];
-    inverse_row<N>(s.E[c][b][r], pp, B, rp);
+    inverse_row<N>(s.E[b][r], pp, B, rp);
     store_row_packed<N>(job.rec, 2u * row_off, rp);
   }
 }
@@ -754,7 +761,7 @@ hipError_t launch_encode_t(const LaunchDesc& d, hipStream_t s) {
 }
 template <int N>
 hipError_t launch_decode_t(const LaunchDesc& d, hipStream_t s) {
-  decode_kernel<N><<<d.tiles, 192, 0, s>>>(d);
+  decode_kernel<N><<<3u * (unsigned)d.tiles, 64, 0, s>>>(d);
   return hipGetLastError();
 }
 
