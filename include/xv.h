@@ -296,7 +296,7 @@ int xv_get_me_geometry(int block, int search_range, int width_blocks, xv_me_geom
 
 /* Empirical tuner: times the motion-search kernel on the first P-picture
  * step of the cube `in` (device memory) coded with p, for the geometries the
- * model ranks highest (max_candidates of them, <= 0: 64), and installs the
+ * model ranks highest (max_candidates of them, <= 0: 512), and installs the
  * fastest for (p->block, p->search_range) as xv_set_me_geometry would.
  * Coded outputs never depend on the geometry.  Synchronises hip_stream; out
  * (optional) receives the chosen geometry and *best_ms (optional) its

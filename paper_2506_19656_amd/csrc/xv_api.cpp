@@ -976,7 +976,7 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
   std::stable_sort(cand.begin(), cand.end(), [&](const MeGeom& a, const MeGeom& b) {
     return me_model_score(N, R, a, wb) > me_model_score(N, R, b, wb);
   });
-  const size_t keep = (size_t)(max_candidates > 0 ? max_candidates : 64);
+  const size_t keep = (size_t)(max_candidates > 0 ? max_candidates : 512);
   if (cand.size() > keep) cand.resize(keep);
   const MeGeom def = geometry_for(N, R, wb);
   if (std::find_if(cand.begin(), cand.end(), [&](const MeGeom& g) {
