@@ -276,9 +276,10 @@ __device__ inline uint16_t convert(double x, double mn, double range, double L) 
 // of a time reads all the pixel's bands together; bands left without a
 // valid sample in the whole series keep their preset value (the band
 // minimum).
+template <class V>
 __device__ inline void fill_missing(const float* __restrict__ d, int64_t src, int nb,
                                     int64_t fstride, int64_t t, int64_t T, int fill_mode,
-                                    uint32_t miss, double (&v)[8]) {
+                                    uint32_t miss, V (&v)[8]) {
   auto probe = [&](int64_t u) {
     float f[8];
 #pragma unroll
@@ -286,7 +287,7 @@ __device__ inline void fill_missing(const float* __restrict__ d, int64_t src, in
 #pragma unroll
     for (int j = 0; j < 8; j++) {
       if (((miss >> j) & 1u) && f[j] == f[j]) {
-        v[j] = (double)f[j];
+        v[j] = (V)f[j];
         miss &= ~(1u << j);
       }
     }
@@ -677,16 +678,18 @@ __global__ void __launch_bounds__(kThreads) pack_vec_kernel(PackArgs a) {
   uint8_t ok[BANDS][G];
 #pragma unroll
   for (int p = 0; p < G; p++) {
-    double dv[8];
+    // samples as float: u16 values and the minimum of a float band are exact
+    // there, and a filled sample is an input float
+    float dv[8];
     uint32_t miss = 0u;
 #pragma unroll
     for (int b = 0; b < BANDS; b++) {
       if constexpr (sizeof(Tv) == 2) {
-        dv[b] = (double)v[p * BANDS + b];
+        dv[b] = (float)v[p * BANDS + b];
       } else {
         const float f = v[p * BANDS + b];
         const bool nan = f != f;
-        dv[b] = nan ? smn[b] : (double)f;
+        dv[b] = nan ? (float)smn[b] : f;
         miss |= (nan && !sall[b]) ? (1u << b) : 0u;
       }
     }
@@ -700,7 +703,7 @@ __global__ void __launch_bounds__(kThreads) pack_vec_kernel(PackArgs a) {
     }
 #pragma unroll
     for (int b = 0; b < BANDS; b++) {
-      q[b][p] = convert(dv[b], smn[b], srg[b], L);
+      q[b][p] = convert((double)dv[b], smn[b], srg[b], L);
       bool valid = true;
       if constexpr (sizeof(Tv) == 4) {
         const float f = v[p * BANDS + b];
