@@ -257,13 +257,22 @@ __global__ void __launch_bounds__(kFinThreads) stats_finalize_kernel(StatsArgs a
 }
 
 // q = floor((x - mn) * L / (mx - mn) + 1/2) clamped to [0, L]; constant band -> 0.
-__device__ inline uint16_t convert(double x, double mn, double range, double L) {
+// The quotient is formed as a product with the band's reciprocal; the two
+// differ by at most a few ulp (below 3e-12, as the quotient is at most L <
+// 2^12), which changes floor(v + 1/2) only when v + 1/2 lies that close to an
+// integer, so within 1e-9 of one the exact IEEE quotient is taken instead and
+// the result is always that of the division.
+__device__ inline uint16_t convert(double x, double mn, double range, double inv, double L) {
   if (range == 0.0) return 0;
-  double d = x - mn;
-  double num = d * L;
-  double v = num / range;
-  double q = floor(v + 0.5);
-  q = q < 0.0 ? 0.0 : q;
+  const double num = (x - mn) * L;
+  double w = num * inv + 0.5;
+  double fw = floor(w);
+  const double fr = w - fw;
+  if (fr < 1e-9 || fr > 1.0 - 1e-9) {
+    w = num / range + 0.5;
+    fw = floor(w);
+  }
+  double q = fw < 0.0 ? 0.0 : fw;
   q = q > L ? L : q;
   return (uint16_t)q;
 }
@@ -314,13 +323,14 @@ __device__ inline void fill_missing(const float* __restrict__ d, int64_t src, in
 template <typename Tv>
 __global__ void __launch_bounds__(kThreads) pack_kernel(PackArgs a) {
   Tv* stage = (Tv*)xv_stage_lds;
-  __shared__ double smn[XV_MAX_BANDS], srg[XV_MAX_BANDS];
+  __shared__ double smn[XV_MAX_BANDS], srg[XV_MAX_BANDS], sinv[XV_MAX_BANDS];
   __shared__ int sall[XV_MAX_BANDS];
   const int bands = a.bands;
   const bool gaps = sizeof(Tv) == 4 && *a.nan_total != 0u;
   for (int i = threadIdx.x; i < bands; i += blockDim.x) {
     smn[i] = a.mn[i];
     srg[i] = a.mx[i] - a.mn[i];
+    sinv[i] = srg[i] != 0.0 ? 1.0 / srg[i] : 0.0;
     sall[i] = gaps && (int64_t)a.nan_count[i] == a.T * a.H * a.W;
   }
   const int P = a.chunk_px;
@@ -375,7 +385,7 @@ __global__ void __launch_bounds__(kThreads) pack_kernel(PackArgs a) {
     for (int j = 0; j < 8; j++) {
       if (j >= nb) break;
       const int b = b0 + j;
-      const uint16_t q = convert(v[j], smn[b], srg[b], L);
+      const uint16_t q = convert(v[j], smn[b], srg[b], sinv[b], L);
       const int g = b / 3, c = b - 3 * g;
       const int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
       a.frames[off] = q;
@@ -641,13 +651,14 @@ template <typename Tv, int BANDS>
 __global__ void __launch_bounds__(kThreads) pack_vec_kernel(PackArgs a) {
   using PG = PixGroup<Tv, BANDS>;
   constexpr int G = PG::g;
-  __shared__ double smn[BANDS], srg[BANDS];
+  __shared__ double smn[BANDS], srg[BANDS], sinv[BANDS];
   __shared__ int sall[BANDS];
   const bool gaps = sizeof(Tv) == 4 && *a.nan_total != 0u;
   if (threadIdx.x < BANDS) {
     const int i = threadIdx.x;
     smn[i] = a.mn[i];
     srg[i] = a.mx[i] - a.mn[i];
+    sinv[i] = srg[i] != 0.0 ? 1.0 / srg[i] : 0.0;
     sall[i] = gaps && (int64_t)a.nan_count[i] == a.T * a.H * a.W;
   }
   __syncthreads();
@@ -703,7 +714,7 @@ __global__ void __launch_bounds__(kThreads) pack_vec_kernel(PackArgs a) {
     }
 #pragma unroll
     for (int b = 0; b < BANDS; b++) {
-      q[b][p] = convert((double)dv[b], smn[b], srg[b], L);
+      q[b][p] = convert((double)dv[b], smn[b], srg[b], sinv[b], L);
       bool valid = true;
       if constexpr (sizeof(Tv) == 4) {
         const float f = v[p * BANDS + b];
