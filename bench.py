@@ -331,7 +331,7 @@ def main():
         if cached is not None and f"N{N}" in cached:
             g = cached[f"N{N}"]
             xv.set_me_geometry(N, wl.search_range, g["blocks_per_wg"], g["cands_per_lane"],
-                               g["threads"], g.get("rows_per_lane", 0))
+                               g["threads"], g.get("rows_per_lane", 0), g.get("layout", 1))
             tuning[f"N{N}"] = dict(g, tuned=True, from_file=True)
         elif not args.no_tune:
             print(f"[bench] tuning motion search N={N}", file=sys.stderr, flush=True)

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define XV_ABI_VERSION 3
+#define XV_ABI_VERSION 4
 
 /* status codes */
 #define XV_OK 0
@@ -276,10 +276,18 @@ int xv_server_destroy(xv_server* sv);
 
 /* ---- Launch geometry (never changes coded outputs) -------------------- */
 
+/* Window layouts of the motion-search kernel in LDS.  Column pairs: a
+ * dword holds two horizontally adjacent samples; a lane takes an even
+ * number of candidate columns (2..18) on 1, 2, 3 or (for 2 or 4 columns) 5
+ * candidate rows.  Row pairs: a dword holds two vertically adjacent
+ * samples (twice the LDS); a lane takes 2..9, 11 or 13 candidate columns on
+ * one candidate row. */
+#define XV_ME_COLUMN_PAIRS 1
+#define XV_ME_ROW_PAIRS 2
+
 /* Geometry of the motion-search kernel for one (N, R): blocks per
- * workgroup along x, candidates per lane along x (even), threads per
- * workgroup (multiple of 64, <= 512), candidate rows per lane (1, 2 or 3
- * for any candidate count; 5 for 2 or 4 candidates).
+ * workgroup along x, candidates per lane along x, threads per workgroup
+ * (multiple of 64, <= 512), candidate rows per lane, window layout (above).
  * Zero fields take the default; NULL or all fields zero restores the
  * default for (block, search_range). */
 typedef struct {
@@ -287,6 +295,7 @@ typedef struct {
   int32_t cands_per_lane;
   int32_t threads;
   int32_t rows_per_lane;
+  int32_t layout;
 } xv_me_geometry;
 
 int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g);

@@ -91,6 +91,7 @@ constexpr int kBatch = 8;  // staging loads in flight per thread
 // are 32-bit byte offsets from the channel plane (a padded frame stays below
 // 2^31 bytes, which the host checks).
 typedef const __attribute__((address_space(1))) char gchar;
+typedef uint32_t u32x4_l __attribute__((ext_vector_type(4)));
 
 template <bool kEven>
 __device__ inline void stage_window(uint32_t* win, const uint16_t* ref, const MeShape& s, int nch,
@@ -348,6 +349,293 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
   }
 }
 
+// ---- Row-pair layout --------------------------------------------------
+//
+// The second layout stores, for every window row r and column c, the dword
+// (w[r][c], w[r+1][c]): two vertically adjacent samples.  A candidate at any
+// column offset then reads whole dwords (no realignment), and candidate row r
+// pairs its window rows r + 2j, r + 2j + 1 with current rows 2j, 2j + 1,
+// stored paired the same way.  A lane evaluates KX consecutive candidate
+// columns of one candidate row; KX need not be even, so a group size that
+// divides the span 2R+1 (3 or 11 for R = 16) leaves no column unused.  The
+// window is twice the bytes of the column-pair one.
+struct RpShape {
+  int span, xr, wc, pitch;  // xr pair rows; wc staged columns (even); pitch odd, dwords
+};
+
+__host__ __device__ inline RpShape rp_shape(int N, int R, int kx, int nb) {
+  RpShape s;
+  s.span = 2 * R + 1;
+  s.xr = 2 * R + N - 1;
+  s.wc = nb * N + 2 * R + kx - 1;
+  s.wc += s.wc & 1;
+  s.pitch = s.wc + 1;
+  return s;
+}
+
+// LDS of a workgroup, in dwords: pair rows [3][xr][pitch], paired current
+// blocks [3][nb][N/2][N] from a 16-byte boundary, nb 64-bit keys.
+__host__ __device__ inline MeLds rp_lds_layout(int N, const RpShape& s, int nb) {
+  MeLds l;
+  const size_t x = (size_t)3 * s.xr * s.pitch;
+  l.cur = (x + 3) & ~(size_t)3;
+  l.best = l.cur + (size_t)3 * nb * (N / 2) * N;  // a multiple of 4 past cur
+  l.bytes = l.best * 4 + (size_t)nb * 8;
+  return l;
+}
+
+// Stages the pair rows of the window.  A thread owns column pair m (window
+// columns 2m, 2m+1 at picture columns gx0 + 2m, gx0 + 2m + 1) and walks the
+// (channel, chunk of kRc pair rows) tasks q0, q0 + qstep, ...; a task loads
+// kRc + 1 window rows (zero outside the picture) and writes 2 kRc pair
+// dwords.  Offsets are 32-bit byte offsets from the uniform frame base (a
+// padded frame of three channels stays below 2^31 bytes).
+template <bool kEven>
+__device__ inline void stage_row_pairs(uint32_t* X, const uint16_t* ref, const RpShape& s,
+                                       int nch, int gx0, int gy0, int Hp, int Wp) {
+  constexpr int kRc = 8;
+  typedef const __attribute__((address_space(1))) uint32_t gu32_t;
+  typedef const __attribute__((address_space(1))) uint16_t gu16_t;
+  const uint32_t plane_bytes = 2u * (uint32_t)Hp * (uint32_t)Wp;
+  const uint32_t step = 2u * (uint32_t)Wp;
+  gchar* base = (gchar*)ref;
+  const int mp = s.wc / 2;
+  const int nk = (s.xr + kRc - 1) / kRc;
+  const int qstep = max(1, (int)blockDim.x / mp);
+  const int q0 = (int)threadIdx.x / mp;
+  if (q0 >= qstep) return;
+  for (int m = (int)threadIdx.x - q0 * mp; m < mp; m += (int)blockDim.x) {
+    const int gx = gx0 + 2 * m;
+    const bool in0 = gx >= 0 && gx < Wp, in1 = gx + 1 >= 0 && gx + 1 < Wp;
+    const uint32_t bx0 = 2u * (uint32_t)min(max(gx, 0), Wp - 1);
+    const uint32_t bx1 = 2u * (uint32_t)min(max(gx + 1, 0), Wp - 1);
+    const uint32_t bxe = 2u * (uint32_t)min(max(gx, 0), Wp - 2);
+    int ch = q0 / nk, k = q0 - (q0 / nk) * nk;
+    for (; ch < nch;) {
+      const uint32_t cho = (uint32_t)ch * plane_bytes;
+      const int r0 = k * kRc;
+      uint32_t v[kRc + 1];
+      if (gy0 + r0 >= 0 && gy0 + r0 + kRc < Hp) {
+        // all rows inside the picture: one row offset, stepped
+        uint32_t row = cho + 2u * __umul24((uint32_t)(gy0 + r0), (uint32_t)Wp);
+        if constexpr (kEven) {
+          // an even column pair lies wholly inside or wholly outside
+          if (in0) {
+#pragma unroll
+            for (int u = 0; u <= kRc; u++, row += step) v[u] = *(gu32_t*)(base + (row + bxe));
+          } else {
+#pragma unroll
+            for (int u = 0; u <= kRc; u++) v[u] = 0u;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u <= kRc; u++, row += step) {
+            const uint32_t lo = *(gu16_t*)(base + (row + bx0));
+            const uint32_t hi = *(gu16_t*)(base + (row + bx1));
+            v[u] = (in0 ? lo : 0u) | ((in1 ? hi : 0u) << 16);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u <= kRc; u++) {
+          const int gy = gy0 + r0 + u;
+          const bool yin = (unsigned)gy < (unsigned)Hp;
+          const uint32_t row = cho + 2u * __umul24((uint32_t)min(max(gy, 0), Hp - 1), (uint32_t)Wp);
+          if constexpr (kEven) {
+            const uint32_t w = *(gu32_t*)(base + (row + bxe));
+            v[u] = (yin && in0) ? w : 0u;
+          } else {
+            const uint32_t lo = *(gu16_t*)(base + (row + bx0));
+            const uint32_t hi = *(gu16_t*)(base + (row + bx1));
+            v[u] = ((yin && in0) ? lo : 0u) | (((yin && in1) ? hi : 0u) << 16);
+          }
+        }
+      }
+      uint32_t* xo = X + (ch * s.xr + r0) * s.pitch + 2 * m;
+      if (r0 + kRc <= s.xr) {
+#pragma unroll
+        for (int u = 0; u < kRc; u++) {
+          xo[u * s.pitch] = (v[u] & 0xffffu) | (v[u + 1] << 16);
+          xo[u * s.pitch + 1] = (v[u] >> 16) | (v[u + 1] & 0xffff0000u);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kRc; u++) {
+          if (r0 + u < s.xr) {
+            xo[u * s.pitch] = (v[u] & 0xffffu) | (v[u + 1] << 16);
+            xo[u * s.pitch + 1] = (v[u] >> 16) | (v[u + 1] & 0xffff0000u);
+          }
+        }
+      }
+      k += qstep;
+      while (k >= nk) {
+        k -= nk;
+        ch++;
+      }
+    }
+  }
+}
+
+// pair rows unrolled per channel: all of them up to N = 16, two for N = 32
+template <int N>
+constexpr int kRpUnroll = N <= 16 ? N / 2 : 2;
+
+template <int N, int KX>
+__global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, int nb) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  int tl;
+  const FrameJob& job = *desc_job(jd, blockIdx.x, tl);
+  const int Hp = job.Hp, Wp = job.Wp;
+  const int Hb = Hp / N, Wb = Wp / N;
+  const int runs = (Wb + nb - 1) / nb;
+  if (tl >= Hb * runs) return;
+  const int by = tl / runs;
+  const int bx0 = (tl - by * runs) * nb;
+  const int nbv = min(nb, Wb - bx0);
+  const int nch = job.nch;
+  const RpShape s = rp_shape(N, R, KX, nb);
+  const MeLds ll = rp_lds_layout(N, s, nb);
+  uint32_t* X = lds;
+  uint32_t* curx = lds + ll.cur;
+  unsigned long long* best = (unsigned long long*)(lds + ll.best);
+
+  const int gy0 = by * N - R, gx0 = bx0 * N - R;
+  if ((gx0 & 1) == 0)
+    stage_row_pairs<true>(X, job.ref, s, nch, gx0, gy0, Hp, Wp);
+  else
+    stage_row_pairs<false>(X, job.ref, s, nch, gx0, gy0, Hp, Wp);
+  {
+    // current blocks: dword (c[2j][x], c[2j+1][x]) at [ch][b][j][x]
+    constexpr int CM = N / 2;  // column pairs of a block row
+    const int tasks = nbv * (N / 2) * CM;
+    for (int ch = 0; ch < nch; ch++)
+    for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+      const int m = t % CM, q = t / CM;
+      const int j = q % (N / 2), b = q / (N / 2);
+      const uint32_t off = 2u * __umul24((uint32_t)(ch * Hp + by * N + 2 * j), (uint32_t)Wp) +
+                           2u * (uint32_t)((bx0 + b) * N + 2 * m);
+      const uint32_t a0 = *(const __attribute__((address_space(1))) uint32_t*)((gchar*)job.cur + off);
+      const uint32_t a1 = *(const __attribute__((address_space(1))) uint32_t*)((gchar*)job.cur + off +
+                                                                               2u * (uint32_t)Wp);
+      uint32_t* co = curx + ((ch * nb + b) * (N / 2) + j) * N + 2 * m;
+      co[0] = (a0 & 0xffffu) | (a1 << 16);
+      co[1] = (a0 >> 16) | (a1 & 0xffff0000u);
+    }
+  }
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) best[b] = ~0ull;
+  __syncthreads();
+
+  // Items: (block b, group g of KX candidate columns from the block's first
+  // in-picture column, candidate row r), r fastest so that neighbouring
+  // lanes read pair rows a pitch apart and share the current block.
+  const int y0b = by * N;
+  const int rlo = max(0, R - y0b);
+  const int nr = min(s.span - 1, Hp - N - y0b + R) - rlo + 1;
+  int items = 0;
+  for (int b = 0; b < nbv; b++) {
+    const int x0 = (bx0 + b) * N;
+    const int clo = max(0, R - x0), chi = min(s.span - 1, Wp - N - x0 + R);
+    items += nr * ((chi - clo + KX) / KX);
+  }
+  const int keyshift_sad = R <= 32 ? 21 : 23;
+  const int keyshift_l1 = R <= 32 ? 13 : 15;
+  const float inv_nr = 1.0f / (float)nr;
+  constexpr int NP = KX + N - 1;
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    // The wave's items are consecutive: find the block of its first item
+    // with wave-uniform (scalar) arithmetic, then step each lane on from
+    // there, rarely more than once.
+    const int it0 = __builtin_amdgcn_readfirstlane(it);
+    int b = 0, start = 0, clo, chi, n;
+    for (;; b++) {
+      const int x0 = (bx0 + b) * N;
+      clo = max(0, R - x0);
+      chi = min(s.span - 1, Wp - N - x0 + R);
+      n = nr * ((chi - clo + KX) / KX);
+      if (it0 < start + n || b + 1 >= nbv) break;
+      start += n;
+    }
+    int rem = it - start;
+    while (rem >= n && b + 1 < nbv) {
+      rem -= n;
+      b++;
+      const int x0 = (bx0 + b) * N;
+      clo = max(0, R - x0);
+      chi = min(s.span - 1, Wp - N - x0 + R);
+      n = nr * ((chi - clo + KX) / KX);
+    }
+    // rem / nr in binary32: rem + 1/2 and nr are exact, the quotient is
+    // below 2R + 2 <= 130 with a relative error of a few 2^-24, and its
+    // distance from an integer is at least 1/(2 nr) >= 1/258
+    const int g = (int)(((float)rem + 0.5f) * inv_nr);
+    const int r = rlo + rem - g * nr;
+    const int c0 = clo + g * KX;
+    uint32_t acc[KX];
+#pragma unroll
+    for (int k = 0; k < KX; k++) acc[k] = 0;
+    for (int ch = 0; ch < nch; ch++) {
+      const int xbase = (ch * s.xr + r) * s.pitch + b * N + c0;
+      const u32x4_l* cp = (const u32x4_l*)(curx + (ch * nb + b) * (N / 2) * N);
+#pragma unroll kRpUnroll<N>
+      for (int j = 0; j < N / 2; j++) {
+        uint32_t P[NP], C[N];
+        // One base per pair row and immediate offsets for its NP dwords; the
+        // empty asm keeps the compiler from strength-reducing every load
+        // address into an induction variable of its own.
+        int xo = xbase + 2 * j * s.pitch;
+        asm volatile("" : "+v"(xo));
+#pragma unroll
+        for (int q = 0; q < NP; q++) P[q] = X[xo + q];
+#pragma unroll
+        for (int q = 0; q < N / 4; q++) {
+          const u32x4_l c4 = cp[j * (N / 4) + q];
+          C[4 * q] = c4.x;
+          C[4 * q + 1] = c4.y;
+          C[4 * q + 2] = c4.z;
+          C[4 * q + 3] = c4.w;
+        }
+#pragma unroll
+        for (int k = 0; k < KX; k++)
+#pragma unroll
+          for (int x = 0; x < N; x++) acc[k] = __builtin_amdgcn_sad_u16(P[k + x], C[x], acc[k]);
+      }
+    }
+    // The item's candidates share row r and are visited in increasing dx, so
+    // a strict < over (SAD << 8 | L1) keeps the lexicographic minimum of
+    // (SAD, L1, dy, dx) among them.
+    const int khi = chi - c0;
+    const uint32_t ly = (uint32_t)abs(r - R);
+    uint32_t key[KX], kb32 = 0xffffffffu;
+    const uint32_t cx = (uint32_t)(c0 + KX);  // below 2^16, as is R + KX - k
+#pragma unroll
+    for (int k = 0; k < KX; k++) {
+      // L1 = |c0 + k - R| + |r - R|, the first term as the 16-bit absolute
+      // difference of c0 + KX and R + KX - k
+      const uint32_t l1 = __builtin_amdgcn_sad_u16(cx, (uint32_t)(R + KX - k), ly);
+      key[k] = k <= khi ? (acc[k] << 8) | l1 : 0xffffffffu;
+      kb32 = min(kb32, key[k]);
+    }
+    int bsel = KX;
+#pragma unroll
+    for (int k = KX - 1; k >= 0; k--) bsel = key[k] == kb32 ? k : bsel;
+    if (kb32 != 0xffffffffu) {
+      const unsigned long long idx = (unsigned long long)(r * s.span + c0 + bsel);
+      const unsigned long long key = ((unsigned long long)(kb32 >> 8) << keyshift_sad) |
+                                     ((unsigned long long)(kb32 & 0xffu) << keyshift_l1) | idx;
+      atomicMin(&best[b], key);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbv; b += blockDim.x) {
+    const unsigned long long key = best[b];
+    const int idx = (int)(key & ((1ull << keyshift_l1) - 1));
+    const int dy = idx / s.span - R, dx = idx - (idx / s.span) * s.span - R;
+    int8_t* mv = job.mv + ((size_t)by * Wb + bx0 + b) * 2;
+    mv[0] = (int8_t)dx;
+    mv[1] = (int8_t)dy;
+  }
+}
+
 template <int N, int KX, int ROWS>
 hipError_t launch_me_t(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
   const MeShape sh = me_shape(N, R, KX, g.nb, ROWS);
@@ -394,8 +682,43 @@ auto me_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<2, 1>
 #undef XV_ME_KX
 }
 
+template <int N, int KX>
+hipError_t launch_me_rp_t(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
+  const size_t lds = rp_lds_layout(N, rp_shape(N, R, KX, g.nb), g.nb).bytes;
+  static bool attr_set = false;
+  if (!attr_set && lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)me_rp_kernel<N, KX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  me_rp_kernel<N, KX><<<r.tiles, g.threads, lds, s>>>(r, R, g.nb);
+  return hipGetLastError();
+}
+
+// Calls f.template operator()<KX>() for the row-pair instance of g.kx.
+template <class F>
+auto rp_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<2>()) {
+  using Ret = decltype(f.template operator()<2>());
+  switch (g.kx) {
+    case 2: return f.template operator()<2>();
+    case 3: return f.template operator()<3>();
+    case 4: return f.template operator()<4>();
+    case 5: return f.template operator()<5>();
+    case 6: return f.template operator()<6>();
+    case 7: return f.template operator()<7>();
+    case 8: return f.template operator()<8>();
+    case 9: return f.template operator()<9>();
+    case 11: return f.template operator()<11>();
+    case 13: return f.template operator()<13>();
+    default: return (Ret)hipErrorInvalidValue;
+  }
+}
+
 template <int N>
 hipError_t launch_me_n(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
+  if (g.layout == XV_ME_ROW_PAIRS)
+    return rp_dispatch(g, [&]<int KX>() { return launch_me_rp_t<N, KX>(R, g, r, s); });
   if (g.kx < 2 || g.kx > 18 || (g.kx & 1)) return hipErrorInvalidValue;
   return me_dispatch(g, [&]<int KX, int ROWS>() { return launch_me_t<N, KX, ROWS>(R, g, r, s); });
 }
@@ -404,9 +727,14 @@ hipError_t launch_me_n(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t 
 template <int N>
 int me_vgprs_n(const MeGeom& g) {
   hipFuncAttributes a{};
-  const hipError_t e = me_dispatch(g, [&]<int KX, int ROWS>() {
-    return hipFuncGetAttributes(&a, (const void*)me_kernel<N, KX, ROWS>);
-  });
+  const hipError_t e =
+      g.layout == XV_ME_ROW_PAIRS
+          ? rp_dispatch(g, [&]<int KX>() {
+              return hipFuncGetAttributes(&a, (const void*)me_rp_kernel<N, KX>);
+            })
+          : me_dispatch(g, [&]<int KX, int ROWS>() {
+              return hipFuncGetAttributes(&a, (const void*)me_kernel<N, KX, ROWS>);
+            });
   return (e == hipSuccess && a.numRegs > 0) ? a.numRegs : 128;
 }
 
@@ -421,47 +749,62 @@ int me_vgprs(int N, const MeGeom& g) {
 
 }  // namespace
 
-// Whether a kernel instance exists for (KX, rows).
-bool me_instance_exists(int kx, int rows) {
-  if (kx < 2 || kx > 18 || (kx & 1)) return false;
-  if (rows >= 1 && rows <= 3) return true;
-  return rows == 5 && (kx == 2 || kx == 4);
+// Whether a kernel instance exists for the geometry's layout, KX and rows.
+bool me_instance_exists(const MeGeom& g) {
+  if (g.layout == XV_ME_ROW_PAIRS)
+    return g.rows == 1 && ((g.kx >= 2 && g.kx <= 9) || g.kx == 11 || g.kx == 13);
+  if (g.layout != XV_ME_COLUMN_PAIRS) return false;
+  if (g.kx < 2 || g.kx > 18 || (g.kx & 1)) return false;
+  if (g.rows >= 1 && g.rows <= 3) return true;
+  return g.rows == 5 && (g.kx == 2 || g.kx == 4);
 }
 
 size_t me_lds_bytes_for(int N, int R, const MeGeom& g) {
+  if (g.layout == XV_ME_ROW_PAIRS) return rp_lds_layout(N, rp_shape(N, R, g.kx, g.nb), g.nb).bytes;
   return me_lds_bytes(N, me_shape(N, R, g.kx, g.nb, g.rows), g.nb);
 }
 
 // Model of a CU (160 KB LDS, 4 SIMDs with 512 VGPRs per lane, at most 8
 // waves each) used to rank geometries.  Score = share of SAD instructions in
-// a lane's VALU work (rows N KX N/2 SADs against N + rows - 1 realigned
-// window rows of (KX+N)/2 - 1 realignments each) x share of useful
-// candidates (2R+1 of G KX columns, 2R+1 of rows * ceil((2R+1)/rows) rows) x
-// lane occupancy of the rounds of items x resident waves per SIMD
-// (saturating at 3).
+// a lane's VALU work x share of useful candidates x lane occupancy of the
+// waves that hold items x resident waves per SIMD (saturating at 3).  Per item
+// and channel, column pairs: rows N KX N/2 SADs against N + rows - 1 window
+// rows of (KX+N)/2 - 1 realignments; row pairs: N/2 KX N SADs and N/2
+// address updates.  Per item, about 40 + 6 x candidates instructions select
+// the best candidate.  Useful candidates: 2R+1 of G KX columns, and for
+// column pairs 2R+1 of rows * ceil((2R+1)/rows) rows.
 double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
   const int span = 2 * R + 1;
   const int kx = g.kx, th = g.threads;
   const int G = (span + kx - 1) / kx;
-  // per item and channel: rows * N window-row SAD passes of KX N/2 SADs
-  // against N + rows - 1 realigned window rows
-  const double sad = (double)g.rows * N * kx * N / 2;
-  const double perm = (double)(N + g.rows - 1) * ((kx + N) / 2 - 1);
-  const int dyp = (span + g.rows - 1) / g.rows;
-  const double eff = sad / (sad + perm) * (double)span / (double)(G * kx) *
-                     (double)span / (double)(g.rows * dyp);
-  const MeShape sh = me_shape(N, R, kx, g.nb, g.rows);
-  const size_t lds = me_lds_bytes(N, sh, g.nb);
+  const bool rp = g.layout == XV_ME_ROW_PAIRS;
+  const double sel = (40.0 + 6.0 * kx * g.rows) / 3.0;  // per channel of a 3-channel group
+  double eff;
+  int ipb;
+  if (rp) {
+    const double sad = (double)(N / 2) * kx * N;
+    eff = sad / (sad + N / 2 + sel) * (double)span / (double)(G * kx);
+    ipb = span * G;
+  } else {
+    const double sad = (double)g.rows * N * kx * N / 2;
+    const double perm = (double)(N + g.rows - 1) * ((kx + N) / 2 - 1);
+    const int dyp = (span + g.rows - 1) / g.rows;
+    eff = sad / (sad + perm + sel) * (double)span / (double)(G * kx) * (double)span /
+          (double)(g.rows * dyp);
+    ipb = dyp * G;
+  }
+  const size_t lds = me_lds_bytes_for(N, R, g);
   if (lds > 160 * 1024) return -1.0;
-  // lane occupancy over the runs of a block row: full runs of nb blocks and
-  // a last run of the remaining ones
+  // lane occupancy over the runs of a block row (full runs of nb blocks and
+  // a last run of the remaining ones): a wave with no item left exits, so
+  // only the idle lanes of the last busy wave of a run are lost
   const int wbk = std::max(1, width_blocks);
   const int runs = (wbk + g.nb - 1) / g.nb;
   double busy = 0.0, slots = 0.0;
   for (int r = 0; r < runs; r++) {
-    const int items = std::min(g.nb, wbk - r * g.nb) * sh.ipb;
+    const int items = std::min(g.nb, wbk - r * g.nb) * ipb;
     busy += items;
-    slots += (double)((items + th - 1) / th) * th;
+    slots += (double)((items + 63) / 64) * 64;
   }
   const double lane = busy / slots;
   const int wpg = th / 64;
@@ -478,21 +821,22 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
 std::vector<MeGeom> me_candidates(int N, int R, int width_blocks) {
   std::vector<MeGeom> v;
   const int cmax = std::max(1, std::min(16, width_blocks));
+  auto add = [&](const MeGeom& g) {
+    if (me_instance_exists(g) && me_lds_bytes_for(N, R, g) <= 96 * 1024) v.push_back(g);
+  };
   for (int rows : {1, 2, 3, 5})
     for (int kx = 2; kx <= 18; kx += 2)
       for (int c = 1; c <= cmax; c++)
-        for (int th = 64; th <= 512; th += 64) {
-          const MeGeom g{c, kx, th, rows};
-          if (me_instance_exists(kx, rows) && me_lds_bytes_for(N, R, g) <= 96 * 1024)
-            v.push_back(g);
-        }
+        for (int th = 64; th <= 512; th += 64) add(MeGeom{c, kx, th, rows, XV_ME_COLUMN_PAIRS});
+  for (int kx : {2, 3, 4, 5, 6, 7, 8, 9, 11, 13})
+    for (int c = 1; c <= cmax; c++)
+      for (int th = 64; th <= 512; th += 64) add(MeGeom{c, kx, th, 1, XV_ME_ROW_PAIRS});
   return v;
 }
 
-// Default geometry: the best model score (ties: more blocks per workgroup,
-// fewer redundant window loads).
+// Default geometry: the best model score (ties: more blocks per workgroup).
 MeGeom me_default_geometry(int N, int R, int max_nb) {
-  MeGeom best{1, 2, 256, 1};
+  MeGeom best{1, 2, 256, 1, XV_ME_COLUMN_PAIRS};
   double bs = -2.0;
   for (const MeGeom& g : me_candidates(N, R, max_nb)) {
     const double sc = me_model_score(N, R, g, max_nb);
@@ -510,8 +854,7 @@ int me_tiles_per_job(int Hb, int Wb, const MeGeom& g) {
 
 hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
   if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
-  if (g.threads <= 0 || g.threads > 512 || (g.threads & 63) || g.nb < 1 ||
-      !me_instance_exists(g.kx, g.rows))
+  if (g.threads <= 0 || g.threads > 512 || (g.threads & 63) || g.nb < 1 || !me_instance_exists(g))
     return hipErrorInvalidValue;
   if (me_lds_bytes_for(N, R, g) > 160 * 1024) return hipErrorInvalidValue;
   switch (N) {

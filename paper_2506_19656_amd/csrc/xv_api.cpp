@@ -888,7 +888,7 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
       search_range > 64)
     return fail(XV_EINVAL, "bad block or search range");
   if (!g || (g->blocks_per_wg == 0 && g->cands_per_lane == 0 && g->threads == 0 &&
-             g->rows_per_lane == 0)) {
+             g->rows_per_lane == 0 && g->layout == 0)) {
     std::lock_guard<std::mutex> lk(g_geom_mu);
     g_geom.erase({block, search_range});  // back to the model default
     return XV_OK;
@@ -898,15 +898,25 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
     if (g->blocks_per_wg) m.nb = g->blocks_per_wg;
     if (g->cands_per_lane) m.kx = g->cands_per_lane;
     if (g->threads) m.threads = g->threads;
+    if (g->layout) {
+      if (g->layout != m.layout && !g->rows_per_lane) m.rows = 1;
+      m.layout = g->layout;
+    }
     if (g->rows_per_lane) m.rows = g->rows_per_lane;
   }
+  if (m.layout != XV_ME_COLUMN_PAIRS && m.layout != XV_ME_ROW_PAIRS)
+    return fail(XV_EINVAL, "unknown window layout %d", m.layout);
   if (m.nb < 1 || m.nb > 64) return fail(XV_EINVAL, "blocks_per_wg out of range");
-  if (m.kx < 2 || m.kx > 18 || (m.kx & 1)) return fail(XV_EINVAL, "cands_per_lane must be even in 2..18");
   if (m.threads < 64 || m.threads > 512 || (m.threads & 63))
     return fail(XV_EINVAL, "threads must be a multiple of 64 in 64..512");
-  if (!me_instance_exists(m.kx, m.rows))
-    return fail(XV_EINVAL, "no kernel for %d candidates x %d rows per lane (rows 1..3 for any "
-                "even count 2..18; 5 rows for 2 or 4 candidates)", m.kx, m.rows);
+  if (!me_instance_exists(m))
+    return fail(XV_EINVAL,
+                m.layout == XV_ME_ROW_PAIRS
+                    ? "no row-pair kernel for %d candidates x %d rows per lane (one row; 2..9, "
+                      "11 or 13 candidates)"
+                    : "no column-pair kernel for %d candidates x %d rows per lane (rows 1..3 for "
+                      "any even count 2..18; 5 rows for 2 or 4 candidates)",
+                m.kx, m.rows);
   if (me_lds_bytes_for(block, search_range, m) > 160 * 1024)
     return fail(XV_EINVAL, "geometry needs more than 160 KB of LDS");
   std::lock_guard<std::mutex> lk(g_geom_mu);
@@ -924,6 +934,7 @@ int xv_get_me_geometry(int block, int search_range, int width_blocks, xv_me_geom
   g->cands_per_lane = m.kx;
   g->threads = m.threads;
   g->rows_per_lane = m.rows;
+  g->layout = m.layout;
   return XV_OK;
 }
 
@@ -972,15 +983,26 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
     });
     if (rc != XV_OK) return cleanup(rc);
   }
-  std::vector<MeGeom> cand = me_candidates(N, R, wb);
-  std::stable_sort(cand.begin(), cand.end(), [&](const MeGeom& a, const MeGeom& b) {
-    return me_model_score(N, R, a, wb) > me_model_score(N, R, b, wb);
-  });
+  // the model's best of each window layout, half of the timed set each (the
+  // model's scores are not comparable enough across layouts to rank them
+  // against each other)
+  std::vector<std::pair<double, MeGeom>> scored[2];
+  for (const MeGeom& g : me_candidates(N, R, wb))
+    scored[g.layout == XV_ME_ROW_PAIRS].push_back({me_model_score(N, R, g, wb), g});
   const size_t keep = (size_t)(max_candidates > 0 ? max_candidates : 512);
-  if (cand.size() > keep) cand.resize(keep);
+  std::vector<MeGeom> cand;
+  for (int l = 0; l < 2; l++) {
+    std::stable_sort(scored[l].begin(), scored[l].end(),
+                     [](const auto& a, const auto& b) { return a.first > b.first; });
+    const size_t other = scored[1 - l].size();
+    const size_t take = std::min(scored[l].size(), std::max(keep / 2 + keep % 2 * (l == 0),
+                                                            keep > other ? keep - other : 0));
+    for (size_t i = 0; i < take; i++) cand.push_back(scored[l][i].second);
+  }
   const MeGeom def = geometry_for(N, R, wb);
   if (std::find_if(cand.begin(), cand.end(), [&](const MeGeom& g) {
-        return g.nb == def.nb && g.kx == def.kx && g.threads == def.threads && g.rows == def.rows;
+        return g.nb == def.nb && g.kx == def.kx && g.threads == def.threads &&
+               g.rows == def.rows && g.layout == def.layout;
       }) == cand.end())
     cand.push_back(def);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1028,6 +1050,7 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
     out->cands_per_lane = best.kx;
     out->threads = best.threads;
     out->rows_per_lane = best.rows;
+    out->layout = best.layout;
   }
   if (best_ms) *best_ms = best_t;
   return XV_OK;

@@ -221,15 +221,16 @@ hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 
 struct MeGeom {
   int nb;       // blocks per workgroup along x
-  int kx;       // candidates per lane along x (even)
+  int kx;       // candidates per lane along x
   int threads;  // workgroup size
-  int rows;     // candidate rows per lane (1 or 2)
+  int rows;     // candidate rows per lane
+  int layout;   // XV_ME_COLUMN_PAIRS or XV_ME_ROW_PAIRS
 };
 MeGeom me_default_geometry(int N, int R, int max_nb = 16);
 double me_model_score(int N, int R, const MeGeom& g, int width_blocks);
 std::vector<MeGeom> me_candidates(int N, int R, int width_blocks);
 size_t me_lds_bytes_for(int N, int R, const MeGeom& g);
-bool me_instance_exists(int kx, int rows);
+bool me_instance_exists(const MeGeom& g);
 int me_tiles_per_job(int Hb, int Wb, const MeGeom& g);
 hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& d, hipStream_t s);
 

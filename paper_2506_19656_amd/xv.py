@@ -22,6 +22,7 @@ U16, F32 = 0, 1
 PAD_ZERO, PAD_REPEAT = 0, 1
 FILL_NEAREST, FILL_FORWARD = 0, 1
 FLAG_DROP_WORK = 1
+ME_COLUMN_PAIRS, ME_ROW_PAIRS = 1, 2
 MAX_BANDS, MAX_GROUPS = 64, 22
 K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS, K_BITS_WRITE, K_BITS_PARSE, \
     K_QUALITY = range(10)
@@ -68,7 +69,7 @@ class ExportC(C.Structure):
 
 class MeGeometryC(C.Structure):
     _fields_ = [("blocks_per_wg", C.c_int32), ("cands_per_lane", C.c_int32),
-                ("threads", C.c_int32), ("rows_per_lane", C.c_int32)]
+                ("threads", C.c_int32), ("rows_per_lane", C.c_int32), ("layout", C.c_int32)]
 
 
 class ProfileC(C.Structure):
@@ -351,8 +352,9 @@ def spectral_angle(orig, decoded, stream=None):
 
 
 def set_me_geometry(block: int, search_range: int, blocks_per_wg=0, cands_per_lane=0,
-                    threads=0, rows_per_lane=0):
-    g = MeGeometryC(blocks_per_wg, cands_per_lane, threads, rows_per_lane)
+                    threads=0, rows_per_lane=0, layout=0):
+    """xv_set_me_geometry; layout is ME_COLUMN_PAIRS or ME_ROW_PAIRS (0: default)."""
+    g = MeGeometryC(blocks_per_wg, cands_per_lane, threads, rows_per_lane, layout)
     _check(lib().xv_set_me_geometry(block, search_range, C.byref(g)))
 
 
@@ -360,7 +362,7 @@ def get_me_geometry(block: int, search_range: int, width_blocks: int = 0) -> dic
     g = MeGeometryC()
     _check(lib().xv_get_me_geometry(block, search_range, width_blocks, C.byref(g)))
     return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
-                threads=g.threads, rows_per_lane=g.rows_per_lane)
+                threads=g.threads, rows_per_lane=g.rows_per_lane, layout=g.layout)
 
 
 def autotune_me(cube, params: Params, stream=None, max_candidates: int = 0) -> dict:
@@ -373,7 +375,8 @@ def autotune_me(cube, params: Params, stream=None, max_candidates: int = 0) -> d
     _check(lib().xv_autotune_me(C.byref(cb), C.byref(pc), _stream_handle(stream), max_candidates,
                                 C.byref(g), C.byref(ms)))
     return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
-                threads=g.threads, rows_per_lane=g.rows_per_lane, kernel_ms=ms.value)
+                threads=g.threads, rows_per_lane=g.rows_per_lane, layout=g.layout,
+                kernel_ms=ms.value)
 
 
 def autotune_me_batch(cubes, params, stream=None, max_candidates: int = 0) -> dict:
@@ -387,7 +390,8 @@ def autotune_me_batch(cubes, params, stream=None, max_candidates: int = 0) -> di
     _check(lib().xv_autotune_me_batch(n, cbs, pcs, _stream_handle(stream), max_candidates,
                                       C.byref(g), C.byref(ms)))
     return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
-                threads=g.threads, rows_per_lane=g.rows_per_lane, kernel_ms=ms.value)
+                threads=g.threads, rows_per_lane=g.rows_per_lane, layout=g.layout,
+                kernel_ms=ms.value)
 
 
 def profile_enable(on: bool = True):

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(xvmod):
 
 def test_abi_version_and_status_strings(xvmod):
     L = xvmod.lib()
-    assert L.xv_abi_version() == 3
+    assert L.xv_abi_version() == 4
     assert L.xv_status_str(0) == b"ok"
     assert L.xv_status_str(-1) == b"invalid argument"
 
@@ -82,17 +82,35 @@ def test_null_handles(xvmod):
 
 
 def test_me_geometry_validation(xvmod):
-    with pytest.raises(xvmod.XvError):
-        xvmod.set_me_geometry(8, 8, cands_per_lane=3)
-    with pytest.raises(xvmod.XvError):
-        xvmod.set_me_geometry(8, 8, threads=1024)
+    col, row = xvmod.ME_COLUMN_PAIRS, xvmod.ME_ROW_PAIRS
+    bad = [dict(cands_per_lane=3, rows_per_lane=1, layout=col),   # column pairs: even counts
+           dict(cands_per_lane=2, rows_per_lane=4, layout=col),   # no 4-row instance
+           dict(cands_per_lane=6, rows_per_lane=5, layout=col),   # 5 rows: 2 or 4 columns
+           dict(cands_per_lane=10, rows_per_lane=1, layout=row),  # row pairs: 2..9, 11, 13
+           dict(cands_per_lane=3, rows_per_lane=2, layout=row),   # row pairs: one row
+           dict(cands_per_lane=3, rows_per_lane=1, layout=3),     # no such layout
+           dict(threads=1024), dict(threads=96), dict(blocks_per_wg=65)]
+    for kw in bad:
+        with pytest.raises(xvmod.XvError):
+            xvmod.set_me_geometry(8, 8, **kw)
     with pytest.raises(xvmod.XvError):
         xvmod.set_me_geometry(12, 8)
-    with pytest.raises(xvmod.XvError):
-        xvmod.set_me_geometry(8, 8, rows_per_lane=4)
-    g = xvmod.get_me_geometry(16, 32)
-    assert g["cands_per_lane"] % 2 == 0 and g["threads"] % 64 == 0 and g["blocks_per_wg"] >= 1
-    assert g["rows_per_lane"] in (1, 2, 3, 5)
+    try:
+        xvmod.set_me_geometry(8, 8, 3, 11, 192, 1, row)
+        assert xvmod.get_me_geometry(8, 8) == dict(blocks_per_wg=3, cands_per_lane=11, threads=192,
+                                                  rows_per_lane=1, layout=row)
+        xvmod.set_me_geometry(8, 8, 2, 6, 256, 3, col)
+        assert xvmod.get_me_geometry(8, 8)["layout"] == col
+    finally:
+        xvmod.set_me_geometry(8, 8)
+    for N in (4, 8, 16, 32):
+        g = xvmod.get_me_geometry(N, 16)
+        assert g["threads"] % 64 == 0 and g["blocks_per_wg"] >= 1
+        if g["layout"] == col:
+            assert g["cands_per_lane"] % 2 == 0 and g["rows_per_lane"] in (1, 2, 3, 5)
+        else:
+            assert g["layout"] == row and g["rows_per_lane"] == 1
+            assert g["cands_per_lane"] in (2, 3, 4, 5, 6, 7, 8, 9, 11, 13)
 
 
 def test_memory_record_and_release_without_device_work(xvmod):

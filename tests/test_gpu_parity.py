@@ -196,19 +196,27 @@ def test_motion_geometry_never_changes_outputs():
                                  (7, 10, 192, 1), (1, 2, 64, 2), (2, 18, 128, 2), (5, 8, 256, 2),
                                  (3, 6, 512, 2), (12, 12, 320, 2), (1, 2, 64, 3), (4, 6, 192, 3),
                                  (7, 12, 448, 3), (1, 2, 64, 5), (6, 4, 256, 5), (2, 2, 128, 5)]:
-            xv.set_me_geometry(8, 9, nb, kx, th, rows)
+            xv.set_me_geometry(8, 9, nb, kx, th, rows, xv.ME_COLUMN_PAIRS)
             got = xv.encode_cube(cube, p).host()
             assert np.array_equal(got["mvs"], base["mvs"]), (nb, kx, th, rows)
             assert np.array_equal(got["recon"], base["recon"]), (nb, kx, th, rows)
+        # row-pair layout: every instance, odd and even candidate counts
+        for nb, kx, th in [(1, 2, 64), (2, 13, 128), (5, 3, 256), (3, 11, 512), (7, 5, 192),
+                           (4, 7, 448), (12, 9, 320), (2, 4, 64), (3, 6, 128), (1, 8, 64)]:
+            xv.set_me_geometry(8, 9, nb, kx, th, 1, xv.ME_ROW_PAIRS)
+            got = xv.encode_cube(cube, p).host()
+            assert np.array_equal(got["mvs"], base["mvs"]), ("rows", nb, kx, th)
+            assert np.array_equal(got["recon"], base["recon"]), ("rows", nb, kx, th)
     finally:
         xv.set_me_geometry(8, 9)
-    # both kernel forms against the oracle at every block size, odd and even R
+    # every kernel form against the oracle at every block size, odd and even R
     for N, R in ((4, 3), (16, 8), (32, 5)):
         q = xv.Params(bit_depth=10, qp=22, block=N, search_range=R, gop=4)
         try:
-            for kx, rows in ((0, 1), (0, 2), (0, 3), (2, 5), (4, 5)):
-                xv.set_me_geometry(N, R, 0, kx, 0, rows)
-                check_cube(f"rows{rows}_kx{kx}_N{N}_R{R}", host, q)
+            for kx, rows, lay in ((2, 1, 1), (6, 2, 1), (4, 3, 1), (2, 5, 1), (4, 5, 1),
+                                  (3, 1, 2), (11, 1, 2), (2, 1, 2)):
+                xv.set_me_geometry(N, R, 0, kx, 0, rows, lay)
+                check_cube(f"layout{lay}_rows{rows}_kx{kx}_N{N}_R{R}", host, q)
         finally:
             xv.set_me_geometry(N, R)
 
@@ -220,6 +228,7 @@ def test_batch_tuner_installs_a_geometry_that_keeps_outputs():
     try:
         g = xv.autotune_me_batch(cubes, params, max_candidates=6)
         assert g["rows_per_lane"] in (1, 2, 3, 5) and g["kernel_ms"] > 0
+        assert g["layout"] in (xv.ME_COLUMN_PAIRS, xv.ME_ROW_PAIRS)
         assert xv.get_me_geometry(16, 6)["threads"] == g["threads"]
         after = [e.host() for e in xv.encode_batch(cubes, params)]
         for a, b in zip(before, after):
