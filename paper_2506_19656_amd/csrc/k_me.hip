@@ -214,6 +214,7 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
   }
   const int keyshift_sad = R <= 32 ? 21 : 23;
   const int keyshift_l1 = R <= 32 ? 13 : 15;
+  const float inv_ndy = 1.0f / (float)ndy;
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
     int b = 0, rem = it, glo_c = 0;
     for (;; b++) {
@@ -223,7 +224,9 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
       if (rem < n || b + 1 >= nbv) break;
       rem -= n;
     }
-    const int gq = rem / ndy;
+    // rem / ndy in binary32 (exact: quotient below 2R + 2, distance from an
+    // integer at least 1/(2 ndy))
+    const int gq = (int)(((float)rem + 0.5f) * inv_ndy);
     const int gxi = glo_c + gq;
     const int dy0 = ROWS * (glo_r + rem - gq * ndy);
     uint32_t acc[ROWS][KX];
@@ -316,16 +319,18 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
     const int khi = min(s.span - 1, Wp - N - x0 + R) - c0;      // the padded picture
     uint32_t kb32 = 0xffffffffu;
     int bsel = -1;
+    const uint32_t cx = (uint32_t)(c0 + KX);  // below 2^16, as is R + KX - k
 #pragma unroll
     for (int h = 0; h < ROWS; h++) {
       const int dyv = dy0 + h - R;
       const bool yok = dy0 + h < s.span && (y0 + dyv >= 0) && (y0 + dyv + N <= Hp);
+      const uint32_t ly = (uint32_t)abs(dyv);
 #pragma unroll
       for (int k = 0; k < KX; k++) {
-        const bool ok = yok && k >= klo && k <= khi;
-        const uint32_t l1 = (uint32_t)(abs(c0 + k - R) + abs(dyv));
+        // L1 = |c0 + k - R| + |dy|, the first term as a 16-bit absolute difference
+        const uint32_t l1 = __builtin_amdgcn_sad_u16(cx, (uint32_t)(R + KX - k), ly);
         const uint32_t key = (acc[h][k] << 8) | l1;
-        const bool take = ok && key < kb32;
+        const bool take = yok && k >= klo && k <= khi && key < kb32;
         kb32 = take ? key : kb32;
         bsel = take ? h * KX + k : bsel;
       }
@@ -605,20 +610,20 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
     // (SAD, L1, dy, dx) among them.
     const int khi = chi - c0;
     const uint32_t ly = (uint32_t)abs(r - R);
-    uint32_t key[KX], kb32 = 0xffffffffu;
+    uint32_t kb32 = 0xffffffffu;
+    int bsel = -1;
     const uint32_t cx = (uint32_t)(c0 + KX);  // below 2^16, as is R + KX - k
 #pragma unroll
     for (int k = 0; k < KX; k++) {
       // L1 = |c0 + k - R| + |r - R|, the first term as the 16-bit absolute
       // difference of c0 + KX and R + KX - k
       const uint32_t l1 = __builtin_amdgcn_sad_u16(cx, (uint32_t)(R + KX - k), ly);
-      key[k] = k <= khi ? (acc[k] << 8) | l1 : 0xffffffffu;
-      kb32 = min(kb32, key[k]);
+      const uint32_t key = (acc[k] << 8) | l1;
+      const bool take = k <= khi && key < kb32;
+      kb32 = take ? key : kb32;
+      bsel = take ? k : bsel;
     }
-    int bsel = KX;
-#pragma unroll
-    for (int k = KX - 1; k >= 0; k--) bsel = key[k] == kb32 ? k : bsel;
-    if (kb32 != 0xffffffffu) {
+    if (bsel >= 0) {
       const unsigned long long idx = (unsigned long long)(r * s.span + c0 + bsel);
       const unsigned long long key = ((unsigned long long)(kb32 >> 8) << keyshift_sad) |
                                      ((unsigned long long)(kb32 & 0xffu) << keyshift_l1) | idx;
