@@ -54,7 +54,9 @@ def _measured_traffic():
         return None
     out = {}
     for k, v in t["per_launch_bytes"].items():
-        out.setdefault(k.split("<")[0], []).append(float(v))
+        name = k.split("<")[0]
+        # the two motion-search window layouts are one kernel class
+        out.setdefault("me" if name in ("me_kernel", "me_rp_kernel") else name, []).append(float(v))
     # each kernel launches equally often per block size in the sweep step
     return {k: sum(v) / len(v) for k, v in out.items()}
 
@@ -467,11 +469,10 @@ def main():
         me_avg_ms = me["ms"] / max(1, me["launches"])
         me_terms = me["work"] / max(1, me["launches"])
         achieved = me_terms / (me_avg_ms * 1e-3) / 1e12
-        line["roofline"] = {"kernel": "me_kernel (motion search)", "bound": "alu",
+        line["roofline"] = {"kernel": "motion search (me_rp_kernel / me_kernel)", "bound": "alu",
                             "achieved": round(achieved, 3), "peak": round(SAD_PEAK_TTERMS, 2),
                             "unit": "T SAD-terms/s", "frac": round(achieved / SAD_PEAK_TTERMS, 4),
-                            "traffic": (round(traffic["me_kernel"])
-                                        if "me_kernel" in traffic else None),
+                            "traffic": round(traffic["me"]) if "me" in traffic else None,
                             "traffic_unit": "bytes per launch",
                             "avg_launch_ms": round(me_avg_ms, 4),
                             "launches": me["launches"], "terms_per_launch": me_terms,
