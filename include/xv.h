@@ -281,9 +281,13 @@ int xv_server_destroy(xv_server* sv);
  * number of candidate columns (2..18) on 1, 2, 3 or (for 2 or 4 columns) 5
  * candidate rows.  Row pairs: a dword holds two vertically adjacent
  * samples (twice the LDS); a lane takes 2..9, 11 or 13 candidate columns on
- * one candidate row. */
+ * one candidate row.  Row pairs by channel: the same with the three
+ * channels staged one after another (a third of the LDS); a workgroup's
+ * items, blocks_per_wg x (2R+1) x ceil((2R+1)/cands_per_lane), must not
+ * exceed 3 x threads. */
 #define XV_ME_COLUMN_PAIRS 1
 #define XV_ME_ROW_PAIRS 2
+#define XV_ME_ROW_PAIRS_BY_CHANNEL 3
 
 /* Geometry of the motion-search kernel for one (N, R): blocks per
  * workgroup along x, candidates per lane along x, threads per workgroup

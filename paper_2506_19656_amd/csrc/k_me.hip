@@ -24,6 +24,10 @@
 #include "xv_internal.h"
 
 #include <algorithm>
+
+#ifndef XV_INLINE
+#define XV_INLINE __attribute__((always_inline))
+#endif
 #include <vector>
 
 namespace xv {
@@ -378,16 +382,21 @@ __host__ __device__ inline RpShape rp_shape(int N, int R, int kx, int nb) {
   return s;
 }
 
-// LDS of a workgroup, in dwords: pair rows [3][xr][pitch], paired current
-// blocks [3][nb][N/2][N] from a 16-byte boundary, nb 64-bit keys.
-__host__ __device__ inline MeLds rp_lds_layout(int N, const RpShape& s, int nb) {
+// LDS of a workgroup, in dwords: pair rows [C][xr][pitch], paired current
+// blocks [C][nb][N/2][N] from a 16-byte boundary, nb 64-bit keys; C = 3
+// channels resident at once, or 1 when they are staged one after another.
+__host__ __device__ inline MeLds rp_lds_layout(int N, const RpShape& s, int nb, int chans) {
   MeLds l;
-  const size_t x = (size_t)3 * s.xr * s.pitch;
+  const size_t x = (size_t)chans * s.xr * s.pitch;
   l.cur = (x + 3) & ~(size_t)3;
-  l.best = l.cur + (size_t)3 * nb * (N / 2) * N;  // a multiple of 4 past cur
+  l.best = l.cur + (size_t)chans * nb * (N / 2) * N;  // a multiple of 4 past cur
   l.bytes = l.best * 4 + (size_t)nb * 8;
   return l;
 }
+
+// Items per thread held across the channels when they are staged one after
+// another.
+constexpr int kRpRounds = 3;
 
 // Stages the pair rows of the window.  A thread owns column pair m (window
 // columns 2m, 2m+1 at picture columns gx0 + 2m, gx0 + 2m + 1) and walks the
@@ -485,7 +494,11 @@ __device__ inline void stage_row_pairs(uint32_t* X, const uint16_t* ref, const R
 template <int N>
 constexpr int kRpUnroll = N <= 16 ? N / 2 : 2;
 
-template <int N, int KX>
+// Row-pair motion search.  RND = 0: the three channels' windows are
+// resident together and a thread takes its items one at a time.  RND > 0:
+// the channels are staged one after another into a third of the LDS, and a
+// thread keeps the sums of its (at most RND) items across them.
+template <int N, int KX, int RND>
 __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, int nb) {
   extern __shared__ __align__(16) uint32_t lds[];
   int tl;
@@ -499,36 +512,39 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
   const int nbv = min(nb, Wb - bx0);
   const int nch = job.nch;
   const RpShape s = rp_shape(N, R, KX, nb);
-  const MeLds ll = rp_lds_layout(N, s, nb);
+  const MeLds ll = rp_lds_layout(N, s, nb, RND == 0 ? 3 : 1);
   uint32_t* X = lds;
   uint32_t* curx = lds + ll.cur;
   unsigned long long* best = (unsigned long long*)(lds + ll.best);
-
   const int gy0 = by * N - R, gx0 = bx0 * N - R;
-  if ((gx0 & 1) == 0)
-    stage_row_pairs<true>(X, job.ref, s, nch, gx0, gy0, Hp, Wp);
-  else
-    stage_row_pairs<false>(X, job.ref, s, nch, gx0, gy0, Hp, Wp);
-  {
-    // current blocks: dword (c[2j][x], c[2j+1][x]) at [ch][b][j][x]
+  const uint32_t plane_bytes = 2u * (uint32_t)Hp * (uint32_t)Wp;
+
+  // Stages channels c0 .. c0 + cn - 1 into LDS slots 0 .. cn - 1: the pair
+  // rows of the window and the current blocks, dword (c[2j][x], c[2j+1][x])
+  // at [slot][b][j][x].
+  auto stage = [&](int c0, int cn) XV_INLINE {
+    const uint16_t* ref = (const uint16_t*)((gchar*)job.ref + (size_t)c0 * plane_bytes);
+    if ((gx0 & 1) == 0)
+      stage_row_pairs<true>(X, ref, s, cn, gx0, gy0, Hp, Wp);
+    else
+      stage_row_pairs<false>(X, ref, s, cn, gx0, gy0, Hp, Wp);
     constexpr int CM = N / 2;  // column pairs of a block row
     const int tasks = nbv * (N / 2) * CM;
-    for (int ch = 0; ch < nch; ch++)
-    for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
-      const int m = t % CM, q = t / CM;
-      const int j = q % (N / 2), b = q / (N / 2);
-      const uint32_t off = 2u * __umul24((uint32_t)(ch * Hp + by * N + 2 * j), (uint32_t)Wp) +
-                           2u * (uint32_t)((bx0 + b) * N + 2 * m);
-      const uint32_t a0 = *(const __attribute__((address_space(1))) uint32_t*)((gchar*)job.cur + off);
-      const uint32_t a1 = *(const __attribute__((address_space(1))) uint32_t*)((gchar*)job.cur + off +
-                                                                               2u * (uint32_t)Wp);
-      uint32_t* co = curx + ((ch * nb + b) * (N / 2) + j) * N + 2 * m;
-      co[0] = (a0 & 0xffffu) | (a1 << 16);
-      co[1] = (a0 >> 16) | (a1 & 0xffff0000u);
-    }
-  }
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) best[b] = ~0ull;
-  __syncthreads();
+    for (int ch = 0; ch < cn; ch++)
+      for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+        const int m = t % CM, q = t / CM;
+        const int j = q % (N / 2), b = q / (N / 2);
+        const uint32_t off =
+            2u * __umul24((uint32_t)((c0 + ch) * Hp + by * N + 2 * j), (uint32_t)Wp) +
+            2u * (uint32_t)((bx0 + b) * N + 2 * m);
+        const uint32_t a0 = *(const __attribute__((address_space(1))) uint32_t*)((gchar*)job.cur + off);
+        const uint32_t a1 = *(const __attribute__((address_space(1))) uint32_t*)(
+            (gchar*)job.cur + (off + 2u * (uint32_t)Wp));
+        uint32_t* co = curx + ((ch * nb + b) * (N / 2) + j) * N + 2 * m;
+        co[0] = (a0 & 0xffffu) | (a1 << 16);
+        co[1] = (a0 >> 16) | (a1 & 0xffff0000u);
+      }
+  };
 
   // Items: (block b, group g of KX candidate columns from the block's first
   // in-picture column, candidate row r), r fastest so that neighbouring
@@ -545,13 +561,14 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
   const int keyshift_sad = R <= 32 ? 21 : 23;
   const int keyshift_l1 = R <= 32 ? 13 : 15;
   const float inv_nr = 1.0f / (float)nr;
-  constexpr int NP = KX + N - 1;
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    // The wave's items are consecutive: find the block of its first item
-    // with wave-uniform (scalar) arithmetic, then step each lane on from
-    // there, rarely more than once.
+
+  // (b, r, c0, chi) of item it.  The items of a wave are consecutive: the
+  // block of its first item is found with wave-uniform (scalar) arithmetic,
+  // then each lane steps on from there, rarely more than once.
+  auto decode = [&](int it, int& b, int& r, int& c0, int& chi) XV_INLINE {
     const int it0 = __builtin_amdgcn_readfirstlane(it);
-    int b = 0, start = 0, clo, chi, n;
+    int start = 0, clo, n;
+    b = 0;
     for (;; b++) {
       const int x0 = (bx0 + b) * N;
       clo = max(0, R - x0);
@@ -573,27 +590,33 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
     // below 2R + 2 <= 130 with a relative error of a few 2^-24, and its
     // distance from an integer is at least 1/(2 nr) >= 1/258
     const int g = (int)(((float)rem + 0.5f) * inv_nr);
-    const int r = rlo + rem - g * nr;
-    const int c0 = clo + g * KX;
-    uint32_t acc[KX];
-#pragma unroll
-    for (int k = 0; k < KX; k++) acc[k] = 0;
-    for (int ch = 0; ch < nch; ch++) {
-      const int xbase = (ch * s.xr + r) * s.pitch + b * N + c0;
-      const u32x4_l* cp = (const u32x4_l*)(curx + (ch * nb + b) * (N / 2) * N);
+    r = rlo + rem - g * nr;
+    c0 = clo + g * KX;
+  };
+
+  // acc[k] += SAD of candidate (r, c0 + k) of block b over the channel in
+  // LDS slot sl.  A pair row is taken in chunks of CW columns, which bounds
+  // the registers of N = 32.
+  auto accumulate = [&](int sl, int b, int r, int c0, uint32_t(&acc)[KX]) XV_INLINE {
+    constexpr int CW = N < 16 ? N : 16;  // columns per chunk
+    constexpr int NQ = KX + CW - 1;      // window dwords per chunk
+    const int xbase = (sl * s.xr + r) * s.pitch + b * N + c0;
+    const u32x4_l* cp = (const u32x4_l*)(curx + (sl * nb + b) * (N / 2) * N);
 #pragma unroll kRpUnroll<N>
-      for (int j = 0; j < N / 2; j++) {
-        uint32_t P[NP], C[N];
-        // One base per pair row and immediate offsets for its NP dwords; the
+    for (int j = 0; j < N / 2; j++) {
+#pragma unroll
+      for (int cc = 0; cc < N / CW; cc++) {
+        uint32_t P[NQ], C[CW];
+        // One base per pair row and immediate offsets for its dwords; the
         // empty asm keeps the compiler from strength-reducing every load
         // address into an induction variable of its own.
         int xo = xbase + 2 * j * s.pitch;
         asm volatile("" : "+v"(xo));
 #pragma unroll
-        for (int q = 0; q < NP; q++) P[q] = X[xo + q];
+        for (int q = 0; q < NQ; q++) P[q] = X[xo + cc * CW + q];
 #pragma unroll
-        for (int q = 0; q < N / 4; q++) {
-          const u32x4_l c4 = cp[j * (N / 4) + q];
+        for (int q = 0; q < CW / 4; q++) {
+          const u32x4_l c4 = cp[j * (N / 4) + cc * (CW / 4) + q];
           C[4 * q] = c4.x;
           C[4 * q + 1] = c4.y;
           C[4 * q + 2] = c4.z;
@@ -602,12 +625,18 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
 #pragma unroll
         for (int k = 0; k < KX; k++)
 #pragma unroll
-          for (int x = 0; x < N; x++) acc[k] = __builtin_amdgcn_sad_u16(P[k + x], C[x], acc[k]);
+          for (int x = 0; x < CW; x++) acc[k] = __builtin_amdgcn_sad_u16(P[k + x], C[x], acc[k]);
+        // keep the next chunk's loads after these sums: hoisting them costs
+        // registers, hence waves, and other waves hide the LDS latency
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-    // The item's candidates share row r and are visited in increasing dx, so
-    // a strict < over (SAD << 8 | L1) keeps the lexicographic minimum of
-    // (SAD, L1, dy, dx) among them.
+  };
+
+  // The item's candidates share row r and are visited in increasing dx, so
+  // a strict < over (SAD << 8 | L1) keeps the lexicographic minimum of
+  // (SAD, L1, dy, dx) among them; its full key goes to the block's LDS min.
+  auto select = [&](int b, int r, int c0, int chi, const uint32_t(&acc)[KX]) XV_INLINE {
     const int khi = chi - c0;
     const uint32_t ly = (uint32_t)abs(r - R);
     uint32_t kb32 = 0xffffffffu;
@@ -629,6 +658,44 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
                                      ((unsigned long long)(kb32 & 0xffu) << keyshift_l1) | idx;
       atomicMin(&best[b], key);
     }
+  };
+
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) best[b] = ~0ull;
+  if constexpr (RND == 0) {
+    stage(0, nch);
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+      int b, r, c0, chi;
+      decode(it, b, r, c0, chi);
+      uint32_t acc[KX];
+#pragma unroll
+      for (int k = 0; k < KX; k++) acc[k] = 0;
+      for (int ch = 0; ch < nch; ch++) accumulate(ch, b, r, c0, acc);
+      select(b, r, c0, chi, acc);
+    }
+  } else {
+    // the host admits a geometry only if every workgroup's items fit in RND
+    // rounds of its threads
+    int ib[RND], ir[RND], ic[RND], ih[RND];
+    uint32_t acc[RND][KX];
+#pragma unroll
+    for (int u = 0; u < RND; u++) {
+      const int it = threadIdx.x + u * blockDim.x;
+      if (it < items) decode(it, ib[u], ir[u], ic[u], ih[u]);
+#pragma unroll
+      for (int k = 0; k < KX; k++) acc[u][k] = 0;
+    }
+    for (int ch = 0; ch < nch; ch++) {
+      if (ch > 0) __syncthreads();  // every read of the previous channel done
+      stage(ch, 1);
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < RND; u++)
+        if (threadIdx.x + u * blockDim.x < items) accumulate(0, ib[u], ir[u], ic[u], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < RND; u++)
+      if (threadIdx.x + u * blockDim.x < items) select(ib[u], ir[u], ic[u], ih[u], acc[u]);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < nbv; b += blockDim.x) {
@@ -687,17 +754,17 @@ auto me_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<2, 1>
 #undef XV_ME_KX
 }
 
-template <int N, int KX>
+template <int N, int KX, int RND>
 hipError_t launch_me_rp_t(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
-  const size_t lds = rp_lds_layout(N, rp_shape(N, R, KX, g.nb), g.nb).bytes;
+  const size_t lds = rp_lds_layout(N, rp_shape(N, R, KX, g.nb), g.nb, RND == 0 ? 3 : 1).bytes;
   static bool attr_set = false;
   if (!attr_set && lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)me_rp_kernel<N, KX>,
+    hipError_t e = hipFuncSetAttribute((const void*)me_rp_kernel<N, KX, RND>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  me_rp_kernel<N, KX><<<r.tiles, g.threads, lds, s>>>(r, R, g.nb);
+  me_rp_kernel<N, KX, RND><<<r.tiles, g.threads, lds, s>>>(r, R, g.nb);
   return hipGetLastError();
 }
 
@@ -723,7 +790,9 @@ auto rp_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<2>())
 template <int N>
 hipError_t launch_me_n(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
   if (g.layout == XV_ME_ROW_PAIRS)
-    return rp_dispatch(g, [&]<int KX>() { return launch_me_rp_t<N, KX>(R, g, r, s); });
+    return rp_dispatch(g, [&]<int KX>() { return launch_me_rp_t<N, KX, 0>(R, g, r, s); });
+  if (g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL)
+    return rp_dispatch(g, [&]<int KX>() { return launch_me_rp_t<N, KX, kRpRounds>(R, g, r, s); });
   if (g.kx < 2 || g.kx > 18 || (g.kx & 1)) return hipErrorInvalidValue;
   return me_dispatch(g, [&]<int KX, int ROWS>() { return launch_me_t<N, KX, ROWS>(R, g, r, s); });
 }
@@ -735,7 +804,11 @@ int me_vgprs_n(const MeGeom& g) {
   const hipError_t e =
       g.layout == XV_ME_ROW_PAIRS
           ? rp_dispatch(g, [&]<int KX>() {
-              return hipFuncGetAttributes(&a, (const void*)me_rp_kernel<N, KX>);
+              return hipFuncGetAttributes(&a, (const void*)me_rp_kernel<N, KX, 0>);
+            })
+      : g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL
+          ? rp_dispatch(g, [&]<int KX>() {
+              return hipFuncGetAttributes(&a, (const void*)me_rp_kernel<N, KX, kRpRounds>);
             })
           : me_dispatch(g, [&]<int KX, int ROWS>() {
               return hipFuncGetAttributes(&a, (const void*)me_kernel<N, KX, ROWS>);
@@ -756,7 +829,7 @@ int me_vgprs(int N, const MeGeom& g) {
 
 // Whether a kernel instance exists for the geometry's layout, KX and rows.
 bool me_instance_exists(const MeGeom& g) {
-  if (g.layout == XV_ME_ROW_PAIRS)
+  if (g.layout == XV_ME_ROW_PAIRS || g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL)
     return g.rows == 1 && ((g.kx >= 2 && g.kx <= 9) || g.kx == 11 || g.kx == 13);
   if (g.layout != XV_ME_COLUMN_PAIRS) return false;
   if (g.kx < 2 || g.kx > 18 || (g.kx & 1)) return false;
@@ -765,8 +838,24 @@ bool me_instance_exists(const MeGeom& g) {
 }
 
 size_t me_lds_bytes_for(int N, int R, const MeGeom& g) {
-  if (g.layout == XV_ME_ROW_PAIRS) return rp_lds_layout(N, rp_shape(N, R, g.kx, g.nb), g.nb).bytes;
+  if (g.layout == XV_ME_ROW_PAIRS)
+    return rp_lds_layout(N, rp_shape(N, R, g.kx, g.nb), g.nb, 3).bytes;
+  if (g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL)
+    return rp_lds_layout(N, rp_shape(N, R, g.kx, g.nb), g.nb, 1).bytes;
   return me_lds_bytes(N, me_shape(N, R, g.kx, g.nb, g.rows), g.nb);
+}
+
+// Whether the geometry can run (N, R): its LDS fits a CU, and with the
+// channels staged one after another every workgroup's items (at most nb
+// blocks x 2R+1 rows x ceil((2R+1)/KX) column groups) fit in the rounds a
+// thread holds.
+bool me_geometry_fits(int N, int R, const MeGeom& g) {
+  if (me_lds_bytes_for(N, R, g) > 160 * 1024) return false;
+  if (g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL) {
+    const long span = 2L * R + 1, groups = (span + g.kx - 1) / g.kx;
+    if ((long)g.nb * span * groups > (long)kRpRounds * g.threads) return false;
+  }
+  return true;
 }
 
 // Model of a CU (160 KB LDS, 4 SIMDs with 512 VGPRs per lane, at most 8
@@ -782,7 +871,7 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
   const int span = 2 * R + 1;
   const int kx = g.kx, th = g.threads;
   const int G = (span + kx - 1) / kx;
-  const bool rp = g.layout == XV_ME_ROW_PAIRS;
+  const bool rp = g.layout == XV_ME_ROW_PAIRS || g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL;
   const double sel = (40.0 + 6.0 * kx * g.rows) / 3.0;  // per channel of a 3-channel group
   double eff;
   int ipb;
@@ -799,7 +888,7 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
     ipb = dyp * G;
   }
   const size_t lds = me_lds_bytes_for(N, R, g);
-  if (lds > 160 * 1024) return -1.0;
+  if (!me_geometry_fits(N, R, g)) return -1.0;
   // lane occupancy over the runs of a block row (full runs of nb blocks and
   // a last run of the remaining ones): a wave with no item left exits, so
   // only the idle lanes of the last busy wave of a run are lost
@@ -827,15 +916,17 @@ std::vector<MeGeom> me_candidates(int N, int R, int width_blocks) {
   std::vector<MeGeom> v;
   const int cmax = std::max(1, std::min(16, width_blocks));
   auto add = [&](const MeGeom& g) {
-    if (me_instance_exists(g) && me_lds_bytes_for(N, R, g) <= 96 * 1024) v.push_back(g);
+    if (me_instance_exists(g) && me_geometry_fits(N, R, g) && me_lds_bytes_for(N, R, g) <= 96 * 1024)
+      v.push_back(g);
   };
   for (int rows : {1, 2, 3, 5})
     for (int kx = 2; kx <= 18; kx += 2)
       for (int c = 1; c <= cmax; c++)
         for (int th = 64; th <= 512; th += 64) add(MeGeom{c, kx, th, rows, XV_ME_COLUMN_PAIRS});
-  for (int kx : {2, 3, 4, 5, 6, 7, 8, 9, 11, 13})
-    for (int c = 1; c <= cmax; c++)
-      for (int th = 64; th <= 512; th += 64) add(MeGeom{c, kx, th, 1, XV_ME_ROW_PAIRS});
+  for (int lay : {XV_ME_ROW_PAIRS, XV_ME_ROW_PAIRS_BY_CHANNEL})
+    for (int kx : {2, 3, 4, 5, 6, 7, 8, 9, 11, 13})
+      for (int c = 1; c <= cmax; c++)
+        for (int th = 64; th <= 512; th += 64) add(MeGeom{c, kx, th, 1, lay});
   return v;
 }
 
@@ -861,7 +952,7 @@ hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& r, hipStre
   if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
   if (g.threads <= 0 || g.threads > 512 || (g.threads & 63) || g.nb < 1 || !me_instance_exists(g))
     return hipErrorInvalidValue;
-  if (me_lds_bytes_for(N, R, g) > 160 * 1024) return hipErrorInvalidValue;
+  if (!me_geometry_fits(N, R, g)) return hipErrorInvalidValue;
   switch (N) {
     case 4: return launch_me_n<4>(R, g, r, s);
     case 8: return launch_me_n<8>(R, g, r, s);

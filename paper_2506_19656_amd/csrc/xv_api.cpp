@@ -904,14 +904,15 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
     }
     if (g->rows_per_lane) m.rows = g->rows_per_lane;
   }
-  if (m.layout != XV_ME_COLUMN_PAIRS && m.layout != XV_ME_ROW_PAIRS)
+  if (m.layout != XV_ME_COLUMN_PAIRS && m.layout != XV_ME_ROW_PAIRS &&
+      m.layout != XV_ME_ROW_PAIRS_BY_CHANNEL)
     return fail(XV_EINVAL, "unknown window layout %d", m.layout);
   if (m.nb < 1 || m.nb > 64) return fail(XV_EINVAL, "blocks_per_wg out of range");
   if (m.threads < 64 || m.threads > 512 || (m.threads & 63))
     return fail(XV_EINVAL, "threads must be a multiple of 64 in 64..512");
   if (!me_instance_exists(m))
     return fail(XV_EINVAL,
-                m.layout == XV_ME_ROW_PAIRS
+                m.layout != XV_ME_COLUMN_PAIRS
                     ? "no row-pair kernel for %d candidates x %d rows per lane (one row; 2..9, "
                       "11 or 13 candidates)"
                     : "no column-pair kernel for %d candidates x %d rows per lane (rows 1..3 for "
@@ -919,6 +920,8 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g) {
                 m.kx, m.rows);
   if (me_lds_bytes_for(block, search_range, m) > 160 * 1024)
     return fail(XV_EINVAL, "geometry needs more than 160 KB of LDS");
+  if (!me_geometry_fits(block, search_range, m))
+    return fail(XV_EINVAL, "a workgroup's items exceed 3 rounds of its threads");
   std::lock_guard<std::mutex> lk(g_geom_mu);
   g_geom[{block, search_range}] = m;
   return XV_OK;
@@ -983,21 +986,30 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
     });
     if (rc != XV_OK) return cleanup(rc);
   }
-  // the model's best of each window layout, half of the timed set each (the
-  // model's scores are not comparable enough across layouts to rank them
-  // against each other)
-  std::vector<std::pair<double, MeGeom>> scored[2];
+  // the model's best of each window layout, an equal share of the timed set
+  // each (the model's scores are not comparable enough across layouts to
+  // rank them against each other); a share a layout cannot fill goes to the
+  // others
+  constexpr int kLayouts = 3;  // XV_ME_COLUMN_PAIRS .. XV_ME_ROW_PAIRS_BY_CHANNEL
+  std::vector<std::pair<double, MeGeom>> scored[kLayouts];
   for (const MeGeom& g : me_candidates(N, R, wb))
-    scored[g.layout == XV_ME_ROW_PAIRS].push_back({me_model_score(N, R, g, wb), g});
+    scored[g.layout - 1].push_back({me_model_score(N, R, g, wb), g});
   const size_t keep = (size_t)(max_candidates > 0 ? max_candidates : 512);
+  size_t share[kLayouts] = {0, 0, 0};
+  for (size_t left = keep, open = kLayouts; left > 0 && open > 0;) {
+    open = 0;
+    for (int l = 0; l < kLayouts && left > 0; l++)
+      if (share[l] < scored[l].size()) {
+        share[l]++;
+        left--;
+        open++;
+      }
+  }
   std::vector<MeGeom> cand;
-  for (int l = 0; l < 2; l++) {
+  for (int l = 0; l < kLayouts; l++) {
     std::stable_sort(scored[l].begin(), scored[l].end(),
                      [](const auto& a, const auto& b) { return a.first > b.first; });
-    const size_t other = scored[1 - l].size();
-    const size_t take = std::min(scored[l].size(), std::max(keep / 2 + keep % 2 * (l == 0),
-                                                            keep > other ? keep - other : 0));
-    for (size_t i = 0; i < take; i++) cand.push_back(scored[l][i].second);
+    for (size_t i = 0; i < share[l]; i++) cand.push_back(scored[l][i].second);
   }
   const MeGeom def = geometry_for(N, R, wb);
   if (std::find_if(cand.begin(), cand.end(), [&](const MeGeom& g) {

@@ -224,12 +224,13 @@ struct MeGeom {
   int kx;       // candidates per lane along x
   int threads;  // workgroup size
   int rows;     // candidate rows per lane
-  int layout;   // XV_ME_COLUMN_PAIRS or XV_ME_ROW_PAIRS
+  int layout;   // XV_ME_COLUMN_PAIRS, XV_ME_ROW_PAIRS or XV_ME_ROW_PAIRS_BY_CHANNEL
 };
 MeGeom me_default_geometry(int N, int R, int max_nb = 16);
 double me_model_score(int N, int R, const MeGeom& g, int width_blocks);
 std::vector<MeGeom> me_candidates(int N, int R, int width_blocks);
 size_t me_lds_bytes_for(int N, int R, const MeGeom& g);
+bool me_geometry_fits(int N, int R, const MeGeom& g);
 bool me_instance_exists(const MeGeom& g);
 int me_tiles_per_job(int Hb, int Wb, const MeGeom& g);
 hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& d, hipStream_t s);

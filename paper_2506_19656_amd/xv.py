@@ -22,7 +22,7 @@ U16, F32 = 0, 1
 PAD_ZERO, PAD_REPEAT = 0, 1
 FILL_NEAREST, FILL_FORWARD = 0, 1
 FLAG_DROP_WORK = 1
-ME_COLUMN_PAIRS, ME_ROW_PAIRS = 1, 2
+ME_COLUMN_PAIRS, ME_ROW_PAIRS, ME_ROW_PAIRS_BY_CHANNEL = 1, 2, 3
 MAX_BANDS, MAX_GROUPS = 64, 22
 K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS, K_BITS_WRITE, K_BITS_PARSE, \
     K_QUALITY = range(10)
@@ -353,7 +353,8 @@ def spectral_angle(orig, decoded, stream=None):
 
 def set_me_geometry(block: int, search_range: int, blocks_per_wg=0, cands_per_lane=0,
                     threads=0, rows_per_lane=0, layout=0):
-    """xv_set_me_geometry; layout is ME_COLUMN_PAIRS or ME_ROW_PAIRS (0: default)."""
+    """xv_set_me_geometry; layout is ME_COLUMN_PAIRS, ME_ROW_PAIRS or
+    ME_ROW_PAIRS_BY_CHANNEL (0: default)."""
     g = MeGeometryC(blocks_per_wg, cands_per_lane, threads, rows_per_lane, layout)
     _check(lib().xv_set_me_geometry(block, search_range, C.byref(g)))
 

@@ -88,7 +88,9 @@ def test_me_geometry_validation(xvmod):
            dict(cands_per_lane=6, rows_per_lane=5, layout=col),   # 5 rows: 2 or 4 columns
            dict(cands_per_lane=10, rows_per_lane=1, layout=row),  # row pairs: 2..9, 11, 13
            dict(cands_per_lane=3, rows_per_lane=2, layout=row),   # row pairs: one row
-           dict(cands_per_lane=3, rows_per_lane=1, layout=3),     # no such layout
+           dict(cands_per_lane=3, rows_per_lane=1, layout=4),     # no such layout
+           dict(blocks_per_wg=16, cands_per_lane=2, threads=64, rows_per_lane=1,
+                layout=xvmod.ME_ROW_PAIRS_BY_CHANNEL),            # items > 3 rounds
            dict(threads=1024), dict(threads=96), dict(blocks_per_wg=65)]
     for kw in bad:
         with pytest.raises(xvmod.XvError):
@@ -109,7 +111,7 @@ def test_me_geometry_validation(xvmod):
         if g["layout"] == col:
             assert g["cands_per_lane"] % 2 == 0 and g["rows_per_lane"] in (1, 2, 3, 5)
         else:
-            assert g["layout"] == row and g["rows_per_lane"] == 1
+            assert g["layout"] in (row, xvmod.ME_ROW_PAIRS_BY_CHANNEL) and g["rows_per_lane"] == 1
             assert g["cands_per_lane"] in (2, 3, 4, 5, 6, 7, 8, 9, 11, 13)
 
 

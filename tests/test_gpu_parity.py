@@ -207,6 +207,16 @@ def test_motion_geometry_never_changes_outputs():
             got = xv.encode_cube(cube, p).host()
             assert np.array_equal(got["mvs"], base["mvs"]), ("rows", nb, kx, th)
             assert np.array_equal(got["recon"], base["recon"]), ("rows", nb, kx, th)
+        # row pairs staged channel by channel: items of a workgroup within
+        # three rounds of its threads (span 19 here)
+        for nb, kx, th in [(1, 2, 64), (2, 13, 128), (5, 3, 256), (3, 11, 512), (7, 5, 192),
+                           (4, 7, 448), (12, 9, 320), (2, 4, 64), (3, 6, 128), (1, 8, 64)]:
+            xv.set_me_geometry(8, 9, nb, kx, th, 1, xv.ME_ROW_PAIRS_BY_CHANNEL)
+            got = xv.encode_cube(cube, p).host()
+            assert np.array_equal(got["mvs"], base["mvs"]), ("by channel", nb, kx, th)
+            assert np.array_equal(got["recon"], base["recon"]), ("by channel", nb, kx, th)
+        with pytest.raises(xv.XvError):  # 16 x 19 x 10 items > 3 x 64
+            xv.set_me_geometry(8, 9, 16, 2, 64, 1, xv.ME_ROW_PAIRS_BY_CHANNEL)
     finally:
         xv.set_me_geometry(8, 9)
     # every kernel form against the oracle at every block size, odd and even R
@@ -215,8 +225,11 @@ def test_motion_geometry_never_changes_outputs():
         try:
             for kx, rows, lay in ((2, 1, 1), (6, 2, 1), (4, 3, 1), (2, 5, 1), (4, 5, 1),
                                   (3, 1, 2), (11, 1, 2), (2, 1, 2)):
-                xv.set_me_geometry(N, R, 0, kx, 0, rows, lay)
+                xv.set_me_geometry(N, R, 2, kx, 256, rows, lay)
                 check_cube(f"layout{lay}_rows{rows}_kx{kx}_N{N}_R{R}", host, q)
+            for kx in (3, 11, 2):
+                xv.set_me_geometry(N, R, 1, kx, 512, 1, xv.ME_ROW_PAIRS_BY_CHANNEL)
+                check_cube(f"layout3_kx{kx}_N{N}_R{R}", host, q)
         finally:
             xv.set_me_geometry(N, R)
 
@@ -228,7 +241,7 @@ def test_batch_tuner_installs_a_geometry_that_keeps_outputs():
     try:
         g = xv.autotune_me_batch(cubes, params, max_candidates=6)
         assert g["rows_per_lane"] in (1, 2, 3, 5) and g["kernel_ms"] > 0
-        assert g["layout"] in (xv.ME_COLUMN_PAIRS, xv.ME_ROW_PAIRS)
+        assert g["layout"] in (xv.ME_COLUMN_PAIRS, xv.ME_ROW_PAIRS, xv.ME_ROW_PAIRS_BY_CHANNEL)
         assert xv.get_me_geometry(16, 6)["threads"] == g["threads"]
         after = [e.host() for e in xv.encode_batch(cubes, params)]
         for a, b in zip(before, after):
