@@ -10,15 +10,16 @@
 //
 // Mapping onto gfx950:
 //  * a workgroup owns a horizontal run of `nb` blocks; the union of their
-//    search windows, (N + 2R + 1) rows x (nb N + G KX) columns per channel,
-//    is staged in LDS as packed u16 pairs with an odd dword pitch, so lanes
-//    that differ in dy hit different banks;
-//  * a lane evaluates KX consecutive candidates dx at two consecutive rows
-//    dy ("item") and reuses every reference dword it loads, and realigns,
-//    for all 2 KX of them;
+//    search windows is staged in LDS with an odd dword pitch, so lanes that
+//    read different window rows hit different banks;
 //  * v_sad_u16 adds |a.lo-b.lo| + |a.hi-b.hi| in one instruction (two SAD
-//    terms per lane-op); odd candidate offsets use pairs realigned with
-//    alignbit;
+//    terms per lane-op).  Two window layouts pair the samples differently:
+//    column pairs (two horizontally adjacent samples per dword; odd
+//    candidate offsets realigned with alignbit; a lane takes KX candidate
+//    columns on ROWS candidate rows and reuses every loaded dword for all of
+//    them) and row pairs (two vertically adjacent samples per dword, so any
+//    column offset reads whole dwords; a lane takes KX candidate columns of
+//    one candidate row), the latter optionally staged channel by channel;
 //  * the argmin is one 64-bit key (SAD << 21 | L1 << 13 | raster index for
 //    R <= 32; 23/15 for larger R) reduced with an LDS atomic min.
 #include "xv_internal.h"
