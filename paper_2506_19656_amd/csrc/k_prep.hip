@@ -280,7 +280,8 @@ __device__ inline uint16_t convert(double x, double mn, double range, double inv
 // Missing-sample fill along time for up to 8 bands of one pixel at once;
 // `src` indexes the first of them in frame 0, `fstride` is the frame size in
 // elements, bit j of `miss` marks band j as missing at time t.  NEAREST: the
-// valid sample at the smallest |t - t'|, ties to the earlier t'.  FORWARD:
+// valid sample at the smallest |t - t'|, ties to the earlier t', searched
+// from distance dd0 on (the caller has resolved the nearer ones).  FORWARD:
 // the last valid value before t, else the first one after it.  Each probe
 // of a time reads all the pixel's bands together; bands left without a
 // valid sample in the whole series keep their preset value (the band
@@ -288,7 +289,7 @@ __device__ inline uint16_t convert(double x, double mn, double range, double inv
 template <class V>
 __device__ inline void fill_missing(const float* __restrict__ d, int64_t src, int nb,
                                     int64_t fstride, int64_t t, int64_t T, int fill_mode,
-                                    uint32_t miss, V (&v)[8]) {
+                                    uint32_t miss, V (&v)[8], int64_t dd0 = 1) {
   auto probe = [&](int64_t u) {
     float f[8];
 #pragma unroll
@@ -306,7 +307,7 @@ __device__ inline void fill_missing(const float* __restrict__ d, int64_t src, in
     for (int64_t u = t + 1; u < T && miss; u++) probe(u);
     return;
   }
-  for (int64_t dd = 1; miss && (t - dd >= 0 || t + dd < T); dd++) {
+  for (int64_t dd = dd0; miss && (t - dd >= 0 || t + dd < T); dd++) {
     if (t - dd >= 0) probe(t - dd);
     if (miss && t + dd < T) probe(t + dd);
   }
@@ -687,34 +688,79 @@ __global__ void __launch_bounds__(kThreads) pack_vec_kernel(PackArgs a) {
   const double L = (double)((1 << a.bit_depth) - 1);
   uint16_t q[BANDS][G];
   uint8_t ok[BANDS][G];
+  // samples as float: u16 values and the minimum of a float band are exact
+  // there, and a filled sample is an input float
+  float dv[G][8];
+  uint32_t miss[G];
 #pragma unroll
   for (int p = 0; p < G; p++) {
-    // samples as float: u16 values and the minimum of a float band are exact
-    // there, and a filled sample is an input float
-    float dv[8];
-    uint32_t miss = 0u;
+    miss[p] = 0u;
 #pragma unroll
     for (int b = 0; b < BANDS; b++) {
       if constexpr (sizeof(Tv) == 2) {
-        dv[b] = (float)v[p * BANDS + b];
+        dv[p][b] = (float)v[p * BANDS + b];
       } else {
         const float f = v[p * BANDS + b];
         const bool nan = f != f;
-        dv[b] = nan ? (float)smn[b] : f;
-        miss |= (nan && !sall[b]) ? (1u << b) : 0u;
+        dv[p][b] = nan ? (float)smn[b] : f;
+        miss[p] |= (nan && !sall[b]) ? (1u << b) : 0u;
       }
     }
+  }
+  if constexpr (sizeof(Tv) == 4) {
+    uint32_t any = 0u;
+#pragma unroll
+    for (int p = 0; p < G; p++) any |= miss[p];
+    if (any) {
+      int64_t dd0 = 1;
+      if (a.fill_mode == XV_FILL_NEAREST) {
+        // the usual case resolves at distance 1: load times t - 1 and t + 1
+        // of the group's pixels together, take t - 1 where valid, else
+        // t + 1, and search further only for what is still missing
+        const float* df = (const float*)d;
+        float fm[PG::ne], fp[PG::ne];
+        const bool hm = t >= 1, hp = t + 1 < a.T;
+#pragma unroll
+        for (int p = 0; p < G; p++) {
+          const int64_t px = (ys * a.W + min(x0 + p, (int)a.W - 1)) * BANDS;
+#pragma unroll
+          for (int b = 0; b < BANDS; b++) {
+            fm[p * BANDS + b] = hm ? df[(t - 1) * fstride + px + b] : __builtin_nanf("");
+            fp[p * BANDS + b] = hp ? df[(t + 1) * fstride + px + b] : __builtin_nanf("");
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < G; p++)
+#pragma unroll
+          for (int b = 0; b < BANDS; b++) {
+            const float m = fm[p * BANDS + b], n = fp[p * BANDS + b];
+            if ((miss[p] >> b) & 1u) {
+              if (m == m) {
+                dv[p][b] = m;
+                miss[p] &= ~(1u << b);
+              } else if (n == n) {
+                dv[p][b] = n;
+                miss[p] &= ~(1u << b);
+              }
+            }
+          }
+        dd0 = 2;
+      }
+#pragma unroll
+      for (int p = 0; p < G; p++)
+        if (miss[p]) {
+          const int xs = min(x0 + p, (int)a.W - 1);
+          fill_missing((const float*)d, (ys * a.W + xs) * BANDS, BANDS, fstride, t, a.T, a.fill_mode,
+                       miss[p], dv[p], dd0);
+        }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < G; p++) {
     const bool real = y < a.H && x0 + p < a.W;
-    if constexpr (sizeof(Tv) == 4) {
-      if (miss) {
-        const int xs = min(x0 + p, (int)a.W - 1);
-        fill_missing((const float*)d, (ys * a.W + xs) * BANDS, BANDS, fstride, t, a.T,
-                     a.fill_mode, miss, dv);
-      }
-    }
 #pragma unroll
     for (int b = 0; b < BANDS; b++) {
-      q[b][p] = convert((double)dv[b], smn[b], srg[b], sinv[b], L);
+      q[b][p] = convert((double)dv[p][b], smn[b], srg[b], sinv[b], L);
       bool valid = true;
       if constexpr (sizeof(Tv) == 4) {
         const float f = v[p * BANDS + b];
