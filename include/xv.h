@@ -302,6 +302,13 @@ typedef struct {
   int32_t layout;
 } xv_me_geometry;
 
+/* Installs g for (block, search_range) in this process.  A layout other
+ * than the default's with rows_per_lane zero takes one candidate row per
+ * lane.  Errors: XV_EINVAL for a bad block or search range, an unknown
+ * layout, a count of candidates or rows the layout has no kernel for,
+ * threads outside 64..512 or not a multiple of 64, blocks_per_wg outside
+ * 1..64, more than 160 KB of LDS, or (row pairs by channel) more items per
+ * workgroup than three rounds of its threads. */
 int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g);
 /* Geometry used for (block, search_range) on frames width_blocks blocks wide
  * (width_blocks <= 0: 16): the one set or tuned, else the model default. */
@@ -309,7 +316,8 @@ int xv_get_me_geometry(int block, int search_range, int width_blocks, xv_me_geom
 
 /* Empirical tuner: times the motion-search kernel on the first P-picture
  * step of the cube `in` (device memory) coded with p, for the geometries the
- * model ranks highest (max_candidates of them, <= 0: 512), and installs the
+ * model ranks highest (max_candidates of them, <= 0: 512, shared equally
+ * among the window layouts), and installs the
  * fastest for (p->block, p->search_range) as xv_set_me_geometry would.
  * Coded outputs never depend on the geometry.  Synchronises hip_stream; out
  * (optional) receives the chosen geometry and *best_ms (optional) its
