@@ -142,3 +142,21 @@ def test_profile_classes_match_the_header():
     assert len(xv.K_NAMES) == n
     p = xv.ProfileC()
     assert len(p.ms) == n and len(p.launches) == n and len(p.work) == n
+
+
+def test_default_geometries_are_admissible(xvmod):
+    # the model's default for every block size over the search-range range is
+    # a geometry the setter accepts (LDS, instances, rounds of items)
+    try:
+        for N in (4, 8, 16, 32):
+            for R in (0, 1, 2, 5, 8, 16, 23, 32, 33, 48, 64):
+                for wb in (1, 3, 16, 45):
+                    g = xvmod.get_me_geometry(N, R, wb)
+                    xvmod.set_me_geometry(N, R, g["blocks_per_wg"], g["cands_per_lane"],
+                                          g["threads"], g["rows_per_lane"], g["layout"])
+                    assert xvmod.get_me_geometry(N, R, wb) == g, (N, R, wb, g)
+                    xvmod.set_me_geometry(N, R)
+    finally:
+        for N in (4, 8, 16, 32):
+            for R in (0, 1, 2, 5, 8, 16, 23, 32, 33, 48, 64):
+                xvmod.set_me_geometry(N, R)
