@@ -375,7 +375,7 @@ def main():
         t0 = time.perf_counter()
         encs = xv.encode_batch([cube] * len(params), params)
         xv.decode_batch(encs, outs)
-        ms = [xv.psnr_bpppb(cube, e) for e in encs]
+        ms = xv.psnr_bpppb_batch([cube] * len(encs), encs)
         for e in encs:
             e.free()
         if lat is not None:

@@ -165,6 +165,14 @@ int xv_decode_cube(const xv_encoded* e, const xv_cube* out, void* hip_stream);
  * Synchronises hip_stream.  m is caller memory.  Errors: XV_EINVAL, XV_EHIP. */
 int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m,
                   void* hip_stream);
+/* The metrics of n encodes with one synchronisation of hip_stream: ms[i] as
+ * xv_psnr_bpppb(origs ? &origs[i] : NULL, encs[i], &ms[i]) would give them.
+ * origs (n cubes) may be NULL; ms is caller memory for n results.  The
+ * metric spans are gathered in a device buffer the call allocates and
+ * frees.  Errors: XV_EINVAL (n < 1, a NULL pointer, a cube that differs
+ * from its encode), XV_ENOMEM, XV_EHIP. */
+int xv_psnr_bpppb_batch(int n, const xv_cube* origs, const xv_encoded* const* encs,
+                        xv_metrics* ms, void* hip_stream);
 
 /* Structural similarity per band (Sec. II-C names SSIM, Wang et al. 2004,
  * without parameters; this is the stated reading): in the coded domain, each

@@ -774,37 +774,40 @@ int xv_spectral_angle(const xv_cube* orig, const xv_cube* decoded, double* mean_
   return XV_OK;
 }
 
-int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m, void* hip_stream) {
-  if (!e || !m) return fail(XV_EINVAL, "null encoded cube or metrics");
-  hipStream_t s = (hipStream_t)hip_stream;
-  const int bands = (int)e->bands, G = e->G;
-  bool have_phys = false;
-  if (orig) {
-    int rc = check_cube(orig, "original");
-    if (rc != XV_OK) return rc;
-    if (orig->T != e->T || orig->H != e->H || orig->W != e->W || orig->bands != e->bands ||
-        orig->dtype != e->src_dtype)
-      return fail(XV_EINVAL, "original cube differs from the encoded one");
-    if (e->recon) {
-      PhysArgs a{orig->data, orig->dtype, e->recon, e->T, e->H, e->W, bands, e->Hp, e->Wp,
-                 e->p.bit_depth, e->mn, e->mx, e->phys_partial, e->phys, e->phys_nb,
-                 chunk_px_for(e->W, bands)};
-      const double ib = orig->dtype == XV_U16 ? 2.0 : 4.0;
-      ProfScope ps(XV_K_METRICS, s, (double)e->T * e->H * e->W * bands * (ib + 2.0));
-      XV_HIP(launch_phys_sse(a, s), "physical error kernel");
-      have_phys = true;
-    }
+namespace {
+
+// Checks orig against e and launches the physical-domain error kernels when
+// both the original and the reconstruction are there; *have_phys tells.
+int launch_metrics(const xv_cube* orig, const xv_encoded* e, hipStream_t s, bool* have_phys) {
+  *have_phys = false;
+  if (!orig) return XV_OK;
+  int rc = check_cube(orig, "original");
+  if (rc != XV_OK) return rc;
+  if (orig->T != e->T || orig->H != e->H || orig->W != e->W || orig->bands != e->bands ||
+      orig->dtype != e->src_dtype)
+    return fail(XV_EINVAL, "original cube differs from the encoded one");
+  if (e->recon) {
+    PhysArgs a{orig->data, orig->dtype, e->recon, e->T, e->H, e->W, (int)e->bands, e->Hp,
+               e->Wp, e->p.bit_depth, e->mn, e->mx, e->phys_partial, e->phys, e->phys_nb,
+               chunk_px_for(e->W, (int)e->bands)};
+    const double ib = orig->dtype == XV_U16 ? 2.0 : 4.0;
+    ProfScope ps(XV_K_METRICS, s, (double)e->T * e->H * e->W * e->bands * (ib + 2.0));
+    XV_HIP(launch_phys_sse(a, s), "physical error kernel");
+    *have_phys = true;
   }
-  std::vector<uint64_t> host(e->span_bytes / 8);
-  XV_HIP(hipMemcpyAsync(host.data(), e->span, e->span_bytes, hipMemcpyDeviceToHost, s), "copy metrics");
-  XV_HIP(hipStreamSynchronize(s), "synchronise metrics");
-  const double* mn = (const double*)host.data();
+  return XV_OK;
+}
+
+// Fills m from a host copy of e's metric span (band min and max, physical
+// squared errors, valid counts, coded squared errors, bit totals).
+void fill_metrics(const xv_encoded* e, const uint64_t* span, bool dphys, xv_metrics* m) {
+  const int bands = (int)e->bands, G = e->G;
+  const double* mn = (const double*)span;
   const double* mx = mn + bands;
   const double* phys = mx + bands;
   const unsigned long long* nv = (const unsigned long long*)(phys + bands);
   const unsigned long long* sse = nv + bands;
   const unsigned long long* bits = sse + 3 * G;
-  const bool dphys = have_phys;
 
   memset(m, 0, sizeof *m);
   m->bands = bands;
@@ -846,6 +849,59 @@ int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m, void*
   m->mv_bits = mb;
   m->header_bits = 128ull * bands + 256ull;
   m->bpppb = (double)(cb + mb) / (pix * (double)bands);
+}
+
+}  // namespace
+
+int xv_psnr_bpppb(const xv_cube* orig, const xv_encoded* e, xv_metrics* m, void* hip_stream) {
+  if (!e || !m) return fail(XV_EINVAL, "null encoded cube or metrics");
+  hipStream_t s = (hipStream_t)hip_stream;
+  bool have_phys = false;
+  int rc = launch_metrics(orig, e, s, &have_phys);
+  if (rc != XV_OK) return rc;
+  std::vector<uint64_t> host(e->span_bytes / 8);
+  XV_HIP(hipMemcpyAsync(host.data(), e->span, e->span_bytes, hipMemcpyDeviceToHost, s), "copy metrics");
+  XV_HIP(hipStreamSynchronize(s), "synchronise metrics");
+  fill_metrics(e, host.data(), have_phys, m);
+  return XV_OK;
+}
+
+int xv_psnr_bpppb_batch(int n, const xv_cube* origs, const xv_encoded* const* encs, xv_metrics* ms,
+                        void* hip_stream) {
+  if (n < 1 || !encs || !ms) return fail(XV_EINVAL, "bad metrics batch");
+  for (int i = 0; i < n; i++)
+    if (!encs[i]) return fail(XV_EINVAL, "null encoded cube %d in the metrics batch", i);
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<char> phys(n, 0);
+  size_t total = 0;
+  for (int i = 0; i < n; i++) {
+    bool hp = false;
+    const int rc = launch_metrics(origs ? &origs[i] : nullptr, encs[i], s, &hp);
+    if (rc != XV_OK) return rc;
+    phys[i] = hp;
+    total += encs[i]->span_bytes;
+  }
+  // the spans gathered in one device buffer, one copy to the host, one wait
+  void* gather = nullptr;
+  XV_HIP(dev_alloc(&gather, total, s), "device allocation of the metrics gather");
+  size_t off = 0;
+  hipError_t he = hipSuccess;
+  for (int i = 0; i < n && he == hipSuccess; i++) {
+    he = hipMemcpyAsync((char*)gather + off, encs[i]->span, encs[i]->span_bytes,
+                        hipMemcpyDeviceToDevice, s);
+    off += encs[i]->span_bytes;
+  }
+  std::vector<uint64_t> host(total / 8);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(host.data(), gather, total, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  dev_free(gather, s);
+  XV_HIP(he, "gather metrics");
+  off = 0;
+  for (int i = 0; i < n; i++) {
+    fill_metrics(encs[i], host.data() + off / 8, phys[i], &ms[i]);
+    off += encs[i]->span_bytes;
+  }
   return XV_OK;
 }
 

@@ -105,7 +105,8 @@ class ServerStatsC(C.Structure):
 OP_ENCODE, OP_DECODE = 0, 1
 
 EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube",
-            "xv_decode_cube", "xv_psnr_bpppb", "xv_encoded_export", "xv_encoded_free",
+            "xv_decode_cube", "xv_psnr_bpppb", "xv_psnr_bpppb_batch", "xv_encoded_export",
+            "xv_encoded_free",
             "xv_encode_batch", "xv_decode_batch", "xv_set_me_geometry", "xv_get_me_geometry",
             "xv_autotune_me", "xv_autotune_me_batch", "xv_profile_enable", "xv_profile_select", "xv_profile_read", "xv_server_create",
             "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
@@ -131,6 +132,8 @@ def lib():
         L.xv_encode_cube.argtypes = [C.POINTER(Cube), C.POINTER(ParamsC), vp, C.POINTER(vp)]
         L.xv_decode_cube.argtypes = [vp, C.POINTER(Cube), vp]
         L.xv_psnr_bpppb.argtypes = [C.POINTER(Cube), vp, C.POINTER(MetricsC), vp]
+        L.xv_psnr_bpppb_batch.argtypes = [C.c_int, C.POINTER(Cube), C.POINTER(vp),
+                                          C.POINTER(MetricsC), vp]
         L.xv_ssim.argtypes = [vp, C.POINTER(C.c_double), vp]
         L.xv_spectral_angle.argtypes = [C.POINTER(Cube), C.POINTER(Cube), C.POINTER(C.c_double),
                                         C.POINTER(C.c_uint64), vp]
@@ -326,6 +329,21 @@ def psnr_bpppb(orig, enc: Encoded, stream=None) -> dict:
     m = MetricsC()
     cp = C.byref(_cube(orig)) if orig is not None else None
     _check(lib().xv_psnr_bpppb(cp, enc.handle, C.byref(m), _stream_handle(stream)))
+    return _metrics_dict(m)
+
+
+def psnr_bpppb_batch(origs, encs, stream=None) -> list:
+    """xv_psnr_bpppb_batch: metrics of several encodes, one synchronisation;
+    origs may be None (no physical-domain PSNR)."""
+    n = len(encs)
+    ms = (MetricsC * n)()
+    hs = (C.c_void_p * n)(*[e.handle for e in encs])
+    cbs = (Cube * n)(*[_cube(c) for c in origs]) if origs is not None else None
+    _check(lib().xv_psnr_bpppb_batch(n, cbs, hs, ms, _stream_handle(stream)))
+    return [_metrics_dict(m) for m in ms]
+
+
+def _metrics_dict(m) -> dict:
     Bn, G = m.bands, m.groups
     return dict(psnr=list(m.psnr[:Bn]), psnr_phys=list(m.psnr_phys[:Bn]),
                 sse_phys=list(m.sse_phys[:Bn]), sse=list(m.sse[:Bn]),

@@ -78,6 +78,11 @@ def test_null_handles(xvmod):
     assert L.xv_decode_cube(None, None, None) == xvmod.EINVAL
     m = xvmod.MetricsC()
     assert L.xv_psnr_bpppb(None, None, C.byref(m), None) == xvmod.EINVAL
+    ms = (xvmod.MetricsC * 2)()
+    assert L.xv_psnr_bpppb_batch(0, None, None, ms, None) == xvmod.EINVAL
+    assert L.xv_psnr_bpppb_batch(2, None, None, ms, None) == xvmod.EINVAL
+    hs = (C.c_void_p * 2)(None, None)
+    assert L.xv_psnr_bpppb_batch(2, None, hs, ms, None) == xvmod.EINVAL
     L.xv_encoded_free(None)  # no-op
 
 

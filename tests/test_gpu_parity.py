@@ -186,6 +186,34 @@ def test_batch_equals_plain_and_is_deterministic():
         assert torch.equal(outs[i], single)
 
 
+def _same_metrics(a, b):
+    assert a.keys() == b.keys()
+    for k in a:
+        x, y = np.asarray(a[k], dtype=np.float64), np.asarray(b[k], dtype=np.float64)
+        assert np.array_equal(x, y, equal_nan=True), (k, a[k], b[k])
+
+
+def test_batched_metrics_equal_single_calls():
+    cubes = [_to_dev(_textured(4, 40, 56, 5, seed=51)),
+             torch.from_numpy(synth.s2cloud_cube(seed=3, T=4, H=32, W=40, bands=4).numpy()).cuda(),
+             _to_dev(_textured(3, 24, 24, 2, seed=52))]
+    params = [xv.Params(bit_depth=10, qp=27, block=8, search_range=4, gop=4),
+              xv.Params(bit_depth=12, qp=22, block=16, search_range=3, gop=2),
+              xv.Params(bit_depth=8, qp=32, block=4, search_range=2, gop=3)]
+    encs = [xv.encode_cube(c, p) for c, p in zip(cubes, params)]
+    single = [xv.psnr_bpppb(c, e) for c, e in zip(cubes, encs)]
+    batch = xv.psnr_bpppb_batch(cubes, encs)
+    for a, b in zip(single, batch):
+        _same_metrics(a, b)
+    single = [xv.psnr_bpppb(None, e) for e in encs]
+    for a, b in zip(single, xv.psnr_bpppb_batch(None, encs)):
+        _same_metrics(a, b)
+    with pytest.raises(xv.XvError):  # a cube that differs from its encode
+        xv.psnr_bpppb_batch([cubes[1], cubes[0], cubes[2]], encs)
+    for e in encs:
+        e.free()
+
+
 def test_motion_geometry_never_changes_outputs():
     host = _textured(4, 64, 96, 3, seed=21)
     cube = _to_dev(host)
