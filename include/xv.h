@@ -325,11 +325,12 @@ int xv_get_me_geometry(int block, int search_range, int width_blocks, xv_me_geom
 /* Empirical tuner: times the motion-search kernel on the first P-picture
  * step of the cube `in` (device memory) coded with p, for the geometries the
  * model ranks highest (max_candidates of them, <= 0: 512, shared equally
- * among the window layouts), and installs the
- * fastest for (p->block, p->search_range) as xv_set_me_geometry would.
+ * among the window layouts), times the six fastest again in nine
+ * interleaved rounds, and installs the one with the lowest median for
+ * (p->block, p->search_range) as xv_set_me_geometry would.
  * Coded outputs never depend on the geometry.  Synchronises hip_stream; out
  * (optional) receives the chosen geometry and *best_ms (optional) its
- * kernel time.  Errors: XV_EINVAL (also for a cube with T < 2), XV_ENOMEM,
+ * median kernel time.  Errors: XV_EINVAL (also for a cube with T < 2), XV_ENOMEM,
  * XV_EHIP. */
 int xv_autotune_me(const xv_cube* in, const xv_params* p, void* hip_stream, int max_candidates,
                    xv_me_geometry* out, double* best_ms);

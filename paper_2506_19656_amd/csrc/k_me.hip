@@ -639,6 +639,31 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
   // (SAD, L1, dy, dx) among them; its full key goes to the block's LDS min.
   auto select = [&](int b, int r, int c0, int chi, const uint32_t(&acc)[KX]) XV_INLINE {
     const int khi = chi - c0;
+    if constexpr (N <= 8) {
+      if (R <= 32) {
+        // One 32-bit key SAD << 11 | L1 << 4 | k holds the whole order
+        // (SAD < 3 N^2 2^12 <= 2^20, L1 <= 64, k < 16), so a plain min picks
+        // the candidate; 16 L1 + k comes from one 16-bit SAD of operands
+        // scaled by 16.
+        const uint32_t cx16 = 16u * (uint32_t)(c0 + KX);
+        const uint32_t ly16 = 16u * (uint32_t)abs(r - R);
+        uint32_t kb = 0xffffffffu;
+#pragma unroll
+        for (int k = 0; k < KX; k++) {
+          const uint32_t lk = __builtin_amdgcn_sad_u16(cx16, 16u * (uint32_t)(R + KX - k), ly16 + k);
+          const uint32_t key = (acc[k] << 11) | lk;
+          kb = k <= khi ? min(kb, key) : kb;
+        }
+        if (kb != 0xffffffffu) {
+          const int k = (int)(kb & 15u);
+          const unsigned long long idx = (unsigned long long)(r * s.span + c0 + k);
+          const unsigned long long key = ((unsigned long long)(kb >> 11) << keyshift_sad) |
+                                         ((unsigned long long)((kb >> 4) & 127u) << keyshift_l1) | idx;
+          atomicMin(&best[b], key);
+        }
+        return;
+      }
+    }
     const uint32_t ly = (uint32_t)abs(r - R);
     uint32_t kb32 = 0xffffffffu;
     int bsel = -1;

@@ -260,6 +260,17 @@ def test_motion_geometry_never_changes_outputs():
                 check_cube(f"layout3_kx{kx}_N{N}_R{R}", host, q)
         finally:
             xv.set_me_geometry(N, R)
+    # small blocks select with one packed 32-bit key up to R = 32, with the
+    # general key beyond
+    for R in (32, 33):
+        q = xv.Params(bit_depth=12, qp=22, block=8, search_range=R, gop=4)
+        try:
+            for nb, kx, lay in ((2, 3, xv.ME_ROW_PAIRS), (1, 11, xv.ME_ROW_PAIRS),
+                                (1, 13, xv.ME_ROW_PAIRS_BY_CHANNEL)):
+                xv.set_me_geometry(8, R, nb, kx, 512, 1, lay)
+                check_cube(f"layout{lay}_kx{kx}_N8_R{R}", host, q)
+        finally:
+            xv.set_me_geometry(8, R)
 
 
 def test_batch_tuner_installs_a_geometry_that_keeps_outputs():
