@@ -155,6 +155,25 @@ def test_edge_shapes():
                xv.Params(bit_depth=8, qp=0, block=4, search_range=2, gop=3))
 
 
+@pytest.mark.parametrize("layout,nb,kx,threads,rows", [
+    (xv.ME_COLUMN_PAIRS, 2, 2, 256, 3), (xv.ME_ROW_PAIRS, 2, 5, 256, 1),
+    (xv.ME_ROW_PAIRS_BY_CHANNEL, 1, 5, 512, 1)])
+def test_edge_shapes_every_layout(layout, nb, kx, threads, rows):
+    # pictures smaller than the window, one block wide, one band (a single
+    # real channel), odd window origins (odd R)
+    cases = [("tiny_frame_big_R", _textured(4, 8, 8, 3, seed=1), 10, 8, 16),
+             ("one_pixel_wide", _textured(3, 5, 1, 1, seed=5), 8, 4, 2),
+             ("one_band_odd_R", _textured(4, 20, 44, 1, seed=6), 10, 4, 5),
+             ("two_bands_R7", _textured(4, 40, 24, 2, seed=7), 12, 8, 7)]
+    for name, host, B, N, R in cases:
+        try:
+            xv.set_me_geometry(N, R, nb, kx, threads, rows, layout)
+            check_cube(f"{name}_layout{layout}", host,
+                       xv.Params(bit_depth=B, qp=27, block=N, search_range=R, gop=4))
+        finally:
+            xv.set_me_geometry(N, R)
+
+
 def test_s2cloud_reduced_sweep():
     host = synth.s2cloud_cube(T=40).numpy()
     for N in (8, 16, 32):
