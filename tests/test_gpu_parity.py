@@ -174,6 +174,26 @@ def test_edge_shapes_every_layout(layout, nb, kx, threads, rows):
             xv.set_me_geometry(N, R)
 
 
+def test_row_pair_layouts_at_extreme_search_ranges():
+    # R = 0 (one candidate: every other column of a group lies past the
+    # range), R = 1, and R = 64 (a window of 2R + N - 1 pair rows that only
+    # the channel-by-channel staging fits in LDS)
+    host = _textured(4, 48, 64, 3, seed=61)
+    cases = [(8, 0, 1, 2, xv.ME_ROW_PAIRS), (16, 0, 2, 11, xv.ME_ROW_PAIRS_BY_CHANNEL),
+             (8, 1, 3, 3, xv.ME_ROW_PAIRS), (4, 1, 2, 5, xv.ME_ROW_PAIRS_BY_CHANNEL),
+             (4, 64, 1, 13, xv.ME_ROW_PAIRS_BY_CHANNEL), (8, 64, 1, 13, xv.ME_ROW_PAIRS_BY_CHANNEL),
+             (16, 64, 1, 13, xv.ME_ROW_PAIRS_BY_CHANNEL)]
+    for N, R, nb, kx, lay in cases:
+        try:
+            xv.set_me_geometry(N, R, nb, kx, 512, 1, lay)
+            check_cube(f"N{N}_R{R}_layout{lay}_kx{kx}", host,
+                       xv.Params(bit_depth=10, qp=27, block=N, search_range=R, gop=4))
+        finally:
+            xv.set_me_geometry(N, R)
+    with pytest.raises(xv.XvError):  # all three channels of R = 64 exceed the LDS
+        xv.set_me_geometry(16, 64, 1, 13, 512, 1, xv.ME_ROW_PAIRS)
+
+
 def test_s2cloud_reduced_sweep():
     host = synth.s2cloud_cube(T=40).numpy()
     for N in (8, 16, 32):
