@@ -28,7 +28,7 @@ FILL_NEAREST, FILL_FORWARD = 0, 1
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math, no FP contraction)."""
     if force or not os.path.exists(LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fopenmp", "-ffp-contract=off",
+        cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-fopenmp", "-ffp-contract=off",
                "-fno-fast-math", "-shared", "-fPIC", SRC, "-o", LIB + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)

@@ -770,3 +770,131 @@ def test_spectral_angle_matches_numpy_bruteforce():
     w = d.reshape(-1, 6).astype(np.float64)
     r = np.clip((u * w).sum(1) / (np.sqrt((u * u).sum(1)) * np.sqrt((w * w).sum(1))), -1, 1)
     assert n == u.shape[0] and abs(v - float(np.arccos(r).mean())) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The transform matrix, stage order, rounding and clipping, and the dead-zone
+# boundaries, against tables typed from ITU-T H.265 and hand-worked examples
+# (tests/golden/hevc_*.txt, deadzone_thresholds.txt)
+# ---------------------------------------------------------------------------
+
+def _golden_sections(name):
+    """Sections "name rows cols" followed by rows of integers."""
+    secs = {}
+    rows = _rows(name)
+    i = 0
+    while i < len(rows):
+        key, nr, nc = rows[i][0], int(rows[i][1]), int(rows[i][2])
+        secs[key] = np.array([[int(v) for v in r] for r in rows[i + 1:i + 1 + nr]], np.int64)
+        assert secs[key].shape == (nr, nc), key
+        i += 1 + nr
+    return secs
+
+
+def test_dct_matrix_golden_is_a_cosine_table():
+    """The typed table itself: every entry has the sign of its cosine and lies
+    within 1.5 of 64 sqrt(2) cos (a check of the typing, not of the oracle)."""
+    sec = _golden_sections("hevc_dct_matrix.txt")
+
+    def cos_entry(N, k, n):
+        return 64.0 * math.sqrt(2.0) * math.cos(math.pi * (2 * n + 1) * k / (2 * N))
+
+    checks = [(32, k, 0, sec["col0_32"][k, 0]) for k in range(1, 32)]
+    checks += [(4, k, n, sec["m4"][k, n]) for k in range(1, 4) for n in range(4)]
+    checks += [(8, k, n, sec["m8"][k, n]) for k in range(1, 8) for n in range(8)]
+    checks += [(16, 2 * i + 1, n, sec["m16_odd"][i, n]) for i in range(8) for n in range(16)]
+    checks += [(32, 2 * i + 1, n, sec["m32_odd_1357"][i, n]) for i in range(4) for n in range(32)]
+    for N, k, n, v in checks:
+        c = cos_entry(N, k, n)
+        assert np.sign(v) == np.sign(c) and abs(v - c) < 1.5, (N, k, n, v)
+    assert sec["col0_32"][0, 0] == 64 and (sec["m4"][0] == 64).all() and (sec["m8"][0] == 64).all()
+
+
+def test_dct_matrix_equals_the_standard_table():
+    """Every typed entry of the H.265 table equals the oracle's matrix: the
+    first column of the 32-point matrix holds all 31 distinct magnitudes, so
+    a wrong magnitude anywhere in the oracle's table fails here."""
+    sec = _golden_sections("hevc_dct_matrix.txt")
+    M32 = O.dct_matrix(32).astype(np.int64)
+    assert (M32[:, 0] == sec["col0_32"][:, 0]).all()
+    assert (M32[1:8:2] == sec["m32_odd_1357"]).all()
+    assert (O.dct_matrix(16).astype(np.int64)[1::2] == sec["m16_odd"]).all()
+    assert (O.dct_matrix(8).astype(np.int64) == sec["m8"]).all()
+    assert (O.dct_matrix(4).astype(np.int64) == sec["m4"]).all()
+
+
+def _transform_examples():
+    rows = _rows("hevc_transform_examples.txt")
+    out, i = [], 0
+    while i < len(rows):
+        kind, N, B = rows[i][0], int(rows[i][1]), int(rows[i][2])
+        i += 1
+        mats = {}
+        while rows[i][0] != "end":
+            name = rows[i][0]
+            mats[name] = np.array([[int(v) for v in r] for r in rows[i + 1:i + 1 + N]], np.int64)
+            i += 1 + N
+        out.append((kind, N, B, mats))
+        i += 1
+    return out
+
+
+def test_transform_examples_are_consistent():
+    """Each listed intermediate tile follows from the previous one by the
+    stage written in the fixture header, with the typed standard matrices
+    (a check of the hand derivation; the oracle is not involved)."""
+    sec = _golden_sections("hevc_dct_matrix.txt")
+    mats = {4: sec["m4"], 8: sec["m8"]}
+    for kind, N, B, m in _transform_examples():
+        M = mats[N]
+        lg = int(math.log2(N))
+        if kind == "forward":
+            s1, s2 = lg + B - 9, lg + 6
+            assert ((m["r"] @ M.T + (1 << (s1 - 1))) >> s1 == m["T"]).all()
+            assert ((M @ m["T"] + (1 << (s2 - 1))) >> s2 == m["C"]).all()
+        else:
+            E = np.clip((M.T @ m["d"] + 64) >> 7, -32768, 32767)
+            assert (E == m["E"]).all()
+            assert ((m["E"] @ M + (1 << (19 - B))) >> (20 - B) == m["r"]).all()
+
+
+def test_forward_transform_worked_examples():
+    """The rows-then-columns order and the stage-1 rounding add: on these
+    inputs the columns-first order and a truncating stage 1 each change
+    several coefficients."""
+    n = 0
+    for kind, N, B, m in _transform_examples():
+        if kind != "forward":
+            continue
+        assert (O.forward_transform(m["r"], B) == m["C"]).all(), (N, B)
+        n += 1
+    assert n == 2
+
+
+def test_inverse_transform_worked_examples():
+    """The columns-then-rows order with the 16-bit clip after stage 1: the
+    first examples change under a rows-first order, the saturating one
+    without the clip."""
+    n = 0
+    for kind, N, B, m in _transform_examples():
+        if kind != "inverse":
+            continue
+        assert (O.inverse_transform(m["d"], B) == m["r"]).all(), (N, B, m["d"][0].tolist())
+        n += 1
+    assert n == 3
+
+
+def test_deadzone_boundaries_hand_worked():
+    """Levels on both sides of the 0/1 and 1/2 decisions for the intra
+    (171/512) and inter (85/512) rounding offsets, and the dequantised value
+    of each level."""
+    for N, B, qp, intra, c, lev, deq in (tuple(int(v) for v in r)
+                                         for r in _rows("deadzone_thresholds.txt")):
+        C = np.zeros((N, N), np.int32)
+        C[0, 0] = c
+        C[N - 1, 1] = -c  # the same decision at another position, opposite sign
+        L = O.quantize(C, B, qp, bool(intra))
+        assert L[0, 0] == lev and L[N - 1, 1] == -lev, (qp, intra, c)
+        assert np.count_nonzero(L) == (2 if lev else 0)
+        D = O.dequantize(L, B, qp)
+        assert D[0, 0] == deq and D[N - 1, 1] == -deq, (qp, c, lev)
