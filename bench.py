@@ -1,16 +1,23 @@
 """Benchmark of the coding loop on one MI355X.
 
-Workload (default): the Sentinel-2-like cloud-gapped cube, 500 frames x
-128 x 128 x 6 bands float32 with ~10% NaN, converted to 12 bits and coded at
-QP {17, 22, 27, 32, 37} x block {8, 16, 32} (15 runs), search range 16,
-closed GOPs of 16.  One step = encode + decode + PSNR/bpppb of all 15 runs.
+Headline workload: the Planet-like cube (stand-in for DynamicEarthNet),
+730 daily frames x 1024 x 1024 x 4 bands u16 (RGB + NIR; the second band
+group carries NIR and two zero channels), converted to 10 bits and coded at
+QP 22 and QP 32 with 16 x 16 blocks, search range 32, closed GOPs of 16.
+One step = encode + decode + PSNR/bpppb of both QP runs over the whole cube.
 The cube is generated on the GPU and resident in HBM before timing starts.
 
 Two forms are timed back to back on the same inputs:
-  plain    one cube-run at a time (xv_encode_cube / xv_decode_cube)
-  batched  all 15 runs per call (xv_encode_batch / xv_decode_batch: one launch
-           per frame step and block-size class)
+  plain    one run at a time (xv_encode_cube / xv_decode_cube / xv_psnr_bpppb)
+  batched  both runs per call (xv_encode_batch / xv_decode_batch /
+           xv_psnr_bpppb_batch: one launch per frame step covering both runs)
 Both produce bit-identical outputs (checked), hence identical PSNR and bpppb.
+
+Secondary sections (not the headline): the cloud-gapped Sentinel-2-like sweep
+(500 x 128 x 128 x 6 f32, 15 QP x N runs), the reanalysis-like cube
+(744 x 721 x 1440 x 3 f32, QP 17 and 27, N = 32, R = 8), SSIM / spectral
+angle and the bitstream on the headline runs, a small serving mix, and the
+oracle on the host cores on sampled GOP units of the headline cube.
 
 Prints ONE JSON line.  `value` is the batched throughput in Mpx*band/s of
 encode + decode (px*band = T*H*W*bands per run, summed over runs).
@@ -18,6 +25,7 @@ encode + decode (px*band = T*H*W*bands per run, summed over runs).
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import math
 import os
@@ -34,17 +42,23 @@ HBM_PEAK_GBS = 8000.0
 # v_sad_u16: 2 SAD terms per lane-op; 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 SAD_PEAK_TTERMS = 256 * 64 * 2.4e9 * 2 / 1e12
 
-# Measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB
-# copy), with the sha256 of the kernel sources they were taken on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "s2cloud_sweep_hbm_traffic.json")
+HEADLINE = "planet"
 
 
-def _measured_traffic():
-    """Per-kernel HBM bytes per launch from the committed counter summary, or
-    None when any listed kernel source has changed since it was taken."""
+def traffic_file(workload: str) -> str:
+    """Measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a
+    1 GiB copy) of one workload, with the sha256 of the kernel sources they
+    were taken on."""
+    stem = {"s2cloud": "s2cloud_sweep"}.get(workload, workload)
+    return os.path.join(ROOT, "profiles", f"{stem}_hbm_traffic.json")
+
+
+def _measured_traffic(workload: str):
+    """Per-kernel-class HBM bytes per launch from the committed counter
+    summary, or None when any listed kernel source has changed since."""
     import hashlib
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(workload)) as f:
             t = json.load(f)
         for rel, digest in t["sources_sha256"].items():
             with open(os.path.join(ROOT, rel), "rb") as f:
@@ -55,9 +69,8 @@ def _measured_traffic():
     out = {}
     for k, v in t["per_launch_bytes"].items():
         name = k.split("<")[0]
-        # the two motion-search window layouts are one kernel class
+        # the motion-search window layouts are one kernel class
         out.setdefault("me" if name in ("me_kernel", "me_rp_kernel") else name, []).append(float(v))
-    # each kernel launches equally often per block size in the sweep step
     return {k: sum(v) / len(v) for k, v in out.items()}
 
 
@@ -70,33 +83,230 @@ def _percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(cube_host, wl, seconds_hint=""):
-    """The oracle as it stands, on the host cores: encode + decode + metrics of
-    all 15 runs over the full cube (the same work as one GPU step)."""
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload_params(xv, wl):
+    runs = [(qp, N) for N in wl.blocks for qp in wl.qps]
+    params = [xv.Params(bit_depth=wl.bit_depth, qp=qp, block=N, search_range=wl.search_range,
+                        gop=wl.gop, pad_mode=wl.pad_mode, fill_mode=wl.fill_mode)
+              for qp, N in runs]
+    return runs, params
+
+
+def describe(wl) -> str:
+    kind = {"planet": "u16 Voronoi land-cover patches (stand-in for DynamicEarthNet), RGB+NIR, "
+                      "second band group NIR + 2 zero channels",
+            "s2cloud": "f32 with ~10% NaN cloud gaps (stand-in for DeepExtremeCubes)",
+            "era5": "f32 reanalysis-like variables (stand-in for ERA5), rows edge-padded to 736"}
+    return (f"{wl.name}: {wl.T}x{wl.H}x{wl.W}x{wl.bands} {kind.get(wl.name, wl.dtype)}, "
+            f"B={wl.bit_depth}, QP{list(wl.qps)} x N{list(wl.blocks)} "
+            f"({len(wl.qps) * len(wl.blocks)} runs per step), R={wl.search_range}, "
+            f"GOP {wl.gop}, pad {'zero' if wl.pad_mode == 0 else 'repeat'}")
+
+
+def tune(xv, wl, cube, params, cached, no_tune):
+    """Motion-search launch geometry per block size, tuned on the first P step
+    of exactly the batch the timed steps launch (outputs never depend on it)."""
+    tuning = {}
+    R = wl.search_range
+    for N in wl.blocks:
+        key = f"N{N}R{R}"
+        if cached is not None and key in cached:
+            g = cached[key]
+            xv.set_me_geometry(N, R, g["blocks_per_wg"], g["cands_per_lane"], g["threads"],
+                               g.get("rows_per_lane", 0), g.get("layout", 1))
+            tuning[key] = dict(g, tuned=True, from_file=True)
+        elif not no_tune:
+            _log(f"tuning motion search {wl.name} N={N} R={R}")
+            pn = [p for p in params if p.block == N]
+            tuning[key] = dict(xv.autotune_me_batch([cube] * len(pn), pn), tuned=True)
+        else:
+            tuning[key] = dict(xv.get_me_geometry(N, R, -(-wl.W // N)), tuned=False)
+    return tuning
+
+
+def run_workload(xv, torch, wl, cube, params, steps, warmup, mode="both", profile_me=True):
+    """Times the plain and batched forms; returns their throughput, the
+    metrics of the runs, and the kernel profile of the timed steps (motion
+    search only) and of one extra step (every class)."""
+    outs = [torch.empty_like(cube) for _ in params]
+    pxb_step = wl.px_band * len(params)
+
+    def step_plain(lat=None):
+        ms = []
+        for p, out in zip(params, outs):
+            t0 = time.perf_counter()
+            enc = xv.encode_cube(cube, p)
+            xv.decode_cube(enc, out)
+            ms.append(xv.psnr_bpppb(cube, enc))  # synchronises
+            enc.free()
+            if lat is not None:
+                lat.append((time.perf_counter() - t0) * 1e3)
+        return ms
+
+    def step_batched(lat=None):
+        t0 = time.perf_counter()
+        encs = xv.encode_batch([cube] * len(params), params)
+        xv.decode_batch(encs, outs)
+        ms = xv.psnr_bpppb_batch([cube] * len(encs), encs)
+        for e in encs:
+            e.free()
+        if lat is not None:
+            lat.append((time.perf_counter() - t0) * 1e3)
+        return ms
+
+    def timed(fn, profile):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        lat = []
+        if profile:
+            # only the dominant kernel (motion search) is event-timed inside
+            # the timed region: every event pair costs queue time
+            xv.profile_select([xv.K_ME])
+            xv.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ms = fn(lat)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = xv.profile_read() if profile else None
+        if profile:
+            xv.profile_enable(False)
+        return dt, lat, ms, prof
+
+    res, prof, prof_all = {}, None, None
+    ms_plain = ms_batch = None
+    if mode in ("both", "plain"):
+        _log(f"{wl.name}: plain path")
+        dt, lat, ms_plain, _ = timed(step_plain, profile=False)
+        res["plain"] = dict(value=pxb_step * steps / dt / 1e6, ms_per_step=dt / steps * 1e3,
+                            p50_ms=_percentile(lat, 0.5), p99_ms=_percentile(lat, 0.99),
+                            latency_unit="one run: encode+decode+metrics")
+    if mode in ("both", "batched"):
+        _log(f"{wl.name}: batched path")
+        dt, lat, ms_batch, prof = timed(step_batched, profile=profile_me)
+        # every kernel class, timed on one more step outside the timed region
+        xv.profile_select(None)
+        xv.profile_enable(True)
+        step_batched()
+        prof_all = xv.profile_read()
+        xv.profile_enable(False)
+        res["batched"] = dict(value=pxb_step * steps / dt / 1e6, ms_per_step=dt / steps * 1e3,
+                              p50_ms=_percentile(lat, 0.5), p99_ms=_percentile(lat, 0.99),
+                              latency_unit=f"one step: all {len(params)} runs")
+    if ms_plain is not None and ms_batch is not None:
+        same = all(a["psnr"] == b["psnr"] and a["bpppb"] == b["bpppb"]
+                   and a["coef_bits"] == b["coef_bits"] and a["mv_bits"] == b["mv_bits"]
+                   for a, b in zip(ms_plain, ms_batch))
+        if not same:
+            raise SystemExit(f"{wl.name}: batched and plain paths disagree")
+    del outs
+    return dict(res=res, ms=ms_batch if ms_batch is not None else ms_plain, prof=prof,
+                prof_all=prof_all, pxb_step=pxb_step)
+
+
+def rooflines(r, traffic):
+    """Roofline objects: motion search from the timed steps, the transform and
+    decode kernels from the extra fully profiled step."""
+    out = {}
+    prof, prof_all = r["prof"], r["prof_all"]
+    traffic = traffic or {}
+    if prof is not None and prof["me"]["launches"]:
+        me = prof["me"]
+        avg_ms = me["ms"] / me["launches"]
+        terms = me["work"] / me["launches"]
+        achieved = terms / (avg_ms * 1e-3) / 1e12
+        out["roofline"] = {"kernel": "motion search (me_rp_kernel / me_kernel)", "bound": "alu",
+                           "achieved": round(achieved, 3), "peak": round(SAD_PEAK_TTERMS, 2),
+                           "unit": "T SAD-terms/s", "frac": round(achieved / SAD_PEAK_TTERMS, 4),
+                           "traffic": round(traffic["me"]) if "me" in traffic else None,
+                           "traffic_unit": "bytes per launch",
+                           "avg_launch_ms": round(avg_ms, 4), "launches": me["launches"],
+                           "terms_per_launch": terms,
+                           "timed": "HIP events around every motion-search launch of the timed "
+                                    "steps (no other class timed there)"}
+    if prof_all is not None:
+        for key, kname, label in (("roofline_encode", "encode_kernel",
+                                   "encode_kernel (fused transform coding)"),
+                                  ("roofline_decode", "decode_kernel", "decode_kernel")):
+            d = prof_all[kname.split("_")[0]]
+            if not d["launches"]:
+                continue
+            avg = d["ms"] / d["launches"]
+            gbs = d["work"] / d["launches"] / (avg * 1e-3) / 1e9
+            out[key] = {"kernel": label, "bound": "hbm", "achieved": round(gbs, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": round(traffic[kname]) if kname in traffic else None,
+                        "traffic_unit": "bytes per launch",
+                        "algorithmic_bytes_per_launch": round(d["work"] / d["launches"]),
+                        "avg_launch_ms": round(avg, 4), "launches": d["launches"],
+                        "timed": "one batched step after the timed region, every class timed"}
+        out["kernel_ms_per_step"] = {k: round(v["ms"], 3) for k, v in prof_all.items()
+                                     if v["launches"]}
+    return out
+
+
+def forms_summary(res):
+    return {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+            for k, v in res.items()}
+
+
+def cpu_baseline(cube_host, wl, units_per_qp=8, frames_per_unit=4, cores=None):
+    """The oracle as it stands, on the host cores, on a bounded sample of the
+    headline step: for each QP, `units_per_qp` (group, GOP) units spread over
+    both groups and the cube's length, the first `frames_per_unit` pictures of
+    each (the I picture and P pictures with the full search), encoded and then
+    decoded, one unit per host thread.  The oracle's band statistics run over
+    the whole cube; their time is prorated to the sample's share of the step."""
+    import numpy as np
     from oracle import oracle as O
     O.lib()
-    runs = [(qp, N) for N in wl.blocks for qp in wl.qps]
+    if cores is None:
+        cores = max(1, min(int(os.environ.get("OMP_NUM_THREADS", "16")), os.cpu_count() or 1))
+    T, H, W, Bn = cube_host.shape
+    G = (Bn + 2) // 3
+    ngop = -(-T // wl.gop)
     t0 = time.perf_counter()
-    for qp, N in runs:
-        p = O.CodingParams(bit_depth=wl.bit_depth, qp=qp, block=N, search_range=wl.search_range,
-                           gop=wl.gop, pad_mode=wl.pad_mode, fill_mode=wl.fill_mode)
-        enc = O.encode_cube(cube_host, p)
-        rec = O.decode_cube(p, cube_host.shape, enc["levels"], enc["mvs"])
-        O.denormalize_cube(rec, cube_host.shape, N, wl.bit_depth, enc["mn"], enc["mx"],
-                           O.F32 if cube_host.dtype.name == "float32" else O.U16)
-        O.metrics(cube_host, enc, p)
-    dt = time.perf_counter() - t0
-    pxb = wl.px_band * len(runs)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pxb / dt / 1e6, "unit": "Mpx·band/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full step: all {len(runs)} runs on the {wl.T}x{wl.H}x{wl.W}x"
-                      f"{wl.bands} cube, encode+decode+metrics, {dt:.1f} s wall"}
+    mn, mx, _ = O.stats(cube_host)
+    t_stats = time.perf_counter() - t0
+    gops = np.linspace(0, ngop - 1, units_per_qp // G).round().astype(int)
+    units = [(qp, g, int(k) * wl.gop, min(frames_per_unit, T - int(k) * wl.gop))
+             for qp in wl.qps for g in range(G) for k in gops]
+
+    def one(u):
+        qp, g, t0_, n = u
+        p = O.CodingParams(bit_depth=wl.bit_depth, qp=qp, block=wl.blocks[0],
+                           search_range=wl.search_range, gop=wl.gop, pad_mode=wl.pad_mode,
+                           fill_mode=wl.fill_mode)
+        o = O.encode_gop(cube_host, mn, mx, p, g, t0_, n)
+        O.decode_gop(p, H, W, o["levels"], o["mvs"])
+        return min(3, Bn - 3 * g) * n * H * W
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        pxb = sum(ex.map(one, units))
+    t_units = time.perf_counter() - t0
+    step_pxb = wl.px_band * len(wl.qps) * len(wl.blocks)
+    t = t_units + t_stats * pxb / step_pxb
+    return {"value": pxb / t / 1e6, "unit": "Mpx·band/s", "cores": min(cores, len(units)),
+            "kind": "oracle",
+            "sample": f"{len(units)} (QP, group, GOP) units of the {wl.T}x{wl.H}x{wl.W}x{wl.bands} "
+                      f"cube (QP {list(wl.qps)} x groups 0..{G - 1} x GOPs {gops.tolist()}), the "
+                      f"first {frames_per_unit} pictures of each (I + {frames_per_unit - 1} P, "
+                      f"full search R={wl.search_range}), encode + decode, one unit per host "
+                      f"thread: {pxb / 1e6:.1f} Mpx·band in {t_units:.1f} s wall, plus the "
+                      f"whole-cube band statistics ({t_stats:.1f} s) prorated to the sample "
+                      f"({pxb / step_pxb:.4f} of a step). A whole unit has 15 P pictures per I, "
+                      f"so the sample slightly favours the oracle."}
 
 
 def quality_bench(xv, torch, cube, params, runs, steps):
     """SSIM of the coded planes (xv_ssim) and spectral angle of the decoded
-    cube (xv_spectral_angle) for every run of the sweep: the values, and the
-    kernel time per step of all runs from HIP events."""
+    cube (xv_spectral_angle) for every run: the values, and the kernel time
+    per step of all runs from HIP events."""
     encs = xv.encode_batch([cube] * len(params), params)
     outs = [torch.empty_like(cube) for _ in params]
     xv.decode_batch(encs, outs)
@@ -111,6 +321,7 @@ def quality_bench(xv, torch, cube, params, runs, steps):
     xv.profile_enable(False)
     for e in encs:
         e.free()
+    del outs
     pxb = cube.numel() * len(params)
     out = {"ssim_mean_per_run": [round(sum(s) / len(s), 6) for s, _ in vals],
            "spectral_angle_rad_per_run": [round(a, 8) for _, (a, _) in vals],
@@ -125,10 +336,9 @@ def quality_bench(xv, torch, cube, params, runs, steps):
 
 
 def bits_bench(xv, torch, cube, params, pxb_step, steps):
-    """Serialise the sweep's 15 encoded runs (xv_pack) and parse them back
-    (xv_unpack), timed per call on the host (each call synchronises once) and
-    per kernel with HIP events; checks that the parsed levels equal the
-    encoded ones."""
+    """Serialise the encoded runs (xv_pack) and parse them back (xv_unpack),
+    timed per call on the host (each call synchronises once) and per kernel
+    with HIP events; checks that the parsed levels equal the encoded ones."""
     import numpy as np
     encs = xv.encode_batch([cube] * len(params), params)
     torch.cuda.synchronize()
@@ -156,9 +366,11 @@ def bits_bench(xv, torch, cube, params, pxb_step, steps):
             p.free()
     prof = xv.profile_read()
     xv.profile_enable(False)
-    same = all(np.array_equal(a.export()["levels"].cpu().numpy(),
-                              b.export()["levels"].cpu().numpy())
-               for a, b in [(encs[0], xv.unpack(xv.pack(encs[0]).tensor()))])
+    pk = xv.pack(encs[0])
+    up = xv.unpack(pk.tensor())
+    same = bool(torch.equal(up.export()["levels"], encs[0].export()["levels"]))
+    up.free()
+    pk.free()
     wr, pa = prof["bits_write"], prof["bits_parse"]
     coded = sum(e.export()["levels"].numel() for e in encs)  # coded samples (levels read)
     out = {"runs": len(encs), "payload_MB_per_step": round(payload / 8 / 1e6, 3),
@@ -166,7 +378,7 @@ def bits_bench(xv, torch, cube, params, pxb_step, steps):
            "unpack_ms_per_step": round(t_unpack / steps * 1e3, 3),
            "pack_Mpx_band_s": round(pxb_step * steps / t_pack / 1e6, 1),
            "unpack_Mpx_band_s": round(pxb_step * steps / t_unpack / 1e6, 1),
-           "parsed_equals_encoded": bool(same)}
+           "parsed_equals_encoded": same}
     if wr["launches"]:
         ms = wr["ms"] / steps
         out["write_kernel_ms_per_step"] = round(ms, 3)
@@ -180,15 +392,16 @@ def bits_bench(xv, torch, cube, params, pxb_step, steps):
     return out
 
 
-def serve_bench(xv, synth, torch, n=160, seed=4, loads=(0.5, 0.9, 1.2, 2.0)):
+def serve_bench(xv, synth, torch, n=160, seed=4, loads=(0.5, 0.9, 1.2, 2.0),
+                t_range=(16, 96), s_range=(64, 256)):
     """Serving mix: requests with the mix's recipe (encode or decode with
     p = 1/2, log-uniform sizes, bands {3, 4, 6}, QP 17..37, N = 16, R = 16)
-    at sizes capped to T <= 96 and side <= 256 so the run takes seconds.
-    Offered loads are fractions of the plain path's measured capacity; the
-    plain baseline serves the same arrivals one request at a time."""
+    at sizes capped to t_range and s_range.  Offered loads are fractions of
+    the plain path's measured capacity; the plain baseline serves the same
+    arrivals one request at a time."""
     import numpy as np
     dev = torch.device("cuda:0")
-    reqs = synth.request_trace(n, rate_per_s=1.0, seed=seed, t_range=(16, 96), s_range=(64, 256))
+    reqs = synth.request_trace(n, rate_per_s=1.0, seed=seed, t_range=t_range, s_range=s_range)
     items = []
     for r in reqs:
         cube = synth.tiny_cube(seed=r.seed, T=r.T, H=r.S, W=r.S, bands=r.bands, device=dev)
@@ -219,8 +432,9 @@ def serve_bench(xv, synth, torch, n=160, seed=4, loads=(0.5, 0.9, 1.2, 2.0)):
     cap_s = time.perf_counter() - t0
     mean_service = cap_s / len(items)
     out = {"requests": len(items), "px_band_total": total_pxb,
-           "trace": "Poisson arrivals; encode/decode p=1/2; T log-uniform 16..96, side "
-                    "log-uniform 64..256 (multiple of 32), bands {3,4,6}, QP 17..37, N=16, R=16",
+           "trace": f"Poisson arrivals; encode/decode p=1/2; T log-uniform {t_range[0]}.."
+                    f"{t_range[1]}, side log-uniform {s_range[0]}..{s_range[1]} (multiple of "
+                    f"32), bands {{3,4,6}}, QP 17..37, N=16, R=16",
            "plain_capacity_mpxb_s": round(total_pxb / cap_s / 1e6, 3), "loads": []}
     rng = np.random.default_rng(seed + 1)
     gaps_unit = rng.exponential(1.0, len(items))
@@ -265,7 +479,40 @@ def serve_bench(xv, synth, torch, n=160, seed=4, loads=(0.5, 0.9, 1.2, 2.0)):
             "plain": {"value": round(total_pxb / plain_span / 1e6, 3),
                       "p50_ms": round(_percentile(lat, 0.5), 3),
                       "p99_ms": round(_percentile(lat, 0.99), 3)}})
+    for it in items:
+        if it[0] == "decode":
+            it[1].free()
     return out
+
+
+def secondary(xv, torch, synth, name, steps, warmup, cached, no_tune):
+    """A secondary workload: plain and batched throughput and the rooflines."""
+    wl = synth.WORKLOADS[name]
+    _log(f"generating {name} cube")
+    cube = synth.make_cube(name, device="cuda")
+    torch.cuda.synchronize()
+    runs, params = workload_params(xv, wl)
+    tuning = tune(xv, wl, cube, params, cached, no_tune)
+    r = run_workload(xv, torch, wl, cube, params, steps, warmup)
+    out = {"workload": describe(wl), "px_band_per_step": r["pxb_step"],
+           "forms": forms_summary(r["res"]), "me_geometry": tuning,
+           "psnr_db_mean_per_run": [round(sum(m["psnr"]) / len(m["psnr"]), 4) for m in r["ms"]],
+           "bpppb_per_run": [round(m["bpppb"], 5) for m in r["ms"]],
+           "runs": [f"QP{qp}/N{N}" for qp, N in runs]}
+    if "plain" in r["res"] and "batched" in r["res"]:
+        out["speedup_batched_vs_plain"] = round(r["res"]["batched"]["value"] /
+                                                r["res"]["plain"]["value"], 3)
+    out.update(rooflines(r, _measured_traffic(name)))
+    del cube
+    return out, tuning
+
+
+def free_device(xv, torch):
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    xv.cache_release()
 
 
 def main():
@@ -279,10 +526,14 @@ def main():
     ap.add_argument("--no-bits", action="store_true", help="skip the bitstream section")
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the SSIM / spectral-angle section")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the cloud-gapped sweep and the reanalysis-like cube")
     ap.add_argument("--counters", action="store_true",
                     help="workload for hardware-counter runs only: one 1 GiB device copy (the "
-                         "calibration of FETCH_SIZE / WRITE_SIZE), then one batched sweep step "
-                         "with the geometry file's geometry; prints no result line")
+                         "calibration of FETCH_SIZE / WRITE_SIZE), then one batched step of the "
+                         "--workload with the geometry file's geometry; prints no result line")
+    ap.add_argument("--workload", default=HEADLINE, choices=["planet", "s2cloud", "era5"],
+                    help="workload of the --counters run")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the motion-search geometry tuner (model defaults)")
     ap.add_argument("--geometry-file", default=None,
@@ -304,18 +555,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    wl = synth.WORKLOADS["s2cloud"]
-    print(f"[bench] generating {wl.name} cube on {dev}", file=sys.stderr, flush=True)
-    cube = synth.s2cloud_cube(device=dev)
-    torch.cuda.synchronize()
-    runs = [(qp, N) for N in wl.blocks for qp in wl.qps]
-    params = [xv.Params(bit_depth=wl.bit_depth, qp=qp, block=N, search_range=wl.search_range,
-                        gop=wl.gop, pad_mode=wl.pad_mode, fill_mode=wl.fill_mode)
-              for qp, N in runs]
-    outs = [torch.empty_like(cube) for _ in runs]
-    pxb_step = wl.px_band * len(runs)
+    cached = None
+    if args.geometry_file and os.path.exists(args.geometry_file):
+        with open(args.geometry_file) as f:
+            cached = json.load(f)
+    all_tuning = {}
 
     if args.counters:
+        if cached is None:
+            raise SystemExit("--counters needs an existing --geometry-file")
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         src.fill_(1)
@@ -323,113 +571,29 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    # launch-geometry tuning (outside the timed region; outputs never depend on it)
-    tuning = {}
-    cached = None
-    if args.geometry_file and os.path.exists(args.geometry_file):
-        with open(args.geometry_file) as f:
-            cached = json.load(f)
-    for N in wl.blocks:
-        if cached is not None and f"N{N}" in cached:
-            g = cached[f"N{N}"]
-            xv.set_me_geometry(N, wl.search_range, g["blocks_per_wg"], g["cands_per_lane"],
-                               g["threads"], g.get("rows_per_lane", 0), g.get("layout", 1))
-            tuning[f"N{N}"] = dict(g, tuned=True, from_file=True)
-        elif not args.no_tune:
-            print(f"[bench] tuning motion search N={N}", file=sys.stderr, flush=True)
-            # tuned on the first P step of exactly the batch the timed steps launch
-            pn = [p for p in params if p.block == N]
-            t = xv.autotune_me_batch([cube] * len(pn), pn)
-            tuning[f"N{N}"] = dict(t, tuned=True)
-        else:
-            tuning[f"N{N}"] = dict(xv.get_me_geometry(N, wl.search_range, -(-wl.W // N)),
-                                   tuned=False)
-    if args.geometry_file and cached is None:
-        with open(args.geometry_file, "w") as f:
-            json.dump(tuning, f)
-
-    if args.counters:
-        if cached is None:
-            raise SystemExit("--counters needs an existing --geometry-file")
+        wl = synth.WORKLOADS[args.workload]
+        cube = synth.make_cube(args.workload, device=dev)
+        runs, params = workload_params(xv, wl)
+        tune(xv, wl, cube, params, cached, True)
+        outs = [torch.empty_like(cube) for _ in params]
         encs = xv.encode_batch([cube] * len(params), params)
         xv.decode_batch(encs, outs)
         torch.cuda.synchronize()
         for e in encs:
             e.free()
-        print("[bench] counter workload done", file=sys.stderr, flush=True)
+        _log("counter workload done")
         return
 
-    def step_plain(lat=None):
-        ms = []
-        for p, out in zip(params, outs):
-            t0 = time.perf_counter()
-            enc = xv.encode_cube(cube, p)
-            xv.decode_cube(enc, out)
-            ms.append(xv.psnr_bpppb(cube, enc))  # synchronises
-            enc.free()
-            if lat is not None:
-                lat.append((time.perf_counter() - t0) * 1e3)
-        return ms
-
-    def step_batched(lat=None):
-        t0 = time.perf_counter()
-        encs = xv.encode_batch([cube] * len(params), params)
-        xv.decode_batch(encs, outs)
-        ms = xv.psnr_bpppb_batch([cube] * len(encs), encs)
-        for e in encs:
-            e.free()
-        if lat is not None:
-            lat.append((time.perf_counter() - t0) * 1e3)
-        return ms
-
-    def timed(fn, profile):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        lat = []
-        if profile:
-            # only the dominant kernel (motion search) is event-timed inside
-            # the timed region: every event pair costs queue time
-            xv.profile_select([xv.K_ME])
-            xv.profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ms = fn(lat)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        prof = xv.profile_read() if profile else None
-        if profile:
-            xv.profile_enable(False)
-        return dt, lat, ms, prof
-
-    res = {}
-    prof_all = None
-    if args.mode in ("both", "plain"):
-        print("[bench] plain path", file=sys.stderr, flush=True)
-        dt, lat, ms_plain, _ = timed(step_plain, profile=False)
-        res["plain"] = dict(value=pxb_step * args.steps / dt / 1e6, ms_per_step=dt / args.steps * 1e3,
-                            p50_ms=_percentile(lat, 0.5), p99_ms=_percentile(lat, 0.99),
-                            latency_unit="one run: encode+decode+metrics")
-    if args.mode in ("both", "batched"):
-        print("[bench] batched path", file=sys.stderr, flush=True)
-        dt, lat, ms_batch, prof = timed(step_batched, profile=True)
-        # every kernel class, timed on one more step outside the timed region
-        xv.profile_select(None)
-        xv.profile_enable(True)
-        step_batched()
-        prof_all = xv.profile_read()
-        xv.profile_enable(False)
-        res["batched"] = dict(value=pxb_step * args.steps / dt / 1e6, ms_per_step=dt / args.steps * 1e3,
-                              p50_ms=_percentile(lat, 0.5), p99_ms=_percentile(lat, 0.99),
-                              latency_unit="one step: all 15 runs")
-    if "plain" in res and "batched" in res:
-        same = all(a["psnr"] == b["psnr"] and a["bpppb"] == b["bpppb"]
-                   for a, b in zip(ms_plain, ms_batch))
-        if not same:
-            raise SystemExit("batched and plain paths disagree")
-    ms = ms_batch if "batched" in res else ms_plain
+    wl = synth.WORKLOADS[HEADLINE]
+    _log(f"generating {wl.name} cube on {dev}")
+    cube = synth.make_cube(HEADLINE, device=dev)
+    torch.cuda.synchronize()
+    runs, params = workload_params(xv, wl)
+    tuning = tune(xv, wl, cube, params, cached, args.no_tune)
+    all_tuning.update(tuning)
+    r = run_workload(xv, torch, wl, cube, params, args.steps, args.warmup, args.mode)
+    res, ms = r["res"], r["ms"]
     main_form = "batched" if "batched" in res else "plain"
-
     line = {
         "metric": METRIC,
         "value": round(res[main_form]["value"], 3),
@@ -443,16 +607,12 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.T}x{wl.H}x{wl.W}x{wl.bands} f32 cube with ~10% "
-                               f"NaN cloud gaps, B={wl.bit_depth}, QP{list(wl.qps)} x "
-                               f"N{list(wl.blocks)} (15 runs), R={wl.search_range}, "
-                               f"GOP {wl.gop}", "form": main_form,
-                   "px_band_per_step": pxb_step},
+        "config": {"workload": describe(wl), "form": main_form,
+                   "px_band_per_step": r["pxb_step"]},
         "me_geometry": tuning,
         "p50_ms": round(res[main_form]["p50_ms"], 3),
         "p99_ms": round(res[main_form]["p99_ms"], 3),
-        "forms": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                  for k, v in res.items()},
+        "forms": forms_summary(res),
         "quality": {"psnr_db_mean_per_run": [round(float(np.mean(m["psnr"])), 4) for m in ms],
                     "psnr_phys_db_mean_per_run": [round(float(np.mean(m["psnr_phys"])), 4)
                                                   for m in ms],
@@ -461,52 +621,37 @@ def main():
     }
     if "plain" in res and "batched" in res:
         line["speedup_batched_vs_plain"] = round(res["batched"]["value"] / res["plain"]["value"], 3)
-    if prof is not None:
-        traffic = _measured_traffic() or {}
-        me = prof["me"]                  # timed region (motion search only)
-        enc = prof_all["encode"]         # one extra step, every class timed
-        dec = prof_all["decode"]
-        me_avg_ms = me["ms"] / max(1, me["launches"])
-        me_terms = me["work"] / max(1, me["launches"])
-        achieved = me_terms / (me_avg_ms * 1e-3) / 1e12
-        line["roofline"] = {"kernel": "motion search (me_rp_kernel / me_kernel)", "bound": "alu",
-                            "achieved": round(achieved, 3), "peak": round(SAD_PEAK_TTERMS, 2),
-                            "unit": "T SAD-terms/s", "frac": round(achieved / SAD_PEAK_TTERMS, 4),
-                            "traffic": round(traffic["me"]) if "me" in traffic else None,
-                            "traffic_unit": "bytes per launch",
-                            "avg_launch_ms": round(me_avg_ms, 4),
-                            "launches": me["launches"], "terms_per_launch": me_terms,
-                            "timed": "HIP events around every motion-search launch of the timed "
-                                     "steps (no other class timed there)"}
-        for name, d in (("encode_kernel (fused transform coding)", enc),
-                        ("decode_kernel", dec)):
-            if d["launches"]:
-                avg = d["ms"] / d["launches"]
-                gbs = d["work"] / d["launches"] / (avg * 1e-3) / 1e9
-                kname = name.split(" ")[0]
-                key = "roofline_encode" if name.startswith("encode") else "roofline_decode"
-                line[key] = {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1),
-                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(gbs / HBM_PEAK_GBS, 4),
-                             "traffic": (round(traffic[kname]) if kname in traffic else None),
-                             "traffic_unit": "bytes per launch",
-                             "algorithmic_bytes_per_launch": round(d["work"] / d["launches"]),
-                             "avg_launch_ms": round(avg, 4), "launches": d["launches"],
-                             "timed": "one batched step after the timed region, every class timed"}
-        line["kernel_ms_per_step"] = {k: round(v["ms"], 3) for k, v in prof_all.items()
-                                      if v["launches"]}
+    line.update(rooflines(r, _measured_traffic(HEADLINE)))
+    qsteps = max(1, min(args.steps, 5))
     if not args.no_quality:
-        print("[bench] quality metrics", file=sys.stderr, flush=True)
-        line["quality_metrics"] = quality_bench(xv, torch, cube, params, runs, args.steps)
+        _log("quality metrics")
+        line["quality_metrics"] = quality_bench(xv, torch, cube, params, runs, qsteps)
     if not args.no_bits:
-        print("[bench] bitstream", file=sys.stderr, flush=True)
-        line["bitstream"] = bits_bench(xv, torch, cube, params, pxb_step, args.steps)
-    if not args.no_serve:
-        print("[bench] serving mix", file=sys.stderr, flush=True)
-        line["served"] = serve_bench(xv, synth, torch)
+        _log("bitstream")
+        line["bitstream"] = bits_bench(xv, torch, cube, params, r["pxb_step"], qsteps)
+    host = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(cube.cpu().numpy(), wl)
+        host = cube.cpu().numpy()
+    del cube, r
+    free_device(xv, torch)
+    if not args.no_secondary:
+        sec = {}
+        for name in ("s2cloud", "era5"):
+            sec[name], t = secondary(xv, torch, synth, name, max(1, min(args.steps, 10)),
+                                     max(1, min(args.warmup, 2)), cached, args.no_tune)
+            all_tuning.update(t)
+            free_device(xv, torch)
+        line["secondary"] = sec
+    if not args.no_serve:
+        _log("serving mix")
+        line["served"] = serve_bench(xv, synth, torch)
+        free_device(xv, torch)
+    if args.geometry_file and cached is None:
+        with open(args.geometry_file, "w") as f:
+            json.dump(all_tuning, f, indent=1)
+    if host is not None:
+        _log("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(host, wl)
     print(json.dumps(line), flush=True)
 
 

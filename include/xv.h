@@ -152,8 +152,12 @@ const char* xv_last_error(void);
 int xv_encode_cube(const xv_cube* in, const xv_params* p, void* hip_stream,
                    xv_encoded** out);
 
-/* Decode an encoded cube into out (device memory owned by the caller, same
- * T, H, W, bands as the encoded cube, dtype XV_U16 or XV_F32).  Output
+/* Decode an encoded cube into out: the reverse of the encode, the library's
+ * video-to-cube step (Sec. II-A, `video2xarray`): prediction from the stored
+ * vectors, dequantisation and inverse transform to the reconstruction, then
+ * the B-bit samples mapped back through the stored band minima and maxima.
+ * out is device memory owned by the caller, with the same T, H, W, bands as
+ * the encoded cube and dtype XV_U16 or XV_F32.  Output
  * samples are min + q (max - min) / (2^B - 1) rounded half up and clamped
  * (u16) or rounded to the nearest float (f32).  Missing samples of the
  * original decode to their filled values.  Errors: XV_EINVAL (shape or dtype
@@ -209,9 +213,9 @@ void xv_encoded_free(xv_encoded* e);
 
 /* Encode n cubes of possibly different shapes and parameters.  Every frame
  * step launches one kernel per (block size, search range) class covering all
- * cubes, and the whole step sequence is replayed from a captured HIP graph.
- * Outputs are identical to n calls of xv_encode_cube.  outs[i] receive the
- * encoded cubes (all NULL on error). */
+ * cubes (motion search, then transform coding), launched eagerly on
+ * hip_stream.  Outputs are identical to n calls of xv_encode_cube.  outs[i]
+ * receive the encoded cubes (all NULL on error). */
 int xv_encode_batch(int n, const xv_cube* cubes, const xv_params* params,
                     void* hip_stream, xv_encoded** outs);
 

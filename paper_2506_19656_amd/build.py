@@ -21,7 +21,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libxv.so")
 
 SOURCES = ["k_prep.hip", "k_me.hip", "k_xform.hip", "k_bits.hip", "k_quality.hip", "xv_alloc.cpp",
-           "xv_api.cpp"]
+           "xv_runtime.cpp", "xv_api.cpp", "xv_quality_api.cpp", "xv_tune.cpp", "xv_bitstream.cpp",
+           "xv_server.cpp"]
 
 ARCH = os.environ.get("XV_OFFLOAD_ARCH", "gfx950")
 
@@ -53,7 +54,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

@@ -19,11 +19,16 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_traffic_summary_is_gated_on_the_kernel_sources():
     sys.path.insert(0, ROOT)
     import bench
-    with open(os.path.join(ROOT, "profiles", "s2cloud_sweep_hbm_traffic.json")) as f:
-        t = json.load(f)
-    assert set(t["sources_sha256"]) and t["per_launch_bytes"]
-    got = bench._measured_traffic()
-    # either the committed figures (sources unchanged) or None, never stale numbers
-    if got is not None:
-        assert set(got) >= {"encode_kernel", "decode_kernel", "me"}
-        assert all(v > 0 for v in got.values())
+    for name in ("planet", "s2cloud", "era5"):
+        path = bench.traffic_file(name)
+        if not os.path.exists(path):
+            assert bench._measured_traffic(name) is None
+            continue
+        with open(path) as f:
+            t = json.load(f)
+        assert set(t["sources_sha256"]) and t["per_launch_bytes"]
+        got = bench._measured_traffic(name)
+        # either the committed figures (sources unchanged) or None, never stale numbers
+        if got is not None:
+            assert set(got) >= {"encode_kernel", "decode_kernel", "me"}
+            assert all(v > 0 for v in got.values())

@@ -118,3 +118,31 @@ def test_corrupt_buffers_are_rejected():
     # the intact buffer still parses
     un = xv.unpack(good)
     assert np.array_equal(un.host()["levels"], enc.host()["levels"])
+
+
+def test_header_offsets_near_two_to_the_64_are_rejected():
+    """Offsets whose sums would wrap around 2^64 are refused by the header
+    checks, before any kernel reads the buffer."""
+    host = _textured(4, 32, 32, 3, seed=11)
+    cube = torch.from_numpy(host).cuda()
+    enc = xv.encode_cube(cube, xv.Params(bit_depth=10, qp=22, block=8, search_range=4, gop=4))
+    pk = xv.pack(enc)
+    good = pk.tensor().clone()
+    hdr = good[:256].cpu().numpy().copy()
+    fields = {"off_span": 136, "span_bytes": 144, "off_index": 152, "off_payload": 160,
+              "nwords": 128, "payload_bits": 120, "nseg": 112}
+    live0 = xv.memory_read()["live_bytes"]
+    for name, off in fields.items():
+        orig = int(hdr[off:off + 8].view(np.uint64)[0])
+        for val in (2 ** 64 - 8, 2 ** 64 - 1 - orig, 2 ** 63 + orig):
+            bad = good.clone()
+            h = hdr.copy()
+            h[off:off + 8] = np.array([val % 2 ** 64], np.uint64).view(np.uint8)
+            bad[:256] = torch.from_numpy(h).cuda()
+            with pytest.raises(xv.XvError) as ei:
+                xv.unpack(bad)
+            assert ei.value.code == xv.EINVAL, (name, val)
+    torch.cuda.synchronize()
+    assert xv.memory_read()["live_bytes"] == live0
+    un = xv.unpack(good)
+    assert np.array_equal(un.host()["levels"], enc.host()["levels"])

@@ -2,12 +2,13 @@
 benchmark times (tuned motion-search geometry, batched multi-run encode).
 
 The oracle cannot code a 6-9 GB cube in test time, so it computes sampled
-outputs one by one: whole GOP units of the cloud-gapped sweep, and the first
-pictures (I and P, full search) of sampled GOP units of the Planet-like and
-reanalysis-like cubes, from band statistics it computes itself over the whole
-cube.  Properties that hold at any size are checked on everything: decode ==
-encoder reconstruction, two encodes are identical, and the batched path equals
-the plain one."""
+outputs one by one: whole GOP units (every picture: converted frames, vectors,
+levels, reconstructions and bit counts) of the cloud-gapped sweep, of the
+Planet-like cube and of the reanalysis-like cube, including each cube's
+shorter last GOP, from band statistics it computes itself over the whole
+cube, and the decoded samples of those units on whole frames.  Properties
+that hold at any size are checked on everything: two encodes are identical,
+and the batched path equals the plain one."""
 import concurrent.futures as cf
 import hashlib
 
@@ -102,62 +103,87 @@ def test_s2cloud_full_sweep_sampled_units():
     assert _digest(again[0]) == _digest(encs[0]) and _digest(again[1]) == _digest(encs[1])
 
 
-def _first_pictures_parity(name, cube, p: xv.Params, units_k, nframes):
+def _unit_decode_reference(cube_host, mn, mx, p: xv.Params, g: int, recon_unit):
+    """The oracle's decoded samples of one unit: its reconstruction of group g
+    mapped back to the input dtype (other groups left out)."""
+    n = recon_unit.shape[0]
+    T, H, W, Bn = cube_host.shape
+    G = (Bn + 2) // 3
+    full = np.zeros((G,) + recon_unit.shape, np.uint16)
+    full[g] = recon_unit
+    dt = O.U16 if cube_host.dtype == np.uint16 else O.F32
+    return O.denormalize_cube(full, (n, H, W, Bn), p.block, p.bit_depth, mn, mx, dt)
+
+
+def _whole_unit_parity(name, cube, params, gops):
+    """Both runs of the workload encoded together as the benchmark encodes
+    them; for every run, band group and sampled GOP, the whole unit (all of
+    its pictures) compared with the oracle, and the decoded cube's samples of
+    that unit compared with the oracle's decode."""
     host = cube.cpu().numpy()
+    T, H, W, Bn = host.shape
+    G = (Bn + 2) // 3
     print(f"[case] {name}: oracle stats over {host.size} samples", flush=True)
     mn, mx, nv = O.stats(host)
-    xv.autotune_me(cube, p)
-    enc = xv.encode_batch([cube], [p])[0]
-    got_all = enc.export()
-    assert np.array_equal(got_all["band_min"].cpu().numpy(), mn)
-    assert np.array_equal(got_all["band_max"].cpu().numpy(), mx)
-    G = (host.shape[3] + 2) // 3
-    units = [(g, k * p.gop, nframes) for g in range(G) for k in units_k]
-    print(f"[case] {name}: oracle on units {units}", flush=True)
-    refs = _oracle_units(host, mn, mx, p, units)
-    for (g, t0, n), ref in zip(units, refs):
-        _compare(f"{name} unit g{g} t{t0}+{n}", _gpu_unit(enc, g, t0, n), ref)
-    # closed loop at full size: decode == denormalised encoder reconstruction
-    out = torch.empty_like(cube)
-    xv.decode_cube(enc, out)
-    m = xv.psnr_bpppb(cube, enc)
-    torch.cuda.synchronize()
-    rec_t = got_all["recon"]
-    for g in range(G):
-        for k in units_k[:1]:
-            t = k * p.gop + 1
-            q = rec_t[g, t].cpu().numpy().view(np.uint16)
-            for c in range(3):
-                b = 3 * g + c
-                if b >= host.shape[3]:
-                    continue
-                H, W = host.shape[1:3]
-                expect = np.array([O.cast_output(O.denormalize(int(v), mn[b], mx[b], p.bit_depth),
-                                                 O.U16 if host.dtype == np.uint16 else O.F32)
-                                   for v in q[c, :H, :W].ravel()[::997]])
-                got = out[t, :, :, b].cpu().numpy().ravel()[::997].astype(np.float64)
-                assert np.array_equal(got, expect), (name, g, t, c)
-    assert all(np.isfinite(m["psnr"])) and m["bpppb"] > 0
-    return enc
+    xv.autotune_me_batch([cube] * len(params), params)
+    encs = xv.encode_batch([cube] * len(params), params)
+    outs = [torch.empty_like(cube) for _ in params]
+    xv.decode_batch(encs, outs)
+    ms = xv.psnr_bpppb_batch([cube] * len(encs), encs)
+    for e in encs:
+        ex = e.export()
+        assert np.array_equal(ex["band_min"].cpu().numpy(), mn)
+        assert np.array_equal(ex["band_max"].cpu().numpy(), mx)
+        assert [int(v) for v in ex["n_valid"].cpu().numpy()] == [int(v) for v in nv]
+    jobs = []
+    for i, p in enumerate(params):
+        for g in range(G):
+            for k in gops:
+                t0 = k * p.gop
+                jobs.append((i, g, t0, min(p.gop, T - t0)))
+    print(f"[case] {name}: oracle on whole units (run, group, t0, len) {jobs}", flush=True)
+    op = {i: _op(p) for i, p in enumerate(params)}
+    with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        refs = list(ex.map(lambda j: O.encode_gop(host, mn, mx, op[j[0]], j[1], j[2], j[3]), jobs))
+    for (i, g, t0, n), ref in zip(jobs, refs):
+        tag = f"{name} QP{params[i].qp} unit g{g} t{t0}+{n}"
+        _compare(tag, _gpu_unit(encs[i], g, t0, n), ref)
+        # the decoded cube on the samples of this unit, whole frames
+        dref = _unit_decode_reference(host, mn, mx, params[i], g, ref["recon"])
+        b0, b1 = 3 * g, min(Bn, 3 * g + 3)
+        got = outs[i][t0:t0 + n, :, :, b0:b1].cpu().numpy()
+        exp = dref[:, :, :, b0:b1]
+        if not np.array_equal(got, exp):
+            d = np.argwhere(got != exp)
+            raise AssertionError(f"{tag}: decoded samples differ in {len(d)} places, "
+                                 f"first {d[0].tolist()}")
+        print(f"[case] {tag}: ok", flush=True)
+    assert all(np.isfinite(m["psnr"]).all() and m["bpppb"] > 0 for m in ms)
+    # the plain path gives the batched path's outputs
+    plain = xv.encode_cube(cube, params[-1])
+    assert _digest(plain) == _digest(encs[-1])
+    plain.free()
+    for e in encs:
+        e.free()
 
 
-@pytest.mark.timeout(900)
-def test_planet_full_size_sampled_first_pictures():
+@pytest.mark.timeout(1100)
+def test_planet_full_size_whole_units():
     wl = synth.WORKLOADS["planet"]
     print(f"[case] planet full {wl.T}x{wl.H}x{wl.W}x{wl.bands}", flush=True)
     cube = synth.planet_cube(device="cuda")
-    for qp in wl.qps:
-        p = xv.Params(bit_depth=wl.bit_depth, qp=qp, block=16, search_range=wl.search_range,
-                      gop=wl.gop, pad_mode=wl.pad_mode)
-        _first_pictures_parity(f"planet qp{qp}", cube, p, units_k=[0, 45], nframes=2)
+    params = [xv.Params(bit_depth=wl.bit_depth, qp=qp, block=16, search_range=wl.search_range,
+                        gop=wl.gop, pad_mode=wl.pad_mode) for qp in wl.qps]
+    # GOP 45 is the last one: frames 720..729, shorter than the others
+    _whole_unit_parity("planet", cube, params, gops=[17, 45])
 
 
 @pytest.mark.timeout(900)
-def test_era5_full_size_sampled_units():
+def test_era5_full_size_whole_units():
     wl = synth.WORKLOADS["era5"]
     print(f"[case] era5 full {wl.T}x{wl.H}x{wl.W}x{wl.bands}", flush=True)
     cube = synth.era5_cube(device="cuda")
-    for qp in wl.qps:
-        p = xv.Params(bit_depth=wl.bit_depth, qp=qp, block=32, search_range=wl.search_range,
-                      gop=wl.gop)
-        _first_pictures_parity(f"era5 qp{qp}", cube, p, units_k=[0, 46], nframes=4)
+    params = [xv.Params(bit_depth=wl.bit_depth, qp=qp, block=32, search_range=wl.search_range,
+                        gop=wl.gop) for qp in wl.qps]
+    # GOP 46 is the last one: frames 736..743
+    _whole_unit_parity("era5", cube, params, gops=[0, 23, 46])
