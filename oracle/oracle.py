@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("bit_depth", C.c_int32), ("qp", C.c_int32), ("block", C.c_int32),
                 ("search_range", C.c_int32), ("gop", C.c_int32),
-                ("pad_mode", C.c_int32), ("fill_mode", C.c_int32)]
+                ("pad_mode", C.c_int32), ("fill_mode", C.c_int32), ("qpel", C.c_int32)]
 
 
 @dataclass
@@ -50,10 +50,11 @@ class CodingParams:
     gop: int = 16
     pad_mode: int = PAD_ZERO
     fill_mode: int = FILL_NEAREST
+    qpel: int = 0
 
     def c(self) -> Params:
         return Params(self.bit_depth, self.qp, self.block, self.search_range,
-                      self.gop, self.pad_mode, self.fill_mode)
+                      self.gop, self.pad_mode, self.fill_mode, self.qpel)
 
 
 _lib = None
@@ -101,6 +102,11 @@ def lib():
         L.xvo_mv_bits.restype = C.c_uint32
         L.xvo_motion_search.argtypes = [p, p, i64, i64, C.c_int, C.c_int, C.c_int, i64,
                                         i64, p, p, p]
+        L.xvo_luma_filter.argtypes = [C.c_int, C.c_int]
+        L.xvo_interp_sample.argtypes = [p, i64, i64, C.c_int, i64, i64]
+        L.xvo_interp_sample.restype = C.c_int32
+        L.xvo_subpel_refine.argtypes = [p, p, i64, i64, C.c_int, C.c_int, C.c_int, i64, i64,
+                                        C.c_int, C.c_int, p, p, p]
         L.xvo_encode_gop.argtypes = [p, C.c_int, i64, i64, i64, i64, p, p,
                                      C.POINTER(Params), i64, i64, i64,
                                      p, p, p, p, p, p, p, p]
@@ -280,6 +286,31 @@ def motion_search(cur: np.ndarray, ref: np.ndarray, N: int, R: int, bx: int, by:
     lib().xvo_motion_search(_ptr(cur), _ptr(ref), Hp, Wp, N, R, nch, bx, by,
                             C.byref(dx), C.byref(dy), C.byref(sad))
     return dx.value, dy.value, sad.value
+
+
+def luma_filter(frac: int, tap: int) -> int:
+    """xvo_luma_filter: H.265 luma interpolation coefficient fL[frac][tap]."""
+    return lib().xvo_luma_filter(frac, tap)
+
+
+def interp_sample(plane: np.ndarray, B: int, xq: int, yq: int) -> int:
+    """xvo_interp_sample: predicted sample at quarter-sample position (xq, yq)."""
+    plane = np.ascontiguousarray(plane, np.uint16)
+    Hp, Wp = plane.shape
+    return lib().xvo_interp_sample(_ptr(plane), Hp, Wp, B, xq, yq)
+
+
+def subpel_refine(cur: np.ndarray, ref: np.ndarray, N: int, B: int, bx: int, by: int,
+                  dx: int, dy: int, nch: int = 3):
+    """xvo_subpel_refine: half- then quarter-sample refinement of (dx, dy);
+    returns (mvx, mvy, sad) with the vector in quarter samples."""
+    cur = np.ascontiguousarray(cur, np.uint16)
+    ref = np.ascontiguousarray(ref, np.uint16)
+    _, Hp, Wp = cur.shape
+    mx, my, sad = C.c_int32(), C.c_int32(), C.c_uint32()
+    lib().xvo_subpel_refine(_ptr(cur), _ptr(ref), Hp, Wp, N, B, nch, bx, by, dx, dy,
+                            C.byref(mx), C.byref(my), C.byref(sad))
+    return mx.value, my.value, sad.value
 
 
 # -- whole-GOP and whole-cube drivers ----------------------------------------

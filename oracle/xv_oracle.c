@@ -629,6 +629,129 @@ void xvo_motion_search(const uint16_t* cur, const uint16_t* ref, int64_t Hp,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Quarter-sample motion (one of the HEVC coding tools the paper's x265      */
+/* presets use, Appendix table of codec configurations; the paper describes  */
+/* none of its internals).  Reading: vectors in quarter samples; the         */
+/* prediction at a fractional position is the ITU-T H.265 luma fractional    */
+/* sample interpolation (clause 8.5.3.3.3.1: 8-tap filters, intermediate     */
+/* shifts shift1 = B - 8, shift2 = 6, shift3 = 14 - B, reference coordinates */
+/* clamped to the picture) followed by the default weighted sample           */
+/* prediction of a single reference (clause 8.5.3.3.4.2: round and shift by  */
+/* 14 - B, clip to [0, 2^B - 1]).  The three planes of a frame are           */
+/* independent bands (4:4:4, no colour transform), so every plane uses the   */
+/* luma filters.                                                             */
+/* ------------------------------------------------------------------------- */
+
+/* Filter coefficient fL[frac][tap] of H.265 (frac in quarter samples 0..3;  */
+/* tap 0..7 weighs the reference sample at integer offset tap - 3).          */
+int xvo_luma_filter(int frac, int tap) {
+  static const int f[4][8] = {{0, 0, 0, 64, 0, 0, 0, 0},
+                              {-1, 4, -10, 58, 17, -5, 1, 0},
+                              {-1, 4, -11, 40, 40, -11, 4, -1},
+                              {0, 1, -5, 17, 58, -10, 4, -1}};
+  return f[frac][tap];
+}
+
+static int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : v > hi ? hi : v; }
+
+static int32_t ref_at(const uint16_t* plane, int64_t Hp, int64_t Wp, int64_t x, int64_t y) {
+  return plane[clamp64(y, 0, Hp - 1) * Wp + clamp64(x, 0, Wp - 1)];
+}
+
+/* Predicted sample at the quarter-sample position (xq, yq) of a plane. */
+int32_t xvo_interp_sample(const uint16_t* plane, int64_t Hp, int64_t Wp, int B,
+                          int64_t xq, int64_t yq) {
+  const int64_t xi = xq >> 2, yi = yq >> 2; /* floor: arithmetic shifts */
+  const int fx = (int)(xq & 3), fy = (int)(yq & 3);
+  const int shift1 = B - 8, shift2 = 6, shift3 = 14 - B;
+  int32_t pred;
+  if (fx == 0 && fy == 0) {
+    pred = ref_at(plane, Hp, Wp, xi, yi) << shift3;
+  } else if (fy == 0) {
+    int32_t acc = 0;
+    for (int i = 0; i < 8; i++) acc += xvo_luma_filter(fx, i) * ref_at(plane, Hp, Wp, xi + i - 3, yi);
+    pred = acc >> shift1;
+  } else if (fx == 0) {
+    int32_t acc = 0;
+    for (int i = 0; i < 8; i++) acc += xvo_luma_filter(fy, i) * ref_at(plane, Hp, Wp, xi, yi + i - 3);
+    pred = acc >> shift1;
+  } else {
+    int32_t tmp[8];
+    for (int n = 0; n < 8; n++) {
+      int32_t acc = 0;
+      for (int i = 0; i < 8; i++)
+        acc += xvo_luma_filter(fx, i) * ref_at(plane, Hp, Wp, xi + i - 3, yi + n - 3);
+      tmp[n] = acc >> shift1;
+    }
+    int32_t acc = 0;
+    for (int i = 0; i < 8; i++) acc += xvo_luma_filter(fy, i) * tmp[i];
+    pred = acc >> shift2;
+  }
+  /* default weighted sample prediction, one reference */
+  const int shw = 14 - B;
+  int32_t v = (pred + (1 << (shw - 1))) >> shw;
+  const int32_t L = (1 << B) - 1;
+  return v < 0 ? 0 : v > L ? L : v;
+}
+
+/* SAD of the block (bx, by) against the prediction at vector (mx, my), in   */
+/* quarter samples, over the group's real channels.                          */
+static uint32_t subpel_sad(const uint16_t* cur, const uint16_t* ref, int64_t Hp, int64_t Wp,
+                           int N, int B, int nch, int64_t bx, int64_t by, int mx, int my) {
+  const int64_t x0 = bx * N, y0 = by * N;
+  uint32_t sad = 0;
+  for (int c = 0; c < nch; c++)
+    for (int i = 0; i < N; i++)
+      for (int j = 0; j < N; j++) {
+        int a = cur[(c * Hp + y0 + i) * Wp + x0 + j];
+        int b = xvo_interp_sample(ref + c * Hp * Wp, Hp, Wp, B, 4 * (x0 + j) + mx,
+                                  4 * (y0 + i) + my);
+        sad += (uint32_t)(a > b ? a - b : b - a);
+      }
+  return sad;
+}
+
+/* Refinement of an integer vector (dx, dy) (reading, as HEVC encoders do):  */
+/* the best of the centre and its 8 half-sample neighbours, then the best of */
+/* that and its 8 quarter-sample neighbours, each by the lexicographic       */
+/* minimum of (SAD, |mx| + |my|, my, mx) with the vector in quarter samples. */
+void xvo_subpel_refine(const uint16_t* cur, const uint16_t* ref, int64_t Hp,
+                       int64_t Wp, int N, int B, int nch, int64_t bx, int64_t by,
+                       int dx, int dy, int32_t* mvx, int32_t* mvy,
+                       uint32_t* best_sad) {
+  int cx = 4 * dx, cy = 4 * dy;
+  uint32_t bs = 0;
+  for (int step = 2; step >= 1; step--) {
+    int bx_ = cx, by_ = cy;
+    bs = UINT32_MAX;
+    int bl1 = 0;
+    for (int oy = -step; oy <= step; oy += step)
+      for (int ox = -step; ox <= step; ox += step) {
+        const int mx = cx + ox, my = cy + oy;
+        const uint32_t sad = subpel_sad(cur, ref, Hp, Wp, N, B, nch, bx, by, mx, my);
+        const int l1 = abs(mx) + abs(my);
+        int better = sad < bs;
+        if (sad == bs) {
+          if (l1 != bl1) better = l1 < bl1;
+          else if (my != by_) better = my < by_;
+          else better = mx < bx_;
+        }
+        if (better) {
+          bs = sad;
+          bl1 = l1;
+          bx_ = mx;
+          by_ = my;
+        }
+      }
+    cx = bx_;
+    cy = by_;
+  }
+  *mvx = cx;
+  *mvy = cy;
+  *best_sad = bs;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Coding of one closed group of pictures of one band group (paper silent on */
 /* codec internals; reading: an I picture predicted from the constant         */
 /* 2^(B-1), then P pictures predicted from the reconstruction of the picture  */
@@ -641,8 +764,18 @@ void xvo_motion_search(const uint16_t* cur, const uint16_t* ref, int64_t Hp,
 /*   mv_bits       : [len][Hb][Wb] u32                                        */
 /*   sse, nvalid   : [3] u64, over valid pixels of the coded GOP              */
 /* ------------------------------------------------------------------------- */
+/* Prediction of sample (x, y) of a P block from the reference plane: the    */
+/* displaced sample for integer vectors, the interpolated one for quarter-    */
+/* sample vectors.                                                            */
+static int predict_sample(const xvo_params* p, const uint16_t* ref_plane, int64_t Hp,
+                          int64_t Wp, int64_t x, int64_t y, int dx, int dy) {
+  if (p->qpel)
+    return xvo_interp_sample(ref_plane, Hp, Wp, p->bit_depth, 4 * x + dx, 4 * y + dy);
+  return ref_plane[(y + dy) * Wp + x + dx];
+}
+
 static void code_block(const xvo_params* p, int intra, const uint16_t* cur,
-                       const uint16_t* pred_plane, int64_t Wp,
+                       const uint16_t* pred_plane, int64_t Hp, int64_t Wp,
                        int64_t x0, int64_t y0, int dx, int dy, int16_t* lev_out,
                        uint16_t* rec_plane, uint32_t* bits_out) {
   int N = p->block, B = p->bit_depth;
@@ -651,7 +784,7 @@ static void code_block(const xvo_params* p, int intra, const uint16_t* cur,
   for (int i = 0; i < N; i++)
     for (int j = 0; j < N; j++) {
       int pv = intra ? (1 << (B - 1))
-                     : pred_plane[(y0 + dy + i) * Wp + x0 + dx + j];
+                     : predict_sample(p, pred_plane, Hp, Wp, x0 + j, y0 + i, dx, dy);
       pred[i * N + j] = pv;
       r[i * N + j] = (int32_t)cur[(y0 + i) * Wp + x0 + j] - pv;
     }
@@ -697,9 +830,17 @@ int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
         int32_t dx = 0, dy = 0;
         uint32_t sad = 0;
         int64_t bi = by * Wb + bx;
-        if (!intra)
+        if (!intra) {
           xvo_motion_search(cur, ref, Hp, Wp, N, p->search_range, nch, bx, by, &dx,
                             &dy, &sad);
+          if (p->qpel) {
+            int32_t qx, qy;
+            xvo_subpel_refine(cur, ref, Hp, Wp, N, p->bit_depth, nch, bx, by, dx, dy,
+                              &qx, &qy, &sad);
+            dx = qx;
+            dy = qy;
+          }
+        }
         mvs[(f * Hb * Wb + bi) * 2 + 0] = (int8_t)dx;
         mvs[(f * Hb * Wb + bi) * 2 + 1] = (int8_t)dy;
         mv_bits[f * Hb * Wb + bi] = intra ? 0 : xvo_mv_bits(dx, dy, pmx, pmy);
@@ -708,7 +849,7 @@ int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
         for (int c = 0; c < 3; c++) {
           int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + bi) * N * N;
           code_block(p, intra, cur + c * plane, ref ? ref + c * plane : NULL,
-                     Wp, bx * N, by * N, dx, dy, lev, rec + c * plane,
+                     Hp, Wp, bx * N, by * N, dx, dy, lev, rec + c * plane,
                      &coef_bits[(f * 3 + c) * Hb * Wb + bi]);
         }
       }
@@ -750,7 +891,7 @@ int xvo_decode_gop(const xvo_params* p, int64_t H, int64_t W, int64_t len,
             for (int j = 0; j < N; j++) {
               int64_t y = by * N + i, x = bx * N + j;
               int pv = f == 0 ? (1 << (B - 1))
-                              : ref[(c * Hp + y + dy) * Wp + x + dx];
+                              : predict_sample(p, ref + c * plane, Hp, Wp, x, y, dx, dy);
               int v = pv + rr[i * N + j];
               if (v < 0) v = 0;
               if (v > L) v = L;
@@ -773,6 +914,9 @@ int xvo_check_params(const xvo_params* p) {
   if (B < 8 || B > 12) return -1;
   if (p->qp < -6 * (B - 8) || p->qp > 51) return -1;
   if (p->search_range < 0 || p->search_range > 64) return -1;
+  if (p->qpel != 0 && p->qpel != 1) return -1;
+  /* quarter-sample vectors reach 4R + 3, which must fit int8 */
+  if (p->qpel && p->search_range > 31) return -1;
   if (p->gop < 1) return -1;
   if (p->pad_mode != XVO_PAD_ZERO && p->pad_mode != XVO_PAD_REPEAT) return -1;
   if (p->fill_mode != XVO_FILL_NEAREST && p->fill_mode != XVO_FILL_FORWARD) return -1;

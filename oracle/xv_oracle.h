@@ -27,6 +27,7 @@ typedef struct {
   int32_t gop;          /* closed GOP length, >= 1 */
   int32_t pad_mode;     /* XVO_PAD_* */
   int32_t fill_mode;    /* XVO_FILL_* */
+  int32_t qpel;         /* 1: quarter-sample motion (R <= 31), 0: integer */
 } xvo_params;
 
 int xvo_selfcheck(void);
@@ -64,6 +65,14 @@ uint32_t xvo_mv_bits(int mvx, int mvy, int pmx, int pmy);
 void xvo_motion_search(const uint16_t* cur, const uint16_t* ref, int64_t Hp,
                        int64_t Wp, int N, int R, int nch, int64_t bx,
                        int64_t by, int32_t* best_dx, int32_t* best_dy,
+                       uint32_t* best_sad);
+
+int xvo_luma_filter(int frac, int tap);
+int32_t xvo_interp_sample(const uint16_t* plane, int64_t Hp, int64_t Wp, int B,
+                          int64_t xq, int64_t yq);
+void xvo_subpel_refine(const uint16_t* cur, const uint16_t* ref, int64_t Hp,
+                       int64_t Wp, int N, int B, int nch, int64_t bx, int64_t by,
+                       int dx, int dy, int32_t* mvx, int32_t* mvy,
                        uint32_t* best_sad);
 
 int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
