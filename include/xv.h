@@ -202,6 +202,20 @@ int xv_ssim(const xv_encoded* e, double* ssim, void* hip_stream);
 int xv_spectral_angle(const xv_cube* orig, const xv_cube* decoded, double* mean_rad,
                       uint64_t* n_pixels, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as xv_spectral_angle, bit for bit, with no allocation of any kind.
+ * Its kernels keep their scratch (per-block partial sums and counts, 65,552
+ * bytes at most) in one static device array per GPU, held until the process
+ * ends; every call on a GPU shares that GPU's array, so calls that overlap
+ * on one GPU (on different streams or threads) race and must be serialised
+ * by the caller.  The caller passes both cubes (device memory) and the host
+ * outputs, as for xv_spectral_angle.  Synchronises hip_stream.  Errors:
+ * XV_EINVAL (shape mismatch, or a grid needing more scratch than the array
+ * holds, which no valid cube does), XV_EHIP. */
+int xv_spectral_angle_noalloc(const xv_cube* orig, const xv_cube* decoded, double* mean_rad,
+                              uint64_t* n_pixels, void* hip_stream);
+
 /* Fill a read-only view of the encoded cube's device buffers. */
 int xv_encoded_export(const xv_encoded* e, xv_export* v);
 

@@ -4,6 +4,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "xv_host.h"
 
@@ -61,8 +63,23 @@ int xv_ssim(const xv_encoded* e, double* ssim, void* hip_stream) {
   return XV_OK;
 }
 
-int xv_spectral_angle(const xv_cube* orig, const xv_cube* decoded, double* mean_rad,
-                      uint64_t* n_pixels, void* hip_stream) {
+}  // extern "C"
+
+// The allocation-free spectral angle's scratch: per-block sums and counts
+// of the largest grid of the per-block pass, then the two totals (65,552
+// bytes).  Each GPU holds its own copy for the life of the process; host code
+// reaches it only through the address hipGetSymbolAddress returns.
+constexpr int kSaMaxBlocks = 4096;
+constexpr size_t kSaScratchBytes = (size_t)kSaMaxBlocks * 16 + 16;
+static __device__ __align__(256) unsigned char scratch[kSaScratchBytes];
+
+namespace {
+
+// Checks the two cubes and fills the kernel arguments; *nblocks receives the
+// grid of the per-block pass (at most kSaMaxBlocks).
+
+int sa_setup(const xv_cube* orig, const xv_cube* decoded, double* mean_rad, SaArgs* a,
+             int* nblocks) {
   if (!mean_rad) return fail(XV_EINVAL, "null output");
   int rc = check_cube(orig, "original");
   if (rc != XV_OK) return rc;
@@ -70,23 +87,29 @@ int xv_spectral_angle(const xv_cube* orig, const xv_cube* decoded, double* mean_
   if (orig->T != decoded->T || orig->H != decoded->H || orig->W != decoded->W ||
       orig->bands != decoded->bands)
     return fail(XV_EINVAL, "spectral angle: cubes differ in shape");
-  hipStream_t s = (hipStream_t)hip_stream;
-  SaArgs a;
-  memset(&a, 0, sizeof a);
-  a.orig = orig->data;
-  a.dec = decoded->data;
-  a.dtype_orig = orig->dtype;
-  a.dtype_dec = decoded->dtype;
-  a.bands = (int)orig->bands;
-  a.npix = orig->T * orig->H * orig->W;
-  const int64_t want = (a.npix + kSaThreads - 1) / kSaThreads;
-  const int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
-  void* mem = nullptr;
-  hipError_t he = dev_alloc(&mem, (size_t)nblocks * 16 + 16, s);
-  if (he != hipSuccess) return fail(XV_ENOMEM, "spectral angle scratch: %s", hipGetErrorString(he));
+  memset(a, 0, sizeof *a);
+  a->orig = orig->data;
+  a->dec = decoded->data;
+  a->dtype_orig = orig->dtype;
+  a->dtype_dec = decoded->dtype;
+  a->bands = (int)orig->bands;
+  a->npix = orig->T * orig->H * orig->W;
+  const int64_t want = (a->npix + kSaThreads - 1) / kSaThreads;
+  *nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, kSaMaxBlocks));
+  return XV_OK;
+}
+
+// Bytes of scratch the kernels use for a grid of nblocks: per-block sums and
+// counts, then the two totals.
+size_t sa_scratch_bytes(int nblocks) { return (size_t)nblocks * 16 + 16; }
+
+// Launches the kernels with their scratch at `mem` and returns the mean.
+int sa_run(const xv_cube* orig, const xv_cube* decoded, SaArgs& a, int nblocks, void* mem,
+           hipStream_t s, double* mean_rad, uint64_t* n_pixels) {
   a.part_sum = (double*)mem;
   a.part_n = (unsigned long long*)(a.part_sum + nblocks);
   a.out = (double*)(a.part_n + nblocks);
+  hipError_t he;
   {
     const double ib = (orig->dtype == XV_U16 ? 2.0 : 4.0) + (decoded->dtype == XV_U16 ? 2.0 : 4.0);
     ProfScope ps(XV_K_QUALITY, s, (double)a.npix * a.bands * ib);
@@ -95,7 +118,6 @@ int xv_spectral_angle(const xv_cube* orig, const xv_cube* decoded, double* mean_
   uint64_t host[2] = {0, 0};
   if (he == hipSuccess) he = hipMemcpyAsync(host, a.out, 16, hipMemcpyDeviceToHost, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
-  dev_free(mem, s);
   if (he != hipSuccess) return fail(XV_EHIP, "spectral angle: %s", hipGetErrorString(he));
   double sum;
   memcpy(&sum, &host[0], 8);
@@ -103,6 +125,60 @@ int xv_spectral_angle(const xv_cube* orig, const xv_cube* decoded, double* mean_
   *mean_rad = n ? sum / (double)n : NAN;
   if (n_pixels) *n_pixels = n;
   return XV_OK;
+}
+
+// Device address of `scratch` on each device, looked up once per device
+// with that device current (the host-side name of the array is not a device
+// address).
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;
+
+int scratch_address(void** out) {
+  int dev = 0;
+  XV_HIP(hipGetDevice(&dev), "current device");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    XV_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "address of the scratch array");
+    if (!ptr) return fail(XV_EHIP, "scratch array has no device address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return XV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xv_spectral_angle(const xv_cube* orig, const xv_cube* decoded, double* mean_rad,
+                      uint64_t* n_pixels, void* hip_stream) {
+  SaArgs a;
+  int nblocks = 0;
+  int rc = sa_setup(orig, decoded, mean_rad, &a, &nblocks);
+  if (rc != XV_OK) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  void* mem = nullptr;
+  hipError_t he = dev_alloc(&mem, sa_scratch_bytes(nblocks), s);
+  if (he != hipSuccess) return fail(XV_ENOMEM, "spectral angle scratch: %s", hipGetErrorString(he));
+  rc = sa_run(orig, decoded, a, nblocks, mem, s, mean_rad, n_pixels);
+  dev_free(mem, s);
+  return rc;
+}
+
+int xv_spectral_angle_noalloc(const xv_cube* orig, const xv_cube* decoded, double* mean_rad,
+                              uint64_t* n_pixels, void* hip_stream) {
+  SaArgs a;
+  int nblocks = 0;
+  int rc = sa_setup(orig, decoded, mean_rad, &a, &nblocks);
+  if (rc != XV_OK) return rc;
+  if (sa_scratch_bytes(nblocks) > kSaScratchBytes)
+    return fail(XV_EINVAL, "spectral angle: %zu bytes of scratch needed, the static array "
+                "holds %zu", sa_scratch_bytes(nblocks), kSaScratchBytes);
+  void* mem = nullptr;
+  if ((rc = scratch_address(&mem)) != XV_OK) return rc;
+  return sa_run(orig, decoded, a, nblocks, mem, (hipStream_t)hip_stream, mean_rad, n_pixels);
 }
 
 }  // extern "C"

@@ -111,7 +111,8 @@ EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube"
             "xv_autotune_me", "xv_autotune_me_batch", "xv_profile_enable", "xv_profile_select", "xv_profile_read", "xv_server_create",
             "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
             "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release", "xv_pack", "xv_packed_view",
-            "xv_packed_free", "xv_unpack", "xv_ssim", "xv_spectral_angle"]
+            "xv_packed_free", "xv_unpack", "xv_ssim", "xv_spectral_angle",
+            "xv_spectral_angle_noalloc"]
 
 _lib = None
 
@@ -137,6 +138,8 @@ def lib():
         L.xv_ssim.argtypes = [vp, C.POINTER(C.c_double), vp]
         L.xv_spectral_angle.argtypes = [C.POINTER(Cube), C.POINTER(Cube), C.POINTER(C.c_double),
                                         C.POINTER(C.c_uint64), vp]
+        L.xv_spectral_angle_noalloc.argtypes = [C.POINTER(Cube), C.POINTER(Cube),
+                                                C.POINTER(C.c_double), C.POINTER(C.c_uint64), vp]
         L.xv_encoded_export.argtypes = [vp, C.POINTER(ExportC)]
         L.xv_encoded_free.argtypes = [vp]
         L.xv_encoded_free.restype = None
@@ -366,6 +369,16 @@ def spectral_angle(orig, decoded, stream=None):
     n = C.c_uint64()
     _check(lib().xv_spectral_angle(C.byref(_cube(orig)), C.byref(_cube(decoded)), C.byref(v),
                                    C.byref(n), _stream_handle(stream)))
+    return v.value, int(n.value)
+
+
+def spectral_angle_noalloc(orig, decoded, stream=None):
+    """xv_spectral_angle_noalloc: as spectral_angle, with the library's static
+    scratch array instead of any allocation."""
+    v = C.c_double()
+    n = C.c_uint64()
+    _check(lib().xv_spectral_angle_noalloc(C.byref(_cube(orig)), C.byref(_cube(decoded)),
+                                           C.byref(v), C.byref(n), _stream_handle(stream)))
     return v.value, int(n.value)
 
 
