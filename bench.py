@@ -15,9 +15,10 @@ Both produce bit-identical outputs (checked), hence identical PSNR and bpppb.
 
 Secondary sections (not the headline): the cloud-gapped Sentinel-2-like sweep
 (500 x 128 x 128 x 6 f32, 15 QP x N runs), the reanalysis-like cube
-(744 x 721 x 1440 x 3 f32, QP 17 and 27, N = 32, R = 8), SSIM / spectral
-angle and the bitstream on the headline runs, a small serving mix, and the
-oracle on the host cores on sampled GOP units of the headline cube.
+(744 x 721 x 1440 x 3 f32, QP 17 and 27, N = 32, R = 8), the sweep again with
+quarter-sample motion against integer vectors, SSIM / spectral angle and the
+bitstream on the headline runs, a small serving mix, and the oracle on the
+host cores on sampled GOP units of the headline cube.
 
 Prints ONE JSON line.  `value` is the batched throughput in Mpx*band/s of
 encode + decode (px*band = T*H*W*bands per run, summed over runs).
@@ -507,6 +508,58 @@ def secondary(xv, torch, synth, name, steps, warmup, cached, no_tune):
     return out, tuning
 
 
+def qpel_bench(xv, torch, synth, steps, warmup, cached, no_tune):
+    """Quarter-sample motion (XV_FLAG_QPEL) on the cloud-gapped sweep: the
+    15 runs coded with the refinement, batched, against the same runs with
+    integer vectors: throughput, the refinement kernel's share of the step,
+    and PSNR / bpppb of both."""
+    wl = synth.WORKLOADS["s2cloud"]
+    cube = synth.make_cube("s2cloud", device="cuda")
+    torch.cuda.synchronize()
+    runs, params = workload_params(xv, wl)
+    tune(xv, wl, cube, params, cached, no_tune)
+    qparams = [xv.Params(bit_depth=p.bit_depth, qp=p.qp, block=p.block,
+                         search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
+                         fill_mode=p.fill_mode, flags=xv.FLAG_QPEL) for p in params]
+    outs = [torch.empty_like(cube) for _ in params]
+
+    def step(ps):
+        encs = xv.encode_batch([cube] * len(ps), ps)
+        xv.decode_batch(encs, outs)
+        ms = xv.psnr_bpppb_batch([cube] * len(encs), encs)
+        for e in encs:
+            e.free()
+        return ms
+
+    out = {"workload": describe(wl) + "; every run coded twice: integer and quarter-sample "
+                                      "vectors", "runs": [f"QP{qp}/N{N}" for qp, N in runs]}
+    for name, ps in (("integer", params), ("quarter_sample", qparams)):
+        for _ in range(warmup):
+            step(ps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ms = step(ps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        xv.profile_select(None)
+        xv.profile_enable(True)
+        step(ps)
+        prof = xv.profile_read()
+        xv.profile_enable(False)
+        out[name] = {"value": round(wl.px_band * len(ps) * steps / dt / 1e6, 3),
+                     "ms_per_step": round(dt / steps * 1e3, 3),
+                     "psnr_db_mean_per_run": [round(sum(m["psnr"]) / len(m["psnr"]), 4) for m in ms],
+                     "bpppb_per_run": [round(m["bpppb"], 5) for m in ms],
+                     "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items()
+                                            if v["launches"]}}
+        if prof["subpel"]["launches"]:
+            sp = prof["subpel"]
+            out[name]["subpel_candidate_samples_per_s"] = sp["work"] / (sp["ms"] * 1e-3)
+    del outs, cube
+    return out
+
+
 def free_device(xv, torch):
     import gc
     gc.collect()
@@ -528,6 +581,8 @@ def main():
                     help="skip the SSIM / spectral-angle section")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the cloud-gapped sweep and the reanalysis-like cube")
+    ap.add_argument("--no-qpel", action="store_true",
+                    help="skip the quarter-sample motion section")
     ap.add_argument("--counters", action="store_true",
                     help="workload for hardware-counter runs only: one 1 GiB device copy (the "
                          "calibration of FETCH_SIZE / WRITE_SIZE), then one batched step of the "
@@ -642,6 +697,11 @@ def main():
             all_tuning.update(t)
             free_device(xv, torch)
         line["secondary"] = sec
+    if not args.no_qpel:
+        _log("quarter-sample motion")
+        line["quarter_sample"] = qpel_bench(xv, torch, synth, max(1, min(args.steps, 10)),
+                                            max(1, min(args.warmup, 2)), cached, args.no_tune)
+        free_device(xv, torch)
     if not args.no_serve:
         _log("serving mix")
         line["served"] = serve_bench(xv, synth, torch)

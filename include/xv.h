@@ -32,7 +32,8 @@
  *   levels                [G][T][3][Hb][Wb][N][N] i16 (block-major; inside a
  *                          block column-major: the level of vertical
  *                          frequency l, horizontal frequency k at k * N + l)
- *   motion vectors        [G][T][Hb][Wb][2] i8 (dx, dy); zero in I pictures
+ *   motion vectors        [G][T][Hb][Wb][2] i8 (dx, dy); zero in I pictures;
+ *                          in quarter samples under XV_FLAG_QPEL
  *   coefficient bits      [G][T][3][Hb][Wb] u32
  *   motion-vector bits    [G][T][Hb][Wb] u32
  */
@@ -46,7 +47,7 @@
 extern "C" {
 #endif
 
-#define XV_ABI_VERSION 4
+#define XV_ABI_VERSION 5
 
 /* status codes */
 #define XV_OK 0
@@ -74,6 +75,11 @@ extern "C" {
 #define XV_FLAG_DROP_WORK 1u /* free converted frames and reconstruction when
                                 the encode completes (physical PSNR and the
                                 export of those buffers become unavailable) */
+#define XV_FLAG_QPEL 2u      /* quarter-sample motion: the integer search's
+                                vector of each block refined to half and then
+                                quarter samples with the H.265 luma
+                                interpolation filters; vectors are stored in
+                                quarter samples (needs search_range <= 31) */
 
 #define XV_MAX_BANDS 64
 #define XV_MAX_GROUPS 22
@@ -92,7 +98,8 @@ typedef struct {
   int32_t bit_depth;    /* B in 8..12: samples are converted to [0, 2^B-1]  */
   int32_t qp;           /* -6(B-8)..51; qP = QP + 6(B-8) drives the step    */
   int32_t block;        /* N in {4, 8, 16, 32}: prediction and transform    */
-  int32_t search_range; /* R in 0..64: motion search over [-R, R]^2         */
+  int32_t search_range; /* R in 0..64 (0..31 with XV_FLAG_QPEL): motion
+                           search over [-R, R]^2                            */
   int32_t gop;          /* closed GOP length >= 1: one I then gop-1 P       */
   int32_t pad_mode;     /* XV_PAD_*                                          */
   int32_t fill_mode;    /* XV_FILL_*                                         */
@@ -371,7 +378,8 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
 #define XV_K_BITS_WRITE 7
 #define XV_K_BITS_PARSE 8
 #define XV_K_QUALITY 9
-#define XV_K_COUNT 10
+#define XV_K_SUBPEL 10 /* quarter-sample refinement and motion compensation */
+#define XV_K_COUNT 11
 
 typedef struct {
   double ms[XV_K_COUNT];       /* summed kernel time per kernel class     */

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libxv.so")
 
-SOURCES = ["k_prep.hip", "k_me.hip", "k_xform.hip", "k_bits.hip", "k_quality.hip", "xv_alloc.cpp",
+SOURCES = ["k_prep.hip", "k_me.hip", "k_xform.hip", "k_subpel.hip", "k_bits.hip", "k_quality.hip",
+           "xv_alloc.cpp",
            "xv_runtime.cpp", "xv_api.cpp", "xv_quality_api.cpp", "xv_tune.cpp", "xv_bitstream.cpp",
            "xv_server.cpp"]
 

@@ -976,6 +976,9 @@ __global__ void plan_kernel(CubePlan p) {
   jb.vmask = p.vmask ? p.vmask + f * 3 * plane : nullptr;
   jb.nan_total = p.nan_total;
   jb.part = p.part ? p.part + f * p.tpf * 5 : nullptr;
+  // one prediction plane per stream (g, k), reused by the stream's steps
+  const int ngop = (p.T + p.gop - 1) / p.gop;
+  jb.pred = (p.pred && s > 0) ? p.pred + ((int64_t)g * ngop + k) * 3 * plane : nullptr;
   jb.Hp = p.Hp;
   jb.Wp = p.Wp;
   jb.H = p.H;

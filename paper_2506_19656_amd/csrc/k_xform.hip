@@ -358,7 +358,7 @@ __device__ inline void store_row_packed(void* base, uint32_t off, const uint32_t
 }
 
 // Prediction row as packed pairs: I -> 2^(B-1); P -> the reference displaced
-// by (dx, dy).  A coded vector keeps the displaced block inside the padded
+// by (dx, dy), or with quarter-sample vectors the step's prediction plane.  A coded vector keeps the displaced block inside the padded
 // picture; the clamp only guarantees in-bounds reads for a corrupt vector.
 // The row is read as aligned dwords and shifted by one sample when the
 // displaced column is odd; the extra dword is then in bounds (rx + N is odd
@@ -371,11 +371,14 @@ __device__ inline void pred_row(const FrameJob& job, int c, int r, int y, int x0
 #pragma unroll
     for (int j = 0; j < N / 2; j++) pp[j] = h | (h << 16);
   } else {
+    // quarter-sample vectors: the step's prediction plane at displacement zero
+    const uint16_t* src = job.pred ? job.pred : job.ref;
+    if (job.pred) dx = dy = 0;
     const int ry = min(max(y - r + dy, 0), job.Hp - N) + r;
     const int rx = min(max(x0 + dx, 0), job.Wp - N);
     const uint32_t off = 2u * ((uint32_t)(c * job.Hp + ry) * (uint32_t)job.Wp + (uint32_t)(rx & ~1));
     // one row pointer with constant offsets, so that the loads merge
-    const XV_G uint32_t* rw = (const XV_G uint32_t*)((const XV_G char*)job.ref + off);
+    const XV_G uint32_t* rw = (const XV_G uint32_t*)((const XV_G char*)src + off);
     uint32_t w[N / 2 + 1];
 #pragma unroll
     for (int j = 0; j < N / 2; j++) w[j] = rw[j];

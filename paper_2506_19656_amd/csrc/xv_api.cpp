@@ -45,7 +45,9 @@ int check_params(const xv_params* p) {
   if (p->gop < 1) return fail(XV_EINVAL, "gop must be >= 1");
   if (p->pad_mode != XV_PAD_ZERO && p->pad_mode != XV_PAD_REPEAT) return fail(XV_EINVAL, "bad pad_mode");
   if (p->fill_mode != XV_FILL_NEAREST && p->fill_mode != XV_FILL_FORWARD) return fail(XV_EINVAL, "bad fill_mode");
-  if (p->flags & ~XV_FLAG_DROP_WORK) return fail(XV_EINVAL, "unknown flags");
+  if (p->flags & ~(XV_FLAG_DROP_WORK | XV_FLAG_QPEL)) return fail(XV_EINVAL, "unknown flags");
+  if ((p->flags & XV_FLAG_QPEL) && p->search_range > 31)
+    return fail(XV_EINVAL, "quarter-sample motion needs search_range <= 31 (int8 vectors)");
   return XV_OK;
 }
 
@@ -91,14 +93,21 @@ EncLayout enc_layout(const xv_encoded* e) {
   L.o_rc = w.take<uint16_t>((size_t)nframes * 3 * plane);
   L.o_vm = e->src_dtype == XV_F32 ? w.take<uint8_t>((size_t)nframes * 3 * plane) : 0;
   L.o_part = w.take<uint64_t>((size_t)nframes * xf_tiles_per_job(e->N, e->Hb, e->Wb) * 5);
+  L.o_pred = (e->p.flags & XV_FLAG_QPEL) ? w.take<uint8_t>(pred_plane_bytes(e)) : 0;
   L.work = w.off;
   return L;
+}
+
+size_t pred_plane_bytes(const xv_encoded* e) {
+  const int64_t ngop = (e->T + e->p.gop - 1) / e->p.gop;
+  return (size_t)e->G * ngop * 3 * (size_t)e->Hp * e->Wp * sizeof(uint16_t);
 }
 
 size_t decode_bytes(const xv_encoded* e) {
   Carve c;
   c.take<uint16_t>((size_t)e->G * e->T * 3 * (size_t)e->Hp * e->Wp);
   c.take<FrameJob>((size_t)e->njobs);
+  if (e->p.flags & XV_FLAG_QPEL) c.take<uint8_t>(pred_plane_bytes(e));
   return c.off;
 }
 
@@ -161,6 +170,7 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   e->recon = (uint16_t*)(wb + o_rc);
   e->vmask = in->dtype == XV_F32 ? (uint8_t*)(wb + o_vm) : nullptr;
   e->tile_part = (unsigned long long*)(wb + o_part);
+  e->pred = (p->flags & XV_FLAG_QPEL) ? (uint16_t*)(wb + lay.o_pred) : nullptr;
   e->tpf = xf_tiles_per_job(e->N, e->Hb, e->Wb);
   *out = e;
 
@@ -182,7 +192,7 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   }
   {
     CubePlan pl{e->frames, e->recon, e->levels, e->mvs, e->cbits, e->mbits, e->vmask,
-                e->nan_total, e->tile_part, e->jobs, (int32_t)T, e->G, p->gop, e->nsteps,
+                e->nan_total, e->tile_part, e->pred, e->jobs, (int32_t)T, e->G, p->gop, e->nsteps,
                 e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)bands, e->N,
                 p->bit_depth, p->qp, e->tpf};
     XV_HIP(launch_plan(pl, s), "plan kernel");
@@ -230,6 +240,8 @@ int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s) {
         return XV_OK;
       });
       if (rc != XV_OK) return rc;
+      uint64_t nl = 0;
+      if ((rc = launch_subpel_step(src, s, &nl)) != XV_OK) return rc;
     }
     int rc = launch_segments(src, 0, geom, [&](const LaunchDesc& d, double work) {
       ProfScope ps(XV_K_ENCODE, s, work);
@@ -250,6 +262,7 @@ int finish_encode(xv_encoded* e) {
     dev_free(e->work, e->stream);
     e->work = nullptr;
     e->tile_part = nullptr;
+    e->pred = nullptr;
     e->frames = nullptr;
     e->recon = nullptr;
     e->vmask = nullptr;
@@ -272,12 +285,15 @@ int decode_prepare(const xv_encoded* e, hipStream_t s, DecodeBuf& db) {
   const int64_t plane = (int64_t)e->Hp * e->Wp;
   size_t o_rc = c.take<uint16_t>((size_t)e->G * e->T * 3 * plane);
   size_t o_jb = c.take<FrameJob>((size_t)e->njobs);
+  const bool qpel = (e->p.flags & XV_FLAG_QPEL) != 0;
+  size_t o_pr = qpel ? c.take<uint8_t>(pred_plane_bytes(e)) : 0;
   db.mem = nullptr;
   XV_HIP(dev_alloc(&db.mem, c.off, s), "device allocation of the decode buffers");
   db.recon = (uint16_t*)((char*)db.mem + o_rc);
   db.jobs = (FrameJob*)((char*)db.mem + o_jb);
+  db.pred = qpel ? (uint16_t*)((char*)db.mem + o_pr) : nullptr;
   CubePlan pl{nullptr, db.recon, e->levels, e->mvs, nullptr, nullptr, nullptr, nullptr,
-              nullptr, db.jobs, (int32_t)e->T, e->G, e->p.gop, e->nsteps,
+              nullptr, db.pred, db.jobs, (int32_t)e->T, e->G, e->p.gop, e->nsteps,
               e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)e->bands, e->N,
               e->p.bit_depth, e->p.qp, 0};
   XV_HIP(launch_plan(pl, s), "plan kernel");
@@ -324,10 +340,80 @@ int decode_steps(std::vector<DecSrc> base, hipStream_t s) {
     std::vector<DecSrc> src;
     for (auto& b : base)
       if (st < b.e->nsteps) src.push_back(DecSrc{b.e, b.jobs, st});
-    int rc = decode_launch(src, s);
+    uint64_t nl = 0;
+    int rc = launch_mc_step(src, s, &nl);
+    if (rc != XV_OK) return rc;
+    rc = decode_launch(src, s);
     if (rc != XV_OK) return rc;
   }
   return XV_OK;
+}
+
+namespace {
+
+// One workgroup per block; segments of the quarter-sample sources of a step.
+// work: predicted samples the launch evaluates (per block, the refinement's
+// 2 x 9 candidates over the real channels plus the 3-channel prediction it
+// writes; motion compensation writes the 3-channel prediction only).
+template <class Src, class JobsOf, class L>
+int launch_blockwise(const std::vector<Src>& src, JobsOf jobs_of, bool refine, L launch,
+                     uint64_t* launches) {
+  size_t i = 0;
+  while (i < src.size()) {
+    LaunchDesc d;
+    memset(&d, 0, sizeof d);
+    int tiles = 0;
+    double work = 0;
+    int N = 0;
+    for (; i < src.size() && d.nseg < kMaxSeg; i++) {
+      const xv_encoded* e = src[i].e;
+      const int st = src[i].step;
+      if (st == 0 || !(e->p.flags & XV_FLAG_QPEL)) continue;
+      N = e->N;
+      const int n = plan_jobs_at((int)e->T, e->G, e->p.gop, st);
+      const int tpj = e->Hb * e->Wb;
+      Seg& g = d.seg[d.nseg++];
+      g.jobs = jobs_of(src[i]) + plan_step_offset((int)e->T, e->G, e->p.gop, st);
+      g.count = n;
+      g.tpj = tpj;
+      g.tile0 = tiles;
+      tiles += n * tpj;
+      double ch = 0;
+      for (int gg = 0; gg < e->G; gg++) ch += std::min<int64_t>(3, e->bands - 3 * gg);
+      const double per_group = refine ? 18.0 * ch / e->G + 3.0 : 3.0;
+      work += (double)n * tpj * (double)e->N * e->N * per_group;
+    }
+    if (d.nseg == 0) continue;
+    d.tiles = tiles;
+    int rc = launch(N, d, work);
+    if (rc != XV_OK) return rc;
+    ++*launches;
+  }
+  return XV_OK;
+}
+
+}  // namespace
+
+int launch_subpel_step(const std::vector<SegSrc>& src, hipStream_t s, uint64_t* launches) {
+  return launch_blockwise(
+      src, [](const SegSrc& x) { return x.e->jobs; }, true,
+      [&](int N, const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_SUBPEL, s, work);
+        XV_HIP(launch_subpel(N, d, s), "quarter-sample refinement kernel");
+        return XV_OK;
+      },
+      launches);
+}
+
+int launch_mc_step(const std::vector<DecSrc>& src, hipStream_t s, uint64_t* launches) {
+  return launch_blockwise(
+      src, [](const DecSrc& x) { return x.jobs; }, false,
+      [&](int N, const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_SUBPEL, s, work);
+        XV_HIP(launch_mc(N, d, s), "motion compensation kernel");
+        return XV_OK;
+      },
+      launches);
 }
 
 int decode_finish(const xv_encoded* e, const xv_cube* out, DecodeBuf& db, hipStream_t s) {

@@ -27,6 +27,7 @@ struct xv_encoded {
   uint16_t* frames;
   uint16_t* recon;
   uint8_t* vmask;
+  uint16_t* pred;  // prediction planes, one per stream (XV_FLAG_QPEL), in work
   int16_t* levels;
   int8_t* mvs;
   uint32_t* cbits;
@@ -104,7 +105,7 @@ void dims_of(xv_encoded* e, const xv_cube* in, const xv_params* p);
 // reconstruction, validity bytes).  Offsets in bytes.
 struct EncLayout {
   size_t o_lev, o_mv, o_cb, o_mb, o_keys, o_span, o_pp, o_jobs, keep;
-  size_t o_fr, o_rc, o_vm, o_part, work;
+  size_t o_fr, o_rc, o_vm, o_part, o_pred, work;
   size_t span_words;
   int phys_nb;
 };
@@ -162,6 +163,7 @@ int check_decode_out(const xv_encoded* e, const xv_cube* out);
 struct DecodeBuf {
   void* mem = nullptr;
   uint16_t* recon = nullptr;
+  uint16_t* pred = nullptr;  // prediction planes (quarter-sample vectors only)
   FrameJob* jobs = nullptr;
 };
 int decode_prepare(const xv_encoded* e, hipStream_t s, DecodeBuf& db);
@@ -172,6 +174,13 @@ struct DecSrc {
   int step;
 };
 int decode_launch(const std::vector<DecSrc>& src, hipStream_t s);
+// Quarter-sample motion of one frame step: refinement of the integer vectors
+// (encode) or the prediction planes from stored vectors (decode), over the
+// sources coded with XV_FLAG_QPEL (step > 0); *launches counts launches.
+int launch_subpel_step(const std::vector<SegSrc>& src, hipStream_t s, uint64_t* launches);
+int launch_mc_step(const std::vector<DecSrc>& src, hipStream_t s, uint64_t* launches);
+// Bytes of the prediction planes: one [3][Hp][Wp] plane per stream.
+size_t pred_plane_bytes(const xv_encoded* e);
 int decode_steps(std::vector<DecSrc> base, hipStream_t s);
 int decode_finish(const xv_encoded* e, const xv_cube* out, DecodeBuf& db, hipStream_t s);
 

@@ -31,6 +31,9 @@ struct FrameJob {
   const uint32_t* nan_total;   // device flag: non-zero -> vmask is meaningful
   unsigned long long* part;    // [tiles of the frame][5] per-tile sums: squared error of
                                // channels 0..2, coefficient bits, vector bits
+  uint16_t* pred;              // [3][Hp][Wp] motion-compensated prediction of a P step
+                               // with quarter-sample vectors (read at displacement
+                               // zero), or null: the prediction is ref displaced
   int32_t Hp, Wp, H, W;
   int32_t nch;                 // channels carrying a real band (1..3)
   int32_t intra;
@@ -73,6 +76,8 @@ struct CubePlan {
   const uint8_t* vmask;
   const uint32_t* nan_total;
   unsigned long long* part;    // [G][T][tpf][5] per-tile sums (null for decode)
+  uint16_t* pred;              // [G][GOPs][3][Hp][Wp] prediction planes, one per stream
+                               // (quarter-sample vectors only), else null
   FrameJob* jobs;              // [sum over steps of jobs]
   int32_t T, G, gop, nsteps, Hp, Wp, H, W, bands, N, bit_depth, qp;
   int32_t tpf;                 // transform tiles per frame
@@ -237,6 +242,12 @@ hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& d, hipStre
 
 int xf_tiles_per_job(int N, int Hb, int Wb);
 hipError_t launch_encode(int N, const LaunchDesc& d, hipStream_t s);
+// Quarter-sample motion (k_subpel.hip): one workgroup per block of a P step.
+// launch_subpel refines the integer vectors in jobs' mv (quarter samples
+// back into mv) and writes the prediction planes; launch_mc writes the
+// prediction planes from stored quarter-sample vectors (decode).
+hipError_t launch_subpel(int N, const LaunchDesc& d, hipStream_t s);
+hipError_t launch_mc(int N, const LaunchDesc& d, hipStream_t s);
 hipError_t launch_decode(int N, const LaunchDesc& d, hipStream_t s);
 hipError_t launch_plan(const CubePlan& p, hipStream_t s);
 

@@ -22,12 +22,13 @@ U16, F32 = 0, 1
 PAD_ZERO, PAD_REPEAT = 0, 1
 FILL_NEAREST, FILL_FORWARD = 0, 1
 FLAG_DROP_WORK = 1
+FLAG_QPEL = 2
 ME_COLUMN_PAIRS, ME_ROW_PAIRS, ME_ROW_PAIRS_BY_CHANNEL = 1, 2, 3
 MAX_BANDS, MAX_GROUPS = 64, 22
 K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS, K_BITS_WRITE, K_BITS_PARSE, \
-    K_QUALITY = range(10)
+    K_QUALITY, K_SUBPEL = range(11)
 K_NAMES = ["stats", "pack", "me", "encode", "decode", "denorm", "metrics", "bits_write",
-           "bits_parse", "quality"]
+           "bits_parse", "quality", "subpel"]
 
 
 class XvError(RuntimeError):
@@ -73,7 +74,7 @@ class MeGeometryC(C.Structure):
 
 
 class ProfileC(C.Structure):
-    _fields_ = [("ms", C.c_double * 10), ("launches", C.c_uint64 * 10), ("work", C.c_double * 10)]
+    _fields_ = [("ms", C.c_double * 11), ("launches", C.c_uint64 * 11), ("work", C.c_double * 11)]
 
 
 class MemoryC(C.Structure):
