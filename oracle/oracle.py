@@ -107,6 +107,10 @@ def lib():
         L.xvo_interp_sample.restype = C.c_int32
         L.xvo_subpel_refine.argtypes = [p, p, i64, i64, C.c_int, C.c_int, C.c_int, i64, i64,
                                         C.c_int, C.c_int, p, p, p]
+        L.xvo_pca_moments.argtypes = [p, i64, i64, p, p]
+        L.xvo_pca_eigen.argtypes = [p, i64, p, p]
+        L.xvo_pca_project.argtypes = [p, i64, i64, p, p, i64, i64, p]
+        L.xvo_pca_inverse.argtypes = [p, i64, i64, i64, p, p, C.c_int, p]
         L.xvo_encode_gop.argtypes = [p, C.c_int, i64, i64, i64, i64, p, p,
                                      C.POINTER(Params), i64, i64, i64,
                                      p, p, p, p, p, p, p, p]
@@ -311,6 +315,52 @@ def subpel_refine(cur: np.ndarray, ref: np.ndarray, N: int, B: int, bx: int, by:
     lib().xvo_subpel_refine(_ptr(cur), _ptr(ref), Hp, Wp, N, B, nch, bx, by, dx, dy,
                             C.byref(mx), C.byref(my), C.byref(sad))
     return mx.value, my.value, sad.value
+
+
+def pca_moments(cube: np.ndarray):
+    """xvo_pca_moments: band means and covariance of a u16 cube [..][Bn]."""
+    cube = np.ascontiguousarray(cube, np.uint16)
+    Bn = cube.shape[-1]
+    npix = cube.size // Bn
+    mean = np.zeros(Bn, np.float64)
+    cov = np.zeros((Bn, Bn), np.float64)
+    if lib().xvo_pca_moments(_ptr(cube), npix, Bn, _ptr(mean), _ptr(cov)) != 0:
+        raise ValueError("xvo_pca_moments failed")
+    return mean, cov
+
+
+def pca_eigen(cov: np.ndarray):
+    """xvo_pca_eigen: eigenvalues (decreasing) and basis [b][j] (column j = PC j)."""
+    cov = np.ascontiguousarray(cov, np.float64)
+    Bn = cov.shape[0]
+    ev = np.zeros(Bn, np.float64)
+    basis = np.zeros((Bn, Bn), np.float64)
+    if lib().xvo_pca_eigen(_ptr(cov), Bn, _ptr(ev), _ptr(basis)) != 0:
+        raise ValueError("xvo_pca_eigen failed")
+    return ev, basis
+
+
+def pca_project(cube: np.ndarray, mean, basis, j0: int, j1: int) -> np.ndarray:
+    """xvo_pca_project: PCs j0..j1-1 of every sample, f32 [..][j1-j0]."""
+    cube = np.ascontiguousarray(cube, np.uint16)
+    Bn = cube.shape[-1]
+    npix = cube.size // Bn
+    out = np.zeros(cube.shape[:-1] + (j1 - j0,), np.float32)
+    lib().xvo_pca_project(_ptr(cube), npix, Bn, _ptr(np.ascontiguousarray(mean)),
+                          _ptr(np.ascontiguousarray(basis)), j0, j1, _ptr(out))
+    return out
+
+
+def pca_inverse(pcs: np.ndarray, mean, basis, out_dtype: int) -> np.ndarray:
+    """xvo_pca_inverse: bands from the first k PCs (pcs f32 [..][k])."""
+    pcs = np.ascontiguousarray(pcs, np.float32)
+    k = pcs.shape[-1]
+    Bn = basis.shape[0]
+    npix = pcs.size // k
+    out = np.zeros(pcs.shape[:-1] + (Bn,), np.uint16 if out_dtype == U16 else np.float32)
+    lib().xvo_pca_inverse(_ptr(pcs), npix, Bn, k, _ptr(np.ascontiguousarray(mean)),
+                          _ptr(np.ascontiguousarray(basis)), out_dtype, _ptr(out))
+    return out
 
 
 # -- whole-GOP and whole-cube drivers ----------------------------------------

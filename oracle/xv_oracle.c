@@ -1007,6 +1007,143 @@ void xvo_denormalize_cube(const uint16_t* recon, int64_t T, int64_t H,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Principal components of the bands before coding (Sec. II-A: the third     */
+/* entry of a mapping rule sets how many PCs are kept; Sec. III-C: PCA over  */
+/* the ten SimpleS2 bands, the least important PC dropped or coded at lower  */
+/* quality).  The paper names no algorithm; reading:                         */
+/*  - every (t, y, x) is one sample of the band vector x in R^Bn (u16 cubes, */
+/*    the integer data the paper applies PCA to);                            */
+/*  - mean m_b = S_b / n and covariance                                      */
+/*    C_bc = (n Q_bc - S_b S_c) / n^2 (population form), from the exact      */
+/*    integer sums S_b = sum x_b and Q_bc = sum x_b x_c, evaluated as the    */
+/*    binary64 chain ((double) num / n) / n;                                 */
+/*  - eigenvectors by the cyclic Jacobi method (Golub and Van Loan,          */
+/*    "Matrix Computations", the symmetric Schur 2x2 rotation applied in     */
+/*    row-cyclic order), sweeps until the off-diagonal sum of squares is at  */
+/*    most 1e-30 of the diagonal's or 60 sweeps; eigenvalues in decreasing   */
+/*    order (ties: original index), each eigenvector's component of largest  */
+/*    magnitude (first such) made positive;                                  */
+/*  - PC j of a sample: y_j = sum_b V[b][j] (x_b - m_b) in binary64, b in    */
+/*    increasing order, rounded to binary32;                                 */
+/*  - inverse from k PCs: x_b = m_b + sum_{j<k} V[b][j] y_j in binary64, j   */
+/*    in increasing order, then cast to the output type as the decode does.  */
+/* ------------------------------------------------------------------------- */
+int xvo_pca_moments(const uint16_t* data, int64_t npix, int64_t Bn, double* mean,
+                    double* cov) {
+  if (npix <= 0 || Bn <= 0 || Bn > 64) return -1;
+  uint64_t S[64] = {0};
+  unsigned __int128* Q = (unsigned __int128*)calloc((size_t)(Bn * Bn), sizeof(unsigned __int128));
+  if (!Q) return -2;
+  for (int64_t i = 0; i < npix; i++) {
+    const uint16_t* x = data + i * Bn;
+    for (int64_t b = 0; b < Bn; b++) {
+      S[b] += x[b];
+      for (int64_t c = 0; c < Bn; c++) Q[b * Bn + c] += (unsigned __int128)((uint64_t)x[b] * x[c]);
+    }
+  }
+  const double n = (double)npix;
+  for (int64_t b = 0; b < Bn; b++) mean[b] = (double)S[b] / n;
+  for (int64_t b = 0; b < Bn; b++)
+    for (int64_t c = 0; c < Bn; c++) {
+      __int128 num = (__int128)((unsigned __int128)npix * Q[b * Bn + c]) -
+                     (__int128)((unsigned __int128)S[b] * S[c]);
+      cov[b * Bn + c] = ((double)num / n) / n;
+    }
+  free(Q);
+  return 0;
+}
+
+int xvo_pca_eigen(const double* cov, int64_t Bn, double* eigval, double* basis) {
+  if (Bn <= 0 || Bn > 64) return -1;
+  double A[64][64], V[64][64];
+  for (int64_t i = 0; i < Bn; i++)
+    for (int64_t j = 0; j < Bn; j++) {
+      A[i][j] = cov[i * Bn + j];
+      V[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 60; sweep++) {
+    double off = 0.0, dia = 0.0;
+    for (int64_t p = 0; p < Bn; p++) {
+      dia += A[p][p] * A[p][p];
+      for (int64_t q = p + 1; q < Bn; q++) off += A[p][q] * A[p][q];
+    }
+    if (off <= 1e-30 * dia) break;
+    for (int64_t p = 0; p < Bn - 1; p++)
+      for (int64_t q = p + 1; q < Bn; q++) {
+        if (A[p][q] == 0.0) continue;
+        /* rotation (c, s) that zeroes A[p][q]: the smaller root t of
+         * t^2 + 2 tau t - 1 = 0, tau = (A[q][q] - A[p][p]) / (2 A[p][q]) */
+        const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double s = t * c;
+        for (int64_t k = 0; k < Bn; k++) { /* A <- A J */
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
+        }
+        for (int64_t k = 0; k < Bn; k++) { /* A <- J^T A */
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
+        }
+        for (int64_t k = 0; k < Bn; k++) { /* V <- V J */
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  /* decreasing eigenvalues, ties by index (selection of the largest left) */
+  int64_t order[64];
+  int used[64] = {0};
+  for (int64_t j = 0; j < Bn; j++) {
+    int64_t best = -1;
+    for (int64_t i = 0; i < Bn; i++)
+      if (!used[i] && (best < 0 || A[i][i] > A[best][best])) best = i;
+    used[best] = 1;
+    order[j] = best;
+  }
+  for (int64_t j = 0; j < Bn; j++) {
+    const int64_t src = order[j];
+    eigval[j] = A[src][src];
+    int64_t arg = 0;
+    for (int64_t b = 1; b < Bn; b++)
+      if (fabs(V[b][src]) > fabs(V[arg][src])) arg = b;
+    const double sg = V[arg][src] < 0.0 ? -1.0 : 1.0;
+    for (int64_t b = 0; b < Bn; b++) basis[b * Bn + j] = sg * V[b][src];
+  }
+  return 0;
+}
+
+void xvo_pca_project(const uint16_t* data, int64_t npix, int64_t Bn, const double* mean,
+                     const double* basis, int64_t j0, int64_t j1, float* out) {
+  for (int64_t i = 0; i < npix; i++)
+    for (int64_t j = j0; j < j1; j++) {
+      double y = 0.0;
+      for (int64_t b = 0; b < Bn; b++) {
+        const double d = (double)data[i * Bn + b] - mean[b];
+        y = y + basis[b * Bn + j] * d;
+      }
+      out[i * (j1 - j0) + (j - j0)] = (float)y;
+    }
+}
+
+void xvo_pca_inverse(const float* pcs, int64_t npix, int64_t Bn, int64_t k,
+                     const double* mean, const double* basis, int out_dtype, void* out) {
+  for (int64_t i = 0; i < npix; i++)
+    for (int64_t b = 0; b < Bn; b++) {
+      double x = mean[b];
+      for (int64_t j = 0; j < k; j++) x = x + basis[b * Bn + j] * (double)pcs[i * k + j];
+      const double v = xvo_cast_output(x, out_dtype);
+      if (out_dtype == XVO_U16)
+        ((uint16_t*)out)[i * Bn + b] = (uint16_t)v;
+      else
+        ((float*)out)[i * Bn + b] = (float)v;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Metrics (Sec. II-C).                                                       */
 /* PSNR with a given peak: 10 log10(peak^2 / MSE); MSE = 0 gives +inf.        */
 /* ------------------------------------------------------------------------- */

@@ -75,6 +75,16 @@ void xvo_subpel_refine(const uint16_t* cur, const uint16_t* ref, int64_t Hp,
                        int dx, int dy, int32_t* mvx, int32_t* mvy,
                        uint32_t* best_sad);
 
+/* PCA of the bands (u16 cubes): exact integer sums, covariance, cyclic
+ * Jacobi eigen-decomposition, projection and its inverse. */
+int xvo_pca_moments(const uint16_t* data, int64_t npix, int64_t Bn, double* mean,
+                    double* cov);
+int xvo_pca_eigen(const double* cov, int64_t Bn, double* eigval, double* basis);
+void xvo_pca_project(const uint16_t* data, int64_t npix, int64_t Bn, const double* mean,
+                     const double* basis, int64_t j0, int64_t j1, float* out);
+void xvo_pca_inverse(const float* pcs, int64_t npix, int64_t Bn, int64_t k,
+                     const double* mean, const double* basis, int out_dtype, void* out);
+
 int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
                    int64_t W, int64_t Bn, const double* mn, const double* mx,
                    const xvo_params* p, int64_t g, int64_t t0, int64_t len,
