@@ -16,8 +16,9 @@ Both produce bit-identical outputs (checked), hence identical PSNR and bpppb.
 Secondary sections (not the headline): the cloud-gapped Sentinel-2-like sweep
 (500 x 128 x 128 x 6 f32, 15 QP x N runs), the reanalysis-like cube
 (744 x 721 x 1440 x 3 f32, QP 17 and 27, N = 32, R = 8), the sweep again with
-quarter-sample motion against integer vectors, SSIM / spectral angle and the
-bitstream on the headline runs, a small serving mix, and the oracle on the
+quarter-sample motion against integer vectors, the headline cube coded as its
+first three principal components, SSIM / spectral angle and the bitstream on
+the headline runs, a small serving mix, and the oracle on the
 host cores on sampled GOP units of the headline cube.
 
 Prints ONE JSON line.  `value` is the batched throughput in Mpx*band/s of
@@ -560,6 +561,75 @@ def qpel_bench(xv, torch, synth, steps, warmup, cached, no_tune):
     return out
 
 
+def pca_bench(xv, torch, wl, cube, steps, warmup, k=3):
+    """Sec. II-A's example on the headline cube: R, G, B, NIR coded as their
+    first k = 3 principal components in one band group instead of two.  One
+    step = PCA fit (moments of the whole cube) + projection + encode of both
+    QP runs of the PC cube + decode + inverse to the four u16 bands.  Quality
+    is the physical-domain PSNR of the inverse against the original (peak =
+    band maximum, Sec. II-C), computed for the report only."""
+    T, H, W, Bn = cube.shape
+    params = [xv.Params(bit_depth=wl.bit_depth, qp=qp, block=wl.blocks[0],
+                        search_range=wl.search_range, gop=wl.gop) for qp in wl.qps]
+    pcs = torch.empty((T, H, W, k), dtype=torch.float32, device=cube.device)
+    dec = [torch.empty_like(pcs) for _ in params]
+    back = [torch.empty_like(cube) for _ in params]
+
+    def step():
+        pca = xv.Pca(cube)  # synchronises (host eigen-decomposition)
+        pca.project(cube, 0, k, pcs)
+        encs = xv.encode_batch([pcs] * len(params), params)
+        xv.decode_batch(encs, dec)
+        ms = xv.psnr_bpppb_batch([pcs] * len(encs), encs)
+        for d, b in zip(dec, back):
+            pca.inverse(d, b)
+        torch.cuda.synchronize()
+        for e in encs:
+            e.free()
+        ev = pca.view()["eigval"]
+        pca.free()
+        return ms, ev
+
+    for _ in range(warmup):
+        step()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ms, ev = step()
+    dt = time.perf_counter() - t0
+    xv.profile_select(None)
+    xv.profile_enable(True)
+    step()
+    prof = xv.profile_read()
+    xv.profile_enable(False)
+    pxb = T * H * W * Bn * len(params)
+    out = {"workload": f"{wl.name} cube, bands coded as their first {k} principal components "
+                       f"(one band group), QP {list(wl.qps)}, N={wl.blocks[0]}, "
+                       f"R={wl.search_range}; one step = fit + project + encode + decode + "
+                       f"inverse of both runs",
+           "value": round(pxb * steps / dt / 1e6, 3), "unit": "Mpx·band/s (original bands)",
+           "ms_per_step": round(dt / steps * 1e3, 3),
+           "explained_variance": [round(float(v / ev.sum()), 6) for v in ev],
+           "kernel_ms_per_step": {kk: round(v["ms"], 3) for kk, v in prof.items() if v["launches"]}}
+    if prof["pca"]["launches"]:
+        d = prof["pca"]
+        out["pca_kernels_GBs"] = round(d["work"] / (d["ms"] * 1e-3) / 1e9, 1)
+        out["pca_kernels_frac_hbm"] = round(d["work"] / (d["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    mx = cube.reshape(-1, Bn).amax(0).double()
+    psnr, bpppb = [], []
+    for b_, m in zip(back, ms):
+        sse = torch.zeros(Bn, dtype=torch.float64, device=cube.device)
+        for t0 in range(0, T, 32):  # in slabs: a float64 copy of the cube is 24 GB
+            diff = (b_[t0:t0 + 32].double() - cube[t0:t0 + 32].double()).reshape(-1, Bn)
+            sse += (diff * diff).sum(0)
+        mse = sse / (T * H * W)
+        psnr.append([round(float(10 * torch.log10(mx[i] ** 2 / mse[i])), 4) for i in range(Bn)])
+        bpppb.append(round((m["coef_bits"] + m["mv_bits"]) / (T * H * W * Bn), 5))
+    out["psnr_phys_db_per_run_band"] = psnr
+    out["bpppb_per_run"] = bpppb
+    del pcs, dec, back
+    return out
+
+
 def free_device(xv, torch):
     import gc
     gc.collect()
@@ -583,6 +653,8 @@ def main():
                     help="skip the cloud-gapped sweep and the reanalysis-like cube")
     ap.add_argument("--no-qpel", action="store_true",
                     help="skip the quarter-sample motion section")
+    ap.add_argument("--no-pca", action="store_true",
+                    help="skip the principal-components section")
     ap.add_argument("--counters", action="store_true",
                     help="workload for hardware-counter runs only: one 1 GiB device copy (the "
                          "calibration of FETCH_SIZE / WRITE_SIZE), then one batched step of the "
@@ -684,6 +756,9 @@ def main():
     if not args.no_bits:
         _log("bitstream")
         line["bitstream"] = bits_bench(xv, torch, cube, params, r["pxb_step"], qsteps)
+    if not args.no_pca:
+        _log("principal components")
+        line["pca"] = pca_bench(xv, torch, wl, cube, max(1, min(args.steps, 3)), 1)
     host = None
     if not args.no_cpu_baseline:
         host = cube.cpu().numpy()

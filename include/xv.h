@@ -379,7 +379,8 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
 #define XV_K_BITS_PARSE 8
 #define XV_K_QUALITY 9
 #define XV_K_SUBPEL 10 /* quarter-sample refinement and motion compensation */
-#define XV_K_COUNT 11
+#define XV_K_PCA 11    /* principal components: moments, projection, inverse */
+#define XV_K_COUNT 12
 
 typedef struct {
   double ms[XV_K_COUNT];       /* summed kernel time per kernel class     */
@@ -437,6 +438,46 @@ void xv_packed_free(xv_packed* p);
  * payload that does not parse as the codes above (nothing is written to
  * *out then), XV_ENOMEM, XV_EHIP. */
 int xv_unpack(const void* data, uint64_t bytes, void* hip_stream, xv_encoded** out);
+
+/* ---- principal components of the bands ------------------------------------
+ * Sec. II-A: a mapping rule's third entry sets how many principal components
+ * (PCs) of its bands are kept, and those PCs are coded instead of the bands
+ * (e.g. the first 3 PCs of R, G, B, NIR in one video); Sec. III-C codes the
+ * ten SimpleS2 bands as 9 PCs, or as all 10 with the less important ones at
+ * lower quality.  The paper names no algorithm; this is the stated reading,
+ * for u16 cubes: every (t, y, x) is one sample of the band vector; the mean
+ * m and population covariance C come from exact integer sums of the samples
+ * and their pairwise products (independent of summation order), with
+ * m_b = S_b / n and C_bc = ((n Q_bc - S_b S_c) / n) / n in binary64; the
+ * eigenvectors come from the cyclic Jacobi method, eigenvalues decreasing,
+ * each eigenvector's largest component positive.  PC j of a sample is
+ * y_j = sum_b V[b][j] (x_b - m_b) in binary64 (b increasing), stored as
+ * binary32; the inverse from the first k PCs is
+ * x_b = m_b + sum_{j<k} V[b][j] y_j (j increasing), rounded like a decode.
+ * A PC cube is an ordinary XV_F32 cube: encode it with xv_encode_cube (or
+ * several PC ranges with different QPs with xv_encode_batch), decode it to
+ * XV_F32, then xv_pca_inverse. */
+typedef struct xv_pca xv_pca;
+
+/* Fit the PCs of a u16 device cube (1 to 64 bands).  Synchronises
+ * hip_stream.  *out is owned by the caller (xv_pca_free).  Errors:
+ * XV_EINVAL (null or bad cube, dtype other than XV_U16), XV_ENOMEM, XV_EHIP. */
+int xv_pca_fit(const xv_cube* in, void* hip_stream, xv_pca** out);
+/* Host copies of the fit (each output optional; caller memory of bands,
+ * bands^2, bands and bands^2 doubles; basis[b * bands + j] is component b of
+ * PC j). */
+int xv_pca_view(const xv_pca* p, int32_t* bands, double* mean, double* cov, double* eigval,
+                double* basis);
+/* PCs j0..j1-1 of every sample of `in` (u16, the fitted band count) into pcs
+ * (XV_F32, same T, H, W, j1 - j0 bands).  Asynchronous.  Errors: XV_EINVAL,
+ * XV_EHIP. */
+int xv_pca_project(const xv_pca* p, const xv_cube* in, int32_t j0, int32_t j1,
+                   const xv_cube* pcs, void* hip_stream);
+/* Bands from the first k = pcs->bands PCs (XV_F32) into out (XV_U16:
+ * nearest integer, halves up, clamped; XV_F32: nearest float; the fitted
+ * band count).  Asynchronous.  Errors: XV_EINVAL, XV_EHIP. */
+int xv_pca_inverse(const xv_pca* p, const xv_cube* pcs, const xv_cube* out, void* hip_stream);
+void xv_pca_free(xv_pca* p);
 
 /* ---- device memory ---------------------------------------------------------
  * Every device buffer of the library comes from one caching allocator per

@@ -322,6 +322,43 @@ static_assert(sizeof(PackHeader) == 256, "pack header size");
 hipError_t launch_write_header(const PackHeader& h, void* dst, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Principal components of the bands (k_pca.hip).
+// ---------------------------------------------------------------------------
+struct PcaMomArgs {
+  const void* data;               // u16 [npix][bands]
+  int64_t npix;
+  int32_t bands;
+  unsigned long long* part;       // [nblocks][P] per-block sums
+  unsigned long long* total;      // [P][2] 128-bit totals (low, high)
+};
+// P = bands (bands + 1) / 2 + bands sums: the upper triangle of Q (row-major,
+// b <= c), then S_0 .. S_{bands-1}.
+int pca_sum_count(int bands);
+int pca_moment_blocks(int64_t npix);
+hipError_t launch_pca_moments(const PcaMomArgs& a, int nblocks, hipStream_t s);
+
+struct PcaProjArgs {
+  const void* data;               // u16 [npix][bands]
+  int64_t npix;
+  int32_t bands, j0, j1;          // PCs j0 .. j1-1
+  const double* mean;             // [bands]
+  const double* basis;            // [bands][bands], column j = PC j
+  void* out;                      // f32 [npix][j1 - j0]
+};
+hipError_t launch_pca_project(const PcaProjArgs& a, hipStream_t s);
+
+struct PcaInvArgs {
+  const void* pcs;                // f32 [npix][k]
+  int64_t npix;
+  int32_t bands, k;
+  const double* mean;
+  const double* basis;
+  int32_t out_dtype;              // XV_U16 or XV_F32
+  void* out;                      // [npix][bands]
+};
+hipError_t launch_pca_inverse(const PcaInvArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Caching device allocator (xv_alloc.cpp).  dev_free keeps the block for
 // reuse: at once on the same stream, on another stream once the work queued
 // before the free has completed.

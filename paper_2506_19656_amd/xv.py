@@ -26,9 +26,9 @@ FLAG_QPEL = 2
 ME_COLUMN_PAIRS, ME_ROW_PAIRS, ME_ROW_PAIRS_BY_CHANNEL = 1, 2, 3
 MAX_BANDS, MAX_GROUPS = 64, 22
 K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS, K_BITS_WRITE, K_BITS_PARSE, \
-    K_QUALITY, K_SUBPEL = range(11)
+    K_QUALITY, K_SUBPEL, K_PCA = range(12)
 K_NAMES = ["stats", "pack", "me", "encode", "decode", "denorm", "metrics", "bits_write",
-           "bits_parse", "quality", "subpel"]
+           "bits_parse", "quality", "subpel", "pca"]
 
 
 class XvError(RuntimeError):
@@ -74,7 +74,7 @@ class MeGeometryC(C.Structure):
 
 
 class ProfileC(C.Structure):
-    _fields_ = [("ms", C.c_double * 11), ("launches", C.c_uint64 * 11), ("work", C.c_double * 11)]
+    _fields_ = [("ms", C.c_double * 12), ("launches", C.c_uint64 * 12), ("work", C.c_double * 12)]
 
 
 class MemoryC(C.Structure):
@@ -113,7 +113,8 @@ EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube"
             "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
             "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release", "xv_pack", "xv_packed_view",
             "xv_packed_free", "xv_unpack", "xv_ssim", "xv_spectral_angle",
-            "xv_spectral_angle_noalloc"]
+            "xv_spectral_angle_noalloc", "xv_pca_fit", "xv_pca_view", "xv_pca_project",
+            "xv_pca_inverse", "xv_pca_free"]
 
 _lib = None
 
@@ -141,6 +142,13 @@ def lib():
                                         C.POINTER(C.c_uint64), vp]
         L.xv_spectral_angle_noalloc.argtypes = [C.POINTER(Cube), C.POINTER(Cube),
                                                 C.POINTER(C.c_double), C.POINTER(C.c_uint64), vp]
+        L.xv_pca_fit.argtypes = [C.POINTER(Cube), vp, C.POINTER(vp)]
+        L.xv_pca_view.argtypes = [vp, C.POINTER(C.c_int32), vp, vp, vp, vp]
+        L.xv_pca_project.argtypes = [vp, C.POINTER(Cube), C.c_int32, C.c_int32, C.POINTER(Cube),
+                                     vp]
+        L.xv_pca_inverse.argtypes = [vp, C.POINTER(Cube), C.POINTER(Cube), vp]
+        L.xv_pca_free.argtypes = [vp]
+        L.xv_pca_free.restype = None
         L.xv_encoded_export.argtypes = [vp, C.POINTER(ExportC)]
         L.xv_encoded_free.argtypes = [vp]
         L.xv_encoded_free.restype = None
@@ -381,6 +389,49 @@ def spectral_angle_noalloc(orig, decoded, stream=None):
     _check(lib().xv_spectral_angle_noalloc(C.byref(_cube(orig)), C.byref(_cube(decoded)),
                                            C.byref(v), C.byref(n), _stream_handle(stream)))
     return v.value, int(n.value)
+
+
+class Pca:
+    """xv_pca_*: principal components of a u16 device cube's bands."""
+
+    def __init__(self, cube, stream=None):
+        self._h = C.c_void_p()
+        _check(lib().xv_pca_fit(C.byref(_cube(cube)), _stream_handle(stream), C.byref(self._h)))
+        b = C.c_int32()
+        _check(lib().xv_pca_view(self._h, C.byref(b), None, None, None, None))
+        self.bands = b.value
+
+    def view(self) -> dict:
+        """Host copies: mean [bands], cov [bands][bands], eigval [bands] and
+        basis [bands][bands] (column j = PC j)."""
+        n = self.bands
+        mean = np.zeros(n, np.float64)
+        cov = np.zeros((n, n), np.float64)
+        ev = np.zeros(n, np.float64)
+        basis = np.zeros((n, n), np.float64)
+        _check(lib().xv_pca_view(self._h, None, mean.ctypes.data_as(C.c_void_p),
+                                 cov.ctypes.data_as(C.c_void_p), ev.ctypes.data_as(C.c_void_p),
+                                 basis.ctypes.data_as(C.c_void_p)))
+        return dict(mean=mean, cov=cov, eigval=ev, basis=basis)
+
+    def project(self, cube, j0, j1, out, stream=None):
+        _check(lib().xv_pca_project(self._h, C.byref(_cube(cube)), j0, j1, C.byref(_cube(out)),
+                                    _stream_handle(stream)))
+
+    def inverse(self, pcs, out, stream=None):
+        _check(lib().xv_pca_inverse(self._h, C.byref(_cube(pcs)), C.byref(_cube(out)),
+                                    _stream_handle(stream)))
+
+    def free(self):
+        if self._h:
+            lib().xv_pca_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def set_me_geometry(block: int, search_range: int, blocks_per_wg=0, cands_per_lane=0,
