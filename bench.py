@@ -129,7 +129,8 @@ def tune(xv, wl, cube, params, cached, no_tune):
     return tuning
 
 
-def run_workload(xv, torch, wl, cube, params, steps, warmup, mode="both", profile_me=True):
+def run_workload(xv, torch, wl, cube, params, steps, warmup, mode="both", profile_me=True,
+                 graphs=True):
     """Times the plain and batched forms; returns their throughput, the
     metrics of the runs, and the kernel profile of the timed steps (motion
     search only) and of one extra step (every class)."""
@@ -199,6 +200,23 @@ def run_workload(xv, torch, wl, cube, params, steps, warmup, mode="both", profil
         res["batched"] = dict(value=pxb_step * steps / dt / 1e6, ms_per_step=dt / steps * 1e3,
                               p50_ms=_percentile(lat, 0.5), p99_ms=_percentile(lat, 0.99),
                               latency_unit=f"one step: all {len(params)} runs")
+        if graphs:
+            # the same batched steps with the frame-step launches replayed
+            # from captured graphs (no event timing inside)
+            _log(f"{wl.name}: batched path, graph replay")
+            xv.set_graph_mode(True)
+            try:
+                dt, lat, ms_graph, _ = timed(step_batched, profile=False)
+            finally:
+                xv.set_graph_mode(False)
+            if any(a["psnr"] != b["psnr"] or a["bpppb"] != b["bpppb"]
+                   for a, b in zip(ms_graph, ms_batch)):
+                raise SystemExit(f"{wl.name}: graph replay and eager launches disagree")
+            res["batched_graph"] = dict(value=pxb_step * steps / dt / 1e6,
+                                        ms_per_step=dt / steps * 1e3,
+                                        p50_ms=_percentile(lat, 0.5),
+                                        p99_ms=_percentile(lat, 0.99),
+                                        latency_unit=f"one step: all {len(params)} runs")
     if ms_plain is not None and ms_batch is not None:
         same = all(a["psnr"] == b["psnr"] and a["bpppb"] == b["bpppb"]
                    and a["coef_bits"] == b["coef_bits"] and a["mv_bits"] == b["mv_bits"]
@@ -614,12 +632,15 @@ def pca_bench(xv, torch, wl, cube, steps, warmup, k=3):
         d = prof["pca"]
         out["pca_kernels_GBs"] = round(d["work"] / (d["ms"] * 1e-3) / 1e9, 1)
         out["pca_kernels_frac_hbm"] = round(d["work"] / (d["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    mx = cube.reshape(-1, Bn).amax(0).double()
+    mx = torch.zeros(Bn, dtype=torch.float64, device=cube.device)
+    for t0 in range(0, T, 32):  # band maxima, in slabs
+        mx = torch.maximum(mx, cube[t0:t0 + 32].to(torch.int32).reshape(-1, Bn).amax(0).double())
     psnr, bpppb = [], []
     for b_, m in zip(back, ms):
         sse = torch.zeros(Bn, dtype=torch.float64, device=cube.device)
         for t0 in range(0, T, 32):  # in slabs: a float64 copy of the cube is 24 GB
-            diff = (b_[t0:t0 + 32].double() - cube[t0:t0 + 32].double()).reshape(-1, Bn)
+            diff = (b_[t0:t0 + 32].to(torch.int32).double() -
+                    cube[t0:t0 + 32].to(torch.int32).double()).reshape(-1, Bn)
             sse += (diff * diff).sum(0)
         mse = sse / (T * H * W)
         psnr.append([round(float(10 * torch.log10(mx[i] ** 2 / mse[i])), 4) for i in range(Bn)])

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define XV_ABI_VERSION 5
+#define XV_ABI_VERSION 6
 
 /* status codes */
 #define XV_OK 0
@@ -243,6 +243,20 @@ int xv_encode_batch(int n, const xv_cube* cubes, const xv_params* params,
 /* Decode n encoded cubes into outs[i] (as xv_decode_cube, batched). */
 int xv_decode_batch(int n, xv_encoded* const* encs, const xv_cube* outs,
                     void* hip_stream);
+
+/* Graph replay of the batched paths (process-wide, off by default).  With it
+ * on and per-launch timing off, xv_encode_batch and xv_decode_batch capture
+ * the frame-step launches of each (block size, search range) class as a HIP
+ * graph the first time a batch of that shape runs on a stream, and replay
+ * it for later batches of the same shape (frame count, groups, GOP, padded
+ * size, block size, search range, quarter-sample flag, motion-search
+ * geometry, stream): each call writes its job tables as usual and copies
+ * them into the graph's own tables before the replay, so outputs are those
+ * of the eager launches.  Up to 32 graphs are kept (least recently used
+ * dropped); xv_cache_release drops them all.  A stream a graph was replayed
+ * on must stay alive until then. */
+int xv_set_graph_mode(int on);
+int xv_get_graph_mode(void);
 
 /* ---- Serving loop: continuous batching of encode / decode requests ---- */
 

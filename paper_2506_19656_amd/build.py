@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libxv.so")
 SOURCES = ["k_prep.hip", "k_me.hip", "k_xform.hip", "k_subpel.hip", "k_bits.hip", "k_quality.hip",
            "k_pca.hip", "xv_alloc.cpp", "xv_pca.cpp",
            "xv_runtime.cpp", "xv_api.cpp", "xv_quality_api.cpp", "xv_tune.cpp", "xv_bitstream.cpp",
-           "xv_server.cpp"]
+           "xv_server.cpp", "xv_graph.cpp"]
 
 ARCH = os.environ.get("XV_OFFLOAD_ARCH", "gfx950")
 

@@ -565,8 +565,9 @@ int xv_encode_batch(int n, const xv_cube* cubes, const xv_params* params, void* 
   // one step loop per (N, R) class; classes are independent
   std::map<std::pair<int, int>, std::vector<xv_encoded*>> cls;
   for (auto* e : all) cls[{e->N, e->p.search_range}].push_back(e);
+  const bool graph = graphs_enabled() && !profiling_enabled();
   for (auto& kv : cls) {
-    int rc = encode_steps(kv.second, s);
+    int rc = graph ? encode_steps_graph(kv.second, s) : encode_steps(kv.second, s);
     if (rc != XV_OK) return cleanup(rc);
   }
   for (int i = 0; i < n; i++) {
@@ -612,8 +613,9 @@ int xv_decode_batch(int n, xv_encoded* const* encs, const xv_cube* outs, void* h
   }
   std::map<int, std::vector<DecSrc>> cls;
   for (int i = 0; i < n; i++) cls[encs[i]->N].push_back(DecSrc{encs[i], bufs[i].jobs, 0});
+  const bool graph = graphs_enabled() && !profiling_enabled();
   for (auto& kv : cls) {
-    int rc = decode_steps(kv.second, s);
+    int rc = graph ? decode_steps_graph(kv.second, s) : decode_steps(kv.second, s);
     if (rc != XV_OK) return cleanup(rc);
   }
   for (int i = 0; i < n; i++) {
@@ -722,6 +724,7 @@ int xv_memory_read(xv_memory* out) {
 }
 
 int xv_cache_release(uint64_t* released_bytes) {
+  graph_cache_release();  // their job tables go back to the cache first
   const size_t n = dev_cache_release();
   if (released_bytes) *released_bytes = n;
   return XV_OK;

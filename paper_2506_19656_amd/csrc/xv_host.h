@@ -87,6 +87,9 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// True while per-launch event timing is enabled (xv_profile_enable).
+bool profiling_enabled();
+
 // ---- motion-search geometry table --------------------------------------------
 // Explicit geometries (xv_set_me_geometry, the tuner) per (N, R); otherwise
 // the model default for the class's widest frame in blocks.
@@ -183,6 +186,14 @@ int launch_mc_step(const std::vector<DecSrc>& src, hipStream_t s, uint64_t* laun
 size_t pred_plane_bytes(const xv_encoded* e);
 int decode_steps(std::vector<DecSrc> base, hipStream_t s);
 int decode_finish(const xv_encoded* e, const xv_cube* out, DecodeBuf& db, hipStream_t s);
+
+// ---- graph replay of the step loops (xv_graph.cpp) ----------------------------
+// With graph mode on (xv_set_graph_mode) and timing off, the batched paths
+// replay a captured graph of the step loop instead of launching it.
+bool graphs_enabled();
+int encode_steps_graph(std::vector<xv_encoded*>& es, hipStream_t s);
+int decode_steps_graph(const std::vector<DecSrc>& base, hipStream_t s);
+size_t graph_cache_release();
 
 }  // namespace host
 }  // namespace xv

@@ -85,6 +85,11 @@ ProfScope::~ProfScope() {
   g_prof_pending.push_back(ProfRec{cls, a, b, work});
 }
 
+bool profiling_enabled() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof_on;
+}
+
 MeGeom geometry_for(int N, int R, int Wb) {
   std::lock_guard<std::mutex> lk(g_geom_mu);
   auto it = g_geom.find({N, R});

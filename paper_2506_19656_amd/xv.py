@@ -114,7 +114,7 @@ EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube"
             "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release", "xv_pack", "xv_packed_view",
             "xv_packed_free", "xv_unpack", "xv_ssim", "xv_spectral_angle",
             "xv_spectral_angle_noalloc", "xv_pca_fit", "xv_pca_view", "xv_pca_project",
-            "xv_pca_inverse", "xv_pca_free"]
+            "xv_pca_inverse", "xv_pca_free", "xv_set_graph_mode", "xv_get_graph_mode"]
 
 _lib = None
 
@@ -149,6 +149,8 @@ def lib():
         L.xv_pca_inverse.argtypes = [vp, C.POINTER(Cube), C.POINTER(Cube), vp]
         L.xv_pca_free.argtypes = [vp]
         L.xv_pca_free.restype = None
+        L.xv_set_graph_mode.argtypes = [C.c_int]
+        L.xv_get_graph_mode.argtypes = []
         L.xv_encoded_export.argtypes = [vp, C.POINTER(ExportC)]
         L.xv_encoded_free.argtypes = [vp]
         L.xv_encoded_free.restype = None
@@ -389,6 +391,15 @@ def spectral_angle_noalloc(orig, decoded, stream=None):
     _check(lib().xv_spectral_angle_noalloc(C.byref(_cube(orig)), C.byref(_cube(decoded)),
                                            C.byref(v), C.byref(n), _stream_handle(stream)))
     return v.value, int(n.value)
+
+
+def set_graph_mode(on: bool):
+    """xv_set_graph_mode: replay captured graphs of the batched step loops."""
+    _check(lib().xv_set_graph_mode(1 if on else 0))
+
+
+def get_graph_mode() -> bool:
+    return bool(lib().xv_get_graph_mode())
 
 
 class Pca:
