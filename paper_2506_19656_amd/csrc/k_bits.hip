@@ -201,33 +201,59 @@ __global__ void __launch_bounds__(kBitsThreads) write_units_kernel(BitsArgs a) {
   bs.flush();
 }
 
-// Bit source over the payload words (byte-swapped back to stream order).
+// Bit reader over the payload words (byte-swapped back to stream order).
+// The next bits of the stream are held MSB-first in a 64-bit register with
+// at least 33 of them valid (the longest code the writer emits), so a code
+// is read with register operations and a new word is fetched only once 32
+// bits have been consumed.  Word reads are clamped to the buffer.
 struct BitSource {
   const uint32_t* words;
   int64_t nwords;
-  uint64_t pos;
+  uint64_t pos;   // bits consumed, from the start of the payload
+  uint64_t buf;   // the next bits, MSB first; bits past nbits are zero
+  int nbits;      // valid bits in buf
+  int64_t next;   // next word to load
 
-  __device__ uint64_t window() const {  // the next 64 bits, MSB first
-    const int64_t w = min((int64_t)(pos >> 5), nwords - 2);
-    const uint64_t hi = __builtin_bswap32(words[w]);
-    const uint64_t lo = __builtin_bswap32(words[w + 1]);
-    return ((hi << 32) | lo) << (pos & 31);
+  __device__ uint32_t word(int64_t w) const {
+    return __builtin_bswap32(words[min(w, nwords - 1)]);
+  }
+  __device__ void refill() {
+    while (nbits <= 32) {
+      buf |= (uint64_t)word(next) << (32 - nbits);
+      nbits += 32;
+      next++;
+    }
+  }
+  __device__ void start(const uint32_t* w, int64_t nw, uint64_t at) {
+    words = w;
+    nwords = nw;
+    pos = at;
+    const int sh = (int)(at & 31);
+    buf = ((uint64_t)word((int64_t)(at >> 5)) << 32) << sh;
+    nbits = 32 - sh;
+    next = (int64_t)(at >> 5) + 1;
+    refill();
+  }
+  __device__ void skip(int n) {
+    buf <<= n;
+    nbits -= n;
+    pos += (uint64_t)n;
+    refill();
   }
   __device__ int bit() {
-    const int b = (int)(window() >> 63);
-    pos++;
+    const int b = (int)(buf >> 63);
+    skip(1);
     return b;
   }
   // ue(k): m leading zeros, then m + 1 bits holding k + 1; false on a code
   // longer than any the writer emits.
   __device__ bool ue(uint32_t& k) {
-    const uint64_t wv = window();
-    if (wv == 0) return false;
-    const int m = __clzll((long long)wv);
+    if (buf == 0) return false;
+    const int m = __clzll((long long)buf);
     if (m > 16) return false;
     const int len = 2 * m + 1;
-    k = (uint32_t)(wv >> (64 - len)) - 1u;
-    pos += len;
+    k = (uint32_t)(buf >> (64 - len)) - 1u;
+    skip(len);
     return true;
   }
   __device__ bool se(int& v) {
@@ -255,7 +281,8 @@ __global__ void __launch_bounds__(kBitsThreads) parse_segments_kernel(BitsArgs a
   const int64_t f = s / spf;
   const int64_t r = s - f * spf;
   const uint64_t end = s + 1 < nseg ? a.index[s + 1] : a.total_bits;
-  BitSource src{a.words, a.nwords, a.index[s]};
+  BitSource src;
+  src.start(a.words, a.nwords, a.index[s]);
   const int t = (int)(f % a.T);
   const bool intra = t % a.gop == 0;
   bool ok = true;

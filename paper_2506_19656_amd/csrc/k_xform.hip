@@ -303,9 +303,20 @@ __device__ inline bool locate_at(const LaunchDesc& jd, int tile, TileCoord& tc) 
   return true;
 }
 
+// XCD-aware order: workgroup IDs are dealt round-robin to the 8 XCDs, each
+// with its own L2.  Mapping the IDs an XCD receives to one contiguous range
+// of tiles keeps vertically and horizontally neighbouring tiles -- which read
+// overlapping rows of the motion-compensated reference -- in the same L2.
+__device__ inline int xcd_tile(int id, int n) {
+  constexpr int kXcd = 8;
+  const int x = id % kXcd, i = id / kXcd;
+  const int per = n / kXcd, rem = n % kXcd;
+  return x * per + min(x, rem) + i;
+}
+
 template <int N>
 __device__ inline bool locate(const LaunchDesc& jd, TileCoord& tc) {
-  return locate_at<N>(jd, (int)blockIdx.x, tc);
+  return locate_at<N>(jd, xcd_tile((int)blockIdx.x, (int)gridDim.x), tc);
 }
 
 // Global memory through address space 1 at a 32-bit byte offset from a base
@@ -617,21 +628,22 @@ encode_kernel(const LaunchDesc jr) {
   // Column stage of column k: forward transform, quantise (levels out to
   // global memory, column-major inside the block, and into the thread's own
   // TD row), dequantise and inverse column transform.
+  const int k = r;
+  const int qP = job.qp + 6 * (B - 8);
+  const Dequant dqp = dequant_params(qP, B + L2N - 5);
+  int lv[N];
+  bool lane_nz = false;
   if (vb) {
-    const int k = r;
-    const int qP = job.qp + 6 * (B - 8);
     const int qbits = 29 + qP / 6 - B - L2N;
     const int off = (job.intra ? 171 : 85) << (qbits - 9);
     const int offn = (1 << qbits) - 1 - off;
     const int qf = kQf[qP % 6];
-    const Dequant dqp = dequant_params(qP, B + L2N - 5);
     uint32_t* row = (uint32_t*)s.TD[c][b][k];
     ivec<N> acc;
     fwd_column<N>(row, acc, 1 << (L2N + 5));
     // level = sgn(C) min(32767, (|C| Qf + off) >> qbits) in signed form:
     // C >= 0: (C Qf + off) >> qbits; C < 0: (C Qf + 2^qbits - 1 - off) >> qbits
     // (|C Qf| < 2^30, so nothing overflows)
-    int lv[N];
 #pragma unroll
     for (int l = 0; l < N; l++) {
       const int C = acc[l] >> (L2N + 6);
@@ -648,6 +660,18 @@ encode_kernel(const LaunchDesc jr) {
       row[m] = __builtin_bit_cast(uint32_t, (u16x2)(a + a + (u16x2){1, 1}));
     }
     store_row_packed<N>(job.lev, 2u * (((uint32_t)c * tc.Hb * tc.Wb + blk) * (N * N) + k * N), lpair);
+    uint32_t any = 0;
+#pragma unroll
+    for (int m = 0; m < N / 2; m++) any |= lpair[m];
+    lane_nz = any != 0u;
+  }
+  // A wave (one channel of the tile) whose levels are all zero -- padding
+  // channels, and flat content at high QP -- skips the inverse stages and the
+  // rate scan: zero levels dequantise and inverse-transform to an exactly
+  // zero residual, so the reconstruction is the prediction, and every block
+  // costs its coded-flag bit only.
+  const bool wave_nz = __any(lane_nz);
+  if (vb && wave_nz) {
     uint32_t dq[N / 2];
     dequant_pairs<N>(lv, dqp, dq);
     inverse_column<N>(dq, s.E[c][b], inv_slot<N>(k));
@@ -655,12 +679,17 @@ encode_kernel(const LaunchDesc jr) {
   __syncthreads();
 
   // Rate proxy per block and channel (levels in TD).
-  block_bits<N>(s, tc, c);
+  if (wave_nz) block_bits<N>(s, tc, c);
 
   // Inverse row stage, reconstruction, squared error.
   if (vb) {
     uint32_t rp[N / 2];
-    inverse_row<N>(s.E[c][b][r], pp, B, rp);
+    if (wave_nz) {
+      inverse_row<N>(s.E[c][b][r], pp, B, rp);
+    } else {
+#pragma unroll
+      for (int j = 0; j < N / 2; j++) rp[j] = pp[j];
+    }
     store_row_packed<N>(job.rec, 2u * row_off, rp);
     if (c < job.nch && y < job.H) {
       const uint32_t sse = usemask ? row_sse<N, true>(cp, rp, job.vmask, row_off, x0, job.W)
@@ -714,8 +743,9 @@ __global__ void __launch_bounds__(64) decode_kernel(const LaunchDesc jr) {
   constexpr int L2N = Tile<N>::L2N;
   __shared__ LdsDec<N> s;
   TileCoord tc;
-  const int c = (int)(blockIdx.x % 3u);
-  if (!locate_at<N>(jr, (int)(blockIdx.x / 3u), tc)) return;
+  const int id = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int c = id % 3;
+  if (!locate_at<N>(jr, id / 3, tc)) return;
   const FrameJob job = *tc.job;
   const int rem = threadIdx.x;
   const int r = rem / NBW;
@@ -729,14 +759,22 @@ __global__ void __launch_bounds__(64) decode_kernel(const LaunchDesc jr) {
   const uint32_t row_off = ((uint32_t)(c * job.Hp + y) * (uint32_t)job.Wp + (uint32_t)x0);
 
   uint32_t pp[N / 2];
+  uint32_t lp[N / 2];
+  const int k = r;  // column k = r of the block: its N levels are contiguous
+  bool lane_nz = false;
   if (vb) {
-    // column k = r of the block: its N levels are contiguous
-    const int k = r;
-    uint32_t lp[N / 2];
     load_row_packed<N>(job.lev, 2u * (((uint32_t)c * tc.Hb * tc.Wb + blk) * (N * N) + k * N), lp);
     int dx = 0, dy = 0;
     if (!job.intra) load_mv(job.mv, 2u * blk, dx, dy);
     pred_row<N>(job, c, r, y, x0, dx, dy, pp);
+    uint32_t any = 0;
+#pragma unroll
+    for (int m = 0; m < N / 2; m++) any |= lp[m];
+    lane_nz = any != 0u;
+  }
+  // all-zero levels in the wave: the residual is exactly zero (as in encode)
+  const bool wave_nz = __any(lane_nz);
+  if (vb && wave_nz) {
     const int qP = job.qp + 6 * (B - 8);
     const Dequant dqp = dequant_params(qP, B + L2N - 5);
     int lv[N];
@@ -752,7 +790,12 @@ __global__ void __launch_bounds__(64) decode_kernel(const LaunchDesc jr) {
   __syncthreads();
   if (vb) {
     uint32_t rp[N / 2];
-    inverse_row<N>(s.E[b][r], pp, B, rp);
+    if (wave_nz) {
+      inverse_row<N>(s.E[b][r], pp, B, rp);
+    } else {
+#pragma unroll
+      for (int j = 0; j < N / 2; j++) rp[j] = pp[j];
+    }
     store_row_packed<N>(job.rec, 2u * row_off, rp);
   }
 }
