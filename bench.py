@@ -505,6 +505,151 @@ def serve_bench(xv, synth, torch, n=160, seed=4, loads=(0.5, 0.9, 1.2, 2.0),
     return out
 
 
+def serve_at_size(xv, synth, torch, n, loads=(0.5, 0.9, 1.2), seed=4):
+    """The serving mix at its stated sizes: n requests (encode or decode with
+    p = 1/2), T log-uniform in 16..730 and side log-uniform in 64..1024 (the
+    tiny recipe's fields up to the Planet-like cube's shape), bands {3, 4, 6},
+    QP 17..37, N = 16, R = 16, GOP 16, Poisson arrivals at the offered loads
+    rho x the plain path's measured capacity.  Inputs are made at arrival time
+    from per-band-count pools of 32 generated 1024 x 1024 frames (frame t of a
+    request is pool frame t mod 32, cropped), so only the requests in flight
+    occupy memory; decode requests decode one of 8 cubes encoded beforehand.
+    Plain = one request at a time in arrival order; served = the continuous-
+    batching server.  Latency = completion - arrival."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    reqs = synth.request_trace(n, rate_per_s=1.0, seed=seed, t_range=(16, 730),
+                               s_range=(64, 1024))
+    # pools held as int16 views of the u16 samples (gathers support that type)
+    pools = {b: synth.tiny_cube(seed=90 + b, T=32, H=1024, W=1024, bands=b,
+                                device=dev).view(torch.int16) for b in (3, 4, 6)}
+    frame_idx = torch.arange(730, device=dev) % 32
+
+    def make(T, S, b):
+        return pools[b].index_select(0, frame_idx[:T])[:, :S, :S, :].contiguous().view(
+            torch.uint16)
+
+    def params(qp):
+        return xv.Params(bit_depth=10, qp=qp, block=16, search_range=16, gop=16,
+                         flags=xv.FLAG_DROP_WORK)
+
+    dec_src = [r for r in reqs if r.op == "decode"][:8]
+    pool_enc = []
+    for r in dec_src:
+        c = make(r.T, r.S, r.bands)
+        pool_enc.append((xv.encode_cube(c, params(r.qp)), (r.T, r.S, r.S, r.bands)))
+        del c
+    torch.cuda.synchronize()
+    items = []
+    k = 0
+    for r in reqs:
+        if r.op == "decode":
+            e, shape = pool_enc[k % len(pool_enc)]
+            k += 1
+            items.append(("decode", e, shape, shape[0] * shape[1] * shape[2] * shape[3]))
+        else:
+            items.append(("encode", (r.T, r.S, r.bands), params(r.qp),
+                          r.T * r.S * r.S * r.bands))
+    total_pxb = sum(it[3] for it in items)
+
+    def run_plain(it):
+        if it[0] == "encode":
+            c = make(*it[1])
+            e = xv.encode_cube(c, it[2])
+            torch.cuda.synchronize()
+            e.free()
+        else:
+            out = torch.empty(it[2], dtype=torch.uint16, device=dev)
+            xv.decode_cube(it[1], out)
+            torch.cuda.synchronize()
+
+    for it in items[:4]:
+        run_plain(it)
+    _log(f"serving at size: plain capacity over {n} requests")
+    t0 = time.perf_counter()
+    for it in items:
+        run_plain(it)
+    cap_s = time.perf_counter() - t0
+    mean_service = cap_s / len(items)
+    out = {"requests": len(items), "px_band_total": total_pxb,
+           "trace": "Poisson arrivals; encode/decode p=1/2; T log-uniform 16..730, side "
+                    "log-uniform 64..1024 (multiple of 32), bands {3,4,6}, QP 17..37, N=16, "
+                    "R=16, GOP 16; decode requests decode one of 8 pre-encoded cubes",
+           "plain_capacity_mpxb_s": round(total_pxb / cap_s / 1e6, 3),
+           "mean_service_ms": round(mean_service * 1e3, 3), "loads": []}
+    rng = np.random.default_rng(seed + 1)
+    gaps_unit = rng.exponential(1.0, len(items))
+    for rho in loads:
+        gaps = gaps_unit * mean_service / rho
+        arrive = np.cumsum(gaps) - gaps[0]
+        _log(f"serving at size: rho {rho} plain")
+        lat = []
+        base = time.perf_counter()
+        for it, a in zip(items, arrive):
+            now = time.perf_counter() - base
+            if now < a:
+                time.sleep(a - now)
+            run_plain(it)
+            lat.append((time.perf_counter() - base - a) * 1e3)
+        plain_span = time.perf_counter() - base
+        _log(f"serving at size: rho {rho} served")
+        sv = xv.Server(max_slots=64, hbm_budget=96 << 30)
+        pending = {}
+        slat = []
+        st_fail = 0
+
+        def reap(block=False):
+            nonlocal st_fail
+            for t in list(pending):
+                r = sv.wait(t) if block else sv.poll(t)
+                if r is None:
+                    continue
+                delay_ms, _ = pending.pop(t)
+                if r["status"] != xv.OK:
+                    st_fail += 1
+                # arrival -> submit (input made on arrival) + submit -> done
+                slat.append(delay_ms + r["done_ms"] - r["submit_ms"])
+                if r["enc"] is not None:
+                    r["enc"].free()
+
+        base = time.perf_counter()
+        for i, (it, a) in enumerate(zip(items, arrive)):
+            now = time.perf_counter() - base
+            if now < a:
+                time.sleep(a - now)
+            if it[0] == "encode":
+                c = make(*it[1])
+                torch.cuda.synchronize()  # the server's stream reads it
+                t = sv.submit_encode(c, it[2])
+                buf = c
+            else:
+                buf = torch.empty(it[2], dtype=torch.uint16, device=dev)
+                torch.cuda.synchronize()
+                t = sv.submit_decode(it[1], buf)
+            pending[t] = ((time.perf_counter() - base - a) * 1e3, buf)
+            if i % 8 == 0:
+                reap()
+        reap(block=True)
+        served_span = time.perf_counter() - base
+        st = sv.stats()
+        sv.close()
+        if st_fail:
+            raise SystemExit("served request failed")
+        out["loads"].append({
+            "rho": rho,
+            "served": {"value": round(total_pxb / served_span / 1e6, 3),
+                       "p50_ms": round(_percentile(slat, 0.5), 3),
+                       "p99_ms": round(_percentile(slat, 0.99), 3),
+                       "peak_active": st["peak_active"], "peak_GB": round(st["peak_bytes"] / 1e9, 1),
+                       "iterations": st["iterations"]},
+            "plain": {"value": round(total_pxb / plain_span / 1e6, 3),
+                      "p50_ms": round(_percentile(lat, 0.5), 3),
+                      "p99_ms": round(_percentile(lat, 0.99), 3)}})
+    for e, _ in pool_enc:
+        e.free()
+    return out
+
+
 def secondary(xv, torch, synth, name, steps, warmup, cached, no_tune):
     """A secondary workload: plain and batched throughput and the rooflines."""
     wl = synth.WORKLOADS[name]
@@ -676,6 +821,9 @@ def main():
                     help="skip the quarter-sample motion section")
     ap.add_argument("--no-pca", action="store_true",
                     help="skip the principal-components section")
+    ap.add_argument("--serve-size", type=int, default=0,
+                    help="run only the serving mix at its stated sizes with this many "
+                         "requests and print its JSON object")
     ap.add_argument("--counters", action="store_true",
                     help="workload for hardware-counter runs only: one 1 GiB device copy (the "
                          "calibration of FETCH_SIZE / WRITE_SIZE), then one batched step of the "
@@ -708,6 +856,11 @@ def main():
         with open(args.geometry_file) as f:
             cached = json.load(f)
     all_tuning = {}
+
+    if args.serve_size > 0:
+        print(json.dumps({"serving_mix_at_size": serve_at_size(xv, synth, torch,
+                                                               args.serve_size)}), flush=True)
+        return
 
     if args.counters:
         if cached is None:
