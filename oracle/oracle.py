@@ -38,7 +38,8 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("bit_depth", C.c_int32), ("qp", C.c_int32), ("block", C.c_int32),
                 ("search_range", C.c_int32), ("gop", C.c_int32),
-                ("pad_mode", C.c_int32), ("fill_mode", C.c_int32), ("qpel", C.c_int32)]
+                ("pad_mode", C.c_int32), ("fill_mode", C.c_int32), ("qpel", C.c_int32),
+                ("intra", C.c_int32)]
 
 
 @dataclass
@@ -51,10 +52,11 @@ class CodingParams:
     pad_mode: int = PAD_ZERO
     fill_mode: int = FILL_NEAREST
     qpel: int = 0
+    intra: int = 0
 
     def c(self) -> Params:
         return Params(self.bit_depth, self.qp, self.block, self.search_range,
-                      self.gop, self.pad_mode, self.fill_mode, self.qpel)
+                      self.gop, self.pad_mode, self.fill_mode, self.qpel, self.intra)
 
 
 _lib = None
@@ -107,6 +109,8 @@ def lib():
         L.xvo_interp_sample.restype = C.c_int32
         L.xvo_subpel_refine.argtypes = [p, p, i64, i64, C.c_int, C.c_int, C.c_int, i64, i64,
                                         C.c_int, C.c_int, p, p, p]
+        L.xvo_intra_refs.argtypes = [p, i64, i64, C.c_int, C.c_int, i64, i64, p]
+        L.xvo_intra_predict.argtypes = [p, C.c_int, C.c_int, C.c_int, p]
         L.xvo_pca_moments.argtypes = [p, i64, i64, p, p]
         L.xvo_pca_eigen.argtypes = [p, i64, p, p]
         L.xvo_pca_project.argtypes = [p, i64, i64, p, p, i64, i64, p]
@@ -128,12 +132,12 @@ def lib():
         L.xvo_bpppb.restype = C.c_double
         L.xvo_phys_sse.argtypes = [p, C.c_int, i64, i64, i64, i64, p, C.c_int, C.c_int,
                                    p, p, p]
-        L.xvo_bitstream_bits.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, p, p]
+        L.xvo_bitstream_bits.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, C.c_int, p, p]
         L.xvo_bitstream_bits.restype = C.c_uint64
-        L.xvo_write_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, p, p, p,
-                                          C.c_uint64, p]
-        L.xvo_read_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, p, C.c_uint64,
-                                         p, p, p]
+        L.xvo_write_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, C.c_int, p, p,
+                                          p, C.c_uint64, p]
+        L.xvo_read_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, C.c_int, p,
+                                         C.c_uint64, p, p, p]
         L.xvo_ssim_window.argtypes = [p]
         L.xvo_ssim_plane.argtypes = [p, p, i64, i64, i64, C.c_int]
         L.xvo_ssim_plane.restype = C.c_double
@@ -317,6 +321,25 @@ def subpel_refine(cur: np.ndarray, ref: np.ndarray, N: int, B: int, bx: int, by:
     return mx.value, my.value, sad.value
 
 
+def intra_refs(rec_plane: np.ndarray, N: int, B: int, bx: int, by: int) -> np.ndarray:
+    """xvo_intra_refs: the 4N + 1 reference samples of block (bx, by) of a
+    [Hp][Wp] plane, in substitution-scan order (H.265 8.4.4.2.2)."""
+    plane = np.ascontiguousarray(rec_plane, np.uint16)
+    Hp, Wp = plane.shape
+    refs = np.zeros(4 * N + 1, np.int32)
+    lib().xvo_intra_refs(_ptr(plane), Hp, Wp, N, B, bx, by, _ptr(refs))
+    return refs
+
+
+def intra_predict(refs: np.ndarray, N: int, mode: int, B: int) -> np.ndarray:
+    """xvo_intra_predict: N x N prediction [y][x] of mode 0 (planar) or 1 (DC)."""
+    r = np.ascontiguousarray(refs, np.int32)
+    assert r.size == 4 * N + 1
+    pred = np.zeros((N, N), np.int32)
+    lib().xvo_intra_predict(_ptr(r), N, mode, B, _ptr(pred))
+    return pred
+
+
 def pca_moments(cube: np.ndarray):
     """xvo_pca_moments: band means and covariance of a u16 cube [..][Bn]."""
     cube = np.ascontiguousarray(cube, np.uint16)
@@ -440,25 +463,26 @@ def encode_cube(cube: np.ndarray, params: CodingParams) -> dict:
     return o
 
 
-def write_bitstream(levels: np.ndarray, mvs: np.ndarray, gop: int) -> dict:
+def write_bitstream(levels: np.ndarray, mvs: np.ndarray, gop: int, imodes: int = 0) -> dict:
     """xvo_write_bitstream: levels [G][T][3][Hb][Wb][N][N] i16 and vectors
     [G][T][Hb][Wb][2] i8 -> payload bytes, its length in bits and the bit
-    offset of every segment (4 * Hb per frame)."""
+    offset of every segment (4 * Hb per frame).  imodes: I blocks carry
+    their intra mode bit."""
     G, T, _, Hb, Wb, N, _ = levels.shape
     levels = np.ascontiguousarray(levels, np.int16)
     mvs = np.ascontiguousarray(mvs, np.int8)
-    bits = int(lib().xvo_bitstream_bits(N, G, T, gop, Hb, Wb, _ptr(levels), _ptr(mvs)))
+    bits = int(lib().xvo_bitstream_bits(N, G, T, gop, Hb, Wb, imodes, _ptr(levels), _ptr(mvs)))
     nbytes = (bits + 7) // 8
     out = np.zeros(max(1, nbytes), np.uint8)
     index = np.zeros(G * T * 4 * Hb, np.uint64)
-    rc = lib().xvo_write_bitstream(N, G, T, gop, Hb, Wb, _ptr(levels), _ptr(mvs), _ptr(out),
-                                   out.size, _ptr(index))
+    rc = lib().xvo_write_bitstream(N, G, T, gop, Hb, Wb, imodes, _ptr(levels), _ptr(mvs),
+                                   _ptr(out), out.size, _ptr(index))
     if rc != 0:
         raise ValueError(f"xvo_write_bitstream failed ({rc})")
     return dict(payload=out[:nbytes], bits=bits, index=index)
 
 
-def read_bitstream(payload: np.ndarray, bits: int, shape_lev, gop: int) -> dict:
+def read_bitstream(payload: np.ndarray, bits: int, shape_lev, gop: int, imodes: int = 0) -> dict:
     """xvo_read_bitstream: sequential parse back to levels and vectors; also
     returns the segment offsets met."""
     G, T, _, Hb, Wb, N, _ = shape_lev
@@ -468,8 +492,8 @@ def read_bitstream(payload: np.ndarray, bits: int, shape_lev, gop: int) -> dict:
     buf = np.ascontiguousarray(payload, np.uint8)
     if buf.size == 0:
         buf = np.zeros(1, np.uint8)
-    rc = lib().xvo_read_bitstream(N, G, T, gop, Hb, Wb, _ptr(buf), bits, _ptr(levels),
-                                  _ptr(mvs), _ptr(index))
+    rc = lib().xvo_read_bitstream(N, G, T, gop, Hb, Wb, imodes, _ptr(buf), bits,
+                                  _ptr(levels), _ptr(mvs), _ptr(index))
     if rc != 0:
         raise ValueError(f"xvo_read_bitstream failed ({rc})")
     return dict(levels=levels, mvs=mvs, index=index)

@@ -461,8 +461,11 @@ static int32_t get_se(bit_reader* r) {
   return (k & 1) ? (int32_t)((k + 1) / 2) : -(int32_t)(k / 2);
 }
 
+/* With imodes set, an I block carries its intra mode as one bit where a P
+ * block carries its vector. */
 uint64_t xvo_bitstream_bits(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                            int64_t Wb, const int16_t* levels, const int8_t* mvs) {
+                            int64_t Wb, int imodes, const int16_t* levels,
+                            const int8_t* mvs) {
   uint64_t bits = 0;
   for (int64_t f = 0; f < G * T; f++) {
     int intra = (f % T) % gop == 0;
@@ -470,7 +473,8 @@ uint64_t xvo_bitstream_bits(int N, int64_t G, int64_t T, int gop, int64_t Hb,
       int pmx = 0, pmy = 0;
       for (int64_t bx = 0; bx < Wb; bx++) {
         const int8_t* mv = mvs + ((f * Hb + by) * Wb + bx) * 2;
-        if (!intra) bits += xvo_mv_bits(mv[0], mv[1], pmx, pmy);
+        if (intra) bits += imodes ? 1 : 0;
+        else bits += xvo_mv_bits(mv[0], mv[1], pmx, pmy);
         pmx = mv[0];
         pmy = mv[1];
       }
@@ -482,8 +486,9 @@ uint64_t xvo_bitstream_bits(int N, int64_t G, int64_t T, int gop, int64_t Hb,
 }
 
 int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                        int64_t Wb, const int16_t* levels, const int8_t* mvs,
-                        uint8_t* out, uint64_t out_bytes, uint64_t* index) {
+                        int64_t Wb, int imodes, const int16_t* levels,
+                        const int8_t* mvs, uint8_t* out, uint64_t out_bytes,
+                        uint64_t* index) {
   int32_t order[32 * 32];
   xvo_scan_order(N, order);
   memset(out, 0, out_bytes);
@@ -499,6 +504,8 @@ int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
         if (!intra) {
           put_se(&w, mv[0] - pmx);
           put_se(&w, mv[1] - pmy);
+        } else if (imodes) {
+          put_bit(&w, mv[0] != 0);
         }
         pmx = mv[0];
         pmy = mv[1];
@@ -533,9 +540,9 @@ int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
 
 /* Sequential parse of the whole stream; index (may be NULL) receives the
  * segment offsets met on the way.  Levels not listed are zero; I frames get
- * the vector (0,0). */
+ * the vector (0,0), or (mode, 0) with imodes. */
 int xvo_read_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                       int64_t Wb, const uint8_t* in, uint64_t bits,
+                       int64_t Wb, int imodes, const uint8_t* in, uint64_t bits,
                        int16_t* levels, int8_t* mvs, uint64_t* index) {
   int32_t order[32 * 32];
   xvo_scan_order(N, order);
@@ -554,6 +561,8 @@ int xvo_read_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
         if (!intra) {
           dx = pmx + get_se(&r);
           dy = pmy + get_se(&r);
+        } else if (imodes) {
+          dx = get_bit(&r);
         }
         mv[0] = (int8_t)dx;
         mv[1] = (int8_t)dy;
@@ -764,6 +773,133 @@ void xvo_subpel_refine(const uint16_t* cur, const uint16_t* ref, int64_t Hp,
 /*   mv_bits       : [len][Hb][Wb] u32                                        */
 /*   sse, nvalid   : [3] u64, over valid pixels of the coded GOP              */
 /* ------------------------------------------------------------------------- */
+/* Intra prediction of I pictures (ITU-T H.265 8.4.4.2).  The paper names    */
+/* no intra modes; the reading is: the two non-directional H.265 modes,      */
+/* planar (0) and DC (1); blocks coded in raster order at the fixed size N,  */
+/* so a sample is available when it lies in the padded picture and in a      */
+/* block before the current one in raster order; every channel treated as   */
+/* H.265 luma (DC edge filter for N < 32); strong smoothing of 32 x 32       */
+/* references on, as in x265's default; one mode per block for the group's   */
+/* three channels, the one with the smaller SAD against the source over the  */
+/* real channels, planar on a tie.                                           */
+/*                                                                           */
+/* refs holds the 4N + 1 reference samples in the order of the substitution  */
+/* scan (H.265 8.4.4.2.2): refs[i] = p[-1][2N-1-i] for i < 2N, refs[2N] =    */
+/* p[-1][-1], refs[2N+1+x] = p[x][-1].                                       */
+/* ------------------------------------------------------------------------- */
+void xvo_intra_refs(const uint16_t* rec_plane, int64_t Hp, int64_t Wp, int N, int B,
+                    int64_t bx, int64_t by, int32_t* refs) {
+  int64_t Wb = Wp / N, cur = by * Wb + bx;
+  int64_t x0 = bx * N, y0 = by * N;
+  int avail[4 * 32 + 1];
+  int n = 4 * N + 1, any = 0;
+  for (int i = 0; i < n; i++) {
+    int64_t x, y;
+    if (i < 2 * N) {
+      x = x0 - 1;
+      y = y0 + (2 * N - 1 - i);
+    } else if (i == 2 * N) {
+      x = x0 - 1;
+      y = y0 - 1;
+    } else {
+      x = x0 + (i - 2 * N - 1);
+      y = y0 - 1;
+    }
+    int in = x >= 0 && y >= 0 && x < Wp && y < Hp;
+    avail[i] = in && (y / N) * Wb + x / N < cur;
+    refs[i] = avail[i] ? rec_plane[y * Wp + x] : 0;
+    any |= avail[i];
+  }
+  if (!any) {
+    for (int i = 0; i < n; i++) refs[i] = 1 << (B - 1);
+    return;
+  }
+  /* the first entry takes the first available sample of the scan; every
+   * other unavailable entry takes the entry before it */
+  if (!avail[0]) {
+    int k = 1;
+    while (!avail[k]) k++;
+    refs[0] = refs[k];
+  }
+  for (int i = 1; i < n; i++)
+    if (!avail[i]) refs[i] = refs[i - 1];
+}
+
+/* p[-1][y] and p[x][-1] of a reference array in scan order */
+#define XVO_LEFT(a, y) ((a)[2 * N - 1 - (y)])
+#define XVO_TOP(a, x) ((a)[2 * N + 1 + (x)])
+
+void xvo_intra_predict(const int32_t* refs, int N, int mode, int B, int32_t* pred) {
+  int k = ilog2(N);
+  if (mode == 0) {
+    /* planar: references smoothed first for N >= 8 (H.265 8.4.4.2.3) */
+    int32_t f[4 * 32 + 1];
+    int n = 4 * N + 1;
+    for (int i = 0; i < n; i++) f[i] = refs[i];
+    if (N >= 8) {
+      int thr = 1 << (B - 5);
+      int corner = XVO_LEFT(refs, -1);
+      int strong = N == 32 &&
+                   abs(corner + XVO_TOP(refs, 2 * N - 1) - 2 * XVO_TOP(refs, N - 1)) < thr &&
+                   abs(corner + XVO_LEFT(refs, 2 * N - 1) - 2 * XVO_LEFT(refs, N - 1)) < thr;
+      if (strong) {
+        /* bilinear between the corner and the far ends of each edge */
+        for (int y = 0; y < 2 * N - 1; y++)
+          XVO_LEFT(f, y) = ((63 - y) * corner + (y + 1) * XVO_LEFT(refs, 2 * N - 1) + 32) >> 6;
+        for (int x = 0; x < 2 * N - 1; x++)
+          XVO_TOP(f, x) = ((63 - x) * corner + (x + 1) * XVO_TOP(refs, 2 * N - 1) + 32) >> 6;
+      } else {
+        /* [1 2 1] along the scan; both ends kept */
+        for (int i = 1; i < n - 1; i++) f[i] = (refs[i - 1] + 2 * refs[i] + refs[i + 1] + 2) >> 2;
+      }
+    }
+    for (int y = 0; y < N; y++)
+      for (int x = 0; x < N; x++)
+        pred[y * N + x] = ((N - 1 - x) * XVO_LEFT(f, y) + (x + 1) * XVO_TOP(f, N) +
+                           (N - 1 - y) * XVO_TOP(f, x) + (y + 1) * XVO_LEFT(f, N) + N) >>
+                          (k + 1);
+  } else {
+    /* DC from the unsmoothed references, edges filtered for N < 32 */
+    int sum = N;
+    for (int i = 0; i < N; i++) sum += XVO_TOP(refs, i) + XVO_LEFT(refs, i);
+    int dc = sum >> (k + 1);
+    for (int i = 0; i < N * N; i++) pred[i] = dc;
+    if (N < 32) {
+      pred[0] = (XVO_LEFT(refs, 0) + 2 * dc + XVO_TOP(refs, 0) + 2) >> 2;
+      for (int x = 1; x < N; x++) pred[x] = (XVO_TOP(refs, x) + 3 * dc + 2) >> 2;
+      for (int y = 1; y < N; y++) pred[y * N] = (XVO_LEFT(refs, y) + 3 * dc + 2) >> 2;
+    }
+  }
+}
+
+#undef XVO_LEFT
+#undef XVO_TOP
+
+/* Mode of an I block (reading above) from the current frame and the        */
+/* partly reconstructed one; preds receives the chosen mode's prediction of  */
+/* each channel, [3][N][N].                                                  */
+static int intra_choose(const uint16_t* cur, const uint16_t* rec, int64_t Hp, int64_t Wp,
+                        int N, int B, int nch, int64_t bx, int64_t by, int32_t* preds) {
+  int64_t plane = Hp * Wp;
+  int32_t refs[4 * 32 + 1], cand[2][3][32 * 32];
+  uint64_t cost[2] = {0, 0};
+  for (int c = 0; c < 3; c++) {
+    xvo_intra_refs(rec + c * plane, Hp, Wp, N, B, bx, by, refs);
+    for (int m = 0; m < 2; m++) {
+      xvo_intra_predict(refs, N, m, B, cand[m][c]);
+      if (c >= nch) continue;
+      for (int y = 0; y < N; y++)
+        for (int x = 0; x < N; x++) {
+          int d = (int)cur[c * plane + (by * N + y) * Wp + bx * N + x] - cand[m][c][y * N + x];
+          cost[m] += (uint64_t)(d < 0 ? -d : d);
+        }
+    }
+  }
+  int mode = cost[1] < cost[0] ? 1 : 0;
+  for (int c = 0; c < 3; c++) memcpy(preds + c * N * N, cand[mode][c], sizeof(int32_t) * N * N);
+  return mode;
+}
+
 /* Prediction of sample (x, y) of a P block from the reference plane: the    */
 /* displaced sample for integer vectors, the interpolated one for quarter-    */
 /* sample vectors.                                                            */
@@ -774,17 +910,18 @@ static int predict_sample(const xvo_params* p, const uint16_t* ref_plane, int64_
   return ref_plane[(y + dy) * Wp + x + dx];
 }
 
-static void code_block(const xvo_params* p, int intra, const uint16_t* cur,
-                       const uint16_t* pred_plane, int64_t Hp, int64_t Wp,
-                       int64_t x0, int64_t y0, int dx, int dy, int16_t* lev_out,
+static void code_block(const xvo_params* p, int intra, const int32_t* ipred,
+                       const uint16_t* cur, const uint16_t* pred_plane, int64_t Hp,
+                       int64_t Wp, int64_t x0, int64_t y0, int dx, int dy, int16_t* lev_out,
                        uint16_t* rec_plane, uint32_t* bits_out) {
   int N = p->block, B = p->bit_depth;
   int L = (1 << B) - 1;
   int32_t r[32 * 32] = {0}, C[32 * 32], d[32 * 32], rr[32 * 32], pred[32 * 32];
   for (int i = 0; i < N; i++)
     for (int j = 0; j < N; j++) {
-      int pv = intra ? (1 << (B - 1))
-                     : predict_sample(p, pred_plane, Hp, Wp, x0 + j, y0 + i, dx, dy);
+      int pv = ipred   ? ipred[i * N + j]
+               : intra ? (1 << (B - 1))
+                       : predict_sample(p, pred_plane, Hp, Wp, x0 + j, y0 + i, dx, dy);
       pred[i * N + j] = pv;
       r[i * N + j] = (int32_t)cur[(y0 + i) * Wp + x0 + j] - pv;
     }
@@ -830,6 +967,10 @@ int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
         int32_t dx = 0, dy = 0;
         uint32_t sad = 0;
         int64_t bi = by * Wb + bx;
+        int32_t ipred[3 * 32 * 32];
+        int use_ipred = intra && p->intra;
+        if (use_ipred) /* the mode travels in the vector's first byte */
+          dx = intra_choose(cur, rec, Hp, Wp, N, p->bit_depth, nch, bx, by, ipred);
         if (!intra) {
           xvo_motion_search(cur, ref, Hp, Wp, N, p->search_range, nch, bx, by, &dx,
                             &dy, &sad);
@@ -843,12 +984,14 @@ int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
         }
         mvs[(f * Hb * Wb + bi) * 2 + 0] = (int8_t)dx;
         mvs[(f * Hb * Wb + bi) * 2 + 1] = (int8_t)dy;
-        mv_bits[f * Hb * Wb + bi] = intra ? 0 : xvo_mv_bits(dx, dy, pmx, pmy);
-        pmx = dx;
-        pmy = dy;
+        mv_bits[f * Hb * Wb + bi] =
+            intra ? (uint32_t)p->intra /* one mode bit */ : xvo_mv_bits(dx, dy, pmx, pmy);
+        pmx = intra ? 0 : dx;
+        pmy = intra ? 0 : dy;
         for (int c = 0; c < 3; c++) {
           int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + bi) * N * N;
-          code_block(p, intra, cur + c * plane, ref ? ref + c * plane : NULL,
+          code_block(p, intra, use_ipred ? ipred + c * N * N : NULL, cur + c * plane,
+                     ref ? ref + c * plane : NULL,
                      Hp, Wp, bx * N, by * N, dx, dy, lev, rec + c * plane,
                      &coef_bits[(f * 3 + c) * Hb * Wb + bi]);
         }
@@ -885,12 +1028,17 @@ int xvo_decode_gop(const xvo_params* p, int64_t H, int64_t W, int64_t len,
         int dy = mvs[(f * Hb * Wb + bi) * 2 + 1];
         for (int c = 0; c < 3; c++) {
           const int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + bi) * N * N;
+          int32_t ipred[32 * 32], refs[4 * 32 + 1];
+          if (f == 0 && p->intra) {  /* mode in the vector's first byte */
+            xvo_intra_refs(rec + c * plane, Hp, Wp, N, B, bx, by, refs);
+            xvo_intra_predict(refs, N, dx, B, ipred);
+          }
           xvo_dequantize(N, B, p->qp, lev, d);
           xvo_inverse_transform(N, B, d, rr);
           for (int i = 0; i < N; i++)
             for (int j = 0; j < N; j++) {
               int64_t y = by * N + i, x = bx * N + j;
-              int pv = f == 0 ? (1 << (B - 1))
+              int pv = f == 0 ? (p->intra ? ipred[i * N + j] : (1 << (B - 1)))
                               : predict_sample(p, ref + c * plane, Hp, Wp, x, y, dx, dy);
               int v = pv + rr[i * N + j];
               if (v < 0) v = 0;
@@ -915,6 +1063,7 @@ int xvo_check_params(const xvo_params* p) {
   if (p->qp < -6 * (B - 8) || p->qp > 51) return -1;
   if (p->search_range < 0 || p->search_range > 64) return -1;
   if (p->qpel != 0 && p->qpel != 1) return -1;
+  if (p->intra != 0 && p->intra != 1) return -1;
   /* quarter-sample vectors reach 4R + 3, which must fit int8 */
   if (p->qpel && p->search_range > 31) return -1;
   if (p->gop < 1) return -1;

@@ -28,6 +28,8 @@ typedef struct {
   int32_t pad_mode;     /* XVO_PAD_* */
   int32_t fill_mode;    /* XVO_FILL_* */
   int32_t qpel;         /* 1: quarter-sample motion (R <= 31), 0: integer */
+  int32_t intra;        /* 1: I blocks predicted by DC / planar from their
+                           reconstructed neighbours, 0: constant 2^(B-1) */
 } xvo_params;
 
 int xvo_selfcheck(void);
@@ -85,6 +87,14 @@ void xvo_pca_project(const uint16_t* data, int64_t npix, int64_t Bn, const doubl
 void xvo_pca_inverse(const float* pcs, int64_t npix, int64_t Bn, int64_t k,
                      const double* mean, const double* basis, int out_dtype, void* out);
 
+/* Intra prediction of I pictures: reference samples of block (bx, by) of a
+ * plane whose blocks before it in raster order are reconstructed, in the
+ * substitution order (p[-1][2N-1] .. p[-1][0], p[-1][-1], p[0][-1] ..
+ * p[2N-1][-1]), and the N x N prediction [y][x] of mode 0 (planar) or 1 (DC). */
+void xvo_intra_refs(const uint16_t* rec_plane, int64_t Hp, int64_t Wp, int N, int B,
+                    int64_t bx, int64_t by, int32_t* refs);
+void xvo_intra_predict(const int32_t* refs, int N, int mode, int B, int32_t* pred);
+
 int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
                    int64_t W, int64_t Bn, const double* mn, const double* mx,
                    const xvo_params* p, int64_t g, int64_t t0, int64_t len,
@@ -110,12 +120,14 @@ void xvo_denormalize_cube(const uint16_t* recon, int64_t T, int64_t H,
  * frame f = g * T + t, intra when t % gop == 0.  index receives the bit
  * offset of each of the 4 * Hb segments per frame. */
 uint64_t xvo_bitstream_bits(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                            int64_t Wb, const int16_t* levels, const int8_t* mvs);
+                            int64_t Wb, int imodes, const int16_t* levels,
+                            const int8_t* mvs);
 int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                        int64_t Wb, const int16_t* levels, const int8_t* mvs,
-                        uint8_t* out, uint64_t out_bytes, uint64_t* index);
+                        int64_t Wb, int imodes, const int16_t* levels,
+                        const int8_t* mvs, uint8_t* out, uint64_t out_bytes,
+                        uint64_t* index);
 int xvo_read_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                       int64_t Wb, const uint8_t* in, uint64_t bits,
+                       int64_t Wb, int imodes, const uint8_t* in, uint64_t bits,
                        int16_t* levels, int8_t* mvs, uint64_t* index);
 
 double xvo_psnr(double peak, double sse, double n);
