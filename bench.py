@@ -101,7 +101,8 @@ def describe(wl) -> str:
     kind = {"planet": "u16 Voronoi land-cover patches (stand-in for DynamicEarthNet), RGB+NIR, "
                       "second band group NIR + 2 zero channels",
             "s2cloud": "f32 with ~10% NaN cloud gaps (stand-in for DeepExtremeCubes)",
-            "era5": "f32 reanalysis-like variables (stand-in for ERA5), rows edge-padded to 736"}
+            "era5": "f32 reanalysis-like variables (stand-in for ERA5), rows edge-padded to 736",
+            "drift": "u16 1/f^3 texture drifting by (0.37, -0.23) samples per frame"}
     return (f"{wl.name}: {wl.T}x{wl.H}x{wl.W}x{wl.bands} {kind.get(wl.name, wl.dtype)}, "
             f"B={wl.bit_depth}, QP{list(wl.qps)} x N{list(wl.blocks)} "
             f"({len(wl.qps) * len(wl.blocks)} runs per step), R={wl.search_range}, "
@@ -673,12 +674,13 @@ def secondary(xv, torch, synth, name, steps, warmup, cached, no_tune):
 
 
 def qpel_bench(xv, torch, synth, steps, warmup, cached, no_tune):
-    """Quarter-sample motion (XV_FLAG_QPEL) on the cloud-gapped sweep: the
-    15 runs coded with the refinement, batched, against the same runs with
-    integer vectors: throughput, the refinement kernel's share of the step,
-    and PSNR / bpppb of both."""
-    wl = synth.WORKLOADS["s2cloud"]
-    cube = synth.make_cube("s2cloud", device="cuda")
+    """Quarter-sample motion (XV_FLAG_QPEL) on the drift cube, whose texture
+    moves by fractions of a sample per frame: its runs coded with the
+    refinement, batched, against the same runs with integer vectors:
+    throughput, the refinement kernel's share of the step, and PSNR / bpppb
+    of both."""
+    wl = synth.WORKLOADS["drift"]
+    cube = synth.make_cube("drift", device="cuda")
     torch.cuda.synchronize()
     runs, params = workload_params(xv, wl)
     tune(xv, wl, cube, params, cached, no_tune)
@@ -721,6 +723,54 @@ def qpel_bench(xv, torch, synth, steps, warmup, cached, no_tune):
             sp = prof["subpel"]
             out[name]["subpel_candidate_samples_per_s"] = sp["work"] / (sp["ms"] * 1e-3)
     del outs, cube
+    return out
+
+
+def intra_bench(xv, torch, wl, cube, params, runs, steps, warmup=1):
+    """Intra-predicted I pictures (XV_FLAG_INTRA) on the headline cube: the
+    same runs, batched, with every I block predicted by planar or DC from its
+    reconstructed neighbours (the I step coded in wavefronts) instead of the
+    constant mid-level: throughput, the wavefront kernel's share of the step
+    and its bandwidth, and PSNR / bpppb."""
+    iparams = [xv.Params(bit_depth=p.bit_depth, qp=p.qp, block=p.block,
+                         search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
+                         fill_mode=p.fill_mode, flags=xv.FLAG_INTRA) for p in params]
+    outs = [torch.empty_like(cube) for _ in iparams]
+
+    def step():
+        encs = xv.encode_batch([cube] * len(iparams), iparams)
+        xv.decode_batch(encs, outs)
+        ms = xv.psnr_bpppb_batch([cube] * len(encs), encs)
+        for e in encs:
+            e.free()
+        return ms
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ms = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    xv.profile_select(None)
+    xv.profile_enable(True)
+    step()
+    prof = xv.profile_read()
+    xv.profile_enable(False)
+    del outs
+    px_band = wl.px_band * len(iparams)
+    out = {"workload": describe(wl) + "; I pictures intra-predicted (planar / DC)",
+           "runs": [f"QP{qp}/N{N}" for qp, N in runs],
+           "value": round(px_band * steps / dt / 1e6, 3),
+           "ms_per_step": round(dt / steps * 1e3, 3),
+           "psnr_db_mean_per_run": [round(sum(m["psnr"]) / len(m["psnr"]), 4) for m in ms],
+           "bpppb_per_run": [round(m["bpppb"], 5) for m in ms],
+           "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}}
+    ip = prof["intra"]
+    if ip["launches"]:
+        out["intra_launches_per_step"] = int(ip["launches"])
+        out["intra_GBps"] = round(ip["work"] / (ip["ms"] * 1e-3) / 1e9, 1)
     return out
 
 
@@ -819,6 +869,8 @@ def main():
                     help="skip the cloud-gapped sweep and the reanalysis-like cube")
     ap.add_argument("--no-qpel", action="store_true",
                     help="skip the quarter-sample motion section")
+    ap.add_argument("--no-intra", action="store_true",
+                    help="skip the intra-predicted I pictures section")
     ap.add_argument("--no-pca", action="store_true",
                     help="skip the principal-components section")
     ap.add_argument("--serve-size", type=int, default=0,
@@ -930,6 +982,9 @@ def main():
     if not args.no_bits:
         _log("bitstream")
         line["bitstream"] = bits_bench(xv, torch, cube, params, r["pxb_step"], qsteps)
+    if not args.no_intra:
+        _log("intra-predicted I pictures")
+        line["intra"] = intra_bench(xv, torch, wl, cube, params, runs, qsteps)
     if not args.no_pca:
         _log("principal components")
         line["pca"] = pca_bench(xv, torch, wl, cube, max(1, min(args.steps, 3)), 1)

@@ -32,7 +32,8 @@
  *   levels                [G][T][3][Hb][Wb][N][N] i16 (block-major; inside a
  *                          block column-major: the level of vertical
  *                          frequency l, horizontal frequency k at k * N + l)
- *   motion vectors        [G][T][Hb][Wb][2] i8 (dx, dy); zero in I pictures;
+ *   motion vectors        [G][T][Hb][Wb][2] i8 (dx, dy); zero in I pictures
+ *                          ((mode, 0) under XV_FLAG_INTRA: 0 planar, 1 DC);
  *                          in quarter samples under XV_FLAG_QPEL
  *   coefficient bits      [G][T][3][Hb][Wb] u32
  *   motion-vector bits    [G][T][Hb][Wb] u32
@@ -47,7 +48,7 @@
 extern "C" {
 #endif
 
-#define XV_ABI_VERSION 6
+#define XV_ABI_VERSION 7
 
 /* status codes */
 #define XV_OK 0
@@ -80,6 +81,16 @@ extern "C" {
                                 quarter samples with the H.265 luma
                                 interpolation filters; vectors are stored in
                                 quarter samples (needs search_range <= 31) */
+#define XV_FLAG_INTRA 4u     /* intra prediction of I pictures: each block
+                                predicted from its reconstructed neighbours
+                                by planar or DC (ITU-T H.265 8.4.4.2), the
+                                mode with the smaller SAD over the real
+                                channels (planar on a tie), one mode per
+                                block for the group; blocks coded in raster
+                                order, so a picture is coded in wavefronts.
+                                The mode is stored as the first byte of the
+                                block's vector entry and costs one vector
+                                bit. */
 
 #define XV_MAX_BANDS 64
 #define XV_MAX_GROUPS 22
@@ -394,7 +405,8 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
 #define XV_K_QUALITY 9
 #define XV_K_SUBPEL 10 /* quarter-sample refinement and motion compensation */
 #define XV_K_PCA 11    /* principal components: moments, projection, inverse */
-#define XV_K_COUNT 12
+#define XV_K_INTRA 12  /* intra-predicted I pictures, one launch per wavefront */
+#define XV_K_COUNT 13
 
 typedef struct {
   double ms[XV_K_COUNT];       /* summed kernel time per kernel class     */
@@ -419,7 +431,8 @@ int xv_profile_read(xv_profile* out);
  * Codes are the Exp-Golomb ue/se codes of ITU-T H.265 clause 9.2, MSB-first.
  * Payload order, frame by frame (f = g*T + t): the vectors of the frame's
  * blocks in raster order (se(dx - pdx), se(dy - pdy) with the left
- * neighbour's vector as predictor, (0,0) in column 0; nothing for I frames),
+ * neighbour's vector as predictor, (0,0) in column 0; nothing for I frames,
+ * or one mode bit per block under XV_FLAG_INTRA),
  * then for channel c = 0, 1, 2 the blocks' coefficients in raster order (a
  * coded-flag bit, then ue(nnz-1) and per nonzero level in up-right diagonal
  * scan order ue(run), se(level)).  The payload has exactly coef_bits +

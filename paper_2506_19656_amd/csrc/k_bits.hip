@@ -7,7 +7,8 @@
 // bytes.  Stream order, frame by frame (f = g * T + t): the vector units of
 // the frame's blocks in raster order (se(dx - pdx), se(dy - pdy), the left
 // neighbour's vector as predictor, (0,0) in column 0; I frames have empty
-// vector units), then for channel c = 0, 1, 2 the coefficient units of the
+// vector units, or one bit holding the block's intra mode when I blocks are
+// intra-predicted), then for channel c = 0, 1, 2 the coefficient units of the
 // blocks in raster order (coded flag, then ue(nnz - 1) and per nonzero level
 // in up-right diagonal scan order ue(run), se(level)).  A frame therefore
 // has 4 Hb Wb units; a row of Wb units is a segment, whose bit offset is
@@ -165,6 +166,11 @@ __global__ void __launch_bounds__(kBitsThreads) write_units_kernel(BitsArgs a) {
   const int64_t r = u - f * 4 * hw;
   if (r < hw) {
     const int8_t* mv = a.mvs + (f * hw + r) * 2;
+    if ((f % a.T) % a.gop == 0) {  // an intra mode (I units are empty otherwise)
+      bs.put(mv[0] != 0 ? 1u : 0u, 1);
+      bs.flush();
+      return;
+    }
     int pmx = 0, pmy = 0;
     if (r % a.Wb != 0) {
       pmx = mv[-2];
@@ -299,6 +305,8 @@ __global__ void __launch_bounds__(kBitsThreads) parse_segments_kernel(BitsArgs a
         dx = pmx + ddx;
         dy = pmy + ddy;
         ok = ok && dx >= -128 && dx <= 127 && dy >= -128 && dy <= 127;
+      } else if (a.imodes) {
+        dx = src.bit();
       }
       a.mvs_out[blk * 2] = (int8_t)dx;
       a.mvs_out[blk * 2 + 1] = (int8_t)dy;

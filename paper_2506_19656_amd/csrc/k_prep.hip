@@ -978,13 +978,15 @@ __global__ void plan_kernel(CubePlan p) {
   jb.part = p.part ? p.part + f * p.tpf * 5 : nullptr;
   // one prediction plane per stream (g, k), reused by the stream's steps
   const int ngop = (p.T + p.gop - 1) / p.gop;
-  jb.pred = (p.pred && s > 0) ? p.pred + ((int64_t)g * ngop + k) * 3 * plane : nullptr;
+  jb.pred = (p.pred && (s > 0 ? p.qpel : p.imode)) ? p.pred + ((int64_t)g * ngop + k) * 3 * plane
+                                                    : nullptr;
   jb.Hp = p.Hp;
   jb.Wp = p.Wp;
   jb.H = p.H;
   jb.W = p.W;
   jb.nch = min(3, p.bands - 3 * g);
   jb.intra = s == 0;
+  jb.imode = s == 0 && p.imode;
   jb.bit_depth = p.bit_depth;
   jb.qp = p.qp;
   p.jobs[i] = jb;

@@ -25,6 +25,7 @@
 // the forward column stage, whose inputs may need the full 16 bits, stays a
 // plain matrix product.  All sums are exact integers, so the factorised
 // forms give the same results as the matrix products they replace.
+#include <algorithm>
 #include <utility>
 
 #include "xv_internal.h"
@@ -368,21 +369,22 @@ __device__ inline void store_row_packed(void* base, uint32_t off, const uint32_t
   }
 }
 
-// Prediction row as packed pairs: I -> 2^(B-1); P -> the reference displaced
-// by (dx, dy), or with quarter-sample vectors the step's prediction plane.  A coded vector keeps the displaced block inside the padded
-// picture; the clamp only guarantees in-bounds reads for a corrupt vector.
-// The row is read as aligned dwords and shifted by one sample when the
-// displaced column is odd; the extra dword is then in bounds (rx + N is odd
-// and Wp even, so rx + N < Wp).
+// Prediction row as packed pairs: the step's prediction plane where it has
+// one (quarter-sample P steps, intra-predicted I steps); else I -> 2^(B-1)
+// and P -> the reference displaced by (dx, dy).  A coded vector keeps the
+// displaced block inside the padded picture; the clamp only guarantees
+// in-bounds reads for a corrupt vector.  The row is read as aligned dwords
+// and shifted by one sample when the displaced column is odd; the extra
+// dword is then in bounds (rx + N is odd and Wp even, so rx + N < Wp).
 template <int N>
 __device__ inline void pred_row(const FrameJob& job, int c, int r, int y, int x0, int dx, int dy,
                                 uint32_t (&pp)[N / 2]) {
-  if (job.intra) {
+  if (job.intra && !job.pred) {
     const uint32_t h = 1u << (job.bit_depth - 1);
 #pragma unroll
     for (int j = 0; j < N / 2; j++) pp[j] = h | (h << 16);
   } else {
-    // quarter-sample vectors: the step's prediction plane at displacement zero
+    // a prediction plane is read at displacement zero
     const uint16_t* src = job.pred ? job.pred : job.ref;
     if (job.pred) dx = dy = 0;
     const int ry = min(max(y - r + dy, 0), job.Hp - N) + r;
@@ -701,7 +703,11 @@ encode_kernel(const LaunchDesc jr) {
   if (c == 0 && r == 0 && vb) {
     uint32_t bits = 0;
     if (job.intra) {
-      gst<uint16_t>(job.mv, 2u * blk, (uint16_t)0);
+      // an intra mode (written by the wavefront kernel) costs one bit
+      if (job.imode)
+        bits = 1u;
+      else
+        gst<uint16_t>(job.mv, 2u * blk, (uint16_t)0);
     } else {
       int pmx = 0, pmy = 0;
       if (bx > 0) load_mv(job.mv, 2u * (blk - 1), pmx, pmy);
@@ -800,6 +806,248 @@ __global__ void __launch_bounds__(64) decode_kernel(const LaunchDesc jr) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Intra-predicted I steps, one wavefront per launch.  In raster order a
+// block predicts from its left, top-left, top and top-right neighbours, all
+// in earlier wavefronts w = bx + 2 by, so the blocks of one wavefront are
+// independent.  A workgroup takes NBW blocks of the wavefront (consecutive
+// by) with their 3 channels, in the thread layout of the transform kernel
+// (wave c = channel; lane = block row r of block b).
+//
+// References (ITU-T H.265 8.4.4.2.2) in substitution-scan order: entry i <
+// 2N holds p[-1][2N-1-i], entry 2N the corner, entry 2N+1+x holds p[x][-1].
+// With equal blocks in raster order the left block is available iff bx > 0,
+// the top one iff by > 0, the top-left iff both, the top-right iff by > 0
+// and bx + 1 < Wb, the bottom-left never.  The substitution scan then
+// reduces to reading every entry from one fixed sample: left entries from
+// the left column (its lower half repeating p[-1][N-1]) or, without a left
+// block, p[0][-1]; the corner from itself, else p[-1][0], else p[0][-1];
+// top entries from the top row (past p[N-1][-1] repeating it without a
+// top-right block) or, without a top block, p[-1][0]; nothing available:
+// 2^(B-1).
+// ---------------------------------------------------------------------------
+template <int N>
+struct alignas(16) LdsIntra {
+  int16_t TD[3][Tile<N>::NBW][N][Tile<N>::P];
+  int16_t E[3][Tile<N>::NBW][N][Tile<N>::P];
+  uint16_t ref[3][Tile<N>::NBW][4 * N + 2];  // substituted references
+  uint16_t flt[3][Tile<N>::NBW][4 * N + 2];  // smoothed for planar (N >= 8)
+  uint32_t sad[Tile<N>::NBW][2];             // per block: planar, DC
+};
+
+template <int N>
+__device__ inline int intra_ref(const FrameJob& job, int c, int x0, int y0, bool aL, bool aT,
+                                bool aTR, int i) {
+  if (!aL && !aT) return 1 << (job.bit_depth - 1);
+  int x, y;
+  if (i < 2 * N) {
+    x = aL ? x0 - 1 : x0;
+    y = aL ? y0 + min(2 * N - 1 - i, N - 1) : y0 - 1;
+  } else if (i == 2 * N) {
+    x = aL ? x0 - 1 : x0;
+    y = aT ? y0 - 1 : y0;
+  } else {
+    x = aT ? x0 + min(i - 2 * N - 1, aTR ? 2 * N - 1 : N - 1) : x0 - 1;
+    y = aT ? y0 - 1 : y0;
+  }
+  return gld<uint16_t>(job.rec, 2u * ((uint32_t)(c * job.Hp + y) * (uint32_t)job.Wp + (uint32_t)x));
+}
+
+template <int N>
+__global__ void __launch_bounds__(192) intra_kernel(const LaunchDesc jr, int wave, int decode) {
+  constexpr int NBW = Tile<N>::NBW;
+  constexpr int L2N = Tile<N>::L2N;
+  constexpr int NR = 4 * N + 1;
+  __shared__ LdsIntra<N> s;
+  int tl;
+  const FrameJob job = *desc_job(jr, (int)blockIdx.x, tl);
+  const int Hb = job.Hp / N, Wb = job.Wp / N;
+  // the wavefront's blocks: by in [by_lo, by_hi], bx = wave - 2 by
+  const int lo = wave - (Wb - 1);
+  const int by_lo = lo > 0 ? (lo + 1) / 2 : 0;
+  const int by_hi = min(Hb - 1, wave / 2);
+  const int by0 = by_lo + tl * NBW;
+  if (by0 > by_hi) return;  // the whole workgroup
+
+  const int t = threadIdx.x;
+  const int c = t >> 6;
+  const int rem = t & 63;
+  const int r = rem / NBW;
+  const int b = rem - r * NBW;
+  const int by = by0 + b;
+  const bool vb = by <= by_hi;  // then 0 <= bx < Wb
+  const int bx = wave - 2 * by;
+  const int B = job.bit_depth;
+  const int x0 = bx * N, y0 = by * N;
+  const uint32_t blk = (uint32_t)(by * Wb + bx);
+  const uint32_t row_off = (uint32_t)(c * job.Hp + y0 + r) * (uint32_t)job.Wp + (uint32_t)x0;
+  if (t < 2 * NBW) s.sad[t >> 1][t & 1] = 0u;
+
+  if (vb) {
+    const bool aL = bx > 0, aT = by > 0, aTR = aT && bx + 1 < Wb;
+    for (int i = r; i < NR; i += N) s.ref[c][b][i] = (uint16_t)intra_ref<N>(job, c, x0, y0, aL, aT, aTR, i);
+  }
+  __syncthreads();
+
+  // planar's references: [1 2 1] along the scan (ends kept), or at N = 32 the
+  // strong bilinear smoothing when both edges are near-linear (8.4.4.2.3)
+  if constexpr (N >= 8) {
+    if (vb) {
+      const uint16_t* rf = s.ref[c][b];
+      const int corner = rf[2 * N], endL = rf[0], midL = rf[N], endT = rf[4 * N], midT = rf[3 * N];
+      const int thr = 1 << (B - 5);
+      const bool strong = N == 32 && abs(corner + endT - 2 * midT) < thr &&
+                          abs(corner + endL - 2 * midL) < thr;
+      for (int i = r; i < NR; i += N) {
+        int v;
+        if (i == 0 || i == 4 * N) {
+          v = rf[i];
+        } else if (strong) {
+          if (i < 2 * N) {
+            const int yy = 2 * N - 1 - i;
+            v = ((63 - yy) * corner + (yy + 1) * endL + 32) >> 6;
+          } else if (i == 2 * N) {
+            v = corner;
+          } else {
+            const int xx = i - 2 * N - 1;
+            v = ((63 - xx) * corner + (xx + 1) * endT + 32) >> 6;
+          }
+        } else {
+          v = (rf[i - 1] + 2 * rf[i] + rf[i + 1] + 2) >> 2;
+        }
+        s.flt[c][b][i] = (uint16_t)v;
+      }
+    }
+    __syncthreads();
+  }
+
+  // planar (8.4.4.2.5) and DC (8.4.4.2.6, edges filtered below N = 32) at
+  // (x, r) of block b, channel c
+  const uint16_t* rf = s.ref[c][b];
+  const uint16_t* pf = N >= 8 ? s.flt[c][b] : s.ref[c][b];
+  int dc = 0;
+  if (vb) {
+    int sum = N;
+    for (int i = 0; i < N; i++) sum += rf[2 * N + 1 + i] + rf[2 * N - 1 - i];
+    dc = sum >> (L2N + 1);
+  }
+  auto planar = [&](int x) {
+    return ((N - 1 - x) * pf[2 * N - 1 - r] + (x + 1) * pf[3 * N + 1] +
+            (N - 1 - r) * pf[2 * N + 1 + x] + (r + 1) * pf[N - 1] + N) >>
+           (L2N + 1);
+  };
+  auto dcv = [&](int x) {
+    if (N < 32 && r == 0 && x == 0) return (rf[2 * N - 1] + 2 * dc + rf[2 * N + 1] + 2) >> 2;
+    if (N < 32 && r == 0) return (rf[2 * N + 1 + x] + 3 * dc + 2) >> 2;
+    if (N < 32 && x == 0) return (rf[2 * N - 1 - r] + 3 * dc + 2) >> 2;
+    return dc;
+  };
+
+  uint32_t cp[N / 2];
+  int mode = 0;
+  if (!decode) {
+    // mode: the smaller SAD over the real channels, planar on a tie
+    if (vb) {
+      load_row_packed<N>(job.cur, 2u * row_off, cp);
+      if (c < job.nch) {
+        uint32_t s0 = 0, s1 = 0;
+#pragma unroll
+        for (int x = 0; x < N; x++) {
+          const int v = (int)((cp[x >> 1] >> (16 * (x & 1))) & 0xffffu);
+          s0 += (uint32_t)abs(v - planar(x));
+          s1 += (uint32_t)abs(v - dcv(x));
+        }
+        atomicAdd(&s.sad[b][0], s0);
+        atomicAdd(&s.sad[b][1], s1);
+      }
+    }
+    __syncthreads();
+    mode = s.sad[b][1] < s.sad[b][0] ? 1 : 0;
+  } else if (vb) {
+    mode = (gld<uint16_t>(job.mv, 2u * blk) & 0xffu) != 0u ? 1 : 0;
+  }
+
+  uint32_t pp[N / 2];
+  if (vb) {
+#pragma unroll
+    for (int j = 0; j < N / 2; j++) {
+      const int a0 = mode ? dcv(2 * j) : planar(2 * j);
+      const int a1 = mode ? dcv(2 * j + 1) : planar(2 * j + 1);
+      pp[j] = (uint32_t)a0 | ((uint32_t)a1 << 16);
+    }
+  }
+
+  const int qP = job.qp + 6 * (B - 8);
+  const Dequant dqp = dequant_params(qP, B + L2N - 5);
+  const int k = r;  // column stages: block column k
+  if (!decode) {
+    // residual, forward rows (as the transform kernel)
+    if (vb) {
+      uint32_t er[N / 2];
+#pragma unroll
+      for (int m = 0; m < N / 2; m++) er[m] = psub(cp[m], pp[m]);
+      const int s1 = L2N + B - 9;
+      int acc[N];
+      fwd_part<N, 1>(er, acc, 1 << (s1 - 1));
+#pragma unroll
+      for (int kk = 0; kk < N; kk++) s.TD[c][b][kk][r] = (int16_t)(acc[kk] >> s1);
+    }
+    __syncthreads();
+    // forward column, intra dead-zone quantisation, dequantisation, inverse
+    // column; the levels themselves are written by the transform kernel's
+    // pass over the step
+    if (vb) {
+      const int qbits = 29 + qP / 6 - B - L2N;
+      const int off = 171 << (qbits - 9);
+      const int offn = (1 << qbits) - 1 - off;
+      const int qf = kQf[qP % 6];
+      ivec<N> acc;
+      fwd_column<N>((const uint32_t*)s.TD[c][b][k], acc, 1 << (L2N + 5));
+      int lv[N];
+#pragma unroll
+      for (int l = 0; l < N; l++) {
+        const int C = acc[l] >> (L2N + 6);
+        const int v = (__mul24(C, qf) + (C >= 0 ? off : offn)) >> qbits;
+        lv[l] = min(max(v, -32767), 32767);
+      }
+      uint32_t dq[N / 2];
+      dequant_pairs<N>(lv, dqp, dq);
+      inverse_column<N>(dq, s.E[c][b], inv_slot<N>(k));
+    }
+  } else if (vb) {
+    uint32_t lp[N / 2];
+    load_row_packed<N>(job.lev, 2u * (((uint32_t)c * Hb * Wb + blk) * (N * N) + k * N), lp);
+    int lv[N];
+#pragma unroll
+    for (int m = 0; m < N / 2; m++) {
+      lv[2 * m] = (int)(int16_t)(lp[m] & 0xffffu);
+      lv[2 * m + 1] = (int)(int16_t)(lp[m] >> 16);
+    }
+    uint32_t dq[N / 2];
+    dequant_pairs<N>(lv, dqp, dq);
+    inverse_column<N>(dq, s.E[c][b], inv_slot<N>(k));
+  }
+  __syncthreads();
+
+  // inverse rows and reconstruction; encode also keeps the prediction and
+  // the mode
+  if (vb) {
+    uint32_t rp[N / 2];
+    inverse_row<N>(s.E[c][b][r], pp, B, rp);
+    store_row_packed<N>(job.rec, 2u * row_off, rp);
+    if (!decode) {
+      store_row_packed<N>(job.pred, 2u * row_off, pp);
+      if (c == 0 && r == 0) gst<uint16_t>(job.mv, 2u * blk, (uint16_t)mode);
+    }
+  }
+}
+
+template <int N>
+hipError_t launch_intra_t(const LaunchDesc& d, int wave, int decode, hipStream_t s) {
+  intra_kernel<N><<<d.tiles, 192, 0, s>>>(d, wave, decode);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t launch_encode_t(const LaunchDesc& d, hipStream_t s) {
   encode_kernel<N><<<d.tiles, 192, 0, s>>>(d);
@@ -825,6 +1073,24 @@ hipError_t launch_encode(int N, const LaunchDesc& r, hipStream_t s) {
     case 8: return launch_encode_t<8>(r, s);
     case 16: return launch_encode_t<16>(r, s);
     case 32: return launch_encode_t<32>(r, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int intra_tiles_per_job(int N, int Hb, int Wb) {
+  // a wavefront holds at most min(Hb, ceil(Wb / 2)) blocks
+  const int nbw = 64 / N;
+  const int most = std::min(Hb, (Wb + 1) / 2);
+  return (most + nbw - 1) / nbw;
+}
+
+hipError_t launch_intra(int N, const LaunchDesc& r, int wave, int decode, hipStream_t s) {
+  if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
+  switch (N) {
+    case 4: return launch_intra_t<4>(r, wave, decode, s);
+    case 8: return launch_intra_t<8>(r, wave, decode, s);
+    case 16: return launch_intra_t<16>(r, wave, decode, s);
+    case 32: return launch_intra_t<32>(r, wave, decode, s);
     default: return hipErrorInvalidValue;
   }
 }

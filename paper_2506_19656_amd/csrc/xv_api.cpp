@@ -45,7 +45,8 @@ int check_params(const xv_params* p) {
   if (p->gop < 1) return fail(XV_EINVAL, "gop must be >= 1");
   if (p->pad_mode != XV_PAD_ZERO && p->pad_mode != XV_PAD_REPEAT) return fail(XV_EINVAL, "bad pad_mode");
   if (p->fill_mode != XV_FILL_NEAREST && p->fill_mode != XV_FILL_FORWARD) return fail(XV_EINVAL, "bad fill_mode");
-  if (p->flags & ~(XV_FLAG_DROP_WORK | XV_FLAG_QPEL)) return fail(XV_EINVAL, "unknown flags");
+  if (p->flags & ~(XV_FLAG_DROP_WORK | XV_FLAG_QPEL | XV_FLAG_INTRA))
+    return fail(XV_EINVAL, "unknown flags");
   if ((p->flags & XV_FLAG_QPEL) && p->search_range > 31)
     return fail(XV_EINVAL, "quarter-sample motion needs search_range <= 31 (int8 vectors)");
   return XV_OK;
@@ -93,7 +94,8 @@ EncLayout enc_layout(const xv_encoded* e) {
   L.o_rc = w.take<uint16_t>((size_t)nframes * 3 * plane);
   L.o_vm = e->src_dtype == XV_F32 ? w.take<uint8_t>((size_t)nframes * 3 * plane) : 0;
   L.o_part = w.take<uint64_t>((size_t)nframes * xf_tiles_per_job(e->N, e->Hb, e->Wb) * 5);
-  L.o_pred = (e->p.flags & XV_FLAG_QPEL) ? w.take<uint8_t>(pred_plane_bytes(e)) : 0;
+  L.o_pred = (e->p.flags & (XV_FLAG_QPEL | XV_FLAG_INTRA)) ? w.take<uint8_t>(pred_plane_bytes(e))
+                                                           : 0;
   L.work = w.off;
   return L;
 }
@@ -170,7 +172,7 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   e->recon = (uint16_t*)(wb + o_rc);
   e->vmask = in->dtype == XV_F32 ? (uint8_t*)(wb + o_vm) : nullptr;
   e->tile_part = (unsigned long long*)(wb + o_part);
-  e->pred = (p->flags & XV_FLAG_QPEL) ? (uint16_t*)(wb + lay.o_pred) : nullptr;
+  e->pred = (p->flags & (XV_FLAG_QPEL | XV_FLAG_INTRA)) ? (uint16_t*)(wb + lay.o_pred) : nullptr;
   e->tpf = xf_tiles_per_job(e->N, e->Hb, e->Wb);
   *out = e;
 
@@ -194,7 +196,8 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
     CubePlan pl{e->frames, e->recon, e->levels, e->mvs, e->cbits, e->mbits, e->vmask,
                 e->nan_total, e->tile_part, e->pred, e->jobs, (int32_t)T, e->G, p->gop, e->nsteps,
                 e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)bands, e->N,
-                p->bit_depth, p->qp, e->tpf};
+                p->bit_depth, p->qp, e->tpf, (p->flags & XV_FLAG_QPEL) != 0,
+                (p->flags & XV_FLAG_INTRA) != 0};
     XV_HIP(launch_plan(pl, s), "plan kernel");
   }
   return XV_OK;
@@ -242,6 +245,10 @@ int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s) {
       if (rc != XV_OK) return rc;
       uint64_t nl = 0;
       if ((rc = launch_subpel_step(src, s, &nl)) != XV_OK) return rc;
+    } else {
+      uint64_t nl = 0;
+      int rc = launch_intra_step(src, s, &nl);
+      if (rc != XV_OK) return rc;
     }
     int rc = launch_segments(src, 0, geom, [&](const LaunchDesc& d, double work) {
       ProfScope ps(XV_K_ENCODE, s, work);
@@ -295,7 +302,7 @@ int decode_prepare(const xv_encoded* e, hipStream_t s, DecodeBuf& db) {
   CubePlan pl{nullptr, db.recon, e->levels, e->mvs, nullptr, nullptr, nullptr, nullptr,
               nullptr, db.pred, db.jobs, (int32_t)e->T, e->G, e->p.gop, e->nsteps,
               e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)e->bands, e->N,
-              e->p.bit_depth, e->p.qp, 0};
+              e->p.bit_depth, e->p.qp, 0, qpel, (e->p.flags & XV_FLAG_INTRA) != 0};
   XV_HIP(launch_plan(pl, s), "plan kernel");
   return XV_OK;
 }
@@ -314,6 +321,7 @@ int decode_launch(const std::vector<DecSrc>& src, hipStream_t s) {
     for (; i < src.size() && d.nseg < kMaxSeg; i++) {
       const xv_encoded* e = src[i].e;
       const int st = src[i].step;
+      if (st == 0 && (e->p.flags & XV_FLAG_INTRA)) continue;  // wavefront kernel's
       const int n = plan_jobs_at((int)e->T, e->G, e->p.gop, st);
       const int tpj = xf_tiles_per_job(e->N, e->Hb, e->Wb);
       Seg& g = d.seg[d.nseg++];
@@ -325,6 +333,7 @@ int decode_launch(const std::vector<DecSrc>& src, hipStream_t s) {
       // level + pred in, recon out: 6 B per sample (an I step has no pred read)
       work += (double)n * 3.0 * e->Hp * e->Wp * (st == 0 ? 4.0 : 6.0);
     }
+    if (d.nseg == 0) continue;
     d.tiles = tiles;
     ProfScope ps(XV_K_DECODE, s, work);
     XV_HIP(launch_decode(N, d, s), "decode kernel");
@@ -343,6 +352,7 @@ int decode_steps(std::vector<DecSrc> base, hipStream_t s) {
     uint64_t nl = 0;
     int rc = launch_mc_step(src, s, &nl);
     if (rc != XV_OK) return rc;
+    if ((rc = launch_intra_decode_step(src, s, &nl)) != XV_OK) return rc;
     rc = decode_launch(src, s);
     if (rc != XV_OK) return rc;
   }
@@ -414,6 +424,67 @@ int launch_mc_step(const std::vector<DecSrc>& src, hipStream_t s, uint64_t* laun
         return XV_OK;
       },
       launches);
+}
+
+namespace {
+
+// One launch per wavefront for each chunk of up to kMaxSeg intra sources
+// at step 0 (one class: one N).  work per launch: the algorithmic bytes of
+// the wavefront's blocks (encode: current, reconstruction and prediction,
+// 6 B per sample; decode: level and reconstruction, 4 B).
+template <class Src, class JobsOf>
+int launch_intra_waves(const std::vector<Src>& src, JobsOf jobs_of, int decode, hipStream_t s,
+                       uint64_t* launches) {
+  size_t i = 0;
+  while (i < src.size()) {
+    LaunchDesc d;
+    memset(&d, 0, sizeof d);
+    int tiles = 0, N = 0, waves = 0;
+    std::vector<std::pair<const xv_encoded*, int>> chunk;
+    for (; i < src.size() && d.nseg < kMaxSeg; i++) {
+      const xv_encoded* e = src[i].e;
+      if (src[i].step != 0 || !(e->p.flags & XV_FLAG_INTRA)) continue;
+      N = e->N;
+      const int n = plan_jobs_at((int)e->T, e->G, e->p.gop, 0);
+      const int tpj = intra_tiles_per_job(e->N, e->Hb, e->Wb);
+      Seg& g = d.seg[d.nseg++];
+      g.jobs = jobs_of(src[i]);
+      g.count = n;
+      g.tpj = tpj;
+      g.tile0 = tiles;
+      tiles += n * tpj;
+      waves = std::max(waves, intra_waves(e->Hb, e->Wb));
+      chunk.push_back({e, n});
+    }
+    if (d.nseg == 0) continue;
+    d.tiles = tiles;
+    for (int w = 0; w < waves; w++) {
+      double work = 0;
+      for (auto& ce : chunk) {
+        const int Hb = ce.first->Hb, Wb = ce.first->Wb;
+        const int lo = w - (Wb - 1) > 0 ? (w - (Wb - 1) + 1) / 2 : 0;
+        const int hi = std::min(Hb - 1, w / 2);
+        if (hi >= lo)
+          work += (double)ce.second * (hi - lo + 1) * 3.0 * N * N * (decode ? 4.0 : 6.0);
+      }
+      ProfScope ps(XV_K_INTRA, s, work);
+      XV_HIP(launch_intra(N, d, w, decode, s), "intra wavefront kernel");
+      ++*launches;
+    }
+  }
+  return XV_OK;
+}
+
+}  // namespace
+
+int launch_intra_step(const std::vector<SegSrc>& src, hipStream_t s, uint64_t* launches) {
+  return launch_intra_waves(
+      src, [](const SegSrc& x) { return x.e->jobs; }, 0, s, launches);
+}
+
+int launch_intra_decode_step(const std::vector<DecSrc>& src, hipStream_t s, uint64_t* launches) {
+  return launch_intra_waves(
+      src, [](const DecSrc& x) { return x.jobs; }, 1, s, launches);
 }
 
 int decode_finish(const xv_encoded* e, const xv_cube* out, DecodeBuf& db, hipStream_t s) {

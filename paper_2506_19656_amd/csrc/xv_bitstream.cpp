@@ -28,6 +28,7 @@ BitsArgs bits_args_of(const xv_encoded* e) {
   a.Wb = e->Wb;
   a.T = (int32_t)e->T;
   a.gop = e->p.gop;
+  a.imodes = (e->p.flags & XV_FLAG_INTRA) != 0;
   a.nunits = (int64_t)e->G * e->T * 4 * e->Hb * e->Wb;
   return a;
 }

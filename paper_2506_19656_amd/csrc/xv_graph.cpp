@@ -10,7 +10,7 @@
 // graph, whose kernels then reach this call's frames, levels and
 // reconstructions through them.  The key is everything the launches depend
 // on: per cube the frame count, group count, GOP, padded size, block size,
-// search range and quarter-sample flag; the motion-search geometry of the
+// search range and the quarter-sample and intra flags; the motion-search geometry of the
 // class; and the stream.  Graphs hold kernel nodes only (no memset or copy
 // nodes).  Capture runs on a stream of the library's own, so the caller's
 // stream may be the null stream; nothing captured executes during capture.
@@ -70,7 +70,8 @@ std::vector<int64_t> dims_key(const std::vector<const xv_encoded*>& es) {
   std::vector<int64_t> d;
   for (const xv_encoded* e : es) {
     const int64_t v[] = {e->T, e->G, e->p.gop, e->Hp, e->Wp, e->N, e->p.search_range,
-                         (int64_t)(e->p.flags & XV_FLAG_QPEL), e->nsteps, e->njobs};
+                         (int64_t)(e->p.flags & (XV_FLAG_QPEL | XV_FLAG_INTRA)), e->nsteps,
+                         e->njobs};
     d.insert(d.end(), v, v + 10);
   }
   return d;

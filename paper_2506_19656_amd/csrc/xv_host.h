@@ -27,7 +27,7 @@ struct xv_encoded {
   uint16_t* frames;
   uint16_t* recon;
   uint8_t* vmask;
-  uint16_t* pred;  // prediction planes, one per stream (XV_FLAG_QPEL), in work
+  uint16_t* pred;  // prediction planes, one per stream (XV_FLAG_QPEL or XV_FLAG_INTRA), in work
   int16_t* levels;
   int8_t* mvs;
   uint32_t* cbits;
@@ -146,8 +146,10 @@ int launch_segments(const std::vector<SegSrc>& src, int tpj_kind, const MeGeom& 
       g.tile0 = tiles;
       tiles += n * tpj;
       // transform: algorithmic bytes (cur + pred in, level + recon out, 8 B per
-      // sample; an I step has a constant prediction, 6 B); search: SAD terms
-      work += tpj_kind == 0 ? xf_frames(e, s) * 3.0 * e->Hp * e->Wp * (s == 0 ? 6.0 : 8.0)
+      // sample; an I step without intra modes has a constant prediction, 6 B);
+      // search: SAD terms
+      const bool const_pred = s == 0 && !(e->p.flags & XV_FLAG_INTRA);
+      work += tpj_kind == 0 ? xf_frames(e, s) * 3.0 * e->Hp * e->Wp * (const_pred ? 6.0 : 8.0)
                             : me_work(e, s);
     }
     d.tiles = tiles;
@@ -182,6 +184,12 @@ int decode_launch(const std::vector<DecSrc>& src, hipStream_t s);
 // sources coded with XV_FLAG_QPEL (step > 0); *launches counts launches.
 int launch_subpel_step(const std::vector<SegSrc>& src, hipStream_t s, uint64_t* launches);
 int launch_mc_step(const std::vector<DecSrc>& src, hipStream_t s, uint64_t* launches);
+// Intra-predicted I steps (XV_FLAG_INTRA), one launch per wavefront, over
+// the sources at step 0 that carry the flag: encode (mode choice, coding,
+// reconstruction and prediction plane; the transform launch of the step
+// follows) and decode (reconstruction; decode_launch skips these steps).
+int launch_intra_step(const std::vector<SegSrc>& src, hipStream_t s, uint64_t* launches);
+int launch_intra_decode_step(const std::vector<DecSrc>& src, hipStream_t s, uint64_t* launches);
 // Bytes of the prediction planes: one [3][Hp][Wp] plane per stream.
 size_t pred_plane_bytes(const xv_encoded* e);
 int decode_steps(std::vector<DecSrc> base, hipStream_t s);

@@ -31,12 +31,16 @@ struct FrameJob {
   const uint32_t* nan_total;   // device flag: non-zero -> vmask is meaningful
   unsigned long long* part;    // [tiles of the frame][5] per-tile sums: squared error of
                                // channels 0..2, coefficient bits, vector bits
-  uint16_t* pred;              // [3][Hp][Wp] motion-compensated prediction of a P step
-                               // with quarter-sample vectors (read at displacement
-                               // zero), or null: the prediction is ref displaced
+  uint16_t* pred;              // [3][Hp][Wp] prediction plane read at displacement
+                               // zero: the motion-compensated prediction of a P step
+                               // with quarter-sample vectors, or the intra prediction
+                               // of an I step with intra modes; null: the prediction
+                               // is ref displaced (P) or 2^(B-1) (I)
   int32_t Hp, Wp, H, W;
   int32_t nch;                 // channels carrying a real band (1..3)
-  int32_t intra;
+  int32_t intra;               // I picture
+  int32_t imode;               // I picture whose blocks are intra-predicted; the mode
+                               // is the first byte of the block's vector entry
   int32_t bit_depth, qp;
 };
 
@@ -76,11 +80,14 @@ struct CubePlan {
   const uint8_t* vmask;
   const uint32_t* nan_total;
   unsigned long long* part;    // [G][T][tpf][5] per-tile sums (null for decode)
-  uint16_t* pred;              // [G][GOPs][3][Hp][Wp] prediction planes, one per stream
-                               // (quarter-sample vectors only), else null
+  uint16_t* pred;              // [G][GOPs][3][Hp][Wp] prediction planes, one per stream,
+                               // or null
   FrameJob* jobs;              // [sum over steps of jobs]
   int32_t T, G, gop, nsteps, Hp, Wp, H, W, bands, N, bit_depth, qp;
   int32_t tpf;                 // transform tiles per frame
+  int32_t qpel;                // P steps read their prediction from pred
+  int32_t imode;               // I blocks intra-predicted; with pred, the I step's
+                               // prediction goes to pred too (encode)
 };
 
 // Per-group totals of the per-tile sums, in a fixed order: sse [3G] and
@@ -249,6 +256,16 @@ hipError_t launch_encode(int N, const LaunchDesc& d, hipStream_t s);
 hipError_t launch_subpel(int N, const LaunchDesc& d, hipStream_t s);
 hipError_t launch_mc(int N, const LaunchDesc& d, hipStream_t s);
 hipError_t launch_decode(int N, const LaunchDesc& d, hipStream_t s);
+// Intra-predicted I steps (k_xform.hip): blocks in raster order depend on
+// their left, top-left, top and top-right neighbours, so block (bx, by) runs
+// in wavefront w = bx + 2 by, one launch per wavefront over every job of d.
+// Encode chooses the mode, codes the block and writes its reconstruction,
+// its prediction (job pred plane) and its mode (job mv); the transform
+// kernel then recodes the step from the prediction plane for levels, bit
+// counts and sums.  Decode reconstructs from the stored levels and modes.
+int intra_tiles_per_job(int N, int Hb, int Wb);
+inline int intra_waves(int Hb, int Wb) { return Wb + 2 * Hb - 2; }
+hipError_t launch_intra(int N, const LaunchDesc& d, int wave, int decode, hipStream_t s);
 hipError_t launch_plan(const CubePlan& p, hipStream_t s);
 
 struct DenormArgs {
@@ -285,6 +302,7 @@ hipError_t launch_phys_sse(const PhysArgs& a, hipStream_t s);
 // ---------------------------------------------------------------------------
 struct BitsArgs {
   int32_t N, Hb, Wb, T, gop;
+  int32_t imodes;              // I blocks carry their intra mode as one bit
   int64_t nunits;              // G * T * 4 * Hb * Wb
   const uint32_t* cbits;       // [G][T][3][Hb][Wb] unit lengths (pack)
   const uint32_t* mbits;       // [G][T][Hb][Wb]

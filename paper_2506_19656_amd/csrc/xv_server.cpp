@@ -160,6 +160,7 @@ int iterate(xv_server* sv, const std::vector<SReq*>& run, uint64_t* launches) {
       if (rc != XV_OK) return rc;
       if ((rc = launch_subpel_step(p, sv->s, launches)) != XV_OK) return rc;
     }
+    if (int rc = launch_intra_step(kv.second, sv->s, launches); rc != XV_OK) return rc;
     int rc = launch_segments(kv.second, 0, geom, [&](const LaunchDesc& d, double work) {
       ProfScope ps(XV_K_ENCODE, sv->s, work);
       XV_HIP(launch_encode(N, d, sv->s), "transform kernel");
@@ -171,6 +172,7 @@ int iterate(xv_server* sv, const std::vector<SReq*>& run, uint64_t* launches) {
   for (auto& kv : dec_cls) {
     int rc = launch_mc_step(kv.second, sv->s, launches);
     if (rc != XV_OK) return rc;
+    if ((rc = launch_intra_decode_step(kv.second, sv->s, launches)) != XV_OK) return rc;
     rc = decode_launch(kv.second, sv->s);
     if (rc != XV_OK) return rc;
     ++*launches;

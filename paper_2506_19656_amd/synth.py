@@ -80,6 +80,9 @@ WORKLOADS = {
     "planet": Workload("planet", 730, 1024, 1024, 4, "u16", 10, (22, 32), (16,), 32),
     # 744 x 721x1440 x 3 f32 reanalysis-like, 12-bit, N=32, R=8
     "era5": Workload("era5", 744, 721, 1440, 3, "f32", 12, (17, 27), (32,), 8),
+    # 128 x 256x256 x 3 u16 texture drifting by fractions of a sample per
+    # frame, 10-bit, N=16, R=16 (the content sub-sample motion is for)
+    "drift": Workload("drift", 128, 256, 256, 3, "u16", 10, (22, 27, 32, 37), (16,), 16),
 }
 
 
@@ -219,6 +222,33 @@ def era5_cube(seed: int = 3, T: int = 744, H: int = 721, W: int = 1440, bands: i
     return out
 
 
+def drift_cube(seed: int = 5, T: int = 128, H: int = 256, W: int = 256, bands: int = 3,
+               velocity=(0.37, -0.23), device="cpu") -> torch.Tensor:
+    """uint16 cube [T, H, W, bands] of a periodic 1/f^3 texture per band
+    translated by t * velocity samples (x, y) in frame t -- an exact
+    sub-sample shift, applied as a phase ramp on the texture's spectrum --
+    scaled to a peak excursion of 4800 about 5000, plus white noise (sigma
+    8), clipped to [0, 10000] and rounded: the motion of a registration
+    drift or an advected field, which integer vectors only approximate."""
+    gen = _gen(seed, device)
+    fy = torch.fft.fftfreq(H, device=device).view(H, 1)
+    fx = torch.fft.rfftfreq(W, device=device).view(1, W // 2 + 1)
+    f = torch.sqrt(fx * fx + fy * fy)
+    amp = torch.where(f > 0, f.clamp_min(1e-12) ** -1.5, torch.zeros_like(f))
+    spec = torch.complex(torch.randn((bands, H, W // 2 + 1), generator=gen, device=device),
+                         torch.randn((bands, H, W // 2 + 1), generator=gen, device=device)) * amp
+    base = torch.fft.irfft2(spec, s=(H, W))
+    scale = 4800.0 / base.abs().amax(dim=(1, 2), keepdim=True).clamp_min(1e-12)
+    vx, vy = velocity
+    out = torch.empty((T, H, W, bands), dtype=torch.uint16, device=device)
+    for t in range(T):
+        ph = torch.exp(torch.complex(torch.zeros_like(f), -2 * math.pi * (fx * vx * t + fy * vy * t)))
+        frame = torch.fft.irfft2(spec * ph, s=(H, W)) * scale + 5000.0
+        frame = frame + 8.0 * torch.randn((bands, H, W), generator=gen, device=device)
+        out[t] = _to_u16(frame.clamp(0, 10000)).permute(1, 2, 0)
+    return out
+
+
 def make_cube(name: str, device="cpu", **kw) -> torch.Tensor:
     if name == "tiny":
         return tiny_cube(device=device, **kw)
@@ -228,6 +258,8 @@ def make_cube(name: str, device="cpu", **kw) -> torch.Tensor:
         return planet_cube(device=device, **kw)
     if name == "era5":
         return era5_cube(device=device, **kw)
+    if name == "drift":
+        return drift_cube(device=device, **kw)
     raise KeyError(name)
 
 

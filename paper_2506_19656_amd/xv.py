@@ -23,12 +23,13 @@ PAD_ZERO, PAD_REPEAT = 0, 1
 FILL_NEAREST, FILL_FORWARD = 0, 1
 FLAG_DROP_WORK = 1
 FLAG_QPEL = 2
+FLAG_INTRA = 4
 ME_COLUMN_PAIRS, ME_ROW_PAIRS, ME_ROW_PAIRS_BY_CHANNEL = 1, 2, 3
 MAX_BANDS, MAX_GROUPS = 64, 22
 K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS, K_BITS_WRITE, K_BITS_PARSE, \
-    K_QUALITY, K_SUBPEL, K_PCA = range(12)
+    K_QUALITY, K_SUBPEL, K_PCA, K_INTRA = range(13)
 K_NAMES = ["stats", "pack", "me", "encode", "decode", "denorm", "metrics", "bits_write",
-           "bits_parse", "quality", "subpel", "pca"]
+           "bits_parse", "quality", "subpel", "pca", "intra"]
 
 
 class XvError(RuntimeError):
@@ -74,7 +75,7 @@ class MeGeometryC(C.Structure):
 
 
 class ProfileC(C.Structure):
-    _fields_ = [("ms", C.c_double * 12), ("launches", C.c_uint64 * 12), ("work", C.c_double * 12)]
+    _fields_ = [("ms", C.c_double * 13), ("launches", C.c_uint64 * 13), ("work", C.c_double * 13)]
 
 
 class MemoryC(C.Structure):

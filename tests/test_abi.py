@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(xvmod):
 
 def test_abi_version_and_status_strings(xvmod):
     L = xvmod.lib()
-    assert L.xv_abi_version() == 6
+    assert L.xv_abi_version() == 7
     assert L.xv_status_str(0) == b"ok"
     assert L.xv_status_str(-1) == b"invalid argument"
 

@@ -21,7 +21,8 @@ INT_KEYS = ("frames", "levels", "mvs", "recon", "coef_bits", "mv_bits")
 def _oparams(p: xv.Params) -> O.CodingParams:
     return O.CodingParams(bit_depth=p.bit_depth, qp=p.qp, block=p.block,
                           search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
-                          fill_mode=p.fill_mode, qpel=1 if p.flags & xv.FLAG_QPEL else 0)
+                          fill_mode=p.fill_mode, qpel=1 if p.flags & xv.FLAG_QPEL else 0,
+                          intra=1 if p.flags & xv.FLAG_INTRA else 0)
 
 
 def _to_dev(a: np.ndarray) -> torch.Tensor:
