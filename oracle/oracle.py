@@ -39,7 +39,7 @@ class Params(C.Structure):
     _fields_ = [("bit_depth", C.c_int32), ("qp", C.c_int32), ("block", C.c_int32),
                 ("search_range", C.c_int32), ("gop", C.c_int32),
                 ("pad_mode", C.c_int32), ("fill_mode", C.c_int32), ("qpel", C.c_int32),
-                ("intra", C.c_int32)]
+                ("intra", C.c_int32), ("split", C.c_int32)]
 
 
 @dataclass
@@ -53,10 +53,12 @@ class CodingParams:
     fill_mode: int = FILL_NEAREST
     qpel: int = 0
     intra: int = 0
+    split: int = 0
 
     def c(self) -> Params:
         return Params(self.bit_depth, self.qp, self.block, self.search_range,
-                      self.gop, self.pad_mode, self.fill_mode, self.qpel, self.intra)
+                      self.gop, self.pad_mode, self.fill_mode, self.qpel, self.intra,
+                      self.split)
 
 
 _lib = None
@@ -115,13 +117,16 @@ def lib():
         L.xvo_pca_eigen.argtypes = [p, i64, p, p]
         L.xvo_pca_project.argtypes = [p, i64, i64, p, p, i64, i64, p]
         L.xvo_pca_inverse.argtypes = [p, i64, i64, i64, p, p, C.c_int, p]
+        L.xvo_split_lambda.argtypes = [C.c_int, C.c_int]
+        L.xvo_split_lambda.restype = C.c_int32
+        L.xvo_split_choose.argtypes = [C.c_uint32, C.c_int, C.c_int, p, p, p, C.c_int32]
         L.xvo_encode_gop.argtypes = [p, C.c_int, i64, i64, i64, i64, p, p,
                                      C.POINTER(Params), i64, i64, i64,
-                                     p, p, p, p, p, p, p, p]
-        L.xvo_decode_gop.argtypes = [C.POINTER(Params), i64, i64, i64, p, p, p]
+                                     p, p, p, p, p, p, p, p, p]
+        L.xvo_decode_gop.argtypes = [C.POINTER(Params), i64, i64, i64, p, p, p, p]
         L.xvo_encode_cube.argtypes = [p, C.c_int, i64, i64, i64, i64, C.POINTER(Params),
-                                      p, p, p, p, p, p, p, p, p, p]
-        L.xvo_decode_cube.argtypes = [C.POINTER(Params), i64, i64, i64, i64, p, p, p]
+                                      p, p, p, p, p, p, p, p, p, p, p]
+        L.xvo_decode_cube.argtypes = [C.POINTER(Params), i64, i64, i64, i64, p, p, p, p]
         L.xvo_denormalize_cube.argtypes = [p, i64, i64, i64, i64, C.c_int, C.c_int,
                                            p, p, C.c_int, p]
         L.xvo_psnr.argtypes = [C.c_double, C.c_double, C.c_double]
@@ -132,11 +137,12 @@ def lib():
         L.xvo_bpppb.restype = C.c_double
         L.xvo_phys_sse.argtypes = [p, C.c_int, i64, i64, i64, i64, p, C.c_int, C.c_int,
                                    p, p, p]
-        L.xvo_bitstream_bits.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, C.c_int, p, p]
+        L.xvo_bitstream_bits.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, C.c_int, p, p,
+                                         p]
         L.xvo_bitstream_bits.restype = C.c_uint64
         L.xvo_write_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, C.c_int, p, p,
-                                          p, C.c_uint64, p]
-        L.xvo_read_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, C.c_int, p,
+                                          p, p, C.c_uint64, p]
+        L.xvo_read_bitstream.argtypes = [C.c_int, i64, i64, C.c_int, i64, i64, C.c_int, p, p,
                                          C.c_uint64, p, p, p]
         L.xvo_ssim_window.argtypes = [p]
         L.xvo_ssim_plane.argtypes = [p, p, i64, i64, i64, C.c_int]
@@ -388,16 +394,32 @@ def pca_inverse(pcs: np.ndarray, mean, basis, out_dtype: int) -> np.ndarray:
 
 # -- whole-GOP and whole-cube drivers ----------------------------------------
 
-def _gop_arrays(len_, Hp, Wp, N):
+def _gop_arrays(len_, Hp, Wp, N, split=0):
     Hb, Wb = Hp // N, Wp // N
+    m = 2 if split else 1  # vectors on the N/2 grid with the adaptive block size
     return dict(
         frames=np.zeros((len_, 3, Hp, Wp), np.uint16),
         levels=np.zeros((len_, 3, Hb, Wb, N, N), np.int16),
-        mvs=np.zeros((len_, Hb, Wb, 2), np.int8),
+        mvs=np.zeros((len_, m * Hb, m * Wb, 2), np.int8),
         recon=np.zeros((len_, 3, Hp, Wp), np.uint16),
         coef_bits=np.zeros((len_, 3, Hb, Wb), np.uint32),
         mv_bits=np.zeros((len_, Hb, Wb), np.uint32),
+        splits=np.zeros((len_, Hb, Wb), np.uint8),
     )
+
+
+def split_choose(sad_whole: int, v, sads, cells, lam16: int) -> int:
+    """xvo_split_choose: 1 when the four cells cost less than the whole block."""
+    sa = np.array(sads, np.uint32)
+    ux = np.array([c[0] for c in cells], np.int32)
+    uy = np.array([c[1] for c in cells], np.int32)
+    return int(lib().xvo_split_choose(sad_whole, v[0], v[1], _ptr(sa), _ptr(ux), _ptr(uy),
+                                      lam16))
+
+
+def split_lambda(qp: int, B: int) -> int:
+    """xvo_split_lambda: the whole/split cost multiplier in 1/16 SAD units."""
+    return int(lib().xvo_split_lambda(qp, B))
 
 
 def encode_gop(cube, mn, mx, params: CodingParams, g: int, t0: int, len_: int):
@@ -405,28 +427,29 @@ def encode_gop(cube, mn, mx, params: CodingParams, g: int, t0: int, len_: int):
     T, H, W, Bn = cube.shape
     N = params.block
     Hp, Wp = padded(H, N), padded(W, N)
-    o = _gop_arrays(len_, Hp, Wp, N)
+    o = _gop_arrays(len_, Hp, Wp, N, params.split)
     sse = np.zeros(3, np.uint64)
     nv = np.zeros(3, np.uint64)
     pc = params.c()
     rc = lib().xvo_encode_gop(_ptr(cube), _dtype_code(cube), T, H, W, Bn, _ptr(mn), _ptr(mx),
                               C.byref(pc), g, t0, len_, _ptr(o["frames"]), _ptr(o["levels"]),
                               _ptr(o["mvs"]), _ptr(o["recon"]), _ptr(o["coef_bits"]),
-                              _ptr(o["mv_bits"]), _ptr(sse), _ptr(nv))
+                              _ptr(o["mv_bits"]), _ptr(o["splits"]), _ptr(sse), _ptr(nv))
     if rc != 0:
         raise ValueError(f"xvo_encode_gop failed ({rc})")
     o["sse"], o["nvalid"] = sse, nv
     return o
 
 
-def decode_gop(params: CodingParams, H: int, W: int, levels, mvs):
+def decode_gop(params: CodingParams, H: int, W: int, levels, mvs, splits=None):
     N = params.block
     len_ = levels.shape[0]
     Hp, Wp = padded(H, N), padded(W, N)
     rec = np.zeros((len_, 3, Hp, Wp), np.uint16)
     pc = params.c()
+    sp = _ptr(np.ascontiguousarray(splits, np.uint8)) if splits is not None else None
     rc = lib().xvo_decode_gop(C.byref(pc), H, W, len_, _ptr(np.ascontiguousarray(levels)),
-                              _ptr(np.ascontiguousarray(mvs)), _ptr(rec))
+                              _ptr(np.ascontiguousarray(mvs)), sp, _ptr(rec))
     if rc != 0:
         raise ValueError(f"xvo_decode_gop failed ({rc})")
     return rec
@@ -439,13 +462,15 @@ def encode_cube(cube: np.ndarray, params: CodingParams) -> dict:
     G = (Bn + 2) // 3
     Hp, Wp = padded(H, N), padded(W, N)
     Hb, Wb = Hp // N, Wp // N
+    m = 2 if params.split else 1  # vectors on the N/2 grid with the adaptive block size
     o = dict(
         frames=np.zeros((G, T, 3, Hp, Wp), np.uint16),
         levels=np.zeros((G, T, 3, Hb, Wb, N, N), np.int16),
-        mvs=np.zeros((G, T, Hb, Wb, 2), np.int8),
+        mvs=np.zeros((G, T, m * Hb, m * Wb, 2), np.int8),
         recon=np.zeros((G, T, 3, Hp, Wp), np.uint16),
         coef_bits=np.zeros((G, T, 3, Hb, Wb), np.uint32),
         mv_bits=np.zeros((G, T, Hb, Wb), np.uint32),
+        splits=np.zeros((G, T, Hb, Wb), np.uint8),
     )
     mn = np.zeros(Bn, np.float64)
     mx = np.zeros(Bn, np.float64)
@@ -456,57 +481,75 @@ def encode_cube(cube: np.ndarray, params: CodingParams) -> dict:
     rc = lib().xvo_encode_cube(_ptr(cube), _dtype_code(cube), T, H, W, Bn, C.byref(pc),
                                _ptr(mn), _ptr(mx), _ptr(o["frames"]), _ptr(o["levels"]),
                                _ptr(o["mvs"]), _ptr(o["recon"]), _ptr(o["coef_bits"]),
-                               _ptr(o["mv_bits"]), _ptr(sse), _ptr(nv))
+                               _ptr(o["mv_bits"]), _ptr(o["splits"]), _ptr(sse), _ptr(nv))
     if rc != 0:
         raise ValueError(f"xvo_encode_cube failed ({rc})")
     o.update(mn=mn, mx=mx, sse=sse, nvalid=nv)
     return o
 
 
-def write_bitstream(levels: np.ndarray, mvs: np.ndarray, gop: int, imodes: int = 0) -> dict:
+def write_bitstream(levels: np.ndarray, mvs: np.ndarray, gop: int, imodes: int = 0,
+                    splits=None) -> dict:
     """xvo_write_bitstream: levels [G][T][3][Hb][Wb][N][N] i16 and vectors
     [G][T][Hb][Wb][2] i8 -> payload bytes, its length in bits and the bit
     offset of every segment (4 * Hb per frame).  imodes: I blocks carry
-    their intra mode bit."""
+    their intra mode bit; splits ([G][T][Hb][Wb], adaptive block size: the
+    vectors are then on the N/2 grid)."""
     G, T, _, Hb, Wb, N, _ = levels.shape
     levels = np.ascontiguousarray(levels, np.int16)
     mvs = np.ascontiguousarray(mvs, np.int8)
-    bits = int(lib().xvo_bitstream_bits(N, G, T, gop, Hb, Wb, imodes, _ptr(levels), _ptr(mvs)))
+    sp = None
+    if splits is not None:
+        splits = np.ascontiguousarray(splits, np.uint8)
+        sp = _ptr(splits)
+    bits = int(lib().xvo_bitstream_bits(N, G, T, gop, Hb, Wb, imodes, sp, _ptr(levels),
+                                        _ptr(mvs)))
     nbytes = (bits + 7) // 8
     out = np.zeros(max(1, nbytes), np.uint8)
     index = np.zeros(G * T * 4 * Hb, np.uint64)
-    rc = lib().xvo_write_bitstream(N, G, T, gop, Hb, Wb, imodes, _ptr(levels), _ptr(mvs),
+    rc = lib().xvo_write_bitstream(N, G, T, gop, Hb, Wb, imodes, sp, _ptr(levels), _ptr(mvs),
                                    _ptr(out), out.size, _ptr(index))
     if rc != 0:
         raise ValueError(f"xvo_write_bitstream failed ({rc})")
     return dict(payload=out[:nbytes], bits=bits, index=index)
 
 
-def read_bitstream(payload: np.ndarray, bits: int, shape_lev, gop: int, imodes: int = 0) -> dict:
-    """xvo_read_bitstream: sequential parse back to levels and vectors; also
-    returns the segment offsets met."""
+def read_bitstream(payload: np.ndarray, bits: int, shape_lev, gop: int, imodes: int = 0,
+                   split: int = 0) -> dict:
+    """xvo_read_bitstream: sequential parse back to levels and vectors (and
+    split flags with the adaptive block size); also returns the segment
+    offsets met."""
     G, T, _, Hb, Wb, N, _ = shape_lev
+    m = 2 if split else 1
     levels = np.zeros(shape_lev, np.int16)
-    mvs = np.zeros((G, T, Hb, Wb, 2), np.int8)
+    mvs = np.zeros((G, T, m * Hb, m * Wb, 2), np.int8)
+    splits = np.zeros((G, T, Hb, Wb), np.uint8)
     index = np.zeros(G * T * 4 * Hb, np.uint64)
     buf = np.ascontiguousarray(payload, np.uint8)
     if buf.size == 0:
         buf = np.zeros(1, np.uint8)
-    rc = lib().xvo_read_bitstream(N, G, T, gop, Hb, Wb, imodes, _ptr(buf), bits,
+    rc = lib().xvo_read_bitstream(N, G, T, gop, Hb, Wb, imodes,
+                                  _ptr(splits) if split else None, _ptr(buf), bits,
                                   _ptr(levels), _ptr(mvs), _ptr(index))
     if rc != 0:
         raise ValueError(f"xvo_read_bitstream failed ({rc})")
-    return dict(levels=levels, mvs=mvs, index=index)
+    out = dict(levels=levels, mvs=mvs, index=index)
+    if split:
+        out["splits"] = splits
+    return out
 
 
-def decode_cube(params: CodingParams, shape, levels, mvs) -> np.ndarray:
+def decode_cube(params: CodingParams, shape, levels, mvs, splits=None) -> np.ndarray:
     T, H, W, Bn = shape
     N = params.block
     G = (Bn + 2) // 3
     rec = np.zeros((G, T, 3, padded(H, N), padded(W, N)), np.uint16)
     pc = params.c()
+    if params.split and splits is None:
+        raise ValueError("the adaptive block size needs the split flags")
+    sp = _ptr(np.ascontiguousarray(splits, np.uint8)) if params.split else None
     rc = lib().xvo_decode_cube(C.byref(pc), T, H, W, Bn, _ptr(np.ascontiguousarray(levels)),
-                               _ptr(np.ascontiguousarray(mvs)), _ptr(rec))
+                               _ptr(np.ascontiguousarray(mvs)), sp, _ptr(rec))
     if rc != 0:
         raise ValueError(f"xvo_decode_cube failed ({rc})")
     return rec

@@ -461,54 +461,167 @@ static int32_t get_se(bit_reader* r) {
   return (k & 1) ? (int32_t)((k + 1) / 2) : -(int32_t)(k / 2);
 }
 
-/* With imodes set, an I block carries its intra mode as one bit where a P
- * block carries its vector. */
+/* Stream structure shared by the three functions below.  Per frame: the
+ * vector units of the blocks in raster order, then for channel c = 0, 1, 2
+ * the coefficient units of the blocks in raster order; a row of units is a
+ * segment.  A P block's vector unit holds se(dx - pdx), se(dy - pdy) with
+ * the left block's vector as predictor ((0,0) in column 0).  An I block's
+ * vector unit is empty, or one intra-mode bit with imodes.  With the
+ * adaptive block size (splits non-NULL) a P block's vector unit is its split
+ * flag and then its one or four vectors (the vector and predictor rule of
+ * the split reading), and its coefficient unit holds one N x N or four
+ * N/2 x N/2 block codes in z-order.  A block code: the coded flag, then
+ * ue(nnz - 1) and per nonzero level in up-right diagonal scan order ue(run),
+ * se(level). */
+typedef struct {
+  int N;
+  int64_t G, T, Hb, Wb;
+  int gop, imodes;
+  int32_t order[32 * 32], order_h[16 * 16];
+} stream_shape;
+
+static void shape_init(stream_shape* sh, int N, int64_t G, int64_t T, int gop, int64_t Hb,
+                       int64_t Wb, int imodes) {
+  sh->N = N;
+  sh->G = G;
+  sh->T = T;
+  sh->gop = gop;
+  sh->Hb = Hb;
+  sh->Wb = Wb;
+  sh->imodes = imodes;
+  xvo_scan_order(N, sh->order);
+  if (N >= 8) xvo_scan_order(N / 2, sh->order_h);
+}
+
+/* vectors of frame f: [Hb][Wb][2], or [2 Hb][2 Wb][2] with splits */
+static const int8_t* frame_mvs(const stream_shape* sh, const int8_t* mvs, int64_t f, int split) {
+  return mvs + f * (split ? 4 : 1) * sh->Hb * sh->Wb * 2;
+}
+
+/* Vector-unit codes of block (bx, by) of a P frame with splits: the flag,
+ * then each coded vector against the cell to its left; calls put_se for
+ * each difference (w NULL: only counts).  Returns the unit's length. */
+static uint32_t split_vector_unit(const stream_shape* sh, const int8_t* mvu, int split,
+                                  int64_t bx, int64_t by, bit_writer* w) {
+  int64_t Wu = 2 * sh->Wb;
+  uint32_t bits = 1;
+  if (w) put_bit(w, split);
+  for (int i = 0; i < (split ? 4 : 1); i++) {
+    int64_t xu = 2 * bx + (i & 1), yu = 2 * by + (i >> 1);
+    int pmx = xu > 0 ? mvu[2 * (yu * Wu + xu - 1)] : 0;
+    int pmy = xu > 0 ? mvu[2 * (yu * Wu + xu - 1) + 1] : 0;
+    int mx = mvu[2 * (yu * Wu + xu)], my = mvu[2 * (yu * Wu + xu) + 1];
+    bits += xvo_mv_bits(mx, my, pmx, pmy);
+    if (w) {
+      put_se(w, mx - pmx);
+      put_se(w, my - pmy);
+    }
+  }
+  return bits;
+}
+
+static void put_block(bit_writer* w, int n, const int32_t* order, const int16_t* lev) {
+  int nnz = 0;
+  for (int i = 0; i < n * n; i++) nnz += lev[i] != 0;
+  put_bit(w, nnz > 0);
+  if (nnz == 0) return;
+  put_ue(w, (uint32_t)(nnz - 1));
+  int run = 0;
+  for (int i = 0; i < n * n; i++) {
+    int16_t v = lev[order[i]];
+    if (v == 0) {
+      run++;
+      continue;
+    }
+    put_ue(w, (uint32_t)run);
+    put_se(w, v);
+    run = 0;
+  }
+}
+
+static void get_block(bit_reader* r, int n, const int32_t* order, int16_t* lev) {
+  if (!get_bit(r)) return;
+  int nnz = (int)get_ue(r) + 1;
+  int p = -1;
+  for (int k = 0; k < nnz && !r->overrun; k++) {
+    p += (int)get_ue(r) + 1;
+    int32_t v = get_se(r);
+    if (p >= n * n) {
+      r->overrun = 1;
+      break;
+    }
+    lev[order[p]] = (int16_t)v;
+  }
+}
+
 uint64_t xvo_bitstream_bits(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                            int64_t Wb, int imodes, const int16_t* levels,
-                            const int8_t* mvs) {
+                            int64_t Wb, int imodes, const uint8_t* splits,
+                            const int16_t* levels, const int8_t* mvs) {
+  stream_shape sh;
+  shape_init(&sh, N, G, T, gop, Hb, Wb, imodes);
+  int h = N / 2;
   uint64_t bits = 0;
   for (int64_t f = 0; f < G * T; f++) {
     int intra = (f % T) % gop == 0;
+    const int8_t* fm = frame_mvs(&sh, mvs, f, splits != NULL);
+    const uint8_t* fs = splits ? splits + f * Hb * Wb : NULL;
     for (int64_t by = 0; by < Hb; by++) {
       int pmx = 0, pmy = 0;
       for (int64_t bx = 0; bx < Wb; bx++) {
-        const int8_t* mv = mvs + ((f * Hb + by) * Wb + bx) * 2;
-        if (intra) bits += imodes ? 1 : 0;
-        else bits += xvo_mv_bits(mv[0], mv[1], pmx, pmy);
-        pmx = mv[0];
-        pmy = mv[1];
+        if (intra) {
+          bits += imodes ? 1 : 0;
+        } else if (fs) {
+          bits += split_vector_unit(&sh, fm, fs[by * Wb + bx], bx, by, NULL);
+        } else {
+          const int8_t* mv = fm + (by * Wb + bx) * 2;
+          bits += xvo_mv_bits(mv[0], mv[1], pmx, pmy);
+          pmx = mv[0];
+          pmy = mv[1];
+        }
       }
     }
-    for (int64_t i = 0; i < 3 * Hb * Wb; i++)
-      bits += xvo_coef_bits(N, levels + (f * 3 * Hb * Wb + i) * N * N);
+    for (int64_t i = 0; i < 3 * Hb * Wb; i++) {
+      const int16_t* lev = levels + (f * 3 * Hb * Wb + i) * N * N;
+      if (fs && !intra && fs[i % (Hb * Wb)]) {
+        for (int q = 0; q < 4; q++) bits += xvo_coef_bits(h, lev + q * h * h);
+      } else {
+        bits += xvo_coef_bits(N, lev);
+      }
+    }
   }
   return bits;
 }
 
 int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                        int64_t Wb, int imodes, const int16_t* levels,
-                        const int8_t* mvs, uint8_t* out, uint64_t out_bytes,
-                        uint64_t* index) {
-  int32_t order[32 * 32];
-  xvo_scan_order(N, order);
+                        int64_t Wb, int imodes, const uint8_t* splits,
+                        const int16_t* levels, const int8_t* mvs, uint8_t* out,
+                        uint64_t out_bytes, uint64_t* index) {
+  stream_shape sh;
+  shape_init(&sh, N, G, T, gop, Hb, Wb, imodes);
+  int h = N / 2;
   memset(out, 0, out_bytes);
   bit_writer w = {out, out_bytes * 8, 0, 0};
   int64_t seg = 0;
   for (int64_t f = 0; f < G * T; f++) {
     int intra = (f % T) % gop == 0;
+    const int8_t* fm = frame_mvs(&sh, mvs, f, splits != NULL);
+    const uint8_t* fs = splits ? splits + f * Hb * Wb : NULL;
     for (int64_t by = 0; by < Hb; by++) {
       index[seg++] = w.pos;
       int pmx = 0, pmy = 0;
       for (int64_t bx = 0; bx < Wb; bx++) {
-        const int8_t* mv = mvs + ((f * Hb + by) * Wb + bx) * 2;
-        if (!intra) {
+        if (intra) {
+          /* the mode is the vector's first byte */
+          if (imodes) put_bit(&w, fm[(by * Wb + bx) * 2] != 0);
+        } else if (fs) {
+          split_vector_unit(&sh, fm, fs[by * Wb + bx], bx, by, &w);
+        } else {
+          const int8_t* mv = fm + (by * Wb + bx) * 2;
           put_se(&w, mv[0] - pmx);
           put_se(&w, mv[1] - pmy);
-        } else if (imodes) {
-          put_bit(&w, mv[0] != 0);
+          pmx = mv[0];
+          pmy = mv[1];
         }
-        pmx = mv[0];
-        pmy = mv[1];
       }
     }
     for (int c = 0; c < 3; c++)
@@ -516,21 +629,10 @@ int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
         index[seg++] = w.pos;
         for (int64_t bx = 0; bx < Wb; bx++) {
           const int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + by * Wb + bx) * N * N;
-          int nnz = 0;
-          for (int i = 0; i < N * N; i++) nnz += lev[i] != 0;
-          put_bit(&w, nnz > 0);
-          if (nnz == 0) continue;
-          put_ue(&w, (uint32_t)(nnz - 1));
-          int run = 0;
-          for (int i = 0; i < N * N; i++) {
-            int16_t v = lev[order[i]];
-            if (v == 0) {
-              run++;
-              continue;
-            }
-            put_ue(&w, (uint32_t)run);
-            put_se(&w, v);
-            run = 0;
+          if (fs && !intra && fs[by * Wb + bx]) {
+            for (int q = 0; q < 4; q++) put_block(&w, h, sh.order_h, lev + q * h * h);
+          } else {
+            put_block(&w, N, sh.order, lev);
           }
         }
       }
@@ -540,23 +642,50 @@ int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
 
 /* Sequential parse of the whole stream; index (may be NULL) receives the
  * segment offsets met on the way.  Levels not listed are zero; I frames get
- * the vector (0,0), or (mode, 0) with imodes. */
+ * the vector (0,0), or (mode, 0) with imodes; with splits, the split flags
+ * of P blocks are read into splits (I blocks: 0) and whole blocks repeat
+ * their vector over their four cells. */
 int xvo_read_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                       int64_t Wb, int imodes, const uint8_t* in, uint64_t bits,
-                       int16_t* levels, int8_t* mvs, uint64_t* index) {
-  int32_t order[32 * 32];
-  xvo_scan_order(N, order);
+                       int64_t Wb, int imodes, uint8_t* splits, const uint8_t* in,
+                       uint64_t bits, int16_t* levels, int8_t* mvs, uint64_t* index) {
+  stream_shape sh;
+  shape_init(&sh, N, G, T, gop, Hb, Wb, imodes);
+  int h = N / 2;
+  int64_t Wu = 2 * Wb;
   bit_reader r = {in, bits, 0, 0};
   int64_t seg = 0;
   memset(levels, 0, (size_t)(G * T * 3 * Hb * Wb * N * N) * sizeof(int16_t));
   for (int64_t f = 0; f < G * T; f++) {
     int intra = (f % T) % gop == 0;
+    int8_t* fm = (int8_t*)frame_mvs(&sh, mvs, f, splits != NULL);
+    uint8_t* fs = splits ? splits + f * Hb * Wb : NULL;
     for (int64_t by = 0; by < Hb; by++) {
       if (index) index[seg] = r.pos;
       seg++;
       int pmx = 0, pmy = 0;
       for (int64_t bx = 0; bx < Wb; bx++) {
-        int8_t* mv = mvs + ((f * Hb + by) * Wb + bx) * 2;
+        if (fs) {
+          int split = intra ? 0 : get_bit(&r);
+          fs[by * Wb + bx] = (uint8_t)split;
+          for (int i = 0; i < 4; i++) {
+            int64_t u = (2 * by + (i >> 1)) * Wu + 2 * bx + (i & 1);
+            int mx = 0, my = 0;
+            if (!intra && (split || i == 0)) {
+              int64_t xu = 2 * bx + (i & 1), yu = 2 * by + (i >> 1);
+              int qx = xu > 0 ? fm[2 * (yu * Wu + xu - 1)] : 0;
+              int qy = xu > 0 ? fm[2 * (yu * Wu + xu - 1) + 1] : 0;
+              mx = qx + get_se(&r);
+              my = qy + get_se(&r);
+            } else if (!intra) {
+              mx = fm[2 * ((2 * by) * Wu + 2 * bx)];
+              my = fm[2 * ((2 * by) * Wu + 2 * bx) + 1];
+            }
+            fm[2 * u] = (int8_t)mx;
+            fm[2 * u + 1] = (int8_t)my;
+          }
+          continue;
+        }
+        int8_t* mv = fm + (by * Wb + bx) * 2;
         int dx = 0, dy = 0;
         if (!intra) {
           dx = pmx + get_se(&r);
@@ -576,17 +705,10 @@ int xvo_read_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
         seg++;
         for (int64_t bx = 0; bx < Wb; bx++) {
           int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + by * Wb + bx) * N * N;
-          if (!get_bit(&r)) continue;
-          int nnz = (int)get_ue(&r) + 1;
-          int p = -1;
-          for (int k = 0; k < nnz && !r.overrun; k++) {
-            p += (int)get_ue(&r) + 1;
-            int32_t v = get_se(&r);
-            if (p >= N * N) {
-              r.overrun = 1;
-              break;
-            }
-            lev[order[p]] = (int16_t)v;
+          if (fs && fs[by * Wb + bx]) {
+            for (int q = 0; q < 4; q++) get_block(&r, h, sh.order_h, lev + q * h * h);
+          } else {
+            get_block(&r, N, sh.order, lev);
           }
         }
       }
@@ -910,11 +1032,11 @@ static int predict_sample(const xvo_params* p, const uint16_t* ref_plane, int64_
   return ref_plane[(y + dy) * Wp + x + dx];
 }
 
-static void code_block(const xvo_params* p, int intra, const int32_t* ipred,
+static void code_block(const xvo_params* p, int N, int intra, const int32_t* ipred,
                        const uint16_t* cur, const uint16_t* pred_plane, int64_t Hp,
                        int64_t Wp, int64_t x0, int64_t y0, int dx, int dy, int16_t* lev_out,
                        uint16_t* rec_plane, uint32_t* bits_out) {
-  int N = p->block, B = p->bit_depth;
+  int B = p->bit_depth;
   int L = (1 << B) - 1;
   int32_t r[32 * 32] = {0}, C[32 * 32], d[32 * 32], rr[32 * 32], pred[32 * 32];
   for (int i = 0; i < N; i++)
@@ -939,17 +1061,103 @@ static void code_block(const xvo_params* p, int intra, const int32_t* ipred,
     }
 }
 
+/* Adaptive block size of P pictures (XVO split).  The paper's x265 presets  */
+/* choose block sizes per coding tree; its text gives no rule.  Reading: a   */
+/* block of the configured size N (the tree's root) is either coded whole    */
+/* or split once into four N/2 blocks in z-order, each with its own vector   */
+/* and transform, whichever has the smaller cost J = 16 SAD + lambda16 bits, */
+/* where SAD is each block's full-search SAD (the integer search above) and  */
+/* bits the Exp-Golomb length of its vector against the zero vector (the     */
+/* coded predictors depend on the choices to the left, so the choice does    */
+/* not); a tie keeps the block whole.  lambda = sqrt(0.57 2^((qP-12)/3)),    */
+/* the motion-cost multiplier of the H.265 reference encoder, in 1/16 SAD    */
+/* units.  I pictures are never split.  Vectors live on the N/2 grid (a      */
+/* whole block repeats its vector over its four cells); a block's vector     */
+/* bits are one split flag plus, per coded vector in z-order, se of the      */
+/* difference to the vector of the N/2 cell to the left of its top-left      */
+/* cell ((0,0) in cell column 0).  A split block's levels are its four N/2   */
+/* blocks' levels one after another in z-order.                              */
+int32_t xvo_split_lambda(int qp, int B) {
+  int qP = qp + 6 * (B - 8);
+  return (int32_t)floor(16.0 * sqrt(0.57 * pow(2.0, (qP - 12) / 3.0)) + 0.5);
+}
+
+int xvo_split_choose(uint32_t sad_whole, int vx, int vy, const uint32_t* sads,
+                     const int32_t* ux, const int32_t* uy, int32_t lam16) {
+  uint64_t lam = (uint64_t)lam16;
+  uint64_t j_whole = 16 * (uint64_t)sad_whole + lam * (uint64_t)xvo_mv_bits(vx, vy, 0, 0);
+  uint64_t j_split = 0;
+  for (int i = 0; i < 4; i++)
+    j_split += 16 * (uint64_t)sads[i] + lam * (uint64_t)xvo_mv_bits(ux[i], uy[i], 0, 0);
+  return j_split < j_whole;
+}
+
+static void encode_p_split(const xvo_params* p, const uint16_t* cur, const uint16_t* ref,
+                           int64_t Hp, int64_t Wp, int nch, int16_t* levels, int8_t* mvu,
+                           uint8_t* splits, uint32_t* coef_bits, uint32_t* mv_bits,
+                           uint16_t* rec) {
+  int N = p->block, h = N / 2, R = p->search_range;
+  int64_t Hb = Hp / N, Wb = Wp / N, Wu = 2 * Wb, plane = Hp * Wp;
+  int32_t lam = xvo_split_lambda(p->qp, p->bit_depth);
+  for (int64_t by = 0; by < Hb; by++)
+    for (int64_t bx = 0; bx < Wb; bx++) {
+      int64_t ci = by * Wb + bx;
+      int32_t vx, vy, ux[4], uy[4];
+      uint32_t sad, usad[4];
+      xvo_motion_search(cur, ref, Hp, Wp, N, R, nch, bx, by, &vx, &vy, &sad);
+      for (int i = 0; i < 4; i++)
+        xvo_motion_search(cur, ref, Hp, Wp, h, R, nch, 2 * bx + (i & 1), 2 * by + (i >> 1),
+                          &ux[i], &uy[i], &usad[i]);
+      int split = xvo_split_choose(sad, vx, vy, usad, ux, uy, lam);
+      splits[ci] = (uint8_t)split;
+      for (int i = 0; i < 4; i++) {
+        int64_t u = (2 * by + (i >> 1)) * Wu + 2 * bx + (i & 1);
+        mvu[2 * u] = (int8_t)(split ? ux[i] : vx);
+        mvu[2 * u + 1] = (int8_t)(split ? uy[i] : vy);
+      }
+      uint32_t mb = 1; /* the split flag */
+      for (int i = 0; i < (split ? 4 : 1); i++) {
+        int64_t xu = 2 * bx + (i & 1), yu = 2 * by + (i >> 1);
+        int pmx = 0, pmy = 0;
+        if (xu > 0) {
+          pmx = mvu[2 * (yu * Wu + xu - 1)];
+          pmy = mvu[2 * (yu * Wu + xu - 1) + 1];
+        }
+        mb += xvo_mv_bits(mvu[2 * (yu * Wu + xu)], mvu[2 * (yu * Wu + xu) + 1], pmx, pmy);
+      }
+      mv_bits[ci] = mb;
+      for (int c = 0; c < 3; c++) {
+        int16_t* lev = levels + (c * Hb * Wb + ci) * N * N;
+        uint32_t* cb = &coef_bits[c * Hb * Wb + ci];
+        if (!split) {
+          code_block(p, N, 0, NULL, cur + c * plane, ref + c * plane, Hp, Wp, bx * N, by * N,
+                     vx, vy, lev, rec + c * plane, cb);
+          continue;
+        }
+        *cb = 0;
+        for (int i = 0; i < 4; i++) {
+          uint32_t b;
+          code_block(p, h, 0, NULL, cur + c * plane, ref + c * plane, Hp, Wp,
+                     bx * N + (i & 1) * h, by * N + (i >> 1) * h, ux[i], uy[i], lev + i * h * h,
+                     rec + c * plane, &b);
+          *cb += b;
+        }
+      }
+    }
+}
+
 int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
                    int64_t W, int64_t Bn, const double* mn, const double* mx,
                    const xvo_params* p, int64_t g, int64_t t0, int64_t len,
                    uint16_t* frames, int16_t* levels, int8_t* mvs,
                    uint16_t* recon, uint32_t* coef_bits, uint32_t* mv_bits,
-                   uint64_t* sse, uint64_t* nvalid) {
+                   uint8_t* splits, uint64_t* sse, uint64_t* nvalid) {
   if (xvo_check_params(p) != 0) return -1;
   int N = p->block;
   int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
   int64_t Hb = Hp / N, Wb = Wp / N;
   int64_t plane = Hp * Wp, fsz = 3 * plane;
+  int64_t mvf = (p->split ? 4 : 1) * Hb * Wb; /* vectors per frame */
   int nch = (int)(Bn - 3 * g < 3 ? Bn - 3 * g : 3);
   uint8_t* valid = (uint8_t*)malloc((size_t)fsz);
   if (!valid) return -2;
@@ -961,6 +1169,15 @@ int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
     const uint16_t* ref = f > 0 ? recon + (f - 1) * fsz : NULL;
     int intra = (f == 0);
     xvo_make_frame(data, dtype, T, H, W, Bn, mn, mx, p, g, t, Hp, Wp, cur, valid);
+    if (p->split) {
+      memset(mvs + f * mvf * 2, 0, (size_t)mvf * 2);
+      memset(splits + f * Hb * Wb, 0, (size_t)(Hb * Wb));
+    }
+    if (!intra && p->split) {
+      encode_p_split(p, cur, ref, Hp, Wp, nch, levels + f * fsz, mvs + f * mvf * 2,
+                     splits + f * Hb * Wb, coef_bits + f * 3 * Hb * Wb, mv_bits + f * Hb * Wb,
+                     rec);
+    } else
     for (int64_t by = 0; by < Hb; by++) {
       int pmx = 0, pmy = 0;
       for (int64_t bx = 0; bx < Wb; bx++) {
@@ -982,15 +1199,17 @@ int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
             dy = qy;
           }
         }
-        mvs[(f * Hb * Wb + bi) * 2 + 0] = (int8_t)dx;
-        mvs[(f * Hb * Wb + bi) * 2 + 1] = (int8_t)dy;
+        if (!p->split) { /* (split: I cells stay zero) */
+          mvs[(f * Hb * Wb + bi) * 2 + 0] = (int8_t)dx;
+          mvs[(f * Hb * Wb + bi) * 2 + 1] = (int8_t)dy;
+        }
         mv_bits[f * Hb * Wb + bi] =
             intra ? (uint32_t)p->intra /* one mode bit */ : xvo_mv_bits(dx, dy, pmx, pmy);
         pmx = intra ? 0 : dx;
         pmy = intra ? 0 : dy;
         for (int c = 0; c < 3; c++) {
           int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + bi) * N * N;
-          code_block(p, intra, use_ipred ? ipred + c * N * N : NULL, cur + c * plane,
+          code_block(p, N, intra, use_ipred ? ipred + c * N * N : NULL, cur + c * plane,
                      ref ? ref + c * plane : NULL,
                      Hp, Wp, bx * N, by * N, dx, dy, lev, rec + c * plane,
                      &coef_bits[(f * 3 + c) * Hb * Wb + bi]);
@@ -1011,8 +1230,26 @@ int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
 
 /* Decoding of one GOP from its levels and vectors: the same prediction,
  * dequantisation and inverse transform as the encoder's reconstruction. */
+/* Reconstruction of one N x N P block at (x0, y0) from its levels. */
+static void decode_block(const xvo_params* p, int N, const int16_t* lev,
+                         const uint16_t* ref_plane, int64_t Hp, int64_t Wp, int64_t x0,
+                         int64_t y0, int dx, int dy, uint16_t* rec_plane) {
+  int B = p->bit_depth, L = (1 << B) - 1;
+  int32_t d[32 * 32], rr[32 * 32];
+  xvo_dequantize(N, B, p->qp, lev, d);
+  xvo_inverse_transform(N, B, d, rr);
+  for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++) {
+      int v = predict_sample(p, ref_plane, Hp, Wp, x0 + j, y0 + i, dx, dy) + rr[i * N + j];
+      if (v < 0) v = 0;
+      if (v > L) v = L;
+      rec_plane[(y0 + i) * Wp + x0 + j] = (uint16_t)v;
+    }
+}
+
 int xvo_decode_gop(const xvo_params* p, int64_t H, int64_t W, int64_t len,
-                   const int16_t* levels, const int8_t* mvs, uint16_t* recon) {
+                   const int16_t* levels, const int8_t* mvs, const uint8_t* splits,
+                   uint16_t* recon) {
   if (xvo_check_params(p) != 0) return -1;
   int N = p->block, B = p->bit_depth, L = (1 << B) - 1;
   int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
@@ -1021,11 +1258,32 @@ int xvo_decode_gop(const xvo_params* p, int64_t H, int64_t W, int64_t len,
   for (int64_t f = 0; f < len; f++) {
     uint16_t* rec = recon + f * fsz;
     const uint16_t* ref = f > 0 ? recon + (f - 1) * fsz : NULL;
+    if (f > 0 && p->split) {
+      /* whole blocks take the vector of their top-left cell */
+      int h = N / 2;
+      int64_t Wu = 2 * Wb;
+      const int8_t* mvu = mvs + f * 4 * Hb * Wb * 2;
+      for (int64_t by = 0; by < Hb; by++)
+        for (int64_t bx = 0; bx < Wb; bx++) {
+          int64_t ci = by * Wb + bx;
+          int split = splits[f * Hb * Wb + ci] != 0;
+          for (int c = 0; c < 3; c++) {
+            const int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + ci) * N * N;
+            for (int i = 0; i < (split ? 4 : 1); i++) {
+              int64_t u = (2 * by + (i >> 1)) * Wu + 2 * bx + (i & 1);
+              decode_block(p, split ? h : N, lev + i * h * h, ref + c * plane, Hp, Wp,
+                           bx * N + (i & 1) * h, by * N + (i >> 1) * h, mvu[2 * u],
+                           mvu[2 * u + 1], rec + c * plane);
+            }
+          }
+        }
+      continue;
+    }
     for (int64_t by = 0; by < Hb; by++)
       for (int64_t bx = 0; bx < Wb; bx++) {
         int64_t bi = by * Wb + bx;
-        int dx = mvs[(f * Hb * Wb + bi) * 2 + 0];
-        int dy = mvs[(f * Hb * Wb + bi) * 2 + 1];
+        int dx = p->split ? 0 : mvs[(f * Hb * Wb + bi) * 2 + 0];
+        int dy = p->split ? 0 : mvs[(f * Hb * Wb + bi) * 2 + 1];
         for (int c = 0; c < 3; c++) {
           const int16_t* lev = levels + ((f * 3 + c) * Hb * Wb + bi) * N * N;
           int32_t ipred[32 * 32], refs[4 * 32 + 1];
@@ -1064,6 +1322,9 @@ int xvo_check_params(const xvo_params* p) {
   if (p->search_range < 0 || p->search_range > 64) return -1;
   if (p->qpel != 0 && p->qpel != 1) return -1;
   if (p->intra != 0 && p->intra != 1) return -1;
+  if (p->split != 0 && p->split != 1) return -1;
+  /* adaptive block size: N/2 >= 4, integer vectors, constant I prediction */
+  if (p->split && (N < 8 || p->qpel || p->intra)) return -1;
   /* quarter-sample vectors reach 4R + 3, which must fit int8 */
   if (p->qpel && p->search_range > 31) return -1;
   if (p->gop < 1) return -1;
@@ -1076,12 +1337,13 @@ int xvo_encode_cube(const void* data, int dtype, int64_t T, int64_t H,
                     int64_t W, int64_t Bn, const xvo_params* p, double* mn,
                     double* mx, uint16_t* frames, int16_t* levels, int8_t* mvs,
                     uint16_t* recon, uint32_t* coef_bits, uint32_t* mv_bits,
-                    uint64_t* sse, uint64_t* nvalid) {
+                    uint8_t* splits, uint64_t* sse, uint64_t* nvalid) {
   if (xvo_check_params(p) != 0) return -1;
   int N = p->block;
   int64_t G = (Bn + 2) / 3;
   int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
   int64_t Hb = Hp / N, Wb = Wp / N, fsz = 3 * Hp * Wp;
+  int64_t mvf = (p->split ? 4 : 1) * Hb * Wb;
   int64_t ngop = (T + p->gop - 1) / p->gop;
   xvo_stats(data, dtype, T, H, W, Bn, mn, mx, NULL);
   uint64_t* part = (uint64_t*)calloc((size_t)(G * ngop * 6), sizeof(uint64_t));
@@ -1094,9 +1356,10 @@ int xvo_encode_cube(const void* data, int dtype, int64_t T, int64_t H,
     int64_t len = T - t0 < p->gop ? T - t0 : p->gop;
     int64_t ft = g * T + t0;
     err |= xvo_encode_gop(data, dtype, T, H, W, Bn, mn, mx, p, g, t0, len,
-                          frames + ft * fsz, levels + ft * fsz, mvs + ft * Hb * Wb * 2,
+                          frames + ft * fsz, levels + ft * fsz, mvs + ft * mvf * 2,
                           recon + ft * fsz, coef_bits + ft * 3 * Hb * Wb,
-                          mv_bits + ft * Hb * Wb, part + u * 6, part + u * 6 + 3);
+                          mv_bits + ft * Hb * Wb, splits ? splits + ft * Hb * Wb : NULL,
+                          part + u * 6, part + u * 6 + 3);
   }
   for (int64_t b = 0; b < Bn; b++) { sse[b] = 0; nvalid[b] = 0; }
   for (int64_t u = 0; u < G * ngop; u++) {
@@ -1114,12 +1377,13 @@ int xvo_encode_cube(const void* data, int dtype, int64_t T, int64_t H,
 
 int xvo_decode_cube(const xvo_params* p, int64_t T, int64_t H, int64_t W,
                     int64_t Bn, const int16_t* levels, const int8_t* mvs,
-                    uint16_t* recon) {
+                    const uint8_t* splits, uint16_t* recon) {
   if (xvo_check_params(p) != 0) return -1;
   int N = p->block;
   int64_t G = (Bn + 2) / 3;
   int64_t Hp = (H + N - 1) / N * N, Wp = (W + N - 1) / N * N;
   int64_t Hb = Hp / N, Wb = Wp / N, fsz = 3 * Hp * Wp;
+  int64_t mvf = (p->split ? 4 : 1) * Hb * Wb;
   int64_t ngop = (T + p->gop - 1) / p->gop;
   int err = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
@@ -1128,8 +1392,8 @@ int xvo_decode_cube(const xvo_params* p, int64_t T, int64_t H, int64_t W,
     int64_t t0 = k * p->gop;
     int64_t len = T - t0 < p->gop ? T - t0 : p->gop;
     int64_t ft = g * T + t0;
-    err |= xvo_decode_gop(p, H, W, len, levels + ft * fsz, mvs + ft * Hb * Wb * 2,
-                          recon + ft * fsz);
+    err |= xvo_decode_gop(p, H, W, len, levels + ft * fsz, mvs + ft * mvf * 2,
+                          splits ? splits + ft * Hb * Wb : NULL, recon + ft * fsz);
   }
   return err ? -1 : 0;
 }

@@ -30,6 +30,8 @@ typedef struct {
   int32_t qpel;         /* 1: quarter-sample motion (R <= 31), 0: integer */
   int32_t intra;        /* 1: I blocks predicted by DC / planar from their
                            reconstructed neighbours, 0: constant 2^(B-1) */
+  int32_t split;        /* 1: P blocks coded whole or as four N/2 blocks
+                           (N >= 8, integer vectors, no intra modes) */
 } xvo_params;
 
 int xvo_selfcheck(void);
@@ -95,22 +97,31 @@ void xvo_intra_refs(const uint16_t* rec_plane, int64_t Hp, int64_t Wp, int N, in
                     int64_t bx, int64_t by, int32_t* refs);
 void xvo_intra_predict(const int32_t* refs, int N, int mode, int B, int32_t* pred);
 
+/* Adaptive block size (split): the lambda of the whole/split choice in
+ * 1/16 SAD units; splits is [frames][Hb][Wb] (1 = split), NULL without the
+ * tool.  With the tool the vectors are [frames][2 Hb][2 Wb][2] (N/2 grid). */
+int32_t xvo_split_lambda(int qp, int B);
+/* 1 when the four N/2 blocks (SADs sads, vectors (ux, uy), z-order) cost
+ * less than the whole block (SAD sad_whole, vector (vx, vy)). */
+int xvo_split_choose(uint32_t sad_whole, int vx, int vy, const uint32_t* sads,
+                     const int32_t* ux, const int32_t* uy, int32_t lam16);
 int xvo_encode_gop(const void* data, int dtype, int64_t T, int64_t H,
                    int64_t W, int64_t Bn, const double* mn, const double* mx,
                    const xvo_params* p, int64_t g, int64_t t0, int64_t len,
                    uint16_t* frames, int16_t* levels, int8_t* mvs,
                    uint16_t* recon, uint32_t* coef_bits, uint32_t* mv_bits,
-                   uint64_t* sse, uint64_t* nvalid);
+                   uint8_t* splits, uint64_t* sse, uint64_t* nvalid);
 int xvo_decode_gop(const xvo_params* p, int64_t H, int64_t W, int64_t len,
-                   const int16_t* levels, const int8_t* mvs, uint16_t* recon);
+                   const int16_t* levels, const int8_t* mvs, const uint8_t* splits,
+                   uint16_t* recon);
 int xvo_encode_cube(const void* data, int dtype, int64_t T, int64_t H,
                     int64_t W, int64_t Bn, const xvo_params* p, double* mn,
                     double* mx, uint16_t* frames, int16_t* levels, int8_t* mvs,
                     uint16_t* recon, uint32_t* coef_bits, uint32_t* mv_bits,
-                    uint64_t* sse, uint64_t* nvalid);
+                    uint8_t* splits, uint64_t* sse, uint64_t* nvalid);
 int xvo_decode_cube(const xvo_params* p, int64_t T, int64_t H, int64_t W,
                     int64_t Bn, const int16_t* levels, const int8_t* mvs,
-                    uint16_t* recon);
+                    const uint8_t* splits, uint16_t* recon);
 void xvo_denormalize_cube(const uint16_t* recon, int64_t T, int64_t H,
                           int64_t W, int64_t Bn, int N, int B, const double* mn,
                           const double* mx, int out_dtype, void* out);
@@ -120,15 +131,15 @@ void xvo_denormalize_cube(const uint16_t* recon, int64_t T, int64_t H,
  * frame f = g * T + t, intra when t % gop == 0.  index receives the bit
  * offset of each of the 4 * Hb segments per frame. */
 uint64_t xvo_bitstream_bits(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                            int64_t Wb, int imodes, const int16_t* levels,
-                            const int8_t* mvs);
+                            int64_t Wb, int imodes, const uint8_t* splits,
+                            const int16_t* levels, const int8_t* mvs);
 int xvo_write_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                        int64_t Wb, int imodes, const int16_t* levels,
-                        const int8_t* mvs, uint8_t* out, uint64_t out_bytes,
-                        uint64_t* index);
+                        int64_t Wb, int imodes, const uint8_t* splits,
+                        const int16_t* levels, const int8_t* mvs, uint8_t* out,
+                        uint64_t out_bytes, uint64_t* index);
 int xvo_read_bitstream(int N, int64_t G, int64_t T, int gop, int64_t Hb,
-                       int64_t Wb, int imodes, const uint8_t* in, uint64_t bits,
-                       int16_t* levels, int8_t* mvs, uint64_t* index);
+                       int64_t Wb, int imodes, uint8_t* splits, const uint8_t* in,
+                       uint64_t bits, int16_t* levels, int8_t* mvs, uint64_t* index);
 
 double xvo_psnr(double peak, double sse, double n);
 double xvo_psnr_int(int B, uint64_t sse, uint64_t n);
