@@ -91,6 +91,23 @@ extern "C" {
                                 The mode is stored as the first byte of the
                                 block's vector entry and costs one vector
                                 bit. */
+#define XV_FLAG_SPLIT 8u     /* adaptive block size of P pictures: each
+                                block (block >= 8) coded whole or as four
+                                block/2 blocks in z-order, each with its own
+                                vector and transform, whichever has the
+                                smaller 16 SAD + lambda16 bits (bits of the
+                                vectors against zero; lambda16 =
+                                floor(16 sqrt(0.57 2^((qP-12)/3)) + 1/2),
+                                qP = qp + 6 (bit_depth - 8); a tie keeps it
+                                whole).  Vectors are then stored on the
+                                block/2 grid ([G][T][2Hb][2Wb][2], a whole
+                                block's vector repeated over its four cells)
+                                and a split block's levels are its four
+                                blocks' levels in z-order inside its slot.
+                                A block's vector bits: one split flag plus
+                                se of each coded vector's difference to the
+                                vector of the cell left of its top-left cell.
+                                Not with XV_FLAG_QPEL or XV_FLAG_INTRA. */
 
 #define XV_MAX_BANDS 64
 #define XV_MAX_GROUPS 22
@@ -156,6 +173,7 @@ typedef struct {
   const double* band_max; /* [bands] */
   const uint64_t* sse;    /* [3*groups]: per coded channel; entry 3g+c is band 3g+c */
   const uint64_t* n_valid;/* [bands] */
+  const uint8_t* splits;  /* [groups][T][Hb][Wb] split flags (XV_FLAG_SPLIT), else NULL */
 } xv_export;
 
 int xv_abi_version(void);
@@ -432,10 +450,12 @@ int xv_profile_read(xv_profile* out);
  * Payload order, frame by frame (f = g*T + t): the vectors of the frame's
  * blocks in raster order (se(dx - pdx), se(dy - pdy) with the left
  * neighbour's vector as predictor, (0,0) in column 0; nothing for I frames,
- * or one mode bit per block under XV_FLAG_INTRA),
+ * or one mode bit per block under XV_FLAG_INTRA; under XV_FLAG_SPLIT a P
+ * block's split flag and then its one or four vectors),
  * then for channel c = 0, 1, 2 the blocks' coefficients in raster order (a
  * coded-flag bit, then ue(nnz-1) and per nonzero level in up-right diagonal
- * scan order ue(run), se(level)).  The payload has exactly coef_bits +
+ * scan order ue(run), se(level); a split block: its four blocks' codes in
+ * z-order).  The payload has exactly coef_bits +
  * mv_bits bits.  Every block row of vectors or of one channel's
  * coefficients is a segment whose bit offset is stored, so rows parse in
  * parallel.  Buffer layout (little-endian): a 256-byte header (magic

@@ -8,9 +8,12 @@
 // the frame's blocks in raster order (se(dx - pdx), se(dy - pdy), the left
 // neighbour's vector as predictor, (0,0) in column 0; I frames have empty
 // vector units, or one bit holding the block's intra mode when I blocks are
-// intra-predicted), then for channel c = 0, 1, 2 the coefficient units of the
+// intra-predicted; with the adaptive block size a P block's unit is its
+// split flag and then its one or four vectors, each against the vector of
+// the cell left of its top-left cell), then for channel c = 0, 1, 2 the coefficient units of the
 // blocks in raster order (coded flag, then ue(nnz - 1) and per nonzero level
-// in up-right diagonal scan order ue(run), se(level)).  A frame therefore
+// in up-right diagonal scan order ue(run), se(level); a split block: its four
+// N/2 blocks' codes in z-order).  A frame therefore
 // has 4 Hb Wb units; a row of Wb units is a segment, whose bit offset is
 // stored so that segments parse independently.
 //
@@ -149,11 +152,40 @@ __device__ inline void build_scan_table(uint16_t* scan, int N) {
   }
 }
 
+// Codes of one block's levels (n x n, column-major) in scan order.
+__device__ inline void put_block(BitSink& bs, const int16_t* lev, int n, const uint16_t* scan) {
+  int nnz = 0;
+  for (int i = 0; i < n * n; i += 8) {
+    const uint4 w = *(const uint4*)(lev + i);
+    const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++) nnz += ((q[j] & 0xffffu) != 0) + ((q[j] >> 16) != 0);
+  }
+  bs.put(nnz > 0 ? 1u : 0u, 1);
+  if (nnz > 0) {
+    bs.ue((uint32_t)(nnz - 1));
+    int run = 0, seen = 0;
+    for (int p = 0; p < n * n && seen < nnz; p++) {
+      const int v = lev[scan[p]];
+      if (v == 0) {
+        run++;
+        continue;
+      }
+      bs.ue((uint32_t)run);
+      bs.se(v);
+      run = 0;
+      seen++;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBitsThreads) write_units_kernel(BitsArgs a) {
   __shared__ uint64_t buf[kBitsThreads];
   __shared__ uint16_t scan[32 * 32];
+  __shared__ uint16_t scan_h[16 * 16];
   const int N = a.N;
   build_scan_table(scan, N);
+  if (a.splits) build_scan_table(scan_h, N / 2);
   const int64_t u = (int64_t)blockIdx.x * kBitsThreads + threadIdx.x;
   const uint64_t len = u < a.nunits ? unit_len(a, u) : 0u;
   const uint64_t off = a.block_off[blockIdx.x] + block_exclusive_u64(len, buf);  // syncs
@@ -164,44 +196,43 @@ __global__ void __launch_bounds__(kBitsThreads) write_units_kernel(BitsArgs a) {
   const int64_t hw = (int64_t)a.Hb * a.Wb;
   const int64_t f = u / (4 * hw);
   const int64_t r = u - f * 4 * hw;
+  const bool intra = (f % a.T) % a.gop == 0;
   if (r < hw) {
-    const int8_t* mv = a.mvs + (f * hw + r) * 2;
-    if ((f % a.T) % a.gop == 0) {  // an intra mode (I units are empty otherwise)
-      bs.put(mv[0] != 0 ? 1u : 0u, 1);
-      bs.flush();
-      return;
+    if (a.splits) {  // a P block's split flag and vectors (I units are empty)
+      const int8_t* mvu = a.mvs + f * 4 * hw * 2;
+      const int by = (int)(r / a.Wb), bx = (int)(r - (int64_t)by * a.Wb);
+      const int64_t Wu = 2 * (int64_t)a.Wb;
+      const bool sp = a.splits[f * hw + r] != 0;
+      bs.put(sp ? 1u : 0u, 1);
+      for (int i = 0; i < (sp ? 4 : 1); i++) {
+        const int64_t xu = 2 * bx + (i & 1), yu = 2 * by + (i >> 1);
+        const int8_t* v = mvu + (yu * Wu + xu) * 2;
+        const int pmx = xu > 0 ? v[-2] : 0, pmy = xu > 0 ? v[-1] : 0;
+        bs.se(v[0] - pmx);
+        bs.se(v[1] - pmy);
+      }
+    } else {
+      const int8_t* mv = a.mvs + (f * hw + r) * 2;
+      if (intra) {  // an intra mode (I units are empty otherwise)
+        bs.put(mv[0] != 0 ? 1u : 0u, 1);
+        bs.flush();
+        return;
+      }
+      int pmx = 0, pmy = 0;
+      if (r % a.Wb != 0) {
+        pmx = mv[-2];
+        pmy = mv[-1];
+      }
+      bs.se(mv[0] - pmx);
+      bs.se(mv[1] - pmy);
     }
-    int pmx = 0, pmy = 0;
-    if (r % a.Wb != 0) {
-      pmx = mv[-2];
-      pmy = mv[-1];
-    }
-    bs.se(mv[0] - pmx);
-    bs.se(mv[1] - pmy);
   } else {
     const int16_t* lev = a.levels + (f * 3 * hw + (r - hw)) * N * N;
-    int nnz = 0;
-    for (int i = 0; i < N * N; i += 8) {
-      const uint4 w = *(const uint4*)(lev + i);
-      const uint32_t q[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-      for (int j = 0; j < 4; j++) nnz += ((q[j] & 0xffffu) != 0) + ((q[j] >> 16) != 0);
-    }
-    bs.put(nnz > 0 ? 1u : 0u, 1);
-    if (nnz > 0) {
-      bs.ue((uint32_t)(nnz - 1));
-      int run = 0, seen = 0;
-      for (int p = 0; p < N * N && seen < nnz; p++) {
-        const int v = lev[scan[p]];
-        if (v == 0) {
-          run++;
-          continue;
-        }
-        bs.ue((uint32_t)run);
-        bs.se(v);
-        run = 0;
-        seen++;
-      }
+    if (a.splits && !intra && a.splits[f * hw + (r - hw) % hw]) {
+      const int h = N / 2;
+      for (int q = 0; q < 4; q++) put_block(bs, lev + q * h * h, h, scan_h);
+    } else {
+      put_block(bs, lev, N, scan);
     }
   }
   bs.flush();
@@ -274,10 +305,33 @@ struct BitSource {
 // Any inconsistency (a code no writer emits, a position past the block, a
 // vector out of range, a segment not ending where the next begins) sets
 // *err and stops that segment.
+// Levels of one n x n block (column-major, zero on entry) from its codes.
+__device__ inline bool get_block(BitSource& src, int16_t* lev, int n, const uint16_t* scan) {
+  bool ok = true;
+  if (src.bit()) {
+    uint32_t k;
+    ok = src.ue(k) && k < (uint32_t)(n * n);
+    const int nnz = ok ? (int)k + 1 : 0;
+    int p = -1;
+    for (int i = 0; i < nnz && ok; i++) {
+      uint32_t run;
+      int v;
+      ok = src.ue(run) && src.se(v) && v != 0 && v >= -32767 && v <= 32767;
+      if (!ok) break;
+      p += (int)run + 1;
+      ok = p < n * n;
+      if (ok) lev[scan[p]] = (int16_t)v;
+    }
+  }
+  return ok;
+}
+
 __global__ void __launch_bounds__(kBitsThreads) parse_segments_kernel(BitsArgs a) {
   __shared__ uint16_t scan[32 * 32];
+  __shared__ uint16_t scan_h[16 * 16];
   const int N = a.N;
   build_scan_table(scan, N);
+  if (a.splits_out) build_scan_table(scan_h, N / 2);
   __syncthreads();
   const int64_t s = (int64_t)blockIdx.x * kBitsThreads + threadIdx.x;
   const int64_t nseg = a.nunits / a.Wb;
@@ -292,7 +346,38 @@ __global__ void __launch_bounds__(kBitsThreads) parse_segments_kernel(BitsArgs a
   const int t = (int)(f % a.T);
   const bool intra = t % a.gop == 0;
   bool ok = true;
-  if (r < a.Hb) {
+  // with split flags the vector rows parse first (phase 0), then the
+  // coefficient rows, which need the flags (phase 1)
+  if (a.phase >= 0 && (r < a.Hb) != (a.phase == 0)) return;
+  if (r < a.Hb && a.splits_out) {
+    const int64_t row = r;
+    const int64_t Wu = 2 * (int64_t)a.Wb;
+    int8_t* mvu = a.mvs_out + f * 4 * hw * 2;
+    for (int bx = 0; bx < a.Wb && ok; bx++) {
+      const int64_t blk = f * hw + row * a.Wb + bx;
+      const uint64_t p0 = src.pos;
+      const bool sp = !intra && src.bit();
+      a.splits_out[blk] = sp ? 1 : 0;
+      for (int i = 0; i < 4; i++) {
+        const int64_t xu = 2 * bx + (i & 1), yu = 2 * row + (i >> 1);
+        int8_t* v = mvu + (yu * Wu + xu) * 2;
+        int mx = 0, my = 0;
+        if (!intra && (sp || i == 0)) {
+          int ddx = 0, ddy = 0;
+          ok = ok && src.se(ddx) && src.se(ddy);
+          mx = (xu > 0 ? v[-2] : 0) + ddx;
+          my = (xu > 0 ? v[-1] : 0) + ddy;
+          ok = ok && mx >= -128 && mx <= 127 && my >= -128 && my <= 127;
+        } else if (!intra) {  // a whole block repeats its vector
+          mx = mvu[(2 * row * Wu + 2 * bx) * 2];
+          my = mvu[(2 * row * Wu + 2 * bx) * 2 + 1];
+        }
+        v[0] = (int8_t)mx;
+        v[1] = (int8_t)my;
+      }
+      a.mbits_out[blk] = (uint32_t)(src.pos - p0);
+    }
+  } else if (r < a.Hb) {
     const int64_t row = r;
     int pmx = 0, pmy = 0;
     for (int bx = 0; bx < a.Wb && ok; bx++) {
@@ -321,20 +406,11 @@ __global__ void __launch_bounds__(kBitsThreads) parse_segments_kernel(BitsArgs a
       const int64_t blk = (f * 3 + c) * hw + row * a.Wb + bx;
       int16_t* lev = a.levels_out + blk * N * N;
       const uint64_t p0 = src.pos;
-      if (src.bit()) {
-        uint32_t k;
-        ok = src.ue(k) && k < (uint32_t)(N * N);
-        const int nnz = ok ? (int)k + 1 : 0;
-        int p = -1;
-        for (int i = 0; i < nnz && ok; i++) {
-          uint32_t run;
-          int v;
-          ok = src.ue(run) && src.se(v) && v != 0 && v >= -32767 && v <= 32767;
-          if (!ok) break;
-          p += (int)run + 1;
-          ok = p < N * N;
-          if (ok) lev[scan[p]] = (int16_t)v;
-        }
+      if (a.splits_out && a.splits_out[f * hw + row * a.Wb + bx]) {
+        const int h = N / 2;
+        for (int q = 0; q < 4 && ok; q++) ok = get_block(src, lev + q * h * h, h, scan_h);
+      } else {
+        ok = get_block(src, lev, N, scan);
       }
       a.cbits_out[blk] = (uint32_t)(src.pos - p0);
     }
@@ -370,8 +446,20 @@ hipError_t launch_bits_write(const BitsArgs& a, hipStream_t s) {
 hipError_t launch_bits_parse(const BitsArgs& a, hipStream_t s) {
   const int64_t nseg = a.nunits / a.Wb;
   if (nseg <= 0) return hipSuccess;
-  parse_segments_kernel<<<blocks_for(nseg, kBitsThreads), kBitsThreads, 0, s>>>(a);
-  return hipGetLastError();
+  if (!a.splits_out) {
+    BitsArgs b = a;
+    b.phase = -1;
+    parse_segments_kernel<<<blocks_for(nseg, kBitsThreads), kBitsThreads, 0, s>>>(b);
+    return hipGetLastError();
+  }
+  for (int ph = 0; ph < 2; ph++) {
+    BitsArgs b = a;
+    b.phase = ph;
+    parse_segments_kernel<<<blocks_for(nseg, kBitsThreads), kBitsThreads, 0, s>>>(b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_write_header(const PackHeader& h, void* dst, hipStream_t s) {

@@ -356,6 +356,7 @@ __global__ void __launch_bounds__(512) me_kernel(const LaunchDesc jd, int R, int
     int8_t* mv = job.mv + ((size_t)by * Wb + bx0 + b) * 2;
     mv[0] = (int8_t)dx;
     mv[1] = (int8_t)dy;
+    if (job.sad) job.sad[(size_t)by * Wb + bx0 + b] = (uint32_t)(key >> keyshift_sad);
   }
 }
 
@@ -731,6 +732,7 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
     int8_t* mv = job.mv + ((size_t)by * Wb + bx0 + b) * 2;
     mv[0] = (int8_t)dx;
     mv[1] = (int8_t)dy;
+    if (job.sad) job.sad[(size_t)by * Wb + bx0 + b] = (uint32_t)(key >> keyshift_sad);
   }
 }
 
@@ -968,6 +970,60 @@ MeGeom me_default_geometry(int N, int R, int max_nb) {
     }
   }
   return best;
+}
+
+// ---- adaptive block size: whole or split ---------------------------------
+// One thread per block of a P step: J = 16 SAD + lambda16 bits for the whole
+// block (size-N search) and summed over its four N/2 cells (size-N/2
+// search, z-order), bits = Exp-Golomb lengths of each vector against zero;
+// split iff the cells cost less.  Whole blocks repeat their vector over
+// their cells, so the cell grid then holds every block's final vectors.
+namespace {
+
+constexpr int kDecideThreads = 256;
+
+__device__ inline uint32_t se_len(int v) {
+  return v ? 65u - 2u * (uint32_t)__builtin_clz((uint32_t)abs(v)) : 1u;
+}
+
+__global__ void __launch_bounds__(kDecideThreads) split_decide_kernel(const LaunchDesc d, int N) {
+  int tl;
+  const FrameJob* jp = desc_job(d, (int)blockIdx.x, tl);
+  const int Hb = jp->Hp / N, Wb = jp->Wp / N;
+  const int ci = tl * kDecideThreads + (int)threadIdx.x;
+  if (ci >= Hb * Wb) return;
+  const int by = ci / Wb, bx = ci - by * Wb;
+  const int Wu = 2 * Wb;
+  int8_t* mv = jp->mv;
+  const uint64_t lam = (uint32_t)jp->lambda16;
+  const int vx = jp->mv_whole[2 * ci], vy = jp->mv_whole[2 * ci + 1];
+  const uint64_t jw = 16ull * jp->sad_whole[ci] + lam * (se_len(vx) + se_len(vy));
+  uint64_t js = 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int u = (2 * by + (i >> 1)) * Wu + 2 * bx + (i & 1);
+    js += 16ull * jp->sad[u] + lam * (se_len(mv[2 * u]) + se_len(mv[2 * u + 1]));
+  }
+  const bool split = js < jw;
+  jp->split[ci] = split ? 1 : 0;
+  if (!split) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int u = (2 * by + (i >> 1)) * Wu + 2 * bx + (i & 1);
+      mv[2 * u] = (int8_t)vx;
+      mv[2 * u + 1] = (int8_t)vy;
+    }
+  }
+}
+
+}  // namespace
+
+int split_tiles_per_job(int Hb, int Wb) { return (Hb * Wb + kDecideThreads - 1) / kDecideThreads; }
+
+hipError_t launch_split_decide(int N, const LaunchDesc& r, hipStream_t s) {
+  if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
+  split_decide_kernel<<<r.tiles, kDecideThreads, 0, s>>>(r, N);
+  return hipGetLastError();
 }
 
 int me_tiles_per_job(int Hb, int Wb, const MeGeom& g) {

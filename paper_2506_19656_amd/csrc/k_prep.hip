@@ -970,7 +970,14 @@ __global__ void plan_kernel(CubePlan p) {
   jb.ref = s > 0 ? p.recon + (f - 1) * 3 * plane : nullptr;
   jb.rec = p.recon + f * 3 * plane;
   jb.lev = p.lev + f * 3 * (int64_t)Hb * Wb * p.N * p.N;
-  jb.mv = p.mv + f * (int64_t)Hb * Wb * 2;
+  // vectors per frame: one per block, or one per N/2 cell with split flags
+  const int64_t mvf = (p.split ? 4 : 1) * (int64_t)Hb * Wb;
+  jb.mv = p.mv + f * mvf * 2;
+  jb.split = p.split ? p.split + f * (int64_t)Hb * Wb : nullptr;
+  jb.sad = p.sad_cell ? p.sad_cell + f * mvf : nullptr;
+  jb.mv_whole = p.mv_whole ? p.mv_whole + f * (int64_t)Hb * Wb * 2 : nullptr;
+  jb.sad_whole = p.sad_whole ? p.sad_whole + f * (int64_t)Hb * Wb : nullptr;
+  jb.lambda16 = p.lambda16;
   jb.cbits = p.cbits ? p.cbits + f * 3 * (int64_t)Hb * Wb : nullptr;
   jb.mbits = p.mbits ? p.mbits + f * (int64_t)Hb * Wb : nullptr;
   jb.vmask = p.vmask ? p.vmask + f * 3 * plane : nullptr;
@@ -990,6 +997,14 @@ __global__ void plan_kernel(CubePlan p) {
   jb.bit_depth = p.bit_depth;
   jb.qp = p.qp;
   p.jobs[i] = jb;
+  if (p.jobs_whole) {
+    // the size-N search of the adaptive block size writes here
+    FrameJob jw = jb;
+    jw.mv = jb.mv_whole;
+    jw.sad = jb.sad_whole;
+    jw.split = nullptr;
+    p.jobs_whole[i] = jw;
+  }
 }
 
 inline int grid_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }

@@ -476,7 +476,8 @@ __device__ inline void inverse_row(const int16_t* Erow, const uint32_t (&pp)[N /
   }
 }
 
-// Rate proxy of every block of channel c in the tile (one wave per channel).
+// Rate proxy of every coded block of channel c in the tile (one wave per
+// channel; bit b of `coded` set for block b).
 // The tile holds w = 2|level| + 1.  Lane (b, j) takes scan positions jN ..
 // jN+N-1 of block b.  Each nonzero level at position p with previous nonzero
 // q (-1 if none) costs ue(p-q-1) + se(level) = 128 - 2 (clz(p - q) +
@@ -485,10 +486,10 @@ __device__ inline void inverse_row(const int16_t* Erow, const uint32_t (&pp)[N /
 // replaces that term once the last nonzero of the earlier segments is known.
 // Adds 2^17 * count + sum of clz terms to s.cbits[c][b].
 template <int N>
-__device__ inline void block_bits(LdsEnc<N>& s, const TileCoord& tc, int c) {
+__device__ inline void block_bits(LdsEnc<N>& s, uint32_t coded, int c) {
   const int lane = threadIdx.x & 63;
   const int b = lane / N, j = lane - b * N;
-  const bool vb = (tc.bx0 + b) < tc.Wb;
+  const bool vb = (coded >> b) & 1u;
   const char* tile = (const char*)&s.TD[c][b][0][0];
   uint32_t acc = 0;
   int prev = -1, first = N;
@@ -576,7 +577,43 @@ __device__ inline uint32_t row_sse(const uint32_t (&cp)[N / 2], const uint32_t (
   return (uint32_t)sse;
 }
 
-template <int N>
+// Adaptive block size roles (kRole): 0 -- no split flags; 1 -- size-N
+// kernel, codes the whole blocks (all blocks of an I step), writes every
+// block's vector bits and zero coefficient bits for split blocks; 2 --
+// size-N/2 kernel over the cell grid, codes the cells of split blocks into
+// their block's level slot (z-order) and adds their coefficient bits to
+// their block's.
+template <int kRole>
+__device__ inline bool split_codes(const FrameJob& job, int by, int bx, int Wb) {
+  if constexpr (kRole == 1) return job.intra || !job.split[by * Wb + bx];
+  if constexpr (kRole == 2) return !job.intra && job.split[(by >> 1) * (Wb >> 1) + (bx >> 1)];
+  return true;
+}
+
+// Level offset (elements) of column k of block (by, bx), channel c: blocks
+// are [3][Hb][Wb][N*N]; a cell of a split block sits at z-position
+// 2 (by & 1) + (bx & 1) inside its block's (2N)^2 slot.
+template <int N, int kRole>
+__device__ inline uint32_t level_offset(int c, int by, int bx, int Hb, int Wb, int k) {
+  if constexpr (kRole == 2) {
+    const uint32_t blk2 = (uint32_t)((by >> 1) * (Wb >> 1) + (bx >> 1));
+    const uint32_t z = (uint32_t)(((by & 1) << 1) | (bx & 1));
+    return ((uint32_t)c * (uint32_t)(Hb >> 1) * (uint32_t)(Wb >> 1) + blk2) * (4 * N * N) + z * (N * N) +
+           (uint32_t)(k * N);
+  }
+  return ((uint32_t)c * (uint32_t)Hb * (uint32_t)Wb + (uint32_t)(by * Wb + bx)) * (N * N) +
+         (uint32_t)(k * N);
+}
+
+// Vector entry of block (by, bx): the block's own, or with split flags
+// (role 1) its top-left cell on the cell grid.
+template <int kRole>
+__device__ inline uint32_t vector_index(int by, int bx, int Wb) {
+  if constexpr (kRole == 1) return (uint32_t)(2 * by * 2 * Wb + 2 * bx);
+  return (uint32_t)(by * Wb + bx);
+}
+
+template <int N, int kRole>
 __global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(Tile<N>::kEncWaves)))
 encode_kernel(const LaunchDesc jr) {
   constexpr int NBW = Tile<N>::NBW;
@@ -594,7 +631,8 @@ encode_kernel(const LaunchDesc jr) {
   const int r = rem / NBW;      // block row (row stages) / column (column stages)
   const int b = rem - r * NBW;
   const int bx = tc.bx0 + b;
-  const bool vb = bx < tc.Wb;
+  const bool vb = bx < tc.Wb;                                   // the block exists
+  const bool code = vb && split_codes<kRole>(job, tc.by, bx, tc.Wb);  // this kernel codes it
   const int B = job.bit_depth;
   const int x0 = bx * N;
   const int y = tc.by * N + r;
@@ -606,14 +644,16 @@ encode_kernel(const LaunchDesc jr) {
     s.mvbits = 0u;
     s.cbsum = 0u;
   }
+  // coded blocks of the tile, bit b (lanes 0 .. NBW-1 are r = 0)
+  const uint32_t coded = (uint32_t)__ballot(code) & ((1u << NBW) - 1u);
 
   int dx = 0, dy = 0;
-  if (vb && !job.intra) load_mv(job.mv, 2u * blk, dx, dy);
+  if (code && !job.intra) load_mv(job.mv, 2u * vector_index<kRole>(tc.by, bx, tc.Wb), dx, dy);
 
   // Forward row stage of row r: T[y][k] = (sum_x M[k][x] res[x] + 2^(s1-1)) >> s1,
   // stored transposed.
   uint32_t cp[N / 2], pp[N / 2];
-  if (vb) {
+  if (code) {
     load_row_packed<N>(job.cur, 2u * row_off, cp);
     pred_row<N>(job, c, r, y, x0, dx, dy, pp);
     uint32_t er[N / 2];
@@ -635,7 +675,7 @@ encode_kernel(const LaunchDesc jr) {
   const Dequant dqp = dequant_params(qP, B + L2N - 5);
   int lv[N];
   bool lane_nz = false;
-  if (vb) {
+  if (code) {
     const int qbits = 29 + qP / 6 - B - L2N;
     const int off = (job.intra ? 171 : 85) << (qbits - 9);
     const int offn = (1 << qbits) - 1 - off;
@@ -661,7 +701,7 @@ encode_kernel(const LaunchDesc jr) {
       const u16x2 a = __builtin_bit_cast(u16x2, __builtin_elementwise_max(v, -v));
       row[m] = __builtin_bit_cast(uint32_t, (u16x2)(a + a + (u16x2){1, 1}));
     }
-    store_row_packed<N>(job.lev, 2u * (((uint32_t)c * tc.Hb * tc.Wb + blk) * (N * N) + k * N), lpair);
+    store_row_packed<N>(job.lev, 2u * level_offset<N, kRole>(c, tc.by, bx, tc.Hb, tc.Wb, k), lpair);
     uint32_t any = 0;
 #pragma unroll
     for (int m = 0; m < N / 2; m++) any |= lpair[m];
@@ -673,7 +713,7 @@ encode_kernel(const LaunchDesc jr) {
   // zero residual, so the reconstruction is the prediction, and every block
   // costs its coded-flag bit only.
   const bool wave_nz = __any(lane_nz);
-  if (vb && wave_nz) {
+  if (code && wave_nz) {
     uint32_t dq[N / 2];
     dequant_pairs<N>(lv, dqp, dq);
     inverse_column<N>(dq, s.E[c][b], inv_slot<N>(k));
@@ -681,10 +721,10 @@ encode_kernel(const LaunchDesc jr) {
   __syncthreads();
 
   // Rate proxy per block and channel (levels in TD).
-  if (wave_nz) block_bits<N>(s, tc, c);
+  if (wave_nz) block_bits<N>(s, coded, c);
 
   // Inverse row stage, reconstruction, squared error.
-  if (vb) {
+  if (code) {
     uint32_t rp[N / 2];
     if (wave_nz) {
       inverse_row<N>(s.E[c][b][r], pp, B, rp);
@@ -700,41 +740,90 @@ encode_kernel(const LaunchDesc jr) {
     }
   }
 
-  if (c == 0 && r == 0 && vb) {
-    uint32_t bits = 0;
-    if (job.intra) {
-      // an intra mode (written by the wavefront kernel) costs one bit
-      if (job.imode)
-        bits = 1u;
-      else
-        gst<uint16_t>(job.mv, 2u * blk, (uint16_t)0);
-    } else {
-      int pmx = 0, pmy = 0;
-      if (bx > 0) load_mv(job.mv, 2u * (blk - 1), pmx, pmy);
-      // se(v) costs 2 floor(log2 |v|) + 3 bits, 1 for v = 0
-      const int ex = dx - pmx, ey = dy - pmy;
-      bits = (ex ? 65u - 2u * (uint32_t)__builtin_clz((uint32_t)abs(ex)) : 1u) +
-             (ey ? 65u - 2u * (uint32_t)__builtin_clz((uint32_t)abs(ey)) : 1u);
+  // se(v) costs 2 floor(log2 |v|) + 3 bits, 1 for v = 0
+  auto se_len = [](int v) { return v ? 65u - 2u * (uint32_t)__builtin_clz((uint32_t)abs(v)) : 1u; };
+  if constexpr (kRole == 0) {
+    if (c == 0 && r == 0 && vb) {
+      uint32_t bits = 0;
+      if (job.intra) {
+        // an intra mode (written by the wavefront kernel) costs one bit
+        if (job.imode)
+          bits = 1u;
+        else
+          gst<uint16_t>(job.mv, 2u * blk, (uint16_t)0);
+      } else {
+        int pmx = 0, pmy = 0;
+        if (bx > 0) load_mv(job.mv, 2u * (blk - 1), pmx, pmy);
+        bits = se_len(dx - pmx) + se_len(dy - pmy);
+      }
+      gst<uint32_t>(job.mbits, 4u * blk, bits);
+      if (bits) atomicAdd(&s.mvbits, bits);
     }
-    gst<uint32_t>(job.mbits, 4u * blk, bits);
-    if (bits) atomicAdd(&s.mvbits, bits);
+  } else if constexpr (kRole == 1) {
+    // every block's vector unit: I -- nothing (flags and cells zeroed);
+    // P -- the split flag, then per coded vector (one, or four in z-order) se
+    // of its difference to the vector of the cell left of its top-left cell
+    if (c == 0 && r == 0 && vb) {
+      const uint32_t Wu = 2u * (uint32_t)tc.Wb;
+      const uint32_t u0 = vector_index<1>(tc.by, bx, tc.Wb);
+      uint32_t bits = 0;
+      if (job.intra) {
+        job.split[blk] = 0;
+        gst<uint16_t>(job.mv, 2u * u0, (uint16_t)0);
+        gst<uint16_t>(job.mv, 2u * (u0 + 1), (uint16_t)0);
+        gst<uint16_t>(job.mv, 2u * (u0 + Wu), (uint16_t)0);
+        gst<uint16_t>(job.mv, 2u * (u0 + Wu + 1), (uint16_t)0);
+      } else {
+        const bool sp = job.split[blk] != 0;
+        bits = 1u;
+        for (int i = 0; i < (sp ? 4 : 1); i++) {
+          const uint32_t u = u0 + (uint32_t)(i >> 1) * Wu + (uint32_t)(i & 1);
+          const bool first_col = bx == 0 && (i & 1) == 0;
+          int mx, my, pmx = 0, pmy = 0;
+          load_mv(job.mv, 2u * u, mx, my);
+          if (!first_col) load_mv(job.mv, 2u * (u - 1), pmx, pmy);
+          bits += se_len(mx - pmx) + se_len(my - pmy);
+        }
+      }
+      gst<uint32_t>(job.mbits, 4u * blk, bits);
+      if (bits) atomicAdd(&s.mvbits, bits);
+    }
   }
   __syncthreads();
   if (t < 3 * NBW) {
     const int cc = t / NBW, bb = t - cc * NBW;
-    if (tc.bx0 + bb < tc.Wb) {
+    const int bxx = tc.bx0 + bb;
+    if (bxx < tc.Wb) {
       // bits = 1 (coded flag) + [nnz > 0] (ue(nnz - 1) + 128 nnz - 2 sum clz)
       const uint32_t v = s.cbits[cc][bb];
       const uint32_t nnz = v >> 17, sum = v & 0x1ffffu;
+      const bool cb = (coded >> bb) & 1u;
       const uint32_t bits =
-          1u + (nnz > 0 ? 63u - 2u * (uint32_t)__builtin_clz(nnz) + 128u * nnz - 2u * sum : 0u);
-      gst<uint32_t>(job.cbits, 4u * (((uint32_t)cc * tc.Hb + tc.by) * tc.Wb + tc.bx0 + bb), bits);
-      atomicAdd(&s.cbsum, bits);  // 3 * 64 * N coefficients of < 64 bits: no overflow
+          cb ? 1u + (nnz > 0 ? 63u - 2u * (uint32_t)__builtin_clz(nnz) + 128u * nnz - 2u * sum : 0u)
+             : 0u;
+      if constexpr (kRole == 2) {
+        // a cell adds to its block's count (zeroed by the size-N kernel)
+        if (cb) {
+          const uint32_t Wb2 = (uint32_t)tc.Wb >> 1;
+          atomicAdd(job.cbits + ((uint32_t)cc * ((uint32_t)tc.Hb >> 1) + (uint32_t)(tc.by >> 1)) * Wb2 +
+                        (uint32_t)(bxx >> 1),
+                    bits);
+        }
+      } else {
+        gst<uint32_t>(job.cbits, 4u * (((uint32_t)cc * tc.Hb + tc.by) * tc.Wb + bxx), bits);
+      }
+      if (bits) atomicAdd(&s.cbsum, bits);  // 3 * 64 * N coefficients of < 64 bits: no overflow
     }
   }
   __syncthreads();
   // this tile's sums; the per-group totals are formed after the last step
-  const uint32_t part = 40u * (uint32_t)tc.tl;
+  // (the size-N/2 kernel's tiles follow the size-N kernel's)
+  uint32_t tile = (uint32_t)tc.tl;
+  if constexpr (kRole == 2) {
+    constexpr int NBW2 = Tile<2 * N>::NBW;
+    tile += (uint32_t)((tc.Hb >> 1) * (((tc.Wb >> 1) + NBW2 - 1) / NBW2));
+  }
+  const uint32_t part = 40u * tile;
   if (t == 0) {
     gst<unsigned long long>(job.part, part + 24, (unsigned long long)s.cbsum);
     gst<unsigned long long>(job.part, part + 32, (unsigned long long)s.mvbits);
@@ -743,7 +832,9 @@ encode_kernel(const LaunchDesc jr) {
 }
 
 // One wave per (tile, channel): workgroup 3 w + c decodes channel c of tile w.
-template <int N>
+// kRole as for the transform kernel: 1 decodes whole blocks, 2 the cells of
+// split blocks.
+template <int N, int kRole>
 __global__ void __launch_bounds__(64) decode_kernel(const LaunchDesc jr) {
   constexpr int NBW = Tile<N>::NBW;
   constexpr int L2N = Tile<N>::L2N;
@@ -757,11 +848,10 @@ __global__ void __launch_bounds__(64) decode_kernel(const LaunchDesc jr) {
   const int r = rem / NBW;
   const int b = rem - r * NBW;
   const int bx = tc.bx0 + b;
-  const bool vb = bx < tc.Wb;
+  const bool vb = bx < tc.Wb && split_codes<kRole>(job, tc.by, bx, tc.Wb);
   const int B = job.bit_depth;
   const int x0 = bx * N;
   const int y = tc.by * N + r;
-  const uint32_t blk = (uint32_t)(tc.by * tc.Wb + bx);
   const uint32_t row_off = ((uint32_t)(c * job.Hp + y) * (uint32_t)job.Wp + (uint32_t)x0);
 
   uint32_t pp[N / 2];
@@ -769,9 +859,9 @@ __global__ void __launch_bounds__(64) decode_kernel(const LaunchDesc jr) {
   const int k = r;  // column k = r of the block: its N levels are contiguous
   bool lane_nz = false;
   if (vb) {
-    load_row_packed<N>(job.lev, 2u * (((uint32_t)c * tc.Hb * tc.Wb + blk) * (N * N) + k * N), lp);
+    load_row_packed<N>(job.lev, 2u * level_offset<N, kRole>(c, tc.by, bx, tc.Hb, tc.Wb, k), lp);
     int dx = 0, dy = 0;
-    if (!job.intra) load_mv(job.mv, 2u * blk, dx, dy);
+    if (!job.intra) load_mv(job.mv, 2u * vector_index<kRole>(tc.by, bx, tc.Wb), dx, dy);
     pred_row<N>(job, c, r, y, x0, dx, dy, pp);
     uint32_t any = 0;
 #pragma unroll
@@ -1048,14 +1138,14 @@ hipError_t launch_intra_t(const LaunchDesc& d, int wave, int decode, hipStream_t
   return hipGetLastError();
 }
 
-template <int N>
+template <int N, int kRole = 0>
 hipError_t launch_encode_t(const LaunchDesc& d, hipStream_t s) {
-  encode_kernel<N><<<d.tiles, 192, 0, s>>>(d);
+  encode_kernel<N, kRole><<<d.tiles, 192, 0, s>>>(d);
   return hipGetLastError();
 }
-template <int N>
+template <int N, int kRole = 0>
 hipError_t launch_decode_t(const LaunchDesc& d, hipStream_t s) {
-  decode_kernel<N><<<3u * (unsigned)d.tiles, 64, 0, s>>>(d);
+  decode_kernel<N, kRole><<<3u * (unsigned)d.tiles, 64, 0, s>>>(d);
   return hipGetLastError();
 }
 
@@ -1093,6 +1183,48 @@ hipError_t launch_intra(int N, const LaunchDesc& r, int wave, int decode, hipStr
     case 32: return launch_intra_t<32>(r, wave, decode, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_encode_split(int N, int role, const LaunchDesc& r, hipStream_t s) {
+  if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
+  if (role == 1) {
+    switch (N) {
+      case 8: return launch_encode_t<8, 1>(r, s);
+      case 16: return launch_encode_t<16, 1>(r, s);
+      case 32: return launch_encode_t<32, 1>(r, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (role == 2) {
+    switch (N) {
+      case 4: return launch_encode_t<4, 2>(r, s);
+      case 8: return launch_encode_t<8, 2>(r, s);
+      case 16: return launch_encode_t<16, 2>(r, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_decode_split(int N, int role, const LaunchDesc& r, hipStream_t s) {
+  if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
+  if (role == 1) {
+    switch (N) {
+      case 8: return launch_decode_t<8, 1>(r, s);
+      case 16: return launch_decode_t<16, 1>(r, s);
+      case 32: return launch_decode_t<32, 1>(r, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (role == 2) {
+    switch (N) {
+      case 4: return launch_decode_t<4, 2>(r, s);
+      case 8: return launch_decode_t<8, 2>(r, s);
+      case 16: return launch_decode_t<16, 2>(r, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_decode(int N, const LaunchDesc& r, hipStream_t s) {

@@ -45,10 +45,12 @@ int check_params(const xv_params* p) {
   if (p->gop < 1) return fail(XV_EINVAL, "gop must be >= 1");
   if (p->pad_mode != XV_PAD_ZERO && p->pad_mode != XV_PAD_REPEAT) return fail(XV_EINVAL, "bad pad_mode");
   if (p->fill_mode != XV_FILL_NEAREST && p->fill_mode != XV_FILL_FORWARD) return fail(XV_EINVAL, "bad fill_mode");
-  if (p->flags & ~(XV_FLAG_DROP_WORK | XV_FLAG_QPEL | XV_FLAG_INTRA))
+  if (p->flags & ~(XV_FLAG_DROP_WORK | XV_FLAG_QPEL | XV_FLAG_INTRA | XV_FLAG_SPLIT))
     return fail(XV_EINVAL, "unknown flags");
   if ((p->flags & XV_FLAG_QPEL) && p->search_range > 31)
     return fail(XV_EINVAL, "quarter-sample motion needs search_range <= 31 (int8 vectors)");
+  if ((p->flags & XV_FLAG_SPLIT) && (N < 8 || (p->flags & (XV_FLAG_QPEL | XV_FLAG_INTRA))))
+    return fail(XV_EINVAL, "the adaptive block size needs block >= 8, integer vectors and no intra modes");
   return XV_OK;
 }
 
@@ -70,6 +72,17 @@ void dims_of(xv_encoded* e, const xv_cube* in, const xv_params* p) {
   e->src_dtype = in->dtype;
 }
 
+int tiles_per_frame(const xv_encoded* e) {
+  int t = xf_tiles_per_job(e->N, e->Hb, e->Wb);
+  if (e->p.flags & XV_FLAG_SPLIT) t += xf_tiles_per_job(e->N / 2, 2 * e->Hb, 2 * e->Wb);
+  return t;
+}
+
+int32_t split_lambda16(int qp, int bit_depth) {
+  const int qP = qp + 6 * (bit_depth - 8);
+  return (int32_t)floor(16.0 * sqrt(0.57 * pow(2.0, (qP - 12) / 3.0)) + 0.5);
+}
+
 EncLayout enc_layout(const xv_encoded* e) {
   EncLayout L{};
   const int64_t G = e->G, T = e->T;
@@ -77,9 +90,10 @@ EncLayout enc_layout(const xv_encoded* e) {
   const int64_t nframes = G * T;
   const int64_t nblk = nframes * e->Hb * e->Wb;
   const int64_t bands = e->bands;
+  const bool split = (e->p.flags & XV_FLAG_SPLIT) != 0;
   Carve k;
   L.o_lev = k.take<int16_t>((size_t)nframes * 3 * plane);
-  L.o_mv = k.take<int8_t>((size_t)nblk * 2);
+  L.o_mv = k.take<int8_t>((size_t)nblk * 2 * (split ? 4 : 1));
   L.o_cb = k.take<uint32_t>((size_t)nblk * 3);
   L.o_mb = k.take<uint32_t>((size_t)nblk);
   L.o_keys = k.take<uint32_t>((size_t)bands + 1 + (size_t)kStatsMaxBlocks * 3 * bands);
@@ -87,15 +101,20 @@ EncLayout enc_layout(const xv_encoded* e) {
   L.o_span = k.take<uint64_t>(L.span_words);
   L.phys_nb = phys_blocks(T * e->H * e->W * bands);
   L.o_pp = k.take<double>((size_t)L.phys_nb * bands);
-  L.o_jobs = k.take<FrameJob>((size_t)e->njobs);
+  // with the adaptive block size the size-N search's table follows the main one
+  L.o_jobs = k.take<FrameJob>((size_t)e->njobs * (split ? 2 : 1));
+  L.o_split = split ? k.take<uint8_t>((size_t)nblk) : 0;
   L.keep = k.off;
   Carve w;
   L.o_fr = w.take<uint16_t>((size_t)nframes * 3 * plane);
   L.o_rc = w.take<uint16_t>((size_t)nframes * 3 * plane);
   L.o_vm = e->src_dtype == XV_F32 ? w.take<uint8_t>((size_t)nframes * 3 * plane) : 0;
-  L.o_part = w.take<uint64_t>((size_t)nframes * xf_tiles_per_job(e->N, e->Hb, e->Wb) * 5);
+  L.o_part = w.take<uint64_t>((size_t)nframes * tiles_per_frame(e) * 5);
   L.o_pred = (e->p.flags & (XV_FLAG_QPEL | XV_FLAG_INTRA)) ? w.take<uint8_t>(pred_plane_bytes(e))
                                                            : 0;
+  L.o_mvw = split ? w.take<int8_t>((size_t)nblk * 2) : 0;
+  L.o_sadw = split ? w.take<uint32_t>((size_t)nblk) : 0;
+  L.o_sadc = split ? w.take<uint32_t>((size_t)nblk * 4) : 0;
   L.work = w.off;
   return L;
 }
@@ -135,6 +154,9 @@ void bind_keep(xv_encoded* e, const EncLayout& lay) {
   e->bits = e->sse + 3 * G;
   e->phys_partial = (double*)(kb + lay.o_pp);
   e->jobs = (FrameJob*)(kb + lay.o_jobs);
+  const bool split = (e->p.flags & XV_FLAG_SPLIT) != 0;
+  e->splits = split ? (uint8_t*)(kb + lay.o_split) : nullptr;
+  e->jobs_whole = split ? e->jobs + e->njobs : nullptr;
 }
 
 // Allocates the encoded object and launches stats, pack and plan.
@@ -173,7 +195,11 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   e->vmask = in->dtype == XV_F32 ? (uint8_t*)(wb + o_vm) : nullptr;
   e->tile_part = (unsigned long long*)(wb + o_part);
   e->pred = (p->flags & (XV_FLAG_QPEL | XV_FLAG_INTRA)) ? (uint16_t*)(wb + lay.o_pred) : nullptr;
-  e->tpf = xf_tiles_per_job(e->N, e->Hb, e->Wb);
+  const bool split = (p->flags & XV_FLAG_SPLIT) != 0;
+  e->mv_whole = split ? (int8_t*)(wb + lay.o_mvw) : nullptr;
+  e->sad_whole = split ? (uint32_t*)(wb + lay.o_sadw) : nullptr;
+  e->sad_cell = split ? (uint32_t*)(wb + lay.o_sadc) : nullptr;
+  e->tpf = tiles_per_frame(e);
   *out = e;
 
   const double elb = in->dtype == XV_U16 ? 2.0 : 4.0;
@@ -197,7 +223,8 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
                 e->nan_total, e->tile_part, e->pred, e->jobs, (int32_t)T, e->G, p->gop, e->nsteps,
                 e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)bands, e->N,
                 p->bit_depth, p->qp, e->tpf, (p->flags & XV_FLAG_QPEL) != 0,
-                (p->flags & XV_FLAG_INTRA) != 0};
+                (p->flags & XV_FLAG_INTRA) != 0, e->splits, e->mv_whole, e->sad_whole,
+                e->sad_cell, e->jobs_whole, split ? split_lambda16(p->qp, p->bit_depth) : 0};
     XV_HIP(launch_plan(pl, s), "plan kernel");
   }
   return XV_OK;
@@ -206,8 +233,8 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
 // SAD terms of a motion-search launch: (2R+1)^2 per real-channel sample.
 // SAD terms of one motion-search step: every candidate that keeps the
 // displaced block inside the padded picture, N^2 terms per real channel.
-double me_work(const xv_encoded* e, int s) {
-  const int R = e->p.search_range, N = e->N;
+double me_work(const xv_encoded* e, int s, int n) {
+  const int R = e->p.search_range, N = n > 0 ? n : e->N;
   auto axis = [&](int P) {  // sum over block positions of the admissible displacements
     double tot = 0;
     for (int x0 = 0; x0 + N <= P; x0 += N) tot += std::min(R, P - N - x0) - std::max(-R, -x0) + 1;
@@ -233,31 +260,130 @@ int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s) {
   int maxsteps = 0;
   for (auto* e : es) maxsteps = std::max(maxsteps, e->nsteps);
   for (int st = 0; st < maxsteps; st++) {
-    std::vector<SegSrc> src;
+    // sources with the adaptive block size take their own launches
+    std::vector<SegSrc> src, split;
     for (auto* e : es)
-      if (st < e->nsteps) src.push_back(SegSrc{e, st});
+      if (st < e->nsteps) ((e->p.flags & XV_FLAG_SPLIT) ? split : src).push_back(SegSrc{e, st});
     if (st > 0) {
-      int rc = launch_segments(src, 1, geom, [&](const LaunchDesc& d, double work) {
-        ProfScope ps(XV_K_ME, s, work);
-        XV_HIP(launch_me(N, R, geom, d, s), "motion search kernel");
-        return XV_OK;
-      });
-      if (rc != XV_OK) return rc;
-      uint64_t nl = 0;
-      if ((rc = launch_subpel_step(src, s, &nl)) != XV_OK) return rc;
+      if (!src.empty()) {
+        int rc = launch_segments(src, 1, geom, [&](const LaunchDesc& d, double work) {
+          ProfScope ps(XV_K_ME, s, work);
+          XV_HIP(launch_me(N, R, geom, d, s), "motion search kernel");
+          return XV_OK;
+        });
+        if (rc != XV_OK) return rc;
+        uint64_t nl = 0;
+        if ((rc = launch_subpel_step(src, s, &nl)) != XV_OK) return rc;
+      }
+      if (int rc = launch_split_search(split, s); rc != XV_OK) return rc;
     } else {
       uint64_t nl = 0;
       int rc = launch_intra_step(src, s, &nl);
       if (rc != XV_OK) return rc;
     }
-    int rc = launch_segments(src, 0, geom, [&](const LaunchDesc& d, double work) {
-      ProfScope ps(XV_K_ENCODE, s, work);
-      XV_HIP(launch_encode(N, d, s), "transform kernel");
-      return XV_OK;
-    });
-    if (rc != XV_OK) return rc;
+    if (!src.empty()) {
+      int rc = launch_segments(src, 0, geom, [&](const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_ENCODE, s, work);
+        XV_HIP(launch_encode(N, d, s), "transform kernel");
+        return XV_OK;
+      });
+      if (rc != XV_OK) return rc;
+    }
+    if (int rc = launch_split_transform(split, s); rc != XV_OK) return rc;
   }
   return XV_OK;
+}
+
+int launch_split_search(const std::vector<SegSrc>& src, hipStream_t s) {
+  if (src.empty()) return XV_OK;
+  const int N = src[0].e->N, R = src[0].e->p.search_range;
+  int max_wb = 1;
+  for (auto& x : src) max_wb = std::max(max_wb, x.e->Wb);
+  const MeGeom gw = geometry_for(N, R, max_wb);
+  const MeGeom gc = geometry_for(N / 2, R, 2 * max_wb);
+  // size N: the second job table (vectors and SADs of whole blocks)
+  int rc = launch_chunks(
+      src, [](const SegSrc& x) { return x.e->jobs_whole; },
+      [&](const xv_encoded* e) { return me_tiles_per_job(e->Hb, e->Wb, gw); },
+      [](const SegSrc& x) { return me_work(x.e, x.step); },
+      [&](const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_ME, s, work);
+        XV_HIP(launch_me(N, R, gw, d, s), "motion search kernel (whole blocks)");
+        return XV_OK;
+      });
+  if (rc != XV_OK) return rc;
+  // size N/2: the cells, into the cell grid of the main table
+  rc = launch_chunks(
+      src, [](const SegSrc& x) { return x.e->jobs; },
+      [&](const xv_encoded* e) { return me_tiles_per_job(2 * e->Hb, 2 * e->Wb, gc); },
+      [&](const SegSrc& x) { return me_work(x.e, x.step, N / 2); },
+      [&](const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_ME, s, work);
+        XV_HIP(launch_me(N / 2, R, gc, d, s), "motion search kernel (cells)");
+        return XV_OK;
+      });
+  if (rc != XV_OK) return rc;
+  return launch_chunks(
+      src, [](const SegSrc& x) { return x.e->jobs; },
+      [](const xv_encoded* e) { return split_tiles_per_job(e->Hb, e->Wb); },
+      [](const SegSrc&) { return 0.0; },
+      [&](const LaunchDesc& d, double) {
+        XV_HIP(launch_split_decide(N, d, s), "whole-or-split choice kernel");
+        return XV_OK;
+      });
+}
+
+int launch_split_transform(const std::vector<SegSrc>& src, hipStream_t s) {
+  if (src.empty()) return XV_OK;
+  const int N = src[0].e->N;
+  // the step's algorithmic bytes go with the size-N launch
+  int rc = launch_chunks(
+      src, [](const SegSrc& x) { return x.e->jobs; },
+      [&](const xv_encoded* e) { return xf_tiles_per_job(N, e->Hb, e->Wb); },
+      [](const SegSrc& x) {
+        return xf_frames(x.e, x.step) * 3.0 * x.e->Hp * x.e->Wp * (x.step == 0 ? 6.0 : 8.0);
+      },
+      [&](const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_ENCODE, s, work);
+        XV_HIP(launch_encode_split(N, 1, d, s), "transform kernel (whole blocks)");
+        return XV_OK;
+      });
+  if (rc != XV_OK) return rc;
+  return launch_chunks(
+      src, [](const SegSrc& x) { return x.e->jobs; },
+      [&](const xv_encoded* e) { return xf_tiles_per_job(N / 2, 2 * e->Hb, 2 * e->Wb); },
+      [](const SegSrc&) { return 0.0; },
+      [&](const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_ENCODE, s, work);
+        XV_HIP(launch_encode_split(N / 2, 2, d, s), "transform kernel (cells)");
+        return XV_OK;
+      });
+}
+
+int launch_split_decode(const std::vector<DecSrc>& src, hipStream_t s) {
+  if (src.empty()) return XV_OK;
+  const int N = src[0].e->N;
+  int rc = launch_chunks(
+      src, [](const DecSrc& x) { return x.jobs; },
+      [&](const xv_encoded* e) { return xf_tiles_per_job(N, e->Hb, e->Wb); },
+      [](const DecSrc& x) {
+        return xf_frames(x.e, x.step) * 3.0 * x.e->Hp * x.e->Wp * (x.step == 0 ? 4.0 : 6.0);
+      },
+      [&](const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_DECODE, s, work);
+        XV_HIP(launch_decode_split(N, 1, d, s), "decode kernel (whole blocks)");
+        return XV_OK;
+      });
+  if (rc != XV_OK) return rc;
+  return launch_chunks(
+      src, [](const DecSrc& x) { return x.jobs; },
+      [&](const xv_encoded* e) { return xf_tiles_per_job(N / 2, 2 * e->Hb, 2 * e->Wb); },
+      [](const DecSrc&) { return 0.0; },
+      [&](const LaunchDesc& d, double work) {
+        ProfScope ps(XV_K_DECODE, s, work);
+        XV_HIP(launch_decode_split(N / 2, 2, d, s), "decode kernel (cells)");
+        return XV_OK;
+      });
 }
 
 // After the last step: per-group totals from the per-tile sums, then the
@@ -270,6 +396,9 @@ int finish_encode(xv_encoded* e) {
     e->work = nullptr;
     e->tile_part = nullptr;
     e->pred = nullptr;
+    e->mv_whole = nullptr;
+    e->sad_whole = nullptr;
+    e->sad_cell = nullptr;
     e->frames = nullptr;
     e->recon = nullptr;
     e->vmask = nullptr;
@@ -302,14 +431,20 @@ int decode_prepare(const xv_encoded* e, hipStream_t s, DecodeBuf& db) {
   CubePlan pl{nullptr, db.recon, e->levels, e->mvs, nullptr, nullptr, nullptr, nullptr,
               nullptr, db.pred, db.jobs, (int32_t)e->T, e->G, e->p.gop, e->nsteps,
               e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)e->bands, e->N,
-              e->p.bit_depth, e->p.qp, 0, qpel, (e->p.flags & XV_FLAG_INTRA) != 0};
+              e->p.bit_depth, e->p.qp, 0, qpel, (e->p.flags & XV_FLAG_INTRA) != 0,
+              e->splits, nullptr, nullptr, nullptr, nullptr, 0};
   XV_HIP(launch_plan(pl, s), "plan kernel");
   return XV_OK;
 }
 
 
 // One launch per chunk of segments; each source brings its own step.
-int decode_launch(const std::vector<DecSrc>& src, hipStream_t s) {
+// Sources with the adaptive block size take their own launches.
+int decode_launch(const std::vector<DecSrc>& all, hipStream_t s) {
+  if (all.empty()) return XV_OK;
+  std::vector<DecSrc> src, split;
+  for (auto& x : all) ((x.e->p.flags & XV_FLAG_SPLIT) ? split : src).push_back(x);
+  if (int rc = launch_split_decode(split, s); rc != XV_OK) return rc;
   if (src.empty()) return XV_OK;
   const int N = src[0].e->N;
   size_t i = 0;
@@ -773,6 +908,7 @@ int xv_encoded_export(const xv_encoded* e, xv_export* v) {
   v->band_max = e->mx;
   v->sse = (const uint64_t*)e->sse;
   v->n_valid = (const uint64_t*)e->nvalid;
+  v->splits = e->splits;
   return XV_OK;
 }
 

@@ -47,6 +47,7 @@ int xv_pack(const xv_encoded* e, void* hip_stream, xv_packed** out) {
   a.mbits = e->mbits;
   a.levels = e->levels;
   a.mvs = e->mvs;
+  a.splits = e->splits;
   const int64_t nb = bits_scan_blocks(a.nunits);
   void* scratch = nullptr;
   XV_HIP(dev_alloc(&scratch, (size_t)(nb + 1) * 8, s), "device allocation of the scan buffer");
@@ -196,6 +197,7 @@ int xv_unpack(const void* data, uint64_t bytes, void* hip_stream, xv_encoded** o
   a.mvs_out = e->mvs;
   a.cbits_out = e->cbits;
   a.mbits_out = e->mbits;
+  a.splits_out = e->splits;
   a.err = (uint32_t*)err;
   const int64_t lev_words = (int64_t)e->G * e->T * 3 * e->Hp * e->Wp / 2;
   uint32_t herr = 0;

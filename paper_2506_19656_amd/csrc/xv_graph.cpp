@@ -70,8 +70,8 @@ std::vector<int64_t> dims_key(const std::vector<const xv_encoded*>& es) {
   std::vector<int64_t> d;
   for (const xv_encoded* e : es) {
     const int64_t v[] = {e->T, e->G, e->p.gop, e->Hp, e->Wp, e->N, e->p.search_range,
-                         (int64_t)(e->p.flags & (XV_FLAG_QPEL | XV_FLAG_INTRA)), e->nsteps,
-                         e->njobs};
+                         (int64_t)(e->p.flags & (XV_FLAG_QPEL | XV_FLAG_INTRA | XV_FLAG_SPLIT)),
+                         e->nsteps, e->njobs};
     d.insert(d.end(), v, v + 10);
   }
   return d;
@@ -156,19 +156,27 @@ int encode_steps_graph(std::vector<xv_encoded*>& es, hipStream_t s) {
   for (auto* e : es) max_wb = std::max(max_wb, e->Wb);
   GraphKey key{0, s, geometry_for(es[0]->N, es[0]->p.search_range, max_wb),
                dims_key(std::vector<const xv_encoded*>(es.begin(), es.end()))};
+  // with the adaptive block size the size-N search's table follows the main
+  // one and is refreshed with it
   std::vector<size_t> bytes;
-  for (auto* e : es) bytes.push_back((size_t)e->njobs * sizeof(FrameJob));
+  for (auto* e : es)
+    bytes.push_back((size_t)e->njobs * sizeof(FrameJob) * (e->jobs_whole ? 2 : 1));
   return replay(
       key, bytes, [&](size_t i) { return (const void*)es[i]->jobs; },
       [&](const std::vector<FrameJob*>& fixed, hipStream_t cs) {
-        // the step loop with every cube's job table at its fixed address
-        std::vector<FrameJob*> own;
+        // the step loop with every cube's job tables at their fixed addresses
+        std::vector<FrameJob*> own, own_whole;
         for (size_t i = 0; i < es.size(); i++) {
           own.push_back(es[i]->jobs);
+          own_whole.push_back(es[i]->jobs_whole);
           es[i]->jobs = fixed[i];
+          if (es[i]->jobs_whole) es[i]->jobs_whole = fixed[i] + es[i]->njobs;
         }
         const int rc = encode_steps(es, cs);
-        for (size_t i = 0; i < es.size(); i++) es[i]->jobs = own[i];
+        for (size_t i = 0; i < es.size(); i++) {
+          es[i]->jobs = own[i];
+          es[i]->jobs_whole = own_whole[i];
+        }
         return rc;
       },
       s);

@@ -48,6 +48,14 @@ struct xv_encoded {
   double* phys_partial;      // [phys_blocks][bands]
   int phys_nb;
   xv::FrameJob* jobs;
+  // adaptive block size (XV_FLAG_SPLIT), else null: split flags [G][T][Hb][Wb]
+  // and the size-N search's job table, jobs + njobs (keep); its vectors and
+  // SADs and the cells' SADs (work)
+  uint8_t* splits;
+  xv::FrameJob* jobs_whole;
+  int8_t* mv_whole;
+  uint32_t* sad_whole;
+  uint32_t* sad_cell;
 };
 
 namespace xv {
@@ -107,20 +115,32 @@ void dims_of(xv_encoded* e, const xv_cube* in, const xv_params* p);
 // statistics, metric span, job table) and "work" (converted frames,
 // reconstruction, validity bytes).  Offsets in bytes.
 struct EncLayout {
-  size_t o_lev, o_mv, o_cb, o_mb, o_keys, o_span, o_pp, o_jobs, keep;
-  size_t o_fr, o_rc, o_vm, o_part, o_pred, work;
+  size_t o_lev, o_mv, o_cb, o_mb, o_keys, o_span, o_pp, o_jobs, o_split, keep;
+  size_t o_fr, o_rc, o_vm, o_part, o_pred, o_mvw, o_sadw, o_sadc, work;
   size_t span_words;
   int phys_nb;
 };
 EncLayout enc_layout(const xv_encoded* e);
+// Transform tiles per frame: the size-N kernel's, plus with the adaptive
+// block size the size-N/2 kernel's (its tile sums follow).
+int tiles_per_frame(const xv_encoded* e);
+// The whole/split cost multiplier in 1/16 SAD units.
+int32_t split_lambda16(int qp, int bit_depth);
 size_t decode_bytes(const xv_encoded* e);
 void bind_keep(xv_encoded* e, const EncLayout& lay);
 int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_encoded** out);
-double me_work(const xv_encoded* e, int s);
+// SAD terms of motion-search step s at block size n (0: the cube's N).
+double me_work(const xv_encoded* e, int s, int n = 0);
 double xf_frames(const xv_encoded* e, int s);
 
 struct SegSrc {
   xv_encoded* e;
+  int step;
+};
+
+struct DecSrc {
+  const xv_encoded* e;
+  xv::FrameJob* jobs;
   int step;
 };
 
@@ -159,6 +179,41 @@ int launch_segments(const std::vector<SegSrc>& src, int tpj_kind, const MeGeom& 
   return XV_OK;
 }
 
+// One launch per chunk of up to kMaxSeg sources, with each source's job
+// table (of step 0), tiles per job and work given by the caller.
+template <class Src, class Jobs, class Tpj, class Work, class F>
+int launch_chunks(const std::vector<Src>& src, Jobs jobs_of, Tpj tpj_of, Work work_of, F launch) {
+  size_t i = 0;
+  while (i < src.size()) {
+    LaunchDesc d;
+    memset(&d, 0, sizeof d);
+    int tiles = 0;
+    double work = 0;
+    for (; i < src.size() && d.nseg < kMaxSeg; i++) {
+      const xv_encoded* e = src[i].e;
+      const int st = src[i].step;
+      Seg& g = d.seg[d.nseg++];
+      g.jobs = jobs_of(src[i]) + plan_step_offset((int)e->T, e->G, e->p.gop, st);
+      g.count = plan_jobs_at((int)e->T, e->G, e->p.gop, st);
+      g.tpj = tpj_of(e);
+      g.tile0 = tiles;
+      tiles += g.count * g.tpj;
+      work += work_of(src[i]);
+    }
+    d.tiles = tiles;
+    int rc = launch(d, work);
+    if (rc != XV_OK) return rc;
+  }
+  return XV_OK;
+}
+
+// Adaptive block size (sources with XV_FLAG_SPLIT, one class): the P step's
+// searches at N and N/2 and the whole-or-split choice; the step's transform
+// coding (size-N kernel, then size-N/2 kernel); the decode of a step.
+int launch_split_search(const std::vector<SegSrc>& src, hipStream_t s);
+int launch_split_transform(const std::vector<SegSrc>& src, hipStream_t s);
+int launch_split_decode(const std::vector<DecSrc>& src, hipStream_t s);
+
 int encode_steps(std::vector<xv_encoded*>& es, hipStream_t s);
 int finish_encode(xv_encoded* e);
 
@@ -173,11 +228,6 @@ struct DecodeBuf {
 };
 int decode_prepare(const xv_encoded* e, hipStream_t s, DecodeBuf& db);
 
-struct DecSrc {
-  const xv_encoded* e;
-  xv::FrameJob* jobs;
-  int step;
-};
 int decode_launch(const std::vector<DecSrc>& src, hipStream_t s);
 // Quarter-sample motion of one frame step: refinement of the integer vectors
 // (encode) or the prediction planes from stored vectors (decode), over the

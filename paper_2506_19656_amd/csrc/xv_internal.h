@@ -36,12 +36,18 @@ struct FrameJob {
                                // with quarter-sample vectors, or the intra prediction
                                // of an I step with intra modes; null: the prediction
                                // is ref displaced (P) or 2^(B-1) (I)
+  uint8_t* split;              // adaptive block size: [Hb][Wb] split flags, else null;
+                               // mv is then the [2 Hb][2 Wb] grid of N/2 cells
+  uint32_t* sad;               // SAD of each searched block's vector, or null
+  int8_t* mv_whole;            // adaptive block size, P steps: the size-N search's
+  uint32_t* sad_whole;         // vectors [Hb][Wb][2] and SADs [Hb][Wb]
   int32_t Hp, Wp, H, W;
   int32_t nch;                 // channels carrying a real band (1..3)
   int32_t intra;               // I picture
   int32_t imode;               // I picture whose blocks are intra-predicted; the mode
                                // is the first byte of the block's vector entry
   int32_t bit_depth, qp;
+  int32_t lambda16;            // adaptive block size: whole/split cost multiplier
 };
 
 constexpr int kMaxSeg = 32;
@@ -88,6 +94,16 @@ struct CubePlan {
   int32_t qpel;                // P steps read their prediction from pred
   int32_t imode;               // I blocks intra-predicted; with pred, the I step's
                                // prediction goes to pred too (encode)
+  // adaptive block size (null / 0 without): split flags [G][T][Hb][Wb], the
+  // size-N search's vectors and SADs [G][T][Hb][Wb], the cells' SADs
+  // [G][T][2 Hb][2 Wb], and a second job table (same order) whose mv / sad
+  // are the size-N ones, for that search
+  uint8_t* split;
+  int8_t* mv_whole;
+  uint32_t* sad_whole;
+  uint32_t* sad_cell;
+  FrameJob* jobs_whole;
+  int32_t lambda16;
 };
 
 // Per-group totals of the per-tile sums, in a fixed order: sse [3G] and
@@ -249,6 +265,19 @@ hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& d, hipStre
 
 int xf_tiles_per_job(int N, int Hb, int Wb);
 hipError_t launch_encode(int N, const LaunchDesc& d, hipStream_t s);
+// Adaptive block size (k_xform.hip).  role 1: the size-N kernel over a
+// step's blocks: codes the whole blocks, writes every block's vector bits
+// (split flag and coded vectors) and zero coefficient bits for split blocks;
+// role 2: the size-N/2 kernel over the N/2 grid (N here is N/2): codes the
+// cells of split blocks, adds their coefficient bits to their block's and
+// writes its tile sums after the size-N kernel's.  Role 1 runs first.
+hipError_t launch_encode_split(int N, int role, const LaunchDesc& d, hipStream_t s);
+hipError_t launch_decode_split(int N, int role, const LaunchDesc& d, hipStream_t s);
+// Whole-or-split choice of every block of a P step (k_me.hip), after the
+// size-N search (mv_whole, sad_whole) and the size-N/2 search (mv, sad on
+// the cell grid): writes split flags and the final cell vectors.
+int split_tiles_per_job(int Hb, int Wb);
+hipError_t launch_split_decide(int N, const LaunchDesc& d, hipStream_t s);
 // Quarter-sample motion (k_subpel.hip): one workgroup per block of a P step.
 // launch_subpel refines the integer vectors in jobs' mv (quarter samples
 // back into mv) and writes the prediction planes; launch_mc writes the
@@ -319,6 +348,11 @@ struct BitsArgs {
   uint32_t* cbits_out;
   uint32_t* mbits_out;
   uint32_t* err;               // (parse) set on an inconsistent stream
+  // adaptive block size: split flags [G][T][Hb][Wb] (pack) / out (parse), else
+  // null; vectors are then on the [2 Hb][2 Wb] cell grid
+  const uint8_t* splits;
+  uint8_t* splits_out;
+  int32_t phase;               // (parse) -1 all segments, 0 vector, 1 coefficient rows
 };
 int64_t bits_scan_blocks(int64_t nunits);
 hipError_t launch_bits_scan(const BitsArgs& a, hipStream_t s);

@@ -147,9 +147,22 @@ int iterate(xv_server* sv, const std::vector<SReq*>& run, uint64_t* launches) {
     int max_wb = 1;
     for (auto& sg : kv.second) max_wb = std::max(max_wb, sg.e->Wb);
     const MeGeom geom = geometry_for(N, R, max_wb);
-    std::vector<SegSrc> p;
-    for (auto& sg : kv.second)
-      if (sg.step > 0) p.push_back(sg);
+    // requests with the adaptive block size take their own launches
+    std::vector<SegSrc> p, all, split, split_p;
+    for (auto& sg : kv.second) {
+      const bool sp = (sg.e->p.flags & XV_FLAG_SPLIT) != 0;
+      (sp ? split : all).push_back(sg);
+      if (sg.step > 0) (sp ? split_p : p).push_back(sg);
+    }
+    if (!split_p.empty()) {
+      if (int rc = launch_split_search(split_p, sv->s); rc != XV_OK) return rc;
+      *launches += 3;
+    }
+    if (!split.empty()) {
+      if (int rc = launch_split_transform(split, sv->s); rc != XV_OK) return rc;
+      *launches += 2;
+    }
+    if (all.empty()) continue;
     if (!p.empty()) {
       int rc = launch_segments(p, 1, geom, [&](const LaunchDesc& d, double work) {
         ProfScope ps(XV_K_ME, sv->s, work);
@@ -160,8 +173,8 @@ int iterate(xv_server* sv, const std::vector<SReq*>& run, uint64_t* launches) {
       if (rc != XV_OK) return rc;
       if ((rc = launch_subpel_step(p, sv->s, launches)) != XV_OK) return rc;
     }
-    if (int rc = launch_intra_step(kv.second, sv->s, launches); rc != XV_OK) return rc;
-    int rc = launch_segments(kv.second, 0, geom, [&](const LaunchDesc& d, double work) {
+    if (int rc = launch_intra_step(all, sv->s, launches); rc != XV_OK) return rc;
+    int rc = launch_segments(all, 0, geom, [&](const LaunchDesc& d, double work) {
       ProfScope ps(XV_K_ENCODE, sv->s, work);
       XV_HIP(launch_encode(N, d, sv->s), "transform kernel");
       ++*launches;

@@ -24,6 +24,7 @@ FILL_NEAREST, FILL_FORWARD = 0, 1
 FLAG_DROP_WORK = 1
 FLAG_QPEL = 2
 FLAG_INTRA = 4
+FLAG_SPLIT = 8
 ME_COLUMN_PAIRS, ME_ROW_PAIRS, ME_ROW_PAIRS_BY_CHANNEL = 1, 2, 3
 MAX_BANDS, MAX_GROUPS = 64, 22
 K_STATS, K_PACK, K_ME, K_ENCODE, K_DECODE, K_DENORM, K_METRICS, K_BITS_WRITE, K_BITS_PARSE, \
@@ -66,7 +67,7 @@ class ExportC(C.Structure):
                 ("reserved", C.c_int32), ("frames", C.c_void_p), ("recon", C.c_void_p),
                 ("levels", C.c_void_p), ("mvs", C.c_void_p), ("coef_bits", C.c_void_p),
                 ("mv_bits", C.c_void_p), ("band_min", C.c_void_p), ("band_max", C.c_void_p),
-                ("sse", C.c_void_p), ("n_valid", C.c_void_p)]
+                ("sse", C.c_void_p), ("n_valid", C.c_void_p), ("splits", C.c_void_p)]
 
 
 class MeGeometryC(C.Structure):
@@ -270,7 +271,11 @@ class Encoded:
         # stored column-major inside a block ([k][l]); presented as [l][k]
         lev = view(v.levels, (G, T, 3, Hb, Wb, N, N), "<i2")
         out["levels"] = None if lev is None else lev.transpose(-1, -2)
-        out["mvs"] = view(v.mvs, (G, T, Hb, Wb, 2), "|i1")
+        out["levels_raw"] = lev
+        # adaptive block size: split flags, vectors on the N/2 cell grid
+        out["splits"] = view(v.splits, (G, T, Hb, Wb), "|i1")
+        m = 2 if v.splits else 1
+        out["mvs"] = view(v.mvs, (G, T, m * Hb, m * Wb, 2), "|i1")
         out["coef_bits"] = view(v.coef_bits, (G, T, 3, Hb, Wb), "<i4")
         out["mv_bits"] = view(v.mv_bits, (G, T, Hb, Wb), "<i4")
         out["band_min"] = view(v.band_min, (Bn,), "<f8")
@@ -291,6 +296,17 @@ class Encoded:
         for k, ty in types.items():
             t = ex[k]
             out[k] = None if t is None else t.cpu().numpy().view(ty)
+        if ex["splits"] is not None:
+            # a split block's slot holds its four N/2 blocks (z-order), each
+            # column-major: present each as [l][k], one after another
+            sp = ex["splits"].cpu().numpy().view(np.uint8)
+            out["splits"] = sp
+            raw = ex["levels_raw"].cpu().numpy().view(np.int16)
+            N = raw.shape[-1]
+            h = N // 2
+            flat = raw.reshape(*raw.shape[:-2], 4, h, h).swapaxes(-1, -2).reshape(raw.shape)
+            mask = sp.astype(bool)[:, :, None, :, :, None, None]
+            out["levels"] = np.where(mask, flat, out["levels"])
         return out
 
     def free(self):

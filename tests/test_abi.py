@@ -49,7 +49,7 @@ def _cube(xv, data=1 << 20, dtype=0, T=4, H=16, W=16, Bn=3):
                                          ("block", 64), ("qp", 52), ("qp", -13),
                                          ("search_range", 65), ("search_range", -1),
                                          ("gop", 0), ("pad_mode", 2), ("fill_mode", 5),
-                                         ("flags", 8)])
+                                         ("flags", 16)])
 def test_invalid_params_are_rejected_before_any_device_work(xvmod, field, value):
     p = xvmod.Params(bit_depth=10, qp=27, block=8, search_range=8, gop=16)
     setattr(p, field, value)

@@ -22,7 +22,8 @@ def _oparams(p: xv.Params) -> O.CodingParams:
     return O.CodingParams(bit_depth=p.bit_depth, qp=p.qp, block=p.block,
                           search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
                           fill_mode=p.fill_mode, qpel=1 if p.flags & xv.FLAG_QPEL else 0,
-                          intra=1 if p.flags & xv.FLAG_INTRA else 0)
+                          intra=1 if p.flags & xv.FLAG_INTRA else 0,
+                          split=1 if p.flags & xv.FLAG_SPLIT else 0)
 
 
 def _to_dev(a: np.ndarray) -> torch.Tensor:
@@ -49,6 +50,8 @@ def check_cube(name: str, host: np.ndarray, p: xv.Params, decode_dtypes=("same",
             raise AssertionError(f"{name}: {k} differs in {len(diff)} elements, first at "
                                  f"{diff[0].tolist()}: gpu={got[k][tuple(diff[0])]} "
                                  f"oracle={ref[k][tuple(diff[0])]}")
+    if op.split:
+        assert np.array_equal(got["splits"], ref["splits"]), f"{name}: split flags differ"
     assert np.array_equal(got["band_min"], ref["mn"]) and np.array_equal(got["band_max"], ref["mx"])
     Bn = host.shape[3]
     sse_gpu = [int(got["sse"][3 * (b // 3) + b % 3]) for b in range(Bn)]
@@ -62,7 +65,8 @@ def check_cube(name: str, host: np.ndarray, p: xv.Params, decode_dtypes=("same",
     assert m["coef_bits"] == om["coef_bits"] and m["mv_bits"] == om["mv_bits"]
     assert abs(m["bpppb"] - om["bpppb"]) <= 1e-12 * max(1.0, om["bpppb"])
     # decode: closed loop and the caller's dtype
-    dec_q = O.decode_cube(op, host.shape, ref["levels"], ref["mvs"])
+    dec_q = O.decode_cube(op, host.shape, ref["levels"], ref["mvs"],
+                          ref["splits"] if op.split else None)
     assert np.array_equal(dec_q, ref["recon"])
     for dt in decode_dtypes:
         tdt = cube.dtype if dt == "same" else dt
