@@ -726,6 +726,67 @@ def qpel_bench(xv, torch, synth, steps, warmup, cached, no_tune):
     return out
 
 
+def split_bench(xv, torch, wl, cube, params, runs, steps, cached, no_tune, warmup=1):
+    """Adaptive block size (XV_FLAG_SPLIT) on the headline cube: the same
+    runs, batched, with every P block coded whole or as four N/2 blocks by
+    SAD + lambda * bits: throughput (the second search at N/2 doubles the
+    motion search), the share of split blocks, and PSNR / bpppb.  The N/2
+    search's launch geometry is tuned like the N one (on the same runs at
+    block N/2).  Returns (section, tuning)."""
+    import dataclasses
+    sparams = [xv.Params(bit_depth=p.bit_depth, qp=p.qp, block=p.block,
+                         search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
+                         fill_mode=p.fill_mode, flags=xv.FLAG_SPLIT) for p in params]
+    half = dataclasses.replace(wl, blocks=tuple(b // 2 for b in wl.blocks))
+    hparams = [xv.Params(bit_depth=p.bit_depth, qp=p.qp, block=p.block // 2,
+                         search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
+                         fill_mode=p.fill_mode) for p in params]
+    tuning = tune(xv, half, cube, hparams, cached, no_tune)
+    outs = [torch.empty_like(cube) for _ in sparams]
+    frac = []
+
+    def step(count=False):
+        encs = xv.encode_batch([cube] * len(sparams), sparams)
+        xv.decode_batch(encs, outs)
+        ms = xv.psnr_bpppb_batch([cube] * len(encs), encs)
+        if count:
+            for e in encs:
+                sp = e.export()["splits"]
+                frac.append(float(sp.to(torch.int32).sum().item()) / sp.numel())
+        for e in encs:
+            e.free()
+        return ms
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ms = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    xv.profile_select(None)
+    xv.profile_enable(True)
+    step(count=True)
+    prof = xv.profile_read()
+    xv.profile_enable(False)
+    del outs
+    px_band = wl.px_band * len(sparams)
+    n_i = -(-wl.T // params[0].gop)  # I pictures per stream group
+    return {"workload": describe(wl) + "; P blocks whole or split into four N/2 blocks",
+            "me_geometry_half": tuning,
+            "runs": [f"QP{qp}/N{N}" for qp, N in runs],
+            "value": round(px_band * steps / dt / 1e6, 3),
+            "ms_per_step": round(dt / steps * 1e3, 3),
+            "psnr_db_mean_per_run": [round(sum(m["psnr"]) / len(m["psnr"]), 4) for m in ms],
+            "bpppb_per_run": [round(m["bpppb"], 5) for m in ms],
+            # over all blocks, I pictures (never split) included
+            "split_block_fraction_per_run": [round(f, 4) for f in frac],
+            "split_block_fraction_of_P_blocks": [round(f * wl.T / (wl.T - n_i), 4) for f in frac],
+            "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}}, \
+        tuning
+
+
 def intra_bench(xv, torch, wl, cube, params, runs, steps, warmup=1):
     """Intra-predicted I pictures (XV_FLAG_INTRA) on the headline cube: the
     same runs, batched, with every I block predicted by planar or DC from its
@@ -871,6 +932,8 @@ def main():
                     help="skip the quarter-sample motion section")
     ap.add_argument("--no-intra", action="store_true",
                     help="skip the intra-predicted I pictures section")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the adaptive block size section")
     ap.add_argument("--no-pca", action="store_true",
                     help="skip the principal-components section")
     ap.add_argument("--serve-size", type=int, default=0,
@@ -985,6 +1048,11 @@ def main():
     if not args.no_intra:
         _log("intra-predicted I pictures")
         line["intra"] = intra_bench(xv, torch, wl, cube, params, runs, qsteps)
+    if not args.no_split:
+        _log("adaptive block size")
+        line["split"], t = split_bench(xv, torch, wl, cube, params, runs, max(1, min(args.steps, 3)),
+                                       cached, args.no_tune)
+        all_tuning.update(t)
     if not args.no_pca:
         _log("principal components")
         line["pca"] = pca_bench(xv, torch, wl, cube, max(1, min(args.steps, 3)), 1)
@@ -1010,9 +1078,14 @@ def main():
         _log("serving mix")
         line["served"] = serve_bench(xv, synth, torch)
         free_device(xv, torch)
-    if args.geometry_file and cached is None:
+    # write the geometry file when it was missing, or add the keys tuned now
+    fresh = {k: {f: v[f] for f in v if f != "from_file"}
+             for k, v in all_tuning.items() if not v.get("from_file") and v.get("tuned")}
+    if args.geometry_file and (cached is None or fresh):
+        merged = dict(cached or {})
+        merged.update(fresh if cached is not None else all_tuning)
         with open(args.geometry_file, "w") as f:
-            json.dump(all_tuning, f, indent=1)
+            json.dump(merged, f, indent=1)
     if host is not None:
         _log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(host, wl)
