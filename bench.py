@@ -109,9 +109,10 @@ def describe(wl) -> str:
             f"GOP {wl.gop}, pad {'zero' if wl.pad_mode == 0 else 'repeat'}")
 
 
-def tune(xv, wl, cube, params, cached, no_tune):
+def tune(xv, wl, cube, params, cached, no_tune, max_candidates=0):
     """Motion-search launch geometry per block size, tuned on the first P step
-    of exactly the batch the timed steps launch (outputs never depend on it)."""
+    of exactly the batch the timed steps launch (outputs never depend on it);
+    max_candidates > 0 limits the timed set (the model's best first)."""
     tuning = {}
     R = wl.search_range
     for N in wl.blocks:
@@ -124,7 +125,8 @@ def tune(xv, wl, cube, params, cached, no_tune):
         elif not no_tune:
             _log(f"tuning motion search {wl.name} N={N} R={R}")
             pn = [p for p in params if p.block == N]
-            tuning[key] = dict(xv.autotune_me_batch([cube] * len(pn), pn), tuned=True)
+            tuning[key] = dict(xv.autotune_me_batch([cube] * len(pn), pn,
+                                                    max_candidates=max_candidates), tuned=True)
         else:
             tuning[key] = dict(xv.get_me_geometry(N, R, -(-wl.W // N)), tuned=False)
     return tuning
@@ -741,7 +743,8 @@ def split_bench(xv, torch, wl, cube, params, runs, steps, cached, no_tune, warmu
     hparams = [xv.Params(bit_depth=p.bit_depth, qp=p.qp, block=p.block // 2,
                          search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
                          fill_mode=p.fill_mode) for p in params]
-    tuning = tune(xv, half, cube, hparams, cached, no_tune)
+    # a short tuning (the model's 48 best) keeps this section's cost small
+    tuning = tune(xv, half, cube, hparams, cached, no_tune, max_candidates=48)
     outs = [torch.empty_like(cube) for _ in sparams]
     frac = []
 
@@ -783,8 +786,11 @@ def split_bench(xv, torch, wl, cube, params, runs, steps, cached, no_tune, warmu
             # over all blocks, I pictures (never split) included
             "split_block_fraction_per_run": [round(f, 4) for f in frac],
             "split_block_fraction_of_P_blocks": [round(f * wl.T / (wl.T - n_i), 4) for f in frac],
-            "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]}}, \
-        tuning
+            "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]},
+            # both searches (N and N/2) over their in-picture SAD terms
+            "me_Tterms_per_s": round(prof["me"]["work"] / (prof["me"]["ms"] * 1e-3) / 1e12, 3),
+            "me_frac_sad_peak": round(prof["me"]["work"] / (prof["me"]["ms"] * 1e-3) / 1e12
+                                      / SAD_PEAK_TTERMS, 4)}, tuning
 
 
 def intra_bench(xv, torch, wl, cube, params, runs, steps, warmup=1):
@@ -832,6 +838,8 @@ def intra_bench(xv, torch, wl, cube, params, runs, steps, warmup=1):
     if ip["launches"]:
         out["intra_launches_per_step"] = int(ip["launches"])
         out["intra_GBps"] = round(ip["work"] / (ip["ms"] * 1e-3) / 1e9, 1)
+        # latency-bound small launches: their algorithmic bytes against HBM
+        out["intra_frac_hbm"] = round(ip["work"] / (ip["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     return out
 
 

@@ -28,7 +28,9 @@ KEYS = ("frames", "levels", "mvs", "recon", "coef_bits", "mv_bits")
 def _op(p: xv.Params) -> O.CodingParams:
     return O.CodingParams(bit_depth=p.bit_depth, qp=p.qp, block=p.block,
                           search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
-                          fill_mode=p.fill_mode)
+                          fill_mode=p.fill_mode, qpel=int(bool(p.flags & xv.FLAG_QPEL)),
+                          intra=int(bool(p.flags & xv.FLAG_INTRA)),
+                          split=int(bool(p.flags & xv.FLAG_SPLIT)))
 
 
 def _gpu_unit(enc: xv.Encoded, g: int, t0: int, n: int) -> dict:
@@ -36,7 +38,17 @@ def _gpu_unit(enc: xv.Encoded, g: int, t0: int, n: int) -> dict:
     ex = enc.export()
     types = {"frames": np.uint16, "recon": np.uint16, "levels": np.int16, "mvs": np.int8,
              "coef_bits": np.uint32, "mv_bits": np.uint32}
-    return {k: ex[k][g, t0:t0 + n].cpu().numpy().view(ty) for k, ty in types.items()}
+    out = {k: ex[k][g, t0:t0 + n].cpu().numpy().view(ty) for k, ty in types.items()}
+    if ex["splits"] is not None:
+        # a split block's slot: its four N/2 blocks in z-order, each
+        # column-major; presented like the oracle's, each as [l][k]
+        sp = ex["splits"][g, t0:t0 + n].cpu().numpy().view(np.uint8)
+        raw = ex["levels_raw"][g, t0:t0 + n].cpu().numpy().view(np.int16)
+        N = raw.shape[-1]
+        cells = raw.reshape(*raw.shape[:-2], 4, N // 2, N // 2).swapaxes(-1, -2).reshape(raw.shape)
+        out["levels"] = np.where(sp.astype(bool)[:, None, :, :, None, None], cells, out["levels"])
+        out["splits"] = sp
+    return out
 
 
 def _oracle_units(cube_host, mn, mx, p: xv.Params, units):
@@ -115,7 +127,7 @@ def _unit_decode_reference(cube_host, mn, mx, p: xv.Params, g: int, recon_unit):
     return O.denormalize_cube(full, (n, H, W, Bn), p.block, p.bit_depth, mn, mx, dt)
 
 
-def _whole_unit_parity(name, cube, params, gops):
+def _whole_unit_parity(name, cube, params, gops, groups=None):
     """Both runs of the workload encoded together as the benchmark encodes
     them; for every run, band group and sampled GOP, the whole unit (all of
     its pictures) compared with the oracle, and the decoded cube's samples of
@@ -137,7 +149,7 @@ def _whole_unit_parity(name, cube, params, gops):
         assert [int(v) for v in ex["n_valid"].cpu().numpy()] == [int(v) for v in nv]
     jobs = []
     for i, p in enumerate(params):
-        for g in range(G):
+        for g in (range(G) if groups is None else groups):
             for k in gops:
                 t0 = k * p.gop
                 jobs.append((i, g, t0, min(p.gop, T - t0)))
@@ -147,7 +159,10 @@ def _whole_unit_parity(name, cube, params, gops):
         refs = list(ex.map(lambda j: O.encode_gop(host, mn, mx, op[j[0]], j[1], j[2], j[3]), jobs))
     for (i, g, t0, n), ref in zip(jobs, refs):
         tag = f"{name} QP{params[i].qp} unit g{g} t{t0}+{n}"
-        _compare(tag, _gpu_unit(encs[i], g, t0, n), ref)
+        got = _gpu_unit(encs[i], g, t0, n)
+        _compare(tag, got, ref)
+        if "splits" in got:
+            assert np.array_equal(got["splits"], ref["splits"]), tag
         # the decoded cube on the samples of this unit, whole frames
         dref = _unit_decode_reference(host, mn, mx, params[i], g, ref["recon"])
         b0, b1 = 3 * g, min(Bn, 3 * g + 3)
@@ -165,6 +180,20 @@ def _whole_unit_parity(name, cube, params, gops):
     plain.free()
     for e in encs:
         e.free()
+
+
+@pytest.mark.timeout(900)
+def test_planet_full_size_coding_tools():
+    # intra-predicted I pictures and the adaptive block size on the
+    # benchmark cube, batched as the bench runs them: the last (short) GOP of
+    # band group 1 (NIR and two zero channels) whole, for each tool
+    wl = synth.WORKLOADS["planet"]
+    print(f"[case] planet full {wl.T}x{wl.H}x{wl.W}x{wl.bands}: intra, split", flush=True)
+    cube = synth.planet_cube(device="cuda")
+    params = [xv.Params(bit_depth=wl.bit_depth, qp=qp, block=16, search_range=wl.search_range,
+                        gop=wl.gop, pad_mode=wl.pad_mode, flags=f)
+              for qp, f in ((22, xv.FLAG_INTRA), (32, xv.FLAG_SPLIT))]
+    _whole_unit_parity("planet tools", cube, params, gops=[45], groups=[1])
 
 
 @pytest.mark.timeout(1100)
