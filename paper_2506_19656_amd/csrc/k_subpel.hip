@@ -31,6 +31,9 @@ namespace xv {
 namespace {
 
 // fL[frac][tap] of H.265; tap i weighs the sample at integer offset i - 3.
+// Taps are below 64 in magnitude and the samples they weigh (u16 samples of
+// at most 12 bits, 16-bit filter outputs) fit 24 bits, so every product is a
+// full-rate 24-bit multiply (__mul24) and exact.
 __constant__ int kLuma[4][8] = {{0, 0, 0, 64, 0, 0, 0, 0},
                                 {-1, 4, -10, 58, 17, -5, 1, 0},
                                 {-1, 4, -11, 40, 40, -11, 4, -1},
@@ -96,7 +99,7 @@ __device__ inline void hpass(SpLds<N>& s, int xs, int xo, int fx, int shift1) {
     const int r = rem / N, j = rem - (rem / N) * N;
     int acc = 0;
 #pragma unroll
-    for (int i = 0; i < 8; i++) acc += f[i] * (int)s.win[c][r][j + xo + 1 + i];
+    for (int i = 0; i < 8; i++) acc += __mul24(f[i], (int)s.win[c][r][j + xo + 1 + i]);
     s.hb[xs][c][r][j] = (int16_t)(acc >> shift1);
   }
 }
@@ -115,11 +118,12 @@ __device__ inline int vsample(const SpLds<N>& s, int c, int i, int j, int xs, in
     int acc = 0;
     if (fx) {
 #pragma unroll
-      for (int t = 0; t < 8; t++) acc += kLuma[fy][t] * (int)s.hb[xs][c][i + yo + 1 + t][j];
+      for (int t = 0; t < 8; t++) acc += __mul24(kLuma[fy][t], (int)s.hb[xs][c][i + yo + 1 + t][j]);
       pred = acc >> 6;
     } else {
 #pragma unroll
-      for (int t = 0; t < 8; t++) acc += kLuma[fy][t] * (int)s.win[c][i + yo + 1 + t][j + xo + 4];
+      for (int t = 0; t < 8; t++)
+        acc += __mul24(kLuma[fy][t], (int)s.win[c][i + yo + 1 + t][j + xo + 4]);
       pred = acc >> (B - 8);
     }
   }
@@ -231,8 +235,9 @@ __global__ void __launch_bounds__(sp_threads<N>()) subpel_kernel(const LaunchDes
       s.best[1] = bmy;
     }
     __syncthreads();
-    cx = s.best[0];
-    cy = s.best[1];
+    // the same for every lane: keep it (and the filter choices) scalar
+    cx = __builtin_amdgcn_readfirstlane(s.best[0]);
+    cy = __builtin_amdgcn_readfirstlane(s.best[1]);
     if (st == 0) __syncthreads();  // the next stage overwrites hb and best
   }
   // the winner is one of the last stage's three columns and three rows; the
