@@ -109,26 +109,29 @@ def describe(wl) -> str:
             f"GOP {wl.gop}, pad {'zero' if wl.pad_mode == 0 else 'repeat'}")
 
 
-def tune(xv, wl, cube, params, cached, no_tune, max_candidates=0):
+def tune(xv, wl, cube, params, cached, no_tune, max_candidates=0, split=False):
     """Motion-search launch geometry per block size, tuned on the first P step
     of exactly the batch the timed steps launch (outputs never depend on it);
-    max_candidates > 0 limits the timed set (the model's best first)."""
+    max_candidates > 0 limits the timed set (the model's best first).  split:
+    the adaptive block size's search (params carry FLAG_SPLIT)."""
     tuning = {}
     R = wl.search_range
+    setter = xv.set_me_split_geometry if split else xv.set_me_geometry
+    getter = xv.get_me_split_geometry if split else xv.get_me_geometry
     for N in wl.blocks:
-        key = f"N{N}R{R}"
+        key = f"N{N}R{R}" + ("split" if split else "")
         if cached is not None and key in cached:
             g = cached[key]
-            xv.set_me_geometry(N, R, g["blocks_per_wg"], g["cands_per_lane"], g["threads"],
-                               g.get("rows_per_lane", 0), g.get("layout", 1))
+            setter(N, R, g["blocks_per_wg"], g["cands_per_lane"], g["threads"],
+                   g.get("rows_per_lane", 0), g.get("layout", 1))
             tuning[key] = dict(g, tuned=True, from_file=True)
         elif not no_tune:
-            _log(f"tuning motion search {wl.name} N={N} R={R}")
+            _log(f"tuning motion search {wl.name} N={N} R={R}" + (" (split)" if split else ""))
             pn = [p for p in params if p.block == N]
             tuning[key] = dict(xv.autotune_me_batch([cube] * len(pn), pn,
                                                     max_candidates=max_candidates), tuned=True)
         else:
-            tuning[key] = dict(xv.get_me_geometry(N, R, -(-wl.W // N)), tuned=False)
+            tuning[key] = dict(getter(N, R, -(-wl.W // N)), tuned=False)
     return tuning
 
 
@@ -731,20 +734,14 @@ def qpel_bench(xv, torch, synth, steps, warmup, cached, no_tune):
 def split_bench(xv, torch, wl, cube, params, runs, steps, cached, no_tune, warmup=1):
     """Adaptive block size (XV_FLAG_SPLIT) on the headline cube: the same
     runs, batched, with every P block coded whole or as four N/2 blocks by
-    SAD + lambda * bits: throughput (the second search at N/2 doubles the
-    motion search), the share of split blocks, and PSNR / bpppb.  The N/2
-    search's launch geometry is tuned like the N one (on the same runs at
-    block N/2).  Returns (section, tuning)."""
-    import dataclasses
+    SAD + lambda * bits: throughput (one search serves the blocks and their
+    cells, with four partial sums per candidate; its geometry tuned like the
+    plain search's), the share of split blocks, and PSNR / bpppb.  Returns
+    (section, tuning)."""
     sparams = [xv.Params(bit_depth=p.bit_depth, qp=p.qp, block=p.block,
                          search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
                          fill_mode=p.fill_mode, flags=xv.FLAG_SPLIT) for p in params]
-    half = dataclasses.replace(wl, blocks=tuple(b // 2 for b in wl.blocks))
-    hparams = [xv.Params(bit_depth=p.bit_depth, qp=p.qp, block=p.block // 2,
-                         search_range=p.search_range, gop=p.gop, pad_mode=p.pad_mode,
-                         fill_mode=p.fill_mode) for p in params]
-    # a short tuning (the model's 48 best) keeps this section's cost small
-    tuning = tune(xv, half, cube, hparams, cached, no_tune, max_candidates=48)
+    tuning = tune(xv, wl, cube, sparams, cached, no_tune, split=True)
     outs = [torch.empty_like(cube) for _ in sparams]
     frac = []
 
@@ -777,7 +774,7 @@ def split_bench(xv, torch, wl, cube, params, runs, steps, cached, no_tune, warmu
     px_band = wl.px_band * len(sparams)
     n_i = -(-wl.T // params[0].gop)  # I pictures per stream group
     return {"workload": describe(wl) + "; P blocks whole or split into four N/2 blocks",
-            "me_geometry_half": tuning,
+            "me_geometry": tuning,
             "runs": [f"QP{qp}/N{N}" for qp, N in runs],
             "value": round(px_band * steps / dt / 1e6, 3),
             "ms_per_step": round(dt / steps * 1e3, 3),
@@ -787,7 +784,8 @@ def split_bench(xv, torch, wl, cube, params, runs, steps, cached, no_tune, warmu
             "split_block_fraction_per_run": [round(f, 4) for f in frac],
             "split_block_fraction_of_P_blocks": [round(f * wl.T / (wl.T - n_i), 4) for f in frac],
             "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items() if v["launches"]},
-            # both searches (N and N/2) over their in-picture SAD terms
+            # the combined search over the whole blocks' in-picture SAD terms
+            # (each term serves a block and one of its cells)
             "me_Tterms_per_s": round(prof["me"]["work"] / (prof["me"]["ms"] * 1e-3) / 1e12, 3),
             "me_frac_sad_peak": round(prof["me"]["work"] / (prof["me"]["ms"] * 1e-3) / 1e12
                                       / SAD_PEAK_TTERMS, 4)}, tuning

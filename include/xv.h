@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define XV_ABI_VERSION 7
+#define XV_ABI_VERSION 8
 
 /* status codes */
 #define XV_OK 0
@@ -390,6 +390,15 @@ int xv_set_me_geometry(int block, int search_range, const xv_me_geometry* g);
  * (width_blocks <= 0: 16): the one set or tuned, else the model default. */
 int xv_get_me_geometry(int block, int search_range, int width_blocks, xv_me_geometry* g);
 
+/* The same pair for the search of the adaptive block size (XV_FLAG_SPLIT),
+ * which finds the vectors of every block and of its four N/2 cells in one
+ * pass (block 8, 16 or 32): row-pair layouts only, 5, 7, 11 or 13
+ * candidates per lane, one row; staged by channel, a workgroup's items
+ * must not exceed 2 rounds of its threads for 5 or 7 candidates, 1 round
+ * for 11 or 13.  Same errors as above. */
+int xv_set_me_split_geometry(int block, int search_range, const xv_me_geometry* g);
+int xv_get_me_split_geometry(int block, int search_range, int width_blocks, xv_me_geometry* g);
+
 /* Empirical tuner: times the motion-search kernel on the first P-picture
  * step of the cube `in` (device memory) coded with p, for the geometries the
  * model ranks highest (max_candidates of them, <= 0: 512, shared equally
@@ -405,7 +414,10 @@ int xv_autotune_me(const xv_cube* in, const xv_params* p, void* hip_stream, int 
 /* The same over the first P-picture step of a batch coded together, as
  * xv_encode_batch would launch it: n cubes with their params, which must
  * all share block and search_range.  Tuning on the batch that will run
- * accounts for its grid size, which changes the best geometry. */
+ * accounts for its grid size, which changes the best geometry.  With
+ * XV_FLAG_SPLIT in every params entry (in none or all), both tuners time
+ * and install the adaptive block size's search instead, as
+ * xv_set_me_split_geometry would. */
 int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, void* hip_stream,
                          int max_candidates, xv_me_geometry* out, double* best_ms);
 

@@ -387,12 +387,13 @@ __host__ __device__ inline RpShape rp_shape(int N, int R, int kx, int nb) {
 // LDS of a workgroup, in dwords: pair rows [C][xr][pitch], paired current
 // blocks [C][nb][N/2][N] from a 16-byte boundary, nb 64-bit keys; C = 3
 // channels resident at once, or 1 when they are staged one after another.
-__host__ __device__ inline MeLds rp_lds_layout(int N, const RpShape& s, int nb, int chans) {
+__host__ __device__ inline MeLds rp_lds_layout(int N, const RpShape& s, int nb, int chans,
+                                               int keys = 1) {
   MeLds l;
   const size_t x = (size_t)chans * s.xr * s.pitch;
   l.cur = (x + 3) & ~(size_t)3;
   l.best = l.cur + (size_t)chans * nb * (N / 2) * N;  // a multiple of 4 past cur
-  l.bytes = l.best * 4 + (size_t)nb * 8;
+  l.bytes = l.best * 4 + (size_t)nb * keys * 8;
   return l;
 }
 
@@ -495,12 +496,28 @@ __device__ inline void stage_row_pairs(uint32_t* X, const uint16_t* ref, const R
 // pair rows unrolled per channel: all of them up to N = 16, two for N = 32
 template <int N>
 constexpr int kRpUnroll = N <= 16 ? N / 2 : 2;
+// the same over half a block's pair rows (the combined search's halves)
+template <int N>
+constexpr int kRpUnrollHalf = N <= 16 ? N / 4 : 2;
 
 // Row-pair motion search.  RND = 0: the three channels' windows are
 // resident together and a thread takes its items one at a time.  RND > 0:
 // the channels are staged one after another into a third of the LDS, and a
 // thread keeps the sums of its (at most RND) items across them.
-template <int N, int KX, int RND>
+//
+// SP = 1: the search of the adaptive block size, whole blocks and their four
+// N/2 cells in one pass.  A candidate's SAD over a block is the sum of its
+// SADs over the four cells, so the sums are kept per cell (top/bottom half of
+// the pair rows, left/right half of the columns) and each of the five
+// targets (the block, its cells in z-order) takes its own lexicographic
+// minimum over the candidates that keep that target inside the picture.  The
+// candidate set is the union of the targets' (a cell near the picture's
+// left or top edge reaches further than its block); the staged window
+// covers every candidate in [-R, R]^2 with zeros outside the picture, which
+// only candidates invalid for a target read, for that target.  Outputs: the
+// block's vector and SAD to mv_whole / sad_whole, the cells' to the cell
+// grid (mv / sad), exactly what the separate searches at N and N/2 give.
+template <int N, int KX, int RND, int SP = 0>
 __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, int nb) {
   extern __shared__ __align__(16) uint32_t lds[];
   int tl;
@@ -514,7 +531,8 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
   const int nbv = min(nb, Wb - bx0);
   const int nch = job.nch;
   const RpShape s = rp_shape(N, R, KX, nb);
-  const MeLds ll = rp_lds_layout(N, s, nb, RND == 0 ? 3 : 1);
+  constexpr int KEYS = SP ? 5 : 1;  // targets per block
+  const MeLds ll = rp_lds_layout(N, s, nb, RND == 0 ? 3 : 1, KEYS);
   uint32_t* X = lds;
   uint32_t* curx = lds + ll.cur;
   unsigned long long* best = (unsigned long long*)(lds + ll.best);
@@ -551,13 +569,15 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
   // Items: (block b, group g of KX candidate columns from the block's first
   // in-picture column, candidate row r), r fastest so that neighbouring
   // lanes read pair rows a pitch apart and share the current block.
+  // SP: the candidates of the union of the block's and its cells' ranges
+  constexpr int ext = SP ? N / 2 : 0;
   const int y0b = by * N;
-  const int rlo = max(0, R - y0b);
-  const int nr = min(s.span - 1, Hp - N - y0b + R) - rlo + 1;
+  const int rlo = max(0, R - y0b - ext);
+  const int nr = min(s.span - 1, Hp - N + ext - y0b + R) - rlo + 1;
   int items = 0;
   for (int b = 0; b < nbv; b++) {
     const int x0 = (bx0 + b) * N;
-    const int clo = max(0, R - x0), chi = min(s.span - 1, Wp - N - x0 + R);
+    const int clo = max(0, R - x0 - ext), chi = min(s.span - 1, Wp - N + ext - x0 + R);
     items += nr * ((chi - clo + KX) / KX);
   }
   const int keyshift_sad = R <= 32 ? 21 : 23;
@@ -573,8 +593,8 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
     b = 0;
     for (;; b++) {
       const int x0 = (bx0 + b) * N;
-      clo = max(0, R - x0);
-      chi = min(s.span - 1, Wp - N - x0 + R);
+      clo = max(0, R - x0 - ext);
+      chi = min(s.span - 1, Wp - N + ext - x0 + R);
       n = nr * ((chi - clo + KX) / KX);
       if (it0 < start + n || b + 1 >= nbv) break;
       start += n;
@@ -584,8 +604,8 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
       rem -= n;
       b++;
       const int x0 = (bx0 + b) * N;
-      clo = max(0, R - x0);
-      chi = min(s.span - 1, Wp - N - x0 + R);
+      clo = max(0, R - x0 - ext);
+      chi = min(s.span - 1, Wp - N + ext - x0 + R);
       n = nr * ((chi - clo + KX) / KX);
     }
     // rem / nr in binary32: rem + 1/2 and nr are exact, the quotient is
@@ -687,7 +707,157 @@ __global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, 
     }
   };
 
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) best[b] = ~0ull;
+  // SP: acc[q][k] += SAD of candidate (r, c0 + k) over cell q (2 * (lower
+  // half) + right half) of block b, channel in LDS slot sl.
+  auto accumulate4 = [&](int sl, int b, int r, int c0, uint32_t(&acc)[4][KX]) XV_INLINE {
+    constexpr int CW = N < 16 ? N : 16;  // columns per chunk
+    constexpr int NQ = KX + CW - 1;      // window dwords per chunk
+    const int xbase = (sl * s.xr + r) * s.pitch + b * N + c0;
+    const u32x4_l* cp = (const u32x4_l*)(curx + (sl * nb + b) * (N / 2) * N);
+#pragma unroll
+    for (int hy = 0; hy < 2; hy++) {
+#pragma unroll kRpUnrollHalf<N>
+      for (int jj = 0; jj < N / 4; jj++) {
+        const int j = hy * (N / 4) + jj;
+#pragma unroll
+        for (int cc = 0; cc < N / CW; cc++) {
+          uint32_t P[NQ], C[CW];
+          int xo = xbase + 2 * j * s.pitch;
+          asm volatile("" : "+v"(xo));
+#pragma unroll
+          for (int q = 0; q < NQ; q++) P[q] = X[xo + cc * CW + q];
+#pragma unroll
+          for (int q = 0; q < CW / 4; q++) {
+            const u32x4_l c4 = cp[j * (N / 4) + cc * (CW / 4) + q];
+            C[4 * q] = c4.x;
+            C[4 * q + 1] = c4.y;
+            C[4 * q + 2] = c4.z;
+            C[4 * q + 3] = c4.w;
+          }
+#pragma unroll
+          for (int k = 0; k < KX; k++)
+#pragma unroll
+            for (int x = 0; x < CW; x++) {
+              const int qd = 2 * hy + ((cc * CW + x) >= N / 2 ? 1 : 0);
+              acc[qd][k] = __builtin_amdgcn_sad_u16(P[k + x], C[x], acc[qd][k]);
+            }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+  };
+
+  // SP: the five targets' minima over the item's candidates.  Target t = 0
+  // is the block (the sum of the four cells), t = 1 + q cell q; a candidate
+  // counts for a target only if it keeps the target inside the picture.
+  auto select5 = [&](int b, int r, int c0, const uint32_t(&acc)[4][KX]) XV_INLINE {
+    constexpr int h = N / 2;
+    const int x0 = (bx0 + b) * N;
+    const uint32_t ly = (uint32_t)abs(r - R);
+    const uint32_t cx = (uint32_t)(c0 + KX);
+    int clo[5], chi[5];
+    bool rok[5];
+#pragma unroll
+    for (int t = 0; t < 5; t++) {
+      const int n = t == 0 ? N : h;
+      const int xs = x0 + (t == 0 ? 0 : ((t - 1) & 1) * h);
+      const int ys = y0b + (t == 0 ? 0 : ((t - 1) >> 1) * h);
+      clo[t] = max(0, R - xs) - c0;
+      chi[t] = min(s.span - 1, Wp - n - xs + R) - c0;
+      rok[t] = r >= R - ys && r <= Hp - n - ys + R;
+    }
+    uint32_t kb[5];
+    int bsel[5];
+#pragma unroll
+    for (int t = 0; t < 5; t++) {
+      kb[t] = 0xffffffffu;
+      bsel[t] = -1;
+    }
+#pragma unroll
+    for (int k = 0; k < KX; k++) {
+      const uint32_t l1 = __builtin_amdgcn_sad_u16(cx, (uint32_t)(R + KX - k), ly);
+#pragma unroll
+      for (int t = 0; t < 5; t++) {
+        const uint32_t sad = t == 0 ? acc[0][k] + acc[1][k] + acc[2][k] + acc[3][k] : acc[t - 1][k];
+        const uint32_t key = (sad << 8) | l1;
+        const bool take = rok[t] && k >= clo[t] && k <= chi[t] && key < kb[t];
+        kb[t] = take ? key : kb[t];
+        bsel[t] = take ? k : bsel[t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 5; t++)
+      if (bsel[t] >= 0) {
+        const unsigned long long idx = (unsigned long long)(r * s.span + c0 + bsel[t]);
+        const unsigned long long key = ((unsigned long long)(kb[t] >> 8) << keyshift_sad) |
+                                       ((unsigned long long)(kb[t] & 0xffu) << keyshift_l1) | idx;
+        atomicMin(&best[b * 5 + t], key);
+      }
+  };
+
+  for (int b = threadIdx.x; b < nb * KEYS; b += blockDim.x) best[b] = ~0ull;
+  if constexpr (SP) {
+    if constexpr (RND == 0) {
+      stage(0, nch);
+      __syncthreads();
+      for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        int b, r, c0, chi;
+        decode(it, b, r, c0, chi);
+        uint32_t acc[4][KX];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+          for (int k = 0; k < KX; k++) acc[q][k] = 0;
+        for (int ch = 0; ch < nch; ch++) accumulate4(ch, b, r, c0, acc);
+        select5(b, r, c0, acc);
+      }
+    } else {
+      int ib[RND], ir[RND], ic[RND], ih[RND];
+      uint32_t acc[RND][4][KX];
+#pragma unroll
+      for (int u = 0; u < RND; u++) {
+        const int it = threadIdx.x + u * blockDim.x;
+        if (it < items) decode(it, ib[u], ir[u], ic[u], ih[u]);
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+          for (int k = 0; k < KX; k++) acc[u][q][k] = 0;
+      }
+      for (int ch = 0; ch < nch; ch++) {
+        if (ch > 0) __syncthreads();  // every read of the previous channel done
+        stage(ch, 1);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < RND; u++)
+          if (threadIdx.x + u * blockDim.x < items) accumulate4(0, ib[u], ir[u], ic[u], acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < RND; u++)
+        if (threadIdx.x + u * blockDim.x < items) select5(ib[u], ir[u], ic[u], acc[u]);
+    }
+    __syncthreads();
+    const int Wu = 2 * Wb;
+    for (int i = threadIdx.x; i < nbv * 5; i += blockDim.x) {
+      const int b = i / 5, t = i - (i / 5) * 5;
+      const unsigned long long key = best[i];
+      const int idx = (int)(key & ((1ull << keyshift_l1) - 1));
+      const int dy = idx / s.span - R, dx = idx - (idx / s.span) * s.span - R;
+      const uint32_t sad = (uint32_t)(key >> keyshift_sad);
+      if (t == 0) {
+        const size_t ci = (size_t)by * Wb + bx0 + b;
+        job.mv_whole[2 * ci] = (int8_t)dx;
+        job.mv_whole[2 * ci + 1] = (int8_t)dy;
+        job.sad_whole[ci] = sad;
+      } else {
+        const int sx = (t - 1) & 1, sy = (t - 1) >> 1;
+        const size_t u = (size_t)(2 * by + sy) * Wu + 2 * (bx0 + b) + sx;
+        job.mv[2 * u] = (int8_t)dx;
+        job.mv[2 * u + 1] = (int8_t)dy;
+        job.sad[u] = sad;
+      }
+    }
+    return;
+  }
   if constexpr (RND == 0) {
     stage(0, nch);
     __syncthreads();
@@ -796,6 +966,53 @@ hipError_t launch_me_rp_t(int R, const MeGeom& g, const LaunchDesc& r, hipStream
   return hipGetLastError();
 }
 
+// The combined whole-and-cells search (SP = 1) exists for KX = 5, 7, 11 and
+// 13 in both row-pair layouts; staged by channel, a thread keeps
+// kSplitRounds(KX) items (four sums per candidate each).
+constexpr int kSplitRounds(int kx) { return kx >= 11 ? 1 : 2; }
+
+template <int N, int KX, int RND>
+hipError_t launch_me_rp_split_t(int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
+  const size_t lds = rp_lds_layout(N, rp_shape(N, R, KX, g.nb), g.nb, RND == 0 ? 3 : 1, 5).bytes;
+  static bool attr_set = false;
+  if (!attr_set && lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)me_rp_kernel<N, KX, RND, 1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  me_rp_kernel<N, KX, RND, 1><<<r.tiles, g.threads, lds, s>>>(r, R, g.nb);
+  return hipGetLastError();
+}
+
+// Calls f.template operator()<KX, RND>() for the combined search's instance
+// of g.
+template <class F>
+auto split_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<5, 0>()) {
+  using Ret = decltype(f.template operator()<5, 0>());
+  const bool byc = g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL;
+  switch (g.kx) {
+#define XV_SPLIT_KX(kx) \
+  case kx:              \
+    return byc ? f.template operator()<kx, kSplitRounds(kx)>() : f.template operator()<kx, 0>();
+    XV_SPLIT_KX(5)
+    XV_SPLIT_KX(7)
+    XV_SPLIT_KX(11)
+    XV_SPLIT_KX(13)
+#undef XV_SPLIT_KX
+    default: return (Ret)hipErrorInvalidValue;
+  }
+}
+
+template <int N>
+int me_split_vgprs_n(const MeGeom& g) {
+  hipFuncAttributes a{};
+  const hipError_t e = split_dispatch(g, [&]<int KX, int RND>() {
+    return hipFuncGetAttributes(&a, (const void*)me_rp_kernel<N, KX, RND, 1>);
+  });
+  return (e == hipSuccess && a.numRegs > 0) ? a.numRegs : 128;
+}
+
 // Calls f.template operator()<KX>() for the row-pair instance of g.kx.
 template <class F>
 auto rp_dispatch(const MeGeom& g, F&& f) -> decltype(f.template operator()<2>()) {
@@ -895,12 +1112,16 @@ bool me_geometry_fits(int N, int R, const MeGeom& g) {
 // address updates.  Per item, about 40 + 6 x candidates instructions select
 // the best candidate.  Useful candidates: 2R+1 of G KX columns, and for
 // column pairs 2R+1 of rows * ceil((2R+1)/rows) rows.
-double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
+namespace {
+
+// The model for an instance with vgpr registers per lane, lds bytes per
+// workgroup and sel instructions of selection per item and channel.
+double model_score(int N, int R, const MeGeom& g, int width_blocks, int vgpr, size_t lds,
+                   double sel) {
   const int span = 2 * R + 1;
   const int kx = g.kx, th = g.threads;
   const int G = (span + kx - 1) / kx;
   const bool rp = g.layout == XV_ME_ROW_PAIRS || g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL;
-  const double sel = (40.0 + 6.0 * kx * g.rows) / 3.0;  // per channel of a 3-channel group
   double eff;
   int ipb;
   if (rp) {
@@ -915,8 +1136,6 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
           (double)(g.rows * dyp);
     ipb = dyp * G;
   }
-  const size_t lds = me_lds_bytes_for(N, R, g);
-  if (!me_geometry_fits(N, R, g)) return -1.0;
   // lane occupancy over the runs of a block row (full runs of nb blocks and
   // a last run of the remaining ones): a wave with no item left exits, so
   // only the idle lanes of the last busy wave of a run are lost
@@ -930,7 +1149,6 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
   }
   const double lane = busy / slots;
   const int wpg = th / 64;
-  const int vgpr = me_vgprs(N, g);
   const int waves_by_vgpr = std::max(1, std::min(8, 512 / std::max(1, vgpr)));
   const int wg_lds = (int)((160 * 1024) / std::max<size_t>(1, lds));
   const int wg_waves = (4 * waves_by_vgpr) / wpg;
@@ -938,6 +1156,14 @@ double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
   if (wg == 0) return -1.0;
   const double occ = std::min(3.0, (double)(wg * wpg) / 4.0);
   return eff * lane * occ;
+}
+
+}  // namespace
+
+double me_model_score(int N, int R, const MeGeom& g, int width_blocks) {
+  if (!me_geometry_fits(N, R, g)) return -1.0;
+  return model_score(N, R, g, width_blocks, me_vgprs(N, g), me_lds_bytes_for(N, R, g),
+                     (40.0 + 6.0 * g.kx * g.rows) / 3.0);  // per channel of a 3-channel group
 }
 
 std::vector<MeGeom> me_candidates(int N, int R, int width_blocks) {
@@ -1024,6 +1250,89 @@ hipError_t launch_split_decide(int N, const LaunchDesc& r, hipStream_t s) {
   if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
   split_decide_kernel<<<r.tiles, kDecideThreads, 0, s>>>(r, N);
   return hipGetLastError();
+}
+
+// ---- the combined search's geometry ------------------------------------------
+bool me_split_instance_exists(int N, const MeGeom& g) {
+  return (N == 8 || N == 16 || N == 32) && g.rows == 1 &&
+         (g.layout == XV_ME_ROW_PAIRS || g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL) &&
+         (g.kx == 5 || g.kx == 7 || g.kx == 11 || g.kx == 13);
+}
+
+size_t me_split_lds_bytes(int N, int R, const MeGeom& g) {
+  return rp_lds_layout(N, rp_shape(N, R, g.kx, g.nb), g.nb,
+                       g.layout == XV_ME_ROW_PAIRS ? 3 : 1, 5).bytes;
+}
+
+int me_split_rounds(const MeGeom& g) {
+  return g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL ? kSplitRounds(g.kx) : 0;
+}
+
+bool me_split_fits(int N, int R, const MeGeom& g) {
+  if (!me_split_instance_exists(N, g) || g.nb < 1 || g.threads < 64 || g.threads > 512 ||
+      (g.threads & 63))
+    return false;
+  if (me_split_lds_bytes(N, R, g) > 160 * 1024) return false;
+  if (g.layout == XV_ME_ROW_PAIRS_BY_CHANNEL) {
+    const long span = 2L * R + 1, groups = (span + g.kx - 1) / g.kx;
+    if ((long)g.nb * span * groups > (long)me_split_rounds(g) * g.threads) return false;
+  }
+  return true;
+}
+
+// Model score of a combined-search geometry: the plain search's model with
+// this instance's registers and LDS and a selection over five targets.
+double me_split_model_score(int N, int R, const MeGeom& g, int width_blocks) {
+  if (!me_split_fits(N, R, g)) return -1.0;
+  int vgpr = 128;
+  switch (N) {
+    case 8: vgpr = me_split_vgprs_n<8>(g); break;
+    case 16: vgpr = me_split_vgprs_n<16>(g); break;
+    default: vgpr = me_split_vgprs_n<32>(g); break;
+  }
+  return model_score(N, R, g, width_blocks, vgpr, me_split_lds_bytes(N, R, g),
+                     (40.0 + 5 * 6.0 * g.kx) / 3.0);
+}
+
+std::vector<MeGeom> me_split_candidates(int N, int R, int width_blocks) {
+  std::vector<MeGeom> v;
+  const int cmax = std::max(1, std::min(16, width_blocks));
+  for (int lay : {XV_ME_ROW_PAIRS, XV_ME_ROW_PAIRS_BY_CHANNEL})
+    for (int kx : {5, 7, 11, 13})
+      for (int c = 1; c <= cmax; c++)
+        for (int th = 64; th <= 512; th += 64) {
+          const MeGeom g{c, kx, th, 1, lay};
+          if (me_split_fits(N, R, g) && me_split_lds_bytes(N, R, g) <= 96 * 1024) v.push_back(g);
+        }
+  return v;
+}
+
+MeGeom me_split_default_geometry(int N, int R, int width_blocks) {
+  MeGeom best{1, 13, 384, 1, XV_ME_ROW_PAIRS_BY_CHANNEL};
+  double bs = -2.0;
+  for (const MeGeom& g : me_split_candidates(N, R, width_blocks)) {
+    const double sc = me_split_model_score(N, R, g, width_blocks);
+    if (sc > bs + 1e-9 || (sc > bs - 1e-9 && g.nb > best.nb)) {
+      bs = sc;
+      best = g;
+    }
+  }
+  return best;
+}
+
+hipError_t launch_me_split(int N, int R, const MeGeom& g, const LaunchDesc& r, hipStream_t s) {
+  if (r.nseg <= 0 || r.tiles <= 0) return hipSuccess;
+  if (!me_split_fits(N, R, g)) return hipErrorInvalidValue;
+  auto go = [&]<int NN>() {
+    return split_dispatch(
+        g, [&]<int KX, int RND>() { return launch_me_rp_split_t<NN, KX, RND>(R, g, r, s); });
+  };
+  switch (N) {
+    case 8: return go.template operator()<8>();
+    case 16: return go.template operator()<16>();
+    case 32: return go.template operator()<32>();
+    default: return hipErrorInvalidValue;
+  }
 }
 
 int me_tiles_per_job(int Hb, int Wb, const MeGeom& g) {

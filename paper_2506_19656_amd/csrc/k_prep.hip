@@ -997,14 +997,6 @@ __global__ void plan_kernel(CubePlan p) {
   jb.bit_depth = p.bit_depth;
   jb.qp = p.qp;
   p.jobs[i] = jb;
-  if (p.jobs_whole) {
-    // the size-N search of the adaptive block size writes here
-    FrameJob jw = jb;
-    jw.mv = jb.mv_whole;
-    jw.sad = jb.sad_whole;
-    jw.split = nullptr;
-    p.jobs_whole[i] = jw;
-  }
 }
 
 inline int grid_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }

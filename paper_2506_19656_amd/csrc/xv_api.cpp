@@ -101,8 +101,7 @@ EncLayout enc_layout(const xv_encoded* e) {
   L.o_span = k.take<uint64_t>(L.span_words);
   L.phys_nb = phys_blocks(T * e->H * e->W * bands);
   L.o_pp = k.take<double>((size_t)L.phys_nb * bands);
-  // with the adaptive block size the size-N search's table follows the main one
-  L.o_jobs = k.take<FrameJob>((size_t)e->njobs * (split ? 2 : 1));
+  L.o_jobs = k.take<FrameJob>((size_t)e->njobs);
   L.o_split = split ? k.take<uint8_t>((size_t)nblk) : 0;
   L.keep = k.off;
   Carve w;
@@ -156,7 +155,6 @@ void bind_keep(xv_encoded* e, const EncLayout& lay) {
   e->jobs = (FrameJob*)(kb + lay.o_jobs);
   const bool split = (e->p.flags & XV_FLAG_SPLIT) != 0;
   e->splits = split ? (uint8_t*)(kb + lay.o_split) : nullptr;
-  e->jobs_whole = split ? e->jobs + e->njobs : nullptr;
 }
 
 // Allocates the encoded object and launches stats, pack and plan.
@@ -224,7 +222,7 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
                 e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)bands, e->N,
                 p->bit_depth, p->qp, e->tpf, (p->flags & XV_FLAG_QPEL) != 0,
                 (p->flags & XV_FLAG_INTRA) != 0, e->splits, e->mv_whole, e->sad_whole,
-                e->sad_cell, e->jobs_whole, split ? split_lambda16(p->qp, p->bit_depth) : 0};
+                e->sad_cell, split ? split_lambda16(p->qp, p->bit_depth) : 0};
     XV_HIP(launch_plan(pl, s), "plan kernel");
   }
   return XV_OK;
@@ -299,27 +297,16 @@ int launch_split_search(const std::vector<SegSrc>& src, hipStream_t s) {
   const int N = src[0].e->N, R = src[0].e->p.search_range;
   int max_wb = 1;
   for (auto& x : src) max_wb = std::max(max_wb, x.e->Wb);
-  const MeGeom gw = geometry_for(N, R, max_wb);
-  const MeGeom gc = geometry_for(N / 2, R, 2 * max_wb);
-  // size N: the second job table (vectors and SADs of whole blocks)
+  const MeGeom g = split_geometry_for(N, R, max_wb);
+  // one search for the whole blocks and their cells; the SAD terms counted
+  // are the whole blocks' (each term serves the block and one cell)
   int rc = launch_chunks(
-      src, [](const SegSrc& x) { return x.e->jobs_whole; },
-      [&](const xv_encoded* e) { return me_tiles_per_job(e->Hb, e->Wb, gw); },
+      src, [](const SegSrc& x) { return x.e->jobs; },
+      [&](const xv_encoded* e) { return me_tiles_per_job(e->Hb, e->Wb, g); },
       [](const SegSrc& x) { return me_work(x.e, x.step); },
       [&](const LaunchDesc& d, double work) {
         ProfScope ps(XV_K_ME, s, work);
-        XV_HIP(launch_me(N, R, gw, d, s), "motion search kernel (whole blocks)");
-        return XV_OK;
-      });
-  if (rc != XV_OK) return rc;
-  // size N/2: the cells, into the cell grid of the main table
-  rc = launch_chunks(
-      src, [](const SegSrc& x) { return x.e->jobs; },
-      [&](const xv_encoded* e) { return me_tiles_per_job(2 * e->Hb, 2 * e->Wb, gc); },
-      [&](const SegSrc& x) { return me_work(x.e, x.step, N / 2); },
-      [&](const LaunchDesc& d, double work) {
-        ProfScope ps(XV_K_ME, s, work);
-        XV_HIP(launch_me(N / 2, R, gc, d, s), "motion search kernel (cells)");
+        XV_HIP(launch_me_split(N, R, g, d, s), "motion search kernel (whole blocks and cells)");
         return XV_OK;
       });
   if (rc != XV_OK) return rc;
@@ -432,7 +419,7 @@ int decode_prepare(const xv_encoded* e, hipStream_t s, DecodeBuf& db) {
               nullptr, db.pred, db.jobs, (int32_t)e->T, e->G, e->p.gop, e->nsteps,
               e->Hp, e->Wp, (int32_t)e->H, (int32_t)e->W, (int32_t)e->bands, e->N,
               e->p.bit_depth, e->p.qp, 0, qpel, (e->p.flags & XV_FLAG_INTRA) != 0,
-              e->splits, nullptr, nullptr, nullptr, nullptr, 0};
+              e->splits, nullptr, nullptr, nullptr, 0};
   XV_HIP(launch_plan(pl, s), "plan kernel");
   return XV_OK;
 }

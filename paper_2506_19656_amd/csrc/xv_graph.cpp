@@ -10,8 +10,9 @@
 // graph, whose kernels then reach this call's frames, levels and
 // reconstructions through them.  The key is everything the launches depend
 // on: per cube the frame count, group count, GOP, padded size, block size,
-// search range and the quarter-sample and intra flags; the motion-search geometry of the
-// class; and the stream.  Graphs hold kernel nodes only (no memset or copy
+// search range and the quarter-sample, intra and adaptive-block-size flags; the
+// motion-search geometries of the class (plain, and combined for the adaptive
+// block size); and the stream.  Graphs hold kernel nodes only (no memset or copy
 // nodes).  Capture runs on a stream of the library's own, so the caller's
 // stream may be the null stream; nothing captured executes during capture.
 #include <string.h>
@@ -36,12 +37,14 @@ hipStream_t g_capture_stream = nullptr;
 struct GraphKey {
   int kind;  // 0 encode steps, 1 decode steps
   hipStream_t stream;
-  MeGeom geom;
+  MeGeom geom, sgeom;  // sgeom: the combined search's (zero without split cubes)
   std::vector<int64_t> dims;
   bool operator<(const GraphKey& o) const {
-    return std::tie(kind, stream, geom.nb, geom.kx, geom.threads, geom.rows, geom.layout, dims) <
+    return std::tie(kind, stream, geom.nb, geom.kx, geom.threads, geom.rows, geom.layout,
+                    sgeom.nb, sgeom.kx, sgeom.threads, sgeom.rows, sgeom.layout, dims) <
            std::tie(o.kind, o.stream, o.geom.nb, o.geom.kx, o.geom.threads, o.geom.rows,
-                    o.geom.layout, o.dims);
+                    o.geom.layout, o.sgeom.nb, o.sgeom.kx, o.sgeom.threads, o.sgeom.rows,
+                    o.sgeom.layout, o.dims);
   }
 };
 
@@ -152,31 +155,29 @@ bool graphs_enabled() {
 }
 
 int encode_steps_graph(std::vector<xv_encoded*>& es, hipStream_t s) {
-  int max_wb = 1;
-  for (auto* e : es) max_wb = std::max(max_wb, e->Wb);
-  GraphKey key{0, s, geometry_for(es[0]->N, es[0]->p.search_range, max_wb),
+  // the widest frame, of all cubes and of those with the adaptive block size
+  int max_wb = 1, max_wb_split = 0;
+  for (auto* e : es) {
+    max_wb = std::max(max_wb, e->Wb);
+    if (e->p.flags & XV_FLAG_SPLIT) max_wb_split = std::max(max_wb_split, e->Wb);
+  }
+  const int N = es[0]->N, R = es[0]->p.search_range;
+  GraphKey key{0, s, geometry_for(N, R, max_wb),
+               max_wb_split ? split_geometry_for(N, R, max_wb_split) : MeGeom{},
                dims_key(std::vector<const xv_encoded*>(es.begin(), es.end()))};
-  // with the adaptive block size the size-N search's table follows the main
-  // one and is refreshed with it
   std::vector<size_t> bytes;
-  for (auto* e : es)
-    bytes.push_back((size_t)e->njobs * sizeof(FrameJob) * (e->jobs_whole ? 2 : 1));
+  for (auto* e : es) bytes.push_back((size_t)e->njobs * sizeof(FrameJob));
   return replay(
       key, bytes, [&](size_t i) { return (const void*)es[i]->jobs; },
       [&](const std::vector<FrameJob*>& fixed, hipStream_t cs) {
-        // the step loop with every cube's job tables at their fixed addresses
-        std::vector<FrameJob*> own, own_whole;
+        // the step loop with every cube's job table at its fixed address
+        std::vector<FrameJob*> own;
         for (size_t i = 0; i < es.size(); i++) {
           own.push_back(es[i]->jobs);
-          own_whole.push_back(es[i]->jobs_whole);
           es[i]->jobs = fixed[i];
-          if (es[i]->jobs_whole) es[i]->jobs_whole = fixed[i] + es[i]->njobs;
         }
         const int rc = encode_steps(es, cs);
-        for (size_t i = 0; i < es.size(); i++) {
-          es[i]->jobs = own[i];
-          es[i]->jobs_whole = own_whole[i];
-        }
+        for (size_t i = 0; i < es.size(); i++) es[i]->jobs = own[i];
         return rc;
       },
       s);
@@ -185,7 +186,7 @@ int encode_steps_graph(std::vector<xv_encoded*>& es, hipStream_t s) {
 int decode_steps_graph(const std::vector<DecSrc>& base, hipStream_t s) {
   std::vector<const xv_encoded*> es;
   for (auto& b : base) es.push_back(b.e);
-  GraphKey key{1, s, MeGeom{}, dims_key(es)};
+  GraphKey key{1, s, MeGeom{}, MeGeom{}, dims_key(es)};
   std::vector<size_t> bytes;
   for (auto& b : base) bytes.push_back((size_t)b.e->njobs * sizeof(FrameJob));
   return replay(

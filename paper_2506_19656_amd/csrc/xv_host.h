@@ -49,10 +49,8 @@ struct xv_encoded {
   int phys_nb;
   xv::FrameJob* jobs;
   // adaptive block size (XV_FLAG_SPLIT), else null: split flags [G][T][Hb][Wb]
-  // and the size-N search's job table, jobs + njobs (keep); its vectors and
-  // SADs and the cells' SADs (work)
+  // (keep); the whole blocks' vectors and SADs and the cells' SADs (work)
   uint8_t* splits;
-  xv::FrameJob* jobs_whole;
   int8_t* mv_whole;
   uint32_t* sad_whole;
   uint32_t* sad_cell;
@@ -103,6 +101,10 @@ bool profiling_enabled();
 // the model default for the class's widest frame in blocks.
 MeGeom geometry_for(int N, int R, int Wb = 16);
 void geometry_install(int N, int R, const MeGeom& g);
+// The same for the adaptive block size's combined search
+// (xv_set_me_split_geometry, the tuner on XV_FLAG_SPLIT params).
+MeGeom split_geometry_for(int N, int R, int Wb = 16);
+void split_geometry_install(int N, int R, const MeGeom& g);
 
 // ---- validation ----------------------------------------------------------------
 int check_cube(const xv_cube* c, const char* name);

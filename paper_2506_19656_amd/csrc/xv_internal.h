@@ -39,7 +39,7 @@ struct FrameJob {
   uint8_t* split;              // adaptive block size: [Hb][Wb] split flags, else null;
                                // mv is then the [2 Hb][2 Wb] grid of N/2 cells
   uint32_t* sad;               // SAD of each searched block's vector, or null
-  int8_t* mv_whole;            // adaptive block size, P steps: the size-N search's
+  int8_t* mv_whole;            // adaptive block size, P steps: the whole blocks'
   uint32_t* sad_whole;         // vectors [Hb][Wb][2] and SADs [Hb][Wb]
   int32_t Hp, Wp, H, W;
   int32_t nch;                 // channels carrying a real band (1..3)
@@ -95,14 +95,12 @@ struct CubePlan {
   int32_t imode;               // I blocks intra-predicted; with pred, the I step's
                                // prediction goes to pred too (encode)
   // adaptive block size (null / 0 without): split flags [G][T][Hb][Wb], the
-  // size-N search's vectors and SADs [G][T][Hb][Wb], the cells' SADs
-  // [G][T][2 Hb][2 Wb], and a second job table (same order) whose mv / sad
-  // are the size-N ones, for that search
+  // whole blocks' vectors and SADs [G][T][Hb][Wb] and the cells' SADs
+  // [G][T][2 Hb][2 Wb]
   uint8_t* split;
   int8_t* mv_whole;
   uint32_t* sad_whole;
   uint32_t* sad_cell;
-  FrameJob* jobs_whole;
   int32_t lambda16;
 };
 
@@ -262,6 +260,19 @@ bool me_geometry_fits(int N, int R, const MeGeom& g);
 bool me_instance_exists(const MeGeom& g);
 int me_tiles_per_job(int Hb, int Wb, const MeGeom& g);
 hipError_t launch_me(int N, int R, const MeGeom& g, const LaunchDesc& d, hipStream_t s);
+// Adaptive block size: one search for whole blocks and their N/2 cells
+// (k_me.hip; row-pair layouts, KX 5, 7, 11 or 13, N 8..32): the block's
+// vector and SAD to mv_whole / sad_whole, the cells' to the cell grid
+// (mv / sad).  Its geometries, model and candidates mirror the plain
+// search's; by channel, a thread keeps me_split_rounds(g) items.
+bool me_split_instance_exists(int N, const MeGeom& g);
+size_t me_split_lds_bytes(int N, int R, const MeGeom& g);
+int me_split_rounds(const MeGeom& g);
+bool me_split_fits(int N, int R, const MeGeom& g);
+double me_split_model_score(int N, int R, const MeGeom& g, int width_blocks);
+std::vector<MeGeom> me_split_candidates(int N, int R, int width_blocks);
+MeGeom me_split_default_geometry(int N, int R, int width_blocks);
+hipError_t launch_me_split(int N, int R, const MeGeom& g, const LaunchDesc& d, hipStream_t s);
 
 int xf_tiles_per_job(int N, int Hb, int Wb);
 hipError_t launch_encode(int N, const LaunchDesc& d, hipStream_t s);
@@ -274,8 +285,8 @@ hipError_t launch_encode(int N, const LaunchDesc& d, hipStream_t s);
 hipError_t launch_encode_split(int N, int role, const LaunchDesc& d, hipStream_t s);
 hipError_t launch_decode_split(int N, int role, const LaunchDesc& d, hipStream_t s);
 // Whole-or-split choice of every block of a P step (k_me.hip), after the
-// size-N search (mv_whole, sad_whole) and the size-N/2 search (mv, sad on
-// the cell grid): writes split flags and the final cell vectors.
+// combined search (whole blocks: mv_whole, sad_whole; cells: mv, sad on the
+// cell grid): writes split flags and the final cell vectors.
 int split_tiles_per_job(int Hb, int Wb);
 hipError_t launch_split_decide(int N, const LaunchDesc& d, hipStream_t s);
 // Quarter-sample motion (k_subpel.hip): one workgroup per block of a P step.

@@ -66,6 +66,8 @@ hipEvent_t prof_event_locked() {
 std::mutex g_geom_mu;
 std::map<std::pair<int, int>, MeGeom> g_geom;
 std::map<std::tuple<int, int, int>, MeGeom> g_geom_default;
+std::map<std::pair<int, int>, MeGeom> g_split_geom;
+std::map<std::tuple<int, int, int>, MeGeom> g_split_geom_default;
 }  // namespace
 
 ProfScope::ProfScope(int c, hipStream_t st, double w) : cls(c), s(st), work(w) {
@@ -110,6 +112,23 @@ void geometry_install(int N, int R, const MeGeom& g) {
 void geometry_reset(int N, int R) {
   std::lock_guard<std::mutex> lk(g_geom_mu);
   g_geom.erase({N, R});
+}
+
+MeGeom split_geometry_for(int N, int R, int Wb) {
+  std::lock_guard<std::mutex> lk(g_geom_mu);
+  auto it = g_split_geom.find({N, R});
+  if (it != g_split_geom.end()) return it->second;
+  const int wb = std::max(1, std::min(16, Wb));
+  auto d = g_split_geom_default.find({N, R, wb});
+  if (d != g_split_geom_default.end()) return d->second;
+  MeGeom g = me_split_default_geometry(N, R, wb);
+  g_split_geom_default[{N, R, wb}] = g;
+  return g;
+}
+
+void split_geometry_install(int N, int R, const MeGeom& g) {
+  std::lock_guard<std::mutex> lk(g_geom_mu);
+  g_split_geom[{N, R}] = g;
 }
 
 }  // namespace host
@@ -184,6 +203,53 @@ int xv_get_me_geometry(int block, int search_range, int width_blocks, xv_me_geom
       search_range > 64)
     return fail(XV_EINVAL, "bad block or search range");
   MeGeom m = geometry_for(block, search_range, width_blocks > 0 ? width_blocks : 16);
+  g->blocks_per_wg = m.nb;
+  g->cands_per_lane = m.kx;
+  g->threads = m.threads;
+  g->rows_per_lane = m.rows;
+  g->layout = m.layout;
+  return XV_OK;
+}
+
+int xv_set_me_split_geometry(int block, int search_range, const xv_me_geometry* g) {
+  if (!(block == 8 || block == 16 || block == 32) || search_range < 0 || search_range > 64)
+    return fail(XV_EINVAL, "bad block or search range for the adaptive block size");
+  if (!g || (g->blocks_per_wg == 0 && g->cands_per_lane == 0 && g->threads == 0 &&
+             g->rows_per_lane == 0 && g->layout == 0)) {
+    std::lock_guard<std::mutex> lk(g_geom_mu);
+    g_split_geom.erase({block, search_range});  // back to the model default
+    return XV_OK;
+  }
+  MeGeom m = me_split_default_geometry(block, search_range, 16);
+  if (g->blocks_per_wg) m.nb = g->blocks_per_wg;
+  if (g->cands_per_lane) m.kx = g->cands_per_lane;
+  if (g->threads) m.threads = g->threads;
+  if (g->layout) m.layout = g->layout;
+  if (g->rows_per_lane) m.rows = g->rows_per_lane;
+  if (m.layout != XV_ME_ROW_PAIRS && m.layout != XV_ME_ROW_PAIRS_BY_CHANNEL)
+    return fail(XV_EINVAL, "the combined search has row-pair layouts only (got %d)", m.layout);
+  if (m.nb < 1 || m.nb > 64) return fail(XV_EINVAL, "blocks_per_wg out of range");
+  if (m.threads < 64 || m.threads > 512 || (m.threads & 63))
+    return fail(XV_EINVAL, "threads must be a multiple of 64 in 64..512");
+  if (!me_split_instance_exists(block, m))
+    return fail(XV_EINVAL,
+                "no combined-search kernel for %d candidates x %d rows per lane (one row; 5, 7, "
+                "11 or 13 candidates)",
+                m.kx, m.rows);
+  if (me_split_lds_bytes(block, search_range, m) > 160 * 1024)
+    return fail(XV_EINVAL, "geometry needs more than 160 KB of LDS");
+  if (!me_split_fits(block, search_range, m))
+    return fail(XV_EINVAL, "a workgroup's items exceed %d round(s) of its threads",
+                me_split_rounds(m));
+  split_geometry_install(block, search_range, m);
+  return XV_OK;
+}
+
+int xv_get_me_split_geometry(int block, int search_range, int width_blocks, xv_me_geometry* g) {
+  if (!g) return fail(XV_EINVAL, "null geometry");
+  if (!(block == 8 || block == 16 || block == 32) || search_range < 0 || search_range > 64)
+    return fail(XV_EINVAL, "bad block or search range for the adaptive block size");
+  MeGeom m = split_geometry_for(block, search_range, width_blocks > 0 ? width_blocks : 16);
   g->blocks_per_wg = m.nb;
   g->cands_per_lane = m.kx;
   g->threads = m.threads;

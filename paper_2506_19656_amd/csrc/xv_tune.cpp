@@ -1,6 +1,7 @@
 // xv_tune.cpp -- the empirical motion-search geometry tuner
 // (xv_autotune_me, xv_autotune_me_batch): candidates ranked by the CU model,
-// timed on the first P-picture step of the batch that will run.
+// timed on the first P-picture step of the batch that will run.  Params with
+// XV_FLAG_SPLIT tune the adaptive block size's combined search instead.
 #include <algorithm>
 #include <vector>
 
@@ -29,7 +30,10 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
       return fail(XV_EINVAL, "tuning needs a P picture (T >= 2, gop >= 2)");
     if (params[i].block != params[0].block || params[i].search_range != params[0].search_range)
       return fail(XV_EINVAL, "tuning batch mixes block sizes or search ranges");
+    if ((params[i].flags ^ params[0].flags) & XV_FLAG_SPLIT)
+      return fail(XV_EINVAL, "tuning batch mixes the adaptive block size with fixed blocks");
   }
+  const bool split = (params[0].flags & XV_FLAG_SPLIT) != 0;
   hipStream_t s = (hipStream_t)hip_stream;
   std::vector<xv_encoded*> encs(n, nullptr);
   auto cleanup = [&](int r) {
@@ -39,7 +43,7 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
   };
   for (int i = 0; i < n; i++) {
     xv_params q = params[i];
-    q.flags = 0;
+    q.flags = split ? XV_FLAG_SPLIT : 0;
     if ((rc = encode_prepare(&cubes[i], &q, s, &encs[i])) != XV_OK) return cleanup(rc);
   }
   const int N = encs[0]->N, R = params[0].search_range;
@@ -50,10 +54,11 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
     std::vector<SegSrc> src;
     for (auto* e : encs) src.push_back(SegSrc{e, 0});
     const MeGeom g0 = geometry_for(N, R, wb);
-    rc = launch_segments(src, 0, g0, [&](const LaunchDesc& d, double) {
-      XV_HIP(launch_encode(N, d, s), "transform kernel");
-      return XV_OK;
-    });
+    rc = split ? launch_split_transform(src, s)
+               : launch_segments(src, 0, g0, [&](const LaunchDesc& d, double) {
+                   XV_HIP(launch_encode(N, d, s), "transform kernel");
+                   return XV_OK;
+                 });
     if (rc != XV_OK) return cleanup(rc);
   }
   // the model's best of each window layout, an equal share of the timed set
@@ -62,8 +67,13 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
   // others
   constexpr int kLayouts = 3;  // XV_ME_COLUMN_PAIRS .. XV_ME_ROW_PAIRS_BY_CHANNEL
   std::vector<std::pair<double, MeGeom>> scored[kLayouts];
-  for (const MeGeom& g : me_candidates(N, R, wb))
-    scored[g.layout - 1].push_back({me_model_score(N, R, g, wb), g});
+  if (split) {
+    for (const MeGeom& g : me_split_candidates(N, R, wb))
+      scored[g.layout - 1].push_back({me_split_model_score(N, R, g, wb), g});
+  } else {
+    for (const MeGeom& g : me_candidates(N, R, wb))
+      scored[g.layout - 1].push_back({me_model_score(N, R, g, wb), g});
+  }
   const size_t keep = (size_t)(max_candidates > 0 ? max_candidates : 512);
   size_t share[kLayouts] = {0, 0, 0};
   for (size_t left = keep, open = kLayouts; left > 0 && open > 0;) {
@@ -81,7 +91,7 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
                      [](const auto& a, const auto& b) { return a.first > b.first; });
     for (size_t i = 0; i < share[l]; i++) cand.push_back(scored[l][i].second);
   }
-  const MeGeom def = geometry_for(N, R, wb);
+  const MeGeom def = split ? split_geometry_for(N, R, wb) : geometry_for(N, R, wb);
   if (std::find_if(cand.begin(), cand.end(), [&](const MeGeom& g) {
         return g.nb == def.nb && g.kx == def.kx && g.threads == def.threads &&
                g.rows == def.rows && g.layout == def.layout;
@@ -97,7 +107,8 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
   auto time_once = [&](const MeGeom& g, float* ms) {
     (void)hipEventRecord(ev0, s);
     int r = launch_segments(src, 1, g, [&](const LaunchDesc& d, double) {
-      XV_HIP(launch_me(N, R, g, d, s), "motion search kernel");
+      XV_HIP(split ? launch_me_split(N, R, g, d, s) : launch_me(N, R, g, d, s),
+             "motion search kernel");
       return XV_OK;
     });
     (void)hipEventRecord(ev1, s);
@@ -147,7 +158,10 @@ int xv_autotune_me_batch(int n, const xv_cube* cubes, const xv_params* params, v
   cleanup(XV_OK);
   if (rc != XV_OK) return rc;
   XV_HIP(hipStreamSynchronize(s), "synchronise tuning");
-  geometry_install(N, R, best);
+  if (split)
+    split_geometry_install(N, R, best);
+  else
+    geometry_install(N, R, best);
   if (out) {
     out->blocks_per_wg = best.nb;
     out->cands_per_lane = best.kx;

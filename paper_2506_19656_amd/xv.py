@@ -111,7 +111,7 @@ EXPORTED = ["xv_abi_version", "xv_status_str", "xv_last_error", "xv_encode_cube"
             "xv_decode_cube", "xv_psnr_bpppb", "xv_psnr_bpppb_batch", "xv_encoded_export",
             "xv_encoded_free",
             "xv_encode_batch", "xv_decode_batch", "xv_set_me_geometry", "xv_get_me_geometry",
-            "xv_autotune_me", "xv_autotune_me_batch", "xv_profile_enable", "xv_profile_select", "xv_profile_read", "xv_server_create",
+            "xv_set_me_split_geometry", "xv_get_me_split_geometry", "xv_autotune_me", "xv_autotune_me_batch", "xv_profile_enable", "xv_profile_select", "xv_profile_read", "xv_server_create",
             "xv_server_submit", "xv_server_poll", "xv_server_wait", "xv_server_cancel",
             "xv_server_stats_read", "xv_server_destroy", "xv_memory_read", "xv_cache_release", "xv_pack", "xv_packed_view",
             "xv_packed_free", "xv_unpack", "xv_ssim", "xv_spectral_angle",
@@ -161,6 +161,9 @@ def lib():
         L.xv_decode_batch.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(Cube), vp]
         L.xv_set_me_geometry.argtypes = [C.c_int, C.c_int, C.POINTER(MeGeometryC)]
         L.xv_get_me_geometry.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(MeGeometryC)]
+        L.xv_set_me_split_geometry.argtypes = [C.c_int, C.c_int, C.POINTER(MeGeometryC)]
+        L.xv_get_me_split_geometry.argtypes = [C.c_int, C.c_int, C.c_int,
+                                               C.POINTER(MeGeometryC)]
         L.xv_autotune_me.argtypes = [C.POINTER(Cube), C.POINTER(ParamsC), vp, C.c_int,
                                      C.POINTER(MeGeometryC), C.POINTER(C.c_double)]
         L.xv_autotune_me_batch.argtypes = [C.c_int, C.POINTER(Cube), C.POINTER(ParamsC), vp,
@@ -473,6 +476,21 @@ def set_me_geometry(block: int, search_range: int, blocks_per_wg=0, cands_per_la
 def get_me_geometry(block: int, search_range: int, width_blocks: int = 0) -> dict:
     g = MeGeometryC()
     _check(lib().xv_get_me_geometry(block, search_range, width_blocks, C.byref(g)))
+    return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
+                threads=g.threads, rows_per_lane=g.rows_per_lane, layout=g.layout)
+
+
+def set_me_split_geometry(block: int, search_range: int, blocks_per_wg=0, cands_per_lane=0,
+                          threads=0, rows_per_lane=0, layout=0):
+    """xv_set_me_split_geometry: the adaptive block size's search (row-pair
+    layouts, 5, 7, 11 or 13 candidates per lane; all zero: default)."""
+    g = MeGeometryC(blocks_per_wg, cands_per_lane, threads, rows_per_lane, layout)
+    _check(lib().xv_set_me_split_geometry(block, search_range, C.byref(g)))
+
+
+def get_me_split_geometry(block: int, search_range: int, width_blocks: int = 0) -> dict:
+    g = MeGeometryC()
+    _check(lib().xv_get_me_split_geometry(block, search_range, width_blocks, C.byref(g)))
     return dict(blocks_per_wg=g.blocks_per_wg, cands_per_lane=g.cands_per_lane,
                 threads=g.threads, rows_per_lane=g.rows_per_lane, layout=g.layout)
 

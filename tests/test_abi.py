@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(xvmod):
 
 def test_abi_version_and_status_strings(xvmod):
     L = xvmod.lib()
-    assert L.xv_abi_version() == 7
+    assert L.xv_abi_version() == 8
     assert L.xv_status_str(0) == b"ok"
     assert L.xv_status_str(-1) == b"invalid argument"
 
@@ -118,6 +118,45 @@ def test_me_geometry_validation(xvmod):
         else:
             assert g["layout"] in (row, xvmod.ME_ROW_PAIRS_BY_CHANNEL) and g["rows_per_lane"] == 1
             assert g["cands_per_lane"] in (2, 3, 4, 5, 6, 7, 8, 9, 11, 13)
+
+
+def test_me_split_geometry_validation(xvmod):
+    col, row, byc = xvmod.ME_COLUMN_PAIRS, xvmod.ME_ROW_PAIRS, xvmod.ME_ROW_PAIRS_BY_CHANNEL
+    bad = [dict(cands_per_lane=6, rows_per_lane=1, layout=col),   # row-pair layouts only
+           dict(cands_per_lane=9, rows_per_lane=1, layout=row),   # 5, 7, 11 or 13 candidates
+           dict(cands_per_lane=5, rows_per_lane=2, layout=row),   # one row
+           # by channel, 13 candidates: 65 x 5 = 325 items per block, one round
+           dict(blocks_per_wg=1, cands_per_lane=13, threads=256, rows_per_lane=1, layout=byc),
+           # 5 candidates: 65 x 13 = 845 items per block, two rounds
+           dict(blocks_per_wg=1, cands_per_lane=5, threads=384, rows_per_lane=1, layout=byc),
+           dict(threads=1024), dict(blocks_per_wg=65)]
+    for kw in bad:
+        with pytest.raises(xvmod.XvError):
+            xvmod.set_me_split_geometry(16, 32, **kw)
+    for N in (4, 12):  # the adaptive block size needs N >= 8
+        with pytest.raises(xvmod.XvError):
+            xvmod.set_me_split_geometry(N, 16)
+    try:
+        xvmod.set_me_split_geometry(16, 32, 1, 13, 384, 1, byc)
+        assert xvmod.get_me_split_geometry(16, 32) == dict(
+            blocks_per_wg=1, cands_per_lane=13, threads=384, rows_per_lane=1, layout=byc)
+        xvmod.set_me_split_geometry(16, 32, 1, 5, 448, 1, byc)  # 845 <= 2 x 448
+        xvmod.set_me_split_geometry(16, 32, 2, 7, 256, 1, row)
+        assert xvmod.get_me_split_geometry(16, 32)["layout"] == row
+        # the plain search's table is a different one
+        assert xvmod.get_me_geometry(16, 32, 64)["cands_per_lane"] != 7 or \
+            xvmod.get_me_geometry(16, 32, 64)["layout"] != row
+    finally:
+        xvmod.set_me_split_geometry(16, 32)
+    for N in (8, 16, 32):
+        for R in (8, 16, 32):
+            g = xvmod.get_me_split_geometry(N, R, 1024 // N)
+            assert g["layout"] in (row, byc) and g["rows_per_lane"] == 1
+            assert g["cands_per_lane"] in (5, 7, 11, 13) and g["threads"] % 64 == 0
+            # the default is one the setter accepts
+            xvmod.set_me_split_geometry(N, R, g["blocks_per_wg"], g["cands_per_lane"],
+                                        g["threads"], 1, g["layout"])
+            xvmod.set_me_split_geometry(N, R)
 
 
 def test_memory_record_and_release_without_device_work(xvmod):

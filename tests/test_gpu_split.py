@@ -159,3 +159,39 @@ def test_split_at_a_large_picture():
     p = xv.Params(bit_depth=10, qp=27, block=16, search_range=8, gop=16, flags=xv.FLAG_SPLIT)
     print("[case] split 1024x1024 N16", flush=True)
     check_cube("split 1024^2", host, p)
+
+
+def test_split_search_geometry_never_changes_outputs():
+    # every combined-search instance (both row-pair layouts, 5, 7, 11 and 13
+    # candidates per lane) at several workgroup shapes, on ragged frames whose
+    # edge cells reach candidates their blocks cannot; one geometry against
+    # the oracle, the others against it
+    for N, R in ((8, 9), (16, 5), (32, 4)):
+        host = _mixed_motion(4, 45 + N, 70 + 2 * N, 4, seed=N + R)
+        cube = torch.from_numpy(host).cuda()
+        p = xv.Params(bit_depth=10, qp=25, block=N, search_range=R, gop=4, flags=xv.FLAG_SPLIT)
+        span = 2 * R + 1
+        ref = None
+        try:
+            for lay in (xv.ME_ROW_PAIRS, xv.ME_ROW_PAIRS_BY_CHANNEL):
+                for kx in (5, 7, 11, 13):
+                    rounds = 1 if kx >= 11 else 2
+                    for nb, th in ((1, 64), (3, 192), (2, 512)):
+                        items = nb * span * (-(-span // kx))
+                        if lay == xv.ME_ROW_PAIRS_BY_CHANNEL and items > rounds * th:
+                            continue
+                        xv.set_me_split_geometry(N, R, nb, kx, th, 1, lay)
+                        print(f"[case] split geometry N{N} R{R} layout{lay} kx{kx} nb{nb} th{th}",
+                              flush=True)
+                        if ref is None:
+                            check_cube(f"split geometry N{N}", host, p)
+                            ref = _digest(xv.encode_cube(cube, p))
+                        else:
+                            assert _digest(xv.encode_cube(cube, p)) == ref, (lay, kx, nb, th)
+            # the tuner on split params installs the combined search's geometry
+            g = xv.autotune_me_batch([cube], [p], max_candidates=6)
+            assert xv.get_me_split_geometry(N, R) == {k: g[k] for k in (
+                "blocks_per_wg", "cands_per_lane", "threads", "rows_per_lane", "layout")}
+            assert _digest(xv.encode_cube(cube, p)) == ref
+        finally:
+            xv.set_me_split_geometry(N, R)
