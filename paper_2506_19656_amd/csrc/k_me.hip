@@ -517,8 +517,19 @@ constexpr int kRpUnrollHalf = N <= 16 ? N / 4 : 2;
 // only candidates invalid for a target read, for that target.  Outputs: the
 // block's vector and SAD to mv_whole / sad_whole, the cells' to the cell
 // grid (mv / sad), exactly what the separate searches at N and N/2 give.
+// Waves per SIMD the register allocator is asked to leave room for: 4 for
+// the plain search (the widest instances otherwise take 3, and every
+// instance reaches 4 without spilling); the launch bound's 2 for the
+// combined search (5 for the instances that reach it, with chunks of one
+// cell column to save registers, measured slower).  Resident waves still
+// depend on LDS and workgroup size.
+template <int SP>
+constexpr int kRpWaves = SP ? 2 : 4;
+
 template <int N, int KX, int RND, int SP = 0>
-__global__ void __launch_bounds__(512) me_rp_kernel(const LaunchDesc jd, int R, int nb) {
+__global__ void __launch_bounds__(512)
+    __attribute__((amdgpu_waves_per_eu(kRpWaves<SP>)))
+    me_rp_kernel(const LaunchDesc jd, int R, int nb) {
   extern __shared__ __align__(16) uint32_t lds[];
   int tl;
   const FrameJob& job = *desc_job(jd, blockIdx.x, tl);
