@@ -137,7 +137,11 @@ def _whole_unit_parity(name, cube, params, gops, groups=None):
     G = (Bn + 2) // 3
     print(f"[case] {name}: oracle stats over {host.size} samples", flush=True)
     mn, mx, nv = O.stats(host)
-    xv.autotune_me_batch([cube] * len(params), params)
+    # each search tuned on its own runs (plain, adaptive block size)
+    for split in (False, True):
+        ps = [p for p in params if bool(p.flags & xv.FLAG_SPLIT) == split]
+        if ps:
+            xv.autotune_me_batch([cube] * len(ps), ps)
     encs = xv.encode_batch([cube] * len(params), params)
     outs = [torch.empty_like(cube) for _ in params]
     xv.decode_batch(encs, outs)
