@@ -252,6 +252,7 @@ struct alignas(16) LdsEnc {
   uint32_t cbits[3][Tile<N>::NBW];
   uint32_t mvbits;
   uint32_t cbsum;
+  uint8_t runs[256];  // kRunTab, for the rate proxy
 };
 
 // Decode works one channel per workgroup (the channels of a frame are
@@ -283,6 +284,29 @@ constexpr ScanTab<N> make_scan_tab() {
 }
 template <int N>
 constexpr ScanTab<N> kScanTab = make_scan_tab<N>();
+
+// Run table of the rate proxy: for an 8-bit mask c of nonzero positions,
+// the sum over its set bits b of floor(log2(b - a)), a the previous set bit
+// (-1 for the first).
+struct alignas(16) RunTab {
+  uint8_t v[256];
+};
+constexpr RunTab make_run_tab() {
+  RunTab t{};
+  for (int c = 0; c < 256; c++) {
+    int prev = -1, sum = 0;
+    for (int b = 0; b < 8; b++)
+      if ((c >> b) & 1) {
+        int g = b - prev, l = 0;
+        while (g >>= 1) l++;
+        sum += l;
+        prev = b;
+      }
+    t.v[c] = (uint8_t)sum;
+  }
+  return t;
+}
+constexpr RunTab kRunTab = make_run_tab();
 
 struct TileCoord {
   const FrameJob* job;
@@ -481,10 +505,20 @@ __device__ inline void inverse_row(const int16_t* Erow, const uint32_t (&pp)[N /
 // The tile holds w = 2|level| + 1.  Lane (b, j) takes scan positions jN ..
 // jN+N-1 of block b.  Each nonzero level at position p with previous nonzero
 // q (-1 if none) costs ue(p-q-1) + se(level) = 128 - 2 (clz(p - q) +
-// clz(|level|)) bits, and clz(|level|) = clz(w) + 1.  A lane adds up count and
-// clz terms with its own segment start as q of its first nonzero, then
-// replaces that term once the last nonzero of the earlier segments is known.
-// Adds 2^17 * count + sum of clz terms to s.cbits[c][b].
+// clz(|level|)) bits, and clz(|level|) = clz(w) + 1.  The lane's terms, with
+// its own segment start as q of its first nonzero, are accumulated as
+// 2^17 * count + sum of the clz terms; that term is replaced once the last
+// nonzero of the earlier segments is known.  Adds the block's total to
+// s.cbits[c][b].
+//
+// The lane reads each w once and keeps two things: S = sum of clz(w) over
+// all N positions (a zero level gives clz(1) = 31) and the mask m of its
+// nonzero positions, built as the sum of min(w, 2) << i less the sum of
+// 1 << i.  Then, with R = sum over m's set bits of floor(log2 gap) (gaps as
+// above, from the 8-bit run table and one correction per further byte of
+// m), the accumulated sum is count (2^17 + 63) - R + S - 31 N: each nonzero
+// contributes 2^17 + 1 + (31 - floor(log2 gap)) + clz(w), and the zero
+// levels' 31 each leave S.
 template <int N>
 __device__ inline void block_bits(LdsEnc<N>& s, uint32_t coded, int c) {
   const int lane = threadIdx.x & 63;
@@ -494,26 +528,55 @@ __device__ inline void block_bits(LdsEnc<N>& s, uint32_t coded, int c) {
   uint32_t acc = 0;
   int prev = -1, first = N;
   if (vb) {
-    uint32_t sc[N];
     const uint32_t* tab = kScanTab<N>.v + j * N;
+    uint32_t S = 0, ml = 0, mh = 0;
+    // groups of at most eight positions (their table offsets and levels in
+    // flight together): registers, hence waves
+    constexpr int GP = N < 8 ? N : 8;
 #pragma unroll
-    for (int q = 0; q < N / 4; q++) {
-      const u32x4 w = gld<u32x4>(tab, 16 * q);
-      sc[4 * q] = w.x;
-      sc[4 * q + 1] = w.y;
-      sc[4 * q + 2] = w.z;
-      sc[4 * q + 3] = w.w;
+    for (int g0 = 0; g0 < N; g0 += GP) {
+      uint32_t sc[GP];
+#pragma unroll
+      for (int q = 0; q < GP / 4; q++) {
+        const u32x4 w = gld<u32x4>(tab, 4 * g0 + 16 * q);
+        sc[4 * q] = w.x;
+        sc[4 * q + 1] = w.y;
+        sc[4 * q + 2] = w.z;
+        sc[4 * q + 3] = w.w;
+      }
+#pragma unroll
+      for (int u = 0; u < GP; u++) {
+        const int i = g0 + u;
+        const uint32_t w = *(const uint16_t*)(tile + sc[u]);  // >= 1
+        S += (uint32_t)__builtin_clz(w);
+        const uint32_t v = min(w, 2u);
+        if (i < 16)
+          ml += v << i;
+        else
+          mh += v << (i - 16);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
+    uint32_t m = ml - (N >= 16 ? 0xffffu : (1u << N) - 1u);
+    if constexpr (N > 16) m |= (mh - 0xffffu) << 16;
+    if (m) {
+      int r = 0;
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-      const uint32_t w = *(const uint16_t*)(tile + sc[i]);
-      const bool nz = w != 1u;
-      // i - prev >= 1 and w >= 1: both counts are defined
-      const uint32_t t = (uint32_t)__builtin_clz((uint32_t)(i - prev)) + (uint32_t)__builtin_clz(w) +
-                         ((1u << 17) + 1u);
-      acc += nz ? t : 0u;
-      first = min(first, nz ? i : N);
-      prev = nz ? i : prev;
+      for (int k = 0; k < (N + 7) / 8; k++) {
+        const uint32_t ck = (m >> (8 * k)) & 0xffu;
+        r += s.runs[ck];
+        if (k > 0 && ck) {
+          // the byte's first gap runs from the last set bit below it
+          const uint32_t lo = m & ((1u << (8 * k)) - 1u);
+          const int last = lo ? 31 - __builtin_clz(lo) : -1;
+          const int f = __builtin_ctz(ck);
+          r += (31 - __builtin_clz((uint32_t)(8 * k + f - last))) -
+               (31 - __builtin_clz((uint32_t)(f + 1)));
+        }
+      }
+      acc = (uint32_t)__builtin_popcount(m) * ((1u << 17) + 63u) - (uint32_t)r + S - 31u * N;
+      first = __builtin_ctz(m);
+      prev = 31 - __builtin_clz(m);
     }
   }
   // last nonzero of the nearest earlier segment of the same block
@@ -637,9 +700,13 @@ encode_kernel(const LaunchDesc jr) {
   const int x0 = bx * N;
   const int y = tc.by * N + r;
   const uint32_t blk = (uint32_t)(tc.by * tc.Wb + bx);                  // block index in a plane
-  const uint32_t row_off = ((uint32_t)(c * job.Hp + y) * (uint32_t)job.Wp + (uint32_t)x0);  // samples
+  // byte offset of the thread's row; opaque to the compiler, so that the
+  // sample offset is not kept beside it (the kernel is at its register limit)
+  uint32_t row_b = 2u * ((uint32_t)(c * job.Hp + y) * (uint32_t)job.Wp + (uint32_t)x0);
+  asm volatile("" : "+v"(row_b));
   if (t < 3) s.sse[t] = 0ull;
   if (t < 3 * NBW) s.cbits[t / NBW][t % NBW] = 0u;
+  if (t < 64) ((uint32_t*)s.runs)[t] = gld<uint32_t>(kRunTab.v, 4u * (uint32_t)t);
   if (t == 0) {
     s.mvbits = 0u;
     s.cbsum = 0u;
@@ -654,7 +721,7 @@ encode_kernel(const LaunchDesc jr) {
   // stored transposed.
   uint32_t cp[N / 2], pp[N / 2];
   if (code) {
-    load_row_packed<N>(job.cur, 2u * row_off, cp);
+    load_row_packed<N>(job.cur, row_b, cp);
     pred_row<N>(job, c, r, y, x0, dx, dy, pp);
     uint32_t er[N / 2];
 #pragma unroll
@@ -732,9 +799,9 @@ encode_kernel(const LaunchDesc jr) {
 #pragma unroll
       for (int j = 0; j < N / 2; j++) rp[j] = pp[j];
     }
-    store_row_packed<N>(job.rec, 2u * row_off, rp);
+    store_row_packed<N>(job.rec, row_b, rp);
     if (c < job.nch && y < job.H) {
-      const uint32_t sse = usemask ? row_sse<N, true>(cp, rp, job.vmask, row_off, x0, job.W)
+      const uint32_t sse = usemask ? row_sse<N, true>(cp, rp, job.vmask, row_b >> 1, x0, job.W)
                                    : row_sse<N, false>(cp, rp, nullptr, 0, x0, job.W);
       if (sse) atomicAdd(&s.sse[c], (unsigned long long)sse);
     }
