@@ -79,6 +79,23 @@ __device__ inline int dot2(uint32_t c, uint32_t x, int acc) {
   return __builtin_amdgcn_sdot2(as_v(c), as_v(x), acc, false);
 }
 
+// The first product of a sum: the same operation in its three-operand form
+// with the constant pair in a scalar register and the start value in a
+// vector register (or zero), so that no vector move initialises the
+// accumulator (the two-operand form accumulates into its destination).
+template <uint32_t C>
+__device__ inline int dot2_first(uint32_t x, int acc) {
+  int r;
+  asm("v_dot2_i32_i16 %0, %1, %2, %3" : "=v"(r) : "s"(C), "v"(x), "v"(acc));
+  return r;
+}
+template <uint32_t C>
+__device__ inline int dot2_first0(uint32_t x) {
+  int r;
+  asm("v_dot2_i32_i16 %0, %1, %2, 0" : "=v"(r) : "s"(C), "v"(x));
+  return r;
+}
+
 template <int N>
 struct Tile {
   static constexpr int NBW = 64 / N;    // blocks per workgroup along x
@@ -104,7 +121,7 @@ __device__ inline void fwd_part(const uint32_t (&xp)[n / 2], Out& out, int rnd) 
   if constexpr (n == 4) {
     unroll<4>([&](auto kk) XV_INLINE {
       constexpr int k = kk;
-      int a = dot2(kPair<4, k, 0, k, 1>, xp[0], rnd);
+      int a = dot2_first<kPair<4, k, 0, k, 1>>(xp[0], rnd);
       a = dot2(kPair<4, k, 2, k, 3>, xp[1], a);
       out[S * k] = a;
     });
@@ -119,9 +136,9 @@ __device__ inline void fwd_part(const uint32_t (&xp)[n / 2], Out& out, int rnd) 
     });
     unroll<n / 2>([&](auto kk) XV_INLINE {
       constexpr int k = 2 * kk + 1;
-      int a = rnd;
-      unroll<n / 4>([&](auto jj) XV_INLINE {
-        constexpr int j = jj;
+      int a = dot2_first<kPair<n, k, 0, k, 1>>(op[0], rnd);
+      unroll<n / 4 - 1>([&](auto jj) XV_INLINE {
+        constexpr int j = jj + 1;
         a = dot2(kPair<n, k, 2 * j, k, 2 * j + 1>, op[j], a);
       });
       out[S * k] = a;
@@ -143,7 +160,7 @@ __device__ inline void inv_part(const uint32_t* ip, int (&out)[n], int rnd) {
   if constexpr (n == 4) {
     unroll<4>([&](auto mm) XV_INLINE {
       constexpr int m = mm;
-      int a = dot2(kPair<4, 0, m, 1, m>, ip[0], rnd);
+      int a = dot2_first<kPair<4, 0, m, 1, m>>(ip[0], rnd);
       a = dot2(kPair<4, 2, m, 3, m>, ip[1], a);
       out[m] = a;
     });
@@ -152,9 +169,9 @@ __device__ inline void inv_part(const uint32_t* ip, int (&out)[n], int rnd) {
     inv_part<n / 2>(ip + n / 4, E, rnd);
     unroll<n / 2>([&](auto mm) XV_INLINE {
       constexpr int m = mm;
-      int o = 0;
-      unroll<n / 4>([&](auto jj) XV_INLINE {
-        constexpr int j = jj;
+      int o = dot2_first0<kPair<n, 1, m, 3, m>>(ip[0]);
+      unroll<n / 4 - 1>([&](auto jj) XV_INLINE {
+        constexpr int j = jj + 1;
         o = dot2(kPair<n, 4 * j + 1, m, 4 * j + 3, m>, ip[j], o);
       });
       out[m] = E[m] + o;
@@ -206,9 +223,9 @@ template <int N>
 __device__ inline void fwd_product(const uint32_t (&t)[N / 2], ivec<N>& out, int rnd) {
   unroll<N>([&](auto ll) XV_INLINE {
     constexpr int l = ll;
-    int a = rnd;
-    unroll<N / 2>([&](auto jj) XV_INLINE {
-      constexpr int j = jj;
+    int a = dot2_first<kPair<N, l, 0, l, 1>>(t[0], rnd);
+    unroll<N / 2 - 1>([&](auto jj) XV_INLINE {
+      constexpr int j = jj + 1;
       a = dot2(kPair<N, l, 2 * j, l, 2 * j + 1>, t[j], a);
     });
     out[l] = a;
