@@ -240,13 +240,13 @@ __device__ inline void fwd_column(const uint32_t* tp, ivec<N>& out, int rnd) {
   bool fast = false;
   if constexpr (N >= 16) {
     constexpr short kLim = (short)(32767 >> (ilog2c(N) - 2));
-    s16x2 mx = {0, 0};
+    s16x2 mx = as_v(t[0]), mn = as_v(t[0]);
 #pragma unroll
-    for (int j = 0; j < N / 2; j++) {
-      const s16x2 v = as_v(t[j]);  // |T| < 2^15 (row-stage headroom), so -v is exact
-      mx = __builtin_elementwise_max(mx, __builtin_elementwise_max(v, -v));
+    for (int j = 1; j < N / 2; j++) {
+      mx = __builtin_elementwise_max(mx, as_v(t[j]));
+      mn = __builtin_elementwise_min(mn, as_v(t[j]));
     }
-    fast = __all(mx.x <= kLim && mx.y <= kLim);
+    fast = __all(max(mx.x, mx.y) <= kLim && min(mn.x, mn.y) >= -kLim);
   }
   if (fast)
     fwd_part<N, 1>(t, out, rnd);
@@ -643,12 +643,21 @@ __device__ inline uint32_t row_sse(const uint32_t (&cp)[N / 2], const uint32_t (
       pm[j] = __umul24(t, 0xffffu);
     }
   }
+  int sse = 0;  // at most 32 * 4095^2 < 2^31
+  if (!kMask && x0 + N <= W) {
+    // every sample valid: no mask
+#pragma unroll
+    for (int j = 0; j < N / 2; j++) {
+      const uint32_t d = psub(cp[j], rp[j]);
+      sse = dot2(d, d, sse);
+    }
+    return (uint32_t)sse;
+  }
   if (x0 + N > W) {
 #pragma unroll
     for (int j = 0; j < N / 2; j++)
       pm[j] &= (x0 + 2 * j < W ? 0xffffu : 0u) | (x0 + 2 * j + 1 < W ? 0xffff0000u : 0u);
   }
-  int sse = 0;  // at most 32 * 4095^2 < 2^31
 #pragma unroll
   for (int j = 0; j < N / 2; j++) {
     const uint32_t d = psub(cp[j], rp[j]) & pm[j];
@@ -769,12 +778,23 @@ encode_kernel(const LaunchDesc jr) {
     fwd_column<N>(row, acc, 1 << (L2N + 5));
     // level = sgn(C) min(32767, (|C| Qf + off) >> qbits) in signed form:
     // C >= 0: (C Qf + off) >> qbits; C < 0: (C Qf + 2^qbits - 1 - off) >> qbits
-    // (|C Qf| < 2^30, so nothing overflows)
+    // (|C Qf| < 2^30, so nothing overflows).  |C| <= 2^15 (the DC row's 64 N
+    // is the largest absolute row sum of M, and |T| <= 2^15), so with
+    // qbits >= 15 every |level| is at most 2^15 Qf / 2^15 + 1 <= 26215 and
+    // the clamp cannot act: a wave-uniform branch leaves it out.
+    if (qbits >= 15) {
 #pragma unroll
-    for (int l = 0; l < N; l++) {
-      const int C = acc[l] >> (L2N + 6);
-      const int v = (__mul24(C, qf) + (C >= 0 ? off : offn)) >> qbits;
-      lv[l] = min(max(v, -32767), 32767);
+      for (int l = 0; l < N; l++) {
+        const int C = acc[l] >> (L2N + 6);
+        lv[l] = (__mul24(C, qf) + (C >= 0 ? off : offn)) >> qbits;
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < N; l++) {
+        const int C = acc[l] >> (L2N + 6);
+        const int v = (__mul24(C, qf) + (C >= 0 ? off : offn)) >> qbits;
+        lv[l] = min(max(v, -32767), 32767);
+      }
     }
     // levels out; the tile row gets 2|level| + 1 (never zero) for the rate proxy
     uint32_t lpair[N / 2];
