@@ -646,12 +646,23 @@ __device__ inline void store_run_g(T* __restrict__ p, const T (&q)[G], bool alig
     if (i < n) p[i] = q[i];
 }
 
-// Conversion and packing of one pixel group per thread over the padded
-// frame (rows past H replicate row H - 1, columns past W column W - 1).
+// Pixel groups a thread of the vectorised u16 kernels takes (groups of ne
+// elements): their loads are issued together, so that enough bytes are in
+// flight to keep HBM busy -- about 32 elements per thread, at most 4
+// groups.  The f32 kernels, whose conversions take a binary64 division per
+// sample, keep one group (more measured slower).
+__host__ __device__ constexpr int vec_unroll(int elem, int ne) {
+  return elem != 2 ? 1 : ne >= 32 ? 1 : (32 / ne > 4 ? 4 : 32 / ne);
+}
+
+// Conversion and packing over the padded frame (rows past H replicate row
+// H - 1, columns past W column W - 1): vec_unroll pixel groups per thread,
+// blockDim.x groups apart, their input loads issued together.
 template <typename Tv, int BANDS>
 __global__ void __launch_bounds__(kThreads) pack_vec_kernel(PackArgs a) {
   using PG = PixGroup<Tv, BANDS>;
   constexpr int G = PG::g;
+  constexpr int kVecUnroll = vec_unroll((int)sizeof(Tv), PG::ne);
   __shared__ double smn[BANDS], srg[BANDS], sinv[BANDS];
   __shared__ int sall[BANDS];
   const bool gaps = sizeof(Tv) == 4 && *a.nan_total != 0u;
@@ -664,143 +675,184 @@ __global__ void __launch_bounds__(kThreads) pack_vec_kernel(PackArgs a) {
   }
   __syncthreads();
   const int gpr = (a.Wp + G - 1) / G;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= a.T * a.Hp * gpr) return;
-  const int64_t row = gid / gpr;
-  const int x0 = (int)(gid - row * gpr) * G;
-  const int64_t t = row / a.Hp;
-  const int y = (int)(row - t * a.Hp);
-  const int64_t ys = y < a.H ? y : a.H - 1;
+  const int64_t total = a.T * a.Hp * gpr;
+  const int64_t gid0 = (int64_t)blockIdx.x * blockDim.x * kVecUnroll + threadIdx.x;
   const Tv* d = (const Tv*)a.data;
   const int64_t fstride = a.H * a.W * BANDS;
-  const Tv* src = d + t * fstride + ys * a.W * BANDS;
-  Tv v[PG::ne];
-  if (x0 + G <= a.W) {
-    load_granules<Tv, PG::ne>(src + (int64_t)x0 * BANDS, v);
-  } else {
+  Tv vs[kVecUnroll][PG::ne];
+  int64_t ts[kVecUnroll];
+  int x0s[kVecUnroll], y_s[kVecUnroll];
 #pragma unroll
-    for (int p = 0; p < G; p++) {
-      const int xs = min(x0 + p, (int)a.W - 1);
+  for (int u = 0; u < kVecUnroll; u++) {
+    const int64_t gid = gid0 + (int64_t)u * blockDim.x;
+    if (gid >= total) break;
+    const int64_t row = gid / gpr;
+    const int x0 = (int)(gid - row * gpr) * G;
+    const int64_t t = row / a.Hp;
+    const int y = (int)(row - t * a.Hp);
+    ts[u] = t;
+    x0s[u] = x0;
+    y_s[u] = y;
+    const int64_t ys = y < a.H ? y : a.H - 1;
+    const Tv* src = d + t * fstride + ys * a.W * BANDS;
+    if (x0 + G <= a.W) {
+      load_granules<Tv, PG::ne>(src + (int64_t)x0 * BANDS, vs[u]);
+    } else {
 #pragma unroll
-      for (int b = 0; b < BANDS; b++) v[p * BANDS + b] = src[(int64_t)xs * BANDS + b];
-    }
-  }
-  const double L = (double)((1 << a.bit_depth) - 1);
-  uint16_t q[BANDS][G];
-  uint8_t ok[BANDS][G];
-  // samples as float: u16 values and the minimum of a float band are exact
-  // there, and a filled sample is an input float
-  float dv[G][8];
-  uint32_t miss[G];
+      for (int p = 0; p < G; p++) {
+        const int xs = min(x0 + p, (int)a.W - 1);
 #pragma unroll
-  for (int p = 0; p < G; p++) {
-    miss[p] = 0u;
-#pragma unroll
-    for (int b = 0; b < BANDS; b++) {
-      if constexpr (sizeof(Tv) == 2) {
-        dv[p][b] = (float)v[p * BANDS + b];
-      } else {
-        const float f = v[p * BANDS + b];
-        const bool nan = f != f;
-        dv[p][b] = nan ? (float)smn[b] : f;
-        miss[p] |= (nan && !sall[b]) ? (1u << b) : 0u;
+        for (int b = 0; b < BANDS; b++) vs[u][p * BANDS + b] = src[(int64_t)xs * BANDS + b];
       }
     }
   }
-  if constexpr (sizeof(Tv) == 4) {
-    uint32_t any = 0u;
 #pragma unroll
-    for (int p = 0; p < G; p++) any |= miss[p];
-    if (any) {
-      int64_t dd0 = 1;
-      if (a.fill_mode == XV_FILL_NEAREST) {
-        // the usual case resolves at distance 1: load times t - 1 and t + 1
-        // of the group's pixels together, take t - 1 where valid, else
-        // t + 1, and search further only for what is still missing
-        const float* df = (const float*)d;
-        float fm[PG::ne], fp[PG::ne];
-        const bool hm = t >= 1, hp = t + 1 < a.T;
+  for (int u = 0; u < kVecUnroll; u++) {
+    if (gid0 + (int64_t)u * blockDim.x >= total) break;
+    const int64_t t = ts[u];
+    const int x0 = x0s[u];
+    const int y = y_s[u];
+    const int64_t ys = y < a.H ? y : a.H - 1;
+    const Tv(&v)[PG::ne] = vs[u];
+    const double L = (double)((1 << a.bit_depth) - 1);
+    uint16_t q[BANDS][G];
+    uint8_t ok[BANDS][G];
+    // samples as float: u16 values and the minimum of a float band are exact
+    // there, and a filled sample is an input float
+    float dv[G][8];
+    uint32_t miss[G];
 #pragma unroll
-        for (int p = 0; p < G; p++) {
-          const int64_t px = (ys * a.W + min(x0 + p, (int)a.W - 1)) * BANDS;
+    for (int p = 0; p < G; p++) {
+      miss[p] = 0u;
 #pragma unroll
-          for (int b = 0; b < BANDS; b++) {
-            fm[p * BANDS + b] = hm ? df[(t - 1) * fstride + px + b] : __builtin_nanf("");
-            fp[p * BANDS + b] = hp ? df[(t + 1) * fstride + px + b] : __builtin_nanf("");
+      for (int b = 0; b < BANDS; b++) {
+        if constexpr (sizeof(Tv) == 2) {
+          dv[p][b] = (float)v[p * BANDS + b];
+        } else {
+          const float f = v[p * BANDS + b];
+          const bool nan = f != f;
+          dv[p][b] = nan ? (float)smn[b] : f;
+          miss[p] |= (nan && !sall[b]) ? (1u << b) : 0u;
+        }
+      }
+    }
+    if constexpr (sizeof(Tv) == 4) {
+      uint32_t any = 0u;
+#pragma unroll
+      for (int p = 0; p < G; p++) any |= miss[p];
+      if (any) {
+        int64_t dd0 = 1;
+        if (a.fill_mode == XV_FILL_NEAREST) {
+          // the usual case resolves at distance 1: load times t - 1 and t + 1
+          // of the group's pixels together, take t - 1 where valid, else
+          // t + 1, and search further only for what is still missing
+          const float* df = (const float*)d;
+          float fm[PG::ne], fp[PG::ne];
+          const bool hm = t >= 1, hp = t + 1 < a.T;
+#pragma unroll
+          for (int p = 0; p < G; p++) {
+            const int64_t px = (ys * a.W + min(x0 + p, (int)a.W - 1)) * BANDS;
+#pragma unroll
+            for (int b = 0; b < BANDS; b++) {
+              fm[p * BANDS + b] = hm ? df[(t - 1) * fstride + px + b] : __builtin_nanf("");
+              fp[p * BANDS + b] = hp ? df[(t + 1) * fstride + px + b] : __builtin_nanf("");
+            }
           }
+#pragma unroll
+          for (int p = 0; p < G; p++)
+#pragma unroll
+            for (int b = 0; b < BANDS; b++) {
+              const float m = fm[p * BANDS + b], n = fp[p * BANDS + b];
+              if ((miss[p] >> b) & 1u) {
+                if (m == m) {
+                  dv[p][b] = m;
+                  miss[p] &= ~(1u << b);
+                } else if (n == n) {
+                  dv[p][b] = n;
+                  miss[p] &= ~(1u << b);
+                }
+              }
+            }
+          dd0 = 2;
         }
 #pragma unroll
         for (int p = 0; p < G; p++)
-#pragma unroll
-          for (int b = 0; b < BANDS; b++) {
-            const float m = fm[p * BANDS + b], n = fp[p * BANDS + b];
-            if ((miss[p] >> b) & 1u) {
-              if (m == m) {
-                dv[p][b] = m;
-                miss[p] &= ~(1u << b);
-              } else if (n == n) {
-                dv[p][b] = n;
-                miss[p] &= ~(1u << b);
-              }
-            }
+          if (miss[p]) {
+            const int xs = min(x0 + p, (int)a.W - 1);
+            fill_missing((const float*)d, (ys * a.W + xs) * BANDS, BANDS, fstride, t, a.T, a.fill_mode,
+                         miss[p], dv[p], dd0);
           }
-        dd0 = 2;
       }
-#pragma unroll
-      for (int p = 0; p < G; p++)
-        if (miss[p]) {
-          const int xs = min(x0 + p, (int)a.W - 1);
-          fill_missing((const float*)d, (ys * a.W + xs) * BANDS, BANDS, fstride, t, a.T, a.fill_mode,
-                       miss[p], dv[p], dd0);
-        }
     }
-  }
 #pragma unroll
-  for (int p = 0; p < G; p++) {
-    const bool real = y < a.H && x0 + p < a.W;
+    for (int p = 0; p < G; p++) {
+      const bool real = y < a.H && x0 + p < a.W;
+#pragma unroll
+      for (int b = 0; b < BANDS; b++) {
+        q[b][p] = convert((double)dv[p][b], smn[b], srg[b], sinv[b], L);
+        bool valid = true;
+        if constexpr (sizeof(Tv) == 4) {
+          const float f = v[p * BANDS + b];
+          valid = f == f;
+        }
+        ok[b][p] = (uint8_t)(valid && real);
+      }
+    }
+    const int64_t plane = (int64_t)a.Hp * a.Wp;
+    const int64_t o = (int64_t)y * a.Wp + x0;
+    const bool al = (a.Wp % G) == 0;
+    const int n = min(G, a.Wp - x0);
 #pragma unroll
     for (int b = 0; b < BANDS; b++) {
-      q[b][p] = convert((double)dv[p][b], smn[b], srg[b], sinv[b], L);
-      bool valid = true;
-      if constexpr (sizeof(Tv) == 4) {
-        const float f = v[p * BANDS + b];
-        valid = f == f;
-      }
-      ok[b][p] = (uint8_t)(valid && real);
+      const int g = b / 3, c = b - 3 * g;
+      const int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
+      store_run_g<G>(a.frames + off, q[b], al, n);
+      if (gaps) store_run_g<G>(a.vmask + off, ok[b], al, n);
     }
-  }
-  const int64_t plane = (int64_t)a.Hp * a.Wp;
-  const int64_t o = (int64_t)y * a.Wp + x0;
-  const bool al = (a.Wp % G) == 0;
-  const int n = min(G, a.Wp - x0);
+    constexpr int GL = (BANDS - 1) / 3;  // last group
+    uint16_t z[G];
+    uint8_t zm[G];
 #pragma unroll
-  for (int b = 0; b < BANDS; b++) {
-    const int g = b / 3, c = b - 3 * g;
-    const int64_t off = ((int64_t)(g * a.T + t) * 3 + c) * plane + o;
-    store_run_g<G>(a.frames + off, q[b], al, n);
-    if (gaps) store_run_g<G>(a.vmask + off, ok[b], al, n);
-  }
-  constexpr int GL = (BANDS - 1) / 3;  // last group
-  uint16_t z[G];
-  uint8_t zm[G];
+    for (int p = 0; p < G; p++) {
+      z[p] = a.pad_mode == XV_PAD_REPEAT ? q[BANDS - 1][p] : (uint16_t)0;
+      zm[p] = 0;
+    }
 #pragma unroll
-  for (int p = 0; p < G; p++) {
-    z[p] = a.pad_mode == XV_PAD_REPEAT ? q[BANDS - 1][p] : (uint16_t)0;
-    zm[p] = 0;
-  }
-#pragma unroll
-  for (int c = BANDS - 3 * GL; c < 3; c++) {
-    const int64_t off = ((int64_t)(GL * a.T + t) * 3 + c) * plane + o;
-    store_run_g<G>(a.frames + off, z, al, n);
-    if (gaps) store_run_g<G>(a.vmask + off, zm, al, n);
+    for (int c = BANDS - 3 * GL; c < 3; c++) {
+      const int64_t off = ((int64_t)(GL * a.T + t) * 3 + c) * plane + o;
+      store_run_g<G>(a.frames + off, z, al, n);
+      if (gaps) store_run_g<G>(a.vmask + off, zm, al, n);
+    }
   }
 }
 
-// Decoded frames back to the caller's dtype, one pixel group per thread.
+
+// A decoded sample back to u16: floor(mn + q R / L + 1/2) clamped to
+// [0, 65535], each operation rounded as written.  For a band range below
+// 2^16 the quotient is taken as a product with 1/L: it then differs from
+// the IEEE quotient by under 2^-35, and so does the sum for every x that
+// does not clamp (|x| < 2^17), which changes the floor only when x + 1/2
+// lies within 2^-20 of an integer; there the exact division is taken.
+__device__ inline double to_u16_sample(uint32_t q, double mn, double range, double L, double invL) {
+  const double num = (double)q * range;  // q < 2^12, range < 2^16 when it matters: exact
+  if (range < 65536.0) {
+    const double w = (mn + num * invL) + 0.5;
+    const double f = floor(w);
+    const double fr = w - f;
+    if (fr >= 0x1p-20 && fr <= 1.0 - 0x1p-20) return f < 0.0 ? 0.0 : (f > 65535.0 ? 65535.0 : f);
+  }
+  const double rr = floor((mn + num / L) + 0.5);
+  return rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
+}
+
+// Decoded frames back to the caller's dtype, vec_unroll pixel groups per
+// thread (groups blockDim.x apart, so that each load instruction of a wave
+// stays contiguous).
 template <typename To, int BANDS>
 __global__ void __launch_bounds__(kThreads) denorm_vec_kernel(DenormArgs a) {
   using PG = PixGroup<To, BANDS>;
   constexpr int G = PG::g;
+  constexpr int kVecUnroll = vec_unroll((int)sizeof(To), PG::ne);
   __shared__ double smn[BANDS], srg[BANDS];
   if (threadIdx.x < BANDS) {
     smn[threadIdx.x] = a.mn[threadIdx.x];
@@ -808,46 +860,59 @@ __global__ void __launch_bounds__(kThreads) denorm_vec_kernel(DenormArgs a) {
   }
   __syncthreads();
   const int gpr = (int)(a.W / G);
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= a.T * a.H * gpr) return;
-  const int64_t row = gid / gpr;
-  const int x0 = (int)(gid - row * gpr) * G;
-  const int64_t t = row / a.H;
-  const int64_t y = row - t * a.H;
+  const int64_t total = a.T * a.H * gpr;
+  const int64_t gid0 = (int64_t)blockIdx.x * blockDim.x * kVecUnroll + threadIdx.x;
   const int64_t plane = (int64_t)a.Hp * a.Wp;
   const bool al = (a.Wp % G) == 0;
   const double L = (double)((1 << a.bit_depth) - 1);
-  uint16_t q[BANDS][G];
+  const double invL = 1.0 / L;
+  uint16_t q[kVecUnroll][BANDS][G];
+  int64_t rows[kVecUnroll];
+  int xs[kVecUnroll];
 #pragma unroll
-  for (int b = 0; b < BANDS; b++) {
-    const int g = b / 3, c = b - 3 * g;
-    load_run_g<G>(a.recon + ((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x0, q[b], al);
-  }
-  To v[PG::ne];
-#pragma unroll
-  for (int p = 0; p < G; p++) {
+  for (int u = 0; u < kVecUnroll; u++) {
+    const int64_t gid = gid0 + (int64_t)u * blockDim.x;
+    if (gid >= total) break;
+    const int64_t row = gid / gpr;
+    const int x0 = (int)(gid - row * gpr) * G;
+    const int64_t t = row / a.H;
+    const int64_t y = row - t * a.H;
+    rows[u] = row;
+    xs[u] = x0;
 #pragma unroll
     for (int b = 0; b < BANDS; b++) {
-      const double num = (double)q[b][p] * srg[b];
-      const double x = smn[b] + num / L;
-      if constexpr (sizeof(To) == 2) {
-        double rr = floor(x + 0.5);
-        rr = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
-        v[p * BANDS + b] = (To)rr;
-      } else {
-        v[p * BANDS + b] = (To)x;
-      }
+      const int g = b / 3, c = b - 3 * g;
+      load_run_g<G>(a.recon + ((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x0, q[u][b], al);
     }
   }
-  store_granules<To, PG::ne>((To*)a.out + (row * a.W + x0) * BANDS, v);
+#pragma unroll
+  for (int u = 0; u < kVecUnroll; u++) {
+    if (gid0 + (int64_t)u * blockDim.x >= total) break;
+    To v[PG::ne];
+#pragma unroll
+    for (int p = 0; p < G; p++) {
+#pragma unroll
+      for (int b = 0; b < BANDS; b++) {
+        if constexpr (sizeof(To) == 2) {
+          v[p * BANDS + b] = (To)to_u16_sample(q[u][b][p], smn[b], srg[b], L, invL);
+        } else {
+          const double num = (double)q[u][b][p] * srg[b];
+          v[p * BANDS + b] = (To)(smn[b] + num / L);
+        }
+      }
+    }
+    store_granules<To, PG::ne>((To*)a.out + (rows[u] * a.W + xs[u]) * BANDS, v);
+  }
 }
 
-// Physical squared error, one pixel group per thread and step of a
-// grid-stride loop; per-band sums in registers, fixed LDS tree per block.
+// Physical squared error, vec_unroll pixel groups per thread and step of a
+// grid-stride loop (their loads issued together); per-band sums in
+// registers, fixed LDS tree per block.
 template <typename Tv, int BANDS>
 __global__ void __launch_bounds__(kThreads) phys_vec_kernel(PhysArgs a) {
   using PG = PixGroup<Tv, BANDS>;
   constexpr int G = PG::g;
+  constexpr int kVecUnroll = vec_unroll((int)sizeof(Tv), PG::ne);
   __shared__ double sred[kThreads];
   __shared__ double smn[BANDS], srg[BANDS];
   if (threadIdx.x < BANDS) {
@@ -860,40 +925,48 @@ __global__ void __launch_bounds__(kThreads) phys_vec_kernel(PhysArgs a) {
   const int64_t plane = (int64_t)a.Hp * a.Wp;
   const bool al = (a.Wp % G) == 0;
   const double L = (double)((1 << a.bit_depth) - 1);
+  const double invL = 1.0 / L;
   const Tv* orig = (const Tv*)a.orig;
   double acc[BANDS];
 #pragma unroll
   for (int b = 0; b < BANDS; b++) acc[b] = 0.0;
-  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
-       gid += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = gid / gpr;
-    const int x0 = (int)(gid - row * gpr) * G;
-    const int64_t t = row / a.H;
-    const int64_t y = row - t * a.H;
-    Tv v[PG::ne];
-    load_granules<Tv, PG::ne>(orig + (row * a.W + x0) * BANDS, v);
-    uint16_t q[BANDS][G];
+  for (int64_t gid0 = (int64_t)blockIdx.x * blockDim.x * kVecUnroll + threadIdx.x; gid0 < total;
+       gid0 += (int64_t)gridDim.x * blockDim.x * kVecUnroll) {
+    Tv v[kVecUnroll][PG::ne];
+    uint16_t q[kVecUnroll][BANDS][G];
 #pragma unroll
-    for (int b = 0; b < BANDS; b++) {
-      const int g = b / 3, c = b - 3 * g;
-      load_run_g<G>(a.recon + ((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x0, q[b], al);
-    }
-#pragma unroll
-    for (int p = 0; p < G; p++) {
+    for (int u = 0; u < kVecUnroll; u++) {
+      const int64_t gid = gid0 + (int64_t)u * blockDim.x;
+      if (gid >= total) break;
+      const int64_t row = gid / gpr;
+      const int x0 = (int)(gid - row * gpr) * G;
+      const int64_t t = row / a.H;
+      const int64_t y = row - t * a.H;
+      load_granules<Tv, PG::ne>(orig + (row * a.W + x0) * BANDS, v[u]);
 #pragma unroll
       for (int b = 0; b < BANDS; b++) {
-        const double xv = (double)v[p * BANDS + b];
-        const double num = (double)q[b][p] * srg[b];
-        const double x = smn[b] + num / L;
-        double xh;
-        if constexpr (sizeof(Tv) == 2) {
-          const double rr = floor(x + 0.5);
-          xh = rr < 0.0 ? 0.0 : (rr > 65535.0 ? 65535.0 : rr);
-        } else {
-          xh = (double)(float)x;
+        const int g = b / 3, c = b - 3 * g;
+        load_run_g<G>(a.recon + ((int64_t)(g * a.T + t) * 3 + c) * plane + y * a.Wp + x0, q[u][b], al);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; u++) {
+      if (gid0 + (int64_t)u * blockDim.x >= total) break;
+#pragma unroll
+      for (int p = 0; p < G; p++) {
+#pragma unroll
+        for (int b = 0; b < BANDS; b++) {
+          const double xv = (double)v[u][p * BANDS + b];
+          double xh;
+          if constexpr (sizeof(Tv) == 2) {
+            xh = to_u16_sample(q[u][b][p], smn[b], srg[b], L, invL);
+          } else {
+            const double num = (double)q[u][b][p] * srg[b];
+            xh = (double)(float)(smn[b] + num / L);
+          }
+          const double e = xv - xh;
+          acc[b] = (xv == xv) ? acc[b] + e * e : acc[b];
         }
-        const double e = xv - xh;
-        acc[b] = (xv == xv) ? acc[b] + e * e : acc[b];
       }
     }
   }
@@ -1100,7 +1173,8 @@ hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
   const int g = group_px(elem, a.bands);
   if (a.bands <= 8 && ((uintptr_t)a.data & 15) == 0 && a.W % g == 0) {
     const int64_t n = a.T * a.Hp * (int64_t)((a.Wp + g - 1) / g);
-    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
+    const int per = kThreads * vec_unroll(elem, g * a.bands);
+    const unsigned grid = (unsigned)((n + per - 1) / per);
     if (a.dtype == XV_U16) {
 #define XV_CALL(B) pack_vec_kernel<uint16_t, B><<<grid, kThreads, 0, s>>>(a)
       XV_BANDS_SWITCH(a.bands, XV_CALL)
@@ -1126,7 +1200,8 @@ hipError_t launch_denorm(const DenormArgs& a, hipStream_t s) {
   const int g = group_px(elem, a.bands);
   if (a.bands <= 8 && ((uintptr_t)a.out & 15) == 0 && a.W % g == 0) {
     const int64_t n = a.T * a.H * (a.W / g);
-    const unsigned grid = (unsigned)((n + kThreads - 1) / kThreads);
+    const int per = kThreads * vec_unroll(elem, g * a.bands);
+    const unsigned grid = (unsigned)((n + per - 1) / per);
     if (a.out_dtype == XV_U16) {
 #define XV_CALL(B) denorm_vec_kernel<uint16_t, B><<<grid, kThreads, 0, s>>>(a)
       XV_BANDS_SWITCH(a.bands, XV_CALL)
