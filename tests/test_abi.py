@@ -159,6 +159,22 @@ def test_me_split_geometry_validation(xvmod):
             xvmod.set_me_split_geometry(N, R)
 
 
+def test_tuner_refuses_mixed_batches_before_any_device_work(xvmod):
+    # the tuner times one search: a batch mixing the adaptive block size with
+    # fixed blocks (or block sizes) is refused after validation alone
+    L = xvmod.lib()
+    cbs = (xvmod.Cube * 2)(_cube(xvmod), _cube(xvmod))
+    for flags1, block1 in ((xvmod.FLAG_SPLIT, 16), (0, 8)):
+        ps = (xvmod.ParamsC * 2)(xvmod.Params(bit_depth=10, qp=27, block=16, search_range=8,
+                                              gop=16).c(),
+                                 xvmod.Params(bit_depth=10, qp=27, block=block1, search_range=8,
+                                              gop=16, flags=flags1).c())
+        g = xvmod.MeGeometryC()
+        ms = C.c_double()
+        assert L.xv_autotune_me_batch(2, cbs, ps, None, 0, C.byref(g), C.byref(ms)) == xvmod.EINVAL
+        assert L.xv_last_error()
+
+
 def test_memory_record_and_release_without_device_work(xvmod):
     m = xvmod.memory_read()
     assert set(m) == {"live_bytes", "cached_bytes", "peak_bytes"}
