@@ -109,11 +109,10 @@ def describe(wl) -> str:
             f"GOP {wl.gop}, pad {'zero' if wl.pad_mode == 0 else 'repeat'}")
 
 
-def tune(xv, wl, cube, params, cached, no_tune, max_candidates=0, split=False):
+def tune(xv, wl, cube, params, cached, no_tune, split=False):
     """Motion-search launch geometry per block size, tuned on the first P step
-    of exactly the batch the timed steps launch (outputs never depend on it);
-    max_candidates > 0 limits the timed set (the model's best first).  split:
-    the adaptive block size's search (params carry FLAG_SPLIT)."""
+    of exactly the batch the timed steps launch (outputs never depend on it).
+    split: the adaptive block size's search (params carry FLAG_SPLIT)."""
     tuning = {}
     R = wl.search_range
     setter = xv.set_me_split_geometry if split else xv.set_me_geometry
@@ -128,8 +127,7 @@ def tune(xv, wl, cube, params, cached, no_tune, max_candidates=0, split=False):
         elif not no_tune:
             _log(f"tuning motion search {wl.name} N={N} R={R}" + (" (split)" if split else ""))
             pn = [p for p in params if p.block == N]
-            tuning[key] = dict(xv.autotune_me_batch([cube] * len(pn), pn,
-                                                    max_candidates=max_candidates), tuned=True)
+            tuning[key] = dict(xv.autotune_me_batch([cube] * len(pn), pn), tuned=True)
         else:
             tuning[key] = dict(getter(N, R, -(-wl.W // N)), tuned=False)
     return tuning
