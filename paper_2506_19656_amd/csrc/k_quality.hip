@@ -7,9 +7,11 @@
 // sum, K1 = 0.01, K2 = 0.03, over every window position inside the real
 // H x W picture.  A band scores the mean over its frames of the per-plane
 // mean.  The window is separable, so a workgroup filters a tile of window
-// positions in two passes through LDS: rows (11 taps, five moment sums in
-// binary64), then columns, then the SSIM of each position.  Per-tile sums go
-// to a partial array that one workgroup per band reduces in a fixed order.
+// positions in two passes through LDS: rows (11 taps, moment sums in
+// binary64), then columns, then the SSIM of each position.  The variances
+// enter SSIM only as their sum, so four moments suffice: the two means,
+// E[a^2 + b^2] and E[ab].  Per-tile sums go to a partial array that one
+// workgroup per band reduces in a fixed order.
 //
 // Spectral angle (Kruse et al., 1993): per pixel, arccos of the normalised
 // dot product of the original and decoded band vectors, in binary64, pixels
@@ -29,9 +31,9 @@ constexpr int kInY = kTileY + 10;        // input rows of a tile
 constexpr int kSsimThreads = 256;
 
 struct alignas(16) SsimLds {
-  double h[5][kInY][kTileX];             // row-filtered a, b, aa, bb, ab
-  double a[kInY][kInX];                  // the tile's samples, converted once
-  double b[kInY][kInX];
+  double h[4][kInY][kTileX];             // row-filtered a, b, aa + bb, ab
+  float a[kInY][kInX];                   // the tile's samples (exact in binary32)
+  float b[kInY][kInX];
   double red[kSsimThreads / 64];
 };
 
@@ -65,8 +67,8 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_kernel(const SsimArgs a) {
     const int r = i / kInX, q = i - r * kInX;
     const int y = y0 + r, x = x0 + q;
     const bool in = y < a.H && x < a.W;  // outside samples only feed skipped positions
-    s.a[r][q] = in ? (double)pa[(size_t)y * a.Wp + x] : 0.0;
-    s.b[r][q] = in ? (double)pb[(size_t)y * a.Wp + x] : 0.0;
+    s.a[r][q] = in ? (float)pa[(size_t)y * a.Wp + x] : 0.0f;
+    s.b[r][q] = in ? (float)pb[(size_t)y * a.Wp + x] : 0.0f;
   }
   __syncthreads();
 
@@ -78,26 +80,24 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_kernel(const SsimArgs a) {
     double u[kHx + 10], v[kHx + 10];
 #pragma unroll
     for (int q = 0; q < kHx + 10; q++) {
-      u[q] = s.a[r][j0 + q];
-      v[q] = s.b[r][j0 + q];
+      u[q] = (double)s.a[r][j0 + q];
+      v[q] = (double)s.b[r][j0 + q];
     }
 #pragma unroll
     for (int jj = 0; jj < kHx; jj++) {
-      double sa = 0.0, sb = 0.0, saa = 0.0, sbb = 0.0, sab = 0.0;
+      double sa = 0.0, sb = 0.0, ss = 0.0, sab = 0.0;
 #pragma unroll
       for (int k = 0; k < 11; k++) {
         const double wu = a.w[k] * u[jj + k], wv = a.w[k] * v[jj + k];
         sa += wu;
         sb += wv;
-        saa = fma(wu, u[jj + k], saa);
-        sbb = fma(wv, v[jj + k], sbb);
+        ss = fma(wv, v[jj + k], fma(wu, u[jj + k], ss));
         sab = fma(wu, v[jj + k], sab);
       }
       s.h[0][r][j0 + jj] = sa;
       s.h[1][r][j0 + jj] = sb;
-      s.h[2][r][j0 + jj] = saa;
-      s.h[3][r][j0 + jj] = sbb;
-      s.h[4][r][j0 + jj] = sab;
+      s.h[2][r][j0 + jj] = ss;
+      s.h[3][r][j0 + jj] = sab;
     }
   }
   __syncthreads();
@@ -107,11 +107,11 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_kernel(const SsimArgs a) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < (kTileY / 2) * kTileX; i += kSsimThreads) {
     const int r0 = (i / kTileX) * 2, j = i - (i / kTileX) * kTileX;
-    double m0[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, m1[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double m0[4] = {0.0, 0.0, 0.0, 0.0}, m1[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 12; k++) {
 #pragma unroll
-      for (int q = 0; q < 5; q++) {
+      for (int q = 0; q < 4; q++) {
         const double h = s.h[q][r0 + k][j];
         if (k < 11) m0[q] = fma(a.w[k], h, m0[q]);
         if (k > 0) m1[q] = fma(a.w[k - 1], h, m1[q]);
@@ -121,11 +121,11 @@ __global__ void __launch_bounds__(kSsimThreads) ssim_kernel(const SsimArgs a) {
     for (int d = 0; d < 2; d++) {
       const double* m = d == 0 ? m0 : m1;
       if (y0 + r0 + d + 11 > a.H || x0 + j + 11 > a.W) continue;
-      const double va = m[2] - m[0] * m[0];
-      const double vb = m[3] - m[1] * m[1];
-      const double cab = m[4] - m[0] * m[1];
-      acc += ((2.0 * m[0] * m[1] + a.C1) * (2.0 * cab + a.C2)) /
-             ((m[0] * m[0] + m[1] * m[1] + a.C1) * (va + vb + a.C2));
+      // sum of the variances, covariance
+      const double mm = m[0] * m[0] + m[1] * m[1];
+      const double vs = m[2] - mm;
+      const double cab = m[3] - m[0] * m[1];
+      acc += ((2.0 * m[0] * m[1] + a.C1) * (2.0 * cab + a.C2)) / ((mm + a.C1) * (vs + a.C2));
     }
   }
   const double tot = block_sum(acc, s.red);
