@@ -138,6 +138,27 @@ def test_float_input_with_gaps(fill, bands):
                decode_dtypes=("same", torch.uint16))
 
 
+def test_u16_output_at_rounding_boundaries():
+    # float bands from 0.5 to 1023.5 at B = 10 (L = 1023, range R = 1023):
+    # band 0 decodes every sample to mn + q R / L = q + 1/2, so its u16
+    # output rounds exactly at half-integers, where the product with 1/L
+    # defers to the exact quotient; bands 1 and 2 are shifted by +2^-12 and
+    # -2^-12 (exact in binary32 at this magnitude), just above and just
+    # below those boundaries
+    rng = np.random.default_rng(31)
+    host = (rng.integers(0, 1024, (5, 24, 40, 3)) + 0.5).astype(np.float64)
+    host[0, 0, 0, :] = 0.5
+    host[0, 0, 1, :] = 1023.5
+    host[..., 1] += 2.0 ** -12
+    host[..., 2] -= 2.0 ** -12
+    assert np.array_equal(host.astype(np.float32).astype(np.float64), host)  # exact in binary32
+    host = host.astype(np.float32)
+    for qp in (-12, 27):
+        check_cube(f"u16_boundary_qp{qp}", host,
+                   xv.Params(bit_depth=10, qp=qp, block=8, search_range=2, gop=5),
+                   decode_dtypes=(torch.uint16,))
+
+
 def test_float_input_without_gaps_and_constant_band():
     host = _textured(6, 33, 41, 3, seed=3, dtype=np.float32)
     host[..., 1] = 273.15  # constant band: q = 0, decodes exactly, PSNR infinite
