@@ -199,6 +199,92 @@ __global__ void __launch_bounds__(kSaThreads) sa_kernel(const SaArgs a) {
   }
 }
 
+// The same with both cubes of one dtype T and BANDS bands, 16-byte aligned,
+// read as whole 16-byte granules: a group of g pixels is ne = g BANDS
+// elements, and a thread loads U groups of each cube before any arithmetic
+// (about 32 elements per cube), so that enough bytes are in flight.  Each
+// pixel's sums run over its bands in the same order as above.
+__host__ __device__ constexpr int sa_gcd(int x, int y) { return y == 0 ? x : sa_gcd(y, x % y); }
+template <typename T, int BANDS>
+struct SaGroup {
+  static constexpr int g = 16 / sa_gcd(16, BANDS * (int)sizeof(T));  // pixels per group
+  static constexpr int ne = g * BANDS;
+  static constexpr int nv = ne * (int)sizeof(T) / 16;  // granules per group
+  static constexpr int U = ne >= 32 ? 1 : (32 / ne > 4 ? 4 : 32 / ne);
+};
+
+template <typename T, int BANDS>
+__global__ void __launch_bounds__(kSaThreads) sa_vec_kernel(const SaArgs a) {
+  using SG = SaGroup<T, BANDS>;
+  constexpr int U = SG::U;
+  __shared__ double red[kSaThreads / 64];
+  __shared__ unsigned long long redn[kSaThreads / 64];
+  const T* o = (const T*)a.orig;
+  const T* d = (const T*)a.dec;
+  const int64_t ngroups = a.npix / SG::g;
+  double acc = 0.0;
+  unsigned long long cnt = 0;
+  for (int64_t q0 = (int64_t)blockIdx.x * kSaThreads * U + threadIdx.x; q0 < ngroups;
+       q0 += (int64_t)gridDim.x * kSaThreads * U) {
+    T ov[U][SG::ne], dv[U][SG::ne];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t q = q0 + (int64_t)u * kSaThreads;
+      if (q >= ngroups) break;
+      uint4 wo[SG::nv], wd[SG::nv];
+#pragma unroll
+      for (int i = 0; i < SG::nv; i++) {
+        wo[i] = ((const uint4*)(o + q * SG::ne))[i];
+        wd[i] = ((const uint4*)(d + q * SG::ne))[i];
+      }
+      __builtin_memcpy(ov[u], wo, sizeof wo);
+      __builtin_memcpy(dv[u], wd, sizeof wd);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (q0 + (int64_t)u * kSaThreads >= ngroups) break;
+#pragma unroll
+      for (int p = 0; p < SG::g; p++) {
+        double dot = 0.0, n1 = 0.0, n2 = 0.0;
+        bool bad = false;
+#pragma unroll
+        for (int b = 0; b < BANDS; b++) {
+          const double x = (double)ov[u][p * BANDS + b], y = (double)dv[u][p * BANDS + b];
+          bad |= (x != x) || (y != y);
+          dot += x * y;
+          n1 += x * x;
+          n2 += y * y;
+        }
+        if (bad || n1 == 0.0 || n2 == 0.0) continue;
+        const double r = fmin(fmax(dot / (sqrt(n1) * sqrt(n2)), -1.0), 1.0);
+        acc += acos(r);
+        cnt++;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    acc += __shfl_down(acc, off);
+    cnt += __shfl_down(cnt, off);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = acc;
+    redn[w] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    unsigned long long n = 0;
+    for (int i = 0; i < kSaThreads / 64; i++) {
+      t += red[i];
+      n += redn[i];
+    }
+    a.part_sum[blockIdx.x] = t;
+    a.part_n[blockIdx.x] = n;
+  }
+}
+
 __global__ void __launch_bounds__(kSaThreads) sa_reduce_kernel(const SaArgs a, int nblocks) {
   __shared__ double red[kSaThreads / 64];
   __shared__ unsigned long long redn[kSaThreads / 64];
@@ -248,9 +334,34 @@ hipError_t launch_ssim(const SsimArgs& a, double* out, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+
+// The granule kernel for both cubes of dtype T, if the shape and alignment
+// allow it.
+template <typename T>
+bool launch_sa_vec(const SaArgs& a, int nblocks, hipStream_t s) {
+  const int g = 16 / sa_gcd(16, a.bands * (int)sizeof(T));
+  if (a.bands > 8 || a.npix % g != 0 || ((uintptr_t)a.orig & 15) || ((uintptr_t)a.dec & 15))
+    return false;
+  switch (a.bands) {
+#define XV_SA(B) \
+  case B:        \
+    sa_vec_kernel<T, B><<<nblocks, kSaThreads, 0, s>>>(a); \
+    return true;
+    XV_SA(1) XV_SA(2) XV_SA(3) XV_SA(4) XV_SA(5) XV_SA(6) XV_SA(7) XV_SA(8)
+#undef XV_SA
+    default: return false;
+  }
+}
+
+}  // namespace
+
 hipError_t launch_spectral_angle(const SaArgs& a, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipErrorInvalidValue;
-  if (a.dtype_orig == XV_U16 && a.dtype_dec == XV_U16)
+  if (a.dtype_orig == a.dtype_dec &&
+      (a.dtype_orig == XV_U16 ? launch_sa_vec<uint16_t>(a, nblocks, s)
+                              : launch_sa_vec<float>(a, nblocks, s))) {
+  } else if (a.dtype_orig == XV_U16 && a.dtype_dec == XV_U16)
     sa_kernel<uint16_t, uint16_t><<<nblocks, kSaThreads, 0, s>>>(a);
   else if (a.dtype_orig == XV_U16)
     sa_kernel<uint16_t, float><<<nblocks, kSaThreads, 0, s>>>(a);
