@@ -984,8 +984,10 @@ __global__ void __launch_bounds__(kThreads) phys_vec_kernel(PhysArgs a) {
 }
 
 // Per-group totals of the transform kernel's per-tile sums: block (g, i)
-// sums quantity i over the T * tpf tiles of group g with a fixed assignment
-// of tiles to threads (4 loads in flight per thread) and a fixed tree.
+// sums quantity i (squared error of channel i < 3; i = 3 coefficient bits,
+// the three channels' slots; i = 4 vector bits) over the T * tpf tiles of
+// group g with a fixed assignment of tiles to threads (4 loads in flight per
+// thread) and a fixed tree.
 constexpr int kTotThreads = 1024;
 
 __global__ void __launch_bounds__(kTotThreads) encode_totals_kernel(
@@ -994,17 +996,28 @@ __global__ void __launch_bounds__(kTotThreads) encode_totals_kernel(
   __shared__ unsigned long long sred[kTotThreads];
   const int g = blockIdx.x / 5, i = blockIdx.x - g * 5;
   const int64_t n = (int64_t)T * tpf;
-  const unsigned long long* pg = part + (int64_t)g * n * 5 + i;
+  const int slot = i < 3 ? i : (i == 3 ? 3 : 6), nslots = i == 3 ? 3 : 1;
+  const unsigned long long* pg = part + (int64_t)g * n * kTileSums + slot;
   unsigned long long v = 0;
   int64_t j = threadIdx.x;
   for (; j + 3 * kTotThreads < n; j += 4 * kTotThreads) {
     unsigned long long w[4];
 #pragma unroll
-    for (int u = 0; u < 4; u++) w[u] = pg[(j + u * kTotThreads) * 5];
+    for (int u = 0; u < 4; u++) w[u] = pg[(j + u * kTotThreads) * kTileSums];
 #pragma unroll
     for (int u = 0; u < 4; u++) v += w[u];
+    if (nslots == 3) {
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        w[u] = pg[(j + u * kTotThreads) * kTileSums + 1] + pg[(j + u * kTotThreads) * kTileSums + 2];
+#pragma unroll
+      for (int u = 0; u < 4; u++) v += w[u];
+    }
   }
-  for (; j < n; j += kTotThreads) v += pg[j * 5];
+  for (; j < n; j += kTotThreads) {
+    v += pg[j * kTileSums];
+    if (nslots == 3) v += pg[j * kTileSums + 1] + pg[j * kTileSums + 2];
+  }
   sred[threadIdx.x] = v;
   __syncthreads();
   for (int w = kTotThreads / 2; w >= 1; w >>= 1) {
@@ -1055,7 +1068,7 @@ __global__ void plan_kernel(CubePlan p) {
   jb.mbits = p.mbits ? p.mbits + f * (int64_t)Hb * Wb : nullptr;
   jb.vmask = p.vmask ? p.vmask + f * 3 * plane : nullptr;
   jb.nan_total = p.nan_total;
-  jb.part = p.part ? p.part + f * p.tpf * 5 : nullptr;
+  jb.part = p.part ? p.part + f * p.tpf * kTileSums : nullptr;
   // one prediction plane per stream (g, k), reused by the stream's steps
   const int ngop = (p.T + p.gop - 1) / p.gop;
   jb.pred = (p.pred && (s > 0 ? p.qpel : p.imode)) ? p.pred + ((int64_t)g * ngop + k) * 3 * plane

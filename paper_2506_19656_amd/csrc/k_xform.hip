@@ -254,6 +254,19 @@ __device__ inline void fwd_column(const uint32_t* tp, ivec<N>& out, int rnd) {
     fwd_product<N>(t, out, rnd);
 }
 
+// Ordering of the LDS accesses of one wave: every lane's earlier reads and
+// writes happen before any lane's later ones.  The waves of a transform
+// workgroup share no LDS data (each has its channel's tiles, sums and run
+// table), so this is all the synchronisation they need.
+// The scheduler keeps each stage's instructions on its side, as a workgroup
+// barrier would (otherwise hoisted work raises the register count).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // LDS layout per workgroup, encode (int16):
 //   TD [3][NBW][N][P]  forward row-stage output transposed ([k][y]); each
 //                      column thread then overwrites its own row k with the
@@ -268,8 +281,7 @@ struct alignas(16) LdsEnc {
   unsigned long long sse[3];
   uint32_t cbits[3][Tile<N>::NBW];
   uint32_t mvbits;
-  uint32_t cbsum;
-  uint8_t runs[256];  // kRunTab, for the rate proxy
+  uint8_t runs[3][256];  // kRunTab, one copy per wave, for the rate proxy
 };
 
 // Decode works one channel per workgroup (the channels of a frame are
@@ -581,7 +593,7 @@ __device__ inline void block_bits(LdsEnc<N>& s, uint32_t coded, int c) {
 #pragma unroll
       for (int k = 0; k < (N + 7) / 8; k++) {
         const uint32_t ck = (m >> (8 * k)) & 0xffu;
-        r += s.runs[ck];
+        r += s.runs[c][ck];
         if (k > 0 && ck) {
           // the byte's first gap runs from the last set bit below it
           const uint32_t lo = m & ((1u << (8 * k)) - 1u);
@@ -730,13 +742,11 @@ encode_kernel(const LaunchDesc jr) {
   // sample offset is not kept beside it (the kernel is at its register limit)
   uint32_t row_b = 2u * ((uint32_t)(c * job.Hp + y) * (uint32_t)job.Wp + (uint32_t)x0);
   asm volatile("" : "+v"(row_b));
-  if (t < 3) s.sse[t] = 0ull;
-  if (t < 3 * NBW) s.cbits[t / NBW][t % NBW] = 0u;
-  if (t < 64) ((uint32_t*)s.runs)[t] = gld<uint32_t>(kRunTab.v, 4u * (uint32_t)t);
-  if (t == 0) {
-    s.mvbits = 0u;
-    s.cbsum = 0u;
-  }
+  // each wave sets up its own channel's sums and run table
+  if (rem == 0) s.sse[c] = 0ull;
+  if (rem < NBW) s.cbits[c][rem] = 0u;
+  ((uint32_t*)s.runs[c])[rem] = gld<uint32_t>(kRunTab.v, 4u * (uint32_t)rem);
+  if (t == 0) s.mvbits = 0u;
   // coded blocks of the tile, bit b (lanes 0 .. NBW-1 are r = 0)
   const uint32_t coded = (uint32_t)__ballot(code) & ((1u << NBW) - 1u);
 
@@ -758,7 +768,7 @@ encode_kernel(const LaunchDesc jr) {
 #pragma unroll
     for (int k = 0; k < N; k++) s.TD[c][b][k][r] = (int16_t)(acc[k] >> s1);
   }
-  __syncthreads();
+  wave_sync();
 
   // Column stage of column k: forward transform, quantise (levels out to
   // global memory, column-major inside the block, and into the thread's own
@@ -822,7 +832,7 @@ encode_kernel(const LaunchDesc jr) {
     dequant_pairs<N>(lv, dqp, dq);
     inverse_column<N>(dq, s.E[c][b], inv_slot<N>(k));
   }
-  __syncthreads();
+  wave_sync();
 
   // Rate proxy per block and channel (levels in TD).
   if (wave_nz) block_bits<N>(s, coded, c);
@@ -837,7 +847,8 @@ encode_kernel(const LaunchDesc jr) {
       for (int j = 0; j < N / 2; j++) rp[j] = pp[j];
     }
     store_row_packed<N>(job.rec, row_b, rp);
-    if (c < job.nch && y < job.H) {
+    // the row index afresh from the lane (mbcnt), not kept from the start
+    if (c < job.nch && tc.by * N + (int)__lane_id() / NBW < job.H) {
       const uint32_t sse = usemask ? row_sse<N, true>(cp, rp, job.vmask, row_b >> 1, x0, job.W)
                                    : row_sse<N, false>(cp, rp, nullptr, 0, x0, job.W);
       if (sse) atomicAdd(&s.sse[c], (unsigned long long)sse);
@@ -893,46 +904,49 @@ encode_kernel(const LaunchDesc jr) {
       if (bits) atomicAdd(&s.mvbits, bits);
     }
   }
-  __syncthreads();
-  if (t < 3 * NBW) {
-    const int cc = t / NBW, bb = t - cc * NBW;
-    const int bxx = tc.bx0 + bb;
-    if (bxx < tc.Wb) {
-      // bits = 1 (coded flag) + [nnz > 0] (ue(nnz - 1) + 128 nnz - 2 sum clz)
-      const uint32_t v = s.cbits[cc][bb];
-      const uint32_t nnz = v >> 17, sum = v & 0x1ffffu;
-      const bool cb = (coded >> bb) & 1u;
-      const uint32_t bits =
-          cb ? 1u + (nnz > 0 ? 63u - 2u * (uint32_t)__builtin_clz(nnz) + 128u * nnz - 2u * sum : 0u)
+  wave_sync();
+  // coefficient bits of the wave's channel c per block (lanes 0 .. NBW-1):
+  // bits = 1 (coded flag) + [nnz > 0] (ue(nnz - 1) + 128 nnz - 2 sum clz).
+  // The lane index is taken afresh (mbcnt), not kept from the start.
+  const int ln = (int)__lane_id();
+  uint32_t cb = 0;
+  if (ln < NBW && tc.bx0 + ln < tc.Wb) {
+    const int bxx = tc.bx0 + ln;
+    const uint32_t v = s.cbits[c][ln];
+    const uint32_t nnz = v >> 17, sum = v & 0x1ffffu;
+    const bool cbk = (coded >> ln) & 1u;
+    cb = cbk ? 1u + (nnz > 0 ? 63u - 2u * (uint32_t)__builtin_clz(nnz) + 128u * nnz - 2u * sum : 0u)
              : 0u;
-      if constexpr (kRole == 2) {
-        // a cell adds to its block's count (zeroed by the size-N kernel)
-        if (cb) {
-          const uint32_t Wb2 = (uint32_t)tc.Wb >> 1;
-          atomicAdd(job.cbits + ((uint32_t)cc * ((uint32_t)tc.Hb >> 1) + (uint32_t)(tc.by >> 1)) * Wb2 +
-                        (uint32_t)(bxx >> 1),
-                    bits);
-        }
-      } else {
-        gst<uint32_t>(job.cbits, 4u * (((uint32_t)cc * tc.Hb + tc.by) * tc.Wb + bxx), bits);
+    if constexpr (kRole == 2) {
+      // a cell adds to its block's count (zeroed by the size-N kernel)
+      if (cbk) {
+        const uint32_t Wb2 = (uint32_t)tc.Wb >> 1;
+        atomicAdd(job.cbits + ((uint32_t)c * ((uint32_t)tc.Hb >> 1) + (uint32_t)(tc.by >> 1)) * Wb2 +
+                      (uint32_t)(bxx >> 1),
+                  cb);
       }
-      if (bits) atomicAdd(&s.cbsum, bits);  // 3 * 64 * N coefficients of < 64 bits: no overflow
+    } else {
+      gst<uint32_t>(job.cbits, 4u * (((uint32_t)c * tc.Hb + tc.by) * tc.Wb + bxx), cb);
     }
   }
-  __syncthreads();
-  // this tile's sums; the per-group totals are formed after the last step
-  // (the size-N/2 kernel's tiles follow the size-N kernel's)
+  // the channel's total over the tile (3 * 64 * N coefficients of < 64 bits
+  // in all: no overflow)
+#pragma unroll
+  for (int o = NBW / 2; o >= 1; o >>= 1) cb += __shfl_xor(cb, o);
+  // this tile's sums, each wave its channel's; the per-group totals are
+  // formed after the last step (the size-N/2 kernel's tiles follow the
+  // size-N kernel's)
   uint32_t tile = (uint32_t)tc.tl;
   if constexpr (kRole == 2) {
     constexpr int NBW2 = Tile<2 * N>::NBW;
     tile += (uint32_t)((tc.Hb >> 1) * (((tc.Wb >> 1) + NBW2 - 1) / NBW2));
   }
-  const uint32_t part = 40u * tile;
-  if (t == 0) {
-    gst<unsigned long long>(job.part, part + 24, (unsigned long long)s.cbsum);
-    gst<unsigned long long>(job.part, part + 32, (unsigned long long)s.mvbits);
+  const uint32_t part = 8u * kTileSums * tile;
+  if (ln == 0) {
+    gst<unsigned long long>(job.part, part + 8u * (uint32_t)c, s.sse[c]);
+    gst<unsigned long long>(job.part, part + 8u * (3u + (uint32_t)c), (unsigned long long)cb);
+    if (c == 0) gst<unsigned long long>(job.part, part + 48u, (unsigned long long)s.mvbits);
   }
-  if (t < 3) gst<unsigned long long>(job.part, part + 8 * t, s.sse[t]);
 }
 
 // One wave per (tile, channel): workgroup 3 w + c decodes channel c of tile w.

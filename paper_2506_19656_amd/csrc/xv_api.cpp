@@ -108,7 +108,7 @@ EncLayout enc_layout(const xv_encoded* e) {
   L.o_fr = w.take<uint16_t>((size_t)nframes * 3 * plane);
   L.o_rc = w.take<uint16_t>((size_t)nframes * 3 * plane);
   L.o_vm = e->src_dtype == XV_F32 ? w.take<uint8_t>((size_t)nframes * 3 * plane) : 0;
-  L.o_part = w.take<uint64_t>((size_t)nframes * tiles_per_frame(e) * 5);
+  L.o_part = w.take<uint64_t>((size_t)nframes * tiles_per_frame(e) * kTileSums);
   L.o_pred = (e->p.flags & (XV_FLAG_QPEL | XV_FLAG_INTRA)) ? w.take<uint8_t>(pred_plane_bytes(e))
                                                            : 0;
   L.o_mvw = split ? w.take<int8_t>((size_t)nblk * 2) : 0;

@@ -22,7 +22,7 @@ struct xv_encoded {
   hipStream_t stream;
   void* keep;  // levels, vectors, bit counts, statistics, job table
   void* work;  // converted frames, reconstruction, validity bytes, per-tile sums
-  unsigned long long* tile_part;  // [G][T][tpf][5] per-tile sums of the transform kernel
+  unsigned long long* tile_part;  // [G][T][tpf][kTileSums] per-tile sums of the transform kernel
   int tpf;                        // transform tiles per frame
   uint16_t* frames;
   uint16_t* recon;

@@ -19,6 +19,11 @@ namespace xv {
 // kMaxSeg segments (contiguous job ranges, e.g. one per cube) that share the
 // block size N and, for motion search, the range R.
 // ---------------------------------------------------------------------------
+// Per-tile sums of the transform kernel: squared error of channels 0..2,
+// coefficient bits of channels 0..2, vector bits (each wave of a tile
+// writes its channel's slots).
+constexpr int kTileSums = 7;
+
 struct FrameJob {
   const uint16_t* cur;         // [3][Hp][Wp] converted frame (encode)
   const uint16_t* ref;         // [3][Hp][Wp] reconstruction of frame t-1 (P)
@@ -29,8 +34,8 @@ struct FrameJob {
   uint32_t* mbits;             // [Hb][Wb]
   const uint8_t* vmask;        // [3][Hp][Wp] validity bytes, or null
   const uint32_t* nan_total;   // device flag: non-zero -> vmask is meaningful
-  unsigned long long* part;    // [tiles of the frame][5] per-tile sums: squared error of
-                               // channels 0..2, coefficient bits, vector bits
+  unsigned long long* part;    // [tiles of the frame][kTileSums] per-tile sums: squared
+                               // error and coefficient bits of channels 0..2, vector bits
   uint16_t* pred;              // [3][Hp][Wp] prediction plane read at displacement
                                // zero: the motion-compensated prediction of a P step
                                // with quarter-sample vectors, or the intra prediction
@@ -85,7 +90,7 @@ struct CubePlan {
   uint32_t* mbits;
   const uint8_t* vmask;
   const uint32_t* nan_total;
-  unsigned long long* part;    // [G][T][tpf][5] per-tile sums (null for decode)
+  unsigned long long* part;    // [G][T][tpf][kTileSums] per-tile sums (null for decode)
   uint16_t* pred;              // [G][GOPs][3][Hp][Wp] prediction planes, one per stream,
                                // or null
   FrameJob* jobs;              // [sum over steps of jobs]
