@@ -983,51 +983,70 @@ __global__ void __launch_bounds__(kThreads) phys_vec_kernel(PhysArgs a) {
   }
 }
 
-// Per-group totals of the transform kernel's per-tile sums: block (g, i)
-// sums quantity i (squared error of channel i < 3; i = 3 coefficient bits,
-// the three channels' slots; i = 4 vector bits) over the T * tpf tiles of
-// group g with a fixed assignment of tiles to threads (4 loads in flight per
-// thread) and a fixed tree.
-constexpr int kTotThreads = 1024;
+// Per-group totals of the transform kernel's per-tile sums, in two passes
+// with a fixed assignment of tiles to threads and a fixed order of addition.
+// Pass 1: block (c, g) reads whole tile records (kTileSums words each,
+// adjacent threads on adjacent records) of chunk c of group g and writes
+// five chunk sums (squared error of channels 0..2, coefficient bits of the
+// three channels, vector bits).  Pass 2: one thread per (g, quantity) adds
+// the chunk sums in chunk order.
+constexpr int kTotThreads = 256;
 
-__global__ void __launch_bounds__(kTotThreads) encode_totals_kernel(
-    const unsigned long long* part, int T, int tpf, unsigned long long* sse,
-    unsigned long long* bits) {
-  __shared__ unsigned long long sred[kTotThreads];
-  const int g = blockIdx.x / 5, i = blockIdx.x - g * 5;
-  const int64_t n = (int64_t)T * tpf;
-  const int slot = i < 3 ? i : (i == 3 ? 3 : 6), nslots = i == 3 ? 3 : 1;
-  const unsigned long long* pg = part + (int64_t)g * n * kTileSums + slot;
-  unsigned long long v = 0;
-  int64_t j = threadIdx.x;
-  for (; j + 3 * kTotThreads < n; j += 4 * kTotThreads) {
-    unsigned long long w[4];
+__global__ void __launch_bounds__(kTotThreads) tile_totals_kernel(
+    const unsigned long long* part, int64_t n, int chunks, unsigned long long* chunk_sum) {
+  const int c = blockIdx.x, g = blockIdx.y;
+  const int64_t per = (n + chunks - 1) / chunks;
+  const int64_t j0 = (int64_t)c * per, j1 = j0 + per < n ? j0 + per : n;
+  const unsigned long long* pg = part + (int64_t)g * n * kTileSums;
+  unsigned long long v[5] = {0, 0, 0, 0, 0};
+  int64_t j = j0 + threadIdx.x;
+  for (; j + kTotThreads < j1; j += 2 * kTotThreads) {  // two records in flight
+    unsigned long long r[2][kTileSums];
 #pragma unroll
-    for (int u = 0; u < 4; u++) w[u] = pg[(j + u * kTotThreads) * kTileSums];
+    for (int u = 0; u < 2; u++)
 #pragma unroll
-    for (int u = 0; u < 4; u++) v += w[u];
-    if (nslots == 3) {
+      for (int k = 0; k < kTileSums; k++) r[u][k] = pg[(j + u * kTotThreads) * kTileSums + k];
 #pragma unroll
-      for (int u = 0; u < 4; u++)
-        w[u] = pg[(j + u * kTotThreads) * kTileSums + 1] + pg[(j + u * kTotThreads) * kTileSums + 2];
-#pragma unroll
-      for (int u = 0; u < 4; u++) v += w[u];
+    for (int u = 0; u < 2; u++) {
+      v[0] += r[u][0];
+      v[1] += r[u][1];
+      v[2] += r[u][2];
+      v[3] += r[u][3] + r[u][4] + r[u][5];
+      v[4] += r[u][6];
     }
   }
-  for (; j < n; j += kTotThreads) {
-    v += pg[j * kTileSums];
-    if (nslots == 3) v += pg[j * kTileSums + 1] + pg[j * kTileSums + 2];
+  if (j < j1) {
+    const unsigned long long* r = pg + j * kTileSums;
+    v[0] += r[0];
+    v[1] += r[1];
+    v[2] += r[2];
+    v[3] += r[3] + r[4] + r[5];
+    v[4] += r[6];
   }
-  sred[threadIdx.x] = v;
+  __shared__ unsigned long long red[5][kTotThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    for (int o = 32; o >= 1; o >>= 1) v[k] += __shfl_xor(v[k], o);
+    if (lane == 0) red[k][wv] = v[k];
+  }
   __syncthreads();
-  for (int w = kTotThreads / 2; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
-    __syncthreads();
+  if (threadIdx.x < 5) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kTotThreads / 64; w++) t += red[threadIdx.x][w];
+    chunk_sum[((int64_t)g * chunks + c) * 5 + threadIdx.x] = t;
   }
-  if (threadIdx.x == 0) {
-    if (i < 3) sse[3 * g + i] = sred[0];
-    else bits[2 * g + i - 3] = sred[0];
-  }
+}
+
+__global__ void totals_finish_kernel(const unsigned long long* chunk_sum, int G, int chunks,
+                                     unsigned long long* sse, unsigned long long* bits) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 5 * G) return;
+  const int g = i / 5, k = i - g * 5;
+  unsigned long long t = 0;
+  for (int c = 0; c < chunks; c++) t += chunk_sum[((int64_t)g * chunks + c) * 5 + k];
+  if (k < 3) sse[3 * g + k] = t;
+  else bits[2 * g + k - 3] = t;
 }
 
 // Job table of one cube, step-major: entry (s, g * nk + k) describes frame
@@ -1096,10 +1115,19 @@ hipError_t launch_plan(const CubePlan& p, hipStream_t s) {
   return hipGetLastError();
 }
 
+int encode_totals_chunks(int64_t tiles) {
+  const int64_t c = (tiles + 8 * kTotThreads - 1) / (8 * kTotThreads);
+  return (int)std::min<int64_t>(kTotMaxChunks, std::max<int64_t>(1, c));
+}
+
 hipError_t launch_encode_totals(const unsigned long long* part, int G, int T, int tpf,
-                                unsigned long long* sse, unsigned long long* bits, hipStream_t s) {
+                                unsigned long long* chunk_sum, unsigned long long* sse,
+                                unsigned long long* bits, hipStream_t s) {
   if (G <= 0) return hipSuccess;
-  encode_totals_kernel<<<G * 5, kTotThreads, 0, s>>>(part, T, tpf, sse, bits);
+  const int64_t n = (int64_t)T * tpf;
+  const int chunks = encode_totals_chunks(n);
+  tile_totals_kernel<<<dim3(chunks, G), kTotThreads, 0, s>>>(part, n, chunks, chunk_sum);
+  totals_finish_kernel<<<(5 * G + 63) / 64, 64, 0, s>>>(chunk_sum, G, chunks, sse, bits);
   return hipGetLastError();
 }
 

@@ -109,6 +109,7 @@ EncLayout enc_layout(const xv_encoded* e) {
   L.o_rc = w.take<uint16_t>((size_t)nframes * 3 * plane);
   L.o_vm = e->src_dtype == XV_F32 ? w.take<uint8_t>((size_t)nframes * 3 * plane) : 0;
   L.o_part = w.take<uint64_t>((size_t)nframes * tiles_per_frame(e) * kTileSums);
+  L.o_tot = w.take<uint64_t>((size_t)G * kTotMaxChunks * 5);
   L.o_pred = (e->p.flags & (XV_FLAG_QPEL | XV_FLAG_INTRA)) ? w.take<uint8_t>(pred_plane_bytes(e))
                                                            : 0;
   L.o_mvw = split ? w.take<int8_t>((size_t)nblk * 2) : 0;
@@ -192,6 +193,7 @@ int encode_prepare(const xv_cube* in, const xv_params* p, hipStream_t s, xv_enco
   e->recon = (uint16_t*)(wb + o_rc);
   e->vmask = in->dtype == XV_F32 ? (uint8_t*)(wb + o_vm) : nullptr;
   e->tile_part = (unsigned long long*)(wb + o_part);
+  e->tot_chunk = (unsigned long long*)(wb + lay.o_tot);
   e->pred = (p->flags & (XV_FLAG_QPEL | XV_FLAG_INTRA)) ? (uint16_t*)(wb + lay.o_pred) : nullptr;
   const bool split = (p->flags & XV_FLAG_SPLIT) != 0;
   e->mv_whole = split ? (int8_t*)(wb + lay.o_mvw) : nullptr;
@@ -376,12 +378,14 @@ int launch_split_decode(const std::vector<DecSrc>& src, hipStream_t s) {
 // After the last step: per-group totals from the per-tile sums, then the
 // work buffers go if the caller asked for that.
 int finish_encode(xv_encoded* e) {
-  XV_HIP(launch_encode_totals(e->tile_part, e->G, (int)e->T, e->tpf, e->sse, e->bits, e->stream),
+  XV_HIP(launch_encode_totals(e->tile_part, e->G, (int)e->T, e->tpf, e->tot_chunk, e->sse,
+                              e->bits, e->stream),
          "encode totals kernel");
   if (e->p.flags & XV_FLAG_DROP_WORK) {
     dev_free(e->work, e->stream);
     e->work = nullptr;
     e->tile_part = nullptr;
+    e->tot_chunk = nullptr;
     e->pred = nullptr;
     e->mv_whole = nullptr;
     e->sad_whole = nullptr;

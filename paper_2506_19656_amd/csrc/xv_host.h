@@ -24,6 +24,7 @@ struct xv_encoded {
   void* work;  // converted frames, reconstruction, validity bytes, per-tile sums
   unsigned long long* tile_part;  // [G][T][tpf][kTileSums] per-tile sums of the transform kernel
   int tpf;                        // transform tiles per frame
+  unsigned long long* tot_chunk;  // [G][kTotMaxChunks][5] chunk sums of the totals, in work
   uint16_t* frames;
   uint16_t* recon;
   uint8_t* vmask;
@@ -118,7 +119,7 @@ void dims_of(xv_encoded* e, const xv_cube* in, const xv_params* p);
 // reconstruction, validity bytes).  Offsets in bytes.
 struct EncLayout {
   size_t o_lev, o_mv, o_cb, o_mb, o_keys, o_span, o_pp, o_jobs, o_split, keep;
-  size_t o_fr, o_rc, o_vm, o_part, o_pred, o_mvw, o_sadw, o_sadc, work;
+  size_t o_fr, o_rc, o_vm, o_part, o_tot, o_pred, o_mvw, o_sadw, o_sadc, work;
   size_t span_words;
   int phys_nb;
 };

@@ -110,9 +110,13 @@ struct CubePlan {
 };
 
 // Per-group totals of the per-tile sums, in a fixed order: sse [3G] and
-// bits [2G] (coefficient, vector) of one encoded cube.
+// bits [2G] (coefficient, vector) of one encoded cube.  chunk_sum holds
+// [G][kTotMaxChunks][5] intermediate sums.
+constexpr int kTotMaxChunks = 256;
+int encode_totals_chunks(int64_t tiles);
 hipError_t launch_encode_totals(const unsigned long long* part, int G, int T, int tpf,
-                                unsigned long long* sse, unsigned long long* bits, hipStream_t s);
+                                unsigned long long* chunk_sum, unsigned long long* sse,
+                                unsigned long long* bits, hipStream_t s);
 
 // Jobs at step s: G * ceil((T - s) / gop); offset of step s in the table.
 inline int plan_jobs_at(int T, int G, int gop, int s) { return G * ((T - s + gop - 1) / gop); }
