@@ -164,17 +164,25 @@ __device__ inline void put_block(BitSink& bs, const int16_t* lev, int n, const u
   bs.put(nnz > 0 ? 1u : 0u, 1);
   if (nnz > 0) {
     bs.ue((uint32_t)(nnz - 1));
+    // eight scan positions per batch, their loads issued together (n * n is
+    // a multiple of 8); zeros after the last nonzero only lengthen a run that
+    // is never written
     int run = 0, seen = 0;
-    for (int p = 0; p < n * n && seen < nnz; p++) {
-      const int v = lev[scan[p]];
-      if (v == 0) {
-        run++;
-        continue;
+    for (int p0 = 0; p0 < n * n && seen < nnz; p0 += 8) {
+      int v[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) v[j] = lev[scan[p0 + j]];
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        if (v[j] == 0) {
+          run++;
+          continue;
+        }
+        bs.ue((uint32_t)run);
+        bs.se(v[j]);
+        run = 0;
+        seen++;
       }
-      bs.ue((uint32_t)run);
-      bs.se(v);
-      run = 0;
-      seen++;
     }
   }
 }
@@ -239,57 +247,73 @@ __global__ void __launch_bounds__(kBitsThreads) write_units_kernel(BitsArgs a) {
 }
 
 // Bit reader over the payload words (byte-swapped back to stream order).
-// The next bits of the stream are held MSB-first in a 64-bit register with
-// at least 33 of them valid (the longest code the writer emits), so a code
-// is read with register operations and a new word is fetched only once 32
-// bits have been consumed.  Word reads are clamped to the buffer.
+// The next bits of the stream are held MSB-first in a 128-bit register pair
+// with at least 65 of them valid (the longest code the writer emits has 33),
+// so a code is read from the upper register alone and two new words are
+// fetched only once 64 bits have been consumed.  Word reads are clamped to
+// the buffer.
 struct BitSource {
   const uint32_t* words;
   int64_t nwords;
-  uint64_t pos;   // bits consumed, from the start of the payload
-  uint64_t buf;   // the next bits, MSB first; bits past nbits are zero
-  int nbits;      // valid bits in buf
-  int64_t next;   // next word to load
+  uint64_t pos;    // bits consumed, from the start of the payload
+  uint64_t hi, lo;  // the next bits, MSB first (hi before lo); bits past nbits are zero
+  int nbits;       // valid bits in hi:lo, at least 65 between codes
+  int64_t next;    // next word to load
 
   __device__ uint32_t word(int64_t w) const {
     return __builtin_bswap32(words[min(w, nwords - 1)]);
   }
+  __device__ uint64_t pair(int64_t w) const { return ((uint64_t)word(w) << 32) | word(w + 1); }
+  // Appends the next 64 payload bits once no more than 64 are left: one wait
+  // for memory per 64 bits parsed (the level stores in flight count in it).
   __device__ void refill() {
-    while (nbits <= 32) {
-      buf |= (uint64_t)word(next) << (32 - nbits);
-      nbits += 32;
-      next++;
+    if (nbits > 64) return;
+    const uint64_t c = pair(next);
+    next += 2;
+    if (nbits == 64) {
+      lo = c;
+    } else {
+      hi |= c >> nbits;
+      lo = c << (64 - nbits);
     }
+    nbits += 64;
   }
   __device__ void start(const uint32_t* w, int64_t nw, uint64_t at) {
     words = w;
     nwords = nw;
     pos = at;
+    const int64_t w0 = (int64_t)(at >> 5);
     const int sh = (int)(at & 31);
-    buf = ((uint64_t)word((int64_t)(at >> 5)) << 32) << sh;
-    nbits = 32 - sh;
-    next = (int64_t)(at >> 5) + 1;
-    refill();
+    hi = pair(w0);
+    lo = pair(w0 + 2);
+    next = w0 + 4;
+    if (sh) {
+      hi = (hi << sh) | (lo >> (64 - sh));
+      lo <<= sh;
+    }
+    nbits = 128 - sh;
   }
+  // n in 1..33
   __device__ void skip(int n) {
-    buf <<= n;
+    hi = (hi << n) | (lo >> (64 - n));
+    lo <<= n;
     nbits -= n;
     pos += (uint64_t)n;
     refill();
   }
   __device__ int bit() {
-    const int b = (int)(buf >> 63);
+    const int b = (int)(hi >> 63);
     skip(1);
     return b;
   }
   // ue(k): m leading zeros, then m + 1 bits holding k + 1; false on a code
   // longer than any the writer emits.
   __device__ bool ue(uint32_t& k) {
-    if (buf == 0) return false;
-    const int m = __clzll((long long)buf);
+    if (hi == 0) return false;
+    const int m = __clzll((long long)hi);
     if (m > 16) return false;
     const int len = 2 * m + 1;
-    k = (uint32_t)(buf >> (64 - len)) - 1u;
+    k = (uint32_t)(hi >> (64 - len)) - 1u;
     skip(len);
     return true;
   }
@@ -298,6 +322,26 @@ struct BitSource {
     if (!ue(k)) return false;
     v = (k & 1) ? (int)((k + 1) / 2) : -(int)(k / 2);
     return true;
+  }
+  // ue(run) then se(v): one shift when the two codes together take at most
+  // 33 bits (both then lie in the upper register), else the two reads.
+  __device__ bool run_level(uint32_t& run, int& v) {
+    if (hi == 0) return false;
+    const int m1 = __clzll((long long)hi);
+    if (m1 > 16) return false;
+    const int l1 = 2 * m1 + 1;
+    const uint64_t x = hi << l1;
+    if (x != 0) {
+      const int l2 = 2 * __clzll((long long)x) + 1;
+      if (l1 + l2 <= 33) {
+        run = (uint32_t)(hi >> (64 - l1)) - 1u;
+        const uint32_t k = (uint32_t)(x >> (64 - l2)) - 1u;
+        v = (k & 1) ? (int)((k + 1) / 2) : -(int)(k / 2);
+        skip(l1 + l2);
+        return true;
+      }
+    }
+    return ue(run) && se(v);
   }
 };
 
@@ -316,7 +360,7 @@ __device__ inline bool get_block(BitSource& src, int16_t* lev, int n, const uint
     for (int i = 0; i < nnz && ok; i++) {
       uint32_t run;
       int v;
-      ok = src.ue(run) && src.se(v) && v != 0 && v >= -32767 && v <= 32767;
+      ok = src.run_level(run, v) && v != 0 && v >= -32767 && v <= 32767;
       if (!ok) break;
       p += (int)run + 1;
       ok = p < n * n;
