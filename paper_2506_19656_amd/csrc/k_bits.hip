@@ -236,7 +236,12 @@ __global__ void __launch_bounds__(kBitsThreads) write_units_kernel(BitsArgs a) {
     }
   } else {
     const int16_t* lev = a.levels + (f * 3 * hw + (r - hw)) * N * N;
-    if (a.splits && !intra && a.splits[f * hw + (r - hw) % hw]) {
+    const bool sp = a.splits && !intra && a.splits[f * hw + (r - hw) % hw];
+    if (len == (sp ? 4u : 1u)) {
+      // one bit per block is a coded flag of 0 alone (a block with a nonzero
+      // level takes at least 6 bits): the levels need not be read
+      bs.put(0u, sp ? 4 : 1);
+    } else if (sp) {
       const int h = N / 2;
       for (int q = 0; q < 4; q++) put_block(bs, lev + q * h * h, h, scan_h);
     } else {
