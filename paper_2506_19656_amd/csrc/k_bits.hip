@@ -356,23 +356,23 @@ struct BitSource {
 // *err and stops that segment.
 // Levels of one n x n block (column-major, zero on entry) from its codes.
 __device__ inline bool get_block(BitSource& src, int16_t* lev, int n, const uint16_t* scan) {
-  bool ok = true;
-  if (src.bit()) {
-    uint32_t k;
-    ok = src.ue(k) && k < (uint32_t)(n * n);
-    const int nnz = ok ? (int)k + 1 : 0;
-    int p = -1;
-    for (int i = 0; i < nnz && ok; i++) {
-      uint32_t run;
-      int v;
-      ok = src.run_level(run, v) && v != 0 && v >= -32767 && v <= 32767;
-      if (!ok) break;
-      p += (int)run + 1;
-      ok = p < n * n;
-      if (ok) lev[scan[p]] = (int16_t)v;
-    }
+  if (!src.bit()) return true;
+  uint32_t k;
+  if (!src.ue(k) || k >= (uint32_t)(n * n)) return false;
+  // a fixed nnz iterations without an early exit; a bad code sets `bad`
+  // (the caller then rejects the whole buffer) and every store stays inside
+  // the block
+  bool bad = false;
+  int p = -1;
+  for (int i = 0; i <= (int)k; i++) {
+    uint32_t run = 0;
+    int v = 0;
+    bad |= !src.run_level(run, v);
+    p = min(p + (int)run + 1, n * n);
+    bad |= v == 0 || v < -32767 || v > 32767 || p == n * n;
+    lev[scan[min(p, n * n - 1)]] = (int16_t)v;
   }
-  return ok;
+  return !bad;
 }
 
 __global__ void __launch_bounds__(kBitsThreads) parse_segments_kernel(BitsArgs a) {
