@@ -988,8 +988,8 @@ __global__ void __launch_bounds__(kThreads) phys_vec_kernel(PhysArgs a) {
 // Pass 1: block (c, g) reads whole tile records (kTileSums words each,
 // adjacent threads on adjacent records) of chunk c of group g and writes
 // five chunk sums (squared error of channels 0..2, coefficient bits of the
-// three channels, vector bits).  Pass 2: one thread per (g, quantity) adds
-// the chunk sums in chunk order.
+// three channels, vector bits).  Pass 2 adds the chunk sums of each (g,
+// quantity); integer sums do not depend on the order.
 constexpr int kTotThreads = 256;
 
 __global__ void __launch_bounds__(kTotThreads) tile_totals_kernel(
@@ -1038,15 +1038,19 @@ __global__ void __launch_bounds__(kTotThreads) tile_totals_kernel(
   }
 }
 
-__global__ void totals_finish_kernel(const unsigned long long* chunk_sum, int G, int chunks,
-                                     unsigned long long* sse, unsigned long long* bits) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 5 * G) return;
-  const int g = i / 5, k = i - g * 5;
+// One wave per (group, quantity): lane l adds chunks l, l + 64, ..., then a
+// butterfly over the wave.
+__global__ void __launch_bounds__(64) totals_finish_kernel(const unsigned long long* chunk_sum,
+                                                          int chunks, unsigned long long* sse,
+                                                          unsigned long long* bits) {
+  const int g = blockIdx.x / 5, k = blockIdx.x - g * 5;
   unsigned long long t = 0;
-  for (int c = 0; c < chunks; c++) t += chunk_sum[((int64_t)g * chunks + c) * 5 + k];
-  if (k < 3) sse[3 * g + k] = t;
-  else bits[2 * g + k - 3] = t;
+  for (int c = threadIdx.x; c < chunks; c += 64) t += chunk_sum[((int64_t)g * chunks + c) * 5 + k];
+  for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+  if (threadIdx.x == 0) {
+    if (k < 3) sse[3 * g + k] = t;
+    else bits[2 * g + k - 3] = t;
+  }
 }
 
 // Job table of one cube, step-major: entry (s, g * nk + k) describes frame
@@ -1127,7 +1131,7 @@ hipError_t launch_encode_totals(const unsigned long long* part, int G, int T, in
   const int64_t n = (int64_t)T * tpf;
   const int chunks = encode_totals_chunks(n);
   tile_totals_kernel<<<dim3(chunks, G), kTotThreads, 0, s>>>(part, n, chunks, chunk_sum);
-  totals_finish_kernel<<<(5 * G + 63) / 64, 64, 0, s>>>(chunk_sum, G, chunks, sse, bits);
+  totals_finish_kernel<<<5 * G, 64, 0, s>>>(chunk_sum, chunks, sse, bits);
   return hipGetLastError();
 }
 
