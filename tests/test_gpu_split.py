@@ -12,6 +12,7 @@ import torch
 from oracle import oracle as O
 from paper_2506_19656_amd import synth
 from paper_2506_19656_amd import xv
+from test_gpu_bitstream import _sections
 from test_gpu_parity import _textured, check_cube
 
 pytestmark = pytest.mark.gpu
@@ -136,10 +137,18 @@ def test_split_bitstream_round_trip():
     op = O.CodingParams(bit_depth=10, qp=25, block=16, search_range=6, gop=3, split=1)
     ref = O.encode_cube(host, op)
     assert ref["splits"].any()
-    # the payload length is the oracle writer's on the oracle's own encode
+    # coefficient units of coded flags 0 only, whole (1 bit) and split (4 bits):
+    # the writer emits those without reading the levels
+    sp = np.broadcast_to(ref["splits"].astype(bool)[:, :, None], ref["coef_bits"].shape)
+    assert ((ref["coef_bits"] == 4) & sp).any() and ((ref["coef_bits"] == 1) & ~sp).any()
+    # payload bytes and index are the oracle writer's on the oracle's own encode
     ref_bits = O.write_bitstream(ref["levels"], ref["mvs"], 3, splits=ref["splits"])
     pk = xv.pack(enc)
     assert pk.view()["payload_bits"] == ref_bits["bits"]
+    sec = _sections(pk.tensor().cpu().numpy())
+    assert np.array_equal(sec["payload"], ref_bits["payload"])
+    assert np.array_equal(sec["index"], ref_bits["index"])
+    assert not sec["tail"].any()
     un = xv.unpack(pk.tensor())
     g = un.host()
     for k in ("levels", "mvs", "coef_bits", "mv_bits", "splits"):
