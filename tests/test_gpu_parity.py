@@ -167,6 +167,21 @@ def test_float_input_without_gaps_and_constant_band():
     assert math.isinf(m["psnr_phys"][1])
 
 
+@pytest.mark.parametrize("T,H,W,N", [(15, 204, 144, 4), (41, 256, 256, 8)])
+def test_group_totals_over_several_ragged_chunks(T, H, W, N):
+    # the per-group totals add the per-tile sums in chunks of at most 2048
+    # tiles (at most 256 chunks per group): these shapes give 2295 and 5248
+    # tiles per group, two and three chunks with a short last one, in two
+    # band groups
+    Hb, Wb = -(-H // N), -(-W // N)
+    n = T * Hb * -(-Wb // (64 // N))
+    chunks = min(256, -(-n // 2048))
+    assert chunks >= 2 and -(-n // chunks) * chunks != n
+    host = _textured(T, H, W, 4, seed=31 + N)
+    check_cube(f"totals_{chunks}_chunks_N{N}", host,
+               xv.Params(bit_depth=10, qp=27, block=N, search_range=4, gop=8))
+
+
 def test_edge_shapes():
     # frame smaller than the search window; single frame; all-intra; gop > T
     check_cube("tiny_frame_big_R", _textured(4, 8, 8, 3, seed=1),
