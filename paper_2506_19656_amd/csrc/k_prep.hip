@@ -1267,9 +1267,12 @@ hipError_t launch_denorm(const DenormArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Blocks of the physical-error kernels (a grid-stride loop of equal work per
+// block): up to 8192, several times what the chip holds at once, so that
+// the last partial round of blocks is a small share of the launch.
 int phys_blocks(int64_t npix) {
   int64_t b = (npix + kThreads * 16 - 1) / (kThreads * 16);
-  return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+  return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
 hipError_t launch_phys_sse(const PhysArgs& a, hipStream_t s) {
